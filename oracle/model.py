@@ -1,0 +1,272 @@
+"""The assembled effective field, energies and RK4 LLG (paper Eqs. heff, hms_d, llg).
+
+H_eff = H_ex + H_ms (+ a uniform applied field), Eq. heff; anisotropy is not
+part of any workload here. Two levels of the potential:
+
+* ``method="direct"`` -- the definition, Eqs. hms_d2/hms_d2b: the point-charge
+  superposition with the periodic Green's function over all node pairs,
+      u_n = (1/4 pi)[ sum_{k != n} G^p(r_n - r_k) q_k + G_reg(0) q_n ] + u_Z,n,
+  (reading: the k = n term of Eq. hms_d2 keeps only the self images).
+* ``method="aim"`` -- the paper's four-step AIM (oracle.aim) plus u_Z.
+
+u_Z is the element-exact correction of Eq. hms_d2b. The charges of the
+body are split by element: each tetrahedron e carries its constant volume
+density rho_e = -Ms_e div(m)_e and, on those of its faces that are surface
+faces of the body (not glued to another tetrahedron of the same material
+after LCA merging: outer boundary and material interfaces, Sec. 3.2.1),
+the linear surface density sigma = Ms_e m.n. Their nodal shares q_i^(e)
+(weights lambda_i, consistent face mass) add up to the weak-form charges.
+For every tetrahedron whose centroid lies within kappa * (mean edge length)
+of r_n in the minimum image (the paper's radius "based on the average edge
+length", Sec. 3.2.2), the exact potential of e replaces the point charges
+that e contributes to the other nodes:
+      u_Z,n = (1/4 pi) sum_e [ int_e rho_e / R + sum_{f surface} int_f sigma / R
+                               - sum_{i in e, i != n} q_i^(e) / |r_n - r_i*| ].
+It acts on m directly (three sparse blocks), separate from the precorrection.
+
+LLG (Eq. llg, reading of the garbled "M x M_n x H"): unit-vector
+Landau-Lifshitz form dm/dt = -gamma0/(1+alpha^2) [m x H + alpha m x (m x H)],
+gamma0 = mu0 * 1.76086e11 m/(A s) (the paper gives no value), classic RK4
+with the norm restored after each full step.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+from scipy.spatial import cKDTree
+
+from . import periodic, fem, pgf as pgfmod, aim as aimmod, elem
+
+MU0 = fem.MU0
+GAMMA0 = MU0 * 1.76086e11
+
+
+def mean_edge_length(xyz, tets):
+    e = np.concatenate([tets[:, [i, j]] for i in range(4) for j in range(i + 1, 4)])
+    e = np.unique(np.sort(e, axis=1), axis=0)
+    return float(np.mean(np.linalg.norm(xyz[e[:, 0]] - xyz[e[:, 1]], axis=1)))
+
+
+class Oracle:
+    def __init__(self, prob, order_p=None, near_boxes=None, z0_radius=None, tol_rel=1e-9,
+                 eta=None, with_aim=True):
+        self.prob = prob
+        self.mask = int(prob.periodic)
+        self.L = np.asarray(prob.L, dtype=np.float64)
+        self.p = prob.order_p if order_p is None else order_p
+        self.r_b = prob.near_boxes if near_boxes is None else near_boxes
+        self.kappa = prob.z0_radius if z0_radius is None else z0_radius
+        self.eta = eta
+        xyz, tets = prob.xyz, prob.tets.astype(np.int64)
+        self.uk, self.reps, self.n_pbc = periodic.unknowns(xyz, self.mask, self.L, tol_rel)
+        self.n = self.reps.size
+        self.ops = fem.LocalOperators(xyz, tets, prob.region, prob.Ms, prob.Aex, self.uk, self.n)
+        self.pos = periodic.remap(xyz[self.reps], self.mask, self.L)
+        self.hbar = mean_edge_length(xyz, tets)
+        self.aim = (aimmod.AIM(self.pos, self.mask, self.L, prob.grid, self.p, self.r_b, eta)
+                    if with_aim else None)
+        self._greg0 = pgfmod.greg0(self.mask, self.L, eta) if self.mask else 0.0
+        self._cache = {}
+
+    # -- inputs ----------------------------------------------------------
+    def unknown_values(self, m_nodes):
+        return np.asarray(m_nodes, dtype=np.float64)[self.reps]
+
+    # -- element-exact correction ------------------------------------------
+    def _minimg(self, d):
+        d = np.array(d, copy=True)
+        for a in range(3):
+            if (self.mask >> a) & 1:
+                d[..., a] -= self.L[a] * np.round(d[..., a] / self.L[a])
+        return d
+
+    def _surface_faces(self):
+        """[T,4] bool: face opposite local vertex a is a surface face of the body."""
+        tets = self.prob.tets.astype(np.int64)
+        U = self.uk[tets]
+        keys, owner, opp = [], [], []
+        for a in range(4):
+            tri = np.sort(np.delete(U, a, axis=1), axis=1)
+            keys.append(tri)
+            owner.append(np.arange(tets.shape[0]))
+            opp.append(np.full(tets.shape[0], a))
+        keys = np.concatenate(keys)
+        owner = np.concatenate(owner)
+        opp = np.concatenate(opp)
+        _, inv, cnt = np.unique(keys, axis=0, return_inverse=True, return_counts=True)
+        inv = inv.ravel()
+        if cnt.max() > 2:
+            raise ValueError("a face is shared by more than two tetrahedra")
+        reg = np.asarray(self.prob.region)[owner]
+        # two sides of one face: interior unless the regions differ
+        first = np.full(cnt.size, -1, dtype=np.int64)
+        other = np.full(cnt.size, -1, dtype=np.int64)
+        for i in range(keys.shape[0]):
+            if first[inv[i]] < 0:
+                first[inv[i]] = i
+            else:
+                other[inv[i]] = i
+        surf = np.ones(keys.shape[0], dtype=bool)
+        both = other >= 0
+        same = np.zeros(cnt.size, dtype=bool)
+        same[both] = reg[first[both]] == reg[other[both]]
+        surf[same[inv]] = False
+        out = np.zeros((tets.shape[0], 4), dtype=bool)
+        out[owner, opp] = surf
+        return out
+
+    def z0(self, rows):
+        """Three sparse blocks [len(rows), N'] with u_Z[rows] = sum_c Z[c] @ m[:, c]."""
+        key = ("z0", tuple(np.asarray(rows).tolist()))
+        if key in self._cache:
+            return self._cache[key]
+        if "surf" not in self._cache:
+            self._cache["surf"] = self._surface_faces()
+        surf_all = self._cache["surf"]
+        prob = self.prob
+        xyz, tets = prob.xyz, prob.tets.astype(np.int64)
+        X = xyz[tets]
+        cen = X.mean(axis=1)
+        rad = self.kappa * self.hbar
+        rows = np.asarray(rows)
+        robs = xyz[self.reps[rows]]
+        # periodic KD-tree: wrap periodic axes into [0, L), pad the others
+        lo = np.minimum(cen.min(axis=0), robs.min(axis=0))
+        ext = np.maximum(cen.max(axis=0), robs.max(axis=0)) - lo
+        box = np.where([(self.mask >> a) & 1 for a in range(3)], self.L, 4 * ext + 4 * rad)
+        tree = cKDTree(np.mod(cen - lo, box), boxsize=box)
+        lists = tree.query_ball_point(np.mod(robs - lo, box), r=rad)
+        pr = np.concatenate([np.full(len(l), i) for i, l in enumerate(lists)]).astype(np.int64)
+        pe = np.concatenate([np.asarray(l, dtype=np.int64) for l in lists])
+        n_obs = rows[pr]
+        r = robs[pr]
+        shift = self._minimg(cen[pe] - r) - (cen[pe] - r)
+        Xs = X[pe] + shift[:, None, :]
+        U = self.uk[tets[pe]]                                     # [P,4]
+        at = (U == n_obs[:, None])
+        vertex = np.where(at.any(axis=1), np.argmax(at, axis=1), -1)
+        if np.any(vertex >= 0):
+            hit = Xs[np.arange(pe.size), np.maximum(vertex, 0)]
+            bad = (vertex >= 0) & (np.linalg.norm(hit - r, axis=1) > 1e-6 * self.hbar)
+            if np.any(bad):
+                raise ValueError("element vertex maps to the observer at another image")
+        grad = self.ops.grad[pe]                                  # [P,4,3]
+        ms = np.asarray(prob.Ms, dtype=np.float64)[prob.region[pe]]
+        V = self.ops.V[pe]
+        dist = np.linalg.norm(r[:, None, :] - Xs, axis=2)          # [P,4]
+        g0 = np.where(at, 0.0, 1.0 / np.maximum(dist, 1e-300))     # point kernel, i != n
+        # volume charge: coefficient of m_j is -Ms grad(lambda_j)
+        IV = elem.tet_inv_r(r, Xs, vertex)
+        exact = -(ms * IV)[:, None, None] * grad                     # [P,4(j),3]
+        point = -(ms * V / 4.0 * g0.sum(axis=1))[:, None, None] * grad
+        surf = surf_all[pe]
+        for a in range(4):
+            sel = np.nonzero(surf[:, a])[0]
+            if sel.size == 0:
+                continue
+            loc = np.array([b for b in range(4) if b != a])
+            T = Xs[sel][:, loc, :]
+            nrm = np.cross(T[:, 1] - T[:, 0], T[:, 2] - T[:, 0])
+            area = 0.5 * np.linalg.norm(nrm, axis=1)
+            nhat = nrm / (2 * area)[:, None]
+            outward = np.einsum("pi,pi->p", nhat, T[:, 0] - Xs[sel][:, a, :]) > 0
+            nhat[~outward] *= -1
+            vloc = np.where(vertex[sel, None] == loc[None, :])
+            tv = np.full(sel.size, -1)
+            tv[vloc[0]] = vloc[1]
+            If = elem.tri_lambda_inv_r(r[sel], T, tv)              # [p,3(l)]
+            for li, j in enumerate(loc):
+                exact[sel, j, :] += (ms[sel] * If[:, li])[:, None] * nhat
+                # share of node i in the face charge of m_j: (A/12)(1 + delta_ij)
+                share = sum(g0[sel, i] * (1.0 + (i == j)) for i in loc)
+                point[sel, j, :] += (ms[sel] * area / 12.0 * share)[:, None] * nhat
+        coef = (exact - point) / (4 * np.pi)
+        rr = np.repeat(pr, 4)
+        cc = U.ravel()
+        out = [sp.csr_matrix((coef[:, :, c].ravel(), (rr, cc)), shape=(rows.size, self.n))
+               for c in range(3)]
+        self._cache[key] = out
+        return out
+
+    # -- potentials ----------------------------------------------------------
+    def potential(self, m, rows=None, method="aim", z0=True):
+        """Corrected potential u [A] at rows (sorted unknown ids) or everywhere."""
+        rows = np.arange(self.n) if rows is None else np.asarray(rows)
+        q = self.ops.charges(m)
+        if method == "aim":
+            key = ("P", tuple(rows.tolist()))
+            if key not in self._cache:
+                self._cache[key] = self.aim.precorrection(rows)
+            U = self.aim.convolve(self.aim.project(q))
+            u = (self.aim.interpolate(U, rows) + self._cache[key] @ q) / (4 * np.pi)
+        elif method == "direct":
+            u = self._direct(q, rows)
+        else:
+            raise ValueError(method)
+        if z0:
+            Z = self.z0(rows)
+            u = u + sum(Z[c] @ m[:, c] for c in range(3))
+        return u
+
+    def _direct(self, q, rows):
+        out = np.empty(rows.size)
+        pos = self.pos
+        for i0 in range(0, rows.size, 64):
+            rr = rows[i0:i0 + 64]
+            d = (pos[rr][:, None, :] - pos[None, :, :]).reshape(-1, 3)
+            same = (rr[:, None] == np.arange(self.n)[None, :]).ravel()
+            g = np.empty(d.shape[0])
+            g[same] = self._greg0
+            g[~same] = pgfmod.pgf(d[~same], self.mask, self.L, self.eta)
+            out[i0:i0 + 64] = g.reshape(rr.size, self.n) @ q
+        return out / (4 * np.pi)
+
+    # -- fields ------------------------------------------------------------
+    def heff(self, m, rows=None, method="aim", terms=("ex", "ms"), h_app=None, z0=True):
+        """H_eff [len(rows),3] (A/m) for unit vectors m [N',3] on the unknowns."""
+        m = np.asarray(m, dtype=np.float64)
+        rows_ = np.arange(self.n) if rows is None else np.asarray(rows)
+        H = np.zeros((rows_.size, 3))
+        if "ex" in terms:
+            H += self.ops.exchange(m)[rows_]
+        if "ms" in terms:
+            ring = np.arange(self.n) if rows is None else self.ops.neighbours(rows_)
+            u = np.zeros(self.n)
+            u[ring] = self.potential(m, ring, method, z0)
+            H += self.ops.gradient_field(u, rows_)
+        if h_app is not None:
+            H += np.asarray(h_app, dtype=np.float64)[None, :]
+        return H
+
+    def charges(self, m):
+        return self.ops.charges(np.asarray(m, dtype=np.float64))
+
+    def energy(self, m, method="aim", h_app=None):
+        """(E_ex, E_ms, E_zeeman) in J."""
+        e_ex = self.ops.exchange_energy(m)
+        q = self.ops.charges(m)
+        u = self.potential(m, None, method)
+        e_ms = 0.5 * MU0 * float(q @ u)
+        e_z = 0.0
+        if h_app is not None:
+            e_z = -MU0 * float(np.sum(self.ops.mu[:, None] * m * np.asarray(h_app)[None, :]))
+        return e_ex, e_ms, e_z
+
+    # -- LLG -------------------------------------------------------------
+    def llg_rhs(self, m, H, alpha):
+        mxh = np.cross(m, H)
+        return -GAMMA0 / (1 + alpha * alpha) * (mxh + alpha * np.cross(m, mxh))
+
+    def rk4(self, m, dt, alpha, n_steps, method="aim", terms=("ex", "ms"), h_app=None):
+        m = np.array(m, dtype=np.float64, copy=True)
+
+        def f(mm):
+            return self.llg_rhs(mm, self.heff(mm, None, method, terms, h_app), alpha)
+        for _ in range(n_steps):
+            k1 = f(m)
+            k2 = f(m + 0.5 * dt * k1)
+            k3 = f(m + 0.5 * dt * k2)
+            k4 = f(m + dt * k3)
+            m = m + dt / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4)
+            m /= np.linalg.norm(m, axis=1, keepdims=True)
+        return m

@@ -1,0 +1,79 @@
+"""Touching periodic unit cells: PBC pairs, LCA merge, unknown numbering.
+
+Paper Sec. 2.2 (after Eq. pm): a node j that is a periodic image of node i
+(r_j = r_i + a lattice vector along periodic axes) carries no unknown of its
+own. Pairs are merged by union-find into their lowest common ancestor (LCA),
+so a corner of a 3D-periodic cube ends up with up to 7 children, and the
+problem size drops to N' = N - N_PBC.
+
+Reading: the LCA representative of a class is its smallest original node
+index; unknowns are numbered by increasing representative index (the paper's
+"first N' points"). Pairs are found one axis at a time (r_j = r_i + L e_a);
+images along diagonals are reached through chains, which union-find merges.
+
+``remap`` is Eq. shift_hms (Sec. 3.2.2, protruding cells): shift every
+unknown by whole periods along each periodic axis so that it lies within half
+a period of the centre r0 (mean of the unknown positions); per-axis, ties to
+the lower image.
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.spatial import cKDTree
+
+
+def pbc_pairs(xyz, mask, L, tol_rel=1e-9):
+    """All (parent, child) index pairs with r_child = r_parent + L_a e_a."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    tol = tol_rel * max(float(np.max(np.abs(L))), float(np.ptp(xyz)))
+    tree = cKDTree(xyz)
+    pairs = []
+    for a in range(3):
+        if not (mask >> a) & 1:
+            continue
+        shifted = xyz.copy()
+        shifted[:, a] += L[a]
+        d, j = tree.query(shifted, distance_upper_bound=tol)
+        ok = np.isfinite(d)
+        pairs.append(np.stack([np.nonzero(ok)[0], j[ok]], axis=1))
+    if not pairs:
+        return np.zeros((0, 2), dtype=np.int64)
+    return np.concatenate(pairs).astype(np.int64)
+
+
+def lca(n_nodes, pairs):
+    """Union-find over PBC pairs; returns root[N] (smallest index of each class)."""
+    parent = np.arange(n_nodes, dtype=np.int64)
+
+    def find(i):
+        while parent[i] != i:
+            parent[i] = parent[parent[i]]
+            i = parent[i]
+        return i
+
+    for i, j in pairs:
+        ri, rj = find(int(i)), find(int(j))
+        if ri != rj:
+            lo, hi = (ri, rj) if ri < rj else (rj, ri)
+            parent[hi] = lo
+    return np.array([find(i) for i in range(n_nodes)], dtype=np.int64)
+
+
+def unknowns(xyz, mask, L, tol_rel=1e-9):
+    """Returns (unknown_of_node[N], rep_node_of_unknown[N'], n_pbc_pairs)."""
+    pairs = pbc_pairs(xyz, mask, L, tol_rel)
+    root = lca(xyz.shape[0], pairs)
+    reps = np.unique(root)
+    uk = np.searchsorted(reps, root)
+    return uk, reps, pairs.shape[0]
+
+
+def remap(pos, mask, L):
+    """Eq. shift_hms: per periodic axis, wrap into [r0 - L/2, r0 + L/2)."""
+    pos = np.array(pos, dtype=np.float64, copy=True)
+    r0 = pos.mean(axis=0)
+    for a in range(3):
+        if (mask >> a) & 1:
+            d = pos[:, a] - r0[a]
+            pos[:, a] = r0[a] + d - L[a] * np.floor(d / L[a] + 0.5)
+    return pos
