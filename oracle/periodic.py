@@ -69,11 +69,14 @@ def unknowns(xyz, mask, L, tol_rel=1e-9):
 
 
 def remap(pos, mask, L):
-    """Eq. shift_hms: per periodic axis, wrap into [r0 - L/2, r0 + L/2)."""
+    """Eq. shift_hms: per periodic axis, wrap into [r0 - L/2, r0 + L/2).
+
+    The shifted coordinate is formed as x - k L (k integer), so unshifted
+    points keep their coordinates bit for bit."""
     pos = np.array(pos, dtype=np.float64, copy=True)
     r0 = pos.mean(axis=0)
     for a in range(3):
         if (mask >> a) & 1:
             d = pos[:, a] - r0[a]
-            pos[:, a] = r0[a] + d - L[a] * np.floor(d / L[a] + 0.5)
+            pos[:, a] = pos[:, a] - L[a] * np.floor(d / L[a] + 0.5)
     return pos
