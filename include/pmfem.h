@@ -1,0 +1,199 @@
+/*
+ * pmfem.h -- C ABI of the MI355X (gfx950) PM-FEM effective-field library.
+ *
+ * The library evaluates the effective field of the periodic micromagnetic
+ * finite element method (Ai, Duan, Lomakin, arXiv 2409.13958) on one GPU:
+ *
+ *   H_eff = H_ex + H_ms (+ a uniform applied field)               (Eq. heff)
+ *
+ * on a tetrahedral mesh of a 1D-, 2D- or 3D-periodic unit cell with linear
+ * (P1) magnetisation (Eq. M_phi). Periodic images on touching cell faces are
+ * merged into their lowest common ancestor (Sec. 2.2), the exchange,
+ * charge and gradient operators are periodised (Secs. 3.1, 3.2.1), and the
+ * magnetostatic potential is the periodic point-charge superposition
+ * (Eq. hms_d2) with the element-exact near correction (Eq. hms_d2b),
+ * evaluated by the four-step FFT-based adaptive integral method with a
+ * periodic Green's function (Sec. 3.2.2). Protruding cells are folded by
+ * Eq. shift_hms. Units are SI throughout.
+ *
+ * Conventions
+ *  - Every entry point returns a pmfem_status (0 = success, < 0 = error);
+ *    pmfem_last_error() gives a message for the last failure of a context.
+ *  - Host arrays passed in are copied; the caller keeps ownership.
+ *  - Device arrays (m_dev, h_dev, ...) belong to the caller; they must hold
+ *    N' rows in the library's unknown order (see pmfem_query) and live on
+ *    the context's device. Work is enqueued on the context's stream and the
+ *    call returns without synchronising; device errors surface as
+ *    PMFEM_EHIP at the latest on the next call.
+ *  - A context is not re-entrant: calls on one context must not overlap.
+ *  - All setup (pmfem_build) runs on the host in FP64 and uploads once.
+ */
+#ifndef PMFEM_H
+#define PMFEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pmfem_ctx pmfem_ctx;
+
+typedef enum {
+  PMFEM_OK = 0,
+  PMFEM_EINVAL = -1,  /* bad argument or material value                    */
+  PMFEM_EMESH = -2,   /* invalid mesh (index out of range, volume <= 0)      */
+  PMFEM_EPBC = -3,    /* periodic faces that do not match                   */
+  PMFEM_EGRID = -4,   /* AIM grid unusable (too short, not a power of two)  */
+  PMFEM_ENOMEM = -5,  /* host or device allocation failed                   */
+  PMFEM_EHIP = -6,    /* HIP runtime error                                  */
+  PMFEM_ESTATE = -7   /* call out of order (e.g. heff before build)         */
+} pmfem_status;
+
+/* Field terms for pmfem_heff. */
+#define PMFEM_TERM_EX 1u  /* exchange, Eq. hex / lapl_2                  */
+#define PMFEM_TERM_MS 2u  /* magnetostatic, Eqs. hms_d1 - hms_d3          */
+
+/*
+ * Create a context on HIP device `hip_device` using stream `hip_stream`
+ * (a hipStream_t, or NULL for the default stream). hip_device = -1 makes a
+ * host-only context: pmfem_build then assembles the operators without any
+ * device work and only the pmfem_export call can read them (used to check
+ * the host setup); pmfem_heff and pmfem_llg_step return PMFEM_ESTATE.
+ */
+int pmfem_create(pmfem_ctx** out, int hip_device, void* hip_stream);
+
+/*
+ * Mesh (Sec. 2.2): n_nodes coordinates xyz[n][3] in metres and n_tets
+ * tetrahedra tets[t][4] (node indices, any orientation) with a region id per
+ * tetrahedron. Image nodes of a touching cell are separate nodes here; they
+ * are paired by pmfem_build.
+ */
+int pmfem_set_mesh(pmfem_ctx* ctx, int64_t n_nodes, const double* xyz, int64_t n_tets,
+                   const int32_t* tets, const int32_t* region);
+
+/* Materials per region: saturation magnetisation Ms[r] > 0 (A/m) and
+ * exchange stiffness Aex[r] >= 0 (J/m). */
+int pmfem_set_materials(pmfem_ctx* ctx, int32_t n_regions, const double* Ms, const double* Aex);
+
+/*
+ * Periodicity (Eq. pm): axis_mask bit0 = x, bit1 = y, bit2 = z; L[3] are
+ * the periods in metres (ignored on non-periodic axes). Two nodes form a
+ * PBC pair when they differ by L along one periodic axis within
+ * match_tol * max(L, mesh extent) (match_tol <= 0 selects 1e-9).
+ */
+int pmfem_set_periodicity(pmfem_ctx* ctx, uint32_t axis_mask, const double L[3],
+                          double match_tol);
+
+/*
+ * AIM parameters (Sec. 3.2.2): grid[3] points per axis; Lagrange order
+ * order_p (1..5) of projection/interpolation; near_boxes = r_b, the
+ * per-axis box radius of the precorrection region; z0_radius_edges = kappa,
+ * the radius of the element-exact correction in mean edge lengths;
+ * precision must be 0 (FP32 grid and operators). On a periodic axis the
+ * grid spacing is L/N and the FFT extent is N; on a non-periodic axis the
+ * grid spans the mesh and the FFT extent is 2N. FFT extents must be powers
+ * of two in [4, 512]; periodic axes need N >= 2 (r_b + p) + 1.
+ */
+int pmfem_set_aim(pmfem_ctx* ctx, const int32_t grid[3], int32_t order_p, int32_t near_boxes,
+                  double z0_radius_edges, int32_t precision);
+
+/*
+ * Build all operators on the host in FP64 (PBC pairs and LCA merge,
+ * periodised P1 operators, grid PGF and its spectrum, precorrection and
+ * element-exact correction), round them once to FP32 and upload them.
+ * Errors: EINVAL, EMESH, EPBC, EGRID, ENOMEM, EHIP, ESTATE (inputs missing).
+ */
+int pmfem_build(pmfem_ctx* ctx);
+
+/*
+ * Sizes and permutations after pmfem_build. n_unknowns = N'.
+ * unknown_of_node[N] (or NULL) maps every mesh node to its unknown;
+ * node_of_unknown[N'] (or NULL) gives the LCA representative node (the
+ * smallest node index of its class). bytes_per_eval (or NULL) receives the
+ * algorithmic HBM bytes of one pmfem_heff call with both terms.
+ */
+int pmfem_query(pmfem_ctx* ctx, int64_t* n_unknowns, int64_t* unknown_of_node,
+                int64_t* node_of_unknown, double* bytes_per_eval);
+
+/*
+ * Effective field: m_dev[N'][3] unit vectors (FP32, device) -> h_dev[N'][3]
+ * in A/m (FP32, device). terms = PMFEM_TERM_EX | PMFEM_TERM_MS. h_applied
+ * (host, 3 doubles, A/m) or NULL adds a uniform applied field.
+ */
+int pmfem_heff(pmfem_ctx* ctx, const float* m_dev, float* h_dev, uint32_t terms,
+               const double* h_applied);
+
+/*
+ * Same as pmfem_heff with both terms, also writing the intermediate
+ * per-unknown results to caller device buffers (each may be NULL):
+ * q_dev[N'] nodal charges (A m, Eq. hms_d1), u_dev[N'] corrected potential
+ * (A, Eq. hms_d2b), hex_dev[N'][3] exchange field (A/m).
+ */
+int pmfem_heff_parts(pmfem_ctx* ctx, const float* m_dev, float* h_dev, float* q_dev,
+                     float* u_dev, float* hex_dev);
+
+/*
+ * Grid convolution alone (step 2 of Sec. 3.2.2): q_grid_dev[Nz][Ny][Nx]
+ * real grid charges -> u_grid_dev[Nz][Ny][Nx] = (1/4 pi) K * Q (x fastest).
+ */
+int pmfem_grid_convolve(pmfem_ctx* ctx, const float* q_grid_dev, float* u_grid_dev);
+
+/*
+ * LLG time stepping (Eq. llg, unit-vector Landau-Lifshitz form,
+ * gamma0 = 2.21276e5 m/(A s)): n_steps classic RK4 steps of size dt (s)
+ * with damping alpha on the FP64 master magnetisation m_dev[N'][3]
+ * (device), each stage evaluating H_eff in FP32, the norm restored in FP64
+ * after every step. h_applied as in pmfem_heff.
+ */
+int pmfem_llg_step(pmfem_ctx* ctx, double* m_dev, double dt, double alpha, int32_t n_steps,
+                   const double* h_applied);
+
+/*
+ * Energies in J for the FP64 magnetisation m_dev[N'][3] (device):
+ * exchange E_ex = m.K m and magnetostatic E_ms = (mu0/2) q.u. Synchronises.
+ */
+int pmfem_energy(pmfem_ctx* ctx, const double* m_dev, double* e_ex, double* e_ms);
+
+/*
+ * Kernel timing with HIP events on the context's stream. After
+ * pmfem_profile_begin(ctx, max_calls), every pmfem_heff call (up to
+ * max_calls) records an event pair around each of its kernels;
+ * pmfem_profile_end synchronises and returns, for each of the n_kernels
+ * (<= 16) kernels in launch order, the summed milliseconds ms[k], the launch
+ * count count[k] and its name into names[k] (at most 31 characters + NUL).
+ */
+int pmfem_profile_begin(pmfem_ctx* ctx, int32_t max_calls);
+int pmfem_profile_end(pmfem_ctx* ctx, int32_t* n_kernels, double* ms, int32_t* count,
+                      char (*names)[32]);
+
+/*
+ * Host copies of an assembled operator, for validation of the setup.
+ * name selects the array (see the table in the library source: "mu",
+ * "loc_rowptr", "loc_col", "loc_val", "z0_rowptr", "z0_col", "z0_val",
+ * "p_rowptr", "p_col", "p_val", "pos", "khat", "kgrid", "box_start",
+ * "grid_info"). With out == NULL only *count (elements) and *elem_bytes
+ * are set; otherwise *count elements are copied to out.
+ */
+int pmfem_export(pmfem_ctx* ctx, const char* name, void* out, int64_t* count,
+                 int32_t* elem_bytes);
+
+/*
+ * Periodic Green's function of the Laplacian (Eq. 2 at zero Bloch phase,
+ * Ewald-regularised; 3D zero cell average, 2D and 1D keeping the
+ * -2 pi |z| / A and -(2/L) ln(rho/L) far fields) at n points r[n][3]
+ * (metres) into out[n]; a point on a lattice site returns the regular part
+ * lim (G - 1/r). Host-only, FP64; eta <= 0 selects the default splitting.
+ */
+int pmfem_pgf_eval(uint32_t axis_mask, const double L[3], double eta, int64_t n,
+                   const double* r, double* out);
+
+const char* pmfem_last_error(const pmfem_ctx* ctx);
+
+void pmfem_destroy(pmfem_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMFEM_H */

@@ -1,0 +1,650 @@
+// C ABI of the library: context lifecycle, upload of the host-built
+// operators, and the launch sequence of one effective-field evaluation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+using namespace pmfem;
+
+struct pmfem_dev {
+  int64_t n = 0;
+  GridParams g{};
+  float4* pos4 = nullptr;
+  int32_t* box_start = nullptr;
+  int2 *brx = nullptr, *bry = nullptr, *brz = nullptr;
+  int32_t *lrp = nullptr, *lcol = nullptr;
+  float4 *lld = nullptr, *lg = nullptr;
+  int32_t *zrp = nullptr, *zcol = nullptr;
+  float4* zv = nullptr;
+  int32_t *prp = nullptr, *pcol = nullptr;
+  float* pv = nullptr;
+  float* khat = nullptr;
+  float2 *twx = nullptr, *twy = nullptr, *twz = nullptr;
+  double* mu = nullptr;
+  float4* hex = nullptr;
+  float *q = nullptr, *uz = nullptr, *u = nullptr, *grid = nullptr;
+  float2* spec = nullptr;
+  double *mst = nullptr, *kk = nullptr, *acc = nullptr;
+  float *m32 = nullptr, *h32 = nullptr;
+  double* part = nullptr;
+  int nparts = 0;
+  std::vector<void*> allocs;
+  // profiling
+  int prof_max = 0, prof_calls = 0;
+  std::vector<hipEvent_t> ev;  // [calls][kernels][2]
+};
+
+namespace {
+
+constexpr int kNumKernels = 9;
+const char* kKernelNames[kNumKernels] = {"k_local",     "k_anterp",    "k_r2c_x",
+                                         "k_fft_y_fwd", "k_fft_z_mul", "k_fft_y_inv",
+                                         "k_c2r_x",     "k_interp_corr", "k_grad"};
+
+int set_err(pmfem_ctx* c, int code, const std::string& m) {
+  if (c) c->err = m;
+  return code;
+}
+
+int hip_err(pmfem_ctx* c, hipError_t e, const char* where) {
+  return set_err(c, PMFEM_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+template <class T>
+int dalloc(pmfem_ctx* c, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) return set_err(c, PMFEM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  c->dev->allocs.push_back((void*)*p);
+  return PMFEM_OK;
+}
+
+template <class T>
+int upload(pmfem_ctx* c, T** p, const void* src, size_t count) {
+  int rc = dalloc(c, p, count);
+  if (rc) return rc;
+  if (count) {
+    hipError_t e = hipMemcpy(*p, src, count * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_err(c, e, "hipMemcpy");
+  }
+  return PMFEM_OK;
+}
+
+void free_dev(pmfem_ctx* c) {
+  if (!c->dev) return;
+  for (void* p : c->dev->allocs) (void)hipFree(p);
+  for (hipEvent_t e : c->dev->ev) (void)hipEventDestroy(e);
+  delete c->dev;
+  c->dev = nullptr;
+}
+
+int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+std::vector<float2> twiddles(int n) {
+  std::vector<float2> t(n / 2 > 0 ? n / 2 : 1);
+  for (int k = 0; k < n / 2; ++k) {
+    double a = -2.0 * kPi * k / n;
+    t[k] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  return t;
+}
+
+// boxes covering each grid index along one axis: (first box, count)
+std::vector<int2> box_ranges(const HostOps& o, int a) {
+  int N = o.N[a], p = o.p, shift = (p - 1) / 2;
+  std::vector<int2> r(N);
+  for (int gi = 0; gi < N; ++gi) {
+    if (o.per[a]) {
+      int s0 = ((gi - p + shift) % N + N) % N;
+      r[gi] = make_int2(s0, p + 1);
+    } else {
+      int first = -1, cnt = 0;
+      for (int b = 0; b < o.nbox[a]; ++b) {
+        int st = std::min(std::max(b - shift, 0), N - p - 1);
+        if (st >= gi - p && st <= gi) {
+          if (first < 0) first = b;
+          ++cnt;
+        }
+      }
+      r[gi] = make_int2(first < 0 ? 0 : first, cnt);
+    }
+  }
+  return r;
+}
+
+int upload_all(pmfem_ctx* c) {
+  HostOps& o = c->ops;
+  pmfem_dev* d = c->dev;
+  const int64_t n = o.n_unk;
+  d->n = n;
+  for (int a = 0; a < 3; ++a) {
+    d->g.N[a] = o.N[a];
+    d->g.M[a] = o.M[a];
+    d->g.logM[a] = ilog2(o.M[a]);
+    d->g.nbox[a] = o.nbox[a];
+  }
+  d->g.p = o.p;
+  int rc;
+  if ((rc = upload(c, &d->pos4, o.pos4.data(), n))) return rc;
+  if ((rc = upload(c, &d->box_start, o.box_start.data(), o.box_start.size()))) return rc;
+  auto bx = box_ranges(o, 0), by = box_ranges(o, 1), bz = box_ranges(o, 2);
+  if ((rc = upload(c, &d->brx, bx.data(), bx.size()))) return rc;
+  if ((rc = upload(c, &d->bry, by.data(), by.size()))) return rc;
+  if ((rc = upload(c, &d->brz, bz.data(), bz.size()))) return rc;
+  const int64_t nnzL = o.loc_rowptr[n];
+  std::vector<float4> ld(nnzL), gg(nnzL);
+  for (int64_t e = 0; e < nnzL; ++e) {
+    const float* v = &o.loc_val[8 * e];
+    ld[e] = make_float4(v[0], v[1], v[2], v[3]);
+    gg[e] = make_float4(v[4], v[5], v[6], 0.f);
+  }
+  if ((rc = upload(c, &d->lrp, o.loc_rowptr.data(), n + 1))) return rc;
+  if ((rc = upload(c, &d->lcol, o.loc_col.data(), nnzL))) return rc;
+  if ((rc = upload(c, &d->lld, ld.data(), nnzL))) return rc;
+  if ((rc = upload(c, &d->lg, gg.data(), nnzL))) return rc;
+  const int64_t nnzZ = o.z0_rowptr[n];
+  if ((rc = upload(c, &d->zrp, o.z0_rowptr.data(), n + 1))) return rc;
+  if ((rc = upload(c, &d->zcol, o.z0_col.data(), nnzZ))) return rc;
+  if ((rc = upload(c, &d->zv, o.z0_val.data(), nnzZ))) return rc;
+  const int64_t nnzP = o.p_rowptr[n];
+  if ((rc = upload(c, &d->prp, o.p_rowptr.data(), n + 1))) return rc;
+  if ((rc = upload(c, &d->pcol, o.p_col.data(), nnzP))) return rc;
+  if ((rc = upload(c, &d->pv, o.p_val.data(), nnzP))) return rc;
+  if ((rc = upload(c, &d->khat, o.khat.data(), o.khat.size()))) return rc;
+  auto tx = twiddles(o.M[0]), ty = twiddles(o.M[1]), tz = twiddles(o.M[2]);
+  if ((rc = upload(c, &d->twx, tx.data(), tx.size()))) return rc;
+  if ((rc = upload(c, &d->twy, ty.data(), ty.size()))) return rc;
+  if ((rc = upload(c, &d->twz, tz.data(), tz.size()))) return rc;
+  if ((rc = upload(c, &d->mu, o.mu.data(), n))) return rc;
+  if ((rc = dalloc(c, &d->hex, n))) return rc;
+  if ((rc = dalloc(c, &d->q, n))) return rc;
+  if ((rc = dalloc(c, &d->uz, n))) return rc;
+  if ((rc = dalloc(c, &d->u, n))) return rc;
+  const int64_t ng = (int64_t)o.N[0] * o.N[1] * o.N[2];
+  if ((rc = dalloc(c, &d->grid, ng))) return rc;
+  const int64_t nspec = (int64_t)o.N[2] * o.M[1] * (o.M[0] / 2 + 1);
+  if ((rc = dalloc(c, &d->spec, nspec))) return rc;
+  if ((rc = dalloc(c, &d->mst, 3 * n))) return rc;
+  if ((rc = dalloc(c, &d->kk, 3 * n))) return rc;
+  if ((rc = dalloc(c, &d->acc, 3 * n))) return rc;
+  if ((rc = dalloc(c, &d->m32, 3 * n))) return rc;
+  if ((rc = dalloc(c, &d->h32, 3 * n))) return rc;
+  d->nparts = 1024;
+  if ((rc = dalloc(c, &d->part, 2 * d->nparts))) return rc;
+  return PMFEM_OK;
+}
+
+hipStream_t stream_of(pmfem_ctx* c) { return (hipStream_t)c->stream; }
+
+// One evaluation. Intermediates land in the context's work buffers.
+int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const double* happ) {
+  pmfem_dev* d = c->dev;
+  hipStream_t s = stream_of(c);
+  const int64_t n = d->n;
+  const GridParams& g = d->g;
+  const int with_ex = (terms & PMFEM_TERM_EX) ? 1 : 0;
+  const int with_ms = (terms & PMFEM_TERM_MS) ? 1 : 0;
+  hipEvent_t* ev = nullptr;
+  if (d->prof_calls < d->prof_max) {
+    ev = &d->ev[(size_t)d->prof_calls * kNumKernels * 2];
+    d->prof_calls++;
+  }
+  auto mark = [&](int k, int which) {
+    if (ev) (void)hipEventRecord(ev[2 * k + which], s);
+  };
+  const int T = 256;
+  mark(0, 0);
+  hipLaunchKernelGGL(k_local, dim3((unsigned)((n * 16 + T - 1) / T)), dim3(T), 0, s, n, m, d->lrp,
+                     d->lcol, d->lld, d->zrp, d->zcol, d->zv, d->hex, d->q, d->uz, with_ex,
+                     with_ms);
+  mark(0, 1);
+  if (with_ms) {
+    const int64_t ng = (int64_t)g.N[0] * g.N[1] * g.N[2];
+    mark(1, 0);
+    hipLaunchKernelGGL(k_anterp, dim3((unsigned)((ng + T - 1) / T)), dim3(T), 0, s, g, d->q,
+                       d->pos4, d->box_start, d->brx, d->bry, d->brz, d->grid);
+    mark(1, 1);
+    const int Mx = g.M[0], My = g.M[1], Mz = g.M[2], Hx = Mx / 2 + 1;
+    const int lpb = std::max(1, 2048 / Mx);
+    const int64_t xlines = (int64_t)((g.N[1] + 1) / 2) * g.N[2];
+    mark(2, 0);
+    hipLaunchKernelGGL(k_r2c_x, dim3((unsigned)((xlines + lpb - 1) / lpb)), dim3(T),
+                       (size_t)(Mx / 2 + lpb * Mx) * sizeof(float2), s, g, d->grid, d->spec,
+                       d->twx, lpb);
+    mark(2, 1);
+    const int By = std::max(1, std::min(16, 4096 / My));
+    const int gy = (Hx + By - 1) / By;
+    mark(3, 0);
+    hipLaunchKernelGGL(k_fft_y, dim3((unsigned)(g.N[2] * gy)), dim3(T),
+                       (size_t)(My / 2 + By * My) * sizeof(float2), s, g, d->spec, d->twy, By, 0,
+                       g.N[1], My);
+    mark(3, 1);
+    const int Bz = std::max(1, std::min(16, 4096 / Mz));
+    const int64_t cols = (int64_t)My * Hx;
+    mark(4, 0);
+    hipLaunchKernelGGL(k_fft_z_mul, dim3((unsigned)((cols + Bz - 1) / Bz)), dim3(T),
+                       (size_t)(Mz / 2 + Bz * Mz) * sizeof(float2), s, g, d->spec, d->khat,
+                       d->twz, Bz);
+    mark(4, 1);
+    mark(5, 0);
+    hipLaunchKernelGGL(k_fft_y, dim3((unsigned)(g.N[2] * gy)), dim3(T),
+                       (size_t)(My / 2 + By * My) * sizeof(float2), s, g, d->spec, d->twy, By, 1,
+                       My, g.N[1]);
+    mark(5, 1);
+    mark(6, 0);
+    hipLaunchKernelGGL(k_c2r_x, dim3((unsigned)((xlines + lpb - 1) / lpb)), dim3(T),
+                       (size_t)(Mx / 2 + lpb * Mx) * sizeof(float2), s, g, d->spec, d->grid,
+                       d->twx, lpb);
+    mark(6, 1);
+    mark(7, 0);
+    hipLaunchKernelGGL(k_interp_corr, dim3((unsigned)((n * 64 + T - 1) / T)), dim3(T), 0, s, g, n,
+                       d->grid, d->pos4, d->prp, d->pcol, d->pv, d->q, d->uz, d->u);
+    mark(7, 1);
+  }
+  float hx = 0.f, hy = 0.f, hz = 0.f;
+  if (happ) {
+    hx = (float)happ[0];
+    hy = (float)happ[1];
+    hz = (float)happ[2];
+  }
+  mark(8, 0);
+  hipLaunchKernelGGL(k_grad, dim3((unsigned)((n * 16 + T - 1) / T)), dim3(T), 0, s, n, d->lrp,
+                     d->lcol, d->lg, d->u, d->hex, h, hx, hy, hz, with_ms);
+  mark(8, 1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_err(c, e, "kernel launch");
+  return PMFEM_OK;
+}
+
+int ready(pmfem_ctx* c) {
+  if (!c) return PMFEM_EINVAL;
+  if (!c->built) return set_err(c, PMFEM_ESTATE, "pmfem_build has not succeeded");
+  if (!c->dev) return set_err(c, PMFEM_ESTATE, "host-only context has no device operators");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_err(c, e, "hipSetDevice");
+  return PMFEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pmfem_create(pmfem_ctx** out, int hip_device, void* hip_stream) {
+  if (!out) return PMFEM_EINVAL;
+  *out = nullptr;
+  if (hip_device >= 0) {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || hip_device >= count) return PMFEM_EHIP;
+  } else if (hip_device != -1) {
+    return PMFEM_EINVAL;
+  }
+  pmfem_ctx* c = new (std::nothrow) pmfem_ctx();
+  if (!c) return PMFEM_ENOMEM;
+  c->device = hip_device;
+  c->stream = hip_stream;
+  *out = c;
+  return PMFEM_OK;
+}
+
+int pmfem_set_mesh(pmfem_ctx* c, int64_t n_nodes, const double* xyz, int64_t n_tets,
+                   const int32_t* tets, const int32_t* region) {
+  if (!c) return PMFEM_EINVAL;
+  if (n_nodes < 4 || n_tets < 1 || !xyz || !tets || !region)
+    return set_err(c, PMFEM_EINVAL, "empty mesh or null array");
+  if (n_nodes > 2000000000LL || n_tets > 2000000000LL) return set_err(c, PMFEM_EINVAL, "mesh too large");
+  c->n_nodes = n_nodes;
+  c->n_tets = n_tets;
+  c->xyz.assign(xyz, xyz + 3 * n_nodes);
+  c->tets.assign(tets, tets + 4 * n_tets);
+  c->region.assign(region, region + n_tets);
+  c->have_mesh = true;
+  c->built = false;
+  return PMFEM_OK;
+}
+
+int pmfem_set_materials(pmfem_ctx* c, int32_t n_regions, const double* Ms, const double* Aex) {
+  if (!c) return PMFEM_EINVAL;
+  if (n_regions < 1 || !Ms || !Aex) return set_err(c, PMFEM_EINVAL, "no regions");
+  c->n_regions = n_regions;
+  c->Ms.assign(Ms, Ms + n_regions);
+  c->Aex.assign(Aex, Aex + n_regions);
+  c->have_mat = true;
+  c->built = false;
+  return PMFEM_OK;
+}
+
+int pmfem_set_periodicity(pmfem_ctx* c, uint32_t axis_mask, const double L[3], double match_tol) {
+  if (!c) return PMFEM_EINVAL;
+  if (axis_mask > 7 || (axis_mask && !L)) return set_err(c, PMFEM_EINVAL, "bad periodicity");
+  c->mask = axis_mask;
+  for (int a = 0; a < 3; ++a) c->L[a] = L ? L[a] : 0.0;
+  c->match_tol = match_tol > 0 ? match_tol : 1e-9;
+  c->built = false;
+  return PMFEM_OK;
+}
+
+int pmfem_set_aim(pmfem_ctx* c, const int32_t grid[3], int32_t order_p, int32_t near_boxes,
+                  double z0_radius_edges, int32_t precision) {
+  if (!c) return PMFEM_EINVAL;
+  if (!grid) return set_err(c, PMFEM_EINVAL, "null grid");
+  for (int a = 0; a < 3; ++a)
+    if (grid[a] < 2 || grid[a] > 1024) return set_err(c, PMFEM_EGRID, "grid size out of range");
+  for (int a = 0; a < 3; ++a) c->grid[a] = grid[a];
+  c->order_p = order_p;
+  c->near_boxes = near_boxes;
+  c->z0_radius = z0_radius_edges;
+  c->precision = precision;
+  c->have_aim = true;
+  c->built = false;
+  return PMFEM_OK;
+}
+
+int pmfem_build(pmfem_ctx* c) {
+  if (!c) return PMFEM_EINVAL;
+  c->built = false;
+  free_dev(c);
+  int rc;
+  try {
+    rc = host_build(c);
+  } catch (const std::bad_alloc&) {
+    return set_err(c, PMFEM_ENOMEM, "host allocation failed");
+  }
+  if (rc != PMFEM_OK) return rc;
+  if (c->device >= 0) {
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_err(c, e, "hipSetDevice");
+    c->dev = new (std::nothrow) pmfem_dev();
+    if (!c->dev) return set_err(c, PMFEM_ENOMEM, "host allocation failed");
+    try {
+      rc = upload_all(c);
+    } catch (const std::bad_alloc&) {
+      rc = set_err(c, PMFEM_ENOMEM, "host allocation failed");
+    }
+    if (rc != PMFEM_OK) {
+      free_dev(c);
+      return rc;
+    }
+  }
+  c->built = true;
+  return PMFEM_OK;
+}
+
+int pmfem_query(pmfem_ctx* c, int64_t* n_unknowns, int64_t* unknown_of_node,
+                int64_t* node_of_unknown, double* bytes_per_eval) {
+  if (!c) return PMFEM_EINVAL;
+  if (!c->built) return set_err(c, PMFEM_ESTATE, "pmfem_build has not succeeded");
+  const HostOps& o = c->ops;
+  if (n_unknowns) *n_unknowns = o.n_unk;
+  if (unknown_of_node) std::memcpy(unknown_of_node, o.unk_of_node.data(), o.n_nodes * sizeof(int64_t));
+  if (node_of_unknown) std::memcpy(node_of_unknown, o.node_of_unk.data(), o.n_unk * sizeof(int64_t));
+  if (bytes_per_eval) {
+    // algorithmic HBM bytes: every array of one evaluation touched once
+    const double n = (double)o.n_unk;
+    const double nL = (double)o.loc_rowptr[o.n_unk], nZ = (double)o.z0_rowptr[o.n_unk],
+                 nP = (double)o.p_rowptr[o.n_unk];
+    const double ng = (double)o.N[0] * o.N[1] * o.N[2];
+    const double hx = o.M[0] / 2 + 1;
+    const double spec = (double)o.N[2] * o.M[1] * hx * 8.0;
+    const double khat = hx * o.M[1] * o.M[2] * 4.0;
+    double b = 0;
+    b += n * (4 + 12 + 16 + 4 + 4 + 4) + nL * (4 + 16) + nZ * (4 + 16);  // k_local
+    b += n * (16 + 4) + ng * 4 + (double)o.box_start.size() * 4;       // k_anterp
+    b += ng * 4 + spec;                                                  // r2c
+    b += 2 * spec;                                                       // y fwd
+    b += 2 * spec + khat;                                                // z
+    b += 2 * spec;                                                       // y inv
+    b += spec + ng * 4;                                                  // c2r
+    b += n * (16 + 4 + 4 + 4 + 4) + ng * 4 + nP * 8;                     // interp+corr
+    b += n * (4 + 4 + 16 + 12) + nL * (4 + 16);                          // grad
+    *bytes_per_eval = b;
+  }
+  return PMFEM_OK;
+}
+
+int pmfem_heff(pmfem_ctx* c, const float* m_dev, float* h_dev, uint32_t terms,
+               const double* h_applied) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!m_dev || !h_dev || terms > 3) return set_err(c, PMFEM_EINVAL, "bad heff arguments");
+  return run_heff(c, m_dev, h_dev, terms, h_applied);
+}
+
+int pmfem_heff_parts(pmfem_ctx* c, const float* m_dev, float* h_dev, float* q_dev, float* u_dev,
+                     float* hex_dev) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!m_dev || !h_dev) return set_err(c, PMFEM_EINVAL, "bad heff arguments");
+  rc = run_heff(c, m_dev, h_dev, PMFEM_TERM_EX | PMFEM_TERM_MS, nullptr);
+  if (rc) return rc;
+  pmfem_dev* d = c->dev;
+  hipStream_t s = stream_of(c);
+  const size_t n = (size_t)d->n;
+  hipError_t e = hipSuccess;
+  if (q_dev) e = hipMemcpyAsync(q_dev, d->q, n * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && u_dev) e = hipMemcpyAsync(u_dev, d->u, n * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && hex_dev)
+    e = hipMemcpy2DAsync(hex_dev, 12, d->hex, 16, 12, n, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_err(c, e, "copy of intermediates");
+  return PMFEM_OK;
+}
+
+int pmfem_grid_convolve(pmfem_ctx* c, const float* q_grid_dev, float* u_grid_dev) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!q_grid_dev || !u_grid_dev) return set_err(c, PMFEM_EINVAL, "null grid buffer");
+  pmfem_dev* d = c->dev;
+  const GridParams& g = d->g;
+  hipStream_t s = stream_of(c);
+  const int64_t ng = (int64_t)g.N[0] * g.N[1] * g.N[2];
+  const int Mx = g.M[0], My = g.M[1], Mz = g.M[2], Hx = Mx / 2 + 1;
+  const int T = 256;
+  const int lpb = std::max(1, 2048 / Mx);
+  const int64_t xlines = (int64_t)((g.N[1] + 1) / 2) * g.N[2];
+  const int By = std::max(1, std::min(16, 4096 / My));
+  const int gy = (Hx + By - 1) / By;
+  const int Bz = std::max(1, std::min(16, 4096 / Mz));
+  const int64_t cols = (int64_t)My * Hx;
+  hipLaunchKernelGGL(k_r2c_x, dim3((unsigned)((xlines + lpb - 1) / lpb)), dim3(T),
+                     (size_t)(Mx / 2 + lpb * Mx) * sizeof(float2), s, g, q_grid_dev, d->spec,
+                     d->twx, lpb);
+  hipLaunchKernelGGL(k_fft_y, dim3((unsigned)(g.N[2] * gy)), dim3(T),
+                     (size_t)(My / 2 + By * My) * sizeof(float2), s, g, d->spec, d->twy, By, 0,
+                     g.N[1], My);
+  hipLaunchKernelGGL(k_fft_z_mul, dim3((unsigned)((cols + Bz - 1) / Bz)), dim3(T),
+                     (size_t)(Mz / 2 + Bz * Mz) * sizeof(float2), s, g, d->spec, d->khat, d->twz,
+                     Bz);
+  hipLaunchKernelGGL(k_fft_y, dim3((unsigned)(g.N[2] * gy)), dim3(T),
+                     (size_t)(My / 2 + By * My) * sizeof(float2), s, g, d->spec, d->twy, By, 1,
+                     My, g.N[1]);
+  hipLaunchKernelGGL(k_c2r_x, dim3((unsigned)((xlines + lpb - 1) / lpb)), dim3(T),
+                     (size_t)(Mx / 2 + lpb * Mx) * sizeof(float2), s, g, d->spec, u_grid_dev,
+                     d->twx, lpb);
+  (void)ng;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_err(c, e, "kernel launch");
+  return PMFEM_OK;
+}
+
+int pmfem_llg_step(pmfem_ctx* c, double* m_dev, double dt, double alpha, int32_t n_steps,
+                   const double* h_applied) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!m_dev || n_steps < 0 || !(dt > 0.0) || !(alpha >= 0.0))
+    return set_err(c, PMFEM_EINVAL, "bad llg arguments");
+  pmfem_dev* d = c->dev;
+  hipStream_t s = stream_of(c);
+  const int64_t n = d->n;
+  const unsigned b3 = (unsigned)((3 * n + 255) / 256), b1 = (unsigned)((n + 255) / 256);
+  const double pref = -kGamma0 / (1.0 + alpha * alpha);
+  const uint32_t terms = PMFEM_TERM_EX | PMFEM_TERM_MS;
+  for (int32_t st = 0; st < n_steps; ++st) {
+    // stage 1 at m
+    hipLaunchKernelGGL(k_rk_stage, dim3(b3), dim3(256), 0, s, n, m_dev, (const double*)nullptr,
+                       0.0, (double*)nullptr, d->m32);
+    if ((rc = run_heff(c, d->m32, d->h32, terms, h_applied))) return rc;
+    hipLaunchKernelGGL(k_rk_rhs, dim3(b1), dim3(256), 0, s, n, (const double*)m_dev, d->h32, pref,
+                       alpha, d->kk, d->acc, 1.0, 1);
+    const double cs[3] = {0.5 * dt, 0.5 * dt, dt};
+    const double ws[3] = {2.0, 2.0, 1.0};
+    for (int k = 0; k < 3; ++k) {
+      hipLaunchKernelGGL(k_rk_stage, dim3(b3), dim3(256), 0, s, n, (const double*)m_dev,
+                         (const double*)d->kk, cs[k], d->mst, d->m32);
+      if ((rc = run_heff(c, d->m32, d->h32, terms, h_applied))) return rc;
+      hipLaunchKernelGGL(k_rk_rhs, dim3(b1), dim3(256), 0, s, n, (const double*)d->mst, d->h32,
+                         pref, alpha, d->kk, d->acc, ws[k], 0);
+    }
+    hipLaunchKernelGGL(k_rk_final, dim3(b1), dim3(256), 0, s, n, m_dev, (const double*)d->acc,
+                       dt / 6.0);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_err(c, e, "kernel launch");
+  return PMFEM_OK;
+}
+
+int pmfem_energy(pmfem_ctx* c, const double* m_dev, double* e_ex, double* e_ms) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!m_dev || !e_ex || !e_ms) return set_err(c, PMFEM_EINVAL, "bad energy arguments");
+  pmfem_dev* d = c->dev;
+  hipStream_t s = stream_of(c);
+  const int64_t n = d->n;
+  hipLaunchKernelGGL(k_rk_stage, dim3((unsigned)((3 * n + 255) / 256)), dim3(256), 0, s, n, m_dev,
+                     (const double*)nullptr, 0.0, (double*)nullptr, d->m32);
+  if ((rc = run_heff(c, d->m32, d->h32, PMFEM_TERM_EX | PMFEM_TERM_MS, nullptr))) return rc;
+  hipLaunchKernelGGL(k_energy, dim3(d->nparts), dim3(256), 0, s, n, m_dev, (const double*)d->mu,
+                     (const float4*)d->hex, (const float*)d->q, (const float*)d->u, d->part);
+  std::vector<double> part(2 * d->nparts);
+  hipError_t e = hipMemcpyAsync(part.data(), d->part, part.size() * sizeof(double),
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_err(c, e, "energy");
+  double a = 0.0, b = 0.0;
+  for (int i = 0; i < d->nparts; ++i) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
+  }
+  *e_ex = -0.5 * kMu0 * a;
+  *e_ms = 0.5 * kMu0 * b;
+  return PMFEM_OK;
+}
+
+int pmfem_profile_begin(pmfem_ctx* c, int32_t max_calls) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (max_calls < 1 || max_calls > 100000) return set_err(c, PMFEM_EINVAL, "bad max_calls");
+  pmfem_dev* d = c->dev;
+  for (hipEvent_t e : d->ev) (void)hipEventDestroy(e);
+  d->ev.assign((size_t)max_calls * kNumKernels * 2, nullptr);
+  for (auto& e : d->ev) {
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return hip_err(c, r, "hipEventCreate");
+  }
+  d->prof_max = max_calls;
+  d->prof_calls = 0;
+  return PMFEM_OK;
+}
+
+int pmfem_profile_end(pmfem_ctx* c, int32_t* n_kernels, double* ms, int32_t* count,
+                      char (*names)[32]) {
+  int rc = ready(c);
+  if (rc) return rc;
+  pmfem_dev* d = c->dev;
+  hipError_t e = hipStreamSynchronize(stream_of(c));
+  if (e != hipSuccess) return hip_err(c, e, "hipStreamSynchronize");
+  if (n_kernels) *n_kernels = kNumKernels;
+  for (int k = 0; k < kNumKernels; ++k) {
+    double tot = 0.0;
+    int cnt = 0;
+    for (int call = 0; call < d->prof_calls; ++call) {
+      hipEvent_t a = d->ev[((size_t)call * kNumKernels + k) * 2];
+      hipEvent_t b = d->ev[((size_t)call * kNumKernels + k) * 2 + 1];
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, a, b) == hipSuccess) {
+        tot += t;
+        ++cnt;
+      }
+    }
+    if (ms) ms[k] = tot;
+    if (count) count[k] = cnt;
+    if (names) {
+      std::strncpy(names[k], kKernelNames[k], 31);
+      names[k][31] = 0;
+    }
+  }
+  (void)hipGetLastError();  // events of kernels that did not run report errors
+  d->prof_max = 0;
+  d->prof_calls = 0;
+  return PMFEM_OK;
+}
+
+int pmfem_export(pmfem_ctx* c, const char* name, void* out, int64_t* count, int32_t* elem_bytes) {
+  if (!c || !name || !count) return PMFEM_EINVAL;
+  if (!c->built) return set_err(c, PMFEM_ESTATE, "pmfem_build has not succeeded");
+  const HostOps& o = c->ops;
+  const void* src = nullptr;
+  int64_t cnt = 0;
+  int32_t eb = 0;
+  std::vector<double> info;
+  std::string nm(name);
+  if (nm == "mu") { src = o.mu.data(); cnt = (int64_t)o.mu.size(); eb = 8; }
+  else if (nm == "pos") { src = o.pos.data(); cnt = (int64_t)o.pos.size(); eb = 8; }
+  else if (nm == "pos4") { src = o.pos4.data(); cnt = (int64_t)o.pos4.size(); eb = 4; }
+  else if (nm == "box_start") { src = o.box_start.data(); cnt = (int64_t)o.box_start.size(); eb = 4; }
+  else if (nm == "loc_rowptr") { src = o.loc_rowptr.data(); cnt = (int64_t)o.loc_rowptr.size(); eb = 4; }
+  else if (nm == "loc_col") { src = o.loc_col.data(); cnt = (int64_t)o.loc_col.size(); eb = 4; }
+  else if (nm == "loc_val") { src = o.loc_val.data(); cnt = (int64_t)o.loc_val.size(); eb = 4; }
+  else if (nm == "z0_rowptr") { src = o.z0_rowptr.data(); cnt = (int64_t)o.z0_rowptr.size(); eb = 4; }
+  else if (nm == "z0_col") { src = o.z0_col.data(); cnt = (int64_t)o.z0_col.size(); eb = 4; }
+  else if (nm == "z0_val") { src = o.z0_val.data(); cnt = (int64_t)o.z0_val.size(); eb = 4; }
+  else if (nm == "p_rowptr") { src = o.p_rowptr.data(); cnt = (int64_t)o.p_rowptr.size(); eb = 4; }
+  else if (nm == "p_col") { src = o.p_col.data(); cnt = (int64_t)o.p_col.size(); eb = 4; }
+  else if (nm == "p_val") { src = o.p_val.data(); cnt = (int64_t)o.p_val.size(); eb = 4; }
+  else if (nm == "khat") { src = o.khat.data(); cnt = (int64_t)o.khat.size(); eb = 4; }
+  else if (nm == "kgrid") { src = o.kgrid.data(); cnt = (int64_t)o.kgrid.size(); eb = 8; }
+  else if (nm == "unk_of_node") { src = o.unk_of_node.data(); cnt = (int64_t)o.unk_of_node.size(); eb = 8; }
+  else if (nm == "node_of_unk") { src = o.node_of_unk.data(); cnt = (int64_t)o.node_of_unk.size(); eb = 8; }
+  else if (nm == "grid_info") {
+    // N[3], M[3], delta[3], origin[3], hbar, p, r_b, periodic[3]
+    for (int a = 0; a < 3; ++a) info.push_back(o.N[a]);
+    for (int a = 0; a < 3; ++a) info.push_back(o.M[a]);
+    for (int a = 0; a < 3; ++a) info.push_back(o.delta[a]);
+    for (int a = 0; a < 3; ++a) info.push_back(o.origin[a]);
+    info.push_back(o.hbar);
+    info.push_back(o.p);
+    info.push_back(o.rb);
+    for (int a = 0; a < 3; ++a) info.push_back(o.per[a]);
+    src = info.data();
+    cnt = (int64_t)info.size();
+    eb = 8;
+  } else {
+    return set_err(c, PMFEM_EINVAL, "unknown export name: " + nm);
+  }
+  *count = cnt;
+  if (elem_bytes) *elem_bytes = eb;
+  if (out && cnt) std::memcpy(out, src, (size_t)cnt * eb);
+  return PMFEM_OK;
+}
+
+const char* pmfem_last_error(const pmfem_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void pmfem_destroy(pmfem_ctx* c) {
+  if (!c) return;
+  if (c->dev && c->device >= 0) (void)hipSetDevice(c->device);
+  free_dev(c);
+  delete c;
+}
+
+}  // extern "C"

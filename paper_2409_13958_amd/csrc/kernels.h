@@ -1,0 +1,46 @@
+// Kernel declarations and launch parameters shared by kernels.hip and capi.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pmfem {
+
+struct GridParams {
+  int N[3];     // grid points per axis
+  int M[3];     // FFT extents (N periodic, 2N otherwise)
+  int logM[3];
+  int nbox[3];  // boxes per axis
+  int p;        // Lagrange order
+};
+
+__global__ void k_local(int64_t n, const float* m, const int32_t* rp, const int32_t* col,
+                        const float4* ld, const int32_t* zrp, const int32_t* zcol,
+                        const float4* zv, float4* hex, float* q, float* uz, int with_ex,
+                        int with_ms);
+__global__ void k_anterp(GridParams g, const float* q, const float4* pos4,
+                         const int32_t* box_start, const int2* brx, const int2* bry,
+                         const int2* brz, float* Q);
+__global__ void k_r2c_x(GridParams g, const float* Q, float2* spec, const float2* twx,
+                        int lines_per_block);
+__global__ void k_fft_y(GridParams g, float2* spec, const float2* twy, int B, int inverse,
+                        int n_in, int n_out);
+__global__ void k_fft_z_mul(GridParams g, float2* spec, const float* khat, const float2* twz,
+                            int B);
+__global__ void k_c2r_x(GridParams g, const float2* spec, float* U, const float2* twx,
+                        int lines_per_block);
+__global__ void k_interp_corr(GridParams g, int64_t n, const float* U, const float4* pos4,
+                              const int32_t* prp, const int32_t* pcol, const float* pval,
+                              const float* q, const float* uz, float* u);
+__global__ void k_grad(int64_t n, const int32_t* rp, const int32_t* col, const float4* gv,
+                       const float* u, const float4* hex, float* h, float hax, float hay,
+                       float haz, int with_ms);
+__global__ void k_rk_stage(int64_t n, const double* m, const double* k, double c, double* mst,
+                           float* m32);
+__global__ void k_rk_rhs(int64_t n, const double* mst, const float* h, double pref,
+                         double alpha, double* kout, double* acc, double weight, int first);
+__global__ void k_rk_final(int64_t n, double* m, const double* acc, double dt6);
+__global__ void k_energy(int64_t n, const double* m, const double* mu, const float4* hex,
+                         const float* q, const float* u, double* part);
+
+}  // namespace pmfem

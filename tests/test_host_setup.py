@@ -1,0 +1,190 @@
+"""Host setup of the library (FP64 C++) against the FP64 oracle, on the CPU.
+
+A host-only context (device -1) runs the whole setup -- PBC pairing and LCA,
+the periodised P1 operators, the grid PGF and its spectrum, the
+precorrection and the element-exact correction -- and exports the arrays;
+each is compared with the oracle's independent construction.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import model, pgf as opgf
+from paper_2409_13958_amd import meshgen as mg
+
+lib = pytest.importorskip("paper_2409_13958_amd.binding")
+
+
+def _ctx(prob, **kw):
+    c = lib.Context.from_problem(prob, device=-1, **kw)
+    return c
+
+
+def _perm(ctx, orc):
+    n, uon, nou, _ = ctx.query()
+    assert n == orc.n
+    return orc.uk[nou]          # library unknown u -> oracle unknown
+
+
+def _csr(ctx, prefix, width, perm, n):
+    rp = ctx.export(prefix + "_rowptr")
+    col = ctx.export(prefix + "_col")
+    val = ctx.export(prefix + "_val").reshape(-1, width)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    return [sp.csr_matrix((val[:, c].astype(np.float64), (perm[rows], perm[col])), shape=(n, n))
+            for c in range(width)]
+
+
+PROBLEMS = {
+    "film_c1": lambda: mg.film_c1(),
+    "box3d_jitter": lambda: mg.kuhn_box((5, 5, 5), 1e-9, periodic=0b111, jitter=0.2,
+                                        grid=(16, 16, 16)),
+    "wire_small": lambda: mg.wire_c2(R=3e-9, period=6e-9, spacing=1.0e-9, n_layers=6,
+                                     grid=(8, 8, 16)),
+    "film_xz": lambda: mg.kuhn_box((6, 3, 6), 1e-9, periodic=0b101, jitter=0.15,
+                                   grid=(16, 4, 16)),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(PROBLEMS))
+def pair(request):
+    prob = PROBLEMS[request.param]()
+    return prob, _ctx(prob), model.Oracle(prob)
+
+
+def test_unknowns_and_lca(pair):
+    prob, ctx, orc = pair
+    n, uon, nou, bpe = ctx.query()
+    assert n == orc.n
+    assert set(nou.tolist()) == set(orc.reps.tolist())
+    # same classes: nodes share a library unknown iff they share an oracle unknown
+    perm = orc.uk[nou]
+    assert np.array_equal(perm[uon], orc.uk)
+    assert bpe > 0
+
+
+def test_lumped_mass(pair):
+    prob, ctx, orc = pair
+    perm = _perm(ctx, orc)
+    mu = ctx.export("mu")
+    assert np.allclose(mu, orc.ops.mu[perm], rtol=1e-13)
+
+
+def test_local_operators(pair):
+    prob, ctx, orc = pair
+    perm = _perm(ctx, orc)
+    n = orc.n
+    L, Dx, Dy, Dz, Gx, Gy, Gz, _ = _csr(ctx, "loc", 8, perm, n)
+    ops = orc.ops
+    Lo = (-2.0 / model.MU0) * sp.diags(1.0 / ops.mu) @ ops.K
+    for mine, ref in [(L, Lo), (Dx, ops.D[0]), (Dy, ops.D[1]), (Dz, ops.D[2])]:
+        diff = abs(mine - ref).max()
+        assert diff <= 2e-7 * abs(ref).max()
+    for c, Gm in enumerate((Gx, Gy, Gz)):
+        ref = sp.diags(1.0 / ops.mu) @ ops.D[c].T
+        assert abs(Gm - ref).max() <= 2e-7 * abs(ref).max()
+
+
+def test_grid_kernel_and_spectrum(pair):
+    prob, ctx, orc = pair
+    info = ctx.export("grid_info")
+    N, M = info[0:3].astype(int), info[3:6].astype(int)
+    assert np.array_equal(N, orc.aim.grid.N) and np.array_equal(M, orc.aim.grid.M)
+    assert np.allclose(info[6:9], orc.aim.grid.delta, rtol=1e-15)
+    kg = ctx.export("kgrid").reshape(M[2], M[1], M[0]).transpose(2, 1, 0)
+    Ko = orc.aim.K
+    assert np.abs(kg - Ko).max() <= 1e-12 * np.abs(Ko).max()
+    kh = ctx.export("khat").reshape(M[2], M[1], M[0] // 2 + 1).transpose(2, 1, 0)
+    ref = (orc.aim.Khat.real / (4 * np.pi * np.prod(M)))[: M[0] // 2 + 1]
+    assert np.abs(kh - ref).max() <= 1e-6 * np.abs(ref).max()
+
+
+def test_node_stencils(pair):
+    prob, ctx, orc = pair
+    perm = _perm(ctx, orc)
+    p4 = ctx.export("pos4").reshape(-1, 4)
+    xi = (orc.aim.s - orc.aim.st)[perm]
+    assert np.abs(p4[:, :3] - xi).max() < 1e-5
+    packed = p4[:, 3].view(np.uint32).astype(np.int64)
+    st = np.stack([(packed >> (10 * a)) & 1023 for a in range(3)], axis=1)
+    assert np.array_equal(st, orc.aim.st[perm] % orc.aim.grid.N[None, :])
+
+
+def test_precorrection(pair):
+    prob, ctx, orc = pair
+    perm = _perm(ctx, orc)
+    n = orc.n
+    (P,) = _csr(ctx, "p", 1, perm, n)
+    ref = orc.aim.precorrection(np.arange(n)) / (4 * np.pi)
+    assert P.nnz == ref.nnz
+    assert abs(P - ref).max() <= 1e-6 * abs(ref).max()
+
+
+def test_element_correction(pair):
+    prob, ctx, orc = pair
+    perm = _perm(ctx, orc)
+    n = orc.n
+    Zx, Zy, Zz, _ = _csr(ctx, "z0", 4, perm, n)
+    ref = orc.z0(np.arange(n))
+    for mine, r in zip((Zx, Zy, Zz), ref):
+        assert abs(mine - r).max() <= 2e-6 * abs(r).max()
+
+
+@pytest.mark.parametrize("mask,L", [(0b111, [1.0, 1.3, 0.8]), (0b011, [1.0, 1.3, 0.0]),
+                                    (0b100, [0.0, 0.0, 1.2]), (0b010, [0.0, 2.0, 0.0]),
+                                    (0b101, [1.1, 0.0, 0.9])])
+def test_library_pgf_matches_oracle(mask, L):
+    rng = np.random.default_rng(41)
+    r = rng.uniform(-1.5, 1.5, (40, 3))
+    r[0] = 0.0
+    mine = lib.pgf_eval(mask, L, r)
+    ref = np.empty(40)
+    ref[1:] = opgf.pgf(r[1:], mask, np.array(L))
+    ref[0] = opgf.greg0(mask, np.array(L))
+    assert np.allclose(mine, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_errors_are_reported():
+    p = mg.film_c1()
+    c = lib.Context(device=-1)
+    with pytest.raises(lib.PmfemError) as e:
+        c.build()
+    assert e.value.code == lib.Status.ESTATE
+    c.set_mesh(p.xyz, p.tets, p.region)
+    c.set_materials(p.Ms, p.Aex)
+    c.set_periodicity(p.periodic, p.L)
+    c.set_aim((8, 16, 4))            # periodic axis too short for r_b = 2, p = 3
+    with pytest.raises(lib.PmfemError) as e:
+        c.build()
+    assert e.value.code == lib.Status.EGRID
+    c.set_aim((16, 16, 3))           # non-periodic FFT extent 6: not a power of two
+    with pytest.raises(lib.PmfemError) as e:
+        c.build()
+    assert e.value.code == lib.Status.EGRID
+    bad = p.tets.copy()
+    bad[0, 1] = bad[0, 0]            # degenerate tetrahedron
+    c.set_mesh(p.xyz, bad, p.region)
+    c.set_aim((16, 16, 4))
+    with pytest.raises(lib.PmfemError) as e:
+        c.build()
+    assert e.value.code == lib.Status.EMESH
+    c.set_mesh(p.xyz, p.tets, p.region)
+    c.set_materials([-1.0], [1e-11])
+    with pytest.raises(lib.PmfemError) as e:
+        c.build()
+    assert e.value.code == lib.Status.EINVAL
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    import os
+    import re
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    hdr = open(os.path.join(root, "include", "pmfem.h")).read()
+    names = set(re.findall(r"^(?:int|void|const char\s*\*)\s*(pmfem_[a-z_0-9]+)\s*\(", hdr,
+                           flags=re.M))
+    assert len(names) >= 18
+    dll = ctypes.CDLL(lib.LIB_PATH)
+    for nm in sorted(names):
+        assert hasattr(dll, nm), nm
+    assert names == set(lib.EXPORTED)
