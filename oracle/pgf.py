@@ -64,12 +64,15 @@ def _real_space(r, mask, L, eta, skip_origin):
         else:
             ranges.append(np.array([0]))
     out = np.zeros(r.shape[0])
+    reach = (_ERFC_CUT + 2.0) / eta + float(np.linalg.norm(rmax))
     for i in ranges[0]:
         for j in ranges[1]:
             for k in ranges[2]:
                 R = np.array([i * L[0] if 0 in per else 0.0,
                               j * L[1] if 1 in per else 0.0,
                               k * L[2] if 2 in per else 0.0])
+                if np.linalg.norm(R) > reach:
+                    continue        # every term of this image is below the cut
                 d = np.linalg.norm(r + R, axis=1)
                 if skip_origin and i == 0 and j == 0 and k == 0:
                     continue

@@ -30,10 +30,12 @@ def lib_fields(prob, m_nodes, **kw):
     hex_ = torch.empty_like(m)
     q = torch.empty(n, dtype=torch.float32, device="cuda")
     u = torch.empty_like(q)
+    hms = torch.empty_like(m)
     ctx.heff_parts(m, h, q, u, hex_)
+    ctx.heff(m, hms, terms=B.TERM_MS)
     torch.cuda.synchronize()
     return ctx, nou, {k: v.cpu().numpy().astype(np.float64)
-                      for k, v in dict(h=h, hex=hex_, q=q, u=u).items()}
+                      for k, v in dict(h=h, hex=hex_, hms=hms, q=q, u=u).items()}
 
 
 SMALL = {
@@ -61,13 +63,14 @@ def test_heff_parity_small(name):
     m = orc.unknown_values(prob.m)
     H = orc.heff(m, method="aim")[perm]
     Hex = orc.heff(m, method="aim", terms=("ex",))[perm]
+    Hms = orc.heff(m, method="aim", terms=("ms",))[perm]
     q = orc.charges(m)[perm]
     u = orc.potential(m, None, "aim")[perm]
-    assert rel(got["hex"], Hex) <= TOL
-    assert rel(got["q"], q) <= TOL
-    assert rel(got["u"], u) <= TOL
-    assert rel(got["h"] - got["hex"], H - Hex) <= TOL
-    assert rel(got["h"], H) <= TOL
+    errs = {k: rel(got[k], ref) for k, ref in
+            dict(hex=Hex, hms=Hms, h=H, q=q, u=u).items()}
+    print(f"[gpu parity] {name} rel L2: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v <= TOL, (k, v)
 
 
 def test_grid_convolution_alone():
