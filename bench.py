@@ -52,7 +52,7 @@ def kernel_bytes(ctx):
         "k_fft_z_mul": 2 * s_full + khat,
         "k_fft_y_inv": s_full + s_in,
         "k_c2r_x": s_in + ng * 4,
-        "k_interp_corr": n * (16 + 4 + 4 + 4 + 4) + ng * 4 + nP * 8,
+        "k_interp_corr": n * (16 + 4 + 4 + 4 + 4) + ng * 4 + nP * 4,
         "k_grad": n * (4 + 4 + 16 + 12) + nL * 20,
     }
 
@@ -70,12 +70,14 @@ def cpu_baseline(prob, rows_sample=64, seed=7):
     from oracle import model
     t0 = time.perf_counter()
     orc = model.Oracle(prob)
+    log(f"  oracle operators built ({time.perf_counter() - t0:.0f} s)")
     rng = np.random.default_rng(seed)
     rows = np.sort(rng.choice(orc.n, size=rows_sample, replace=False))
     ring = orc.ops.neighbours(rows)
     m = orc.unknown_values(prob.m)
     orc.potential(m, ring, "aim")          # builds and caches the ring's P and Z0 rows
     t_setup = time.perf_counter() - t0
+    log(f"  oracle ring rows built ({t_setup:.0f} s)")
     P = orc._cache[("P", tuple(ring.tolist()))]
     Z = orc.z0(ring)
     A = orc.aim

@@ -23,7 +23,7 @@ struct pmfem_dev {
   float4 *lld = nullptr, *lg = nullptr;
   int32_t *zrp = nullptr, *zcol = nullptr;
   float4* zv = nullptr;
-  int32_t *prp = nullptr, *pcol = nullptr;
+  int32_t* prp = nullptr;
   float* pv = nullptr;
   float* khat = nullptr;
   float2 *twx = nullptr, *twy = nullptr, *twz = nullptr;
@@ -135,7 +135,9 @@ int upload_all(pmfem_ctx* c) {
     d->g.logM[a] = ilog2(o.M[a]);
     d->g.nbox[a] = o.nbox[a];
   }
+  for (int a = 0; a < 3; ++a) d->g.per[a] = o.per[a];
   d->g.p = o.p;
+  d->g.rb = o.rb;
   int rc;
   if ((rc = upload(c, &d->pos4, o.pos4.data(), n))) return rc;
   if ((rc = upload(c, &d->box_start, o.box_start.data(), o.box_start.size()))) return rc;
@@ -160,7 +162,6 @@ int upload_all(pmfem_ctx* c) {
   if ((rc = upload(c, &d->zv, o.z0_val.data(), nnzZ))) return rc;
   const int64_t nnzP = o.p_rowptr[n];
   if ((rc = upload(c, &d->prp, o.p_rowptr.data(), n + 1))) return rc;
-  if ((rc = upload(c, &d->pcol, o.p_col.data(), nnzP))) return rc;
   if ((rc = upload(c, &d->pv, o.p_val.data(), nnzP))) return rc;
   if ((rc = upload(c, &d->khat, o.khat.data(), o.khat.size()))) return rc;
   auto tx = twiddles(o.M[0]), ty = twiddles(o.M[1]), tz = twiddles(o.M[2]);
@@ -211,10 +212,11 @@ int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const doubl
                      with_ms);
   mark(0, 1);
   if (with_ms) {
-    const int64_t ng = (int64_t)g.N[0] * g.N[1] * g.N[2];
+    const int64_t ntiles = (int64_t)((g.N[0] + kAntTX - 1) / kAntTX) *
+                           ((g.N[1] + kAntTY - 1) / kAntTY) * ((g.N[2] + kAntTZ - 1) / kAntTZ);
     mark(1, 0);
-    hipLaunchKernelGGL(k_anterp, dim3((unsigned)((ng + T - 1) / T)), dim3(T), 0, s, g, d->q,
-                       d->pos4, d->box_start, d->brx, d->bry, d->brz, d->grid);
+    hipLaunchKernelGGL(k_anterp, dim3((unsigned)ntiles), dim3(T), 0, s, g, d->q, d->pos4,
+                       d->box_start, d->brx, d->bry, d->brz, d->grid);
     mark(1, 1);
     const int Mx = g.M[0], My = g.M[1], Mz = g.M[2], Hx = Mx / 2 + 1;
     const int lpb = std::max(1, 2048 / Mx);
@@ -249,8 +251,9 @@ int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const doubl
                        d->twx, lpb);
     mark(6, 1);
     mark(7, 0);
-    hipLaunchKernelGGL(k_interp_corr, dim3((unsigned)((n * 64 + T - 1) / T)), dim3(T), 0, s, g, n,
-                       d->grid, d->pos4, d->prp, d->pcol, d->pv, d->q, d->uz, d->u);
+    const int64_t nwg = (int64_t)((g.nbox[0] + kIcXS - 1) / kIcXS) * g.nbox[1] * g.nbox[2];
+    hipLaunchKernelGGL(k_interp_corr, dim3((unsigned)nwg), dim3(T), 0, s, g, d->grid, d->pos4,
+                       d->box_start, d->prp, d->pv, d->q, d->uz, d->u);
     mark(7, 1);
   }
   float hx = 0.f, hy = 0.f, hz = 0.f;
@@ -407,7 +410,7 @@ int pmfem_query(pmfem_ctx* c, int64_t* n_unknowns, int64_t* unknown_of_node,
     b += 2 * spec + khat;                                                // z
     b += 2 * spec;                                                       // y inv
     b += spec + ng * 4;                                                  // c2r
-    b += n * (16 + 4 + 4 + 4 + 4) + ng * 4 + nP * 8;                     // interp+corr
+    b += n * (16 + 4 + 4 + 4 + 4) + ng * 4 + nP * 4;                     // interp+corr
     b += n * (4 + 4 + 16 + 12) + nL * (4 + 16);                          // grad
     *bytes_per_eval = b;
   }

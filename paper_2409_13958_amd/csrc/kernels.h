@@ -11,8 +11,22 @@ struct GridParams {
   int M[3];     // FFT extents (N periodic, 2N otherwise)
   int logM[3];
   int nbox[3];  // boxes per axis
+  int per[3];   // periodic axes
   int p;        // Lagrange order
+  int rb;       // near-region radius in boxes (<= 3)
 };
+
+// anterpolation tile (grid points per workgroup) and staged-node capacity
+constexpr int kAntTX = 8, kAntTY = 8, kAntTZ = 4;
+constexpr int kAntCap = 2560;
+constexpr int kAntHalo = (kAntTX + 6) * (kAntTY + 6) * (kAntTZ + 6) + 1;
+// interpolation/precorrection: observer boxes per workgroup along x and the
+// staged source-charge capacity
+constexpr int kIcXS = 64;
+constexpr int kIcPairs = 49;          // (2 r_b + 1)^2 for r_b <= 3
+constexpr int kIcCols = kIcXS + 6;
+constexpr int kIcQCap = 8192;
+constexpr int kIcKQ = 8;              // per-lane cached source charges (S <= 512)
 
 __global__ void k_local(int64_t n, const float* m, const int32_t* rp, const int32_t* col,
                         const float4* ld, const int32_t* zrp, const int32_t* zcol,
@@ -29,8 +43,8 @@ __global__ void k_fft_z_mul(GridParams g, float2* spec, const float* khat, const
                             int B);
 __global__ void k_c2r_x(GridParams g, const float2* spec, float* U, const float2* twx,
                         int lines_per_block);
-__global__ void k_interp_corr(GridParams g, int64_t n, const float* U, const float4* pos4,
-                              const int32_t* prp, const int32_t* pcol, const float* pval,
+__global__ void k_interp_corr(GridParams g, const float* U, const float4* pos4,
+                              const int32_t* box_start, const int32_t* prp, const float* pval,
                               const float* q, const float* uz, float* u);
 __global__ void k_grad(int64_t n, const int32_t* rp, const int32_t* col, const float4* gv,
                        const float* u, const float4* hex, float* h, float hax, float hay,

@@ -24,12 +24,12 @@ namespace pmfem {
 // helpers
 
 __device__ __forceinline__ float lagrange(int a, float xi, int p) {
-  // basis function a of the Lagrange interpolant through 0..p, at xi
-  float v = 1.0f;
-  for (int c = 0; c <= p; ++c) {
-    if (c == a) continue;
-    v *= (xi - (float)c) / (float)(a - c);
-  }
+  // basis function a of the Lagrange interpolant through 0..p at xi:
+  // prod_{c != a} (xi - c) times 1 / prod_{c != a} (a - c) = (-1)^(p-a) / (a! (p-a)!)
+  const float invf[6] = {1.0f, 1.0f, 0.5f, 1.0f / 6.0f, 1.0f / 24.0f, 1.0f / 120.0f};
+  float v = ((p - a) & 1 ? -1.0f : 1.0f) * invf[a] * invf[p - a];
+  for (int c = 0; c <= p; ++c)
+    if (c != a) v *= (xi - (float)c);
   return v;
 }
 
@@ -89,48 +89,150 @@ __global__ void __launch_bounds__(256) k_local(
 }
 
 // ---------------------------------------------------------------------------
-// anterpolation: one thread per grid point gathers from the boxes whose
-// stencils cover it (box ranges per axis precomputed on the host)
+// anterpolation: one workgroup per tile of kAntTX x kAntTY x kAntTZ grid
+// points. The nodes of every box whose stencil can reach the tile (the
+// tile's halo) are staged once in LDS; then each thread gathers, in a fixed
+// order, the contributions of the boxes covering its grid point (per-axis
+// box ranges precomputed on the host). No atomics; the sum order per grid
+// point is fixed, so the result is reproducible bit for bit.
+
+__device__ void block_exclusive_scan(int* a, int n, int* tmp) {
+  // in-place exclusive scan of a[0..n) by blockDim.x threads; tmp holds
+  // blockDim.x ints; a[n] receives the total
+  const int T = blockDim.x, t = threadIdx.x;
+  const int per = (n + T - 1) / T;
+  const int lo = t * per, hi = min(n, lo + per);
+  int sum = 0;
+  for (int i = lo; i < hi; ++i) sum += a[i];
+  tmp[t] = sum;
+  __syncthreads();
+  for (int d = 1; d < T; d <<= 1) {
+    int v = (t >= d) ? tmp[t - d] : 0;
+    __syncthreads();
+    tmp[t] += v;
+    __syncthreads();
+  }
+  int run = tmp[t] - sum;
+  for (int i = lo; i < hi; ++i) {
+    int c = a[i];
+    a[i] = run;
+    run += c;
+  }
+  if (t == T - 1) a[n] = tmp[T - 1];
+  __syncthreads();
+}
+
+__device__ __forceinline__ int halo_start(const int2* br, int g0, int nbox, int per) {
+  (void)nbox;
+  (void)per;
+  return br[g0].x;
+}
 
 __global__ void __launch_bounds__(256) k_anterp(
     GridParams g, const float* __restrict__ q, const float4* __restrict__ pos4,
     const int32_t* __restrict__ box_start, const int2* __restrict__ brx,
     const int2* __restrict__ bry, const int2* __restrict__ brz, float* __restrict__ Q) {
-  int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t ng = (int64_t)g.N[0] * g.N[1] * g.N[2];
-  if (gid >= ng) return;
-  int gx = (int)(gid % g.N[0]);
-  int gy = (int)((gid / g.N[0]) % g.N[1]);
-  int gz = (int)(gid / ((int64_t)g.N[0] * g.N[1]));
-  int2 rx = brx[gx], ry = bry[gy], rz = brz[gz];
-  float acc = 0.f;
-  for (int iz = 0; iz < rz.y; ++iz) {
-    int bz = rz.x + iz;
-    if (bz >= g.nbox[2]) bz -= g.nbox[2];
-    for (int iy = 0; iy < ry.y; ++iy) {
-      int by = ry.x + iy;
-      if (by >= g.nbox[1]) by -= g.nbox[1];
-      for (int ix = 0; ix < rx.y; ++ix) {
-        int bxx = rx.x + ix;
-        if (bxx >= g.nbox[0]) bxx -= g.nbox[0];
-        int64_t b = ((int64_t)bz * g.nbox[1] + by) * g.nbox[0] + bxx;
-        int s0 = box_start[b], s1 = box_start[b + 1];
-        for (int k = s0; k < s1; ++k) {
-          float4 pp = pos4[k];
-          uint32_t pk = __float_as_uint(pp.w);
-          int ax = gx - st_of(pk, 0);
-          int ay = gy - st_of(pk, 1);
-          int az = gz - st_of(pk, 2);
-          if (ax < 0) ax += g.N[0];
-          if (ay < 0) ay += g.N[1];
-          if (az < 0) az += g.N[2];
-          float w = lagrange(ax, pp.x, g.p) * lagrange(ay, pp.y, g.p) * lagrange(az, pp.z, g.p);
-          acc += w * q[k];
-        }
+  __shared__ int s_off[kAntHalo];
+  __shared__ int s_tmp[256];
+  __shared__ float4 s_nd[kAntCap];
+  __shared__ uint32_t s_st[kAntCap];
+  const int ntx = (g.N[0] + kAntTX - 1) / kAntTX, nty = (g.N[1] + kAntTY - 1) / kAntTY;
+  const int tile = blockIdx.x;
+  const int t0[3] = {(tile % ntx) * kAntTX, ((tile / ntx) % nty) * kAntTY,
+                     (tile / (ntx * nty)) * kAntTZ};
+  const int te[3] = {min(kAntTX, g.N[0] - t0[0]), min(kAntTY, g.N[1] - t0[1]),
+                     min(kAntTZ, g.N[2] - t0[2])};
+  const int2* br[3] = {brx, bry, brz};
+  int hs[3], hc[3];
+  for (int a = 0; a < 3; ++a) {
+    int2 f = br[a][t0[a]], l = br[a][t0[a] + te[a] - 1];
+    hs[a] = f.x;
+    if (g.per[a]) {
+      hc[a] = (te[a] - 1) + g.p + 1;
+    } else {
+      hc[a] = l.x + l.y - f.x;
+    }
+  }
+  const int H = hc[0] * hc[1] * hc[2];
+  auto box_of = [&](int h) -> int64_t {
+    int ix = h % hc[0], iy = (h / hc[0]) % hc[1], iz = h / (hc[0] * hc[1]);
+    int bx = (hs[0] + ix) % g.nbox[0], by = (hs[1] + iy) % g.nbox[1],
+        bz = (hs[2] + iz) % g.nbox[2];
+    return ((int64_t)bz * g.nbox[1] + by) * g.nbox[0] + bx;
+  };
+  for (int h = threadIdx.x; h < H; h += blockDim.x) {
+    int64_t b = box_of(h);
+    s_off[h] = box_start[b + 1] - box_start[b];
+  }
+  __syncthreads();
+  block_exclusive_scan(s_off, H, s_tmp);
+  const int total = s_off[H];
+  if (total == 0) {
+    // no node reaches this tile
+    const int lx = threadIdx.x % kAntTX, ly = (threadIdx.x / kAntTX) % kAntTY,
+              lz = threadIdx.x / (kAntTX * kAntTY);
+    if (lx < te[0] && ly < te[1] && lz < te[2])
+      Q[((int64_t)(t0[2] + lz) * g.N[1] + (t0[1] + ly)) * g.N[0] + (t0[0] + lx)] = 0.f;
+    return;
+  }
+  const bool staged = total <= kAntCap;
+  if (staged) {
+    for (int h = threadIdx.x; h < H; h += blockDim.x) {
+      int64_t b = box_of(h);
+      int k0 = box_start[b], k1 = box_start[b + 1], o = s_off[h];
+      for (int k = k0; k < k1; ++k) {
+        float4 pp = pos4[k];
+        s_nd[o + k - k0] = make_float4(pp.x, pp.y, pp.z, q[k]);
+        s_st[o + k - k0] = __float_as_uint(pp.w);
       }
     }
   }
-  Q[gid] = acc;
+  __syncthreads();
+  const int lx = threadIdx.x % kAntTX, ly = (threadIdx.x / kAntTX) % kAntTY,
+            lz = threadIdx.x / (kAntTX * kAntTY);
+  if (lx >= te[0] || ly >= te[1] || lz >= te[2]) return;
+  const int gx = t0[0] + lx, gy = t0[1] + ly, gz = t0[2] + lz;
+  const int2 rx = brx[gx], ry = bry[gy], rz = brz[gz];
+  // halo-relative first box of this point's ranges (periodic: the halo
+  // starts at the box range of the tile's first point, shifted by one box
+  // per grid point)
+  const int ox = g.per[0] ? lx : rx.x - hs[0];
+  const int oy = g.per[1] ? ly : ry.x - hs[1];
+  const int oz = g.per[2] ? lz : rz.x - hs[2];
+  float acc = 0.f;
+  for (int iz = 0; iz < rz.y; ++iz)
+    for (int iy = 0; iy < ry.y; ++iy) {
+      // the x-boxes of one (y, z) row are consecutive in the halo and their
+      // nodes consecutive in the staged arrays
+      const int h0 = ((oz + iz) * hc[1] + (oy + iy)) * hc[0] + ox;
+      const int k0 = s_off[h0], k1 = s_off[h0 + rx.y];
+      for (int k = k0; k < k1; ++k) {
+        float4 nd;
+        uint32_t pk;
+        if (staged) {
+          nd = s_nd[k];
+          pk = s_st[k];
+        } else {
+          // locate node k of the halo in global memory
+          int lo = h0, hi = h0 + rx.y - 1;
+          while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= k) lo = mid; else hi = mid - 1;
+          }
+          int64_t b = box_of(lo);
+          int kg = box_start[b] + (k - s_off[lo]);
+          float4 pp = pos4[kg];
+          nd = make_float4(pp.x, pp.y, pp.z, q[kg]);
+          pk = __float_as_uint(pp.w);
+        }
+        int ax = gx - st_of(pk, 0), ay = gy - st_of(pk, 1), az = gz - st_of(pk, 2);
+        if (ax < 0) ax += g.N[0];
+        if (ay < 0) ay += g.N[1];
+        if (az < 0) az += g.N[2];
+        acc += nd.w * (lagrange(ax, nd.x, g.p) * lagrange(ay, nd.y, g.p) * lagrange(az, nd.z, g.p));
+      }
+    }
+  Q[((int64_t)gz * g.N[1] + gy) * g.N[0] + gx] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -321,35 +423,205 @@ __global__ void __launch_bounds__(256) k_c2r_x(GridParams g, const float2* __res
 }
 
 // ---------------------------------------------------------------------------
-// interpolation + precorrection: one wavefront per row
+// interpolation + precorrection. All rows of one observer box have the same
+// near boxes, hence the same precorrection columns: for each of the
+// (2 r_b + 1)^2 (dy, dz) pairs, the nodes of the 2 r_b + 1 consecutive boxes
+// along x, in box order. The matrix therefore stores values only (row
+// pointer + values); columns are rebuilt from the box table. One workgroup
+// handles kIcXS observer boxes of one (y, z) box row: it stages the source
+// charges of all windows it needs in LDS once, then each wavefront takes
+// whole observer boxes: it caches the box's window charges and its 64
+// stencil values of U in registers and streams the P rows of the box.
+
+template <int W>
+__device__ __forceinline__ int wave_excl_scan(int v, int lane, int& total) {
+  int x = v;
+#pragma unroll
+  for (int d = 1; d < W; d <<= 1) {
+    int y = __shfl_up(x, d, W);
+    if (lane >= d) x += y;
+  }
+  total = __shfl(x, W - 1, W);
+  return x - v;
+}
+
+__device__ __forceinline__ int wrap_box(int b, int nb, int per, bool& ok) {
+  if (per) {
+    if (b < 0) b += nb;
+    if (b >= nb) b -= nb;
+    ok = true;
+  } else {
+    ok = (b >= 0 && b < nb);
+  }
+  return b;
+}
 
 __global__ void __launch_bounds__(256) k_interp_corr(
-    GridParams g, int64_t n, const float* __restrict__ U, const float4* __restrict__ pos4,
-    const int32_t* __restrict__ prp, const int32_t* __restrict__ pcol,
+    GridParams g, const float* __restrict__ U, const float4* __restrict__ pos4,
+    const int32_t* __restrict__ box_start, const int32_t* __restrict__ prp,
     const float* __restrict__ pval, const float* __restrict__ q, const float* __restrict__ uz,
     float* __restrict__ u) {
-  int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  int lane = threadIdx.x & 63;
-  if (row >= n) return;
-  float4 pp = pos4[row];
-  uint32_t pk = __float_as_uint(pp.w);
-  int sx = st_of(pk, 0), sy = st_of(pk, 1), sz = st_of(pk, 2);
-  const int p1 = g.p + 1;
-  const int nst = p1 * p1 * p1;
-  float acc = 0.f;
-  for (int l = lane; l < nst; l += 64) {
-    int ax = l % p1, ay = (l / p1) % p1, az = l / (p1 * p1);
-    int gx = sx + ax, gy = sy + ay, gz = sz + az;
-    if (gx >= g.N[0]) gx -= g.N[0];
-    if (gy >= g.N[1]) gy -= g.N[1];
-    if (gz >= g.N[2]) gz -= g.N[2];
-    float w = lagrange(ax, pp.x, g.p) * lagrange(ay, pp.y, g.p) * lagrange(az, pp.z, g.p);
-    acc += w * U[((int64_t)gz * g.N[1] + gy) * g.N[0] + gx];
+  __shared__ int s_off[kIcPairs * kIcCols + 1];
+  __shared__ int s_tmp[256];
+  __shared__ float s_q[kIcQCap];
+  const int rb = g.rb, W = 2 * rb + 1, npair = W * W;
+  const int nseg = (g.nbox[0] + kIcXS - 1) / kIcXS;
+  const int seg = blockIdx.x % nseg;
+  const int by = (blockIdx.x / nseg) % g.nbox[1];
+  const int bz = blockIdx.x / (nseg * g.nbox[1]);
+  const int bx0 = seg * kIcXS;
+  const int nobs = min(kIcXS, g.nbox[0] - bx0);
+  const int C = nobs + 2 * rb;  // staged columns: boxes bx0 - rb .. bx0 + nobs - 1 + rb
+  // observer rows of this segment
+  const int64_t brow = ((int64_t)bz * g.nbox[1] + by) * g.nbox[0];
+  const int r_first = box_start[brow + bx0], r_last = box_start[brow + bx0 + nobs];
+  if (r_first == r_last) return;  // uniform across the block
+  auto src_box = [&](int i, int c, bool& ok) -> int64_t {
+    int dy = i % W - rb, dz = i / W - rb;
+    bool okx, oky, okz;
+    int sx = wrap_box(bx0 - rb + c, g.nbox[0], g.per[0], okx);
+    int sy = wrap_box(by + dy, g.nbox[1], g.per[1], oky);
+    int sz = wrap_box(bz + dz, g.nbox[2], g.per[2], okz);
+    ok = okx && oky && okz;
+    return ((int64_t)sz * g.nbox[1] + sy) * g.nbox[0] + sx;
+  };
+  const int NE = npair * C;
+  for (int t = threadIdx.x; t < NE; t += blockDim.x) {
+    bool ok;
+    int64_t b = src_box(t / C, t % C, ok);
+    s_off[t] = ok ? box_start[b + 1] - box_start[b] : 0;
   }
-  int e0 = prp[row], e1 = prp[row + 1];
-  for (int e = e0 + lane; e < e1; e += 64) acc += pval[e] * q[pcol[e]];
-  acc = group_sum<64>(acc);
-  if (lane == 0) u[row] = acc + uz[row];
+  __syncthreads();
+  block_exclusive_scan(s_off, NE, s_tmp);
+  const bool staged = s_off[NE] <= kIcQCap;
+  if (staged) {
+    for (int t = threadIdx.x; t < NE; t += blockDim.x) {
+      bool ok;
+      int64_t b = src_box(t / C, t % C, ok);
+      if (!ok) continue;
+      int k0 = box_start[b], k1 = box_start[b + 1], o = s_off[t];
+      for (int k = k0; k < k1; ++k) s_q[o + k - k0] = q[k];
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int p1 = g.p + 1, nst = p1 * p1 * p1;
+  const int shift = (g.p - 1) / 2;
+  for (int ob = wave; ob < nobs; ob += 4) {
+    const int bx = bx0 + ob;
+    const int r0 = box_start[brow + bx], r1 = box_start[brow + bx + 1];
+    if (r0 == r1) continue;
+    // window of pair i: staged columns [ob, ob + 2 rb]
+    int len = 0, wst = 0;
+    if (lane < npair) {
+      wst = s_off[lane * C + ob];
+      len = s_off[lane * C + ob + 2 * rb + 1] - wst;
+    }
+    int S;
+    const int woff = wave_excl_scan<64>(len, lane, S);
+    const int wend = lane < npair ? woff + len : 0x7fffffff;
+    // source charges of this box's windows, cached per lane (j = lane + 64 k)
+    float qv[kIcKQ];
+    const int nk = (S + 63) >> 6;
+    const bool cached = nk <= kIcKQ;
+    auto charge = [&](int j) -> float {
+      // pair holding local index j: first lane whose window end exceeds j
+      int lo = 0;
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1) {
+        int cand = lo + step - 1;
+        int e = __shfl(wend, cand < 63 ? cand : 63, 64);
+        if (e <= j) lo += step;
+      }
+      int i = lo;
+      int o = __shfl(woff, i, 64), st = __shfl(wst, i, 64);
+      int loc = j - o;
+      if (staged) return s_q[st + loc];
+      // unstaged: walk the window's boxes in global memory
+      for (int c = 0; c <= 2 * rb; ++c) {
+        bool ok;
+        int64_t b = src_box(i, ob + c, ok);
+        if (!ok) continue;
+        int nb = box_start[b + 1] - box_start[b];
+        if (loc < nb) return q[box_start[b] + loc];
+        loc -= nb;
+      }
+      return 0.f;
+    };
+    if (cached) {
+#pragma unroll
+      for (int k = 0; k < kIcKQ; ++k) {
+        float v = 0.f;
+        if (k < nk) {
+          int j = lane + 64 * k;
+          float c = charge(j < S ? j : 0);
+          v = j < S ? c : 0.f;
+        }
+        qv[k] = v;
+      }
+    }
+    // stencil values of U for this box (same start for every row of the box)
+    int sta[3];
+    const int bxyz[3] = {bx, by, bz};
+    for (int a = 0; a < 3; ++a) {
+      int st = bxyz[a] - shift;
+      if (g.per[a]) {
+        if (st < 0) st += g.N[a];
+      } else {
+        st = min(max(st, 0), g.N[a] - g.p - 1);
+      }
+      sta[a] = st;
+    }
+    float uv[4];
+    int lax[4], lay[4], laz[4];
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      int l = lane + 64 * s2;
+      uv[s2] = 0.f;
+      lax[s2] = lay[s2] = laz[s2] = 0;
+      if (l < nst) {
+        int ax = l % p1, ay = (l / p1) % p1, az = l / (p1 * p1);
+        int gx = sta[0] + ax, gy = sta[1] + ay, gz = sta[2] + az;
+        if (gx >= g.N[0]) gx -= g.N[0];
+        if (gy >= g.N[1]) gy -= g.N[1];
+        if (gz >= g.N[2]) gz -= g.N[2];
+        uv[s2] = U[((int64_t)gz * g.N[1] + gy) * g.N[0] + gx];
+        lax[s2] = ax;
+        lay[s2] = ay;
+        laz[s2] = az;
+      }
+    }
+    for (int r = r0; r < r1; ++r) {
+      const int pr = prp[r];
+      const int rl = min(S, prp[r + 1] - pr);  // equal by construction; guards the reads
+      float acc = 0.f;
+      if (cached) {
+        float pv[kIcKQ];
+#pragma unroll
+        for (int k = 0; k < kIcKQ; ++k) {
+          int j = lane + 64 * k;
+          pv[k] = (k < nk && j < rl) ? pval[pr + j] : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < kIcKQ; ++k) acc += pv[k] * qv[k];
+      } else {
+        for (int k = 0; k < nk; ++k) {
+          int j = lane + 64 * k;
+          float c = charge(j < S ? j : 0);
+          if (j < rl) acc += pval[pr + j] * c;
+        }
+      }
+      const float4 xi = pos4[r];
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) {
+        if (lane + 64 * s2 < nst)
+          acc += uv[s2] * (lagrange(lax[s2], xi.x, g.p) * lagrange(lay[s2], xi.y, g.p) *
+                           lagrange(laz[s2], xi.z, g.p));
+      }
+      acc = group_sum<64>(acc);
+      if (lane == 0) u[r] = acc + uz[r];
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -97,7 +97,7 @@ int host_build(pmfem_ctx* c) {
   if (c->precision != 0) return fail(c, PMFEM_EINVAL, "only precision 0 (FP32) is supported");
   const int p = c->order_p, rb = c->near_boxes;
   if (p < 1 || p > 5) return fail(c, PMFEM_EINVAL, "order_p must be in [1, 5]");
-  if (rb < 0 || rb > 6) return fail(c, PMFEM_EINVAL, "near_boxes must be in [0, 6]");
+  if (rb < 0 || rb > 3) return fail(c, PMFEM_EINVAL, "near_boxes must be in [0, 3]");
   if (!(c->z0_radius >= 0.0)) return fail(c, PMFEM_EINVAL, "z0_radius must be >= 0");
   for (int32_t r = 0; r < c->n_regions; ++r) {
     if (!(c->Ms[r] > 0.0)) return fail(c, PMFEM_EINVAL, "Ms must be > 0 in every region");
