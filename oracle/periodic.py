@@ -8,8 +8,9 @@ problem size drops to N' = N - N_PBC.
 
 Reading: the LCA representative of a class is its smallest original node
 index; unknowns are numbered by increasing representative index (the paper's
-"first N' points"). Pairs are found one axis at a time (r_j = r_i + L e_a);
-images along diagonals are reached through chains, which union-find merges.
+"first N' points"). Two nodes pair when they coincide modulo the lattice
+(any combination of periods, which covers the paper's combined shifts and
+the images of a protruding cell).
 
 ``remap`` is Eq. shift_hms (Sec. 3.2.2, protruding cells): shift every
 unknown by whole periods along each periodic axis so that it lies within half
@@ -23,22 +24,31 @@ from scipy.spatial import cKDTree
 
 
 def pbc_pairs(xyz, mask, L, tol_rel=1e-9):
-    """All (parent, child) index pairs with r_child = r_parent + L_a e_a."""
+    """All index pairs (i, j), i < j, whose positions differ by a lattice vector.
+
+    Sec. 2.1 defines T-PBC pairs through shifts gamma L_x + zeta L_y + xi L_z
+    with gamma + zeta + xi > 0, i.e. along single axes and their
+    combinations; a protruding cell can hold images at any lattice offset.
+    Reading: i and j pair when they coincide modulo the lattice, which is
+    found with a periodic KD-tree on the positions wrapped into the cell.
+    """
     xyz = np.asarray(xyz, dtype=np.float64)
-    tol = tol_rel * max(float(np.max(np.abs(L))), float(np.ptp(xyz)))
-    tree = cKDTree(xyz)
-    pairs = []
-    for a in range(3):
-        if not (mask >> a) & 1:
-            continue
-        shifted = xyz.copy()
-        shifted[:, a] += L[a]
-        d, j = tree.query(shifted, distance_upper_bound=tol)
-        ok = np.isfinite(d)
-        pairs.append(np.stack([np.nonzero(ok)[0], j[ok]], axis=1))
-    if not pairs:
+    per = [a for a in range(3) if (mask >> a) & 1]
+    if not per:
         return np.zeros((0, 2), dtype=np.int64)
-    return np.concatenate(pairs).astype(np.int64)
+    tol = tol_rel * max(float(np.max(np.abs(L))), float(np.ptp(xyz)))
+    w = xyz.copy()
+    box = np.empty(3)
+    for a in range(3):
+        if a in per:
+            w[:, a] = np.mod(w[:, a], L[a])
+            w[w[:, a] >= L[a], a] -= L[a]
+            box[a] = L[a]
+        else:
+            w[:, a] -= w[:, a].min()
+            box[a] = 2.0 * np.ptp(xyz[:, a]) + 1.0
+    tree = cKDTree(w, boxsize=box)
+    return tree.query_pairs(tol, output_type="ndarray").astype(np.int64)
 
 
 def lca(n_nodes, pairs):

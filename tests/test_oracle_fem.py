@@ -18,26 +18,41 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
 def brute_pairs(xyz, mask, L, tol):
+    """O(N^2) search over all lattice offsets in {-2..2}^d."""
+    per = [a for a in range(3) if (mask >> a) & 1]
+    offs = np.stack(np.meshgrid(*[np.arange(-2, 3) if a in per else np.array([0])
+                                  for a in range(3)], indexing="ij"), -1).reshape(-1, 3)
     out = set()
-    for a in range(3):
-        if not (mask >> a) & 1:
-            continue
-        for i in range(xyz.shape[0]):
-            d = np.linalg.norm(xyz - (xyz[i] + L[a] * np.eye(3)[a]), axis=1)
+    for i in range(xyz.shape[0]):
+        for o in offs:
+            d = np.linalg.norm(xyz - (xyz[i] + o * L), axis=1)
             for j in np.nonzero(d < tol)[0]:
-                out.add((i, int(j)))
+                if j != i:
+                    out.add((min(i, int(j)), max(i, int(j))))
     return out
 
 
 def test_pairs_match_brute_force_and_c1_count():
     p = mg.film_c1()
     pairs = periodic.pbc_pairs(p.xyz, p.periodic, p.L)
-    assert set(map(tuple, pairs.tolist())) == brute_pairs(p.xyz, p.periodic, p.L, 1e-15)
+    got = set((min(a, b), max(a, b)) for a, b in pairs.tolist())
+    assert got == brute_pairs(p.xyz, p.periodic, p.L, 1e-15)
     uk, reps, npairs = periodic.unknowns(p.xyz, p.periodic, p.L)
     assert reps.size == 200 and p.xyz.shape[0] - reps.size == 42
     # representatives are the smallest index of their class
     for n in range(p.xyz.shape[0]):
         assert reps[uk[n]] <= n
+
+
+def test_pairs_across_combined_shifts():
+    """Images that differ by several periods at once, with no single-axis
+    image in the mesh, still merge (protruding cells produce them)."""
+    L = np.array([1.0, 1.0, 1.0])
+    xyz = np.array([[0.2, 0.3, 0.4], [1.2, -0.7, 0.4], [0.2, 0.3, 2.4], [0.5, 0.5, 0.5]])
+    uk, reps, _ = periodic.unknowns(xyz, 0b111, L)
+    assert uk[0] == uk[1] == uk[2] and uk[3] != uk[0]
+    uk2, _, _ = periodic.unknowns(xyz, 0b011, L)
+    assert uk2[0] == uk2[1] and uk2[2] != uk2[0]
 
 
 def test_corner_class_has_eight_members():
