@@ -7,7 +7,7 @@ one full H_eff = H_ex + H_ms evaluation (all nine kernels) of a fixed
 magnetisation already resident in HBM. Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME]
-                    [--no-cpu-baseline]
+                    [--no-cpu-baseline] [--copy-mib MIB]
 """
 from __future__ import annotations
 
@@ -45,7 +45,7 @@ def kernel_bytes(ctx):
     s_full = float(N[2] * M[1]) * hx * 8    # half-spectrum, all My rows
     khat = hx * M[1] * M[2] * 4
     return {
-        "k_local": n * (12 + 4 + 4) + nL * 20 + nZ * 20 + n * (16 + 4 + 4),
+        "k_local": n * (8 + 12 + 4 + 4) + nL * 16 + nZ * 16,
         "k_anterp": n * (4 + 16) + nbox * 4 + ng * 4,
         "k_r2c_x": ng * 4 + s_in,
         "k_fft_y_fwd": s_in + s_full,
@@ -53,7 +53,7 @@ def kernel_bytes(ctx):
         "k_fft_y_inv": s_full + s_in,
         "k_c2r_x": s_in + ng * 4,
         "k_interp_corr": n * (16 + 4 + 4 + 4 + 4) + ng * 4 + nP * 4,
-        "k_grad": n * (4 + 4 + 16 + 12) + nL * 20,
+        "k_grad": n * (4 + 12 + 4 + 12) + nL * 20,
     }
 
 
@@ -121,6 +121,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", default="composite_c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for --gpus {args.gpus}); "
@@ -141,6 +143,16 @@ def main():
     log(f"setup: N'={n}, model bytes/eval={bpe / 1e9:.3f} GB ({time.perf_counter() - t:.1f} s)")
     m = torch.tensor(prob.m[nou], dtype=torch.float32, device="cuda")
     h = torch.empty_like(m)
+    if args.copy_mib > 0:
+        # a plain copy of known size: HBM counters of a profiled run are scaled
+        # by what they read for it (bytes read = bytes written = copy_mib MiB)
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {args.copy_mib} MiB")
+        del src, dst
     for _ in range(args.warmup):
         ctx.heff(m, h)
     torch.cuda.synchronize()

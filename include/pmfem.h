@@ -43,7 +43,7 @@ typedef enum {
   PMFEM_OK = 0,
   PMFEM_EINVAL = -1,  /* bad argument or material value                    */
   PMFEM_EMESH = -2,   /* invalid mesh (index out of range, volume <= 0)      */
-  PMFEM_EPBC = -3,    /* periodic faces that do not match                   */
+  PMFEM_EPBC = -3,    /* periodic images inside one tetrahedron (too coarse) */
   PMFEM_EGRID = -4,   /* AIM grid unusable (too short, not a power of two)  */
   PMFEM_ENOMEM = -5,  /* host or device allocation failed                   */
   PMFEM_EHIP = -6,    /* HIP runtime error                                  */
@@ -79,15 +79,17 @@ int pmfem_set_materials(pmfem_ctx* ctx, int32_t n_regions, const double* Ms, con
 /*
  * Periodicity (Eq. pm): axis_mask bit0 = x, bit1 = y, bit2 = z; L[3] are
  * the periods in metres (ignored on non-periodic axes). Two nodes form a
- * PBC pair when they differ by L along one periodic axis within
- * match_tol * max(L, mesh extent) (match_tol <= 0 selects 1e-9).
+ * PBC pair when they coincide modulo the lattice (any combination of
+ * periods along the periodic axes, Sec. 2.1) within match_tol * max(L, mesh
+ * extent) (match_tol <= 0 selects 1e-9); all images of one point merge into
+ * one unknown. A tetrahedron holding two images of one point is EPBC.
  */
 int pmfem_set_periodicity(pmfem_ctx* ctx, uint32_t axis_mask, const double L[3],
                           double match_tol);
 
 /*
  * AIM parameters (Sec. 3.2.2): grid[3] points per axis; Lagrange order
- * order_p (1..5) of projection/interpolation; near_boxes = r_b, the
+ * order_p (1..5) of projection/interpolation; near_boxes = r_b (0..3), the
  * per-axis box radius of the precorrection region; z0_radius_edges = kappa,
  * the radius of the element-exact correction in mean edge lengths;
  * precision must be 0 (FP32 grid and operators). On a periodic axis the

@@ -18,17 +18,20 @@ struct pmfem_dev {
   GridParams g{};
   float4* pos4 = nullptr;
   int32_t* box_start = nullptr;
+  int32_t* occ = nullptr;  // boxes holding at least one unknown
+  int n_occ = 0;
   int2 *brx = nullptr, *bry = nullptr, *brz = nullptr;
   int32_t *lrp = nullptr, *lcol = nullptr;
-  float4 *lld = nullptr, *lg = nullptr;
+  float *ldx = nullptr, *ldy = nullptr, *ldz = nullptr;  // charge operator D
+  float4* lgl = nullptr;                                   // {Gx, Gy, Gz, L}
   int32_t *zrp = nullptr, *zcol = nullptr;
-  float4* zv = nullptr;
+  float *zx = nullptr, *zy = nullptr, *zz = nullptr;
   int32_t* prp = nullptr;
   float* pv = nullptr;
   float* khat = nullptr;
   float2 *twx = nullptr, *twy = nullptr, *twz = nullptr;
   double* mu = nullptr;
-  float4* hex = nullptr;
+  float* hex = nullptr;  // [n][3] exchange field for pmfem_energy / heff_parts
   float *q = nullptr, *uz = nullptr, *u = nullptr, *grid = nullptr;
   float2* spec = nullptr;
   double *mst = nullptr, *kk = nullptr, *acc = nullptr;
@@ -141,25 +144,49 @@ int upload_all(pmfem_ctx* c) {
   int rc;
   if ((rc = upload(c, &d->pos4, o.pos4.data(), n))) return rc;
   if ((rc = upload(c, &d->box_start, o.box_start.data(), o.box_start.size()))) return rc;
+  {
+    std::vector<int32_t> occ;
+    for (size_t b = 0; b + 1 < o.box_start.size(); ++b)
+      if (o.box_start[b + 1] > o.box_start[b]) occ.push_back((int32_t)b);
+    d->n_occ = (int)occ.size();
+    if ((rc = upload(c, &d->occ, occ.data(), occ.size()))) return rc;
+  }
   auto bx = box_ranges(o, 0), by = box_ranges(o, 1), bz = box_ranges(o, 2);
   if ((rc = upload(c, &d->brx, bx.data(), bx.size()))) return rc;
   if ((rc = upload(c, &d->bry, by.data(), by.size()))) return rc;
   if ((rc = upload(c, &d->brz, bz.data(), bz.size()))) return rc;
   const int64_t nnzL = o.loc_rowptr[n];
-  std::vector<float4> ld(nnzL), gg(nnzL);
-  for (int64_t e = 0; e < nnzL; ++e) {
-    const float* v = &o.loc_val[8 * e];
-    ld[e] = make_float4(v[0], v[1], v[2], v[3]);
-    gg[e] = make_float4(v[4], v[5], v[6], 0.f);
+  {
+    std::vector<float> dx(nnzL), dy(nnzL), dz(nnzL);
+    std::vector<float4> gl(nnzL);
+    for (int64_t e = 0; e < nnzL; ++e) {
+      const float* v = &o.loc_val[8 * e];  // L, Dx, Dy, Dz, Gx, Gy, Gz, 0
+      dx[e] = v[1];
+      dy[e] = v[2];
+      dz[e] = v[3];
+      gl[e] = make_float4(v[4], v[5], v[6], v[0]);
+    }
+    if ((rc = upload(c, &d->lrp, o.loc_rowptr.data(), n + 1))) return rc;
+    if ((rc = upload(c, &d->lcol, o.loc_col.data(), nnzL))) return rc;
+    if ((rc = upload(c, &d->ldx, dx.data(), nnzL))) return rc;
+    if ((rc = upload(c, &d->ldy, dy.data(), nnzL))) return rc;
+    if ((rc = upload(c, &d->ldz, dz.data(), nnzL))) return rc;
+    if ((rc = upload(c, &d->lgl, gl.data(), nnzL))) return rc;
   }
-  if ((rc = upload(c, &d->lrp, o.loc_rowptr.data(), n + 1))) return rc;
-  if ((rc = upload(c, &d->lcol, o.loc_col.data(), nnzL))) return rc;
-  if ((rc = upload(c, &d->lld, ld.data(), nnzL))) return rc;
-  if ((rc = upload(c, &d->lg, gg.data(), nnzL))) return rc;
   const int64_t nnzZ = o.z0_rowptr[n];
-  if ((rc = upload(c, &d->zrp, o.z0_rowptr.data(), n + 1))) return rc;
-  if ((rc = upload(c, &d->zcol, o.z0_col.data(), nnzZ))) return rc;
-  if ((rc = upload(c, &d->zv, o.z0_val.data(), nnzZ))) return rc;
+  {
+    std::vector<float> zx(nnzZ), zy(nnzZ), zz(nnzZ);
+    for (int64_t e = 0; e < nnzZ; ++e) {
+      zx[e] = o.z0_val[4 * e];
+      zy[e] = o.z0_val[4 * e + 1];
+      zz[e] = o.z0_val[4 * e + 2];
+    }
+    if ((rc = upload(c, &d->zrp, o.z0_rowptr.data(), n + 1))) return rc;
+    if ((rc = upload(c, &d->zcol, o.z0_col.data(), nnzZ))) return rc;
+    if ((rc = upload(c, &d->zx, zx.data(), nnzZ))) return rc;
+    if ((rc = upload(c, &d->zy, zy.data(), nnzZ))) return rc;
+    if ((rc = upload(c, &d->zz, zz.data(), nnzZ))) return rc;
+  }
   const int64_t nnzP = o.p_rowptr[n];
   if ((rc = upload(c, &d->prp, o.p_rowptr.data(), n + 1))) return rc;
   if ((rc = upload(c, &d->pv, o.p_val.data(), nnzP))) return rc;
@@ -169,7 +196,7 @@ int upload_all(pmfem_ctx* c) {
   if ((rc = upload(c, &d->twy, ty.data(), ty.size()))) return rc;
   if ((rc = upload(c, &d->twz, tz.data(), tz.size()))) return rc;
   if ((rc = upload(c, &d->mu, o.mu.data(), n))) return rc;
-  if ((rc = dalloc(c, &d->hex, n))) return rc;
+  if ((rc = dalloc(c, &d->hex, 3 * n))) return rc;
   if ((rc = dalloc(c, &d->q, n))) return rc;
   if ((rc = dalloc(c, &d->uz, n))) return rc;
   if ((rc = dalloc(c, &d->u, n))) return rc;
@@ -206,11 +233,13 @@ int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const doubl
     if (ev) (void)hipEventRecord(ev[2 * k + which], s);
   };
   const int T = 256;
-  mark(0, 0);
-  hipLaunchKernelGGL(k_local, dim3((unsigned)((n * 16 + T - 1) / T)), dim3(T), 0, s, n, m, d->lrp,
-                     d->lcol, d->lld, d->zrp, d->zcol, d->zv, d->hex, d->q, d->uz, with_ex,
-                     with_ms);
-  mark(0, 1);
+  if (with_ms) {
+    mark(0, 0);
+    hipLaunchKernelGGL(k_local, dim3((unsigned)((n * 16 + T - 1) / T)), dim3(T), 0, s, n, m,
+                       d->lrp, d->lcol, d->ldx, d->ldy, d->ldz, d->zrp, d->zcol, d->zx, d->zy,
+                       d->zz, d->q, d->uz);
+    mark(0, 1);
+  }
   if (with_ms) {
     const int64_t ntiles = (int64_t)((g.N[0] + kAntTX - 1) / kAntTX) *
                            ((g.N[1] + kAntTY - 1) / kAntTY) * ((g.N[2] + kAntTZ - 1) / kAntTZ);
@@ -251,9 +280,10 @@ int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const doubl
                        d->twx, lpb);
     mark(6, 1);
     mark(7, 0);
-    const int64_t nwg = (int64_t)((g.nbox[0] + kIcXS - 1) / kIcXS) * g.nbox[1] * g.nbox[2];
-    hipLaunchKernelGGL(k_interp_corr, dim3((unsigned)nwg), dim3(T), 0, s, g, d->grid, d->pos4,
-                       d->box_start, d->prp, d->pv, d->q, d->uz, d->u);
+    const int64_t nwg = (d->n_occ + kIcGroups - 1) / kIcGroups;
+    hipLaunchKernelGGL(k_interp_corr, dim3((unsigned)std::max<int64_t>(nwg, 1)), dim3(T), 0, s, g,
+                       d->n_occ, d->occ, d->grid, d->pos4, d->box_start, d->prp, d->pv, d->q,
+                       d->uz, d->u);
     mark(7, 1);
   }
   float hx = 0.f, hy = 0.f, hz = 0.f;
@@ -264,7 +294,7 @@ int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const doubl
   }
   mark(8, 0);
   hipLaunchKernelGGL(k_grad, dim3((unsigned)((n * 16 + T - 1) / T)), dim3(T), 0, s, n, d->lrp,
-                     d->lcol, d->lg, d->u, d->hex, h, hx, hy, hz, with_ms);
+                     d->lcol, d->lgl, m, d->u, h, hx, hy, hz, with_ex, with_ms);
   mark(8, 1);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_err(c, e, "kernel launch");
@@ -403,7 +433,7 @@ int pmfem_query(pmfem_ctx* c, int64_t* n_unknowns, int64_t* unknown_of_node,
     const double spec = (double)o.N[2] * o.M[1] * hx * 8.0;
     const double khat = hx * o.M[1] * o.M[2] * 4.0;
     double b = 0;
-    b += n * (4 + 12 + 16 + 4 + 4 + 4) + nL * (4 + 16) + nZ * (4 + 16);  // k_local
+    b += n * (8 + 12 + 4 + 4) + nL * (4 + 12) + nZ * (4 + 12);            // k_local
     b += n * (16 + 4) + ng * 4 + (double)o.box_start.size() * 4;       // k_anterp
     b += ng * 4 + spec;                                                  // r2c
     b += 2 * spec;                                                       // y fwd
@@ -411,7 +441,7 @@ int pmfem_query(pmfem_ctx* c, int64_t* n_unknowns, int64_t* unknown_of_node,
     b += 2 * spec;                                                       // y inv
     b += spec + ng * 4;                                                  // c2r
     b += n * (16 + 4 + 4 + 4 + 4) + ng * 4 + nP * 4;                     // interp+corr
-    b += n * (4 + 4 + 16 + 12) + nL * (4 + 16);                          // grad
+    b += n * (8 + 12 + 4 + 12) + nL * (4 + 16);                          // grad
     *bytes_per_eval = b;
   }
   return PMFEM_OK;
@@ -438,8 +468,9 @@ int pmfem_heff_parts(pmfem_ctx* c, const float* m_dev, float* h_dev, float* q_de
   hipError_t e = hipSuccess;
   if (q_dev) e = hipMemcpyAsync(q_dev, d->q, n * 4, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess && u_dev) e = hipMemcpyAsync(u_dev, d->u, n * 4, hipMemcpyDeviceToDevice, s);
-  if (e == hipSuccess && hex_dev)
-    e = hipMemcpy2DAsync(hex_dev, 12, d->hex, 16, 12, n, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && hex_dev) {
+    if ((rc = run_heff(c, m_dev, hex_dev, PMFEM_TERM_EX, nullptr))) return rc;
+  }
   if (e != hipSuccess) return hip_err(c, e, "copy of intermediates");
   return PMFEM_OK;
 }
@@ -527,8 +558,9 @@ int pmfem_energy(pmfem_ctx* c, const double* m_dev, double* e_ex, double* e_ms) 
   hipLaunchKernelGGL(k_rk_stage, dim3((unsigned)((3 * n + 255) / 256)), dim3(256), 0, s, n, m_dev,
                      (const double*)nullptr, 0.0, (double*)nullptr, d->m32);
   if ((rc = run_heff(c, d->m32, d->h32, PMFEM_TERM_EX | PMFEM_TERM_MS, nullptr))) return rc;
+  if ((rc = run_heff(c, d->m32, d->hex, PMFEM_TERM_EX, nullptr))) return rc;
   hipLaunchKernelGGL(k_energy, dim3(d->nparts), dim3(256), 0, s, n, m_dev, (const double*)d->mu,
-                     (const float4*)d->hex, (const float*)d->q, (const float*)d->u, d->part);
+                     (const float*)d->hex, (const float*)d->q, (const float*)d->u, d->part);
   std::vector<double> part(2 * d->nparts);
   hipError_t e = hipMemcpyAsync(part.data(), d->part, part.size() * sizeof(double),
                                 hipMemcpyDeviceToHost, s);

@@ -20,18 +20,18 @@ struct GridParams {
 constexpr int kAntTX = 8, kAntTY = 8, kAntTZ = 4;
 constexpr int kAntCap = 2560;
 constexpr int kAntHalo = (kAntTX + 6) * (kAntTY + 6) * (kAntTZ + 6) + 1;
-// interpolation/precorrection: observer boxes per workgroup along x and the
-// staged source-charge capacity
-constexpr int kIcXS = 64;
-constexpr int kIcPairs = 49;          // (2 r_b + 1)^2 for r_b <= 3
-constexpr int kIcCols = kIcXS + 6;
-constexpr int kIcQCap = 8192;
-constexpr int kIcKQ = 8;              // per-lane cached source charges (S <= 512)
+// interpolation/precorrection: groups of 16 lanes, one observer box each;
+// per-group staged source charges and window table
+constexpr int kIcGroup = 16;
+constexpr int kIcGroups = 16;          // per 256-thread workgroup
+constexpr int kIcGQ = 512;             // staged charges per group
+constexpr int kIcPairs = 49;           // (2 r_b + 1)^2 for r_b <= 3
+constexpr int kIcSeg = 2 * kIcPairs;   // a window splits in two at a periodic wrap
 
 __global__ void k_local(int64_t n, const float* m, const int32_t* rp, const int32_t* col,
-                        const float4* ld, const int32_t* zrp, const int32_t* zcol,
-                        const float4* zv, float4* hex, float* q, float* uz, int with_ex,
-                        int with_ms);
+                        const float* dx, const float* dy, const float* dz, const int32_t* zrp,
+                        const int32_t* zcol, const float* zx, const float* zy, const float* zz,
+                        float* q, float* uz);
 __global__ void k_anterp(GridParams g, const float* q, const float4* pos4,
                          const int32_t* box_start, const int2* brx, const int2* bry,
                          const int2* brz, float* Q);
@@ -43,18 +43,18 @@ __global__ void k_fft_z_mul(GridParams g, float2* spec, const float* khat, const
                             int B);
 __global__ void k_c2r_x(GridParams g, const float2* spec, float* U, const float2* twx,
                         int lines_per_block);
-__global__ void k_interp_corr(GridParams g, const float* U, const float4* pos4,
-                              const int32_t* box_start, const int32_t* prp, const float* pval,
-                              const float* q, const float* uz, float* u);
-__global__ void k_grad(int64_t n, const int32_t* rp, const int32_t* col, const float4* gv,
-                       const float* u, const float4* hex, float* h, float hax, float hay,
-                       float haz, int with_ms);
+__global__ void k_interp_corr(GridParams g, int n_occ, const int32_t* occ, const float* U,
+                              const float4* pos4, const int32_t* box_start, const int32_t* prp,
+                              const float* pval, const float* q, const float* uz, float* u);
+__global__ void k_grad(int64_t n, const int32_t* rp, const int32_t* col, const float4* gl,
+                       const float* m, const float* u, float* h, float hax, float hay, float haz,
+                       int with_ex, int with_ms);
 __global__ void k_rk_stage(int64_t n, const double* m, const double* k, double c, double* mst,
                            float* m32);
 __global__ void k_rk_rhs(int64_t n, const double* mst, const float* h, double pref,
                          double alpha, double* kout, double* acc, double weight, int first);
 __global__ void k_rk_final(int64_t n, double* m, const double* acc, double dt6);
-__global__ void k_energy(int64_t n, const double* m, const double* mu, const float4* hex,
+__global__ void k_energy(int64_t n, const double* m, const double* mu, const float* hex,
                          const float* q, const float* u, double* part);
 
 }  // namespace pmfem

@@ -1,7 +1,7 @@
 // gfx950 kernels of the PM-FEM effective-field evaluation.
 //
 // One H_eff evaluation (paper Eqs. heff, hex, hms_d1 - hms_d3):
-//   k_local        H_ex = L m, q = D m (Eq. hms_d1), u_Z = Z0 m (Eq. hms_d2b)
+//   k_local        q = D m (Eq. hms_d1), u_Z = Z0 m (Eq. hms_d2b)
 //   k_anterp       Q = W^T q                      (Sec. 3.2.2, step 1)
 //   k_r2c_x        real-to-complex FFT along x    (step 2)
 //   k_fft_y        FFT along y (forward)
@@ -9,7 +9,7 @@
 //   k_fft_y        FFT along y (inverse)
 //   k_c2r_x        complex-to-real FFT along x -> U = (1/4 pi) K * Q
 //   k_interp_corr  u = W U + P q + u_Z            (steps 3 and 4)
-//   k_grad         H = H_ex - G u (+ H_applied)   (Eq. hms_d3)
+//   k_grad         H = L m - G u (+ H_applied)    (Eqs. hex/lapl_2, hms_d3)
 // All arithmetic is FP32; every reduction is done in a fixed order inside a
 // wavefront or a thread, so results are bitwise reproducible (no atomics).
 #include <hip/hip_runtime.h>
@@ -33,6 +33,34 @@ __device__ __forceinline__ float lagrange(int a, float xi, int p) {
   return v;
 }
 
+// Cubic (p = 3) Lagrange basis through xi = 0, 1, 2, 3 as a polynomial in the
+// centred variable t = xi - 3/2 (|t| <= 3/2, so no cancellation beyond a few
+// ulps): L_a(t) = c0 + c1 t + c2 t^2 + c3 t^3.
+struct Cubic {
+  float c0, c1, c2, c3;
+};
+
+__device__ __forceinline__ Cubic cubic_basis(int a) {
+  Cubic c;
+  c.c0 = (a == 0 || a == 3) ? -0.0625f : 0.5625f;
+  c.c1 = a == 0 ? (1.0f / 24.0f) : a == 1 ? -1.125f : a == 2 ? 1.125f : -(1.0f / 24.0f);
+  c.c2 = (a == 0 || a == 3) ? 0.25f : -0.25f;
+  c.c3 = a == 0 ? -(1.0f / 6.0f) : a == 1 ? 0.5f : a == 2 ? -0.5f : (1.0f / 6.0f);
+  return c;
+}
+
+__device__ __forceinline__ float cubic_eval(const Cubic& c, float xi) {
+  const float t = xi - 1.5f;
+  return fmaf(fmaf(fmaf(c.c3, t, c.c2), t, c.c1), t, c.c0);
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  // make this wavefront's LDS writes visible to its own other lanes
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ int st_of(uint32_t packed, int axis) {
   return (int)((packed >> (10 * axis)) & 1023u);
 }
@@ -46,45 +74,36 @@ __device__ __forceinline__ float group_sum(float v) {
 }
 
 // ---------------------------------------------------------------------------
-// local operators: 16 lanes per row
+// charges and element-exact correction: 16 lanes per row
+//   q_n   = sum_k D_nk . m_k          (local pattern, D stored as three arrays)
+//   u_Z,n = sum_j Z0_nj . m_j          (element-correction pattern)
 
 __global__ void __launch_bounds__(256) k_local(
     int64_t n, const float* __restrict__ m, const int32_t* __restrict__ rp,
-    const int32_t* __restrict__ col, const float4* __restrict__ ld,
-    const int32_t* __restrict__ zrp, const int32_t* __restrict__ zcol,
-    const float4* __restrict__ zv, float4* __restrict__ hex, float* __restrict__ q,
-    float* __restrict__ uz, int with_ex, int with_ms) {
+    const int32_t* __restrict__ col, const float* __restrict__ dx, const float* __restrict__ dy,
+    const float* __restrict__ dz, const int32_t* __restrict__ zrp,
+    const int32_t* __restrict__ zcol, const float* __restrict__ zx,
+    const float* __restrict__ zy, const float* __restrict__ zz, float* __restrict__ q,
+    float* __restrict__ uz) {
   int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
   int lane = threadIdx.x & 15;
   if (row >= n) return;
-  float hx = 0.f, hy = 0.f, hz = 0.f, qq = 0.f, zz = 0.f;
-  int e0 = rp[row], e1 = rp[row + 1];
+  float qq = 0.f, uu = 0.f;
+  const int e0 = rp[row], e1 = rp[row + 1];
+  const int z0 = zrp[row], z1 = zrp[row + 1];
   for (int e = e0 + lane; e < e1; e += 16) {
-    int k = col[e];
-    float4 w = ld[e];
-    float mx = m[3 * (int64_t)k], my = m[3 * (int64_t)k + 1], mz = m[3 * (int64_t)k + 2];
-    hx += w.x * mx;
-    hy += w.x * my;
-    hz += w.x * mz;
-    qq += w.y * mx + w.z * my + w.w * mz;
+    const int64_t k = col[e];
+    qq += dx[e] * m[3 * k] + dy[e] * m[3 * k + 1] + dz[e] * m[3 * k + 2];
   }
-  if (with_ms) {
-    int z0 = zrp[row], z1 = zrp[row + 1];
-    for (int e = z0 + lane; e < z1; e += 16) {
-      int k = zcol[e];
-      float4 w = zv[e];
-      zz += w.x * m[3 * (int64_t)k] + w.y * m[3 * (int64_t)k + 1] + w.z * m[3 * (int64_t)k + 2];
-    }
+  for (int e = z0 + lane; e < z1; e += 16) {
+    const int64_t k = zcol[e];
+    uu += zx[e] * m[3 * k] + zy[e] * m[3 * k + 1] + zz[e] * m[3 * k + 2];
   }
-  hx = group_sum<16>(hx);
-  hy = group_sum<16>(hy);
-  hz = group_sum<16>(hz);
   qq = group_sum<16>(qq);
-  zz = group_sum<16>(zz);
+  uu = group_sum<16>(uu);
   if (lane == 0) {
-    hex[row] = with_ex ? make_float4(hx, hy, hz, 0.f) : make_float4(0.f, 0.f, 0.f, 0.f);
     q[row] = qq;
-    uz[row] = zz;
+    uz[row] = uu;
   }
 }
 
@@ -122,10 +141,10 @@ __device__ void block_exclusive_scan(int* a, int n, int* tmp) {
   __syncthreads();
 }
 
-__device__ __forceinline__ int halo_start(const int2* br, int g0, int nbox, int per) {
-  (void)nbox;
-  (void)per;
-  return br[g0].x;
+// stencil start of box b along an axis (unwrapped for periodic axes)
+__device__ __forceinline__ int box_stencil_start(int b, int N, int p, int per) {
+  const int s0 = b - (p - 1) / 2;
+  return per ? s0 : min(max(s0, 0), N - p - 1);
 }
 
 __global__ void __launch_bounds__(256) k_anterp(
@@ -134,8 +153,7 @@ __global__ void __launch_bounds__(256) k_anterp(
     const int2* __restrict__ bry, const int2* __restrict__ brz, float* __restrict__ Q) {
   __shared__ int s_off[kAntHalo];
   __shared__ int s_tmp[256];
-  __shared__ float4 s_nd[kAntCap];
-  __shared__ uint32_t s_st[kAntCap];
+  __shared__ float4 s_nd[kAntCap];  // xi_x, xi_y, xi_z, q of the staged nodes
   const int ntx = (g.N[0] + kAntTX - 1) / kAntTX, nty = (g.N[1] + kAntTY - 1) / kAntTY;
   const int tile = blockIdx.x;
   const int t0[3] = {(tile % ntx) * kAntTX, ((tile / ntx) % nty) * kAntTY,
@@ -145,93 +163,89 @@ __global__ void __launch_bounds__(256) k_anterp(
   const int2* br[3] = {brx, bry, brz};
   int hs[3], hc[3];
   for (int a = 0; a < 3; ++a) {
-    int2 f = br[a][t0[a]], l = br[a][t0[a] + te[a] - 1];
+    const int2 f = br[a][t0[a]], l = br[a][t0[a] + te[a] - 1];
     hs[a] = f.x;
-    if (g.per[a]) {
-      hc[a] = (te[a] - 1) + g.p + 1;
-    } else {
-      hc[a] = l.x + l.y - f.x;
-    }
+    hc[a] = g.per[a] ? (te[a] - 1) + g.p + 1 : l.x + l.y - f.x;
   }
   const int H = hc[0] * hc[1] * hc[2];
   auto box_of = [&](int h) -> int64_t {
-    int ix = h % hc[0], iy = (h / hc[0]) % hc[1], iz = h / (hc[0] * hc[1]);
-    int bx = (hs[0] + ix) % g.nbox[0], by = (hs[1] + iy) % g.nbox[1],
-        bz = (hs[2] + iz) % g.nbox[2];
+    const int ix = h % hc[0], iy = (h / hc[0]) % hc[1], iz = h / (hc[0] * hc[1]);
+    const int bx = (hs[0] + ix) % g.nbox[0], by = (hs[1] + iy) % g.nbox[1],
+              bz = (hs[2] + iz) % g.nbox[2];
     return ((int64_t)bz * g.nbox[1] + by) * g.nbox[0] + bx;
   };
   for (int h = threadIdx.x; h < H; h += blockDim.x) {
-    int64_t b = box_of(h);
+    const int64_t b = box_of(h);
     s_off[h] = box_start[b + 1] - box_start[b];
   }
   __syncthreads();
   block_exclusive_scan(s_off, H, s_tmp);
   const int total = s_off[H];
-  if (total == 0) {
-    // no node reaches this tile
-    const int lx = threadIdx.x % kAntTX, ly = (threadIdx.x / kAntTX) % kAntTY,
-              lz = threadIdx.x / (kAntTX * kAntTY);
-    if (lx < te[0] && ly < te[1] && lz < te[2])
-      Q[((int64_t)(t0[2] + lz) * g.N[1] + (t0[1] + ly)) * g.N[0] + (t0[0] + lx)] = 0.f;
+  const int lx = threadIdx.x % kAntTX, ly = (threadIdx.x / kAntTX) % kAntTY,
+            lz = threadIdx.x / (kAntTX * kAntTY);
+  const bool inside = lx < te[0] && ly < te[1] && lz < te[2];
+  const int gx = t0[0] + lx, gy = t0[1] + ly, gz = t0[2] + lz;
+  if (total == 0) {  // no node reaches this tile (uniform across the block)
+    if (inside) Q[((int64_t)gz * g.N[1] + gy) * g.N[0] + gx] = 0.f;
     return;
   }
   const bool staged = total <= kAntCap;
   if (staged) {
     for (int h = threadIdx.x; h < H; h += blockDim.x) {
-      int64_t b = box_of(h);
-      int k0 = box_start[b], k1 = box_start[b + 1], o = s_off[h];
+      const int64_t b = box_of(h);
+      const int k0 = box_start[b], k1 = box_start[b + 1], o = s_off[h];
       for (int k = k0; k < k1; ++k) {
-        float4 pp = pos4[k];
+        const float4 pp = pos4[k];
         s_nd[o + k - k0] = make_float4(pp.x, pp.y, pp.z, q[k]);
-        s_st[o + k - k0] = __float_as_uint(pp.w);
       }
     }
   }
   __syncthreads();
-  const int lx = threadIdx.x % kAntTX, ly = (threadIdx.x / kAntTX) % kAntTY,
-            lz = threadIdx.x / (kAntTX * kAntTY);
-  if (lx >= te[0] || ly >= te[1] || lz >= te[2]) return;
-  const int gx = t0[0] + lx, gy = t0[1] + ly, gz = t0[2] + lz;
+  if (!inside) return;
   const int2 rx = brx[gx], ry = bry[gy], rz = brz[gz];
-  // halo-relative first box of this point's ranges (periodic: the halo
-  // starts at the box range of the tile's first point, shifted by one box
-  // per grid point)
+  // halo-relative first box of this point's ranges
   const int ox = g.per[0] ? lx : rx.x - hs[0];
   const int oy = g.per[1] ? ly : ry.x - hs[1];
   const int oz = g.per[2] ? lz : rz.x - hs[2];
   float acc = 0.f;
-  for (int iz = 0; iz < rz.y; ++iz)
+  // stencil index of the point in the k-th box of its range: on a periodic
+  // axis the k-th box starts its stencil k - p points before the point; on a
+  // non-periodic axis the (clamped) stencil start of that box decides
+  for (int iz = 0; iz < rz.y; ++iz) {
+    const int az = g.per[2] ? g.p - iz : gz - box_stencil_start(rz.x + iz, g.N[2], g.p, 0);
     for (int iy = 0; iy < ry.y; ++iy) {
-      // the x-boxes of one (y, z) row are consecutive in the halo and their
-      // nodes consecutive in the staged arrays
-      const int h0 = ((oz + iz) * hc[1] + (oy + iy)) * hc[0] + ox;
-      const int k0 = s_off[h0], k1 = s_off[h0 + rx.y];
-      for (int k = k0; k < k1; ++k) {
-        float4 nd;
-        uint32_t pk;
-        if (staged) {
-          nd = s_nd[k];
-          pk = s_st[k];
-        } else {
-          // locate node k of the halo in global memory
-          int lo = h0, hi = h0 + rx.y - 1;
-          while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] <= k) lo = mid; else hi = mid - 1;
-          }
-          int64_t b = box_of(lo);
-          int kg = box_start[b] + (k - s_off[lo]);
-          float4 pp = pos4[kg];
-          nd = make_float4(pp.x, pp.y, pp.z, q[kg]);
-          pk = __float_as_uint(pp.w);
+      const int ay = g.per[1] ? g.p - iy : gy - box_stencil_start(ry.x + iy, g.N[1], g.p, 0);
+      const int hrow = ((oz + iz) * hc[1] + (oy + iy)) * hc[0] + ox;
+      for (int ix = 0; ix < rx.y; ++ix) {
+        const int ax = g.per[0] ? g.p - ix : gx - box_stencil_start(rx.x + ix, g.N[0], g.p, 0);
+        const int k0 = s_off[hrow + ix], k1 = s_off[hrow + ix + 1];
+        if (k0 == k1) continue;
+        // nodes of one box: all share (ax, ay, az)
+        const bool cubic = g.p == 3;
+        Cubic cx, cy, cz;
+        if (cubic) {
+          cx = cubic_basis(ax);
+          cy = cubic_basis(ay);
+          cz = cubic_basis(az);
         }
-        int ax = gx - st_of(pk, 0), ay = gy - st_of(pk, 1), az = gz - st_of(pk, 2);
-        if (ax < 0) ax += g.N[0];
-        if (ay < 0) ay += g.N[1];
-        if (az < 0) az += g.N[2];
-        acc += nd.w * (lagrange(ax, nd.x, g.p) * lagrange(ay, nd.y, g.p) * lagrange(az, nd.z, g.p));
+        for (int k = k0; k < k1; ++k) {
+          float4 nd;
+          if (staged) {
+            nd = s_nd[k];
+          } else {
+            const int64_t b = box_of(hrow + ix);
+            const int kg = box_start[b] + (k - k0);
+            const float4 pp = pos4[kg];
+            nd = make_float4(pp.x, pp.y, pp.z, q[kg]);
+          }
+          const float w = cubic ? cubic_eval(cx, nd.x) * cubic_eval(cy, nd.y) * cubic_eval(cz, nd.z)
+                                : lagrange(ax, nd.x, g.p) * lagrange(ay, nd.y, g.p) *
+                                      lagrange(az, nd.z, g.p);
+          acc = fmaf(nd.w, w, acc);
+        }
       }
     }
+  }
   Q[((int64_t)gz * g.N[1] + gy) * g.N[0] + gx] = acc;
 }
 
@@ -426,236 +440,246 @@ __global__ void __launch_bounds__(256) k_c2r_x(GridParams g, const float2* __res
 // interpolation + precorrection. All rows of one observer box have the same
 // near boxes, hence the same precorrection columns: for each of the
 // (2 r_b + 1)^2 (dy, dz) pairs, the nodes of the 2 r_b + 1 consecutive boxes
-// along x, in box order. The matrix therefore stores values only (row
-// pointer + values); columns are rebuilt from the box table. One workgroup
-// handles kIcXS observer boxes of one (y, z) box row: it stages the source
-// charges of all windows it needs in LDS once, then each wavefront takes
-// whole observer boxes: it caches the box's window charges and its 64
-// stencil values of U in registers and streams the P rows of the box.
+// along x (a run that splits in two where a periodic x axis wraps), in box
+// order. The matrix therefore stores values only; the columns are rebuilt
+// from the box table. Each group of 16 lanes takes one occupied observer
+// box: it gathers the box's source charges into its own LDS slice in column
+// order, prefetches the first row's matrix values, then for every row of
+// the box forms W U (64 stencil values of the box, weights from the row's
+// local coordinates) plus P q, reduced in a fixed order.
 
 template <int W>
-__device__ __forceinline__ int wave_excl_scan(int v, int lane, int& total) {
+__device__ __forceinline__ int group_excl_scan(int v, int lane, int& total) {
   int x = v;
 #pragma unroll
   for (int d = 1; d < W; d <<= 1) {
-    int y = __shfl_up(x, d, W);
+    const int y = __shfl_up(x, d, W);
     if (lane >= d) x += y;
   }
   total = __shfl(x, W - 1, W);
   return x - v;
 }
 
-__device__ __forceinline__ int wrap_box(int b, int nb, int per, bool& ok) {
-  if (per) {
-    if (b < 0) b += nb;
-    if (b >= nb) b -= nb;
-    ok = true;
-  } else {
-    ok = (b >= 0 && b < nb);
+struct Window {
+  int sA, nA, sB, nB;  // node runs [sA, sA + nA) then [sB, sB + nB)
+};
+
+// source nodes of pair i (dy, dz) for observer box (bx, by, bz)
+__device__ __forceinline__ Window pair_window(const GridParams& g, const int32_t* box_start,
+                                              int i, int bx, int by, int bz) {
+  Window w{0, 0, 0, 0};
+  const int W = 2 * g.rb + 1;
+  int y = by + i % W - g.rb, z = bz + i / W - g.rb;
+  if (g.per[1]) {
+    if (y < 0) y += g.nbox[1];
+    if (y >= g.nbox[1]) y -= g.nbox[1];
+  } else if (y < 0 || y >= g.nbox[1]) {
+    return w;
   }
-  return b;
+  if (g.per[2]) {
+    if (z < 0) z += g.nbox[2];
+    if (z >= g.nbox[2]) z -= g.nbox[2];
+  } else if (z < 0 || z >= g.nbox[2]) {
+    return w;
+  }
+  const int64_t row = ((int64_t)z * g.nbox[1] + y) * g.nbox[0];
+  const int nbx = g.nbox[0];
+  int lo = bx - g.rb, hi = bx + g.rb;
+  int a0, a1, b0 = 0, b1 = -1;
+  if (g.per[0]) {
+    if (lo < 0) {
+      a0 = lo + nbx; a1 = nbx - 1; b0 = 0; b1 = hi;
+    } else if (hi >= nbx) {
+      a0 = lo; a1 = nbx - 1; b0 = 0; b1 = hi - nbx;
+    } else {
+      a0 = lo; a1 = hi;
+    }
+  } else {
+    a0 = max(lo, 0);
+    a1 = min(hi, nbx - 1);
+  }
+  w.sA = box_start[row + a0];
+  w.nA = box_start[row + a1 + 1] - w.sA;
+  if (b1 >= b0) {
+    w.sB = box_start[row + b0];
+    w.nB = box_start[row + b1 + 1] - w.sB;
+  }
+  return w;
 }
 
 __global__ void __launch_bounds__(256) k_interp_corr(
-    GridParams g, const float* __restrict__ U, const float4* __restrict__ pos4,
-    const int32_t* __restrict__ box_start, const int32_t* __restrict__ prp,
-    const float* __restrict__ pval, const float* __restrict__ q, const float* __restrict__ uz,
-    float* __restrict__ u) {
-  __shared__ int s_off[kIcPairs * kIcCols + 1];
-  __shared__ int s_tmp[256];
-  __shared__ float s_q[kIcQCap];
-  const int rb = g.rb, W = 2 * rb + 1, npair = W * W;
-  const int nseg = (g.nbox[0] + kIcXS - 1) / kIcXS;
-  const int seg = blockIdx.x % nseg;
-  const int by = (blockIdx.x / nseg) % g.nbox[1];
-  const int bz = blockIdx.x / (nseg * g.nbox[1]);
-  const int bx0 = seg * kIcXS;
-  const int nobs = min(kIcXS, g.nbox[0] - bx0);
-  const int C = nobs + 2 * rb;  // staged columns: boxes bx0 - rb .. bx0 + nobs - 1 + rb
-  // observer rows of this segment
-  const int64_t brow = ((int64_t)bz * g.nbox[1] + by) * g.nbox[0];
-  const int r_first = box_start[brow + bx0], r_last = box_start[brow + bx0 + nobs];
-  if (r_first == r_last) return;  // uniform across the block
-  auto src_box = [&](int i, int c, bool& ok) -> int64_t {
-    int dy = i % W - rb, dz = i / W - rb;
-    bool okx, oky, okz;
-    int sx = wrap_box(bx0 - rb + c, g.nbox[0], g.per[0], okx);
-    int sy = wrap_box(by + dy, g.nbox[1], g.per[1], oky);
-    int sz = wrap_box(bz + dz, g.nbox[2], g.per[2], okz);
-    ok = okx && oky && okz;
-    return ((int64_t)sz * g.nbox[1] + sy) * g.nbox[0] + sx;
-  };
-  const int NE = npair * C;
-  for (int t = threadIdx.x; t < NE; t += blockDim.x) {
-    bool ok;
-    int64_t b = src_box(t / C, t % C, ok);
-    s_off[t] = ok ? box_start[b + 1] - box_start[b] : 0;
+    GridParams g, int n_occ, const int32_t* __restrict__ occ, const float* __restrict__ U,
+    const float4* __restrict__ pos4, const int32_t* __restrict__ box_start,
+    const int32_t* __restrict__ prp, const float* __restrict__ pval,
+    const float* __restrict__ q, const float* __restrict__ uz, float* __restrict__ u) {
+  constexpr int G = kIcGroup;
+  constexpr int KP = 16;  // prefetched matrix values per lane (rows up to 256 entries)
+  __shared__ float s_qg[kIcGroups][kIcGQ];
+  const int lane = threadIdx.x & (G - 1);
+  const int grp = threadIdx.x / G;
+  const int gid = blockIdx.x * kIcGroups + grp;
+  const bool live = gid < n_occ;
+  const int B = live ? occ[gid] : 0;
+  const int bx = B % g.nbox[0], by = (B / g.nbox[0]) % g.nbox[1], bz = B / (g.nbox[0] * g.nbox[1]);
+  const int r0 = live ? box_start[B] : 0, r1 = live ? box_start[B + 1] : 0;
+  // prefetch the first row's matrix values
+  const int pr0 = live ? prp[r0] : 0;
+  const int rl0 = live ? prp[r0 + 1] - pr0 : 0;
+  float pv[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int j = lane + G * k;
+    pv[k] = j < rl0 ? pval[pr0 + j] : 0.f;
   }
-  __syncthreads();
-  block_exclusive_scan(s_off, NE, s_tmp);
-  const bool staged = s_off[NE] <= kIcQCap;
-  if (staged) {
-    for (int t = threadIdx.x; t < NE; t += blockDim.x) {
-      bool ok;
-      int64_t b = src_box(t / C, t % C, ok);
-      if (!ok) continue;
-      int k0 = box_start[b], k1 = box_start[b + 1], o = s_off[t];
-      for (int k = k0; k < k1; ++k) s_q[o + k - k0] = q[k];
+  // gather the source charges of the box's windows in column order
+  const int W = 2 * g.rb + 1, npair = W * W;
+  int S = 0;
+  for (int t = 0; t * G < npair; ++t) {
+    const int i = t * G + lane;
+    Window w{0, 0, 0, 0};
+    if (live && i < npair) w = pair_window(g, box_start, i, bx, by, bz);
+    int tot;
+    const int off = S + group_excl_scan<G>(w.nA + w.nB, lane, tot);
+    S += tot;
+    if (off + w.nA + w.nB <= kIcGQ) {
+      for (int c = 0; c < w.nA; ++c) s_qg[grp][off + c] = q[w.sA + c];
+      for (int c = 0; c < w.nB; ++c) s_qg[grp][off + w.nA + c] = q[w.sB + c];
     }
   }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int p1 = g.p + 1, nst = p1 * p1 * p1;
+  const bool staged = S <= kIcGQ;
+  wave_lds_sync();
+  // stencil of the box: lane holds the 4 values (ax, ay) = (lane % 4, lane / 4), az = 0..3
   const int shift = (g.p - 1) / 2;
-  for (int ob = wave; ob < nobs; ob += 4) {
-    const int bx = bx0 + ob;
-    const int r0 = box_start[brow + bx], r1 = box_start[brow + bx + 1];
-    if (r0 == r1) continue;
-    // window of pair i: staged columns [ob, ob + 2 rb]
-    int len = 0, wst = 0;
-    if (lane < npair) {
-      wst = s_off[lane * C + ob];
-      len = s_off[lane * C + ob + 2 * rb + 1] - wst;
+  const bool cubic = g.p == 3;
+  int sta[3];
+  const int bxyz[3] = {bx, by, bz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    int st = bxyz[a] - shift;
+    if (g.per[a]) {
+      if (st < 0) st += g.N[a];
+    } else {
+      st = min(max(st, 0), g.N[a] - g.p - 1);
     }
-    int S;
-    const int woff = wave_excl_scan<64>(len, lane, S);
-    const int wend = lane < npair ? woff + len : 0x7fffffff;
-    // source charges of this box's windows, cached per lane (j = lane + 64 k)
-    float qv[kIcKQ];
-    const int nk = (S + 63) >> 6;
-    const bool cached = nk <= kIcKQ;
-    auto charge = [&](int j) -> float {
-      // pair holding local index j: first lane whose window end exceeds j
-      int lo = 0;
+    sta[a] = st;
+  }
+  const int lax = lane & 3, lay = lane >> 2;
+  float uv[4] = {0.f, 0.f, 0.f, 0.f};
+  if (cubic && live) {
+    int gx = sta[0] + lax, gy = sta[1] + lay;
+    if (gx >= g.N[0]) gx -= g.N[0];
+    if (gy >= g.N[1]) gy -= g.N[1];
 #pragma unroll
-      for (int step = 32; step >= 1; step >>= 1) {
-        int cand = lo + step - 1;
-        int e = __shfl(wend, cand < 63 ? cand : 63, 64);
-        if (e <= j) lo += step;
-      }
-      int i = lo;
-      int o = __shfl(woff, i, 64), st = __shfl(wst, i, 64);
-      int loc = j - o;
-      if (staged) return s_q[st + loc];
-      // unstaged: walk the window's boxes in global memory
-      for (int c = 0; c <= 2 * rb; ++c) {
-        bool ok;
-        int64_t b = src_box(i, ob + c, ok);
-        if (!ok) continue;
-        int nb = box_start[b + 1] - box_start[b];
-        if (loc < nb) return q[box_start[b] + loc];
-        loc -= nb;
-      }
-      return 0.f;
-    };
-    if (cached) {
+    for (int az = 0; az < 4; ++az) {
+      int gz = sta[2] + az;
+      if (gz >= g.N[2]) gz -= g.N[2];
+      uv[az] = U[((int64_t)gz * g.N[1] + gy) * g.N[0] + gx];
+    }
+  }
+  const Cubic cx = cubic_basis(lax), cy = cubic_basis(lay);
+  const Cubic cz0 = cubic_basis(0), cz1 = cubic_basis(1), cz2 = cubic_basis(2), cz3 = cubic_basis(3);
+  // rows: the wave runs as many rounds as its largest box has rows
+  int nr = r1 - r0;
+  int maxr = nr;
 #pragma unroll
-      for (int k = 0; k < kIcKQ; ++k) {
-        float v = 0.f;
-        if (k < nk) {
-          int j = lane + 64 * k;
-          float c = charge(j < S ? j : 0);
-          v = j < S ? c : 0.f;
+  for (int o = 32; o >= G; o >>= 1) maxr = max(maxr, __shfl_xor(maxr, o, 64));
+  for (int rr = 0; rr < maxr; ++rr) {
+    const bool act = rr < nr;
+    const int r = r0 + rr;
+    float acc = 0.f;
+    if (act) {
+      const int pr = rr == 0 ? pr0 : prp[r];
+      // the row length equals S by construction; the min keeps every read in bounds
+      const int rl = min(S, rr == 0 ? rl0 : prp[r + 1] - pr);
+      if (staged) {
+        if (rr == 0) {
+#pragma unroll
+          for (int k = 0; k < KP; ++k) {
+            const int j = lane + G * k;
+            if (j < rl) acc = fmaf(pv[k], s_qg[grp][j], acc);
+          }
+          for (int j = lane + G * KP; j < rl; j += G) acc = fmaf(pval[pr + j], s_qg[grp][j], acc);
+        } else {
+          for (int j = lane; j < rl; j += G) acc = fmaf(pval[pr + j], s_qg[grp][j], acc);
         }
-        qv[k] = v;
-      }
-    }
-    // stencil values of U for this box (same start for every row of the box)
-    int sta[3];
-    const int bxyz[3] = {bx, by, bz};
-    for (int a = 0; a < 3; ++a) {
-      int st = bxyz[a] - shift;
-      if (g.per[a]) {
-        if (st < 0) st += g.N[a];
       } else {
-        st = min(max(st, 0), g.N[a] - g.p - 1);
-      }
-      sta[a] = st;
-    }
-    float uv[4];
-    int lax[4], lay[4], laz[4];
-#pragma unroll
-    for (int s2 = 0; s2 < 4; ++s2) {
-      int l = lane + 64 * s2;
-      uv[s2] = 0.f;
-      lax[s2] = lay[s2] = laz[s2] = 0;
-      if (l < nst) {
-        int ax = l % p1, ay = (l / p1) % p1, az = l / (p1 * p1);
-        int gx = sta[0] + ax, gy = sta[1] + ay, gz = sta[2] + az;
-        if (gx >= g.N[0]) gx -= g.N[0];
-        if (gy >= g.N[1]) gy -= g.N[1];
-        if (gz >= g.N[2]) gz -= g.N[2];
-        uv[s2] = U[((int64_t)gz * g.N[1] + gy) * g.N[0] + gx];
-        lax[s2] = ax;
-        lay[s2] = ay;
-        laz[s2] = az;
-      }
-    }
-    for (int r = r0; r < r1; ++r) {
-      const int pr = prp[r];
-      const int rl = min(S, prp[r + 1] - pr);  // equal by construction; guards the reads
-      float acc = 0.f;
-      if (cached) {
-        float pv[kIcKQ];
-#pragma unroll
-        for (int k = 0; k < kIcKQ; ++k) {
-          int j = lane + 64 * k;
-          pv[k] = (k < nk && j < rl) ? pval[pr + j] : 0.f;
-        }
-#pragma unroll
-        for (int k = 0; k < kIcKQ; ++k) acc += pv[k] * qv[k];
-      } else {
-        for (int k = 0; k < nk; ++k) {
-          int j = lane + 64 * k;
-          float c = charge(j < S ? j : 0);
-          if (j < rl) acc += pval[pr + j] * c;
+        // very large rows: walk the windows in global memory
+        for (int j = lane; j < rl; j += G) {
+          int loc = j;
+          float qj = 0.f;
+          for (int i = 0; i < npair; ++i) {
+            const Window w = pair_window(g, box_start, i, bx, by, bz);
+            if (loc < w.nA) { qj = q[w.sA + loc]; break; }
+            loc -= w.nA;
+            if (loc < w.nB) { qj = q[w.sB + loc]; break; }
+            loc -= w.nB;
+          }
+          acc = fmaf(pval[pr + j], qj, acc);
         }
       }
       const float4 xi = pos4[r];
-#pragma unroll
-      for (int s2 = 0; s2 < 4; ++s2) {
-        if (lane + 64 * s2 < nst)
-          acc += uv[s2] * (lagrange(lax[s2], xi.x, g.p) * lagrange(lay[s2], xi.y, g.p) *
-                           lagrange(laz[s2], xi.z, g.p));
+      if (cubic) {
+        const float wxy = cubic_eval(cx, xi.x) * cubic_eval(cy, xi.y);
+        acc = fmaf(wxy * cubic_eval(cz0, xi.z), uv[0], acc);
+        acc = fmaf(wxy * cubic_eval(cz1, xi.z), uv[1], acc);
+        acc = fmaf(wxy * cubic_eval(cz2, xi.z), uv[2], acc);
+        acc = fmaf(wxy * cubic_eval(cz3, xi.z), uv[3], acc);
+      } else {
+        const int p1 = g.p + 1, nst = p1 * p1 * p1;
+        for (int l = lane; l < nst; l += G) {
+          const int ax = l % p1, ay = (l / p1) % p1, az = l / (p1 * p1);
+          int gx = sta[0] + ax, gy = sta[1] + ay, gz = sta[2] + az;
+          if (gx >= g.N[0]) gx -= g.N[0];
+          if (gy >= g.N[1]) gy -= g.N[1];
+          if (gz >= g.N[2]) gz -= g.N[2];
+          acc = fmaf(lagrange(ax, xi.x, g.p) * lagrange(ay, xi.y, g.p) * lagrange(az, xi.z, g.p),
+                     U[((int64_t)gz * g.N[1] + gy) * g.N[0] + gx], acc);
+        }
       }
-      acc = group_sum<64>(acc);
-      if (lane == 0) u[r] = acc + uz[r];
     }
+    acc = group_sum<G>(acc);
+    if (act && lane == 0) u[r] = acc + uz[r];
   }
 }
 
 // ---------------------------------------------------------------------------
-// gradient + sum: 16 lanes per row; writes h[n][3]
+// exchange + gradient + sum over the shared local pattern, 16 lanes per row:
+//   H_n = sum_k ( L_nk m_k - G_nk u_k ) + H_applied,  gl = {Gx, Gy, Gz, L}
 
 __global__ void __launch_bounds__(256) k_grad(int64_t n, const int32_t* __restrict__ rp,
                                               const int32_t* __restrict__ col,
-                                              const float4* __restrict__ gv,
+                                              const float4* __restrict__ gl,
+                                              const float* __restrict__ m,
                                               const float* __restrict__ u,
-                                              const float4* __restrict__ hex,
                                               float* __restrict__ h, float hax, float hay,
-                                              float haz, int with_ms) {
+                                              float haz, int with_ex, int with_ms) {
   int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
   int lane = threadIdx.x & 15;
   if (row >= n) return;
-  float gx = 0.f, gy = 0.f, gz = 0.f;
-  if (with_ms) {
-    int e0 = rp[row], e1 = rp[row + 1];
-    for (int e = e0 + lane; e < e1; e += 16) {
-      float4 w = gv[e];
-      float uk = u[col[e]];
-      gx += w.x * uk;
-      gy += w.y * uk;
-      gz += w.z * uk;
+  float hx = 0.f, hy = 0.f, hz = 0.f;
+  const int e0 = rp[row], e1 = rp[row + 1];
+  for (int e = e0 + lane; e < e1; e += 16) {
+    const int64_t k = col[e];
+    const float4 w = gl[e];
+    if (with_ex) {
+      hx += w.w * m[3 * k];
+      hy += w.w * m[3 * k + 1];
+      hz += w.w * m[3 * k + 2];
+    }
+    if (with_ms) {
+      const float uk = u[k];
+      hx -= w.x * uk;
+      hy -= w.y * uk;
+      hz -= w.z * uk;
     }
   }
-  gx = group_sum<16>(gx);
-  gy = group_sum<16>(gy);
-  gz = group_sum<16>(gz);
+  hx = group_sum<16>(hx);
+  hy = group_sum<16>(hy);
+  hz = group_sum<16>(hz);
   if (lane == 0) {
-    float4 he = hex[row];
-    h[3 * row] = he.x - gx + hax;
-    h[3 * row + 1] = he.y - gy + hay;
-    h[3 * row + 2] = he.z - gz + haz;
+    h[3 * row] = hx + hax;
+    h[3 * row + 1] = hy + hay;
+    h[3 * row + 2] = hz + haz;
   }
 }
 
@@ -712,7 +736,7 @@ __global__ void k_rk_final(int64_t n, double* __restrict__ m, const double* __re
 // energy partial sums: block b writes {sum mu m.Hex, sum q u}
 __global__ void __launch_bounds__(256) k_energy(int64_t n, const double* __restrict__ m,
                                                 const double* __restrict__ mu,
-                                                const float4* __restrict__ hex,
+                                                const float* __restrict__ hex,
                                                 const float* __restrict__ q,
                                                 const float* __restrict__ u,
                                                 double* __restrict__ part) {
@@ -720,8 +744,8 @@ __global__ void __launch_bounds__(256) k_energy(int64_t n, const double* __restr
   double a = 0.0, b = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    float4 he = hex[i];
-    a += mu[i] * (m[3 * i] * he.x + m[3 * i + 1] * he.y + m[3 * i + 2] * he.z);
+    a += mu[i] * (m[3 * i] * hex[3 * i] + m[3 * i + 1] * hex[3 * i + 1] +
+                  m[3 * i + 2] * hex[3 * i + 2]);
     b += (double)q[i] * (double)u[i];
   }
   s0[threadIdx.x] = a;

@@ -1,6 +1,7 @@
 // Host setup of the PM-FEM operators, FP64 arithmetic, run once per build.
 //
-//  1. PBC pairs by spatial hashing and union-find LCA merge (Sec. 2.2).
+//  1. PBC pairs (nodes equal modulo the lattice) by spatial hashing and
+//     union-find LCA merge (Secs. 2.1, 2.2).
 //  2. Folded positions (Eq. shift_hms), grid coordinates, boxes, and the
 //     box-sorted numbering of the unknowns (Sec. 3.2.2).
 //  3. Periodised P1 operators on one shared CSR pattern (Secs. 3.1, 3.2.1):
@@ -145,58 +146,81 @@ int host_build(pmfem_ctx* c) {
     if ((c->mask >> a) & 1) scale = std::max(scale, c->L[a]);
   }
   const double tol = (c->match_tol > 0 ? c->match_tol : 1e-9) * scale;
-  const double cell = tol * 64.0;
   std::vector<int64_t> par(N);
   std::iota(par.begin(), par.end(), 0);
   if (c->mask) {
+    // Two nodes form a PBC pair when they coincide modulo the lattice (any
+    // combination of periods: the combined shifts of Sec. 2.1 and the images
+    // of protruding cells). Positions are wrapped into the cell on periodic
+    // axes and hashed on a grid of cells much larger than the tolerance;
+    // neighbouring cells are visited (cyclically on periodic axes) only for
+    // points within the tolerance of a cell face.
+    const double cell = tol * 64.0;
+    int per[3];
+    int64_t ncell[3];
+    std::vector<double> w(3 * N);
+    for (int a = 0; a < 3; ++a) {
+      per[a] = (c->mask >> a) & 1;
+      ncell[a] = per[a] ? (int64_t)std::ceil(c->L[a] / cell) : 0;
+    }
+    for (int64_t n = 0; n < N; ++n)
+      for (int a = 0; a < 3; ++a) {
+        double v = X[3 * n + a];
+        if (per[a]) {
+          v -= c->L[a] * std::floor(v / c->L[a]);
+          if (v >= c->L[a]) v -= c->L[a];
+        }
+        w[3 * n + a] = v;
+      }
     std::unordered_map<CellKey, std::vector<int32_t>, CellHash> hash;
     hash.reserve((size_t)N * 2);
-    for (int64_t n = 0; n < N; ++n) {
-      CellKey k{(int64_t)std::floor(X[3 * n] / cell), (int64_t)std::floor(X[3 * n + 1] / cell),
-                (int64_t)std::floor(X[3 * n + 2] / cell)};
-      hash[k].push_back((int32_t)n);
-    }
-    for (int a = 0; a < 3; ++a) {
-      if (!((c->mask >> a) & 1)) continue;
-      std::vector<int64_t> match(N, -1);
-      std::atomic<int> ambiguous(0);
-      parallel_for(N, [&](int64_t n) {
-        double t[3] = {X[3 * n], X[3 * n + 1], X[3 * n + 2]};
-        t[a] += c->L[a];
-        int64_t base[3];
-        int rng[3][2];
-        for (int d = 0; d < 3; ++d) {
-          double s = t[d] / cell;
-          base[d] = (int64_t)std::floor(s);
-          double f = s - base[d];
-          rng[d][0] = f < 0.1 ? -1 : 0;
-          rng[d][1] = f > 0.9 ? 1 : 0;
+    auto key_of = [&](const double* v) {
+      return CellKey{(int64_t)std::floor(v[0] / cell), (int64_t)std::floor(v[1] / cell),
+                     (int64_t)std::floor(v[2] / cell)};
+    };
+    for (int64_t n = 0; n < N; ++n) hash[key_of(&w[3 * n])].push_back((int32_t)n);
+    std::vector<std::vector<int32_t>> match(N);
+    parallel_for(N, [&](int64_t n) {
+      const double* v = &w[3 * n];
+      CellKey k0 = key_of(v);
+      int64_t base[3] = {k0.x, k0.y, k0.z};
+      int rng[3][2];
+      for (int d = 0; d < 3; ++d) {
+        double f = v[d] / cell - (double)base[d];
+        rng[d][0] = f < 0.1 ? -1 : 0;
+        rng[d][1] = f > 0.9 ? 1 : 0;
+        if (per[d]) {  // the top cell of a periodic axis may be partial
+          if (base[d] == ncell[d] - 1) rng[d][1] = 1;
+          if (v[d] > c->L[d] - 2.0 * tol) rng[d][1] = 1;
         }
-        int64_t found = -1;
-        for (int dx = rng[0][0]; dx <= rng[0][1]; ++dx)
-          for (int dy = rng[1][0]; dy <= rng[1][1]; ++dy)
-            for (int dz = rng[2][0]; dz <= rng[2][1]; ++dz) {
-              auto it = hash.find(CellKey{base[0] + dx, base[1] + dy, base[2] + dz});
-              if (it == hash.end()) continue;
-              for (int32_t j : it->second) {
-                double e0 = X[3 * j] - t[0], e1 = X[3 * j + 1] - t[1], e2 = X[3 * j + 2] - t[2];
-                if (e0 * e0 + e1 * e1 + e2 * e2 <= tol * tol) {
-                  if (found >= 0 && found != j) ambiguous = 1;
-                  found = j;
-                }
+      }
+      for (int dx = rng[0][0]; dx <= rng[0][1]; ++dx)
+        for (int dy = rng[1][0]; dy <= rng[1][1]; ++dy)
+          for (int dz = rng[2][0]; dz <= rng[2][1]; ++dz) {
+            int64_t kk[3] = {base[0] + dx, base[1] + dy, base[2] + dz};
+            for (int d = 0; d < 3; ++d)
+              if (per[d]) kk[d] = ((kk[d] % ncell[d]) + ncell[d]) % ncell[d];
+            auto it = hash.find(CellKey{kk[0], kk[1], kk[2]});
+            if (it == hash.end()) continue;
+            for (int32_t j : it->second) {
+              if (j <= n) continue;
+              double d2 = 0.0;
+              for (int d = 0; d < 3; ++d) {
+                double e = w[3 * j + d] - v[d];
+                if (per[d]) e -= c->L[d] * std::nearbyint(e / c->L[d]);
+                d2 += e * e;
               }
+              if (d2 <= tol * tol) match[n].push_back(j);
             }
-        match[n] = found;
-      }, 4096);
-      if (ambiguous) return fail(c, PMFEM_EPBC, "a node matches several periodic images");
-      for (int64_t n = 0; n < N; ++n) {
-        if (match[n] < 0) continue;
-        int64_t ra = find_root(par, n), rb2 = find_root(par, match[n]);
+          }
+    }, 4096);
+    for (int64_t n = 0; n < N; ++n)
+      for (int32_t j : match[n]) {
+        int64_t ra = find_root(par, n), rb2 = find_root(par, j);
         if (ra != rb2) {
           if (ra < rb2) par[rb2] = ra; else par[ra] = rb2;
         }
       }
-    }
   }
   std::vector<int64_t> root(N);
   for (int64_t n = 0; n < N; ++n) root[n] = find_root(par, n);
@@ -319,6 +343,15 @@ int host_build(pmfem_ctx* c) {
     std::memcpy(&o.pos4[4 * u + 3], &packed, 4);
   }
   const std::vector<int64_t>& uk = o.unk_of_node;
+  // a tetrahedron whose vertices merge into fewer than four unknowns spans a
+  // whole period: the periodic faces cannot be matched consistently
+  for (int64_t t = 0; t < T; ++t) {
+    const int32_t* v = &tets[4 * t];
+    for (int a2 = 0; a2 < 4; ++a2)
+      for (int b2 = a2 + 1; b2 < 4; ++b2)
+        if (uk[v[a2]] == uk[v[b2]])
+          return fail(c, PMFEM_EPBC, "a tetrahedron spans a whole period (two vertices are images)");
+  }
 
   // ---- 3. local operators ----------------------------------------------------
   std::vector<int64_t> inc_ptr(Np + 1, 0);

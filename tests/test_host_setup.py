@@ -168,7 +168,17 @@ def test_errors_are_reported():
     with pytest.raises(lib.PmfemError) as e:
         c.build()
     assert e.value.code == lib.Status.EMESH
+    # a cell one element thick along a periodic axis: a tet holds two images
+    thin = mg.kuhn_box((1, 4, 4), 1e-9, periodic=0b111, grid=(16, 16, 16))
+    c.set_mesh(thin.xyz, thin.tets, thin.region)
+    c.set_periodicity(thin.periodic, thin.L)
+    c.set_aim((16, 16, 16))
+    with pytest.raises(lib.PmfemError) as e:
+        c.build()
+    assert e.value.code == lib.Status.EPBC
+    c.set_periodicity(p.periodic, p.L)
     c.set_mesh(p.xyz, p.tets, p.region)
+    c.set_aim((16, 16, 4))
     c.set_materials([-1.0], [1e-11])
     with pytest.raises(lib.PmfemError) as e:
         c.build()
