@@ -52,7 +52,10 @@ def kernel_bytes(ctx):
         "k_fft_z_mul": 2 * s_full + khat,
         "k_fft_y_inv": s_full + s_in,
         "k_c2r_x": s_in + ng * 4,
+        "k_fft_xy_fwd": ng * 4 + s_full,
+        "k_fft_yx_inv": s_full + ng * 4,
         "k_interp_corr": n * (16 + 4 + 4 + 4 + 4) + ng * 4 + nP * 4,
+        "k_interp_seg": n * (16 + 4 + 4 + 4 + 4) + ng * 4 + nP * 4,
         "k_grad": n * (4 + 12 + 4 + 12) + nL * 20,
     }
 

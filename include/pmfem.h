@@ -101,6 +101,18 @@ int pmfem_set_aim(pmfem_ctx* ctx, const int32_t grid[3], int32_t order_p, int32_
                   double z0_radius_edges, int32_t precision);
 
 /*
+ * Kernel form of one stage of the evaluation; the results agree within
+ * FP32 rounding order. stage "anterp": 1 tile gather, 2 line gather;
+ * "interp" (interpolation + precorrection): 1 per-box, 2 box-row segment;
+ * "fft": 1 separate x, y, z passes, 2 whole z-planes in LDS for x and y.
+ * variant 0 (the default) picks the staged forms (2) wherever their LDS
+ * plans fit. May be called before or after pmfem_build; EINVAL if the stage
+ * or variant is unknown or a forced form does not fit the built problem
+ * (the previous choice is kept).
+ */
+int pmfem_set_variant(pmfem_ctx* ctx, const char* stage, int32_t variant);
+
+/*
  * Build all operators on the host in FP64 (PBC pairs and LCA merge,
  * periodised P1 operators, grid PGF and its spectrum, precorrection and
  * element-exact correction), round them once to FP32 and upload them.

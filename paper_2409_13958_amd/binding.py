@@ -52,6 +52,7 @@ _SIGS = {
     "pmfem_set_materials": (ctypes.c_int, [_P, _I32, _P, _P]),
     "pmfem_set_periodicity": (ctypes.c_int, [_P, _U32, _P, _D]),
     "pmfem_set_aim": (ctypes.c_int, [_P, _P, _I32, _I32, _D, _I32]),
+    "pmfem_set_variant": (ctypes.c_int, [_P, ctypes.c_char_p, _I32]),
     "pmfem_build": (ctypes.c_int, [_P]),
     "pmfem_query": (ctypes.c_int, [_P, ctypes.POINTER(_I64), _P, _P, _DP]),
     "pmfem_heff": (ctypes.c_int, [_P, _P, _P, _U32, _P]),
@@ -167,6 +168,10 @@ class Context:
         L = np.ascontiguousarray(L, dtype=np.float64)
         self._check(self.lib.pmfem_set_periodicity(self.h, int(mask), _ptr(L), float(tol)),
                     "set_periodicity")
+
+    def set_variant(self, stage, variant):
+        self._check(self.lib.pmfem_set_variant(self.h, stage.encode(), int(variant)),
+                    "set_variant")
 
     def set_aim(self, grid, order_p=3, near_boxes=2, z0_radius=1.0, precision=0):
         g = np.ascontiguousarray(grid, dtype=np.int32)

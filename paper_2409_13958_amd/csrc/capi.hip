@@ -20,6 +20,15 @@ struct pmfem_dev {
   int32_t* box_start = nullptr;
   int32_t* occ = nullptr;  // boxes holding at least one unknown
   int n_occ = 0;
+  AntPlan ap{};            // line form of anterpolation
+  bool ant_ok = false, ic_ok = false, fft_ok = false;  // the plans fit
+  bool ant_line = false;   // false: the tile form k_anterp
+  int ant_threads = 0;
+  IcPlan icp{};            // segment form of interpolation+precorrection
+  bool ic_seg = false;     // false: the per-box form k_interp_corr
+  bool fft_plane = false;  // x and y transforms of a whole z-plane in one kernel
+  size_t fft_plane_lds = 0;
+  const char* kname[9] = {};  // kernel in each profiling slot
   int2 *brx = nullptr, *bry = nullptr, *brz = nullptr;
   int32_t *lrp = nullptr, *lcol = nullptr;
   float *ldx = nullptr, *ldy = nullptr, *ldz = nullptr;  // charge operator D
@@ -47,10 +56,6 @@ struct pmfem_dev {
 namespace {
 
 constexpr int kNumKernels = 9;
-const char* kKernelNames[kNumKernels] = {"k_local",     "k_anterp",    "k_r2c_x",
-                                         "k_fft_y_fwd", "k_fft_z_mul", "k_fft_y_inv",
-                                         "k_c2r_x",     "k_interp_corr", "k_grad"};
-
 int set_err(pmfem_ctx* c, int code, const std::string& m) {
   if (c) c->err = m;
   return code;
@@ -127,6 +132,188 @@ std::vector<int2> box_ranges(const HostOps& o, int a) {
   return r;
 }
 
+// Kernel forms from the context's variant choice (0 automatic: the staged
+// forms wherever their plans fit) and the kernel name of each profiling slot.
+int select_variants(pmfem_ctx* c) {
+  pmfem_dev* d = c->dev;
+  const int va = c->variant[0], vi = c->variant[1], vf = c->variant[2];
+  if ((va == 2 && !d->ant_ok) || (vi == 2 && !d->ic_ok) || (vf == 2 && !d->fft_ok))
+    return set_err(c, PMFEM_EINVAL, "requested kernel form does not fit this problem");
+  d->ant_line = va == 0 ? d->ant_ok : va == 2;
+  d->ic_seg = vi == 0 ? d->ic_ok : vi == 2;
+  d->fft_plane = vf == 0 ? d->fft_ok : vf == 2;
+  const char* names_split[9] = {"k_local",     "k_anterp",    "k_r2c_x",
+                                "k_fft_y_fwd", "k_fft_z_mul", "k_fft_y_inv",
+                                "k_c2r_x",     "k_interp",    "k_grad"};
+  for (int k = 0; k < 9; ++k) d->kname[k] = names_split[k];
+  if (d->fft_plane) {
+    d->kname[2] = "k_fft_xy_fwd";
+    d->kname[3] = "-";
+    d->kname[5] = "-";
+    d->kname[6] = "k_fft_yx_inv";
+  }
+  d->kname[1] = d->ant_line ? "k_anterp_line" : "k_anterp";
+  d->kname[7] = d->ic_seg ? "k_interp_seg" : "k_interp_corr";
+  return PMFEM_OK;
+}
+
+// Line plan for k_anterp_line: the longest x-segment (at most 128 points)
+// whose staged nodes fit in 64 KB of LDS. Returns false if none fits.
+bool plan_anterp(const HostOps& o, const std::vector<int2>& bx, const std::vector<int2>& by,
+                 const std::vector<int2>& bz, AntPlan& pl) {
+  const int nbx = o.nbox[0], nby = o.nbox[1], nbz = o.nbox[2], p = o.p, shift = (p - 1) / 2;
+  const std::vector<int32_t>& bs = o.box_start;
+  int cy = 0, cz = 0;
+  for (const int2& r : by) cy = std::max(cy, r.y);
+  for (const int2& r : bz) cz = std::max(cz, r.y);
+  const int nrow = cy * cz;
+  auto cum = [&](int64_t srow, int tot, int x) -> int64_t {
+    if (o.per[0]) {
+      int64_t wrap = 0;
+      if (x < 0) {
+        x += nbx;
+        wrap = -1;
+      } else if (x > nbx) {
+        x -= nbx;
+        wrap = 1;
+      }
+      return wrap * tot + bs[srow + x];
+    }
+    return bs[srow + std::min(std::max(x, 0), nbx)];
+  };
+  for (int xa = std::min(o.N[0], 128); xa >= 4; xa /= 2) {
+    const int nsx = (o.N[0] + xa - 1) / xa;
+    int sbx = 0;
+    std::vector<int> fbs(nsx), nbss(nsx);
+    for (int sx = 0; sx < nsx; ++sx) {
+      const int x0 = sx * xa, xe = std::min(x0 + xa, o.N[0]) - 1;
+      fbs[sx] = o.per[0] ? x0 - p + shift : bx[x0].x;
+      nbss[sx] = o.per[0] ? (xe - x0 + 1) + p : bx[xe].x + bx[xe].y - bx[x0].x;
+      sbx = std::max(sbx, nbss[sx]);
+    }
+    int64_t ncap = 0;
+    for (int gz = 0; gz < o.N[2]; ++gz)
+      for (int gy = 0; gy < o.N[1]; ++gy)
+        for (int sx = 0; sx < nsx; ++sx) {
+          int64_t staged = 0;
+          for (int iz = 0; iz < bz[gz].y; ++iz)
+            for (int iy = 0; iy < by[gy].y; ++iy) {
+              int b_y = by[gy].x + iy, b_z = bz[gz].x + iz;
+              if (b_y >= nby) b_y -= nby;
+              if (b_z >= nbz) b_z -= nbz;
+              const int64_t srow = ((int64_t)b_z * nby + b_y) * nbx;
+              const int tot = bs[srow + nbx] - bs[srow];
+              if (tot == 0) continue;
+              staged += cum(srow, tot, fbs[sx] + nbss[sx]) - cum(srow, tot, fbs[sx]);
+            }
+          ncap = std::max(ncap, staged);
+        }
+    auto al = [](int64_t b) { return (b + 15) & ~(int64_t)15; };
+    int64_t off = 0;
+    pl.o_x = (int)off;
+    off += al(std::max<int64_t>(ncap, 1) * 4);
+    pl.o_c = (int)off;
+    off += al(std::max<int64_t>(ncap, 1) * 4);
+    pl.o_st = (int)off;
+    off += al(std::max<int64_t>(ncap, 1) * 2);
+    pl.o_meta = (int)off;
+    off += al((int64_t)(7 * nrow + 1) * 4);
+    pl.o_off = (int)off;
+    off += al((int64_t)nrow * (sbx + 1) * 4);
+    if (off <= 65536 && nrow <= 64) {
+      pl.xa = xa;
+      pl.nsx = nsx;
+      pl.nrow = nrow;
+      pl.sbx = sbx;
+      pl.ncap = (int)ncap;
+      pl.lds_bytes = (int)off;
+      return true;
+    }
+  }
+  return false;
+}
+
+// Segment plan for k_interp_seg: the widest x-segment (at most 128 boxes)
+// whose staged arrays fit in 64 KB of LDS. Returns false if none fits.
+bool plan_interp(const HostOps& o, IcPlan& pl) {
+  const int nbx = o.nbox[0], nby = o.nbox[1], nbz = o.nbox[2];
+  const int rb = o.rb, W = 2 * rb + 1, np = W * W, p1 = o.p + 1;
+  const std::vector<int32_t>& bs = o.box_start;
+  int scap = 0;
+  for (int64_t r = 0; r < o.n_unk; ++r)
+    scap = std::max<int>(scap, o.p_rowptr[r + 1] - o.p_rowptr[r]);
+  scap = std::max(4, (scap + 3) & ~3);
+  // cumulative node index of a source row at unwrapped box x (as in the kernel)
+  auto cum = [&](int64_t srow, int tot, int x) -> int64_t {
+    if (o.per[0]) {
+      int64_t wrap = 0;
+      if (x < 0) {
+        x += nbx;
+        wrap = -1;
+      } else if (x > nbx) {
+        x -= nbx;
+        wrap = 1;
+      }
+      return wrap * tot + bs[srow + x];
+    }
+    return bs[srow + std::min(std::max(x, 0), nbx)];
+  };
+  for (int xs = std::min(nbx, 128); xs >= 1; xs /= 2) {
+    const int nsx = (nbx + xs - 1) / xs, sb = xs + 2 * rb;
+    int64_t qcap = 0, rcap = 0;
+    for (int bz = 0; bz < nbz; ++bz)
+      for (int by = 0; by < nby; ++by) {
+        const int64_t orow = ((int64_t)bz * nby + by) * nbx;
+        for (int sx = 0; sx < nsx; ++sx) {
+          const int x0 = sx * xs, xe = std::min(x0 + xs, nbx);
+          const int64_t rows = bs[orow + xe] - bs[orow + x0];
+          if (rows == 0) continue;
+          rcap = std::max(rcap, rows);
+          int64_t staged = 0;
+          for (int i = 0; i < np; ++i) {
+            int y = by + i % W - rb, z = bz + i / W - rb;
+            if (o.per[1]) y = (y + nby) % nby;
+            else if (y < 0 || y >= nby) continue;
+            if (o.per[2]) z = (z + nbz) % nbz;
+            else if (z < 0 || z >= nbz) continue;
+            const int64_t srow = ((int64_t)z * nby + y) * nbx;
+            const int tot = bs[srow + nbx] - bs[srow];
+            if (tot == 0) continue;
+            staged += cum(srow, tot, x0 - rb + sb) - cum(srow, tot, x0 - rb);
+          }
+          qcap = std::max(qcap, staged);
+        }
+      }
+    auto al = [](int64_t b) { return (b + 15) & ~(int64_t)15; };
+    int64_t off = 0;
+    pl.o_q = (int)off;
+    off += al(std::max<int64_t>(qcap, 1) * 4);
+    pl.o_u = (int)off;
+    off += al((int64_t)p1 * p1 * (xs + o.p) * 4);
+    pl.o_col = (int)off;
+    off += al((int64_t)16 * scap * 4);
+    pl.o_meta = (int)off;
+    off += al((int64_t)(5 * np + 1) * 4);
+    pl.o_off = (int)off;
+    off += al((int64_t)np * (sb + 1) * 2);
+    pl.o_row = (int)off;
+    off += al(std::max<int64_t>(rcap, 1) * 2);
+    if (off <= 65536 && qcap < 65536 && rcap < 65536) {
+      pl.xs = xs;
+      pl.nsx = nsx;
+      pl.np = np;
+      pl.sb = sb;
+      pl.qcap = (int)qcap;
+      pl.ux = xs + o.p;
+      pl.scap = scap;
+      pl.rcap = (int)std::max<int64_t>(rcap, 1);
+      pl.lds_bytes = (int)off;
+      return true;
+    }
+  }
+  return false;
+}
+
 int upload_all(pmfem_ctx* c) {
   HostOps& o = c->ops;
   pmfem_dev* d = c->dev;
@@ -151,7 +338,32 @@ int upload_all(pmfem_ctx* c) {
     d->n_occ = (int)occ.size();
     if ((rc = upload(c, &d->occ, occ.data(), occ.size()))) return rc;
   }
+  d->ic_ok = plan_interp(o, d->icp);
+
+  {
+    // whole-plane x/y transforms when a plane (row pairs + half-spectrum
+    // columns) fits in one workgroup's LDS
+    const int Mx = o.M[0], My = o.M[1], Hx = Mx / 2 + 1, pairs = (o.N[1] + 1) / 2;
+    d->fft_plane_lds =
+        (size_t)(Mx / 2 + My / 2 + (size_t)pairs * Mx + (size_t)Hx * (My + 1)) * sizeof(float2);
+    int max_lds = 0;
+    (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
+    d->fft_ok = d->fft_plane_lds <= (size_t)max_lds;
+    if (d->fft_ok && d->fft_plane_lds > 65536) {
+      const int b = (int)d->fft_plane_lds;
+      d->fft_ok =
+          hipFuncSetAttribute((const void*)k_fft_xy_fwd, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              b) == hipSuccess &&
+          hipFuncSetAttribute((const void*)k_fft_yx_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              b) == hipSuccess;
+      (void)hipGetLastError();
+    }
+  }
+
   auto bx = box_ranges(o, 0), by = box_ranges(o, 1), bz = box_ranges(o, 2);
+  d->ant_ok = plan_anterp(o, bx, by, bz, d->ap);
+  d->ant_threads = std::max(64, (d->ap.xa + 63) / 64 * 64);
+  if ((rc = select_variants(c))) return rc;
   if ((rc = upload(c, &d->brx, bx.data(), bx.size()))) return rc;
   if ((rc = upload(c, &d->bry, by.data(), by.size()))) return rc;
   if ((rc = upload(c, &d->brz, bz.data(), bz.size()))) return rc;
@@ -216,6 +428,61 @@ int upload_all(pmfem_ctx* c) {
 
 hipStream_t stream_of(pmfem_ctx* c) { return (hipStream_t)c->stream; }
 
+// Step 2 of the AIM: Ug = (1/4 pi) K * Qg on the grid (profiling slots 2-6).
+template <class Mark>
+void convolve(pmfem_dev* d, hipStream_t s, const float* Qg, float* Ug, Mark&& mark) {
+  const GridParams& g = d->g;
+  const int T = 256;
+  const int Mx = g.M[0], My = g.M[1], Mz = g.M[2], Hx = Mx / 2 + 1;
+  const int Bz = std::max(1, std::min(16, 4096 / Mz));
+  const int64_t cols = (int64_t)My * Hx;
+  if (d->fft_plane) {
+    mark(2, 0);
+    hipLaunchKernelGGL(k_fft_xy_fwd, dim3((unsigned)g.N[2]), dim3(1024), d->fft_plane_lds, s, g,
+                       Qg, d->spec, d->twx, d->twy);
+    mark(2, 1);
+    mark(4, 0);
+    hipLaunchKernelGGL(k_fft_z_mul, dim3((unsigned)((cols + Bz - 1) / Bz)), dim3(T),
+                       (size_t)(Mz / 2 + Bz * Mz) * sizeof(float2), s, g, d->spec, d->khat,
+                       d->twz, Bz);
+    mark(4, 1);
+    mark(6, 0);
+    hipLaunchKernelGGL(k_fft_yx_inv, dim3((unsigned)g.N[2]), dim3(1024), d->fft_plane_lds, s, g,
+                       (const float2*)d->spec, Ug, d->twx, d->twy);
+    mark(6, 1);
+    return;
+  }
+  const int lpb = std::max(1, 2048 / Mx);
+  const int64_t xlines = (int64_t)((g.N[1] + 1) / 2) * g.N[2];
+  mark(2, 0);
+  hipLaunchKernelGGL(k_r2c_x, dim3((unsigned)((xlines + lpb - 1) / lpb)), dim3(T),
+                     (size_t)(Mx / 2 + lpb * Mx) * sizeof(float2), s, g, Qg, d->spec, d->twx,
+                     lpb);
+  mark(2, 1);
+  const int By = std::max(1, std::min(16, 4096 / My));
+  const int gy = (Hx + By - 1) / By;
+  mark(3, 0);
+  hipLaunchKernelGGL(k_fft_y, dim3((unsigned)(g.N[2] * gy)), dim3(T),
+                     (size_t)(My / 2 + By * My) * sizeof(float2), s, g, d->spec, d->twy, By, 0,
+                     g.N[1], My);
+  mark(3, 1);
+  mark(4, 0);
+  hipLaunchKernelGGL(k_fft_z_mul, dim3((unsigned)((cols + Bz - 1) / Bz)), dim3(T),
+                     (size_t)(Mz / 2 + Bz * Mz) * sizeof(float2), s, g, d->spec, d->khat, d->twz,
+                     Bz);
+  mark(4, 1);
+  mark(5, 0);
+  hipLaunchKernelGGL(k_fft_y, dim3((unsigned)(g.N[2] * gy)), dim3(T),
+                     (size_t)(My / 2 + By * My) * sizeof(float2), s, g, d->spec, d->twy, By, 1,
+                     My, g.N[1]);
+  mark(5, 1);
+  mark(6, 0);
+  hipLaunchKernelGGL(k_c2r_x, dim3((unsigned)((xlines + lpb - 1) / lpb)), dim3(T),
+                     (size_t)(Mx / 2 + lpb * Mx) * sizeof(float2), s, g, d->spec, Ug, d->twx,
+                     lpb);
+  mark(6, 1);
+}
+
 // One evaluation. Intermediates land in the context's work buffers.
 int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const double* happ) {
   pmfem_dev* d = c->dev;
@@ -244,46 +511,30 @@ int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const doubl
     const int64_t ntiles = (int64_t)((g.N[0] + kAntTX - 1) / kAntTX) *
                            ((g.N[1] + kAntTY - 1) / kAntTY) * ((g.N[2] + kAntTZ - 1) / kAntTZ);
     mark(1, 0);
-    hipLaunchKernelGGL(k_anterp, dim3((unsigned)ntiles), dim3(T), 0, s, g, d->q, d->pos4,
-                       d->box_start, d->brx, d->bry, d->brz, d->grid);
+    if (d->ant_line) {
+      const AntPlan& pl = d->ap;
+      const int64_t nwg = (int64_t)pl.nsx * g.N[1] * g.N[2];
+      hipLaunchKernelGGL(k_anterp_line, dim3((unsigned)nwg), dim3(d->ant_threads),
+                         (size_t)pl.lds_bytes, s, g, pl, d->q, d->pos4, d->box_start, d->brx,
+                         d->bry, d->brz, d->grid);
+    } else {
+      hipLaunchKernelGGL(k_anterp, dim3((unsigned)ntiles), dim3(T), 0, s, g, d->q, d->pos4,
+                         d->box_start, d->brx, d->bry, d->brz, d->grid);
+    }
     mark(1, 1);
-    const int Mx = g.M[0], My = g.M[1], Mz = g.M[2], Hx = Mx / 2 + 1;
-    const int lpb = std::max(1, 2048 / Mx);
-    const int64_t xlines = (int64_t)((g.N[1] + 1) / 2) * g.N[2];
-    mark(2, 0);
-    hipLaunchKernelGGL(k_r2c_x, dim3((unsigned)((xlines + lpb - 1) / lpb)), dim3(T),
-                       (size_t)(Mx / 2 + lpb * Mx) * sizeof(float2), s, g, d->grid, d->spec,
-                       d->twx, lpb);
-    mark(2, 1);
-    const int By = std::max(1, std::min(16, 4096 / My));
-    const int gy = (Hx + By - 1) / By;
-    mark(3, 0);
-    hipLaunchKernelGGL(k_fft_y, dim3((unsigned)(g.N[2] * gy)), dim3(T),
-                       (size_t)(My / 2 + By * My) * sizeof(float2), s, g, d->spec, d->twy, By, 0,
-                       g.N[1], My);
-    mark(3, 1);
-    const int Bz = std::max(1, std::min(16, 4096 / Mz));
-    const int64_t cols = (int64_t)My * Hx;
-    mark(4, 0);
-    hipLaunchKernelGGL(k_fft_z_mul, dim3((unsigned)((cols + Bz - 1) / Bz)), dim3(T),
-                       (size_t)(Mz / 2 + Bz * Mz) * sizeof(float2), s, g, d->spec, d->khat,
-                       d->twz, Bz);
-    mark(4, 1);
-    mark(5, 0);
-    hipLaunchKernelGGL(k_fft_y, dim3((unsigned)(g.N[2] * gy)), dim3(T),
-                       (size_t)(My / 2 + By * My) * sizeof(float2), s, g, d->spec, d->twy, By, 1,
-                       My, g.N[1]);
-    mark(5, 1);
-    mark(6, 0);
-    hipLaunchKernelGGL(k_c2r_x, dim3((unsigned)((xlines + lpb - 1) / lpb)), dim3(T),
-                       (size_t)(Mx / 2 + lpb * Mx) * sizeof(float2), s, g, d->spec, d->grid,
-                       d->twx, lpb);
-    mark(6, 1);
+    convolve(d, s, d->grid, d->grid, mark);
     mark(7, 0);
-    const int64_t nwg = (d->n_occ + kIcGroups - 1) / kIcGroups;
-    hipLaunchKernelGGL(k_interp_corr, dim3((unsigned)std::max<int64_t>(nwg, 1)), dim3(T), 0, s, g,
-                       d->n_occ, d->occ, d->grid, d->pos4, d->box_start, d->prp, d->pv, d->q,
-                       d->uz, d->u);
+    if (d->ic_seg) {
+      const IcPlan& pl = d->icp;
+      const int64_t nwg = (int64_t)pl.nsx * g.nbox[1] * g.nbox[2];
+      hipLaunchKernelGGL(k_interp_seg, dim3((unsigned)nwg), dim3(T), (size_t)pl.lds_bytes, s, g,
+                         pl, d->grid, d->pos4, d->box_start, d->prp, d->pv, d->q, d->uz, d->u);
+    } else {
+      const int64_t nwg = (d->n_occ + kIcGroups - 1) / kIcGroups;
+      hipLaunchKernelGGL(k_interp_corr, dim3((unsigned)std::max<int64_t>(nwg, 1)), dim3(T), 0, s,
+                         g, d->n_occ, d->occ, d->grid, d->pos4, d->box_start, d->prp, d->pv,
+                         d->q, d->uz, d->u);
+    }
     mark(7, 1);
   }
   float hx = 0.f, hy = 0.f, hz = 0.f;
@@ -366,6 +617,28 @@ int pmfem_set_periodicity(pmfem_ctx* c, uint32_t axis_mask, const double L[3], d
   for (int a = 0; a < 3; ++a) c->L[a] = L ? L[a] : 0.0;
   c->match_tol = match_tol > 0 ? match_tol : 1e-9;
   c->built = false;
+  return PMFEM_OK;
+}
+
+int pmfem_set_variant(pmfem_ctx* c, const char* stage, int32_t variant) {
+  if (!c) return PMFEM_EINVAL;
+  if (!stage) return set_err(c, PMFEM_EINVAL, "null stage");
+  int k = -1;
+  if (std::strcmp(stage, "anterp") == 0) k = 0;
+  if (std::strcmp(stage, "interp") == 0) k = 1;
+  if (std::strcmp(stage, "fft") == 0) k = 2;
+  if (k < 0) return set_err(c, PMFEM_EINVAL, "unknown stage");
+  if (variant < 0 || variant > 2) return set_err(c, PMFEM_EINVAL, "variant must be 0, 1 or 2");
+  const int old = c->variant[k];
+  c->variant[k] = variant;
+  if (c->dev) {
+    const int rc = select_variants(c);
+    if (rc) {
+      c->variant[k] = old;
+      (void)select_variants(c);
+      return rc;
+    }
+  }
   return PMFEM_OK;
 }
 
@@ -482,31 +755,7 @@ int pmfem_grid_convolve(pmfem_ctx* c, const float* q_grid_dev, float* u_grid_dev
   pmfem_dev* d = c->dev;
   const GridParams& g = d->g;
   hipStream_t s = stream_of(c);
-  const int64_t ng = (int64_t)g.N[0] * g.N[1] * g.N[2];
-  const int Mx = g.M[0], My = g.M[1], Mz = g.M[2], Hx = Mx / 2 + 1;
-  const int T = 256;
-  const int lpb = std::max(1, 2048 / Mx);
-  const int64_t xlines = (int64_t)((g.N[1] + 1) / 2) * g.N[2];
-  const int By = std::max(1, std::min(16, 4096 / My));
-  const int gy = (Hx + By - 1) / By;
-  const int Bz = std::max(1, std::min(16, 4096 / Mz));
-  const int64_t cols = (int64_t)My * Hx;
-  hipLaunchKernelGGL(k_r2c_x, dim3((unsigned)((xlines + lpb - 1) / lpb)), dim3(T),
-                     (size_t)(Mx / 2 + lpb * Mx) * sizeof(float2), s, g, q_grid_dev, d->spec,
-                     d->twx, lpb);
-  hipLaunchKernelGGL(k_fft_y, dim3((unsigned)(g.N[2] * gy)), dim3(T),
-                     (size_t)(My / 2 + By * My) * sizeof(float2), s, g, d->spec, d->twy, By, 0,
-                     g.N[1], My);
-  hipLaunchKernelGGL(k_fft_z_mul, dim3((unsigned)((cols + Bz - 1) / Bz)), dim3(T),
-                     (size_t)(Mz / 2 + Bz * Mz) * sizeof(float2), s, g, d->spec, d->khat, d->twz,
-                     Bz);
-  hipLaunchKernelGGL(k_fft_y, dim3((unsigned)(g.N[2] * gy)), dim3(T),
-                     (size_t)(My / 2 + By * My) * sizeof(float2), s, g, d->spec, d->twy, By, 1,
-                     My, g.N[1]);
-  hipLaunchKernelGGL(k_c2r_x, dim3((unsigned)((xlines + lpb - 1) / lpb)), dim3(T),
-                     (size_t)(Mx / 2 + lpb * Mx) * sizeof(float2), s, g, d->spec, u_grid_dev,
-                     d->twx, lpb);
-  (void)ng;
+  convolve(d, s, q_grid_dev, u_grid_dev, [](int, int) {});
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_err(c, e, "kernel launch");
   return PMFEM_OK;
@@ -599,7 +848,7 @@ int pmfem_profile_end(pmfem_ctx* c, int32_t* n_kernels, double* ms, int32_t* cou
   pmfem_dev* d = c->dev;
   hipError_t e = hipStreamSynchronize(stream_of(c));
   if (e != hipSuccess) return hip_err(c, e, "hipStreamSynchronize");
-  if (n_kernels) *n_kernels = kNumKernels;
+  int out = 0;
   for (int k = 0; k < kNumKernels; ++k) {
     double tot = 0.0;
     int cnt = 0;
@@ -612,13 +861,16 @@ int pmfem_profile_end(pmfem_ctx* c, int32_t* n_kernels, double* ms, int32_t* cou
         ++cnt;
       }
     }
-    if (ms) ms[k] = tot;
-    if (count) count[k] = cnt;
+    if (cnt == 0) continue;  // slot not used by this context's launch sequence
+    if (ms) ms[out] = tot;
+    if (count) count[out] = cnt;
     if (names) {
-      std::strncpy(names[k], kKernelNames[k], 31);
-      names[k][31] = 0;
+      std::strncpy(names[out], d->kname[k] ? d->kname[k] : "?", 31);
+      names[out][31] = 0;
     }
+    ++out;
   }
+  if (n_kernels) *n_kernels = out;
   (void)hipGetLastError();  // events of kernels that did not run report errors
   d->prof_max = 0;
   d->prof_calls = 0;

@@ -28,6 +28,35 @@ constexpr int kIcGQ = 512;             // staged charges per group
 constexpr int kIcPairs = 49;           // (2 r_b + 1)^2 for r_b <= 3
 constexpr int kIcSeg = 2 * kIcPairs;   // a window splits in two at a periodic wrap
 
+// interpolation/precorrection over x-segments of box rows: one workgroup
+// per segment of `xs` boxes of one (y, z) box row. Sizes and LDS layout
+// (byte offsets into the dynamic LDS block) are chosen on the host from the
+// box table so that every staged array fits.
+struct IcPlan {
+  int xs;    // boxes per segment along x
+  int nsx;   // segments per box row
+  int np;    // source box rows (2 r_b + 1)^2
+  int sb;    // staged boxes per source row: xs + 2 r_b
+  int qcap;  // staged source charges
+  int ux;    // staged potential points per stencil line: xs + p
+  int scap;  // column buffer per 16-lane group
+  int rcap;  // observer rows per segment
+  int o_q, o_u, o_col, o_meta, o_off, o_row;  // LDS byte offsets
+  int lds_bytes;
+};
+
+// anterpolation by grid lines: one workgroup per segment of `xa` points of
+// one (y, z) grid line; sizes and LDS layout chosen on the host.
+struct AntPlan {
+  int xa;     // points per segment (= threads per workgroup)
+  int nsx;    // segments per line
+  int nrow;   // box rows reaching a line: ((p + 1)^2 at most)
+  int sbx;    // staged boxes per box row (upper bound over segments)
+  int ncap;   // staged nodes per workgroup
+  int o_x, o_c, o_st, o_meta, o_off;  // LDS byte offsets
+  int lds_bytes;
+};
+
 __global__ void k_local(int64_t n, const float* m, const int32_t* rp, const int32_t* col,
                         const float* dx, const float* dy, const float* dz, const int32_t* zrp,
                         const int32_t* zcol, const float* zx, const float* zy, const float* zz,
@@ -35,10 +64,17 @@ __global__ void k_local(int64_t n, const float* m, const int32_t* rp, const int3
 __global__ void k_anterp(GridParams g, const float* q, const float4* pos4,
                          const int32_t* box_start, const int2* brx, const int2* bry,
                          const int2* brz, float* Q);
+__global__ void k_anterp_line(GridParams g, AntPlan pl, const float* q, const float4* pos4,
+                              const int32_t* box_start, const int2* brx, const int2* bry,
+                              const int2* brz, float* Q);
 __global__ void k_r2c_x(GridParams g, const float* Q, float2* spec, const float2* twx,
                         int lines_per_block);
 __global__ void k_fft_y(GridParams g, float2* spec, const float2* twy, int B, int inverse,
                         int n_in, int n_out);
+__global__ void k_fft_xy_fwd(GridParams g, const float* Q, float2* spec, const float2* twx,
+                             const float2* twy);
+__global__ void k_fft_yx_inv(GridParams g, const float2* spec, float* U, const float2* twx,
+                             const float2* twy);
 __global__ void k_fft_z_mul(GridParams g, float2* spec, const float* khat, const float2* twz,
                             int B);
 __global__ void k_c2r_x(GridParams g, const float2* spec, float* U, const float2* twx,
@@ -46,6 +82,9 @@ __global__ void k_c2r_x(GridParams g, const float2* spec, float* U, const float2
 __global__ void k_interp_corr(GridParams g, int n_occ, const int32_t* occ, const float* U,
                               const float4* pos4, const int32_t* box_start, const int32_t* prp,
                               const float* pval, const float* q, const float* uz, float* u);
+__global__ void k_interp_seg(GridParams g, IcPlan pl, const float* U, const float4* pos4,
+                             const int32_t* box_start, const int32_t* prp, const float* pval,
+                             const float* q, const float* uz, float* u);
 __global__ void k_grad(int64_t n, const int32_t* rp, const int32_t* col, const float4* gl,
                        const float* m, const float* u, float* h, float hax, float hay, float haz,
                        int with_ex, int with_ms);

@@ -65,6 +65,24 @@ __device__ __forceinline__ int st_of(uint32_t packed, int axis) {
   return (int)((packed >> (10 * axis)) & 1023u);
 }
 
+// cumulative node index of source row `srow` at unwrapped box x (the node
+// index of its first node, continued across a periodic wrap)
+__device__ __forceinline__ int row_cum(const int32_t* box_start, int64_t srow, int nbx, int per,
+                                       int tot, int x) {
+  if (per) {
+    int wrap = 0;
+    if (x < 0) {
+      x += nbx;
+      wrap = -1;
+    } else if (x > nbx) {
+      x -= nbx;
+      wrap = 1;
+    }
+    return wrap * tot + box_start[srow + x];
+  }
+  return box_start[srow + min(max(x, 0), nbx)];
+}
+
 template <int W>
 __device__ __forceinline__ float group_sum(float v) {
   // butterfly sum over groups of W consecutive lanes (W divides 64)
@@ -250,6 +268,137 @@ __global__ void __launch_bounds__(256) k_anterp(
 }
 
 // ---------------------------------------------------------------------------
+// anterpolation by grid lines. A workgroup takes `xa` consecutive points of
+// one (y, z) grid line, one thread per point. The boxes whose stencils reach
+// the line form at most (p + 1)^2 box rows; their nodes in the x-range of
+// the segment are staged once in LDS with coalesced loads, each reduced to
+// what the line needs: xi_x, its stencil start along x, and the product
+// q L_ay(xi_y) L_az(xi_z) of its charge with its y and z weights at the
+// line. Each thread then sums, row by row and in box order (a fixed order,
+// no atomics), q L_ay L_az L_ax over the nodes of the boxes covering its
+// point.
+
+__device__ __forceinline__ float basis(int a, float xi, int p) {
+  return p == 3 ? cubic_eval(cubic_basis(a), xi) : lagrange(a, xi, p);
+}
+
+__global__ void __launch_bounds__(256) k_anterp_line(
+    GridParams g, AntPlan pl, const float* __restrict__ q, const float4* __restrict__ pos4,
+    const int32_t* __restrict__ box_start, const int2* __restrict__ brx,
+    const int2* __restrict__ bry, const int2* __restrict__ brz, float* __restrict__ Q) {
+  extern __shared__ float4 smem4[];
+  unsigned char* smem = reinterpret_cast<unsigned char*>(smem4);
+  float* s_x = reinterpret_cast<float*>(smem + pl.o_x);
+  float* s_c = reinterpret_cast<float*>(smem + pl.o_c);
+  uint16_t* s_st = reinterpret_cast<uint16_t*>(smem + pl.o_st);
+  int* s_base = reinterpret_cast<int*>(smem + pl.o_meta);  // nrow + 1
+  int* s_c0 = s_base + (pl.nrow + 1);
+  int* s_b0 = s_c0 + pl.nrow;
+  int* s_tot = s_b0 + pl.nrow;
+  int* s_ay = s_tot + pl.nrow;
+  int* s_az = s_ay + pl.nrow;
+  int* s_yz = s_az + pl.nrow;
+  int* s_off = reinterpret_cast<int*>(smem + pl.o_off);  // nrow x (sbx + 1)
+  const int tid = threadIdx.x;
+  const int nbx = g.nbox[0], nby = g.nbox[1], nbz = g.nbox[2];
+  const int sx = blockIdx.x % pl.nsx, line = blockIdx.x / pl.nsx;
+  const int gy = line % g.N[1], gz = line / g.N[1];
+  const int x0 = sx * pl.xa, xa = min(pl.xa, g.N[0] - x0);
+  const int2 ry = bry[gy], rz = brz[gz];
+  const int nrow = ry.y * rz.y;
+  const int p = g.p, shift = (p - 1) / 2;
+  // first staged box (unwrapped on a periodic x) and the staged box count
+  const int2 fx = brx[x0], lxr = brx[x0 + xa - 1];
+  const int fb = g.per[0] ? x0 - p + shift : fx.x;
+  const int nbs = g.per[0] ? xa + p : lxr.x + lxr.y - fx.x;
+  const int sb1 = pl.sbx + 1;
+  // 1. box rows: by = ry.x + iy, bz = rz.x + iz (wrapped on periodic axes)
+  if (tid < nrow) {
+    const int iy = tid % ry.y, iz = tid / ry.y;
+    int by = ry.x + iy, bz = rz.x + iz;
+    if (by >= nby) by -= nby;
+    if (bz >= nbz) bz -= nbz;
+    const int64_t srow = ((int64_t)bz * nby + by) * nbx;
+    const int b0 = box_start[srow], tot = box_start[srow + nbx] - b0;
+    s_b0[tid] = b0;
+    s_tot[tid] = tot;
+    s_c0[tid] = tot > 0 ? row_cum(box_start, srow, nbx, g.per[0], tot, fb) : 0;
+    s_yz[tid] = tot > 0 ? bz * nby + by : -1;
+    // stencil index of the line in this box row's stencils
+    int ay = gy - box_stencil_start(by, g.N[1], p, g.per[1]);
+    int az = gz - box_stencil_start(bz, g.N[2], p, g.per[2]);
+    if (g.per[1]) ay = ((ay % g.N[1]) + g.N[1]) % g.N[1];
+    if (g.per[2]) az = ((az % g.N[2]) + g.N[2]) % g.N[2];
+    s_ay[tid] = ay;
+    s_az[tid] = az;
+  }
+  __syncthreads();
+  for (int e = tid; e < nrow * sb1; e += blockDim.x) {
+    const int j = e / sb1, k = e - j * sb1;
+    int off = 0;
+    if (s_yz[j] >= 0)
+      off = row_cum(box_start, (int64_t)s_yz[j] * nbx, nbx, g.per[0], s_tot[j],
+                    fb + min(k, nbs)) - s_c0[j];
+    s_off[e] = off;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int len = tid < nrow ? s_off[tid * sb1 + nbs] : 0;
+    int x = len;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(x, d, 64);
+      if (tid >= d) x += y;
+    }
+    if (tid < nrow) s_base[tid] = x - len;
+    if (tid == nrow - 1) s_base[nrow] = x;
+  }
+  __syncthreads();
+  // 2. stage the nodes with their y/z weights at this line
+  const int total = min(s_base[nrow], pl.ncap);
+  for (int e = tid; e < total; e += blockDim.x) {
+    int lo = 0, hi = nrow;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_base[mid] <= e) lo = mid;
+      else hi = mid;
+    }
+    const int c = s_c0[lo] + (e - s_base[lo]);
+    int gi = c;
+    if (g.per[0]) {
+      int rel = (c - s_b0[lo]) % s_tot[lo];
+      if (rel < 0) rel += s_tot[lo];
+      gi = s_b0[lo] + rel;
+    }
+    const float4 nd = pos4[gi];
+    const float qq = q[gi];
+    const uint32_t packed = __float_as_uint(nd.w);
+    s_x[e] = nd.x;
+    s_st[e] = (uint16_t)st_of(packed, 0);
+    s_c[e] = qq * basis(s_ay[lo], nd.y, p) * basis(s_az[lo], nd.z, p);
+  }
+  __syncthreads();
+  if (tid >= xa) return;
+  // 3. gather for the point gx
+  const int gx = x0 + tid;
+  const int2 rx = brx[gx];
+  const int k0 = g.per[0] ? tid : rx.x - fb;
+  const int kc = g.per[0] ? p + 1 : rx.y;
+  float acc = 0.f;
+  for (int j = 0; j < nrow; ++j) {
+    const int* off = s_off + j * sb1;
+    const int nb = s_base[j];
+    const int n1 = nb + off[k0 + kc];
+    for (int nn = nb + off[k0]; nn < n1; ++nn) {
+      int a = gx - (int)s_st[nn];
+      if (g.per[0] && a < 0) a += g.N[0];
+      acc = fmaf(s_c[nn], basis(a, s_x[nn], p), acc);
+    }
+  }
+  Q[((int64_t)gz * g.N[1] + gy) * g.N[0] + gx] = acc;
+}
+
+// ---------------------------------------------------------------------------
 // LDS radix-2 FFT on `lines` lines of length n stored contiguously in LDS in
 // bit-reversed order; decimation in time, natural-order output.
 
@@ -317,6 +466,133 @@ __global__ void __launch_bounds__(256) k_r2c_x(GridParams g, const float* __rest
     float2 x1 = make_float2(0.5f * (a.y + b.y), -0.5f * (a.x - b.x));
     spec[((int64_t)z * g.M[1] + y) * Hx + k] = x0;
     if (y + 1 < g.N[1]) spec[((int64_t)z * g.M[1] + y + 1) * Hx + k] = x1;
+  }
+}
+
+// LDS radix-2 FFT as lds_fft, lines `stride` elements apart (a stride of
+// n + 1 keeps column-wise access free of bank conflicts).
+__device__ void lds_fft_s(float2* buf, int n, int logn, int lines, int stride, const float2* tw,
+                          float sign) {
+  const int half_n = n >> 1;
+  const int total = lines * half_n;
+  for (int s = 1; s <= logn; ++s) {
+    const int half = 1 << (s - 1);
+    const int tstep = n >> s;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+      const int line = idx / half_n;
+      const int j = idx - line * half_n;
+      const int grp = j / half;
+      const int k = j - grp * half;
+      const int i0 = line * stride + grp * 2 * half + k;
+      const int i1 = i0 + half;
+      float2 w = tw[k * tstep];
+      w.y *= sign;
+      const float2 a = buf[i0], b = buf[i1];
+      const float2 t = make_float2(b.x * w.x - b.y * w.y, b.x * w.y + b.y * w.x);
+      buf[i0] = make_float2(a.x + t.x, a.y + t.y);
+      buf[i1] = make_float2(a.x - t.x, a.y - t.y);
+    }
+    __syncthreads();
+  }
+}
+
+// Forward transform of one z-plane held whole in LDS: real rows y < Ny are
+// paired into complex lines (R2C along x), separated into the half spectrum
+// kx < Hx, transposed into columns (stride My + 1) and transformed along y.
+// Q[z][y][x] -> spec[z][ky][kx] for all ky < My.
+__global__ void __launch_bounds__(1024) k_fft_xy_fwd(GridParams g, const float* __restrict__ Q,
+                                                     float2* __restrict__ spec,
+                                                     const float2* __restrict__ twx,
+                                                     const float2* __restrict__ twy) {
+  extern __shared__ float2 sh[];
+  const int Mx = g.M[0], My = g.M[1], Hx = Mx / 2 + 1, lx = g.logM[0], ly = g.logM[1];
+  const int Nx = g.N[0], Ny = g.N[1], pairs = (Ny + 1) / 2, cs = My + 1;
+  float2* tx = sh;
+  float2* ty = tx + Mx / 2;
+  float2* A = ty + My / 2;        // [pairs][Mx]
+  float2* C = A + pairs * Mx;     // [Hx][My + 1]
+  const int z = blockIdx.x;
+  for (int i = threadIdx.x; i < Mx / 2; i += blockDim.x) tx[i] = twx[i];
+  for (int i = threadIdx.x; i < My / 2; i += blockDim.x) ty[i] = twy[i];
+  const float* Qz = Q + (int64_t)z * Ny * Nx;
+  for (int idx = threadIdx.x; idx < pairs * Mx; idx += blockDim.x) {
+    const int li = idx / Mx, x = idx - li * Mx, y = 2 * li;
+    float re = 0.f, im = 0.f;
+    if (x < Nx) {
+      re = Qz[(int64_t)y * Nx + x];
+      if (y + 1 < Ny) im = Qz[(int64_t)(y + 1) * Nx + x];
+    }
+    A[li * Mx + bitrev(x, lx)] = make_float2(re, im);
+  }
+  // rows Ny..My-1 of the columns are the zero padding
+  for (int idx = threadIdx.x; idx < Hx * (My - 2 * pairs); idx += blockDim.x) {
+    const int k = idx % Hx, y = 2 * pairs + idx / Hx;
+    C[k * cs + bitrev(y, ly)] = make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  lds_fft_s(A, Mx, lx, pairs, Mx, tx, 1.0f);
+  for (int idx = threadIdx.x; idx < pairs * Hx; idx += blockDim.x) {
+    const int li = idx / Hx, k = idx - li * Hx, y = 2 * li;
+    const float2 a = A[li * Mx + k];
+    const float2 b = A[li * Mx + ((Mx - k) & (Mx - 1))];
+    // X_y = (Z[k] + conj Z[-k]) / 2, X_{y+1} = (Z[k] - conj Z[-k]) / (2i)
+    C[k * cs + bitrev(y, ly)] = make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y));
+    C[k * cs + bitrev(y + 1, ly)] =
+        y + 1 < Ny ? make_float2(0.5f * (a.y + b.y), -0.5f * (a.x - b.x)) : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  lds_fft_s(C, My, ly, Hx, cs, ty, 1.0f);
+  float2* Sz = spec + (int64_t)z * My * Hx;
+  for (int idx = threadIdx.x; idx < My * Hx; idx += blockDim.x) {
+    const int ky = idx / Hx, k = idx - ky * Hx;
+    Sz[idx] = C[k * cs + ky];
+  }
+}
+
+// Inverse of k_fft_xy_fwd for one z-plane: inverse FFT along y of the half
+// spectrum columns, rows y < Ny paired into complex lines with Hermitian
+// extension (C2R along x), inverse FFT along x. spec[z] -> U[z][y][x].
+__global__ void __launch_bounds__(1024) k_fft_yx_inv(GridParams g, const float2* __restrict__ spec,
+                                                     float* __restrict__ U,
+                                                     const float2* __restrict__ twx,
+                                                     const float2* __restrict__ twy) {
+  extern __shared__ float2 sh[];
+  const int Mx = g.M[0], My = g.M[1], Hx = Mx / 2 + 1, lx = g.logM[0], ly = g.logM[1];
+  const int Nx = g.N[0], Ny = g.N[1], pairs = (Ny + 1) / 2, cs = My + 1;
+  float2* tx = sh;
+  float2* ty = tx + Mx / 2;
+  float2* A = ty + My / 2;
+  float2* C = A + pairs * Mx;
+  const int z = blockIdx.x;
+  for (int i = threadIdx.x; i < Mx / 2; i += blockDim.x) tx[i] = twx[i];
+  for (int i = threadIdx.x; i < My / 2; i += blockDim.x) ty[i] = twy[i];
+  const float2* Sz = spec + (int64_t)z * My * Hx;
+  for (int idx = threadIdx.x; idx < My * Hx; idx += blockDim.x) {
+    const int ky = idx / Hx, k = idx - ky * Hx;
+    C[k * cs + bitrev(ky, ly)] = Sz[idx];
+  }
+  __syncthreads();
+  lds_fft_s(C, My, ly, Hx, cs, ty, -1.0f);
+  for (int idx = threadIdx.x; idx < pairs * Mx; idx += blockDim.x) {
+    const int li = idx / Mx, k = idx - li * Mx, y = 2 * li;
+    const int kk = k <= Mx / 2 ? k : Mx - k;
+    float2 a = C[kk * cs + y];
+    float2 b = y + 1 < Ny ? C[kk * cs + y + 1] : make_float2(0.f, 0.f);
+    if (k > Mx / 2) {
+      a.y = -a.y;
+      b.y = -b.y;
+    }
+    // Z = X_y + i X_{y+1}
+    A[li * Mx + bitrev(k, lx)] = make_float2(a.x - b.y, a.y + b.x);
+  }
+  __syncthreads();
+  lds_fft_s(A, Mx, lx, pairs, Mx, tx, -1.0f);
+  float* Uz = U + (int64_t)z * Ny * Nx;
+  for (int idx = threadIdx.x; idx < pairs * Nx; idx += blockDim.x) {
+    const int li = idx / Nx, x = idx - li * Nx, y = 2 * li;
+    const float2 v = A[li * Mx + x];
+    Uz[(int64_t)y * Nx + x] = v.x;
+    if (y + 1 < Ny) Uz[(int64_t)(y + 1) * Nx + x] = v.y;
   }
 }
 
@@ -639,6 +915,201 @@ __global__ void __launch_bounds__(256) k_interp_corr(
     }
     acc = group_sum<G>(acc);
     if (act && lane == 0) u[r] = acc + uz[r];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// interpolation + precorrection, segment form. A workgroup takes `xs`
+// consecutive boxes of one (y, z) box row; their rows are contiguous. Every
+// source charge those rows need lies in the (2 r_b + 1)^2 neighbouring box
+// rows, boxes x0 - r_b .. x0 + xs + r_b - 1 (unwrapped along a periodic x),
+// so these are staged once in LDS with coalesced loads, together with the
+// (p + 1)^2 stencil lines of U the segment reads. Then each 16-lane group
+// takes one observer row at a time: it copies the row's window charges from
+// the staged rows into column order (pair-major, each x-run in unwrapped box
+// order, which is the storage order of the precorrection values), streams
+// the row's matrix values, and adds W U from the staged lines.
+
+__global__ void __launch_bounds__(256) k_interp_seg(
+    GridParams g, IcPlan pl, const float* __restrict__ U, const float4* __restrict__ pos4,
+    const int32_t* __restrict__ box_start, const int32_t* __restrict__ prp,
+    const float* __restrict__ pval, const float* __restrict__ q, const float* __restrict__ uz,
+    float* __restrict__ u) {
+  extern __shared__ float4 smem4[];
+  unsigned char* smem = reinterpret_cast<unsigned char*>(smem4);
+  float* s_q = reinterpret_cast<float*>(smem + pl.o_q);
+  float* s_U = reinterpret_cast<float*>(smem + pl.o_u);
+  int* s_base = reinterpret_cast<int*>(smem + pl.o_meta);  // np + 1 staged row starts
+  int* s_c0 = s_base + (pl.np + 1);                          // cumulative index at x0 - r_b
+  int* s_b0 = s_c0 + pl.np;                                  // first node of the row
+  int* s_tot = s_b0 + pl.np;                                 // nodes in the row
+  int* s_yz = s_tot + pl.np;                                 // row index, -1 if outside
+  uint16_t* s_off = reinterpret_cast<uint16_t*>(smem + pl.o_off);  // np x (sb + 1)
+  uint16_t* s_row = reinterpret_cast<uint16_t*>(smem + pl.o_row);  // box of each row
+  const int tid = threadIdx.x;
+  const int nbx = g.nbox[0], nby = g.nbox[1], nbz = g.nbox[2];
+  const int sx = blockIdx.x % pl.nsx, byz = blockIdx.x / pl.nsx;
+  const int by = byz % nby, bz = byz / nby;
+  const int x0 = sx * pl.xs, xs = min(pl.xs, nbx - x0);
+  const int64_t orow = ((int64_t)bz * nby + by) * nbx;
+  const int r_lo = box_start[orow + x0], r_hi = box_start[orow + x0 + xs];
+  if (r_lo == r_hi) return;  // uniform across the workgroup
+  const int rb = g.rb, W = 2 * rb + 1, np = pl.np, sb1 = pl.sb + 1, p1 = g.p + 1;
+  const int shift = (g.p - 1) / 2;
+
+  // 1. source rows
+  if (tid < np) {
+    int y = by + tid % W - rb, z = bz + tid / W - rb;
+    bool ok = true;
+    if (g.per[1]) y = (y + nby) % nby;
+    else ok = ok && y >= 0 && y < nby;
+    if (g.per[2]) z = (z + nbz) % nbz;
+    else ok = ok && z >= 0 && z < nbz;
+    int b0 = 0, tot = 0, c0 = 0, yz = -1;
+    if (ok) {
+      yz = z * nby + y;
+      const int64_t srow = (int64_t)yz * nbx;
+      b0 = box_start[srow];
+      tot = box_start[srow + nbx] - b0;
+      c0 = row_cum(box_start, srow, nbx, g.per[0], tot, x0 - rb);
+    }
+    s_b0[tid] = b0;
+    s_tot[tid] = tot;
+    s_c0[tid] = c0;
+    s_yz[tid] = tot > 0 ? yz : -1;
+  }
+  __syncthreads();
+  // 2. per source row, staged offset of each unwrapped box x0 - r_b + k
+  for (int e = tid; e < np * sb1; e += blockDim.x) {
+    const int i = e / sb1, k = e - i * sb1;
+    int off = 0;
+    if (s_yz[i] >= 0)
+      off = row_cum(box_start, (int64_t)s_yz[i] * nbx, nbx, g.per[0], s_tot[i], x0 - rb + k) -
+            s_c0[i];
+    s_off[e] = (uint16_t)off;
+  }
+  // observer row -> box of the segment
+  for (int k = tid; k < xs; k += blockDim.x) {
+    const int a = box_start[orow + x0 + k] - r_lo, b = box_start[orow + x0 + k + 1] - r_lo;
+    for (int r = a; r < b && r < pl.rcap; ++r) s_row[r] = (uint16_t)k;
+  }
+  // stencil lines of U: (ay, az) in [0, p]^2, x from the segment's first stencil start
+  const int sty = box_stencil_start(by, g.N[1], g.p, g.per[1]);
+  const int stz = box_stencil_start(bz, g.N[2], g.p, g.per[2]);
+  const int ux0 = box_stencil_start(x0, g.N[0], g.p, g.per[0]);
+  for (int e = tid; e < p1 * p1 * pl.ux; e += blockDim.x) {
+    const int l = e / pl.ux, t = e - l * pl.ux;
+    int y = sty + l % p1, z = stz + l / p1, x = ux0 + t;
+    if (g.per[1]) y = (y + g.N[1]) % g.N[1];
+    if (g.per[2]) z = (z + g.N[2]) % g.N[2];
+    float v = 0.f;
+    if (g.per[0]) {
+      x = (x + g.N[0]) % g.N[0];
+      v = U[((int64_t)z * g.N[1] + y) * g.N[0] + x];
+    } else if (x < g.N[0]) {
+      v = U[((int64_t)z * g.N[1] + y) * g.N[0] + x];
+    }
+    s_U[e] = v;
+  }
+  __syncthreads();
+  // 3. staged row starts (one wave scans np <= 49 lengths)
+  if (tid < 64) {
+    const int len = tid < np ? (int)s_off[tid * sb1 + pl.sb] : 0;
+    int x = len;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(x, d, 64);
+      if (tid >= d) x += y;
+    }
+    if (tid < np) s_base[tid] = x - len;
+    if (tid == np - 1) s_base[np] = x;
+  }
+  __syncthreads();
+  // 4. stage the source charges (coalesced per source row)
+  const int total = min(s_base[np], pl.qcap);
+  for (int e = tid; e < total; e += blockDim.x) {
+    int lo = 0, hi = np;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_base[mid] <= e) lo = mid;
+      else hi = mid;
+    }
+    const int c = s_c0[lo] + (e - s_base[lo]);
+    int gi = c;
+    if (g.per[0]) {
+      int rel = (c - s_b0[lo]) % s_tot[lo];
+      if (rel < 0) rel += s_tot[lo];
+      gi = s_b0[lo] + rel;
+    }
+    s_q[e] = q[gi];
+  }
+  __syncthreads();
+
+  // 5. rows: one per 16-lane group
+  constexpr int G = 16, KP = 16;
+  const int lane = tid & (G - 1), grp = tid / G, ngrp = blockDim.x / G;
+  float* col = reinterpret_cast<float*>(smem + pl.o_col) + grp * pl.scap;
+  const bool cubic = g.p == 3;
+  const Cubic cx = cubic_basis(lane & 3), cy = cubic_basis(lane >> 2);
+  const Cubic cz0 = cubic_basis(0), cz1 = cubic_basis(1), cz2 = cubic_basis(2), cz3 = cubic_basis(3);
+  for (int r = r_lo + grp; r < r_hi; r += ngrp) {
+    const int pr = prp[r];
+    const int S = prp[r + 1] - pr;
+    float pv[KP];
+#pragma unroll
+    for (int j = 0; j < KP; ++j) {
+      const int idx = lane + G * j;
+      pv[j] = idx < S ? pval[pr + idx] : 0.f;
+    }
+    const float4 xi = pos4[r];
+    const int k = r - r_lo < pl.rcap ? (int)s_row[r - r_lo] : 0;
+    // window charges into column order
+    int sacc = 0;
+    for (int i0 = 0; i0 < np; i0 += G) {
+      const int i = i0 + lane;
+      int len = 0, src = 0;
+      if (i < np) {
+        const int a = s_off[i * sb1 + k], b = s_off[i * sb1 + k + W];
+        len = b - a;
+        src = s_base[i] + a;
+      }
+      int tot;
+      const int dst = sacc + group_excl_scan<G>(len, lane, tot);
+      sacc += tot;
+      for (int c = 0; c < len; ++c)
+        if (dst + c < pl.scap) col[dst + c] = s_q[src + c];
+    }
+    wave_lds_sync();
+    const int rl = min(min(S, sacc), pl.scap);
+    float acc = 0.f;
+#pragma unroll
+    for (int j = 0; j < KP; ++j) {
+      const int idx = lane + G * j;
+      if (idx < rl) acc = fmaf(pv[j], col[idx], acc);
+    }
+    for (int idx = lane + G * KP; idx < rl; idx += G) acc = fmaf(pval[pr + idx], col[idx], acc);
+    // W U from the staged stencil lines
+    const int bx = x0 + k;
+    const int rel = g.per[0] ? k : box_stencil_start(bx, g.N[0], g.p, 0) - ux0;
+    if (cubic) {
+      const float* su = s_U + (lane >> 2) * pl.ux + rel + (lane & 3);
+      const int zs = 4 * pl.ux;
+      const float wxy = cubic_eval(cx, xi.x) * cubic_eval(cy, xi.y);
+      acc = fmaf(wxy * cubic_eval(cz0, xi.z), su[0], acc);
+      acc = fmaf(wxy * cubic_eval(cz1, xi.z), su[zs], acc);
+      acc = fmaf(wxy * cubic_eval(cz2, xi.z), su[2 * zs], acc);
+      acc = fmaf(wxy * cubic_eval(cz3, xi.z), su[3 * zs], acc);
+    } else {
+      const int nst = p1 * p1 * p1;
+      for (int l = lane; l < nst; l += G) {
+        const int ax = l % p1, ay = (l / p1) % p1, az = l / (p1 * p1);
+        acc = fmaf(lagrange(ax, xi.x, g.p) * lagrange(ay, xi.y, g.p) * lagrange(az, xi.z, g.p),
+                   s_U[(az * p1 + ay) * pl.ux + rel + ax], acc);
+      }
+    }
+    acc = group_sum<G>(acc);
+    if (lane == 0) u[r] = acc + uz[r];
+    wave_lds_sync();  // the column buffer is rewritten for the next row
   }
 }
 

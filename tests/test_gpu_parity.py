@@ -22,8 +22,14 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def lib_fields(prob, m_nodes, **kw):
+# kernel forms: staged (the default choice) and the basic forms of each stage
+FORMS = {"staged": dict(anterp=2, interp=2, fft=2), "basic": dict(anterp=1, interp=1, fft=1)}
+
+
+def lib_fields(prob, m_nodes, forms=None, **kw):
     ctx = B.Context.from_problem(prob, device=0, **kw)
+    for stage, v in (forms or {}).items():
+        ctx.set_variant(stage, v)
     n, uon, nou, _ = ctx.query()
     m = torch.tensor(np.asarray(m_nodes)[nou], dtype=torch.float32, device="cuda")
     h = torch.empty_like(m)
@@ -57,25 +63,28 @@ def test_heff_parity_small(name):
     prob = SMALL[name]()
     kw = KW.get(name, {})
     print(f"[gpu parity] {name} nodes={prob.n_nodes}", flush=True)
-    ctx, nou, got = lib_fields(prob, prob.m, **kw)
     orc = model.Oracle(prob, order_p=kw.get("order_p"), near_boxes=kw.get("near_boxes"))
-    perm = orc.uk[nou]
     m = orc.unknown_values(prob.m)
-    H = orc.heff(m, method="aim")[perm]
-    Hex = orc.heff(m, method="aim", terms=("ex",))[perm]
-    Hms = orc.heff(m, method="aim", terms=("ms",))[perm]
-    q = orc.charges(m)[perm]
-    u = orc.potential(m, None, "aim")[perm]
-    errs = {k: rel(got[k], ref) for k, ref in
-            dict(hex=Hex, hms=Hms, h=H, q=q, u=u).items()}
-    print(f"[gpu parity] {name} rel L2: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
-    for k, v in errs.items():
-        assert v <= TOL, (k, v)
+    ref = dict(h=orc.heff(m, method="aim"), hex=orc.heff(m, method="aim", terms=("ex",)),
+               hms=orc.heff(m, method="aim", terms=("ms",)), q=orc.charges(m),
+               u=orc.potential(m, None, "aim"))
+    for form, forms in FORMS.items():
+        print(f"[gpu parity] {name} forms={form}", flush=True)
+        ctx, nou, got = lib_fields(prob, prob.m, forms, **kw)
+        perm = orc.uk[nou]
+        errs = {k: rel(got[k], r[perm]) for k, r in ref.items()}
+        print(f"[gpu parity] {name} {form} rel L2: "
+              + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+        for k, v in errs.items():
+            assert v <= TOL, (form, k, v)
 
 
-def test_grid_convolution_alone():
-    prob = mg.wire_c2(R=3e-9, period=6e-9, spacing=1.0e-9, n_layers=6, grid=(8, 8, 16))
+@pytest.mark.parametrize("fft", [1, 2])
+@pytest.mark.parametrize("case", ["wire_small", "box3d_jitter_ragged"])
+def test_grid_convolution_alone(case, fft):
+    prob = SMALL[case]()
     ctx = B.Context.from_problem(prob, device=0)
+    ctx.set_variant("fft", fft)
     orc = model.Oracle(prob)
     N = orc.aim.grid.N
     rng = np.random.default_rng(3)
@@ -85,7 +94,9 @@ def test_grid_convolution_alone():
     ctx.grid_convolve(qg, ug)
     U = ug.cpu().numpy().astype(np.float64).transpose(2, 1, 0)
     ref = orc.aim.convolve(Q) / (4 * np.pi)
-    assert rel(U, ref) <= 1e-6
+    err = rel(U, ref)
+    print(f"[gpu parity] convolution {case} fft={fft}: rel L2 {err:.2e}", flush=True)
+    assert err <= 1e-6
 
 
 def test_bitwise_deterministic_and_terms():

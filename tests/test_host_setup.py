@@ -198,3 +198,14 @@ def test_library_exports_every_declared_symbol():
     for nm in sorted(names):
         assert hasattr(dll, nm), nm
     assert names == set(lib.EXPORTED)
+
+
+def test_kernel_variant_arguments_are_checked():
+    c = lib.Context(device=-1)
+    c.set_variant("anterp", 1)
+    c.set_variant("interp", 2)
+    c.set_variant("fft", 0)
+    for stage, v in (("anterp", 3), ("interp", -1), ("convolution", 1)):
+        with pytest.raises(lib.PmfemError) as e:
+            c.set_variant(stage, v)
+        assert e.value.code == lib.Status.EINVAL
