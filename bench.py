@@ -29,8 +29,8 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_bytes(ctx):
-    """Algorithmic HBM bytes per launch of each kernel (every array once)."""
+def kernel_bytes(ctx, names):
+    """Algorithmic HBM bytes per launch of each named kernel (every array once)."""
     info = ctx.export("grid_info")
     N = info[0:3].astype(np.int64)
     M = info[3:6].astype(np.int64)
@@ -44,7 +44,7 @@ def kernel_bytes(ctx):
     s_in = float(N[2] * N[1]) * hx * 8      # half-spectrum rows y < Ny
     s_full = float(N[2] * M[1]) * hx * 8    # half-spectrum, all My rows
     khat = hx * M[1] * M[2] * 4
-    return {
+    fam = {
         "k_local": n * (8 + 12 + 4 + 4) + nL * 16 + nZ * 16,
         "k_anterp": n * (4 + 16) + nbox * 4 + ng * 4,
         "k_r2c_x": ng * 4 + s_in,
@@ -54,10 +54,12 @@ def kernel_bytes(ctx):
         "k_c2r_x": s_in + ng * 4,
         "k_fft_xy_fwd": ng * 4 + s_full,
         "k_fft_yx_inv": s_full + ng * 4,
-        "k_interp_corr": n * (16 + 4 + 4 + 4 + 4) + ng * 4 + nP * 4,
-        "k_interp_seg": n * (16 + 4 + 4 + 4 + 4) + ng * 4 + nP * 4,
+        "k_interp": n * (16 + 4 + 4 + 4 + 4) + ng * 4 + nP * 4,
         "k_grad": n * (4 + 12 + 4 + 12) + nL * 20,
     }
+    # every form of a stage moves the same algorithmic bytes (longest prefix wins)
+    return {name: next(v for k, v in sorted(fam.items(), key=lambda kv: -len(kv[0]))
+                       if name.startswith(k)) for name in names}
 
 
 def cpu_baseline(prob, rows_sample=64, seed=7):
@@ -170,7 +172,7 @@ def main():
     prof = ctx.profile_end()
     dt = (t1 - t0) / args.steps
     log(f"timed {args.steps} steps: {dt * 1e3:.4f} ms/step")
-    kb = kernel_bytes(ctx)
+    kb = kernel_bytes(ctx, list(prof))
     per_kernel = {k: (ms / max(c, 1), c) for k, (ms, c) in prof.items()}
     for k, (avg, c) in per_kernel.items():
         gbs = kb[k] / (avg * 1e-3) / 1e9 if avg > 0 else 0.0

@@ -103,10 +103,12 @@ int pmfem_set_aim(pmfem_ctx* ctx, const int32_t grid[3], int32_t order_p, int32_
 /*
  * Kernel form of one stage of the evaluation; the results agree within
  * FP32 rounding order. stage "anterp": 1 tile gather, 2 line gather;
- * "interp" (interpolation + precorrection): 1 per-box, 2 box-row segment;
- * "fft": 1 separate x, y, z passes, 2 whole z-planes in LDS for x and y.
- * variant 0 (the default) picks the staged forms (2) wherever their LDS
- * plans fit. May be called before or after pmfem_build; EINVAL if the stage
+ * "interp" (interpolation + precorrection): 1 narrow observer tiles (at
+ * most 4 boxes along x), 2 the largest tiles whose staging fits in LDS;
+ * "fft": 1 separate x, y, z passes, 2 whole z-planes in LDS for x and y;
+ * "spmv" (charges, element correction, exchange and gradient rows): 4, 8
+ * or 16 lanes per row. variant 0 (the default) picks the staged forms (2)
+ * wherever their LDS plans fit, and 16 lanes per row. May be called before or after pmfem_build; EINVAL if the stage
  * or variant is unknown or a forced form does not fit the built problem
  * (the previous choice is kept).
  */

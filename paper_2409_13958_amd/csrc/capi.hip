@@ -18,23 +18,23 @@ struct pmfem_dev {
   GridParams g{};
   float4* pos4 = nullptr;
   int32_t* box_start = nullptr;
-  int32_t* occ = nullptr;  // boxes holding at least one unknown
-  int n_occ = 0;
   AntPlan ap{};            // line form of anterpolation
   bool ant_ok = false, ic_ok = false, fft_ok = false;  // the plans fit
   bool ant_line = false;   // false: the tile form k_anterp
   int ant_threads = 0;
-  IcPlan icp{};            // segment form of interpolation+precorrection
-  bool ic_seg = false;     // false: the per-box form k_interp_corr
+  IcPlan icp{}, icp_small{};  // interpolation+precorrection tiles: chosen, narrow
+  bool ic_small_ok = false;
+  bool ic_seg = false;        // false: the narrow tiles
   bool fft_plane = false;  // x and y transforms of a whole z-plane in one kernel
   size_t fft_plane_lds = 0;
   const char* kname[9] = {};  // kernel in each profiling slot
   int2 *brx = nullptr, *bry = nullptr, *brz = nullptr;
   int32_t *lrp = nullptr, *lcol = nullptr;
-  float *ldx = nullptr, *ldy = nullptr, *ldz = nullptr;  // charge operator D
-  float4* lgl = nullptr;                                   // {Gx, Gy, Gz, L}
-  int32_t *zrp = nullptr, *zcol = nullptr;
-  float *zx = nullptr, *zy = nullptr, *zz = nullptr;
+  int4* drec = nullptr;   // charge operator D: {column, Dx, Dy, Dz}
+  float4* lgl = nullptr;  // {Gx, Gy, Gz, L}
+  int32_t* zrp = nullptr;
+  int4* zrec = nullptr;   // element correction Z0: {column, Zx, Zy, Zz}
+  int lanes = 16;         // lanes per row of k_local / k_grad
   int32_t* prp = nullptr;
   float* pv = nullptr;
   float* khat = nullptr;
@@ -137,8 +137,12 @@ std::vector<int2> box_ranges(const HostOps& o, int a) {
 int select_variants(pmfem_ctx* c) {
   pmfem_dev* d = c->dev;
   const int va = c->variant[0], vi = c->variant[1], vf = c->variant[2];
-  if ((va == 2 && !d->ant_ok) || (vi == 2 && !d->ic_ok) || (vf == 2 && !d->fft_ok))
+  d->lanes = c->variant[3] == 0 ? 16 : c->variant[3];
+  if ((va == 2 && !d->ant_ok) || (vi == 2 && !d->ic_ok) || (vf == 2 && !d->fft_ok) ||
+      (vi == 1 && !d->ic_small_ok))
     return set_err(c, PMFEM_EINVAL, "requested kernel form does not fit this problem");
+  if (!d->ic_ok && !d->ic_small_ok)
+    return set_err(c, PMFEM_EGRID, "near region too dense for the LDS staging of any tile");
   d->ant_line = va == 0 ? d->ant_ok : va == 2;
   d->ic_seg = vi == 0 ? d->ic_ok : vi == 2;
   d->fft_plane = vf == 0 ? d->fft_ok : vf == 2;
@@ -153,7 +157,7 @@ int select_variants(pmfem_ctx* c) {
     d->kname[6] = "k_fft_yx_inv";
   }
   d->kname[1] = d->ant_line ? "k_anterp_line" : "k_anterp";
-  d->kname[7] = d->ic_seg ? "k_interp_seg" : "k_interp_corr";
+  d->kname[7] = "k_interp_tile";
   return PMFEM_OK;
 }
 
@@ -233,80 +237,90 @@ bool plan_anterp(const HostOps& o, const std::vector<int2>& bx, const std::vecto
   return false;
 }
 
-// Segment plan for k_interp_seg: the widest x-segment (at most 128 boxes)
-// whose staged arrays fit in 64 KB of LDS. Returns false if none fits.
-bool plan_interp(const HostOps& o, IcPlan& pl) {
+// Tile plan for k_interp_tile: the largest tile (xs boxes along x times tz
+// box rows along z, both powers of two, xs <= max_xs) whose staged arrays fit
+// the LDS budget; larger tiles stage each source charge fewer times.
+bool plan_interp(const HostOps& o, int max_xs, IcPlan& pl) {
   const int nbx = o.nbox[0], nby = o.nbox[1], nbz = o.nbox[2];
-  const int rb = o.rb, W = 2 * rb + 1, np = W * W, p1 = o.p + 1;
+  const int rb = o.rb, W = 2 * rb + 1, p = o.p;
   const std::vector<int32_t>& bs = o.box_start;
-  int scap = 0;
-  for (int64_t r = 0; r < o.n_unk; ++r)
-    scap = std::max<int>(scap, o.p_rowptr[r + 1] - o.p_rowptr[r]);
-  scap = std::max(4, (scap + 3) & ~3);
-  // cumulative node index of a source row at unwrapped box x (as in the kernel)
-  auto cum = [&](int64_t srow, int tot, int x) -> int64_t {
-    if (o.per[0]) {
-      int64_t wrap = 0;
-      if (x < 0) {
-        x += nbx;
-        wrap = -1;
-      } else if (x > nbx) {
-        x -= nbx;
-        wrap = 1;
-      }
-      return wrap * tot + bs[srow + x];
-    }
-    return bs[srow + std::min(std::max(x, 0), nbx)];
+  auto cnt = [&](int x, int y, int z) -> int64_t {
+    if (o.per[0]) x = (x % nbx + nbx) % nbx;
+    else if (x < 0 || x >= nbx) return 0;
+    if (o.per[1]) y = (y % nby + nby) % nby;
+    else if (y < 0 || y >= nby) return 0;
+    if (o.per[2]) z = (z % nbz + nbz) % nbz;
+    else if (z < 0 || z >= nbz) return 0;
+    const int64_t b = ((int64_t)z * nby + y) * nbx + x;
+    return bs[b + 1] - bs[b];
   };
-  for (int xs = std::min(nbx, 128); xs >= 1; xs /= 2) {
-    const int nsx = (nbx + xs - 1) / xs, sb = xs + 2 * rb;
-    int64_t qcap = 0, rcap = 0;
-    for (int bz = 0; bz < nbz; ++bz)
-      for (int by = 0; by < nby; ++by) {
-        const int64_t orow = ((int64_t)bz * nby + by) * nbx;
+  struct Shape {
+    int xs, tz;
+  };
+  std::vector<Shape> shapes;
+  for (int xs = 1; xs <= std::min(max_xs, 128); xs *= 2)
+    for (int tz = 1; tz <= 16; tz *= 2)
+      if (xs * tz <= 512 && (xs <= nbx || xs == 1) && (tz <= nbz || tz == 1))
+        shapes.push_back({xs, tz});
+  // largest staged-to-observer ratio first: fewest staged boxes per observer box
+  std::sort(shapes.begin(), shapes.end(), [&](const Shape& a, const Shape& b) {
+    const double ra = (double)(a.xs + 2 * rb) * (a.tz + 2 * rb) / (a.xs * a.tz);
+    const double rb2 = (double)(b.xs + 2 * rb) * (b.tz + 2 * rb) / (b.xs * b.tz);
+    return ra < rb2;
+  });
+  for (const Shape& sh : shapes) {
+    const int xs = sh.xs, tz = sh.tz;
+    const int nsx = (nbx + xs - 1) / xs, nsz = (nbz + tz - 1) / tz;
+    const int sbx = xs + 2 * rb, szr = tz + 2 * rb;
+    int64_t qcap = 0, rcap = 0, colmax = 0;
+    for (int sz = 0; sz < nsz; ++sz)
+      for (int by = 0; by < nby; ++by)
         for (int sx = 0; sx < nsx; ++sx) {
-          const int x0 = sx * xs, xe = std::min(x0 + xs, nbx);
-          const int64_t rows = bs[orow + xe] - bs[orow + x0];
+          const int x0 = sx * xs, z0 = sz * tz;
+          int64_t rows = 0;
+          for (int kz = 0; kz < tz && z0 + kz < nbz; ++kz)
+            for (int kx = 0; kx < xs && x0 + kx < nbx; ++kx) rows += cnt(x0 + kx, by, z0 + kz);
           if (rows == 0) continue;
           rcap = std::max(rcap, rows);
           int64_t staged = 0;
-          for (int i = 0; i < np; ++i) {
-            int y = by + i % W - rb, z = bz + i / W - rb;
-            if (o.per[1]) y = (y + nby) % nby;
-            else if (y < 0 || y >= nby) continue;
-            if (o.per[2]) z = (z + nbz) % nbz;
-            else if (z < 0 || z >= nbz) continue;
-            const int64_t srow = ((int64_t)z * nby + y) * nbx;
-            const int tot = bs[srow + nbx] - bs[srow];
-            if (tot == 0) continue;
-            staged += cum(srow, tot, x0 - rb + sb) - cum(srow, tot, x0 - rb);
+          for (int k = 0; k < sbx; ++k) {
+            int64_t col = 0;
+            for (int zz = 0; zz < szr; ++zz)
+              for (int yy = 0; yy < W; ++yy)
+                col += cnt(x0 - rb + k, by - rb + yy, z0 - rb + zz);
+            colmax = std::max(colmax, col);
+            staged += col;
           }
           qcap = std::max(qcap, staged);
         }
-      }
     auto al = [](int64_t b) { return (b + 15) & ~(int64_t)15; };
+    const int ux = xs + p, uzl = tz + p;
     int64_t off = 0;
     pl.o_q = (int)off;
     off += al(std::max<int64_t>(qcap, 1) * 4);
+    pl.o_pos = (int)off;
+    off += al((int64_t)sbx * (szr * W + 1) * 2);
+    pl.o_col0 = (int)off;
+    off += al((int64_t)(sbx + 1) * 4);
     pl.o_u = (int)off;
-    off += al((int64_t)p1 * p1 * (xs + o.p) * 4);
-    pl.o_col = (int)off;
-    off += al((int64_t)16 * scap * 4);
-    pl.o_meta = (int)off;
-    off += al((int64_t)(5 * np + 1) * 4);
-    pl.o_off = (int)off;
-    off += al((int64_t)np * (sb + 1) * 2);
-    pl.o_row = (int)off;
+    off += al((int64_t)uzl * (p + 1) * ux * 4);
+    pl.o_rtab = (int)off;
     off += al(std::max<int64_t>(rcap, 1) * 2);
-    if (off <= 65536 && qcap < 65536 && rcap < 65536) {
+    pl.o_prp = (int)off;
+    off += al(std::max<int64_t>(rcap, 1) * 4);
+    pl.o_seg = (int)off;
+    off += al((int64_t)(2 * tz + 1) * 4);
+    if (off <= 40960 && colmax < 65536 && (int64_t)tz * xs < 65536) {
       pl.xs = xs;
+      pl.tz = tz;
       pl.nsx = nsx;
-      pl.np = np;
-      pl.sb = sb;
-      pl.qcap = (int)qcap;
-      pl.ux = xs + o.p;
-      pl.scap = scap;
+      pl.nsz = nsz;
+      pl.sbx = sbx;
+      pl.szr = szr;
+      pl.qcap = (int)std::max<int64_t>(qcap, 1);
       pl.rcap = (int)std::max<int64_t>(rcap, 1);
+      pl.ux = ux;
+      pl.uzl = uzl;
       pl.lds_bytes = (int)off;
       return true;
     }
@@ -331,14 +345,8 @@ int upload_all(pmfem_ctx* c) {
   int rc;
   if ((rc = upload(c, &d->pos4, o.pos4.data(), n))) return rc;
   if ((rc = upload(c, &d->box_start, o.box_start.data(), o.box_start.size()))) return rc;
-  {
-    std::vector<int32_t> occ;
-    for (size_t b = 0; b + 1 < o.box_start.size(); ++b)
-      if (o.box_start[b + 1] > o.box_start[b]) occ.push_back((int32_t)b);
-    d->n_occ = (int)occ.size();
-    if ((rc = upload(c, &d->occ, occ.data(), occ.size()))) return rc;
-  }
-  d->ic_ok = plan_interp(o, d->icp);
+  d->ic_ok = plan_interp(o, 128, d->icp);
+  d->ic_small_ok = plan_interp(o, 4, d->icp_small);
 
   {
     // whole-plane x/y transforms when a plane (row pairs + half-spectrum
@@ -369,35 +377,36 @@ int upload_all(pmfem_ctx* c) {
   if ((rc = upload(c, &d->brz, bz.data(), bz.size()))) return rc;
   const int64_t nnzL = o.loc_rowptr[n];
   {
-    std::vector<float> dx(nnzL), dy(nnzL), dz(nnzL);
+    std::vector<int4> dr(nnzL);
     std::vector<float4> gl(nnzL);
     for (int64_t e = 0; e < nnzL; ++e) {
       const float* v = &o.loc_val[8 * e];  // L, Dx, Dy, Dz, Gx, Gy, Gz, 0
-      dx[e] = v[1];
-      dy[e] = v[2];
-      dz[e] = v[3];
+      int4 r;
+      r.x = o.loc_col[e];
+      std::memcpy(&r.y, &v[1], 4);
+      std::memcpy(&r.z, &v[2], 4);
+      std::memcpy(&r.w, &v[3], 4);
+      dr[e] = r;
       gl[e] = make_float4(v[4], v[5], v[6], v[0]);
     }
     if ((rc = upload(c, &d->lrp, o.loc_rowptr.data(), n + 1))) return rc;
     if ((rc = upload(c, &d->lcol, o.loc_col.data(), nnzL))) return rc;
-    if ((rc = upload(c, &d->ldx, dx.data(), nnzL))) return rc;
-    if ((rc = upload(c, &d->ldy, dy.data(), nnzL))) return rc;
-    if ((rc = upload(c, &d->ldz, dz.data(), nnzL))) return rc;
+    if ((rc = upload(c, &d->drec, dr.data(), nnzL))) return rc;
     if ((rc = upload(c, &d->lgl, gl.data(), nnzL))) return rc;
   }
   const int64_t nnzZ = o.z0_rowptr[n];
   {
-    std::vector<float> zx(nnzZ), zy(nnzZ), zz(nnzZ);
+    std::vector<int4> zr(nnzZ);
     for (int64_t e = 0; e < nnzZ; ++e) {
-      zx[e] = o.z0_val[4 * e];
-      zy[e] = o.z0_val[4 * e + 1];
-      zz[e] = o.z0_val[4 * e + 2];
+      int4 r;
+      r.x = o.z0_col[e];
+      std::memcpy(&r.y, &o.z0_val[4 * e], 4);
+      std::memcpy(&r.z, &o.z0_val[4 * e + 1], 4);
+      std::memcpy(&r.w, &o.z0_val[4 * e + 2], 4);
+      zr[e] = r;
     }
     if ((rc = upload(c, &d->zrp, o.z0_rowptr.data(), n + 1))) return rc;
-    if ((rc = upload(c, &d->zcol, o.z0_col.data(), nnzZ))) return rc;
-    if ((rc = upload(c, &d->zx, zx.data(), nnzZ))) return rc;
-    if ((rc = upload(c, &d->zy, zy.data(), nnzZ))) return rc;
-    if ((rc = upload(c, &d->zz, zz.data(), nnzZ))) return rc;
+    if ((rc = upload(c, &d->zrec, zr.data(), nnzZ))) return rc;
   }
   const int64_t nnzP = o.p_rowptr[n];
   if ((rc = upload(c, &d->prp, o.p_rowptr.data(), n + 1))) return rc;
@@ -502,9 +511,16 @@ int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const doubl
   const int T = 256;
   if (with_ms) {
     mark(0, 0);
-    hipLaunchKernelGGL(k_local, dim3((unsigned)((n * 16 + T - 1) / T)), dim3(T), 0, s, n, m,
-                       d->lrp, d->lcol, d->ldx, d->ldy, d->ldz, d->zrp, d->zcol, d->zx, d->zy,
-                       d->zz, d->q, d->uz);
+    const dim3 grid((unsigned)((n * d->lanes + T - 1) / T));
+    if (d->lanes == 4)
+      hipLaunchKernelGGL(k_local<4>, grid, dim3(T), 0, s, n, m, d->lrp, d->drec, d->zrp,
+                         d->zrec, d->q, d->uz);
+    else if (d->lanes == 8)
+      hipLaunchKernelGGL(k_local<8>, grid, dim3(T), 0, s, n, m, d->lrp, d->drec, d->zrp,
+                         d->zrec, d->q, d->uz);
+    else
+      hipLaunchKernelGGL(k_local<16>, grid, dim3(T), 0, s, n, m, d->lrp, d->drec, d->zrp,
+                         d->zrec, d->q, d->uz);
     mark(0, 1);
   }
   if (with_ms) {
@@ -524,16 +540,29 @@ int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const doubl
     mark(1, 1);
     convolve(d, s, d->grid, d->grid, mark);
     mark(7, 0);
-    if (d->ic_seg) {
-      const IcPlan& pl = d->icp;
-      const int64_t nwg = (int64_t)pl.nsx * g.nbox[1] * g.nbox[2];
-      hipLaunchKernelGGL(k_interp_seg, dim3((unsigned)nwg), dim3(T), (size_t)pl.lds_bytes, s, g,
-                         pl, d->grid, d->pos4, d->box_start, d->prp, d->pv, d->q, d->uz, d->u);
-    } else {
-      const int64_t nwg = (d->n_occ + kIcGroups - 1) / kIcGroups;
-      hipLaunchKernelGGL(k_interp_corr, dim3((unsigned)std::max<int64_t>(nwg, 1)), dim3(T), 0, s,
-                         g, d->n_occ, d->occ, d->grid, d->pos4, d->box_start, d->prp, d->pv,
-                         d->q, d->uz, d->u);
+    {
+      const IcPlan& pl = d->ic_seg ? d->icp : d->icp_small;
+      const int64_t nwg = (int64_t)pl.nsx * g.nbox[1] * pl.nsz;
+      const dim3 grid((unsigned)nwg), blk(T);
+      const size_t lds = (size_t)pl.lds_bytes;
+      switch (g.rb) {
+        case 0:
+          hipLaunchKernelGGL(k_interp_tile<1>, grid, blk, lds, s, g, pl, d->grid, d->pos4,
+                             d->box_start, d->prp, d->pv, d->q, d->uz, d->u);
+          break;
+        case 1:
+          hipLaunchKernelGGL(k_interp_tile<3>, grid, blk, lds, s, g, pl, d->grid, d->pos4,
+                             d->box_start, d->prp, d->pv, d->q, d->uz, d->u);
+          break;
+        case 2:
+          hipLaunchKernelGGL(k_interp_tile<5>, grid, blk, lds, s, g, pl, d->grid, d->pos4,
+                             d->box_start, d->prp, d->pv, d->q, d->uz, d->u);
+          break;
+        default:
+          hipLaunchKernelGGL(k_interp_tile<7>, grid, blk, lds, s, g, pl, d->grid, d->pos4,
+                             d->box_start, d->prp, d->pv, d->q, d->uz, d->u);
+          break;
+      }
     }
     mark(7, 1);
   }
@@ -544,8 +573,18 @@ int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const doubl
     hz = (float)happ[2];
   }
   mark(8, 0);
-  hipLaunchKernelGGL(k_grad, dim3((unsigned)((n * 16 + T - 1) / T)), dim3(T), 0, s, n, d->lrp,
-                     d->lcol, d->lgl, m, d->u, h, hx, hy, hz, with_ex, with_ms);
+  {
+    const dim3 grid((unsigned)((n * d->lanes + T - 1) / T));
+    if (d->lanes == 4)
+      hipLaunchKernelGGL(k_grad<4>, grid, dim3(T), 0, s, n, d->lrp, d->lcol, d->lgl, m, d->u, h,
+                         hx, hy, hz, with_ex, with_ms);
+    else if (d->lanes == 8)
+      hipLaunchKernelGGL(k_grad<8>, grid, dim3(T), 0, s, n, d->lrp, d->lcol, d->lgl, m, d->u, h,
+                         hx, hy, hz, with_ex, with_ms);
+    else
+      hipLaunchKernelGGL(k_grad<16>, grid, dim3(T), 0, s, n, d->lrp, d->lcol, d->lgl, m, d->u,
+                         h, hx, hy, hz, with_ex, with_ms);
+  }
   mark(8, 1);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_err(c, e, "kernel launch");
@@ -627,8 +666,12 @@ int pmfem_set_variant(pmfem_ctx* c, const char* stage, int32_t variant) {
   if (std::strcmp(stage, "anterp") == 0) k = 0;
   if (std::strcmp(stage, "interp") == 0) k = 1;
   if (std::strcmp(stage, "fft") == 0) k = 2;
+  if (std::strcmp(stage, "spmv") == 0) k = 3;
   if (k < 0) return set_err(c, PMFEM_EINVAL, "unknown stage");
-  if (variant < 0 || variant > 2) return set_err(c, PMFEM_EINVAL, "variant must be 0, 1 or 2");
+  if (k < 3 && (variant < 0 || variant > 2))
+    return set_err(c, PMFEM_EINVAL, "variant must be 0, 1 or 2");
+  if (k == 3 && variant != 0 && variant != 4 && variant != 8 && variant != 16)
+    return set_err(c, PMFEM_EINVAL, "spmv lanes must be 0, 4, 8 or 16");
   const int old = c->variant[k];
   c->variant[k] = variant;
   if (c->dev) {

@@ -70,7 +70,7 @@ struct pmfem_ctx {
   int32_t grid[3] = {0, 0, 0};
   int32_t order_p = 3, near_boxes = 2, precision = 0;
   double z0_radius = 1.0;
-  int32_t variant[3] = {0, 0, 0};  // anterp, interp, fft kernel forms (0 = automatic)
+  int32_t variant[4] = {0, 0, 0, 0};  // anterp, interp, fft forms, spmv lanes (0 = automatic)
   bool have_mesh = false, have_mat = false, have_aim = false;
   bool built = false;
   pmfem::HostOps ops;

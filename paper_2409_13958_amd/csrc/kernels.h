@@ -20,28 +20,19 @@ struct GridParams {
 constexpr int kAntTX = 8, kAntTY = 8, kAntTZ = 4;
 constexpr int kAntCap = 2560;
 constexpr int kAntHalo = (kAntTX + 6) * (kAntTY + 6) * (kAntTZ + 6) + 1;
-// interpolation/precorrection: groups of 16 lanes, one observer box each;
-// per-group staged source charges and window table
-constexpr int kIcGroup = 16;
-constexpr int kIcGroups = 16;          // per 256-thread workgroup
-constexpr int kIcGQ = 512;             // staged charges per group
-constexpr int kIcPairs = 49;           // (2 r_b + 1)^2 for r_b <= 3
-constexpr int kIcSeg = 2 * kIcPairs;   // a window splits in two at a periodic wrap
 
-// interpolation/precorrection over x-segments of box rows: one workgroup
-// per segment of `xs` boxes of one (y, z) box row. Sizes and LDS layout
+// interpolation/precorrection by tiles of observer boxes: one workgroup per
+// xs boxes along x times tz box rows along z at one y. Sizes and LDS layout
 // (byte offsets into the dynamic LDS block) are chosen on the host from the
 // box table so that every staged array fits.
 struct IcPlan {
-  int xs;    // boxes per segment along x
-  int nsx;   // segments per box row
-  int np;    // source box rows (2 r_b + 1)^2
-  int sb;    // staged boxes per source row: xs + 2 r_b
-  int qcap;  // staged source charges
-  int ux;    // staged potential points per stencil line: xs + p
-  int scap;  // column buffer per 16-lane group
-  int rcap;  // observer rows per segment
-  int o_q, o_u, o_col, o_meta, o_off, o_row;  // LDS byte offsets
+  int xs, tz;    // observer boxes per tile along x and z
+  int nsx, nsz;  // tiles along x and z
+  int sbx, szr;  // staged box columns (xs + 2 r_b) and z rows (tz + 2 r_b)
+  int qcap;      // staged source charges
+  int rcap;      // observer rows per tile
+  int ux, uzl;   // staged potential: points per line (xs + p), z-lines (tz + p)
+  int o_q, o_pos, o_col0, o_u, o_rtab, o_prp, o_seg;  // LDS byte offsets
   int lds_bytes;
 };
 
@@ -57,10 +48,9 @@ struct AntPlan {
   int lds_bytes;
 };
 
-__global__ void k_local(int64_t n, const float* m, const int32_t* rp, const int32_t* col,
-                        const float* dx, const float* dy, const float* dz, const int32_t* zrp,
-                        const int32_t* zcol, const float* zx, const float* zy, const float* zz,
-                        float* q, float* uz);
+template <int G>
+__global__ void k_local(int64_t n, const float* m, const int32_t* rp, const int4* drec,
+                        const int32_t* zrp, const int4* zrec, float* q, float* uz);
 __global__ void k_anterp(GridParams g, const float* q, const float4* pos4,
                          const int32_t* box_start, const int2* brx, const int2* bry,
                          const int2* brz, float* Q);
@@ -79,12 +69,12 @@ __global__ void k_fft_z_mul(GridParams g, float2* spec, const float* khat, const
                             int B);
 __global__ void k_c2r_x(GridParams g, const float2* spec, float* U, const float2* twx,
                         int lines_per_block);
-__global__ void k_interp_corr(GridParams g, int n_occ, const int32_t* occ, const float* U,
-                              const float4* pos4, const int32_t* box_start, const int32_t* prp,
-                              const float* pval, const float* q, const float* uz, float* u);
-__global__ void k_interp_seg(GridParams g, IcPlan pl, const float* U, const float4* pos4,
-                             const int32_t* box_start, const int32_t* prp, const float* pval,
-                             const float* q, const float* uz, float* u);
+
+template <int WT>
+__global__ void k_interp_tile(GridParams g, IcPlan pl, const float* U, const float4* pos4,
+                              const int32_t* box_start, const int32_t* prp, const float* pval,
+                              const float* q, const float* uz, float* u);
+template <int G>
 __global__ void k_grad(int64_t n, const int32_t* rp, const int32_t* col, const float4* gl,
                        const float* m, const float* u, float* h, float hax, float hay, float haz,
                        int with_ex, int with_ms);

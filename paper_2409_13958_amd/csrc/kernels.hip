@@ -83,6 +83,44 @@ __device__ __forceinline__ int row_cum(const int32_t* box_start, int64_t srow, i
   return box_start[srow + min(max(x, 0), nbx)];
 }
 
+// Block-strided copy loop with K loads in flight per thread: load(i) for K
+// indices first, then store(i, value) for the same K.
+template <int K, class Load, class Store>
+__device__ __forceinline__ void batched(int n, Load&& load, Store&& store) {
+  for (int i0 = threadIdx.x; i0 < n; i0 += K * blockDim.x) {
+    decltype(load(0)) v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = i0 + k * blockDim.x;
+      if (i < n) v[k] = load(i);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = i0 + k * blockDim.x;
+      if (i < n) store(i, v[k]);
+    }
+  }
+}
+
+// node index of staged element e: rows [base[j], base[j+1]) hold the nodes
+// of box row j from cumulative index c0[j] on (wrapping inside the row on a
+// periodic x axis, where the row has tot[j] nodes starting at b0[j])
+__device__ __forceinline__ int staged_node(int e, int nrow, const int* base, const int* c0,
+                                           const int* b0, const int* tot, int per, int& row) {
+  int lo = 0, hi = nrow;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (base[mid] <= e) lo = mid;
+    else hi = mid;
+  }
+  row = lo;
+  const int c = c0[lo] + (e - base[lo]);
+  if (!per) return c;
+  int rel = (c - b0[lo]) % tot[lo];
+  if (rel < 0) rel += tot[lo];
+  return b0[lo] + rel;
+}
+
 template <int W>
 __device__ __forceinline__ float group_sum(float v) {
   // butterfly sum over groups of W consecutive lanes (W divides 64)
@@ -92,38 +130,54 @@ __device__ __forceinline__ float group_sum(float v) {
 }
 
 // ---------------------------------------------------------------------------
-// charges and element-exact correction: 16 lanes per row
-//   q_n   = sum_k D_nk . m_k          (local pattern, D stored as three arrays)
+// charges and element-exact correction: G lanes per row
+//   q_n   = sum_k D_nk . m_k          (local pattern)
 //   u_Z,n = sum_j Z0_nj . m_j          (element-correction pattern)
+// Each entry is one 16-byte record {column, x, y, z} (one vector load).
 
-__global__ void __launch_bounds__(256) k_local(
-    int64_t n, const float* __restrict__ m, const int32_t* __restrict__ rp,
-    const int32_t* __restrict__ col, const float* __restrict__ dx, const float* __restrict__ dy,
-    const float* __restrict__ dz, const int32_t* __restrict__ zrp,
-    const int32_t* __restrict__ zcol, const float* __restrict__ zx,
-    const float* __restrict__ zy, const float* __restrict__ zz, float* __restrict__ q,
-    float* __restrict__ uz) {
-  int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
-  int lane = threadIdx.x & 15;
-  if (row >= n) return;
+template <int G>
+__global__ void __launch_bounds__(256) k_local(int64_t n, const float* __restrict__ m,
+                                               const int32_t* __restrict__ rp,
+                                               const int4* __restrict__ drec,
+                                               const int32_t* __restrict__ zrp,
+                                               const int4* __restrict__ zrec,
+                                               float* __restrict__ q, float* __restrict__ uz) {
+  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int lane = threadIdx.x & (G - 1);
+  if (row >= n) return;  // whole groups leave together
   float qq = 0.f, uu = 0.f;
   const int e0 = rp[row], e1 = rp[row + 1];
   const int z0 = zrp[row], z1 = zrp[row + 1];
-  for (int e = e0 + lane; e < e1; e += 16) {
-    const int64_t k = col[e];
-    qq += dx[e] * m[3 * k] + dy[e] * m[3 * k + 1] + dz[e] * m[3 * k + 2];
+#pragma unroll 2
+  for (int e = e0 + lane; e < e1; e += G) {
+    const int4 r = drec[e];
+    const float* mk = m + 3 * (int64_t)r.x;
+    qq = fmaf(__int_as_float(r.y), mk[0], qq);
+    qq = fmaf(__int_as_float(r.z), mk[1], qq);
+    qq = fmaf(__int_as_float(r.w), mk[2], qq);
   }
-  for (int e = z0 + lane; e < z1; e += 16) {
-    const int64_t k = zcol[e];
-    uu += zx[e] * m[3 * k] + zy[e] * m[3 * k + 1] + zz[e] * m[3 * k + 2];
+#pragma unroll 2
+  for (int e = z0 + lane; e < z1; e += G) {
+    const int4 r = zrec[e];
+    const float* mk = m + 3 * (int64_t)r.x;
+    uu = fmaf(__int_as_float(r.y), mk[0], uu);
+    uu = fmaf(__int_as_float(r.z), mk[1], uu);
+    uu = fmaf(__int_as_float(r.w), mk[2], uu);
   }
-  qq = group_sum<16>(qq);
-  uu = group_sum<16>(uu);
+  qq = group_sum<G>(qq);
+  uu = group_sum<G>(uu);
   if (lane == 0) {
     q[row] = qq;
     uz[row] = uu;
   }
 }
+
+template __global__ void k_local<4>(int64_t, const float*, const int32_t*, const int4*,
+                                    const int32_t*, const int4*, float*, float*);
+template __global__ void k_local<8>(int64_t, const float*, const int32_t*, const int4*,
+                                    const int32_t*, const int4*, float*, float*);
+template __global__ void k_local<16>(int64_t, const float*, const int32_t*, const int4*,
+                                     const int32_t*, const int4*, float*, float*);
 
 // ---------------------------------------------------------------------------
 // anterpolation: one workgroup per tile of kAntTX x kAntTY x kAntTZ grid
@@ -354,28 +408,37 @@ __global__ void __launch_bounds__(256) k_anterp_line(
     if (tid == nrow - 1) s_base[nrow] = x;
   }
   __syncthreads();
-  // 2. stage the nodes with their y/z weights at this line
+  // 2. stage the nodes with their y/z weights at this line; K elements per
+  // thread per pass so that K independent loads are in flight
   const int total = min(s_base[nrow], pl.ncap);
-  for (int e = tid; e < total; e += blockDim.x) {
-    int lo = 0, hi = nrow;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (s_base[mid] <= e) lo = mid;
-      else hi = mid;
+  constexpr int K = 4;
+  for (int e0 = tid; e0 < total; e0 += K * blockDim.x) {
+    int gi[K], row[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int e = e0 + k * blockDim.x;
+      gi[k] = 0;
+      row[k] = 0;
+      if (e < total) gi[k] = staged_node(e, nrow, s_base, s_c0, s_b0, s_tot, g.per[0], row[k]);
     }
-    const int c = s_c0[lo] + (e - s_base[lo]);
-    int gi = c;
-    if (g.per[0]) {
-      int rel = (c - s_b0[lo]) % s_tot[lo];
-      if (rel < 0) rel += s_tot[lo];
-      gi = s_b0[lo] + rel;
+    float4 nd[K];
+    float qq[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (e0 + k * blockDim.x < total) {
+        nd[k] = pos4[gi[k]];
+        qq[k] = q[gi[k]];
+      }
     }
-    const float4 nd = pos4[gi];
-    const float qq = q[gi];
-    const uint32_t packed = __float_as_uint(nd.w);
-    s_x[e] = nd.x;
-    s_st[e] = (uint16_t)st_of(packed, 0);
-    s_c[e] = qq * basis(s_ay[lo], nd.y, p) * basis(s_az[lo], nd.z, p);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int e = e0 + k * blockDim.x;
+      if (e < total) {
+        s_x[e] = nd[k].x;
+        s_st[e] = (uint16_t)st_of(__float_as_uint(nd[k].w), 0);
+        s_c[e] = qq[k] * basis(s_ay[row[k]], nd[k].y, p) * basis(s_az[row[k]], nd[k].z, p);
+      }
+    }
   }
   __syncthreads();
   if (tid >= xa) return;
@@ -389,6 +452,7 @@ __global__ void __launch_bounds__(256) k_anterp_line(
     const int* off = s_off + j * sb1;
     const int nb = s_base[j];
     const int n1 = nb + off[k0 + kc];
+#pragma unroll 4
     for (int nn = nb + off[k0]; nn < n1; ++nn) {
       int a = gx - (int)s_st[nn];
       if (g.per[0] && a < 0) a += g.N[0];
@@ -515,15 +579,21 @@ __global__ void __launch_bounds__(1024) k_fft_xy_fwd(GridParams g, const float* 
   for (int i = threadIdx.x; i < Mx / 2; i += blockDim.x) tx[i] = twx[i];
   for (int i = threadIdx.x; i < My / 2; i += blockDim.x) ty[i] = twy[i];
   const float* Qz = Q + (int64_t)z * Ny * Nx;
-  for (int idx = threadIdx.x; idx < pairs * Mx; idx += blockDim.x) {
-    const int li = idx / Mx, x = idx - li * Mx, y = 2 * li;
-    float re = 0.f, im = 0.f;
-    if (x < Nx) {
-      re = Qz[(int64_t)y * Nx + x];
-      if (y + 1 < Ny) im = Qz[(int64_t)(y + 1) * Nx + x];
-    }
-    A[li * Mx + bitrev(x, lx)] = make_float2(re, im);
-  }
+  batched<8>(
+      pairs * Mx,
+      [&](int idx) {
+        const int li = idx / Mx, x = idx - li * Mx, y = 2 * li;
+        float2 v = make_float2(0.f, 0.f);
+        if (x < Nx) {
+          v.x = Qz[(int64_t)y * Nx + x];
+          if (y + 1 < Ny) v.y = Qz[(int64_t)(y + 1) * Nx + x];
+        }
+        return v;
+      },
+      [&](int idx, float2 v) {
+        const int li = idx / Mx, x = idx - li * Mx;
+        A[li * Mx + bitrev(x, lx)] = v;
+      });
   // rows Ny..My-1 of the columns are the zero padding
   for (int idx = threadIdx.x; idx < Hx * (My - 2 * pairs); idx += blockDim.x) {
     const int k = idx % Hx, y = 2 * pairs + idx / Hx;
@@ -567,10 +637,12 @@ __global__ void __launch_bounds__(1024) k_fft_yx_inv(GridParams g, const float2*
   for (int i = threadIdx.x; i < Mx / 2; i += blockDim.x) tx[i] = twx[i];
   for (int i = threadIdx.x; i < My / 2; i += blockDim.x) ty[i] = twy[i];
   const float2* Sz = spec + (int64_t)z * My * Hx;
-  for (int idx = threadIdx.x; idx < My * Hx; idx += blockDim.x) {
-    const int ky = idx / Hx, k = idx - ky * Hx;
-    C[k * cs + bitrev(ky, ly)] = Sz[idx];
-  }
+  batched<8>(
+      My * Hx, [&](int idx) { return Sz[idx]; },
+      [&](int idx, float2 v) {
+        const int ky = idx / Hx, k = idx - ky * Hx;
+        C[k * cs + bitrev(ky, ly)] = v;
+      });
   __syncthreads();
   lds_fft_s(C, My, ly, Hx, cs, ty, -1.0f);
   for (int idx = threadIdx.x; idx < pairs * Mx; idx += blockDim.x) {
@@ -638,21 +710,30 @@ __global__ void __launch_bounds__(256) k_fft_z_mul(GridParams g, float2* __restr
   for (int i = threadIdx.x; i < Mz / 2; i += blockDim.x) tw[i] = twz[i];
   const int64_t c0 = (int64_t)blockIdx.x * B;
   const int nb = (int)((plane - c0) < B ? (plane - c0) : B);
-  for (int idx = threadIdx.x; idx < nb * Mz; idx += blockDim.x) {
-    int z = idx / nb, li = idx - z * nb;
-    float2 v = make_float2(0.f, 0.f);
-    if (z < g.N[2]) v = spec[(int64_t)z * plane + c0 + li];
-    buf[li * Mz + bitrev(z, logM)] = v;
-  }
+  batched<8>(
+      nb * Mz,
+      [&](int idx) {
+        const int z = idx / nb, li = idx - z * nb;
+        return z < g.N[2] ? spec[(int64_t)z * plane + c0 + li] : make_float2(0.f, 0.f);
+      },
+      [&](int idx, float2 v) {
+        const int z = idx / nb, li = idx - z * nb;
+        buf[li * Mz + bitrev(z, logM)] = v;
+      });
   __syncthreads();
   lds_fft(buf, Mz, logM, nb, tw, 1.0f);
   // multiply and scatter back in bit-reversed order for the inverse
-  for (int idx = threadIdx.x; idx < nb * Mz; idx += blockDim.x) {
-    int kz = idx / nb, li = idx - kz * nb;
-    float kk = khat[(int64_t)kz * plane + c0 + li];
-    float2 v = buf[li * Mz + kz];
-    buf[li * Mz + kz] = make_float2(v.x * kk, v.y * kk);  // same element, same thread
-  }
+  batched<8>(
+      nb * Mz,
+      [&](int idx) {
+        const int kz = idx / nb, li = idx - kz * nb;
+        return khat[(int64_t)kz * plane + c0 + li];
+      },
+      [&](int idx, float kk) {
+        const int kz = idx / nb, li = idx - kz * nb;
+        const float2 v = buf[li * Mz + kz];
+        buf[li * Mz + kz] = make_float2(v.x * kk, v.y * kk);  // same element, same thread
+      });
   __syncthreads();
   // bit-reverse permutation in place
   for (int idx = threadIdx.x; idx < nb * Mz; idx += blockDim.x) {
@@ -713,410 +794,320 @@ __global__ void __launch_bounds__(256) k_c2r_x(GridParams g, const float2* __res
 }
 
 // ---------------------------------------------------------------------------
-// interpolation + precorrection. All rows of one observer box have the same
-// near boxes, hence the same precorrection columns: for each of the
-// (2 r_b + 1)^2 (dy, dz) pairs, the nodes of the 2 r_b + 1 consecutive boxes
-// along x (a run that splits in two where a periodic x axis wraps), in box
-// order. The matrix therefore stores values only; the columns are rebuilt
-// from the box table. Each group of 16 lanes takes one occupied observer
-// box: it gathers the box's source charges into its own LDS slice in column
-// order, prefetches the first row's matrix values, then for every row of
-// the box forms W U (64 stencil values of the box, weights from the row's
-// local coordinates) plus P q, reduced in a fixed order.
+// interpolation + precorrection (steps 3 and 4), tile form. A workgroup
+// takes the observer boxes x in [x0, x0 + xs), y = by, z in [z0, z0 + tz).
+// Every source box their near regions touch lies in the staged block
+//   x in [x0 - r_b, x0 + xs + r_b), y in [by - r_b, by + r_b],
+//   z in [z0 - r_b, z0 + tz + r_b)
+// whose source charges are copied once into LDS column-major: x box column
+// outermost, then z, then y, then node order. The precorrection values of
+// every row are stored in the matching order (x offset, then z, then y), so
+// the near columns of a row are W contiguous LDS runs, one per x offset:
+// rows z = bz - r_b .. bz + r_b of its column. The (p + 1) y-lines of U for
+// the tile's z range are staged as well. Each group of G lanes then takes
+// one observer row at a time: u_n = W_n U + sum over the runs of P q + u_Z.
 
-template <int W>
-__device__ __forceinline__ int group_excl_scan(int v, int lane, int& total) {
-  int x = v;
-#pragma unroll
-  for (int d = 1; d < W; d <<= 1) {
-    const int y = __shfl_up(x, d, W);
-    if (lane >= d) x += y;
-  }
-  total = __shfl(x, W - 1, W);
-  return x - v;
-}
+constexpr int kIcLanes = 8;
 
-struct Window {
-  int sA, nA, sB, nB;  // node runs [sA, sA + nA) then [sB, sB + nB)
-};
-
-// source nodes of pair i (dy, dz) for observer box (bx, by, bz)
-__device__ __forceinline__ Window pair_window(const GridParams& g, const int32_t* box_start,
-                                              int i, int bx, int by, int bz) {
-  Window w{0, 0, 0, 0};
-  const int W = 2 * g.rb + 1;
-  int y = by + i % W - g.rb, z = bz + i / W - g.rb;
-  if (g.per[1]) {
-    if (y < 0) y += g.nbox[1];
-    if (y >= g.nbox[1]) y -= g.nbox[1];
-  } else if (y < 0 || y >= g.nbox[1]) {
-    return w;
-  }
-  if (g.per[2]) {
-    if (z < 0) z += g.nbox[2];
-    if (z >= g.nbox[2]) z -= g.nbox[2];
-  } else if (z < 0 || z >= g.nbox[2]) {
-    return w;
-  }
-  const int64_t row = ((int64_t)z * g.nbox[1] + y) * g.nbox[0];
-  const int nbx = g.nbox[0];
-  int lo = bx - g.rb, hi = bx + g.rb;
-  int a0, a1, b0 = 0, b1 = -1;
-  if (g.per[0]) {
-    if (lo < 0) {
-      a0 = lo + nbx; a1 = nbx - 1; b0 = 0; b1 = hi;
-    } else if (hi >= nbx) {
-      a0 = lo; a1 = nbx - 1; b0 = 0; b1 = hi - nbx;
-    } else {
-      a0 = lo; a1 = hi;
-    }
-  } else {
-    a0 = max(lo, 0);
-    a1 = min(hi, nbx - 1);
-  }
-  w.sA = box_start[row + a0];
-  w.nA = box_start[row + a1 + 1] - w.sA;
-  if (b1 >= b0) {
-    w.sB = box_start[row + b0];
-    w.nB = box_start[row + b1 + 1] - w.sB;
-  }
-  return w;
-}
-
-__global__ void __launch_bounds__(256) k_interp_corr(
-    GridParams g, int n_occ, const int32_t* __restrict__ occ, const float* __restrict__ U,
-    const float4* __restrict__ pos4, const int32_t* __restrict__ box_start,
-    const int32_t* __restrict__ prp, const float* __restrict__ pval,
-    const float* __restrict__ q, const float* __restrict__ uz, float* __restrict__ u) {
-  constexpr int G = kIcGroup;
-  constexpr int KP = 16;  // prefetched matrix values per lane (rows up to 256 entries)
-  __shared__ float s_qg[kIcGroups][kIcGQ];
-  const int lane = threadIdx.x & (G - 1);
-  const int grp = threadIdx.x / G;
-  const int gid = blockIdx.x * kIcGroups + grp;
-  const bool live = gid < n_occ;
-  const int B = live ? occ[gid] : 0;
-  const int bx = B % g.nbox[0], by = (B / g.nbox[0]) % g.nbox[1], bz = B / (g.nbox[0] * g.nbox[1]);
-  const int r0 = live ? box_start[B] : 0, r1 = live ? box_start[B + 1] : 0;
-  // prefetch the first row's matrix values
-  const int pr0 = live ? prp[r0] : 0;
-  const int rl0 = live ? prp[r0 + 1] - pr0 : 0;
-  float pv[KP];
-#pragma unroll
-  for (int k = 0; k < KP; ++k) {
-    const int j = lane + G * k;
-    pv[k] = j < rl0 ? pval[pr0 + j] : 0.f;
-  }
-  // gather the source charges of the box's windows in column order
-  const int W = 2 * g.rb + 1, npair = W * W;
-  int S = 0;
-  for (int t = 0; t * G < npair; ++t) {
-    const int i = t * G + lane;
-    Window w{0, 0, 0, 0};
-    if (live && i < npair) w = pair_window(g, box_start, i, bx, by, bz);
-    int tot;
-    const int off = S + group_excl_scan<G>(w.nA + w.nB, lane, tot);
-    S += tot;
-    if (off + w.nA + w.nB <= kIcGQ) {
-      for (int c = 0; c < w.nA; ++c) s_qg[grp][off + c] = q[w.sA + c];
-      for (int c = 0; c < w.nB; ++c) s_qg[grp][off + w.nA + c] = q[w.sB + c];
-    }
-  }
-  const bool staged = S <= kIcGQ;
-  wave_lds_sync();
-  // stencil of the box: lane holds the 4 values (ax, ay) = (lane % 4, lane / 4), az = 0..3
-  const int shift = (g.p - 1) / 2;
-  const bool cubic = g.p == 3;
-  int sta[3];
-  const int bxyz[3] = {bx, by, bz};
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    int st = bxyz[a] - shift;
-    if (g.per[a]) {
-      if (st < 0) st += g.N[a];
-    } else {
-      st = min(max(st, 0), g.N[a] - g.p - 1);
-    }
-    sta[a] = st;
-  }
-  const int lax = lane & 3, lay = lane >> 2;
-  float uv[4] = {0.f, 0.f, 0.f, 0.f};
-  if (cubic && live) {
-    int gx = sta[0] + lax, gy = sta[1] + lay;
-    if (gx >= g.N[0]) gx -= g.N[0];
-    if (gy >= g.N[1]) gy -= g.N[1];
-#pragma unroll
-    for (int az = 0; az < 4; ++az) {
-      int gz = sta[2] + az;
-      if (gz >= g.N[2]) gz -= g.N[2];
-      uv[az] = U[((int64_t)gz * g.N[1] + gy) * g.N[0] + gx];
-    }
-  }
-  const Cubic cx = cubic_basis(lax), cy = cubic_basis(lay);
-  const Cubic cz0 = cubic_basis(0), cz1 = cubic_basis(1), cz2 = cubic_basis(2), cz3 = cubic_basis(3);
-  // rows: the wave runs as many rounds as its largest box has rows
-  int nr = r1 - r0;
-  int maxr = nr;
-#pragma unroll
-  for (int o = 32; o >= G; o >>= 1) maxr = max(maxr, __shfl_xor(maxr, o, 64));
-  for (int rr = 0; rr < maxr; ++rr) {
-    const bool act = rr < nr;
-    const int r = r0 + rr;
-    float acc = 0.f;
-    if (act) {
-      const int pr = rr == 0 ? pr0 : prp[r];
-      // the row length equals S by construction; the min keeps every read in bounds
-      const int rl = min(S, rr == 0 ? rl0 : prp[r + 1] - pr);
-      if (staged) {
-        if (rr == 0) {
-#pragma unroll
-          for (int k = 0; k < KP; ++k) {
-            const int j = lane + G * k;
-            if (j < rl) acc = fmaf(pv[k], s_qg[grp][j], acc);
-          }
-          for (int j = lane + G * KP; j < rl; j += G) acc = fmaf(pval[pr + j], s_qg[grp][j], acc);
-        } else {
-          for (int j = lane; j < rl; j += G) acc = fmaf(pval[pr + j], s_qg[grp][j], acc);
-        }
-      } else {
-        // very large rows: walk the windows in global memory
-        for (int j = lane; j < rl; j += G) {
-          int loc = j;
-          float qj = 0.f;
-          for (int i = 0; i < npair; ++i) {
-            const Window w = pair_window(g, box_start, i, bx, by, bz);
-            if (loc < w.nA) { qj = q[w.sA + loc]; break; }
-            loc -= w.nA;
-            if (loc < w.nB) { qj = q[w.sB + loc]; break; }
-            loc -= w.nB;
-          }
-          acc = fmaf(pval[pr + j], qj, acc);
-        }
-      }
-      const float4 xi = pos4[r];
-      if (cubic) {
-        const float wxy = cubic_eval(cx, xi.x) * cubic_eval(cy, xi.y);
-        acc = fmaf(wxy * cubic_eval(cz0, xi.z), uv[0], acc);
-        acc = fmaf(wxy * cubic_eval(cz1, xi.z), uv[1], acc);
-        acc = fmaf(wxy * cubic_eval(cz2, xi.z), uv[2], acc);
-        acc = fmaf(wxy * cubic_eval(cz3, xi.z), uv[3], acc);
-      } else {
-        const int p1 = g.p + 1, nst = p1 * p1 * p1;
-        for (int l = lane; l < nst; l += G) {
-          const int ax = l % p1, ay = (l / p1) % p1, az = l / (p1 * p1);
-          int gx = sta[0] + ax, gy = sta[1] + ay, gz = sta[2] + az;
-          if (gx >= g.N[0]) gx -= g.N[0];
-          if (gy >= g.N[1]) gy -= g.N[1];
-          if (gz >= g.N[2]) gz -= g.N[2];
-          acc = fmaf(lagrange(ax, xi.x, g.p) * lagrange(ay, xi.y, g.p) * lagrange(az, xi.z, g.p),
-                     U[((int64_t)gz * g.N[1] + gy) * g.N[0] + gx], acc);
-        }
-      }
-    }
-    acc = group_sum<G>(acc);
-    if (act && lane == 0) u[r] = acc + uz[r];
-  }
-}
-
-// ---------------------------------------------------------------------------
-// interpolation + precorrection, segment form. A workgroup takes `xs`
-// consecutive boxes of one (y, z) box row; their rows are contiguous. Every
-// source charge those rows need lies in the (2 r_b + 1)^2 neighbouring box
-// rows, boxes x0 - r_b .. x0 + xs + r_b - 1 (unwrapped along a periodic x),
-// so these are staged once in LDS with coalesced loads, together with the
-// (p + 1)^2 stencil lines of U the segment reads. Then each 16-lane group
-// takes one observer row at a time: it copies the row's window charges from
-// the staged rows into column order (pair-major, each x-run in unwrapped box
-// order, which is the storage order of the precorrection values), streams
-// the row's matrix values, and adds W U from the staged lines.
-
-__global__ void __launch_bounds__(256) k_interp_seg(
+template <int WT>
+__global__ void __launch_bounds__(256) k_interp_tile(
     GridParams g, IcPlan pl, const float* __restrict__ U, const float4* __restrict__ pos4,
     const int32_t* __restrict__ box_start, const int32_t* __restrict__ prp,
     const float* __restrict__ pval, const float* __restrict__ q, const float* __restrict__ uz,
     float* __restrict__ u) {
   extern __shared__ float4 smem4[];
   unsigned char* smem = reinterpret_cast<unsigned char*>(smem4);
-  float* s_q = reinterpret_cast<float*>(smem + pl.o_q);
-  float* s_U = reinterpret_cast<float*>(smem + pl.o_u);
-  int* s_base = reinterpret_cast<int*>(smem + pl.o_meta);  // np + 1 staged row starts
-  int* s_c0 = s_base + (pl.np + 1);                          // cumulative index at x0 - r_b
-  int* s_b0 = s_c0 + pl.np;                                  // first node of the row
-  int* s_tot = s_b0 + pl.np;                                 // nodes in the row
-  int* s_yz = s_tot + pl.np;                                 // row index, -1 if outside
-  uint16_t* s_off = reinterpret_cast<uint16_t*>(smem + pl.o_off);  // np x (sb + 1)
-  uint16_t* s_row = reinterpret_cast<uint16_t*>(smem + pl.o_row);  // box of each row
-  const int tid = threadIdx.x;
+  float* s_q = reinterpret_cast<float*>(smem + pl.o_q);               // staged charges
+  uint16_t* s_pos = reinterpret_cast<uint16_t*>(smem + pl.o_pos);    // [sbx][rpc + 1]
+  int* s_col0 = reinterpret_cast<int*>(smem + pl.o_col0);            // [sbx + 1]
+  float* s_U = reinterpret_cast<float*>(smem + pl.o_u);              // [uzl][p + 1][ux]
+  uint16_t* s_rtab = reinterpret_cast<uint16_t*>(smem + pl.o_rtab);  // row -> kz * xs + kx
+  int* s_prp = reinterpret_cast<int*>(smem + pl.o_prp);              // row -> matrix start
+  int* s_seg = reinterpret_cast<int*>(smem + pl.o_seg);  // [tz + 1] row prefix, [tz] first row
+  const int tid = threadIdx.x, T = blockDim.x;
   const int nbx = g.nbox[0], nby = g.nbox[1], nbz = g.nbox[2];
-  const int sx = blockIdx.x % pl.nsx, byz = blockIdx.x / pl.nsx;
-  const int by = byz % nby, bz = byz / nby;
-  const int x0 = sx * pl.xs, xs = min(pl.xs, nbx - x0);
-  const int64_t orow = ((int64_t)bz * nby + by) * nbx;
-  const int r_lo = box_start[orow + x0], r_hi = box_start[orow + x0 + xs];
-  if (r_lo == r_hi) return;  // uniform across the workgroup
-  const int rb = g.rb, W = 2 * rb + 1, np = pl.np, sb1 = pl.sb + 1, p1 = g.p + 1;
-  const int shift = (g.p - 1) / 2;
+  const int rb = g.rb, p = g.p, p1 = p + 1;
+  constexpr int W = WT;  // 2 r_b + 1
+  const int sx = blockIdx.x % pl.nsx;
+  const int rest = blockIdx.x / pl.nsx;
+  const int by = rest % nby, sz = rest / nby;
+  const int x0 = sx * pl.xs, z0 = sz * pl.tz;
+  const int xs = min(pl.xs, nbx - x0), tz = min(pl.tz, nbz - z0);
+  const int sbx = pl.sbx, szr = pl.szr, rpc1 = pl.szr * W + 1;
+  int* s_segfirst = s_seg + (pl.tz + 1);
 
-  // 1. source rows
-  if (tid < np) {
-    int y = by + tid % W - rb, z = bz + tid / W - rb;
-    bool ok = true;
-    if (g.per[1]) y = (y + nby) % nby;
-    else ok = ok && y >= 0 && y < nby;
-    if (g.per[2]) z = (z + nbz) % nbz;
-    else ok = ok && z >= 0 && z < nbz;
-    int b0 = 0, tot = 0, c0 = 0, yz = -1;
-    if (ok) {
-      yz = z * nby + y;
-      const int64_t srow = (int64_t)yz * nbx;
-      b0 = box_start[srow];
-      tot = box_start[srow + nbx] - b0;
-      c0 = row_cum(box_start, srow, nbx, g.per[0], tot, x0 - rb);
-    }
-    s_b0[tid] = b0;
-    s_tot[tid] = tot;
-    s_c0[tid] = c0;
-    s_yz[tid] = tot > 0 ? yz : -1;
-  }
-  __syncthreads();
-  // 2. per source row, staged offset of each unwrapped box x0 - r_b + k
-  for (int e = tid; e < np * sb1; e += blockDim.x) {
-    const int i = e / sb1, k = e - i * sb1;
-    int off = 0;
-    if (s_yz[i] >= 0)
-      off = row_cum(box_start, (int64_t)s_yz[i] * nbx, nbx, g.per[0], s_tot[i], x0 - rb + k) -
-            s_c0[i];
-    s_off[e] = (uint16_t)off;
-  }
-  // observer row -> box of the segment
-  for (int k = tid; k < xs; k += blockDim.x) {
-    const int a = box_start[orow + x0 + k] - r_lo, b = box_start[orow + x0 + k + 1] - r_lo;
-    for (int r = a; r < b && r < pl.rcap; ++r) s_row[r] = (uint16_t)k;
-  }
-  // stencil lines of U: (ay, az) in [0, p]^2, x from the segment's first stencil start
-  const int sty = box_stencil_start(by, g.N[1], g.p, g.per[1]);
-  const int stz = box_stencil_start(bz, g.N[2], g.p, g.per[2]);
-  const int ux0 = box_stencil_start(x0, g.N[0], g.p, g.per[0]);
-  for (int e = tid; e < p1 * p1 * pl.ux; e += blockDim.x) {
-    const int l = e / pl.ux, t = e - l * pl.ux;
-    int y = sty + l % p1, z = stz + l / p1, x = ux0 + t;
-    if (g.per[1]) y = (y + g.N[1]) % g.N[1];
-    if (g.per[2]) z = (z + g.N[2]) % g.N[2];
-    float v = 0.f;
-    if (g.per[0]) {
-      x = (x + g.N[0]) % g.N[0];
-      v = U[((int64_t)z * g.N[1] + y) * g.N[0] + x];
-    } else if (x < g.N[0]) {
-      v = U[((int64_t)z * g.N[1] + y) * g.N[0] + x];
-    }
-    s_U[e] = v;
-  }
-  __syncthreads();
-  // 3. staged row starts (one wave scans np <= 49 lengths)
+  // 0. observer rows: tz contiguous segments of the node order
   if (tid < 64) {
-    const int len = tid < np ? (int)s_off[tid * sb1 + pl.sb] : 0;
-    int x = len;
+    int cnt = 0, first = 0;
+    if (tid < tz) {
+      const int64_t orow = ((int64_t)(z0 + tid) * nby + by) * nbx;
+      first = box_start[orow + x0];
+      cnt = box_start[orow + x0 + xs] - first;
+    }
+    int x = cnt;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
       const int y = __shfl_up(x, d, 64);
       if (tid >= d) x += y;
     }
-    if (tid < np) s_base[tid] = x - len;
-    if (tid == np - 1) s_base[np] = x;
+    if (tid < tz) {
+      s_seg[tid] = x - cnt;
+      s_segfirst[tid] = first;
+    }
+    if (tid == tz - 1) s_seg[tz] = x;
   }
   __syncthreads();
-  // 4. stage the source charges (coalesced per source row)
-  const int total = min(s_base[np], pl.qcap);
-  for (int e = tid; e < total; e += blockDim.x) {
-    int lo = 0, hi = np;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (s_base[mid] <= e) lo = mid;
-      else hi = mid;
+  const int nrows = s_seg[tz];
+  if (nrows == 0) return;  // uniform across the workgroup
+
+  // 1. node counts of the staged boxes (k, zz, yy), stored at their
+  //    column-major slot; lanes run along x so the box table reads coalesce
+  const int nstaged = sbx * szr * W;
+  auto staged_box = [&](int e, int& k, int& zz, int& yy) -> int64_t {
+    k = e % sbx;
+    const int r = e / sbx;
+    yy = r % W;
+    zz = r / W;
+    int x = x0 - rb + k, y = by - rb + yy, z = z0 - rb + zz;
+    if (g.per[0]) x = x < 0 ? x + nbx : (x >= nbx ? x - nbx : x);
+    else if (x < 0 || x >= nbx) return -1;
+    if (g.per[1]) y = y < 0 ? y + nby : (y >= nby ? y - nby : y);
+    else if (y < 0 || y >= nby) return -1;
+    if (g.per[2]) z = z < 0 ? z + nbz : (z >= nbz ? z - nbz : z);
+    else if (z < 0 || z >= nbz) return -1;
+    return ((int64_t)z * nby + y) * nbx + x;
+  };
+  {
+    constexpr int K = 4;
+    for (int e0 = tid; e0 < nstaged; e0 += K * T) {
+      int c[K], slot[K];
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const int e = e0 + j * T;
+        c[j] = 0;
+        slot[j] = -1;
+        if (e < nstaged) {
+          int k, zz, yy;
+          const int64_t b = staged_box(e, k, zz, yy);
+          slot[j] = k * rpc1 + zz * W + yy;
+          if (b >= 0) c[j] = box_start[b + 1] - box_start[b];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+        if (slot[j] >= 0) s_pos[slot[j]] = (uint16_t)c[j];
     }
-    const int c = s_c0[lo] + (e - s_base[lo]);
-    int gi = c;
-    if (g.per[0]) {
-      int rel = (c - s_b0[lo]) % s_tot[lo];
-      if (rel < 0) rel += s_tot[lo];
-      gi = s_b0[lo] + rel;
+  }
+  // stencil lines of U: z-lines [stz(z0), stz(z0) + tz + p), y-lines [sty, sty + p]
+  const int shift = (p - 1) / 2;
+  const int ux0 = box_stencil_start(x0, g.N[0], p, g.per[0]);
+  const int sty = box_stencil_start(by, g.N[1], p, g.per[1]);
+  const int stz = box_stencil_start(z0, g.N[2], p, g.per[2]);
+  {
+    const int nu = pl.uzl * p1 * pl.ux;
+    batched<8>(
+        nu,
+        [&](int e) {
+          const int t = e % pl.ux, l = e / pl.ux;
+          int y = sty + l % p1, z = stz + l / p1, x = ux0 + t;
+          if (g.per[0]) x = x < 0 ? x + g.N[0] : (x >= g.N[0] ? x - g.N[0] : x);
+          if (g.per[1]) y = y < 0 ? y + g.N[1] : (y >= g.N[1] ? y - g.N[1] : y);
+          if (g.per[2]) z = z < 0 ? z + g.N[2] : (z >= g.N[2] ? z - g.N[2] : z);
+          const bool ok = x < g.N[0] && z < g.N[2];
+          return ok ? U[((int64_t)z * g.N[1] + y) * g.N[0] + x] : 0.f;
+        },
+        [&](int e, float v) { s_U[e] = v; });
+  }
+  // row table and matrix starts of the observer rows
+  for (int e = tid; e < tz * xs; e += T) {
+    const int kz = e / xs, kx = e - kz * xs;
+    const int64_t b = ((int64_t)(z0 + kz) * nby + by) * nbx + x0 + kx;
+    const int r0 = box_start[b], r1 = box_start[b + 1];
+    const int s0 = s_seg[kz] + (r0 - s_segfirst[kz]);
+    for (int r = r0; r < r1; ++r) {
+      const int sl = s0 + (r - r0);
+      if (sl < pl.rcap) {
+        s_rtab[sl] = (uint16_t)(kz * pl.xs + kx);
+        s_prp[sl] = prp[r];
+      }
     }
-    s_q[e] = q[gi];
+  }
+  __syncthreads();
+  // 2. per column: exclusive prefix over its (zz, yy) slots, column totals
+  {
+    const int wave = tid >> 6, lane = tid & 63, nw = T >> 6;
+    const int nslot = szr * W;
+    for (int k = wave; k < sbx; k += nw) {
+      int carry = 0;
+      for (int c0 = 0; c0 < nslot; c0 += 64) {
+        const int i = c0 + lane;
+        const int v = i < nslot ? (int)s_pos[k * rpc1 + i] : 0;
+        int x = v;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const int y = __shfl_up(x, d, 64);
+          if (lane >= d) x += y;
+        }
+        if (i < nslot) s_pos[k * rpc1 + i] = (uint16_t)(carry + x - v);
+        carry += __shfl(x, 63, 64);
+      }
+      if (lane == 0) {
+        s_pos[k * rpc1 + nslot] = (uint16_t)carry;
+        s_col0[k] = carry;
+      }
+    }
+  }
+  __syncthreads();
+  if (tid < 64) {  // column starts: exclusive scan of the totals (sbx <= 64 * chunks)
+    int carry = 0;
+    for (int c0 = 0; c0 < sbx; c0 += 64) {
+      const int i = c0 + tid;
+      const int v = i < sbx ? s_col0[i] : 0;
+      int x = v;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (tid >= d) x += y;
+      }
+      if (i < sbx) s_col0[i] = carry + x - v;
+      carry += __shfl(x, 63, 64);
+    }
+    if (tid == 0) s_col0[sbx] = carry;
+  }
+  __syncthreads();
+  // 3. copy the source charges into their slots (lanes along x)
+  {
+    const int total = min(s_col0[sbx], pl.qcap);
+    constexpr int K = 4;
+    for (int e0 = tid; e0 < nstaged; e0 += K * T) {
+      int n0[K], c[K], dst[K];
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const int e = e0 + j * T;
+        c[j] = 0;
+        n0[j] = 0;
+        dst[j] = 0;
+        if (e < nstaged) {
+          int k, zz, yy;
+          const int64_t b = staged_box(e, k, zz, yy);
+          if (b >= 0) {
+            const int slot = k * rpc1 + zz * W + yy;
+            dst[j] = s_col0[k] + s_pos[slot];
+            c[j] = s_pos[slot + 1] - s_pos[slot];
+            n0[j] = box_start[b];
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        // up to 4 nodes of the box in one go, the rest one by one
+        float v[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v[t] = t < c[j] ? q[n0[j] + t] : 0.f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (t < c[j] && dst[j] + t < total) s_q[dst[j] + t] = v[t];
+        for (int t = 4; t < c[j]; ++t)
+          if (dst[j] + t < total) s_q[dst[j] + t] = q[n0[j] + t];
+      }
+    }
   }
   __syncthreads();
 
-  // 5. rows: one per 16-lane group
-  constexpr int G = 16, KP = 16;
-  const int lane = tid & (G - 1), grp = tid / G, ngrp = blockDim.x / G;
-  float* col = reinterpret_cast<float*>(smem + pl.o_col) + grp * pl.scap;
-  const bool cubic = g.p == 3;
-  const Cubic cx = cubic_basis(lane & 3), cy = cubic_basis(lane >> 2);
+  // 4. rows: G lanes per row
+  constexpr int G = kIcLanes;
+  const int lane = tid & (G - 1), grp = tid / G, ngrp = T / G;
+  const int nr = min(nrows, pl.rcap);
+  const bool cubic = p == 3;
+  // lane -> stencil points (ax, ay) = (l % 4, l / 4) for l = lane, lane + G (p = 3)
+  const Cubic cxa = cubic_basis(lane & 3), cya = cubic_basis(lane >> 2);
+  const Cubic cxb = cubic_basis((lane + G) & 3), cyb = cubic_basis((lane + G) >> 2);
   const Cubic cz0 = cubic_basis(0), cz1 = cubic_basis(1), cz2 = cubic_basis(2), cz3 = cubic_basis(3);
-  for (int r = r_lo + grp; r < r_hi; r += ngrp) {
-    const int pr = prp[r];
-    const int S = prp[r + 1] - pr;
-    float pv[KP];
+  for (int sl = grp; sl < nr; sl += ngrp) {
+    const int tab = s_rtab[sl];
+    const int kz = tab / pl.xs, kx = tab - kz * pl.xs;
+    const int r = s_segfirst[kz] + (sl - s_seg[kz]);
+    // the W runs of the row, then all their matrix values in flight at once
+    constexpr int RK = WT <= 5 ? 8 : 4;  // values per lane per run held in registers
+    int qs[WT], ln[WT], po[WT];
+    int pp = s_prp[sl];
 #pragma unroll
-    for (int j = 0; j < KP; ++j) {
-      const int idx = lane + G * j;
-      pv[j] = idx < S ? pval[pr + idx] : 0.f;
+    for (int dx = 0; dx < WT; ++dx) {
+      const int k = kx + dx;
+      const int a = s_pos[k * rpc1 + kz * W], b = s_pos[k * rpc1 + (kz + W) * W];
+      qs[dx] = s_col0[k] + a;
+      ln[dx] = b - a;
+      po[dx] = pp;
+      pp += b - a;
     }
-    const float4 xi = pos4[r];
-    const int k = r - r_lo < pl.rcap ? (int)s_row[r - r_lo] : 0;
-    // window charges into column order
-    int sacc = 0;
-    for (int i0 = 0; i0 < np; i0 += G) {
-      const int i = i0 + lane;
-      int len = 0, src = 0;
-      if (i < np) {
-        const int a = s_off[i * sb1 + k], b = s_off[i * sb1 + k + W];
-        len = b - a;
-        src = s_base[i] + a;
+    float v[WT][RK];
+#pragma unroll
+    for (int dx = 0; dx < WT; ++dx)
+#pragma unroll
+      for (int t = 0; t < RK; ++t) {
+        const int c = lane + G * t;
+        v[dx][t] = c < ln[dx] ? pval[po[dx] + c] : 0.f;
       }
-      int tot;
-      const int dst = sacc + group_excl_scan<G>(len, lane, tot);
-      sacc += tot;
-      for (int c = 0; c < len; ++c)
-        if (dst + c < pl.scap) col[dst + c] = s_q[src + c];
-    }
-    wave_lds_sync();
-    const int rl = min(min(S, sacc), pl.scap);
+    const float4 xi = pos4[r];
     float acc = 0.f;
 #pragma unroll
-    for (int j = 0; j < KP; ++j) {
-      const int idx = lane + G * j;
-      if (idx < rl) acc = fmaf(pv[j], col[idx], acc);
+    for (int dx = 0; dx < WT; ++dx) {
+#pragma unroll
+      for (int t = 0; t < RK; ++t) {
+        const int c = lane + G * t;
+        if (c < ln[dx]) acc = fmaf(v[dx][t], s_q[qs[dx] + c], acc);
+      }
+      for (int c = lane + G * RK; c < ln[dx]; c += G)
+        acc = fmaf(pval[po[dx] + c], s_q[qs[dx] + c], acc);
     }
-    for (int idx = lane + G * KP; idx < rl; idx += G) acc = fmaf(pval[pr + idx], col[idx], acc);
-    // W U from the staged stencil lines
-    const int bx = x0 + k;
-    const int rel = g.per[0] ? k : box_stencil_start(bx, g.N[0], g.p, 0) - ux0;
+    // W U from the staged lines
+    const int bx = x0 + kx, bz = z0 + kz;
+    const int relx = g.per[0] ? kx : box_stencil_start(bx, g.N[0], p, 0) - ux0;
+    const int relz = g.per[2] ? kz : box_stencil_start(bz, g.N[2], p, 0) - stz;
     if (cubic) {
-      const float* su = s_U + (lane >> 2) * pl.ux + rel + (lane & 3);
-      const int zs = 4 * pl.ux;
-      const float wxy = cubic_eval(cx, xi.x) * cubic_eval(cy, xi.y);
-      acc = fmaf(wxy * cubic_eval(cz0, xi.z), su[0], acc);
-      acc = fmaf(wxy * cubic_eval(cz1, xi.z), su[zs], acc);
-      acc = fmaf(wxy * cubic_eval(cz2, xi.z), su[2 * zs], acc);
-      acc = fmaf(wxy * cubic_eval(cz3, xi.z), su[3 * zs], acc);
+      const int zs = p1 * pl.ux;
+      const float* su = s_U + (relz * p1) * pl.ux + relx;
+      const float wz0 = cubic_eval(cz0, xi.z), wz1 = cubic_eval(cz1, xi.z);
+      const float wz2 = cubic_eval(cz2, xi.z), wz3 = cubic_eval(cz3, xi.z);
+      {
+        const float* s0 = su + (lane >> 2) * pl.ux + (lane & 3);
+        const float w = cubic_eval(cxa, xi.x) * cubic_eval(cya, xi.y);
+        acc = fmaf(w, wz0 * s0[0] + wz1 * s0[zs] + wz2 * s0[2 * zs] + wz3 * s0[3 * zs], acc);
+      }
+      {
+        const int l = lane + G;
+        const float* s0 = su + (l >> 2) * pl.ux + (l & 3);
+        const float w = cubic_eval(cxb, xi.x) * cubic_eval(cyb, xi.y);
+        acc = fmaf(w, wz0 * s0[0] + wz1 * s0[zs] + wz2 * s0[2 * zs] + wz3 * s0[3 * zs], acc);
+      }
     } else {
       const int nst = p1 * p1 * p1;
       for (int l = lane; l < nst; l += G) {
         const int ax = l % p1, ay = (l / p1) % p1, az = l / (p1 * p1);
-        acc = fmaf(lagrange(ax, xi.x, g.p) * lagrange(ay, xi.y, g.p) * lagrange(az, xi.z, g.p),
-                   s_U[(az * p1 + ay) * pl.ux + rel + ax], acc);
+        acc = fmaf(lagrange(ax, xi.x, p) * lagrange(ay, xi.y, p) * lagrange(az, xi.z, p),
+                   s_U[((relz + az) * p1 + ay) * pl.ux + relx + ax], acc);
       }
     }
     acc = group_sum<G>(acc);
     if (lane == 0) u[r] = acc + uz[r];
-    wave_lds_sync();  // the column buffer is rewritten for the next row
   }
 }
 
+#define PMFEM_INTERP_TILE(WT)                                                             \
+  template __global__ void k_interp_tile<WT>(GridParams, IcPlan, const float*, const float4*,  \
+                                             const int32_t*, const int32_t*, const float*,     \
+                                             const float*, const float*, float*);
+PMFEM_INTERP_TILE(1)
+PMFEM_INTERP_TILE(3)
+PMFEM_INTERP_TILE(5)
+PMFEM_INTERP_TILE(7)
+#undef PMFEM_INTERP_TILE
+
 // ---------------------------------------------------------------------------
-// exchange + gradient + sum over the shared local pattern, 16 lanes per row:
+// exchange + gradient + sum over the shared local pattern, G lanes per row:
 //   H_n = sum_k ( L_nk m_k - G_nk u_k ) + H_applied,  gl = {Gx, Gy, Gz, L}
 
+template <int G>
 __global__ void __launch_bounds__(256) k_grad(int64_t n, const int32_t* __restrict__ rp,
                                               const int32_t* __restrict__ col,
                                               const float4* __restrict__ gl,
@@ -1124,35 +1115,47 @@ __global__ void __launch_bounds__(256) k_grad(int64_t n, const int32_t* __restri
                                               const float* __restrict__ u,
                                               float* __restrict__ h, float hax, float hay,
                                               float haz, int with_ex, int with_ms) {
-  int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
-  int lane = threadIdx.x & 15;
-  if (row >= n) return;
+  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int lane = threadIdx.x & (G - 1);
+  if (row >= n) return;  // whole groups leave together
   float hx = 0.f, hy = 0.f, hz = 0.f;
   const int e0 = rp[row], e1 = rp[row + 1];
-  for (int e = e0 + lane; e < e1; e += 16) {
+#pragma unroll 2
+  for (int e = e0 + lane; e < e1; e += G) {
     const int64_t k = col[e];
     const float4 w = gl[e];
     if (with_ex) {
-      hx += w.w * m[3 * k];
-      hy += w.w * m[3 * k + 1];
-      hz += w.w * m[3 * k + 2];
+      const float* mk = m + 3 * k;
+      hx = fmaf(w.w, mk[0], hx);
+      hy = fmaf(w.w, mk[1], hy);
+      hz = fmaf(w.w, mk[2], hz);
     }
     if (with_ms) {
       const float uk = u[k];
-      hx -= w.x * uk;
-      hy -= w.y * uk;
-      hz -= w.z * uk;
+      hx = fmaf(-w.x, uk, hx);
+      hy = fmaf(-w.y, uk, hy);
+      hz = fmaf(-w.z, uk, hz);
     }
   }
-  hx = group_sum<16>(hx);
-  hy = group_sum<16>(hy);
-  hz = group_sum<16>(hz);
+  hx = group_sum<G>(hx);
+  hy = group_sum<G>(hy);
+  hz = group_sum<G>(hz);
   if (lane == 0) {
     h[3 * row] = hx + hax;
     h[3 * row + 1] = hy + hay;
     h[3 * row + 2] = hz + haz;
   }
 }
+
+template __global__ void k_grad<4>(int64_t, const int32_t*, const int32_t*, const float4*,
+                                   const float*, const float*, float*, float, float, float, int,
+                                   int);
+template __global__ void k_grad<8>(int64_t, const int32_t*, const int32_t*, const float4*,
+                                   const float*, const float*, float*, float, float, float, int,
+                                   int);
+template __global__ void k_grad<16>(int64_t, const int32_t*, const int32_t*, const float4*,
+                                    const float*, const float*, float*, float, float, float, int,
+                                    int);
 
 // ---------------------------------------------------------------------------
 // LLG (unit-vector Landau-Lifshitz form), classic RK4 in FP64

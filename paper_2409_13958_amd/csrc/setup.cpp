@@ -663,9 +663,10 @@ int host_build(pmfem_ctx* c) {
       int tb[3][16], wr[3][16], dd[3][16], cnt[3];
       for (int a = 0; a < 3; ++a) cnt[a] = near_axis(u, a, tb[a], wr[a], dd[a]);
       int64_t out = o.p_rowptr[u];
-      for (int iz = 0; iz < cnt[2]; ++iz)
-        for (int iy = 0; iy < cnt[1]; ++iy)
-          for (int ix = 0; ix < cnt[0]; ++ix) {
+      // column order: x box offset outermost, then z, then y, then node order
+      for (int ix = 0; ix < cnt[0]; ++ix)
+        for (int iz = 0; iz < cnt[2]; ++iz)
+          for (int iy = 0; iy < cnt[1]; ++iy) {
             int64_t b = ((int64_t)tb[2][iz] * o.nbox[1] + tb[1][iy]) * o.nbox[0] + tb[0][ix];
             for (int32_t k = o.box_start[b]; k < o.box_start[b + 1]; ++k) {
               double wk[3][8];

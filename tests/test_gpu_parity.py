@@ -23,7 +23,9 @@ def rel(a, b):
 
 
 # kernel forms: staged (the default choice) and the basic forms of each stage
-FORMS = {"staged": dict(anterp=2, interp=2, fft=2), "basic": dict(anterp=1, interp=1, fft=1)}
+FORMS = {"staged": dict(anterp=2, interp=2, fft=2, spmv=8),
+         "basic": dict(anterp=1, interp=1, fft=1, spmv=16),
+         "spmv4": dict(spmv=4)}
 
 
 def lib_fields(prob, m_nodes, forms=None, **kw):

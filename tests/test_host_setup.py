@@ -205,7 +205,70 @@ def test_kernel_variant_arguments_are_checked():
     c.set_variant("anterp", 1)
     c.set_variant("interp", 2)
     c.set_variant("fft", 0)
-    for stage, v in (("anterp", 3), ("interp", -1), ("convolution", 1)):
+    c.set_variant("spmv", 8)
+    for stage, v in (("anterp", 3), ("interp", -1), ("convolution", 1), ("spmv", 2)):
         with pytest.raises(lib.PmfemError) as e:
             c.set_variant(stage, v)
         assert e.value.code == lib.Status.EINVAL
+
+
+def _tile_columns(bs, nbox, per, rb, xs, tz):
+    """Near columns of every row as the tile kernel addresses them: per tile,
+    source boxes staged column-major (x box, then z, then y), each row reading
+    one contiguous run per x offset (rows z - r_b .. z + r_b of its column)."""
+    nbx, nby, nbz = nbox
+    W = 2 * rb + 1
+    out = {}
+
+    def box(x, y, z):
+        for a, (v, n) in enumerate(((x, nbx), (y, nby), (z, nbz))):
+            if per[a]:
+                v %= n
+            elif v < 0 or v >= n:
+                return None
+            if a == 0:
+                x = v
+            elif a == 1:
+                y = v
+            else:
+                z = v
+        return (z * nby + y) * nbx + x
+
+    for z0 in range(0, nbz, tz):
+        for by in range(nby):
+            for x0 in range(0, nbx, xs):
+                cols = []  # cols[k] = list over (zz, yy) of node lists
+                for k in range(xs + 2 * rb):
+                    col = []
+                    for zz in range(tz + 2 * rb):
+                        for yy in range(W):
+                            b = box(x0 - rb + k, by - rb + yy, z0 - rb + zz)
+                            col.append([] if b is None else list(range(bs[b], bs[b + 1])))
+                    cols.append(col)
+                for kz in range(min(tz, nbz - z0)):
+                    for kx in range(min(xs, nbx - x0)):
+                        b = box(x0 + kx, by, z0 + kz)
+                        for r in range(bs[b], bs[b + 1]):
+                            seq = []
+                            for dx in range(W):
+                                for slot in cols[kx + dx][kz * W:(kz + W) * W]:
+                                    seq.extend(slot)
+                            out[r] = seq
+    return out
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (4, 2), (8, 16)])
+def test_precorrection_column_order_matches_tile_staging(pair, shape):
+    prob, ctx, orc = pair
+    info = ctx.export("grid_info")
+    N = info[0:3].astype(int)
+    per = info[-3:].astype(int)
+    rb = int(info[-4])
+    nbox = [int(N[a]) if per[a] else int(N[a]) - 1 for a in range(3)]
+    bs = ctx.export("box_start").astype(np.int64)
+    rp = ctx.export("p_rowptr").astype(np.int64)
+    col = ctx.export("p_col").astype(np.int64)
+    got = _tile_columns(bs, nbox, per, rb, *shape)
+    assert len(got) == ctx.n
+    for r in range(ctx.n):
+        assert got[r] == col[rp[r]:rp[r + 1]].tolist(), r
