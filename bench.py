@@ -62,6 +62,27 @@ def kernel_bytes(ctx, names):
                        if name.startswith(k)) for name in names}
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "composite_c3_hbm_traffic.json")
+    src = os.path.join(ROOT, "paper_2409_13958_amd", "csrc", "kernels.hip")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("kernels_hip_sha256") != h:
+        return None
+    for name, b in rec.get("bytes_per_launch", {}).items():
+        if name.split("<")[0] == kernel:
+            return float(b)
+    return None
+
+
 def cpu_baseline(prob, rows_sample=64, seed=7):
     """Time the FP64 oracle on a bounded sample of the same workload.
 
@@ -86,26 +107,34 @@ def cpu_baseline(prob, rows_sample=64, seed=7):
     P = orc._cache[("P", tuple(ring.tolist()))]
     Z = orc.z0(ring)
     A = orc.aim
-    tt = {}
-    t = time.perf_counter()
-    orc.ops.exchange(m)
-    tt["exchange"] = time.perf_counter() - t
-    t = time.perf_counter()
-    q = orc.ops.charges(m)
-    tt["charges"] = time.perf_counter() - t
-    t = time.perf_counter()
-    U = A.convolve(A.project(q))
-    tt["grid"] = time.perf_counter() - t
-    t = time.perf_counter()
-    u_ring = (A.interpolate(U, ring) + P @ q) / (4 * np.pi) + sum(Z[c] @ m[:, c] for c in range(3))
-    tt["ring"] = time.perf_counter() - t
-    u = np.zeros(orc.n)
-    u[ring] = u_ring
-    t = time.perf_counter()
-    orc.ops.gradient_field(u, rows)
-    tt["grad"] = time.perf_counter() - t
+    tt = {k: 0.0 for k in ("exchange", "charges", "grid", "ring", "grad")}
+    reps = 0
+    from threadpoolctl import threadpool_limits
+    limiter = threadpool_limits(limits=1)   # the oracle as it stands, on one core
+    # repeat the evaluation until about 10 s of CPU work have been timed
+    while reps < 200 and (reps == 0 or sum(tt.values()) < 10.0):
+        t = time.perf_counter()
+        orc.ops.exchange(m)
+        tt["exchange"] += time.perf_counter() - t
+        t = time.perf_counter()
+        q = orc.ops.charges(m)
+        tt["charges"] += time.perf_counter() - t
+        t = time.perf_counter()
+        U = A.convolve(A.project(q))
+        tt["grid"] += time.perf_counter() - t
+        t = time.perf_counter()
+        u_ring = ((A.interpolate(U, ring) + P @ q) / (4 * np.pi)
+                  + sum(Z[c] @ m[:, c] for c in range(3)))
+        tt["ring"] += time.perf_counter() - t
+        u = np.zeros(orc.n)
+        u[ring] = u_ring
+        t = time.perf_counter()
+        orc.ops.gradient_field(u, rows)
+        tt["grad"] += time.perf_counter() - t
+        reps += 1
+    limiter.restore_original_limits()
     full = (tt["exchange"] + tt["charges"] + tt["grid"] + tt["ring"] * orc.n / ring.size
-            + tt["grad"] * orc.n / rows.size)
+            + tt["grad"] * orc.n / rows.size) / reps
     return {
         "value": 1.0 / full,
         "unit": "H_eff evals/s",
@@ -114,8 +143,8 @@ def cpu_baseline(prob, rows_sample=64, seed=7):
         "sample": (f"one FP64 oracle evaluation: full-size exchange, charges and 128^3 FFT "
                    f"convolution timed once; interpolation+precorrection+element correction "
                    f"on the {ring.size}-row ring of {rows.size} sampled rows and their "
-                   f"gradient, scaled to N'={orc.n}; timed {sum(tt.values()):.1f} s "
-                   f"(setup {t_setup:.0f} s untimed)"),
+                   f"gradient, scaled to N'={orc.n}; {reps} repetitions, timed "
+                   f"{sum(tt.values()):.1f} s (setup {t_setup:.0f} s untimed)"),
     }
 
 
@@ -210,7 +239,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(dom) if args.config == "composite_c3" else None,
         },
     }
     if rank == 0 and not args.no_cpu_baseline:

@@ -161,8 +161,8 @@ int select_variants(pmfem_ctx* c) {
   return PMFEM_OK;
 }
 
-// Line plan for k_anterp_line: the longest x-segment (at most 128 points)
-// whose staged nodes fit in 64 KB of LDS. Returns false if none fits.
+// Line plan for k_anterp_line: the longest x-segment (at most 128 points,
+// a power of two) whose staged nodes fit in LDS. Returns false if none fits.
 bool plan_anterp(const HostOps& o, const std::vector<int2>& bx, const std::vector<int2>& by,
                  const std::vector<int2>& bz, AntPlan& pl) {
   const int nbx = o.nbox[0], nby = o.nbox[1], nbz = o.nbox[2], p = o.p, shift = (p - 1) / 2;
@@ -171,19 +171,10 @@ bool plan_anterp(const HostOps& o, const std::vector<int2>& bx, const std::vecto
   for (const int2& r : by) cy = std::max(cy, r.y);
   for (const int2& r : bz) cz = std::max(cz, r.y);
   const int nrow = cy * cz;
-  auto cum = [&](int64_t srow, int tot, int x) -> int64_t {
-    if (o.per[0]) {
-      int64_t wrap = 0;
-      if (x < 0) {
-        x += nbx;
-        wrap = -1;
-      } else if (x > nbx) {
-        x -= nbx;
-        wrap = 1;
-      }
-      return wrap * tot + bs[srow + x];
-    }
-    return bs[srow + std::min(std::max(x, 0), nbx)];
+  auto cnt = [&](int x, int64_t rowbase) -> int64_t {
+    if (o.per[0]) x = (x % nbx + nbx) % nbx;
+    else if (x < 0 || x >= nbx) return 0;
+    return bs[rowbase + x + 1] - bs[rowbase + x];
   };
   for (int xa = std::min(o.N[0], 128); xa >= 4; xa /= 2) {
     const int nsx = (o.N[0] + xa - 1) / xa;
@@ -195,41 +186,42 @@ bool plan_anterp(const HostOps& o, const std::vector<int2>& bx, const std::vecto
       nbss[sx] = o.per[0] ? (xe - x0 + 1) + p : bx[xe].x + bx[xe].y - bx[x0].x;
       sbx = std::max(sbx, nbss[sx]);
     }
-    int64_t ncap = 0;
+    int64_t ncap = 0, colmax = 0;
     for (int gz = 0; gz < o.N[2]; ++gz)
       for (int gy = 0; gy < o.N[1]; ++gy)
         for (int sx = 0; sx < nsx; ++sx) {
           int64_t staged = 0;
-          for (int iz = 0; iz < bz[gz].y; ++iz)
-            for (int iy = 0; iy < by[gy].y; ++iy) {
-              int b_y = by[gy].x + iy, b_z = bz[gz].x + iz;
-              if (b_y >= nby) b_y -= nby;
-              if (b_z >= nbz) b_z -= nbz;
-              const int64_t srow = ((int64_t)b_z * nby + b_y) * nbx;
-              const int tot = bs[srow + nbx] - bs[srow];
-              if (tot == 0) continue;
-              staged += cum(srow, tot, fbs[sx] + nbss[sx]) - cum(srow, tot, fbs[sx]);
-            }
+          for (int k = 0; k < nbss[sx]; ++k) {
+            int64_t col = 0;
+            for (int iz = 0; iz < bz[gz].y; ++iz)
+              for (int iy = 0; iy < by[gy].y; ++iy) {
+                int b_y = by[gy].x + iy, b_z = bz[gz].x + iz;
+                if (b_y >= nby) b_y -= nby;
+                if (b_z >= nbz) b_z -= nbz;
+                col += cnt(fbs[sx] + k, ((int64_t)b_z * nby + b_y) * nbx);
+              }
+            colmax = std::max(colmax, col);
+            staged += col;
+          }
           ncap = std::max(ncap, staged);
         }
     auto al = [](int64_t b) { return (b + 15) & ~(int64_t)15; };
     int64_t off = 0;
     pl.o_x = (int)off;
-    off += al(std::max<int64_t>(ncap, 1) * 4);
-    pl.o_c = (int)off;
-    off += al(std::max<int64_t>(ncap, 1) * 4);
+    off += al(std::max<int64_t>(ncap, 1) * 8);
+    pl.o_c = pl.o_x;
     pl.o_st = (int)off;
-    off += al(std::max<int64_t>(ncap, 1) * 2);
-    pl.o_meta = (int)off;
-    off += al((int64_t)(7 * nrow + 1) * 4);
+    off += al((int64_t)sbx * (nrow + 1) * 2);
     pl.o_off = (int)off;
-    off += al((int64_t)nrow * (sbx + 1) * 4);
-    if (off <= 65536 && nrow <= 64) {
+    off += al((int64_t)(sbx + 1) * 4);
+    pl.o_meta = (int)off;
+    off += al((int64_t)2 * nrow * 4);
+    if (off <= 65536 && nrow <= 64 && colmax < 65536) {
       pl.xa = xa;
       pl.nsx = nsx;
       pl.nrow = nrow;
       pl.sbx = sbx;
-      pl.ncap = (int)ncap;
+      pl.ncap = (int)std::max<int64_t>(ncap, 1);
       pl.lds_bytes = (int)off;
       return true;
     }
@@ -370,7 +362,7 @@ int upload_all(pmfem_ctx* c) {
 
   auto bx = box_ranges(o, 0), by = box_ranges(o, 1), bz = box_ranges(o, 2);
   d->ant_ok = plan_anterp(o, bx, by, bz, d->ap);
-  d->ant_threads = std::max(64, (d->ap.xa + 63) / 64 * 64);
+  d->ant_threads = std::max(64, std::min(128, (d->ap.xa + 63) / 64 * 64));
   if ((rc = select_variants(c))) return rc;
   if ((rc = upload(c, &d->brx, bx.data(), bx.size()))) return rc;
   if ((rc = upload(c, &d->bry, by.data(), by.size()))) return rc;

@@ -324,36 +324,31 @@ __global__ void __launch_bounds__(256) k_anterp(
 // ---------------------------------------------------------------------------
 // anterpolation by grid lines. A workgroup takes `xa` consecutive points of
 // one (y, z) grid line, one thread per point. The boxes whose stencils reach
-// the line form at most (p + 1)^2 box rows; their nodes in the x-range of
-// the segment are staged once in LDS with coalesced loads, each reduced to
-// what the line needs: xi_x, its stencil start along x, and the product
-// q L_ay(xi_y) L_az(xi_z) of its charge with its y and z weights at the
-// line. Each thread then sums, row by row and in box order (a fixed order,
-// no atomics), q L_ay L_az L_ax over the nodes of the boxes covering its
-// point.
+// the line form at most (p + 1)^2 box rows; the nodes of those rows in the
+// segment's x range are staged once in LDS, column-major (x box outermost,
+// then box row, then node order), each reduced to what the line needs: its
+// xi_x and the product c = q L_ay(xi_y) L_az(xi_z) of its charge with its y
+// and z weights at the line (a_y, a_z are fixed per box row). A point then
+// sums c L_ax(xi_x) over the p + 1 box columns covering it; a_x is fixed per
+// column, so the inner loop runs over one contiguous LDS range per column.
+// The sum order is fixed (no atomics).
 
 __device__ __forceinline__ float basis(int a, float xi, int p) {
   return p == 3 ? cubic_eval(cubic_basis(a), xi) : lagrange(a, xi, p);
 }
 
-__global__ void __launch_bounds__(256) k_anterp_line(
+__global__ void __launch_bounds__(128) k_anterp_line(
     GridParams g, AntPlan pl, const float* __restrict__ q, const float4* __restrict__ pos4,
     const int32_t* __restrict__ box_start, const int2* __restrict__ brx,
     const int2* __restrict__ bry, const int2* __restrict__ brz, float* __restrict__ Q) {
   extern __shared__ float4 smem4[];
   unsigned char* smem = reinterpret_cast<unsigned char*>(smem4);
-  float* s_x = reinterpret_cast<float*>(smem + pl.o_x);
-  float* s_c = reinterpret_cast<float*>(smem + pl.o_c);
-  uint16_t* s_st = reinterpret_cast<uint16_t*>(smem + pl.o_st);
-  int* s_base = reinterpret_cast<int*>(smem + pl.o_meta);  // nrow + 1
-  int* s_c0 = s_base + (pl.nrow + 1);
-  int* s_b0 = s_c0 + pl.nrow;
-  int* s_tot = s_b0 + pl.nrow;
-  int* s_ay = s_tot + pl.nrow;
-  int* s_az = s_ay + pl.nrow;
-  int* s_yz = s_az + pl.nrow;
-  int* s_off = reinterpret_cast<int*>(smem + pl.o_off);  // nrow x (sbx + 1)
-  const int tid = threadIdx.x;
+  float2* s_nd = reinterpret_cast<float2*>(smem + pl.o_x);          // (xi_x, c) per node
+  uint16_t* s_pos = reinterpret_cast<uint16_t*>(smem + pl.o_st);    // [sbx][nrow + 1]
+  int* s_col0 = reinterpret_cast<int*>(smem + pl.o_off);            // [sbx + 1]
+  int* s_rb = reinterpret_cast<int*>(smem + pl.o_meta);             // [nrow] row base box
+  int* s_ayz = s_rb + pl.nrow;                                      // [nrow] a_y | a_z << 8
+  const int tid = threadIdx.x, T = blockDim.x;
   const int nbx = g.nbox[0], nby = g.nbox[1], nbz = g.nbox[2];
   const int sx = blockIdx.x % pl.nsx, line = blockIdx.x / pl.nsx;
   const int gy = line % g.N[1], gz = line / g.N[1];
@@ -361,102 +356,114 @@ __global__ void __launch_bounds__(256) k_anterp_line(
   const int2 ry = bry[gy], rz = brz[gz];
   const int nrow = ry.y * rz.y;
   const int p = g.p, shift = (p - 1) / 2;
-  // first staged box (unwrapped on a periodic x) and the staged box count
   const int2 fx = brx[x0], lxr = brx[x0 + xa - 1];
-  const int fb = g.per[0] ? x0 - p + shift : fx.x;
+  const int fb = g.per[0] ? x0 - p + shift : fx.x;  // first staged box (unwrapped)
   const int nbs = g.per[0] ? xa + p : lxr.x + lxr.y - fx.x;
-  const int sb1 = pl.sbx + 1;
-  // 1. box rows: by = ry.x + iy, bz = rz.x + iz (wrapped on periodic axes)
+  const int np1 = pl.nrow + 1;
+  // box rows: by = ry.x + iy, bz = rz.x + iz (wrapped on periodic axes)
   if (tid < nrow) {
     const int iy = tid % ry.y, iz = tid / ry.y;
     int by = ry.x + iy, bz = rz.x + iz;
     if (by >= nby) by -= nby;
     if (bz >= nbz) bz -= nbz;
-    const int64_t srow = ((int64_t)bz * nby + by) * nbx;
-    const int b0 = box_start[srow], tot = box_start[srow + nbx] - b0;
-    s_b0[tid] = b0;
-    s_tot[tid] = tot;
-    s_c0[tid] = tot > 0 ? row_cum(box_start, srow, nbx, g.per[0], tot, fb) : 0;
-    s_yz[tid] = tot > 0 ? bz * nby + by : -1;
-    // stencil index of the line in this box row's stencils
     int ay = gy - box_stencil_start(by, g.N[1], p, g.per[1]);
     int az = gz - box_stencil_start(bz, g.N[2], p, g.per[2]);
     if (g.per[1]) ay = ((ay % g.N[1]) + g.N[1]) % g.N[1];
     if (g.per[2]) az = ((az % g.N[2]) + g.N[2]) % g.N[2];
-    s_ay[tid] = ay;
-    s_az[tid] = az;
+    s_rb[tid] = (bz * nby + by) * nbx;
+    s_ayz[tid] = ay | (az << 8);
   }
   __syncthreads();
-  for (int e = tid; e < nrow * sb1; e += blockDim.x) {
-    const int j = e / sb1, k = e - j * sb1;
-    int off = 0;
-    if (s_yz[j] >= 0)
-      off = row_cum(box_start, (int64_t)s_yz[j] * nbx, nbx, g.per[0], s_tot[j],
-                    fb + min(k, nbs)) - s_c0[j];
-    s_off[e] = off;
-  }
-  __syncthreads();
-  if (tid < 64) {
-    const int len = tid < nrow ? s_off[tid * sb1 + nbs] : 0;
-    int x = len;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int y = __shfl_up(x, d, 64);
-      if (tid >= d) x += y;
+  // 1. per column: node counts of its boxes, prefix over the rows
+  for (int k = tid; k < nbs; k += T) {
+    int x = fb + k;
+    if (g.per[0]) x = x < 0 ? x + nbx : (x >= nbx ? x - nbx : x);
+    int run = 0;
+    for (int j = 0; j < nrow; ++j) {
+      const int b = s_rb[j] + x;
+      s_pos[k * np1 + j] = (uint16_t)run;
+      run += box_start[b + 1] - box_start[b];
     }
-    if (tid < nrow) s_base[tid] = x - len;
-    if (tid == nrow - 1) s_base[nrow] = x;
+    s_pos[k * np1 + nrow] = (uint16_t)run;
+    s_col0[k] = run;
   }
   __syncthreads();
-  // 2. stage the nodes with their y/z weights at this line; K elements per
-  // thread per pass so that K independent loads are in flight
-  const int total = min(s_base[nrow], pl.ncap);
-  constexpr int K = 4;
-  for (int e0 = tid; e0 < total; e0 += K * blockDim.x) {
-    int gi[K], row[K];
+  if (tid < 64) {  // column starts
+    int carry = 0;
+    for (int c0 = 0; c0 < nbs; c0 += 64) {
+      const int i = c0 + tid;
+      const int v = i < nbs ? s_col0[i] : 0;
+      int x = v;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int e = e0 + k * blockDim.x;
-      gi[k] = 0;
-      row[k] = 0;
-      if (e < total) gi[k] = staged_node(e, nrow, s_base, s_c0, s_b0, s_tot, g.per[0], row[k]);
-    }
-    float4 nd[K];
-    float qq[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      if (e0 + k * blockDim.x < total) {
-        nd[k] = pos4[gi[k]];
-        qq[k] = q[gi[k]];
+      for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (tid >= d) x += y;
       }
+      if (i < nbs) s_col0[i] = carry + x - v;
+      carry += __shfl(x, 63, 64);
     }
+    if (tid == 0) s_col0[nbs] = carry;
+  }
+  __syncthreads();
+  // 2. stage the nodes with their y/z weights at this line
+  const int cap = pl.ncap;
+  for (int k = tid; k < nbs; k += T) {
+    int x = fb + k;
+    if (g.per[0]) x = x < 0 ? x + nbx : (x >= nbx ? x - nbx : x);
+    const int base = s_col0[k];
+    for (int j = 0; j < nrow; ++j) {
+      const int b = s_rb[j] + x;
+      const int n0 = box_start[b];
+      const int c = s_pos[k * np1 + j + 1] - s_pos[k * np1 + j];
+      const int dst = base + s_pos[k * np1 + j];
+      const int ayz = s_ayz[j];
+      const int ay = ayz & 255, az = ayz >> 8;
+      // up to 4 nodes of the box at once, the rest one by one
+      float4 nd[4];
+      float qq[4];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int e = e0 + k * blockDim.x;
-      if (e < total) {
-        s_x[e] = nd[k].x;
-        s_st[e] = (uint16_t)st_of(__float_as_uint(nd[k].w), 0);
-        s_c[e] = qq[k] * basis(s_ay[row[k]], nd[k].y, p) * basis(s_az[row[k]], nd[k].z, p);
+      for (int t = 0; t < 4; ++t) {
+        if (t < c) {
+          nd[t] = pos4[n0 + t];
+          qq[t] = q[n0 + t];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (t < c && dst + t < cap)
+          s_nd[dst + t] = make_float2(nd[t].x, qq[t] * basis(ay, nd[t].y, p) * basis(az, nd[t].z, p));
+      for (int t = 4; t < c; ++t) {
+        const float4 n4 = pos4[n0 + t];
+        if (dst + t < cap)
+          s_nd[dst + t] = make_float2(n4.x, q[n0 + t] * basis(ay, n4.y, p) * basis(az, n4.z, p));
       }
     }
   }
   __syncthreads();
   if (tid >= xa) return;
-  // 3. gather for the point gx
+  // 3. gather for the point gx, column by column
   const int gx = x0 + tid;
   const int2 rx = brx[gx];
   const int k0 = g.per[0] ? tid : rx.x - fb;
   const int kc = g.per[0] ? p + 1 : rx.y;
   float acc = 0.f;
-  for (int j = 0; j < nrow; ++j) {
-    const int* off = s_off + j * sb1;
-    const int nb = s_base[j];
-    const int n1 = nb + off[k0 + kc];
-#pragma unroll 4
-    for (int nn = nb + off[k0]; nn < n1; ++nn) {
-      int a = gx - (int)s_st[nn];
-      if (g.per[0] && a < 0) a += g.N[0];
-      acc = fmaf(s_c[nn], basis(a, s_x[nn], p), acc);
+  for (int c4 = 0; c4 < kc; ++c4) {
+    const int k = k0 + c4;
+    int a = gx - box_stencil_start(fb + k, g.N[0], p, g.per[0]);
+    if (g.per[0]) a = p - c4;
+    const int n1 = min(s_col0[k + 1], cap);
+    if (p == 3) {
+      const Cubic cb = cubic_basis(a);
+#pragma unroll 2
+      for (int n = s_col0[k]; n < n1; ++n) {
+        const float2 v = s_nd[n];
+        acc = fmaf(v.y, cubic_eval(cb, v.x), acc);
+      }
+    } else {
+      for (int n = s_col0[k]; n < n1; ++n) {
+        const float2 v = s_nd[n];
+        acc = fmaf(v.y, lagrange(a, v.x, p), acc);
+      }
     }
   }
   Q[((int64_t)gz * g.N[1] + gy) * g.N[0] + gx] = acc;
