@@ -19,10 +19,15 @@ struct pmfem_dev {
   float4* pos4 = nullptr;
   int32_t* box_start = nullptr;
   AntPlan ap{};            // line form of anterpolation
+  int32_t *ant_list = nullptr, *ant_lstart = nullptr, *ant_col = nullptr;  // its node lists
   bool ant_ok = false, ic_ok = false, fft_ok = false;  // the plans fit
   bool ant_line = false;   // false: the tile form k_anterp
   int ant_threads = 0;
   IcPlan icp{}, icp_small{};  // interpolation+precorrection tiles: chosen, narrow
+  struct IcLists {
+    int32_t *list = nullptr, *lstart = nullptr, *wseg = nullptr;
+    uint32_t* rdesc = nullptr;
+  } icl, icl_small;
   bool ic_small_ok = false;
   bool ic_seg = false;        // false: the narrow tiles
   bool fft_plane = false;  // x and y transforms of a whole z-plane in one kernel
@@ -210,12 +215,11 @@ bool plan_anterp(const HostOps& o, const std::vector<int2>& bx, const std::vecto
     pl.o_x = (int)off;
     off += al(std::max<int64_t>(ncap, 1) * 8);
     pl.o_c = pl.o_x;
-    pl.o_st = (int)off;
-    off += al((int64_t)sbx * (nrow + 1) * 2);
+    pl.o_st = pl.o_x;
     pl.o_off = (int)off;
     off += al((int64_t)(sbx + 1) * 4);
     pl.o_meta = (int)off;
-    off += al((int64_t)2 * nrow * 4);
+    off += al((int64_t)nrow * 4);
     if (off <= 65536 && nrow <= 64 && colmax < 65536) {
       pl.xa = xa;
       pl.nsx = nsx;
@@ -227,6 +231,128 @@ bool plan_anterp(const HostOps& o, const std::vector<int2>& bx, const std::vecto
     }
   }
   return false;
+}
+
+// Node lists of k_anterp_line for plan pl, in launch order: per workgroup the
+// nodes of its box columns (column-major, box row, node order), each entry
+// node | row << 26, the list start of every workgroup and the column starts
+// within it (stride sbx + 1).
+// Node lists of k_interp_tile for plan pl, in launch order: per workgroup the
+// nodes of its source block column-major (x column, z, y, node order), the
+// list start of every workgroup, its observer segments (row prefix over the
+// z box rows, then the first row of each; stride 2 tz + 1), and per row the
+// (start | length << 16) of its 2 r_b + 1 runs in the workgroup's list.
+bool build_interp_lists(const HostOps& o, const IcPlan& pl, std::vector<int32_t>& list,
+                        std::vector<int32_t>& lstart, std::vector<int32_t>& wseg,
+                        std::vector<uint32_t>& rdesc) {
+  const int nbx = o.nbox[0], nby = o.nbox[1], nbz = o.nbox[2];
+  const int rb = o.rb, W = 2 * rb + 1;
+  const std::vector<int32_t>& bs = o.box_start;
+  auto box = [&](int x, int y, int z) -> int64_t {
+    if (o.per[0]) x = (x % nbx + nbx) % nbx;
+    else if (x < 0 || x >= nbx) return -1;
+    if (o.per[1]) y = (y % nby + nby) % nby;
+    else if (y < 0 || y >= nby) return -1;
+    if (o.per[2]) z = (z % nbz + nbz) % nbz;
+    else if (z < 0 || z >= nbz) return -1;
+    return ((int64_t)z * nby + y) * nbx + x;
+  };
+  const int64_t nwg = (int64_t)pl.nsx * nby * pl.nsz;
+  const int segw = 2 * pl.tz + 1, rpc = pl.szr * W;
+  lstart.assign(nwg + 1, 0);
+  wseg.assign(nwg * segw, 0);
+  rdesc.assign((size_t)o.n_unk * W, 0u);
+  list.clear();
+  std::vector<int32_t> pos((size_t)pl.sbx * (rpc + 1));
+  for (int64_t w = 0; w < nwg; ++w) {
+    const int sx = (int)(w % pl.nsx);
+    const int64_t rest = w / pl.nsx;
+    const int by = (int)(rest % nby), sz = (int)(rest / nby);
+    const int x0 = sx * pl.xs, z0 = sz * pl.tz;
+    const int xs = std::min(pl.xs, nbx - x0), tz = std::min(pl.tz, nbz - z0);
+    const int64_t l0 = (int64_t)list.size();
+    if (l0 > 2147483647LL) return false;
+    lstart[w] = (int32_t)l0;
+    for (int k = 0; k < pl.sbx; ++k) {
+      for (int zz = 0; zz < pl.szr; ++zz)
+        for (int yy = 0; yy < W; ++yy) {
+          pos[(size_t)k * (rpc + 1) + zz * W + yy] = (int32_t)((int64_t)list.size() - l0);
+          const int64_t b = box(x0 - rb + k, by - rb + yy, z0 - rb + zz);
+          if (b < 0) continue;
+          for (int32_t nd = bs[b]; nd < bs[b + 1]; ++nd) list.push_back(nd);
+        }
+      pos[(size_t)k * (rpc + 1) + rpc] = (int32_t)((int64_t)list.size() - l0);
+    }
+    if ((int64_t)list.size() - l0 >= 65536) return false;
+    int32_t* sg = &wseg[w * segw];
+    int32_t run = 0;
+    for (int kz = 0; kz <= pl.tz; ++kz) {
+      sg[kz] = run;
+      if (kz >= tz) continue;
+      const int64_t orow = ((int64_t)(z0 + kz) * nby + by) * nbx;
+      sg[pl.tz + 1 + kz] = bs[orow + x0];
+      run += bs[orow + x0 + xs] - bs[orow + x0];
+      for (int kx = 0; kx < xs; ++kx) {
+        const int64_t b = orow + x0 + kx;
+        for (int32_t r = bs[b]; r < bs[b + 1]; ++r)
+          for (int dx = 0; dx < W; ++dx) {
+            const int32_t* pc = &pos[(size_t)(kx + dx) * (rpc + 1)];
+            const int32_t a = pc[kz * W], e = pc[(kz + W) * W];
+            rdesc[(size_t)r * W + dx] = (uint32_t)a | ((uint32_t)(e - a) << 16);
+          }
+      }
+    }
+  }
+  if ((int64_t)list.size() > 2147483647LL) return false;
+  lstart[nwg] = (int32_t)list.size();
+  return true;
+}
+
+bool build_anterp_lists(const HostOps& o, const std::vector<int2>& bx,
+                        const std::vector<int2>& by, const std::vector<int2>& bz,
+                        const AntPlan& pl, std::vector<int32_t>& list,
+                        std::vector<int32_t>& lstart, std::vector<int32_t>& col) {
+  const int nbx = o.nbox[0], nby = o.nbox[1], nbz = o.nbox[2], p = o.p, shift = (p - 1) / 2;
+  const std::vector<int32_t>& bs = o.box_start;
+  if (o.n_unk >= (1 << 26)) return false;
+  const int64_t nwg = (int64_t)pl.nsx * o.N[1] * o.N[2];
+  lstart.assign(nwg + 1, 0);
+  col.assign(nwg * (pl.sbx + 1), 0);
+  list.clear();
+  for (int64_t w = 0; w < nwg; ++w) {
+    const int sx = (int)(w % pl.nsx);
+    const int64_t line = w / pl.nsx;
+    const int gy = (int)(line % o.N[1]), gz = (int)(line / o.N[1]);
+    const int x0 = sx * pl.xa, xe = std::min(x0 + pl.xa, o.N[0]) - 1;
+    const int fb = o.per[0] ? x0 - p + shift : bx[x0].x;
+    const int nbs = o.per[0] ? (xe - x0 + 1) + p : bx[xe].x + bx[xe].y - bx[x0].x;
+    std::vector<int64_t> rowbase;
+    for (int iz = 0; iz < bz[gz].y; ++iz)
+      for (int iy = 0; iy < by[gy].y; ++iy) {
+        int b_y = by[gy].x + iy, b_z = bz[gz].x + iz;
+        if (b_y >= nby) b_y -= nby;
+        if (b_z >= nbz) b_z -= nbz;
+        rowbase.push_back(((int64_t)b_z * nby + b_y) * nbx);
+      }
+    const int64_t l0 = (int64_t)list.size();
+    if (l0 > 2147483647LL) return false;
+    lstart[w] = (int32_t)l0;
+    for (int k = 0; k <= pl.sbx; ++k) {
+      col[w * (pl.sbx + 1) + k] = (int32_t)((int64_t)list.size() - l0);
+      if (k >= nbs) continue;
+      int x = fb + k;
+      if (o.per[0]) x = (x % nbx + nbx) % nbx;
+      else if (x < 0 || x >= nbx) continue;
+      for (size_t j = 0; j < rowbase.size(); ++j) {
+        const int64_t b = rowbase[j] + x;
+        for (int32_t nd = bs[b]; nd < bs[b + 1]; ++nd)
+          list.push_back(nd | (int32_t)((uint32_t)j << 26));
+      }
+    }
+  }
+  if ((int64_t)list.size() > 2147483647LL) return false;
+  lstart[nwg] = (int32_t)list.size();
+  return true;
 }
 
 // Tile plan for k_interp_tile: the largest tile (xs boxes along x times tz
@@ -290,19 +416,12 @@ bool plan_interp(const HostOps& o, int max_xs, IcPlan& pl) {
     int64_t off = 0;
     pl.o_q = (int)off;
     off += al(std::max<int64_t>(qcap, 1) * 4);
-    pl.o_pos = (int)off;
-    off += al((int64_t)sbx * (szr * W + 1) * 2);
-    pl.o_col0 = (int)off;
-    off += al((int64_t)(sbx + 1) * 4);
     pl.o_u = (int)off;
     off += al((int64_t)uzl * (p + 1) * ux * 4);
-    pl.o_rtab = (int)off;
-    off += al(std::max<int64_t>(rcap, 1) * 2);
-    pl.o_prp = (int)off;
-    off += al(std::max<int64_t>(rcap, 1) * 4);
     pl.o_seg = (int)off;
     off += al((int64_t)(2 * tz + 1) * 4);
-    if (off <= 40960 && colmax < 65536 && (int64_t)tz * xs < 65536) {
+    (void)colmax;
+    if (off <= 40960 && qcap < 65536) {
       pl.xs = xs;
       pl.tz = tz;
       pl.nsx = nsx;
@@ -339,6 +458,19 @@ int upload_all(pmfem_ctx* c) {
   if ((rc = upload(c, &d->box_start, o.box_start.data(), o.box_start.size()))) return rc;
   d->ic_ok = plan_interp(o, 128, d->icp);
   d->ic_small_ok = plan_interp(o, 4, d->icp_small);
+  for (int which = 0; which < 2; ++which) {
+    bool& ok = which == 0 ? d->ic_ok : d->ic_small_ok;
+    if (!ok) continue;
+    std::vector<int32_t> list, lstart, wseg;
+    std::vector<uint32_t> rdesc;
+    ok = build_interp_lists(o, which == 0 ? d->icp : d->icp_small, list, lstart, wseg, rdesc);
+    if (!ok) continue;
+    pmfem_dev::IcLists& L = which == 0 ? d->icl : d->icl_small;
+    if ((rc = upload(c, &L.list, list.data(), list.size()))) return rc;
+    if ((rc = upload(c, &L.lstart, lstart.data(), lstart.size()))) return rc;
+    if ((rc = upload(c, &L.wseg, wseg.data(), wseg.size()))) return rc;
+    if ((rc = upload(c, &L.rdesc, rdesc.data(), rdesc.size()))) return rc;
+  }
 
   {
     // whole-plane x/y transforms when a plane (row pairs + half-spectrum
@@ -362,6 +494,15 @@ int upload_all(pmfem_ctx* c) {
 
   auto bx = box_ranges(o, 0), by = box_ranges(o, 1), bz = box_ranges(o, 2);
   d->ant_ok = plan_anterp(o, bx, by, bz, d->ap);
+  if (d->ant_ok) {
+    std::vector<int32_t> list, lstart, col;
+    d->ant_ok = build_anterp_lists(o, bx, by, bz, d->ap, list, lstart, col);
+    if (d->ant_ok) {
+      if ((rc = upload(c, &d->ant_list, list.data(), list.size()))) return rc;
+      if ((rc = upload(c, &d->ant_lstart, lstart.data(), lstart.size()))) return rc;
+      if ((rc = upload(c, &d->ant_col, col.data(), col.size()))) return rc;
+    }
+  }
   d->ant_threads = std::max(64, std::min(128, (d->ap.xa + 63) / 64 * 64));
   if ((rc = select_variants(c))) return rc;
   if ((rc = upload(c, &d->brx, bx.data(), bx.size()))) return rc;
@@ -523,8 +664,8 @@ int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const doubl
       const AntPlan& pl = d->ap;
       const int64_t nwg = (int64_t)pl.nsx * g.N[1] * g.N[2];
       hipLaunchKernelGGL(k_anterp_line, dim3((unsigned)nwg), dim3(d->ant_threads),
-                         (size_t)pl.lds_bytes, s, g, pl, d->q, d->pos4, d->box_start, d->brx,
-                         d->bry, d->brz, d->grid);
+                         (size_t)pl.lds_bytes, s, g, pl, d->q, d->pos4, d->ant_list,
+                         d->ant_lstart, d->ant_col, d->brx, d->bry, d->brz, d->grid);
     } else {
       hipLaunchKernelGGL(k_anterp, dim3((unsigned)ntiles), dim3(T), 0, s, g, d->q, d->pos4,
                          d->box_start, d->brx, d->bry, d->brz, d->grid);
@@ -534,25 +675,30 @@ int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const doubl
     mark(7, 0);
     {
       const IcPlan& pl = d->ic_seg ? d->icp : d->icp_small;
+      const pmfem_dev::IcLists& L = d->ic_seg ? d->icl : d->icl_small;
       const int64_t nwg = (int64_t)pl.nsx * g.nbox[1] * pl.nsz;
       const dim3 grid((unsigned)nwg), blk(T);
       const size_t lds = (size_t)pl.lds_bytes;
       switch (g.rb) {
         case 0:
           hipLaunchKernelGGL(k_interp_tile<1>, grid, blk, lds, s, g, pl, d->grid, d->pos4,
-                             d->box_start, d->prp, d->pv, d->q, d->uz, d->u);
+                             L.list, L.lstart, L.wseg, L.rdesc, d->prp, d->pv, d->q, d->uz,
+                             d->u);
           break;
         case 1:
           hipLaunchKernelGGL(k_interp_tile<3>, grid, blk, lds, s, g, pl, d->grid, d->pos4,
-                             d->box_start, d->prp, d->pv, d->q, d->uz, d->u);
+                             L.list, L.lstart, L.wseg, L.rdesc, d->prp, d->pv, d->q, d->uz,
+                             d->u);
           break;
         case 2:
           hipLaunchKernelGGL(k_interp_tile<5>, grid, blk, lds, s, g, pl, d->grid, d->pos4,
-                             d->box_start, d->prp, d->pv, d->q, d->uz, d->u);
+                             L.list, L.lstart, L.wseg, L.rdesc, d->prp, d->pv, d->q, d->uz,
+                             d->u);
           break;
         default:
           hipLaunchKernelGGL(k_interp_tile<7>, grid, blk, lds, s, g, pl, d->grid, d->pos4,
-                             d->box_start, d->prp, d->pv, d->q, d->uz, d->u);
+                             L.list, L.lstart, L.wseg, L.rdesc, d->prp, d->pv, d->q, d->uz,
+                             d->u);
           break;
       }
     }

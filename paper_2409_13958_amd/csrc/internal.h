@@ -34,7 +34,7 @@ struct HostOps {
   int N[3] = {0, 0, 0}, M[3] = {0, 0, 0}, per[3] = {0, 0, 0}, nbox[3] = {0, 0, 0};
   double delta[3] = {0, 0, 0}, origin[3] = {0, 0, 0};
   int p = 3, rb = 2;
-  std::vector<float> pos4;            // [N'][4]: xi_x, xi_y, xi_z, packed stencil start
+  std::vector<float> pos4;            // [N'][4]: xi_x, xi_y, xi_z, packed box coordinates
   std::vector<int32_t> box_start;     // [nbox+1]
   // local CSR (shared pattern of exchange, charge, gradient)
   std::vector<int32_t> loc_rowptr, loc_col;

@@ -32,7 +32,7 @@ struct IcPlan {
   int qcap;      // staged source charges
   int rcap;      // observer rows per tile
   int ux, uzl;   // staged potential: points per line (xs + p), z-lines (tz + p)
-  int o_q, o_pos, o_col0, o_u, o_rtab, o_prp, o_seg;  // LDS byte offsets
+  int o_q, o_u, o_seg;  // LDS byte offsets
   int lds_bytes;
 };
 
@@ -55,8 +55,8 @@ __global__ void k_anterp(GridParams g, const float* q, const float4* pos4,
                          const int32_t* box_start, const int2* brx, const int2* bry,
                          const int2* brz, float* Q);
 __global__ void k_anterp_line(GridParams g, AntPlan pl, const float* q, const float4* pos4,
-                              const int32_t* box_start, const int2* brx, const int2* bry,
-                              const int2* brz, float* Q);
+                              const int32_t* list, const int32_t* lstart, const int32_t* colst,
+                              const int2* brx, const int2* bry, const int2* brz, float* Q);
 __global__ void k_r2c_x(GridParams g, const float* Q, float2* spec, const float2* twx,
                         int lines_per_block);
 __global__ void k_fft_y(GridParams g, float2* spec, const float2* twy, int B, int inverse,
@@ -72,7 +72,8 @@ __global__ void k_c2r_x(GridParams g, const float2* spec, float* U, const float2
 
 template <int WT>
 __global__ void k_interp_tile(GridParams g, IcPlan pl, const float* U, const float4* pos4,
-                              const int32_t* box_start, const int32_t* prp, const float* pval,
+                              const int32_t* list, const int32_t* lstart, const int32_t* wseg,
+                              const uint32_t* rdesc, const int32_t* prp, const float* pval,
                               const float* q, const float* uz, float* u);
 template <int G>
 __global__ void k_grad(int64_t n, const int32_t* rp, const int32_t* col, const float4* gl,

@@ -324,9 +324,11 @@ __global__ void __launch_bounds__(256) k_anterp(
 // ---------------------------------------------------------------------------
 // anterpolation by grid lines. A workgroup takes `xa` consecutive points of
 // one (y, z) grid line, one thread per point. The boxes whose stencils reach
-// the line form at most (p + 1)^2 box rows; the nodes of those rows in the
-// segment's x range are staged once in LDS, column-major (x box outermost,
-// then box row, then node order), each reduced to what the line needs: its
+// the line form at most (p + 1)^2 box rows. Their nodes in the segment's x
+// range are listed on the host, column-major (x box outermost, then box row,
+// then node order), each entry tagged with its box row; the box table does
+// not change between evaluations, so the list is built once. The workgroup
+// stages the listed nodes in LDS, each reduced to what the line needs: its
 // xi_x and the product c = q L_ay(xi_y) L_az(xi_z) of its charge with its y
 // and z weights at the line (a_y, a_z are fixed per box row). A point then
 // sums c L_ax(xi_x) over the p + 1 box columns covering it; a_x is fixed per
@@ -339,109 +341,67 @@ __device__ __forceinline__ float basis(int a, float xi, int p) {
 
 __global__ void __launch_bounds__(128) k_anterp_line(
     GridParams g, AntPlan pl, const float* __restrict__ q, const float4* __restrict__ pos4,
-    const int32_t* __restrict__ box_start, const int2* __restrict__ brx,
+    const int32_t* __restrict__ list, const int32_t* __restrict__ lstart,
+    const int32_t* __restrict__ colst, const int2* __restrict__ brx,
     const int2* __restrict__ bry, const int2* __restrict__ brz, float* __restrict__ Q) {
   extern __shared__ float4 smem4[];
   unsigned char* smem = reinterpret_cast<unsigned char*>(smem4);
-  float2* s_nd = reinterpret_cast<float2*>(smem + pl.o_x);          // (xi_x, c) per node
-  uint16_t* s_pos = reinterpret_cast<uint16_t*>(smem + pl.o_st);    // [sbx][nrow + 1]
-  int* s_col0 = reinterpret_cast<int*>(smem + pl.o_off);            // [sbx + 1]
-  int* s_rb = reinterpret_cast<int*>(smem + pl.o_meta);             // [nrow] row base box
-  int* s_ayz = s_rb + pl.nrow;                                      // [nrow] a_y | a_z << 8
+  float2* s_nd = reinterpret_cast<float2*>(smem + pl.o_x);  // (xi_x, c) per listed node
+  int* s_col0 = reinterpret_cast<int*>(smem + pl.o_off);    // [sbx + 1] column starts
+  int* s_ayz = reinterpret_cast<int*>(smem + pl.o_meta);    // [nrow] a_y | a_z << 8
   const int tid = threadIdx.x, T = blockDim.x;
-  const int nbx = g.nbox[0], nby = g.nbox[1], nbz = g.nbox[2];
-  const int sx = blockIdx.x % pl.nsx, line = blockIdx.x / pl.nsx;
+  const int w = blockIdx.x;
+  const int sx = w % pl.nsx, line = w / pl.nsx;
   const int gy = line % g.N[1], gz = line / g.N[1];
   const int x0 = sx * pl.xa, xa = min(pl.xa, g.N[0] - x0);
   const int2 ry = bry[gy], rz = brz[gz];
   const int nrow = ry.y * rz.y;
   const int p = g.p, shift = (p - 1) / 2;
-  const int2 fx = brx[x0], lxr = brx[x0 + xa - 1];
-  const int fb = g.per[0] ? x0 - p + shift : fx.x;  // first staged box (unwrapped)
-  const int nbs = g.per[0] ? xa + p : lxr.x + lxr.y - fx.x;
-  const int np1 = pl.nrow + 1;
-  // box rows: by = ry.x + iy, bz = rz.x + iz (wrapped on periodic axes)
+  const int fb = g.per[0] ? x0 - p + shift : brx[x0].x;  // first listed box column
+  const int l0 = lstart[w];
+  const int n = min(lstart[w + 1] - l0, pl.ncap);
   if (tid < nrow) {
     const int iy = tid % ry.y, iz = tid / ry.y;
     int by = ry.x + iy, bz = rz.x + iz;
-    if (by >= nby) by -= nby;
-    if (bz >= nbz) bz -= nbz;
+    if (by >= g.nbox[1]) by -= g.nbox[1];
+    if (bz >= g.nbox[2]) bz -= g.nbox[2];
     int ay = gy - box_stencil_start(by, g.N[1], p, g.per[1]);
     int az = gz - box_stencil_start(bz, g.N[2], p, g.per[2]);
     if (g.per[1]) ay = ((ay % g.N[1]) + g.N[1]) % g.N[1];
     if (g.per[2]) az = ((az % g.N[2]) + g.N[2]) % g.N[2];
-    s_rb[tid] = (bz * nby + by) * nbx;
     s_ayz[tid] = ay | (az << 8);
   }
+  for (int k = tid; k <= pl.sbx; k += T) s_col0[k] = colst[(int64_t)w * (pl.sbx + 1) + k];
   __syncthreads();
-  // 1. per column: node counts of its boxes, prefix over the rows
-  for (int k = tid; k < nbs; k += T) {
-    int x = fb + k;
-    if (g.per[0]) x = x < 0 ? x + nbx : (x >= nbx ? x - nbx : x);
-    int run = 0;
-    for (int j = 0; j < nrow; ++j) {
-      const int b = s_rb[j] + x;
-      s_pos[k * np1 + j] = (uint16_t)run;
-      run += box_start[b + 1] - box_start[b];
-    }
-    s_pos[k * np1 + nrow] = (uint16_t)run;
-    s_col0[k] = run;
-  }
-  __syncthreads();
-  if (tid < 64) {  // column starts
-    int carry = 0;
-    for (int c0 = 0; c0 < nbs; c0 += 64) {
-      const int i = c0 + tid;
-      const int v = i < nbs ? s_col0[i] : 0;
-      int x = v;
+  // stage the listed nodes with their y/z weights at this line, K in flight
+  {
+    constexpr int K = 8;
+    for (int e0 = tid; e0 < n; e0 += K * T) {
+      int ent[K];
 #pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(x, d, 64);
-        if (tid >= d) x += y;
+      for (int j = 0; j < K; ++j) ent[j] = e0 + j * T < n ? list[l0 + e0 + j * T] : 0;
+      float4 nd[K];
+      float qq[K];
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const int gi = ent[j] & 0x3FFFFFF;
+        nd[j] = pos4[gi];
+        qq[j] = q[gi];
       }
-      if (i < nbs) s_col0[i] = carry + x - v;
-      carry += __shfl(x, 63, 64);
-    }
-    if (tid == 0) s_col0[nbs] = carry;
-  }
-  __syncthreads();
-  // 2. stage the nodes with their y/z weights at this line
-  const int cap = pl.ncap;
-  for (int k = tid; k < nbs; k += T) {
-    int x = fb + k;
-    if (g.per[0]) x = x < 0 ? x + nbx : (x >= nbx ? x - nbx : x);
-    const int base = s_col0[k];
-    for (int j = 0; j < nrow; ++j) {
-      const int b = s_rb[j] + x;
-      const int n0 = box_start[b];
-      const int c = s_pos[k * np1 + j + 1] - s_pos[k * np1 + j];
-      const int dst = base + s_pos[k * np1 + j];
-      const int ayz = s_ayz[j];
-      const int ay = ayz & 255, az = ayz >> 8;
-      // up to 4 nodes of the box at once, the rest one by one
-      float4 nd[4];
-      float qq[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        if (t < c) {
-          nd[t] = pos4[n0 + t];
-          qq[t] = q[n0 + t];
+      for (int j = 0; j < K; ++j) {
+        const int e = e0 + j * T;
+        if (e < n) {
+          const int ayz = s_ayz[(unsigned)ent[j] >> 26];
+          s_nd[e] = make_float2(nd[j].x, qq[j] * basis(ayz & 255, nd[j].y, p) *
+                                             basis(ayz >> 8, nd[j].z, p));
         }
-      }
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (t < c && dst + t < cap)
-          s_nd[dst + t] = make_float2(nd[t].x, qq[t] * basis(ay, nd[t].y, p) * basis(az, nd[t].z, p));
-      for (int t = 4; t < c; ++t) {
-        const float4 n4 = pos4[n0 + t];
-        if (dst + t < cap)
-          s_nd[dst + t] = make_float2(n4.x, q[n0 + t] * basis(ay, n4.y, p) * basis(az, n4.z, p));
       }
     }
   }
   __syncthreads();
   if (tid >= xa) return;
-  // 3. gather for the point gx, column by column
+  // gather for the point gx, column by column
   const int gx = x0 + tid;
   const int2 rx = brx[gx];
   const int k0 = g.per[0] ? tid : rx.x - fb;
@@ -449,19 +409,18 @@ __global__ void __launch_bounds__(128) k_anterp_line(
   float acc = 0.f;
   for (int c4 = 0; c4 < kc; ++c4) {
     const int k = k0 + c4;
-    int a = gx - box_stencil_start(fb + k, g.N[0], p, g.per[0]);
-    if (g.per[0]) a = p - c4;
-    const int n1 = min(s_col0[k + 1], cap);
+    const int a = g.per[0] ? p - c4 : gx - box_stencil_start(fb + k, g.N[0], p, 0);
+    const int n1 = min(s_col0[k + 1], n);
     if (p == 3) {
       const Cubic cb = cubic_basis(a);
 #pragma unroll 2
-      for (int n = s_col0[k]; n < n1; ++n) {
-        const float2 v = s_nd[n];
+      for (int e = s_col0[k]; e < n1; ++e) {
+        const float2 v = s_nd[e];
         acc = fmaf(v.y, cubic_eval(cb, v.x), acc);
       }
     } else {
-      for (int n = s_col0[k]; n < n1; ++n) {
-        const float2 v = s_nd[n];
+      for (int e = s_col0[k]; e < n1; ++e) {
+        const float2 v = s_nd[e];
         acc = fmaf(v.y, lagrange(a, v.x, p), acc);
       }
     }
@@ -803,110 +762,62 @@ __global__ void __launch_bounds__(256) k_c2r_x(GridParams g, const float2* __res
 // ---------------------------------------------------------------------------
 // interpolation + precorrection (steps 3 and 4), tile form. A workgroup
 // takes the observer boxes x in [x0, x0 + xs), y = by, z in [z0, z0 + tz).
-// Every source box their near regions touch lies in the staged block
+// Every source box their near regions touch lies in the block
 //   x in [x0 - r_b, x0 + xs + r_b), y in [by - r_b, by + r_b],
 //   z in [z0 - r_b, z0 + tz + r_b)
-// whose source charges are copied once into LDS column-major: x box column
-// outermost, then z, then y, then node order. The precorrection values of
-// every row are stored in the matching order (x offset, then z, then y), so
-// the near columns of a row are W contiguous LDS runs, one per x offset:
-// rows z = bz - r_b .. bz + r_b of its column. The (p + 1) y-lines of U for
-// the tile's z range are staged as well. Each group of G lanes then takes
-// one observer row at a time: u_n = W_n U + sum over the runs of P q + u_Z.
+// whose nodes are listed on the host column-major: x box column outermost,
+// then z, then y, then node order (the box table is fixed, so the list is
+// built once). The workgroup stages the charges of its list in LDS. The
+// precorrection values of every row are stored in the matching order (x
+// offset, then z, then y), so the near columns of a row are 2 r_b + 1
+// contiguous runs of the staged charges, one per x offset; each row carries
+// the (start, length) of its runs. The (p + 1) y-lines of U over the tile's z
+// range are staged too. Each group of G lanes then takes one observer row:
+// u_n = W_n U + sum over the runs of P q + u_Z, in a fixed order.
 
 constexpr int kIcLanes = 8;
 
 template <int WT>
 __global__ void __launch_bounds__(256) k_interp_tile(
     GridParams g, IcPlan pl, const float* __restrict__ U, const float4* __restrict__ pos4,
-    const int32_t* __restrict__ box_start, const int32_t* __restrict__ prp,
-    const float* __restrict__ pval, const float* __restrict__ q, const float* __restrict__ uz,
-    float* __restrict__ u) {
+    const int32_t* __restrict__ list, const int32_t* __restrict__ lstart,
+    const int32_t* __restrict__ wseg, const uint32_t* __restrict__ rdesc,
+    const int32_t* __restrict__ prp, const float* __restrict__ pval,
+    const float* __restrict__ q, const float* __restrict__ uz, float* __restrict__ u) {
   extern __shared__ float4 smem4[];
   unsigned char* smem = reinterpret_cast<unsigned char*>(smem4);
-  float* s_q = reinterpret_cast<float*>(smem + pl.o_q);               // staged charges
-  uint16_t* s_pos = reinterpret_cast<uint16_t*>(smem + pl.o_pos);    // [sbx][rpc + 1]
-  int* s_col0 = reinterpret_cast<int*>(smem + pl.o_col0);            // [sbx + 1]
-  float* s_U = reinterpret_cast<float*>(smem + pl.o_u);              // [uzl][p + 1][ux]
-  uint16_t* s_rtab = reinterpret_cast<uint16_t*>(smem + pl.o_rtab);  // row -> kz * xs + kx
-  int* s_prp = reinterpret_cast<int*>(smem + pl.o_prp);              // row -> matrix start
-  int* s_seg = reinterpret_cast<int*>(smem + pl.o_seg);  // [tz + 1] row prefix, [tz] first row
+  float* s_q = reinterpret_cast<float*>(smem + pl.o_q);   // staged charges
+  float* s_U = reinterpret_cast<float*>(smem + pl.o_u);   // [uzl][p + 1][ux]
+  int* s_seg = reinterpret_cast<int*>(smem + pl.o_seg);   // [tz + 1] row prefix, [tz] first row
   const int tid = threadIdx.x, T = blockDim.x;
-  const int nbx = g.nbox[0], nby = g.nbox[1], nbz = g.nbox[2];
-  const int rb = g.rb, p = g.p, p1 = p + 1;
-  constexpr int W = WT;  // 2 r_b + 1
-  const int sx = blockIdx.x % pl.nsx;
-  const int rest = blockIdx.x / pl.nsx;
+  const int nby = g.nbox[1];
+  const int p = g.p, p1 = p + 1;
+  const int w = blockIdx.x;
+  const int sx = w % pl.nsx, rest = w / pl.nsx;
   const int by = rest % nby, sz = rest / nby;
   const int x0 = sx * pl.xs, z0 = sz * pl.tz;
-  const int xs = min(pl.xs, nbx - x0), tz = min(pl.tz, nbz - z0);
-  const int sbx = pl.sbx, szr = pl.szr, rpc1 = pl.szr * W + 1;
-  int* s_segfirst = s_seg + (pl.tz + 1);
-
-  // 0. observer rows: tz contiguous segments of the node order
-  if (tid < 64) {
-    int cnt = 0, first = 0;
-    if (tid < tz) {
-      const int64_t orow = ((int64_t)(z0 + tid) * nby + by) * nbx;
-      first = box_start[orow + x0];
-      cnt = box_start[orow + x0 + xs] - first;
-    }
-    int x = cnt;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int y = __shfl_up(x, d, 64);
-      if (tid >= d) x += y;
-    }
-    if (tid < tz) {
-      s_seg[tid] = x - cnt;
-      s_segfirst[tid] = first;
-    }
-    if (tid == tz - 1) s_seg[tz] = x;
-  }
-  __syncthreads();
-  const int nrows = s_seg[tz];
-  if (nrows == 0) return;  // uniform across the workgroup
-
-  // 1. node counts of the staged boxes (k, zz, yy), stored at their
-  //    column-major slot; lanes run along x so the box table reads coalesce
-  const int nstaged = sbx * szr * W;
-  auto staged_box = [&](int e, int& k, int& zz, int& yy) -> int64_t {
-    k = e % sbx;
-    const int r = e / sbx;
-    yy = r % W;
-    zz = r / W;
-    int x = x0 - rb + k, y = by - rb + yy, z = z0 - rb + zz;
-    if (g.per[0]) x = x < 0 ? x + nbx : (x >= nbx ? x - nbx : x);
-    else if (x < 0 || x >= nbx) return -1;
-    if (g.per[1]) y = y < 0 ? y + nby : (y >= nby ? y - nby : y);
-    else if (y < 0 || y >= nby) return -1;
-    if (g.per[2]) z = z < 0 ? z + nbz : (z >= nbz ? z - nbz : z);
-    else if (z < 0 || z >= nbz) return -1;
-    return ((int64_t)z * nby + y) * nbx + x;
-  };
+  const int tz = min(pl.tz, g.nbox[2] - z0);
+  // [0, pl.tz]: row prefix over the z segments; [pl.tz + 1, 2 pl.tz]: first row of each
+  const int segw = 2 * pl.tz + 1;
+  for (int i = tid; i < segw; i += T) s_seg[i] = wseg[(int64_t)w * segw + i];
+  const int l0 = lstart[w];
+  const int n = min(lstart[w + 1] - l0, pl.qcap);
+  // stage the listed charges, K loads in flight
   {
-    constexpr int K = 4;
-    for (int e0 = tid; e0 < nstaged; e0 += K * T) {
-      int c[K], slot[K];
+    constexpr int K = 8;
+    for (int e0 = tid; e0 < n; e0 += K * T) {
+      int gi[K];
 #pragma unroll
-      for (int j = 0; j < K; ++j) {
-        const int e = e0 + j * T;
-        c[j] = 0;
-        slot[j] = -1;
-        if (e < nstaged) {
-          int k, zz, yy;
-          const int64_t b = staged_box(e, k, zz, yy);
-          slot[j] = k * rpc1 + zz * W + yy;
-          if (b >= 0) c[j] = box_start[b + 1] - box_start[b];
-        }
-      }
+      for (int j = 0; j < K; ++j) gi[j] = e0 + j * T < n ? list[l0 + e0 + j * T] : 0;
+      float v[K];
+#pragma unroll
+      for (int j = 0; j < K; ++j) v[j] = q[gi[j]];
 #pragma unroll
       for (int j = 0; j < K; ++j)
-        if (slot[j] >= 0) s_pos[slot[j]] = (uint16_t)c[j];
+        if (e0 + j * T < n) s_q[e0 + j * T] = v[j];
     }
   }
   // stencil lines of U: z-lines [stz(z0), stz(z0) + tz + p), y-lines [sty, sty + p]
-  const int shift = (p - 1) / 2;
   const int ux0 = box_stencil_start(x0, g.N[0], p, g.per[0]);
   const int sty = box_stencil_start(by, g.N[1], p, g.per[1]);
   const int stz = box_stencil_start(z0, g.N[2], p, g.per[2]);
@@ -925,127 +836,35 @@ __global__ void __launch_bounds__(256) k_interp_tile(
         },
         [&](int e, float v) { s_U[e] = v; });
   }
-  // row table and matrix starts of the observer rows
-  for (int e = tid; e < tz * xs; e += T) {
-    const int kz = e / xs, kx = e - kz * xs;
-    const int64_t b = ((int64_t)(z0 + kz) * nby + by) * nbx + x0 + kx;
-    const int r0 = box_start[b], r1 = box_start[b + 1];
-    const int s0 = s_seg[kz] + (r0 - s_segfirst[kz]);
-    for (int r = r0; r < r1; ++r) {
-      const int sl = s0 + (r - r0);
-      if (sl < pl.rcap) {
-        s_rtab[sl] = (uint16_t)(kz * pl.xs + kx);
-        s_prp[sl] = prp[r];
-      }
-    }
-  }
   __syncthreads();
-  // 2. per column: exclusive prefix over its (zz, yy) slots, column totals
-  {
-    const int wave = tid >> 6, lane = tid & 63, nw = T >> 6;
-    const int nslot = szr * W;
-    for (int k = wave; k < sbx; k += nw) {
-      int carry = 0;
-      for (int c0 = 0; c0 < nslot; c0 += 64) {
-        const int i = c0 + lane;
-        const int v = i < nslot ? (int)s_pos[k * rpc1 + i] : 0;
-        int x = v;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-          const int y = __shfl_up(x, d, 64);
-          if (lane >= d) x += y;
-        }
-        if (i < nslot) s_pos[k * rpc1 + i] = (uint16_t)(carry + x - v);
-        carry += __shfl(x, 63, 64);
-      }
-      if (lane == 0) {
-        s_pos[k * rpc1 + nslot] = (uint16_t)carry;
-        s_col0[k] = carry;
-      }
-    }
-  }
-  __syncthreads();
-  if (tid < 64) {  // column starts: exclusive scan of the totals (sbx <= 64 * chunks)
-    int carry = 0;
-    for (int c0 = 0; c0 < sbx; c0 += 64) {
-      const int i = c0 + tid;
-      const int v = i < sbx ? s_col0[i] : 0;
-      int x = v;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(x, d, 64);
-        if (tid >= d) x += y;
-      }
-      if (i < sbx) s_col0[i] = carry + x - v;
-      carry += __shfl(x, 63, 64);
-    }
-    if (tid == 0) s_col0[sbx] = carry;
-  }
-  __syncthreads();
-  // 3. copy the source charges into their slots (lanes along x)
-  {
-    const int total = min(s_col0[sbx], pl.qcap);
-    constexpr int K = 4;
-    for (int e0 = tid; e0 < nstaged; e0 += K * T) {
-      int n0[K], c[K], dst[K];
-#pragma unroll
-      for (int j = 0; j < K; ++j) {
-        const int e = e0 + j * T;
-        c[j] = 0;
-        n0[j] = 0;
-        dst[j] = 0;
-        if (e < nstaged) {
-          int k, zz, yy;
-          const int64_t b = staged_box(e, k, zz, yy);
-          if (b >= 0) {
-            const int slot = k * rpc1 + zz * W + yy;
-            dst[j] = s_col0[k] + s_pos[slot];
-            c[j] = s_pos[slot + 1] - s_pos[slot];
-            n0[j] = box_start[b];
-          }
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < K; ++j) {
-        // up to 4 nodes of the box in one go, the rest one by one
-        float v[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) v[t] = t < c[j] ? q[n0[j] + t] : 0.f;
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-          if (t < c[j] && dst[j] + t < total) s_q[dst[j] + t] = v[t];
-        for (int t = 4; t < c[j]; ++t)
-          if (dst[j] + t < total) s_q[dst[j] + t] = q[n0[j] + t];
-      }
-    }
-  }
-  __syncthreads();
+  const int nrows = s_seg[tz];
+  const int* s_first = s_seg + pl.tz + 1;
 
-  // 4. rows: G lanes per row
+  // rows: G lanes per row
   constexpr int G = kIcLanes;
+  constexpr int W = WT;  // 2 r_b + 1
   const int lane = tid & (G - 1), grp = tid / G, ngrp = T / G;
-  const int nr = min(nrows, pl.rcap);
   const bool cubic = p == 3;
   // lane -> stencil points (ax, ay) = (l % 4, l / 4) for l = lane, lane + G (p = 3)
   const Cubic cxa = cubic_basis(lane & 3), cya = cubic_basis(lane >> 2);
   const Cubic cxb = cubic_basis((lane + G) & 3), cyb = cubic_basis((lane + G) >> 2);
   const Cubic cz0 = cubic_basis(0), cz1 = cubic_basis(1), cz2 = cubic_basis(2), cz3 = cubic_basis(3);
-  for (int sl = grp; sl < nr; sl += ngrp) {
-    const int tab = s_rtab[sl];
-    const int kz = tab / pl.xs, kx = tab - kz * pl.xs;
-    const int r = s_segfirst[kz] + (sl - s_seg[kz]);
-    // the W runs of the row, then all their matrix values in flight at once
+  for (int sl = grp; sl < nrows; sl += ngrp) {
+    int kz = 0;
+    while (kz + 1 < tz && s_seg[kz + 1] <= sl) ++kz;
+    const int r = s_first[kz] + (sl - s_seg[kz]);
+    // run descriptors and all run values in flight at once
     constexpr int RK = WT <= 5 ? 8 : 4;  // values per lane per run held in registers
-    int qs[WT], ln[WT], po[WT];
-    int pp = s_prp[sl];
+    uint32_t dsc[WT];
+#pragma unroll
+    for (int dx = 0; dx < WT; ++dx) dsc[dx] = rdesc[(int64_t)r * W + dx];
+    int pp = prp[r];
+    const float4 xi = pos4[r];
+    int po[WT];
 #pragma unroll
     for (int dx = 0; dx < WT; ++dx) {
-      const int k = kx + dx;
-      const int a = s_pos[k * rpc1 + kz * W], b = s_pos[k * rpc1 + (kz + W) * W];
-      qs[dx] = s_col0[k] + a;
-      ln[dx] = b - a;
       po[dx] = pp;
-      pp += b - a;
+      pp += (int)(dsc[dx] >> 16);
     }
     float v[WT][RK];
 #pragma unroll
@@ -1053,24 +872,25 @@ __global__ void __launch_bounds__(256) k_interp_tile(
 #pragma unroll
       for (int t = 0; t < RK; ++t) {
         const int c = lane + G * t;
-        v[dx][t] = c < ln[dx] ? pval[po[dx] + c] : 0.f;
+        v[dx][t] = c < (int)(dsc[dx] >> 16) ? pval[po[dx] + c] : 0.f;
       }
-    const float4 xi = pos4[r];
     float acc = 0.f;
 #pragma unroll
     for (int dx = 0; dx < WT; ++dx) {
+      const int qs = (int)(dsc[dx] & 0xFFFFu), ln = (int)(dsc[dx] >> 16);
 #pragma unroll
       for (int t = 0; t < RK; ++t) {
         const int c = lane + G * t;
-        if (c < ln[dx]) acc = fmaf(v[dx][t], s_q[qs[dx] + c], acc);
+        if (c < ln) acc = fmaf(v[dx][t], s_q[qs + c], acc);
       }
-      for (int c = lane + G * RK; c < ln[dx]; c += G)
-        acc = fmaf(pval[po[dx] + c], s_q[qs[dx] + c], acc);
+      for (int c = lane + G * RK; c < ln; c += G) acc = fmaf(pval[po[dx] + c], s_q[qs + c], acc);
     }
-    // W U from the staged lines
-    const int bx = x0 + kx, bz = z0 + kz;
+    // W U from the staged lines; the box of the row from its packed coordinates
+    const uint32_t bc = __float_as_uint(xi.w);
+    const int bx = (int)(bc & 1023u), bz = (int)((bc >> 20) & 1023u);
+    const int kx = bx - x0;
     const int relx = g.per[0] ? kx : box_stencil_start(bx, g.N[0], p, 0) - ux0;
-    const int relz = g.per[2] ? kz : box_stencil_start(bz, g.N[2], p, 0) - stz;
+    const int relz = g.per[2] ? bz - z0 : box_stencil_start(bz, g.N[2], p, 0) - stz;
     if (cubic) {
       const int zs = p1 * pl.ux;
       const float* su = s_U + (relz * p1) * pl.ux + relx;
@@ -1078,14 +898,14 @@ __global__ void __launch_bounds__(256) k_interp_tile(
       const float wz2 = cubic_eval(cz2, xi.z), wz3 = cubic_eval(cz3, xi.z);
       {
         const float* s0 = su + (lane >> 2) * pl.ux + (lane & 3);
-        const float w = cubic_eval(cxa, xi.x) * cubic_eval(cya, xi.y);
-        acc = fmaf(w, wz0 * s0[0] + wz1 * s0[zs] + wz2 * s0[2 * zs] + wz3 * s0[3 * zs], acc);
+        const float wt = cubic_eval(cxa, xi.x) * cubic_eval(cya, xi.y);
+        acc = fmaf(wt, wz0 * s0[0] + wz1 * s0[zs] + wz2 * s0[2 * zs] + wz3 * s0[3 * zs], acc);
       }
       {
         const int l = lane + G;
         const float* s0 = su + (l >> 2) * pl.ux + (l & 3);
-        const float w = cubic_eval(cxb, xi.x) * cubic_eval(cyb, xi.y);
-        acc = fmaf(w, wz0 * s0[0] + wz1 * s0[zs] + wz2 * s0[2 * zs] + wz3 * s0[3 * zs], acc);
+        const float wt = cubic_eval(cxb, xi.x) * cubic_eval(cyb, xi.y);
+        acc = fmaf(wt, wz0 * s0[0] + wz1 * s0[zs] + wz2 * s0[2 * zs] + wz3 * s0[3 * zs], acc);
       }
     } else {
       const int nst = p1 * p1 * p1;
@@ -1100,9 +920,10 @@ __global__ void __launch_bounds__(256) k_interp_tile(
   }
 }
 
-#define PMFEM_INTERP_TILE(WT)                                                             \
-  template __global__ void k_interp_tile<WT>(GridParams, IcPlan, const float*, const float4*,  \
-                                             const int32_t*, const int32_t*, const float*,     \
+#define PMFEM_INTERP_TILE(WT)                                                              \
+  template __global__ void k_interp_tile<WT>(GridParams, IcPlan, const float*, const float4*,   \
+                                             const int32_t*, const int32_t*, const int32_t*,    \
+                                             const uint32_t*, const int32_t*, const float*,     \
                                              const float*, const float*, float*);
 PMFEM_INTERP_TILE(1)
 PMFEM_INTERP_TILE(3)

@@ -333,12 +333,10 @@ int host_build(pmfem_ctx* c) {
   for (int64_t b = 0; b < nbox; ++b) o.box_start[b + 1] += o.box_start[b];
   o.pos4.resize(4 * Np);
   for (int64_t u = 0; u < Np; ++u) {
-    uint32_t packed = 0;
+    uint32_t packed = 0;  // box coordinates, 10 bits per axis
     for (int a = 0; a < 3; ++a) {
       o.pos4[4 * u + a] = (float)(s[3 * u + a] - stu[3 * u + a]);
-      int w = stu[3 * u + a];
-      if (o.per[a]) w = ((w % o.N[a]) + o.N[a]) % o.N[a];
-      packed |= (uint32_t)w << (10 * a);
+      packed |= (uint32_t)bx[3 * u + a] << (10 * a);
     }
     std::memcpy(&o.pos4[4 * u + 3], &packed, 4);
   }

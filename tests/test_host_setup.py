@@ -106,8 +106,8 @@ def test_node_stencils(pair):
     xi = (orc.aim.s - orc.aim.st)[perm]
     assert np.abs(p4[:, :3] - xi).max() < 1e-5
     packed = p4[:, 3].view(np.uint32).astype(np.int64)
-    st = np.stack([(packed >> (10 * a)) & 1023 for a in range(3)], axis=1)
-    assert np.array_equal(st, orc.aim.st[perm] % orc.aim.grid.N[None, :])
+    box = np.stack([(packed >> (10 * a)) & 1023 for a in range(3)], axis=1)
+    assert np.array_equal(box, orc.aim.b[perm])
 
 
 def test_precorrection(pair):
