@@ -40,8 +40,9 @@ struct pmfem_dev {
   int32_t* zrp = nullptr;
   int4* zrec = nullptr;   // element correction Z0: {column, Zx, Zy, Zz}
   int lanes = 16;         // lanes per row of k_local / k_grad
-  int32_t* prp = nullptr;
+  int32_t* prp = nullptr;  // device precorrection rows (runs padded to 4 values)
   float* pv = nullptr;
+  int64_t nnz_p_dev = 0;
   float* khat = nullptr;
   float2 *twx = nullptr, *twy = nullptr, *twz = nullptr;
   double* mu = nullptr;
@@ -415,7 +416,7 @@ bool plan_interp(const HostOps& o, int max_xs, IcPlan& pl) {
     const int ux = xs + p, uzl = tz + p;
     int64_t off = 0;
     pl.o_q = (int)off;
-    off += al(std::max<int64_t>(qcap, 1) * 4);
+    off += al((qcap + 4) * 4);  // staged charges and 4 zeros
     pl.o_u = (int)off;
     off += al((int64_t)uzl * (p + 1) * ux * 4);
     pl.o_seg = (int)off;
@@ -541,9 +542,59 @@ int upload_all(pmfem_ctx* c) {
     if ((rc = upload(c, &d->zrp, o.z0_rowptr.data(), n + 1))) return rc;
     if ((rc = upload(c, &d->zrec, zr.data(), nnzZ))) return rc;
   }
-  const int64_t nnzP = o.p_rowptr[n];
-  if ((rc = upload(c, &d->prp, o.p_rowptr.data(), n + 1))) return rc;
-  if ((rc = upload(c, &d->pv, o.p_val.data(), nnzP))) return rc;
+  {
+    // precorrection rows on the device: each x-offset run padded with zeros
+    // to a multiple of 4 values, so every run starts 16-byte aligned
+    const int nbx = o.nbox[0], nby = o.nbox[1], nbz = o.nbox[2], rb = o.rb, W = 2 * rb + 1;
+    auto cnt = [&](int x, int y, int z) -> int64_t {
+      if (o.per[0]) x = (x % nbx + nbx) % nbx;
+      else if (x < 0 || x >= nbx) return 0;
+      if (o.per[1]) y = (y % nby + nby) % nby;
+      else if (y < 0 || y >= nby) return 0;
+      if (o.per[2]) z = (z % nbz + nbz) % nbz;
+      else if (z < 0 || z >= nbz) return 0;
+      const int64_t b = ((int64_t)z * nby + y) * nbx + x;
+      return o.box_start[b + 1] - o.box_start[b];
+    };
+    std::vector<int32_t> prp(n + 1, 0);
+    std::vector<int32_t> runlen((size_t)n * W);
+    int64_t tot = 0;
+    for (int64_t r = 0; r < n; ++r) {
+      const uint32_t bc = [&] {
+        uint32_t v;
+        std::memcpy(&v, &o.pos4[4 * r + 3], 4);
+        return v;
+      }();
+      const int bx = bc & 1023, by = (bc >> 10) & 1023, bz = (bc >> 20) & 1023;
+      int64_t rowlen = 0;
+      prp[r] = (int32_t)tot;
+      for (int dx = 0; dx < W; ++dx) {
+        int64_t len = 0;
+        for (int dz = -rb; dz <= rb; ++dz)
+          for (int dy = -rb; dy <= rb; ++dy) len += cnt(bx + dx - rb, by + dy, bz + dz);
+        runlen[(size_t)r * W + dx] = (int32_t)len;
+        rowlen += len;
+        tot += (len + 3) & ~(int64_t)3;
+      }
+      if (rowlen != o.p_rowptr[r + 1] - o.p_rowptr[r])
+        return set_err(c, PMFEM_EGRID, "precorrection row does not match its near boxes");
+      if (tot > 2147483647LL) return set_err(c, PMFEM_ENOMEM, "padded precorrection too large");
+    }
+    prp[n] = (int32_t)tot;
+    std::vector<float> pv((size_t)tot + 4, 0.f);
+    for (int64_t r = 0; r < n; ++r) {
+      int64_t src = o.p_rowptr[r], dst = prp[r];
+      for (int dx = 0; dx < W; ++dx) {
+        const int32_t len = runlen[(size_t)r * W + dx];
+        std::memcpy(&pv[dst], &o.p_val[src], (size_t)len * sizeof(float));
+        src += len;
+        dst += (len + 3) & ~3;
+      }
+    }
+    if ((rc = upload(c, &d->prp, prp.data(), n + 1))) return rc;
+    if ((rc = upload(c, &d->pv, pv.data(), pv.size()))) return rc;
+    d->nnz_p_dev = tot;
+  }
   if ((rc = upload(c, &d->khat, o.khat.data(), o.khat.size()))) return rc;
   auto tx = twiddles(o.M[0]), ty = twiddles(o.M[1]), tz = twiddles(o.M[2]);
   if ((rc = upload(c, &d->twx, tx.data(), tx.size()))) return rc;

@@ -429,31 +429,39 @@ __global__ void __launch_bounds__(128) k_anterp_line(
 }
 
 // ---------------------------------------------------------------------------
-// LDS radix-2 FFT on `lines` lines of length n stored contiguously in LDS in
-// bit-reversed order; decimation in time, natural-order output.
+// LDS radix-2 FFT on `lines` lines of length n, lines `stride` elements apart
+// (a stride of n + 1 keeps column-wise access free of bank conflicts), input
+// in bit-reversed order; decimation in time, natural-order output. lds_fft is
+// the contiguous case.
 
-__device__ void lds_fft(float2* buf, int n, int logn, int lines, const float2* tw, float sign) {
-  int half_n = n >> 1;
-  int total = lines * half_n;
+__device__ void lds_fft_s(float2* buf, int n, int logn, int lines, int stride, const float2* tw,
+                          float sign) {
+  // radix-2 decimation in time; n = 2^logn, so every index split is a shift
+  const int lh = logn - 1;  // log2(n / 2)
+  const int total = lines << lh;
   for (int s = 1; s <= logn; ++s) {
-    int half = 1 << (s - 1);
-    int tstep = n >> s;
+    const int ls = s - 1;  // log2(half)
+    const int half = 1 << ls;
+    const int tsh = logn - s;  // log2(twiddle step)
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-      int line = idx / half_n;
-      int j = idx - line * half_n;
-      int grp = j / half;
-      int k = j - grp * half;
-      int i0 = line * n + grp * 2 * half + k;
-      int i1 = i0 + half;
-      float2 w = tw[k * tstep];
+      const int line = idx >> lh;
+      const int j = idx & ((1 << lh) - 1);
+      const int k = j & (half - 1);
+      const int i0 = line * stride + ((j >> ls) << (ls + 1)) + k;
+      const int i1 = i0 + half;
+      float2 w = tw[k << tsh];
       w.y *= sign;
-      float2 a = buf[i0], b = buf[i1];
-      float2 t = make_float2(b.x * w.x - b.y * w.y, b.x * w.y + b.y * w.x);
+      const float2 a = buf[i0], b = buf[i1];
+      const float2 t = make_float2(b.x * w.x - b.y * w.y, b.x * w.y + b.y * w.x);
       buf[i0] = make_float2(a.x + t.x, a.y + t.y);
       buf[i1] = make_float2(a.x - t.x, a.y - t.y);
     }
     __syncthreads();
   }
+}
+
+__device__ void lds_fft(float2* buf, int n, int logn, int lines, const float2* tw, float sign) {
+  lds_fft_s(buf, n, logn, lines, n, tw, sign);
 }
 
 __device__ __forceinline__ int bitrev(int i, int logn) { return (int)(__brev((unsigned)i) >> (32 - logn)); }
@@ -499,31 +507,13 @@ __global__ void __launch_bounds__(256) k_r2c_x(GridParams g, const float* __rest
   }
 }
 
-// LDS radix-2 FFT as lds_fft, lines `stride` elements apart (a stride of
-// n + 1 keeps column-wise access free of bank conflicts).
-__device__ void lds_fft_s(float2* buf, int n, int logn, int lines, int stride, const float2* tw,
-                          float sign) {
-  const int half_n = n >> 1;
-  const int total = lines * half_n;
-  for (int s = 1; s <= logn; ++s) {
-    const int half = 1 << (s - 1);
-    const int tstep = n >> s;
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-      const int line = idx / half_n;
-      const int j = idx - line * half_n;
-      const int grp = j / half;
-      const int k = j - grp * half;
-      const int i0 = line * stride + grp * 2 * half + k;
-      const int i1 = i0 + half;
-      float2 w = tw[k * tstep];
-      w.y *= sign;
-      const float2 a = buf[i0], b = buf[i1];
-      const float2 t = make_float2(b.x * w.x - b.y * w.y, b.x * w.y + b.y * w.x);
-      buf[i0] = make_float2(a.x + t.x, a.y + t.y);
-      buf[i1] = make_float2(a.x - t.x, a.y - t.y);
-    }
-    __syncthreads();
-  }
+// n / d for 0 <= n < 2^22 and 1 <= d < 2^10 without an integer divide: the
+// float quotient is off by at most one, which the correction removes.
+__device__ __forceinline__ int fdiv(int n, int d, float inv_d) {
+  int q = (int)((float)n * inv_d);
+  if (q * d > n) --q;
+  else if ((q + 1) * d <= n) ++q;
+  return q;
 }
 
 // Forward transform of one z-plane held whole in LDS: real rows y < Ny are
@@ -545,10 +535,11 @@ __global__ void __launch_bounds__(1024) k_fft_xy_fwd(GridParams g, const float* 
   for (int i = threadIdx.x; i < Mx / 2; i += blockDim.x) tx[i] = twx[i];
   for (int i = threadIdx.x; i < My / 2; i += blockDim.x) ty[i] = twy[i];
   const float* Qz = Q + (int64_t)z * Ny * Nx;
+  const float invHx = 1.0f / (float)Hx;
   batched<8>(
       pairs * Mx,
       [&](int idx) {
-        const int li = idx / Mx, x = idx - li * Mx, y = 2 * li;
+        const int li = idx >> lx, x = idx & (Mx - 1), y = 2 * li;
         float2 v = make_float2(0.f, 0.f);
         if (x < Nx) {
           v.x = Qz[(int64_t)y * Nx + x];
@@ -557,18 +548,19 @@ __global__ void __launch_bounds__(1024) k_fft_xy_fwd(GridParams g, const float* 
         return v;
       },
       [&](int idx, float2 v) {
-        const int li = idx / Mx, x = idx - li * Mx;
+        const int li = idx >> lx, x = idx & (Mx - 1);
         A[li * Mx + bitrev(x, lx)] = v;
       });
   // rows Ny..My-1 of the columns are the zero padding
   for (int idx = threadIdx.x; idx < Hx * (My - 2 * pairs); idx += blockDim.x) {
-    const int k = idx % Hx, y = 2 * pairs + idx / Hx;
+    const int yq = fdiv(idx, Hx, invHx);
+    const int k = idx - yq * Hx, y = 2 * pairs + yq;
     C[k * cs + bitrev(y, ly)] = make_float2(0.f, 0.f);
   }
   __syncthreads();
   lds_fft_s(A, Mx, lx, pairs, Mx, tx, 1.0f);
   for (int idx = threadIdx.x; idx < pairs * Hx; idx += blockDim.x) {
-    const int li = idx / Hx, k = idx - li * Hx, y = 2 * li;
+    const int li = fdiv(idx, Hx, invHx), k = idx - li * Hx, y = 2 * li;
     const float2 a = A[li * Mx + k];
     const float2 b = A[li * Mx + ((Mx - k) & (Mx - 1))];
     // X_y = (Z[k] + conj Z[-k]) / 2, X_{y+1} = (Z[k] - conj Z[-k]) / (2i)
@@ -580,7 +572,7 @@ __global__ void __launch_bounds__(1024) k_fft_xy_fwd(GridParams g, const float* 
   lds_fft_s(C, My, ly, Hx, cs, ty, 1.0f);
   float2* Sz = spec + (int64_t)z * My * Hx;
   for (int idx = threadIdx.x; idx < My * Hx; idx += blockDim.x) {
-    const int ky = idx / Hx, k = idx - ky * Hx;
+    const int ky = fdiv(idx, Hx, invHx), k = idx - ky * Hx;
     Sz[idx] = C[k * cs + ky];
   }
 }
@@ -603,16 +595,17 @@ __global__ void __launch_bounds__(1024) k_fft_yx_inv(GridParams g, const float2*
   for (int i = threadIdx.x; i < Mx / 2; i += blockDim.x) tx[i] = twx[i];
   for (int i = threadIdx.x; i < My / 2; i += blockDim.x) ty[i] = twy[i];
   const float2* Sz = spec + (int64_t)z * My * Hx;
+  const float invHx = 1.0f / (float)Hx;
   batched<8>(
       My * Hx, [&](int idx) { return Sz[idx]; },
       [&](int idx, float2 v) {
-        const int ky = idx / Hx, k = idx - ky * Hx;
+        const int ky = fdiv(idx, Hx, invHx), k = idx - ky * Hx;
         C[k * cs + bitrev(ky, ly)] = v;
       });
   __syncthreads();
   lds_fft_s(C, My, ly, Hx, cs, ty, -1.0f);
   for (int idx = threadIdx.x; idx < pairs * Mx; idx += blockDim.x) {
-    const int li = idx / Mx, k = idx - li * Mx, y = 2 * li;
+    const int li = idx >> lx, k = idx & (Mx - 1), y = 2 * li;
     const int kk = k <= Mx / 2 ? k : Mx - k;
     float2 a = C[kk * cs + y];
     float2 b = y + 1 < Ny ? C[kk * cs + y + 1] : make_float2(0.f, 0.f);
@@ -626,8 +619,9 @@ __global__ void __launch_bounds__(1024) k_fft_yx_inv(GridParams g, const float2*
   __syncthreads();
   lds_fft_s(A, Mx, lx, pairs, Mx, tx, -1.0f);
   float* Uz = U + (int64_t)z * Ny * Nx;
+  const float invNx = 1.0f / (float)Nx;
   for (int idx = threadIdx.x; idx < pairs * Nx; idx += blockDim.x) {
-    const int li = idx / Nx, x = idx - li * Nx, y = 2 * li;
+    const int li = fdiv(idx, Nx, invNx), x = idx - li * Nx, y = 2 * li;
     const float2 v = A[li * Mx + x];
     Uz[(int64_t)y * Nx + x] = v.x;
     if (y + 1 < Ny) Uz[(int64_t)(y + 1) * Nx + x] = v.y;
@@ -775,7 +769,7 @@ __global__ void __launch_bounds__(256) k_c2r_x(GridParams g, const float2* __res
 // range are staged too. Each group of G lanes then takes one observer row:
 // u_n = W_n U + sum over the runs of P q + u_Z, in a fixed order.
 
-constexpr int kIcLanes = 8;
+constexpr int kIcLanes = 8;  // lanes per observer row (8 x 16 B = one 128 B line per load)
 
 template <int WT>
 __global__ void __launch_bounds__(256) k_interp_tile(
@@ -802,7 +796,8 @@ __global__ void __launch_bounds__(256) k_interp_tile(
   for (int i = tid; i < segw; i += T) s_seg[i] = wseg[(int64_t)w * segw + i];
   const int l0 = lstart[w];
   const int n = min(lstart[w + 1] - l0, pl.qcap);
-  // stage the listed charges, K loads in flight
+  // stage the listed charges, K loads in flight; 4 zeros after them
+  if (tid < 4) s_q[n + tid] = 0.f;
   {
     constexpr int K = 8;
     for (int e0 = tid; e0 < n; e0 += K * T) {
@@ -840,73 +835,99 @@ __global__ void __launch_bounds__(256) k_interp_tile(
   const int nrows = s_seg[tz];
   const int* s_first = s_seg + pl.tz + 1;
 
-  // rows: G lanes per row
+  // rows: G lanes per row; the next row's descriptors are fetched while the
+  // current row is formed
   constexpr int G = kIcLanes;
-  constexpr int W = WT;  // 2 r_b + 1
+  constexpr int W = WT;                 // 2 r_b + 1
+  constexpr int RK = WT <= 5 ? 2 : 1;  // float4 chunks per lane per run held in registers
   const int lane = tid & (G - 1), grp = tid / G, ngrp = T / G;
   const bool cubic = p == 3;
-  // lane -> stencil points (ax, ay) = (l % 4, l / 4) for l = lane, lane + G (p = 3)
-  const Cubic cxa = cubic_basis(lane & 3), cya = cubic_basis(lane >> 2);
-  const Cubic cxb = cubic_basis((lane + G) & 3), cyb = cubic_basis((lane + G) >> 2);
-  const Cubic cz0 = cubic_basis(0), cz1 = cubic_basis(1), cz2 = cubic_basis(2), cz3 = cubic_basis(3);
-  for (int sl = grp; sl < nrows; sl += ngrp) {
+  auto fetch = [&](int sl, uint32_t* dsc, int& pp, float4& xi, int& r) {
     int kz = 0;
     while (kz + 1 < tz && s_seg[kz + 1] <= sl) ++kz;
-    const int r = s_first[kz] + (sl - s_seg[kz]);
-    // run descriptors and all run values in flight at once
-    constexpr int RK = WT <= 5 ? 8 : 4;  // values per lane per run held in registers
-    uint32_t dsc[WT];
+    r = s_first[kz] + (sl - s_seg[kz]);
 #pragma unroll
     for (int dx = 0; dx < WT; ++dx) dsc[dx] = rdesc[(int64_t)r * W + dx];
-    int pp = prp[r];
-    const float4 xi = pos4[r];
+    pp = prp[r];
+    xi = pos4[r];
+  };
+  uint32_t dsc[WT];
+  int pp = 0, r = 0;
+  float4 xi = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (grp < nrows) fetch(grp, dsc, pp, xi, r);
+  for (int sl = grp; sl < nrows; sl += ngrp) {
+    // all run values of the row in flight at once: each run's values start
+    // 16-byte aligned (runs are padded with zeros to a multiple of 4)
     int po[WT];
+    {
+      int acc_p = pp;
 #pragma unroll
-    for (int dx = 0; dx < WT; ++dx) {
-      po[dx] = pp;
-      pp += (int)(dsc[dx] >> 16);
+      for (int dx = 0; dx < WT; ++dx) {
+        po[dx] = acc_p;
+        acc_p += ((int)(dsc[dx] >> 16) + 3) & ~3;
+      }
     }
-    float v[WT][RK];
+    float4 v[WT][RK];
 #pragma unroll
     for (int dx = 0; dx < WT; ++dx)
 #pragma unroll
       for (int t = 0; t < RK; ++t) {
-        const int c = lane + G * t;
-        v[dx][t] = c < (int)(dsc[dx] >> 16) ? pval[po[dx] + c] : 0.f;
+        const int c = 4 * (lane + G * t);
+        v[dx][t] = c < (int)(dsc[dx] >> 16)
+                       ? *reinterpret_cast<const float4*>(pval + po[dx] + c)
+                       : make_float4(0.f, 0.f, 0.f, 0.f);
       }
+    uint32_t dn[WT];
+    int ppn = 0, rn = 0;
+    float4 xin = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (sl + ngrp < nrows) fetch(sl + ngrp, dn, ppn, xin, rn);
     float acc = 0.f;
 #pragma unroll
     for (int dx = 0; dx < WT; ++dx) {
       const int qs = (int)(dsc[dx] & 0xFFFFu), ln = (int)(dsc[dx] >> 16);
+      // the padding values are zero and the staged charges are padded with
+      // zeros, so the 4 products of a chunk need no per-value test
 #pragma unroll
       for (int t = 0; t < RK; ++t) {
-        const int c = lane + G * t;
-        if (c < ln) acc = fmaf(v[dx][t], s_q[qs + c], acc);
+        const int c = 4 * (lane + G * t);
+        if (c < ln) {
+          const float* sq = s_q + qs + c;
+          acc = fmaf(v[dx][t].x, sq[0], acc);
+          acc = fmaf(v[dx][t].y, sq[1], acc);
+          acc = fmaf(v[dx][t].z, sq[2], acc);
+          acc = fmaf(v[dx][t].w, sq[3], acc);
+        }
       }
-      for (int c = lane + G * RK; c < ln; c += G) acc = fmaf(pval[po[dx] + c], s_q[qs + c], acc);
+      for (int c = 4 * (lane + G * RK); c < ln; c += 4 * G) {
+        const float4 pv4 = *reinterpret_cast<const float4*>(pval + po[dx] + c);
+        const float* sq = s_q + qs + c;
+        acc = fmaf(pv4.x, sq[0], acc);
+        acc = fmaf(pv4.y, sq[1], acc);
+        acc = fmaf(pv4.z, sq[2], acc);
+        acc = fmaf(pv4.w, sq[3], acc);
+      }
     }
     // W U from the staged lines; the box of the row from its packed coordinates
     const uint32_t bc = __float_as_uint(xi.w);
     const int bx = (int)(bc & 1023u), bz = (int)((bc >> 20) & 1023u);
-    const int kx = bx - x0;
-    const int relx = g.per[0] ? kx : box_stencil_start(bx, g.N[0], p, 0) - ux0;
+    const int relx = g.per[0] ? bx - x0 : box_stencil_start(bx, g.N[0], p, 0) - ux0;
     const int relz = g.per[2] ? bz - z0 : box_stencil_start(bz, g.N[2], p, 0) - stz;
     if (cubic) {
+      // lane -> ax = lane % 4 and the two y points 2 (lane / 4), 2 (lane / 4) + 1
       const int zs = p1 * pl.ux;
-      const float* su = s_U + (relz * p1) * pl.ux + relx;
-      const float wz0 = cubic_eval(cz0, xi.z), wz1 = cubic_eval(cz1, xi.z);
-      const float wz2 = cubic_eval(cz2, xi.z), wz3 = cubic_eval(cz3, xi.z);
-      {
-        const float* s0 = su + (lane >> 2) * pl.ux + (lane & 3);
-        const float wt = cubic_eval(cxa, xi.x) * cubic_eval(cya, xi.y);
-        acc = fmaf(wt, wz0 * s0[0] + wz1 * s0[zs] + wz2 * s0[2 * zs] + wz3 * s0[3 * zs], acc);
+      const int ax = lane & 3, ay0 = (lane >> 2) * 2;
+      const float* su = s_U + (relz * p1 + ay0) * pl.ux + relx + ax;
+      float wz[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) wz[a] = cubic_eval(cubic_basis(a), xi.z);
+      float sy = 0.f;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const float* s0 = su + i * pl.ux;
+        const float t = wz[0] * s0[0] + wz[1] * s0[zs] + wz[2] * s0[2 * zs] + wz[3] * s0[3 * zs];
+        sy = fmaf(cubic_eval(cubic_basis(ay0 + i), xi.y), t, sy);
       }
-      {
-        const int l = lane + G;
-        const float* s0 = su + (l >> 2) * pl.ux + (l & 3);
-        const float wt = cubic_eval(cxb, xi.x) * cubic_eval(cyb, xi.y);
-        acc = fmaf(wt, wz0 * s0[0] + wz1 * s0[zs] + wz2 * s0[2 * zs] + wz3 * s0[3 * zs], acc);
-      }
+      acc = fmaf(cubic_eval(cubic_basis(ax), xi.x), sy, acc);
     } else {
       const int nst = p1 * p1 * p1;
       for (int l = lane; l < nst; l += G) {
@@ -917,6 +938,11 @@ __global__ void __launch_bounds__(256) k_interp_tile(
     }
     acc = group_sum<G>(acc);
     if (lane == 0) u[r] = acc + uz[r];
+#pragma unroll
+    for (int dx = 0; dx < WT; ++dx) dsc[dx] = dn[dx];
+    pp = ppn;
+    xi = xin;
+    r = rn;
   }
 }
 
