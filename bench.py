@@ -45,7 +45,8 @@ def kernel_bytes(ctx, names):
     s_full = float(N[2] * M[1]) * hx * 8    # half-spectrum, all My rows
     khat = hx * M[1] * M[2] * 4
     fam = {
-        "k_local": n * (8 + 12 + 4 + 4) + nL * 16 + nZ * 16,
+        "k_charges": n * (4 + 12 + 4) + nL * 16,
+        "k_zcorr": n * (4 + 12 + 4) + nZ * 16,
         "k_anterp": n * (4 + 16) + nbox * 4 + ng * 4,
         "k_r2c_x": ng * 4 + s_in,
         "k_fft_y_fwd": s_in + s_full,

@@ -22,7 +22,9 @@
  *  - Host arrays passed in are copied; the caller keeps ownership.
  *  - Device arrays (m_dev, h_dev, ...) belong to the caller; they must hold
  *    N' rows in the library's unknown order (see pmfem_query) and live on
- *    the context's device. Work is enqueued on the context's stream and the
+ *    the context's device. Work is enqueued on the context's stream (part
+ *    of it on one internal stream of the same device that is forked from
+ *    and joined back to the context's stream within each call) and the
  *    call returns without synchronising; device errors surface as
  *    PMFEM_EHIP at the latest on the next call.
  *  - A context is not re-entrant: calls on one context must not overlap.

@@ -32,14 +32,16 @@ struct pmfem_dev {
   bool ic_seg = false;        // false: the narrow tiles
   bool fft_plane = false;  // x and y transforms of a whole z-plane in one kernel
   size_t fft_plane_lds = 0;
-  const char* kname[9] = {};  // kernel in each profiling slot
+  const char* kname[10] = {};  // kernel in each profiling slot
+  hipStream_t side = nullptr;   // second stream: element correction beside the grid steps
+  hipEvent_t fork = nullptr, join = nullptr;
   int2 *brx = nullptr, *bry = nullptr, *brz = nullptr;
   int32_t *lrp = nullptr, *lcol = nullptr;
   int4* drec = nullptr;   // charge operator D: {column, Dx, Dy, Dz}
   float4* lgl = nullptr;  // {Gx, Gy, Gz, L}
   int32_t* zrp = nullptr;
   int4* zrec = nullptr;   // element correction Z0: {column, Zx, Zy, Zz}
-  int lanes = 16;         // lanes per row of k_local / k_grad
+  int lanes = 16;         // lanes per row of k_rowdot3 / k_grad
   int32_t* prp = nullptr;  // device precorrection rows (runs padded to 4 values)
   float* pv = nullptr;
   int64_t nnz_p_dev = 0;
@@ -61,7 +63,7 @@ struct pmfem_dev {
 
 namespace {
 
-constexpr int kNumKernels = 9;
+constexpr int kNumKernels = 10;
 int set_err(pmfem_ctx* c, int code, const std::string& m) {
   if (c) c->err = m;
   return code;
@@ -94,8 +96,12 @@ int upload(pmfem_ctx* c, T** p, const void* src, size_t count) {
 
 void free_dev(pmfem_ctx* c) {
   if (!c->dev) return;
+  if (c->dev->side) (void)hipStreamSynchronize(c->dev->side);
   for (void* p : c->dev->allocs) (void)hipFree(p);
   for (hipEvent_t e : c->dev->ev) (void)hipEventDestroy(e);
+  if (c->dev->fork) (void)hipEventDestroy(c->dev->fork);
+  if (c->dev->join) (void)hipEventDestroy(c->dev->join);
+  if (c->dev->side) (void)hipStreamDestroy(c->dev->side);
   delete c->dev;
   c->dev = nullptr;
 }
@@ -152,10 +158,10 @@ int select_variants(pmfem_ctx* c) {
   d->ant_line = va == 0 ? d->ant_ok : va == 2;
   d->ic_seg = vi == 0 ? d->ic_ok : vi == 2;
   d->fft_plane = vf == 0 ? d->fft_ok : vf == 2;
-  const char* names_split[9] = {"k_local",     "k_anterp",    "k_r2c_x",
-                                "k_fft_y_fwd", "k_fft_z_mul", "k_fft_y_inv",
-                                "k_c2r_x",     "k_interp",    "k_grad"};
-  for (int k = 0; k < 9; ++k) d->kname[k] = names_split[k];
+  const char* names_split[10] = {"k_charges",   "k_anterp",    "k_r2c_x",     "k_fft_y_fwd",
+                                 "k_fft_z_mul", "k_fft_y_inv", "k_c2r_x",     "k_interp",
+                                 "k_grad",      "k_zcorr"};
+  for (int k = 0; k < 10; ++k) d->kname[k] = names_split[k];
   if (d->fft_plane) {
     d->kname[2] = "k_fft_xy_fwd";
     d->kname[3] = "-";
@@ -443,6 +449,12 @@ bool plan_interp(const HostOps& o, int max_xs, IcPlan& pl) {
 int upload_all(pmfem_ctx* c) {
   HostOps& o = c->ops;
   pmfem_dev* d = c->dev;
+  {
+    hipError_t e = hipStreamCreateWithFlags(&d->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&d->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&d->join, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_err(c, e, "side stream");
+  }
   const int64_t n = o.n_unk;
   d->n = n;
   for (int a = 0; a < 3; ++a) {
@@ -693,19 +705,28 @@ int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const doubl
     if (ev) (void)hipEventRecord(ev[2 * k + which], s);
   };
   const int T = 256;
-  if (with_ms) {
-    mark(0, 0);
+  auto rowdot3 = [&](hipStream_t st, const int32_t* rp, const int4* rec, float* out) {
     const dim3 grid((unsigned)((n * d->lanes + T - 1) / T));
     if (d->lanes == 4)
-      hipLaunchKernelGGL(k_local<4>, grid, dim3(T), 0, s, n, m, d->lrp, d->drec, d->zrp,
-                         d->zrec, d->q, d->uz);
+      hipLaunchKernelGGL(k_rowdot3<4>, grid, dim3(T), 0, st, n, m, rp, rec, out);
     else if (d->lanes == 8)
-      hipLaunchKernelGGL(k_local<8>, grid, dim3(T), 0, s, n, m, d->lrp, d->drec, d->zrp,
-                         d->zrec, d->q, d->uz);
+      hipLaunchKernelGGL(k_rowdot3<8>, grid, dim3(T), 0, st, n, m, rp, rec, out);
     else
-      hipLaunchKernelGGL(k_local<16>, grid, dim3(T), 0, s, n, m, d->lrp, d->drec, d->zrp,
-                         d->zrec, d->q, d->uz);
+      hipLaunchKernelGGL(k_rowdot3<16>, grid, dim3(T), 0, st, n, m, rp, rec, out);
+  };
+  if (with_ms) {
+    mark(0, 0);
+    rowdot3(s, d->lrp, d->drec, d->q);
     mark(0, 1);
+    // element correction on the side stream, beside anterpolation and the
+    // FFT (both bound by latency and ALU rather than HBM); joined before
+    // interpolation
+    (void)hipEventRecord(d->fork, s);
+    (void)hipStreamWaitEvent(d->side, d->fork, 0);
+    if (ev) (void)hipEventRecord(ev[2 * 9], d->side);
+    rowdot3(d->side, d->zrp, d->zrec, d->uz);
+    if (ev) (void)hipEventRecord(ev[2 * 9 + 1], d->side);
+    (void)hipEventRecord(d->join, d->side);
   }
   if (with_ms) {
     const int64_t ntiles = (int64_t)((g.N[0] + kAntTX - 1) / kAntTX) *
@@ -723,6 +744,7 @@ int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const doubl
     }
     mark(1, 1);
     convolve(d, s, d->grid, d->grid, mark);
+    (void)hipStreamWaitEvent(s, d->join, 0);
     mark(7, 0);
     {
       const IcPlan& pl = d->ic_seg ? d->icp : d->icp_small;
@@ -938,7 +960,7 @@ int pmfem_query(pmfem_ctx* c, int64_t* n_unknowns, int64_t* unknown_of_node,
     const double spec = (double)o.N[2] * o.M[1] * hx * 8.0;
     const double khat = hx * o.M[1] * o.M[2] * 4.0;
     double b = 0;
-    b += n * (8 + 12 + 4 + 4) + nL * (4 + 12) + nZ * (4 + 12);            // k_local
+    b += n * (8 + 12 + 4 + 4) + nL * (4 + 12) + nZ * (4 + 12);            // k_rowdot3 x2
     b += n * (16 + 4) + ng * 4 + (double)o.box_start.size() * 4;       // k_anterp
     b += ng * 4 + spec;                                                  // r2c
     b += 2 * spec;                                                       // y fwd

@@ -49,8 +49,8 @@ struct AntPlan {
 };
 
 template <int G>
-__global__ void k_local(int64_t n, const float* m, const int32_t* rp, const int4* drec,
-                        const int32_t* zrp, const int4* zrec, float* q, float* uz);
+__global__ void k_rowdot3(int64_t n, const float* m, const int32_t* rp, const int4* rec,
+                          float* out);
 __global__ void k_anterp(GridParams g, const float* q, const float4* pos4,
                          const int32_t* box_start, const int2* brx, const int2* bry,
                          const int2* brz, float* Q);

@@ -1,14 +1,13 @@
 // gfx950 kernels of the PM-FEM effective-field evaluation.
 //
 // One H_eff evaluation (paper Eqs. heff, hex, hms_d1 - hms_d3):
-//   k_local        q = D m (Eq. hms_d1), u_Z = Z0 m (Eq. hms_d2b)
-//   k_anterp       Q = W^T q                      (Sec. 3.2.2, step 1)
-//   k_r2c_x        real-to-complex FFT along x    (step 2)
-//   k_fft_y        FFT along y (forward)
+//   k_rowdot3      q = D m (Eq. hms_d1); on a second stream u_Z = Z0 m (Eq. hms_d2b)
+//   k_anterp_line  Q = W^T q                      (Sec. 3.2.2, step 1; k_anterp: tile form)
+//   k_fft_xy_fwd   real-to-complex FFT along x, FFT along y, per z-plane (step 2)
 //   k_fft_z_mul    FFT along z, multiply by the PGF spectrum, inverse along z
-//   k_fft_y        FFT along y (inverse)
-//   k_c2r_x        complex-to-real FFT along x -> U = (1/4 pi) K * Q
-//   k_interp_corr  u = W U + P q + u_Z            (steps 3 and 4)
+//   k_fft_yx_inv   inverse FFT along y, complex-to-real along x -> U = (1/4 pi) K * Q
+//                  (k_r2c_x, k_fft_y, k_c2r_x: the same passes one axis at a time)
+//   k_interp_tile  u = W U + P q + u_Z            (steps 3 and 4)
 //   k_grad         H = L m - G u (+ H_applied)    (Eqs. hex/lapl_2, hms_d3)
 // All arithmetic is FP32; every reduction is done in a fixed order inside a
 // wavefront or a thread, so results are bitwise reproducible (no atomics).
@@ -130,54 +129,38 @@ __device__ __forceinline__ float group_sum(float v) {
 }
 
 // ---------------------------------------------------------------------------
-// charges and element-exact correction: G lanes per row
-//   q_n   = sum_k D_nk . m_k          (local pattern)
-//   u_Z,n = sum_j Z0_nj . m_j          (element-correction pattern)
-// Each entry is one 16-byte record {column, x, y, z} (one vector load).
+// charges and element-exact correction, G lanes per row, one 16-byte record
+// {column, x, y, z} per entry (one vector load):
+//   k_charges:  q_n   = sum_k D_nk . m_k     (local pattern)
+//   k_zcorr:    u_Z,n = sum_j Z0_nj . m_j     (element-correction pattern)
+// The two are independent; the library runs k_zcorr on a second stream,
+// beside anterpolation and the FFT.
 
 template <int G>
-__global__ void __launch_bounds__(256) k_local(int64_t n, const float* __restrict__ m,
-                                               const int32_t* __restrict__ rp,
-                                               const int4* __restrict__ drec,
-                                               const int32_t* __restrict__ zrp,
-                                               const int4* __restrict__ zrec,
-                                               float* __restrict__ q, float* __restrict__ uz) {
+__global__ void __launch_bounds__(256) k_rowdot3(int64_t n, const float* __restrict__ m,
+                                                 const int32_t* __restrict__ rp,
+                                                 const int4* __restrict__ rec,
+                                                 float* __restrict__ out) {
   const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   const int lane = threadIdx.x & (G - 1);
   if (row >= n) return;  // whole groups leave together
-  float qq = 0.f, uu = 0.f;
+  float acc = 0.f;
   const int e0 = rp[row], e1 = rp[row + 1];
-  const int z0 = zrp[row], z1 = zrp[row + 1];
 #pragma unroll 2
   for (int e = e0 + lane; e < e1; e += G) {
-    const int4 r = drec[e];
+    const int4 r = rec[e];
     const float* mk = m + 3 * (int64_t)r.x;
-    qq = fmaf(__int_as_float(r.y), mk[0], qq);
-    qq = fmaf(__int_as_float(r.z), mk[1], qq);
-    qq = fmaf(__int_as_float(r.w), mk[2], qq);
+    acc = fmaf(__int_as_float(r.y), mk[0], acc);
+    acc = fmaf(__int_as_float(r.z), mk[1], acc);
+    acc = fmaf(__int_as_float(r.w), mk[2], acc);
   }
-#pragma unroll 2
-  for (int e = z0 + lane; e < z1; e += G) {
-    const int4 r = zrec[e];
-    const float* mk = m + 3 * (int64_t)r.x;
-    uu = fmaf(__int_as_float(r.y), mk[0], uu);
-    uu = fmaf(__int_as_float(r.z), mk[1], uu);
-    uu = fmaf(__int_as_float(r.w), mk[2], uu);
-  }
-  qq = group_sum<G>(qq);
-  uu = group_sum<G>(uu);
-  if (lane == 0) {
-    q[row] = qq;
-    uz[row] = uu;
-  }
+  acc = group_sum<G>(acc);
+  if (lane == 0) out[row] = acc;
 }
 
-template __global__ void k_local<4>(int64_t, const float*, const int32_t*, const int4*,
-                                    const int32_t*, const int4*, float*, float*);
-template __global__ void k_local<8>(int64_t, const float*, const int32_t*, const int4*,
-                                    const int32_t*, const int4*, float*, float*);
-template __global__ void k_local<16>(int64_t, const float*, const int32_t*, const int4*,
-                                     const int32_t*, const int4*, float*, float*);
+template __global__ void k_rowdot3<4>(int64_t, const float*, const int32_t*, const int4*, float*);
+template __global__ void k_rowdot3<8>(int64_t, const float*, const int32_t*, const int4*, float*);
+template __global__ void k_rowdot3<16>(int64_t, const float*, const int32_t*, const int4*, float*);
 
 // ---------------------------------------------------------------------------
 // anterpolation: one workgroup per tile of kAntTX x kAntTY x kAntTZ grid
