@@ -13,6 +13,10 @@
 
 using namespace pmfem;
 
+#ifndef PMFEM_IC_LDS_BUDGET
+#define PMFEM_IC_LDS_BUDGET 24576  // LDS bytes per interpolation tile
+#endif
+
 struct pmfem_dev {
   int64_t n = 0;
   GridParams g{};
@@ -428,7 +432,7 @@ bool plan_interp(const HostOps& o, int max_xs, IcPlan& pl) {
     pl.o_seg = (int)off;
     off += al((int64_t)(2 * tz + 1) * 4);
     (void)colmax;
-    if (off <= 40960 && qcap < 65536) {
+    if (off <= PMFEM_IC_LDS_BUDGET && qcap < 65536) {
       pl.xs = xs;
       pl.tz = tz;
       pl.nsx = nsx;
@@ -606,6 +610,8 @@ int upload_all(pmfem_ctx* c) {
     if ((rc = upload(c, &d->prp, prp.data(), n + 1))) return rc;
     if ((rc = upload(c, &d->pv, pv.data(), pv.size()))) return rc;
     d->nnz_p_dev = tot;
+    d->icp.plast = (int)tot;  // pv holds tot + 4 values
+    d->icp_small.plast = (int)tot;
   }
   if ((rc = upload(c, &d->khat, o.khat.data(), o.khat.size()))) return rc;
   auto tx = twiddles(o.M[0]), ty = twiddles(o.M[1]), tz = twiddles(o.M[2]);

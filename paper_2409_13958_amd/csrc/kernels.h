@@ -32,6 +32,7 @@ struct IcPlan {
   int qcap;      // staged source charges
   int rcap;      // observer rows per tile
   int ux, uzl;   // staged potential: points per line (xs + p), z-lines (tz + p)
+  int plast;     // last valid 4-value chunk start of the device matrix values
   int o_q, o_u, o_seg;  // LDS byte offsets
   int lds_bytes;
 };

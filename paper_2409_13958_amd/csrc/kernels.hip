@@ -752,7 +752,11 @@ __global__ void __launch_bounds__(256) k_c2r_x(GridParams g, const float2* __res
 // range are staged too. Each group of G lanes then takes one observer row:
 // u_n = W_n U + sum over the runs of P q + u_Z, in a fixed order.
 
-constexpr int kIcLanes = 8;  // lanes per observer row (8 x 16 B = one 128 B line per load)
+#ifndef PMFEM_IC_LANES
+#define PMFEM_IC_LANES 8
+#endif
+// lanes per observer row (8 x 16 B = one 128 B line per load); 4, 8 or 16
+constexpr int kIcLanes = PMFEM_IC_LANES;
 
 template <int WT>
 __global__ void __launch_bounds__(256) k_interp_tile(
@@ -822,9 +826,21 @@ __global__ void __launch_bounds__(256) k_interp_tile(
   // current row is formed
   constexpr int G = kIcLanes;
   constexpr int W = WT;                 // 2 r_b + 1
-  constexpr int RK = WT <= 5 ? 2 : 1;  // float4 chunks per lane per run held in registers
+#ifndef PMFEM_IC_RK
+#define PMFEM_IC_RK 2
+#endif
+  // float4 chunks per lane per run held in registers
+  constexpr int RK = WT <= 5 ? PMFEM_IC_RK : 1;
   const int lane = tid & (G - 1), grp = tid / G, ngrp = T / G;
   const bool cubic = p == 3;
+  // lane-constant parts of the interpolation weights (p = 3): lane -> x point
+  // ax = lane % 4 and the NY = 16 / G y points from ay0 = NY (lane / 4)
+  constexpr int NY = 16 / G;
+  const int ax = lane & 3, ay0 = (lane >> 2) * NY;
+  const Cubic cbx = cubic_basis(ax);
+  Cubic cby[NY];
+#pragma unroll
+  for (int i = 0; i < NY; ++i) cby[i] = cubic_basis(ay0 + i);
   auto fetch = [&](int sl, uint32_t* dsc, int& pp, float4& xi, int& r) {
     int kz = 0;
     while (kz + 1 < tz && s_seg[kz + 1] <= sl) ++kz;
@@ -850,15 +866,15 @@ __global__ void __launch_bounds__(256) k_interp_tile(
         acc_p += ((int)(dsc[dx] >> 16) + 3) & ~3;
       }
     }
+    // branch-free slots: a slot past its run reads a valid (finite) matrix
+    // chunk and pairs it with the zeros after the staged charges
     float4 v[WT][RK];
 #pragma unroll
     for (int dx = 0; dx < WT; ++dx)
 #pragma unroll
       for (int t = 0; t < RK; ++t) {
         const int c = 4 * (lane + G * t);
-        v[dx][t] = c < (int)(dsc[dx] >> 16)
-                       ? *reinterpret_cast<const float4*>(pval + po[dx] + c)
-                       : make_float4(0.f, 0.f, 0.f, 0.f);
+        v[dx][t] = *reinterpret_cast<const float4*>(pval + min(po[dx] + c, pl.plast));
       }
     uint32_t dn[WT];
     int ppn = 0, rn = 0;
@@ -873,13 +889,11 @@ __global__ void __launch_bounds__(256) k_interp_tile(
 #pragma unroll
       for (int t = 0; t < RK; ++t) {
         const int c = 4 * (lane + G * t);
-        if (c < ln) {
-          const float* sq = s_q + qs + c;
-          acc = fmaf(v[dx][t].x, sq[0], acc);
-          acc = fmaf(v[dx][t].y, sq[1], acc);
-          acc = fmaf(v[dx][t].z, sq[2], acc);
-          acc = fmaf(v[dx][t].w, sq[3], acc);
-        }
+        const float* sq = s_q + (c < ln ? qs + c : n);
+        acc = fmaf(v[dx][t].x, sq[0], acc);
+        acc = fmaf(v[dx][t].y, sq[1], acc);
+        acc = fmaf(v[dx][t].z, sq[2], acc);
+        acc = fmaf(v[dx][t].w, sq[3], acc);
       }
       for (int c = 4 * (lane + G * RK); c < ln; c += 4 * G) {
         const float4 pv4 = *reinterpret_cast<const float4*>(pval + po[dx] + c);
@@ -896,27 +910,24 @@ __global__ void __launch_bounds__(256) k_interp_tile(
     const int relx = g.per[0] ? bx - x0 : box_stencil_start(bx, g.N[0], p, 0) - ux0;
     const int relz = g.per[2] ? bz - z0 : box_stencil_start(bz, g.N[2], p, 0) - stz;
     if (cubic) {
-      // lane -> ax = lane % 4 and the two y points 2 (lane / 4), 2 (lane / 4) + 1
       const int zs = p1 * pl.ux;
-      const int ax = lane & 3, ay0 = (lane >> 2) * 2;
       const float* su = s_U + (relz * p1 + ay0) * pl.ux + relx + ax;
-      float wz[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) wz[a] = cubic_eval(cubic_basis(a), xi.z);
+      const float wz0 = cubic_eval(cubic_basis(0), xi.z), wz1 = cubic_eval(cubic_basis(1), xi.z);
+      const float wz2 = cubic_eval(cubic_basis(2), xi.z), wz3 = cubic_eval(cubic_basis(3), xi.z);
       float sy = 0.f;
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < NY; ++i) {
         const float* s0 = su + i * pl.ux;
-        const float t = wz[0] * s0[0] + wz[1] * s0[zs] + wz[2] * s0[2 * zs] + wz[3] * s0[3 * zs];
-        sy = fmaf(cubic_eval(cubic_basis(ay0 + i), xi.y), t, sy);
+        const float t = wz0 * s0[0] + wz1 * s0[zs] + wz2 * s0[2 * zs] + wz3 * s0[3 * zs];
+        sy = fmaf(cubic_eval(cby[i], xi.y), t, sy);
       }
-      acc = fmaf(cubic_eval(cubic_basis(ax), xi.x), sy, acc);
+      acc = fmaf(cubic_eval(cbx, xi.x), sy, acc);
     } else {
       const int nst = p1 * p1 * p1;
       for (int l = lane; l < nst; l += G) {
-        const int ax = l % p1, ay = (l / p1) % p1, az = l / (p1 * p1);
-        acc = fmaf(lagrange(ax, xi.x, p) * lagrange(ay, xi.y, p) * lagrange(az, xi.z, p),
-                   s_U[((relz + az) * p1 + ay) * pl.ux + relx + ax], acc);
+        const int lx = l % p1, ly = (l / p1) % p1, lz = l / (p1 * p1);
+        acc = fmaf(lagrange(lx, xi.x, p) * lagrange(ly, xi.y, p) * lagrange(lz, xi.z, p),
+                   s_U[((relz + lz) * p1 + ly) * pl.ux + relx + lx], acc);
       }
     }
     acc = group_sum<G>(acc);
