@@ -57,6 +57,8 @@ def kernel_bytes(ctx, names):
         "k_fft_yx_inv": s_full + ng * 4,
         "k_interp": n * (16 + 4 + 4 + 4 + 4) + ng * 4 + nP * 4,
         "k_grad": n * (4 + 12 + 4 + 12) + nL * 20,
+        "k_exch": n * (4 + 12 + 12) + nL * 8,
+        "k_gsum": n * (4 + 4 + 12 + 12) + nL * 16,
     }
     # every form of a stage moves the same algorithmic bytes (longest prefix wins)
     return {name: next(v for k, v in sorted(fam.items(), key=lambda kv: -len(kv[0]))

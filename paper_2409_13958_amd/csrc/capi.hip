@@ -36,16 +36,18 @@ struct pmfem_dev {
   bool ic_seg = false;        // false: the narrow tiles
   bool fft_plane = false;  // x and y transforms of a whole z-plane in one kernel
   size_t fft_plane_lds = 0;
-  const char* kname[10] = {};  // kernel in each profiling slot
+  const char* kname[11] = {};  // kernel in each profiling slot
   hipStream_t side = nullptr;   // second stream: element correction beside the grid steps
   hipEvent_t fork = nullptr, join = nullptr;
   int2 *brx = nullptr, *bry = nullptr, *brz = nullptr;
-  int32_t *lrp = nullptr, *lcol = nullptr;
+  int32_t* lrp = nullptr;
   int4* drec = nullptr;   // charge operator D: {column, Dx, Dy, Dz}
-  float4* lgl = nullptr;  // {Gx, Gy, Gz, L}
+  int2* lrec = nullptr;   // exchange: {column, L}
+  int4* grec = nullptr;   // gradient: {column, Gx, Gy, Gz}
   int32_t* zrp = nullptr;
   int4* zrec = nullptr;   // element correction Z0: {column, Zx, Zy, Zz}
-  int lanes = 16;         // lanes per row of k_rowdot3 / k_grad
+  int lanes_l = 4, lanes_z = 8;  // lanes per row on the local and element-correction patterns
+  int auto_l = 4, auto_z = 8;     // chosen from the mean row lengths
   int32_t* prp = nullptr;  // device precorrection rows (runs padded to 4 values)
   float* pv = nullptr;
   int64_t nnz_p_dev = 0;
@@ -67,7 +69,7 @@ struct pmfem_dev {
 
 namespace {
 
-constexpr int kNumKernels = 10;
+constexpr int kNumKernels = 11;
 int set_err(pmfem_ctx* c, int code, const std::string& m) {
   if (c) c->err = m;
   return code;
@@ -153,7 +155,8 @@ std::vector<int2> box_ranges(const HostOps& o, int a) {
 int select_variants(pmfem_ctx* c) {
   pmfem_dev* d = c->dev;
   const int va = c->variant[0], vi = c->variant[1], vf = c->variant[2];
-  d->lanes = c->variant[3] == 0 ? 16 : c->variant[3];
+  d->lanes_l = c->variant[3] == 0 ? d->auto_l : c->variant[3];
+  d->lanes_z = c->variant[3] == 0 ? d->auto_z : c->variant[3];
   if ((va == 2 && !d->ant_ok) || (vi == 2 && !d->ic_ok) || (vf == 2 && !d->fft_ok) ||
       (vi == 1 && !d->ic_small_ok))
     return set_err(c, PMFEM_EINVAL, "requested kernel form does not fit this problem");
@@ -162,10 +165,10 @@ int select_variants(pmfem_ctx* c) {
   d->ant_line = va == 0 ? d->ant_ok : va == 2;
   d->ic_seg = vi == 0 ? d->ic_ok : vi == 2;
   d->fft_plane = vf == 0 ? d->fft_ok : vf == 2;
-  const char* names_split[10] = {"k_charges",   "k_anterp",    "k_r2c_x",     "k_fft_y_fwd",
+  const char* names_split[11] = {"k_charges",   "k_anterp",    "k_r2c_x",     "k_fft_y_fwd",
                                  "k_fft_z_mul", "k_fft_y_inv", "k_c2r_x",     "k_interp",
-                                 "k_grad",      "k_zcorr"};
-  for (int k = 0; k < 10; ++k) d->kname[k] = names_split[k];
+                                 "k_gsum",      "k_zcorr",     "k_exch"};
+  for (int k = 0; k < 11; ++k) d->kname[k] = names_split[k];
   if (d->fft_plane) {
     d->kname[2] = "k_fft_xy_fwd";
     d->kname[3] = "-";
@@ -527,24 +530,36 @@ int upload_all(pmfem_ctx* c) {
   if ((rc = upload(c, &d->brz, bz.data(), bz.size()))) return rc;
   const int64_t nnzL = o.loc_rowptr[n];
   {
-    std::vector<int4> dr(nnzL);
-    std::vector<float4> gl(nnzL);
+    std::vector<int4> dr(nnzL), gr(nnzL);
+    std::vector<int2> lr(nnzL);
     for (int64_t e = 0; e < nnzL; ++e) {
       const float* v = &o.loc_val[8 * e];  // L, Dx, Dy, Dz, Gx, Gy, Gz, 0
-      int4 r;
-      r.x = o.loc_col[e];
+      int4 r, q4;
+      int2 l2;
+      r.x = q4.x = l2.x = o.loc_col[e];
       std::memcpy(&r.y, &v[1], 4);
       std::memcpy(&r.z, &v[2], 4);
       std::memcpy(&r.w, &v[3], 4);
+      std::memcpy(&q4.y, &v[4], 4);
+      std::memcpy(&q4.z, &v[5], 4);
+      std::memcpy(&q4.w, &v[6], 4);
+      std::memcpy(&l2.y, &v[0], 4);
       dr[e] = r;
-      gl[e] = make_float4(v[4], v[5], v[6], v[0]);
+      gr[e] = q4;
+      lr[e] = l2;
     }
     if ((rc = upload(c, &d->lrp, o.loc_rowptr.data(), n + 1))) return rc;
-    if ((rc = upload(c, &d->lcol, o.loc_col.data(), nnzL))) return rc;
     if ((rc = upload(c, &d->drec, dr.data(), nnzL))) return rc;
-    if ((rc = upload(c, &d->lgl, gl.data(), nnzL))) return rc;
+    if ((rc = upload(c, &d->lrec, lr.data(), nnzL))) return rc;
+    if ((rc = upload(c, &d->grec, gr.data(), nnzL))) return rc;
   }
   const int64_t nnzZ = o.z0_rowptr[n];
+  {
+    // about four entries per lane
+    auto pick = [](double mean) { return mean > 48.0 ? 16 : mean > 24.0 ? 8 : 4; };
+    d->auto_l = pick((double)nnzL / std::max<int64_t>(n, 1));
+    d->auto_z = pick((double)nnzZ / std::max<int64_t>(n, 1));
+  }
   {
     std::vector<int4> zr(nnzZ);
     for (int64_t e = 0; e < nnzZ; ++e) {
@@ -711,18 +726,27 @@ int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const doubl
     if (ev) (void)hipEventRecord(ev[2 * k + which], s);
   };
   const int T = 256;
-  auto rowdot3 = [&](hipStream_t st, const int32_t* rp, const int4* rec, float* out) {
-    const dim3 grid((unsigned)((n * d->lanes + T - 1) / T));
-    if (d->lanes == 4)
+  auto exch = [&](hipStream_t st) {
+    const dim3 grid((unsigned)((n * d->lanes_l + T - 1) / T));
+    if (d->lanes_l == 4)
+      hipLaunchKernelGGL(k_exch<4>, grid, dim3(T), 0, st, n, d->lrp, d->lrec, m, d->hex);
+    else if (d->lanes_l == 8)
+      hipLaunchKernelGGL(k_exch<8>, grid, dim3(T), 0, st, n, d->lrp, d->lrec, m, d->hex);
+    else
+      hipLaunchKernelGGL(k_exch<16>, grid, dim3(T), 0, st, n, d->lrp, d->lrec, m, d->hex);
+  };
+  auto rowdot3 = [&](hipStream_t st, const int32_t* rp, const int4* rec, float* out, int lanes) {
+    const dim3 grid((unsigned)((n * lanes + T - 1) / T));
+    if (lanes == 4)
       hipLaunchKernelGGL(k_rowdot3<4>, grid, dim3(T), 0, st, n, m, rp, rec, out);
-    else if (d->lanes == 8)
+    else if (lanes == 8)
       hipLaunchKernelGGL(k_rowdot3<8>, grid, dim3(T), 0, st, n, m, rp, rec, out);
     else
       hipLaunchKernelGGL(k_rowdot3<16>, grid, dim3(T), 0, st, n, m, rp, rec, out);
   };
   if (with_ms) {
     mark(0, 0);
-    rowdot3(s, d->lrp, d->drec, d->q);
+    rowdot3(s, d->lrp, d->drec, d->q, d->lanes_l);
     mark(0, 1);
     // element correction on the side stream, beside anterpolation and the
     // FFT (both bound by latency and ALU rather than HBM); joined before
@@ -730,9 +754,18 @@ int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const doubl
     (void)hipEventRecord(d->fork, s);
     (void)hipStreamWaitEvent(d->side, d->fork, 0);
     if (ev) (void)hipEventRecord(ev[2 * 9], d->side);
-    rowdot3(d->side, d->zrp, d->zrec, d->uz);
+    rowdot3(d->side, d->zrp, d->zrec, d->uz, d->lanes_z);
     if (ev) (void)hipEventRecord(ev[2 * 9 + 1], d->side);
+    if (with_ex) {
+      if (ev) (void)hipEventRecord(ev[2 * 10], d->side);
+      exch(d->side);
+      if (ev) (void)hipEventRecord(ev[2 * 10 + 1], d->side);
+    }
     (void)hipEventRecord(d->join, d->side);
+  } else if (with_ex) {
+    mark(10, 0);
+    exch(s);
+    mark(10, 1);
   }
   if (with_ms) {
     const int64_t ntiles = (int64_t)((g.N[0] + kAntTX - 1) / kAntTX) *
@@ -791,16 +824,16 @@ int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const doubl
   }
   mark(8, 0);
   {
-    const dim3 grid((unsigned)((n * d->lanes + T - 1) / T));
-    if (d->lanes == 4)
-      hipLaunchKernelGGL(k_grad<4>, grid, dim3(T), 0, s, n, d->lrp, d->lcol, d->lgl, m, d->u, h,
-                         hx, hy, hz, with_ex, with_ms);
-    else if (d->lanes == 8)
-      hipLaunchKernelGGL(k_grad<8>, grid, dim3(T), 0, s, n, d->lrp, d->lcol, d->lgl, m, d->u, h,
-                         hx, hy, hz, with_ex, with_ms);
+    const dim3 grid((unsigned)((n * d->lanes_l + T - 1) / T));
+    if (d->lanes_l == 4)
+      hipLaunchKernelGGL(k_gsum<4>, grid, dim3(T), 0, s, n, d->lrp, d->grec, d->u, d->hex, h, hx,
+                         hy, hz, with_ex, with_ms);
+    else if (d->lanes_l == 8)
+      hipLaunchKernelGGL(k_gsum<8>, grid, dim3(T), 0, s, n, d->lrp, d->grec, d->u, d->hex, h, hx,
+                         hy, hz, with_ex, with_ms);
     else
-      hipLaunchKernelGGL(k_grad<16>, grid, dim3(T), 0, s, n, d->lrp, d->lcol, d->lgl, m, d->u,
-                         h, hx, hy, hz, with_ex, with_ms);
+      hipLaunchKernelGGL(k_gsum<16>, grid, dim3(T), 0, s, n, d->lrp, d->grec, d->u, d->hex, h,
+                         hx, hy, hz, with_ex, with_ms);
   }
   mark(8, 1);
   hipError_t e = hipGetLastError();
@@ -966,15 +999,14 @@ int pmfem_query(pmfem_ctx* c, int64_t* n_unknowns, int64_t* unknown_of_node,
     const double spec = (double)o.N[2] * o.M[1] * hx * 8.0;
     const double khat = hx * o.M[1] * o.M[2] * 4.0;
     double b = 0;
-    b += n * (8 + 12 + 4 + 4) + nL * (4 + 12) + nZ * (4 + 12);            // k_rowdot3 x2
-    b += n * (16 + 4) + ng * 4 + (double)o.box_start.size() * 4;       // k_anterp
-    b += ng * 4 + spec;                                                  // r2c
-    b += 2 * spec;                                                       // y fwd
-    b += 2 * spec + khat;                                                // z
-    b += 2 * spec;                                                       // y inv
-    b += spec + ng * 4;                                                  // c2r
+    b += 2 * n * (4 + 12 + 4) + nL * 16 + nZ * 16;                      // charges, u_Z
+    b += n * (16 + 4) + ng * 4 + (double)o.box_start.size() * 4;       // anterpolation
+    b += ng * 4 + spec;                                                  // x/y forward
+    b += 2 * spec + khat;                                                // z, K multiply
+    b += spec + ng * 4;                                                  // y/x inverse
     b += n * (16 + 4 + 4 + 4 + 4) + ng * 4 + nP * 4;                     // interp+corr
-    b += n * (8 + 12 + 4 + 12) + nL * (4 + 16);                          // grad
+    b += n * (4 + 12 + 12) + nL * 8;                                     // exchange
+    b += n * (4 + 4 + 12 + 12) + nL * 16;                                // gradient sum
     *bytes_per_eval = b;
   }
   return PMFEM_OK;
@@ -1001,9 +1033,8 @@ int pmfem_heff_parts(pmfem_ctx* c, const float* m_dev, float* h_dev, float* q_de
   hipError_t e = hipSuccess;
   if (q_dev) e = hipMemcpyAsync(q_dev, d->q, n * 4, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess && u_dev) e = hipMemcpyAsync(u_dev, d->u, n * 4, hipMemcpyDeviceToDevice, s);
-  if (e == hipSuccess && hex_dev) {
-    if ((rc = run_heff(c, m_dev, hex_dev, PMFEM_TERM_EX, nullptr))) return rc;
-  }
+  if (e == hipSuccess && hex_dev)
+    e = hipMemcpyAsync(hex_dev, d->hex, 3 * n * 4, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return hip_err(c, e, "copy of intermediates");
   return PMFEM_OK;
 }
@@ -1066,8 +1097,8 @@ int pmfem_energy(pmfem_ctx* c, const double* m_dev, double* e_ex, double* e_ms) 
   const int64_t n = d->n;
   hipLaunchKernelGGL(k_rk_stage, dim3((unsigned)((3 * n + 255) / 256)), dim3(256), 0, s, n, m_dev,
                      (const double*)nullptr, 0.0, (double*)nullptr, d->m32);
+  // the both-terms evaluation leaves H_ex in d->hex and q, u in their buffers
   if ((rc = run_heff(c, d->m32, d->h32, PMFEM_TERM_EX | PMFEM_TERM_MS, nullptr))) return rc;
-  if ((rc = run_heff(c, d->m32, d->hex, PMFEM_TERM_EX, nullptr))) return rc;
   hipLaunchKernelGGL(k_energy, dim3(d->nparts), dim3(256), 0, s, n, m_dev, (const double*)d->mu,
                      (const float*)d->hex, (const float*)d->q, (const float*)d->u, d->part);
   std::vector<double> part(2 * d->nparts);

@@ -77,9 +77,11 @@ __global__ void k_interp_tile(GridParams g, IcPlan pl, const float* U, const flo
                               const uint32_t* rdesc, const int32_t* prp, const float* pval,
                               const float* q, const float* uz, float* u);
 template <int G>
-__global__ void k_grad(int64_t n, const int32_t* rp, const int32_t* col, const float4* gl,
-                       const float* m, const float* u, float* h, float hax, float hay, float haz,
-                       int with_ex, int with_ms);
+__global__ void k_exch(int64_t n, const int32_t* rp, const int2* lrec, const float* m, float* hex);
+template <int G>
+__global__ void k_gsum(int64_t n, const int32_t* rp, const int4* grec, const float* u,
+                       const float* hex, float* h, float hax, float hay, float haz, int with_hex,
+                       int with_ms);
 __global__ void k_rk_stage(int64_t n, const double* m, const double* k, double c, double* mst,
                            float* m32);
 __global__ void k_rk_rhs(int64_t n, const double* mst, const float* h, double pref,

@@ -8,7 +8,8 @@
 //   k_fft_yx_inv   inverse FFT along y, complex-to-real along x -> U = (1/4 pi) K * Q
 //                  (k_r2c_x, k_fft_y, k_c2r_x: the same passes one axis at a time)
 //   k_interp_tile  u = W U + P q + u_Z            (steps 3 and 4)
-//   k_grad         H = L m - G u (+ H_applied)    (Eqs. hex/lapl_2, hms_d3)
+//   k_exch         H_ex = L m (second stream)     (Eqs. hex, lapl_2)
+//   k_gsum         H = H_ex - G u (+ H_applied)   (Eq. hms_d3, heff)
 // All arithmetic is FP32; every reduction is done in a fixed order inside a
 // wavefront or a thread, so results are bitwise reproducible (no atomics).
 #include <hip/hip_runtime.h>
@@ -952,17 +953,17 @@ PMFEM_INTERP_TILE(7)
 #undef PMFEM_INTERP_TILE
 
 // ---------------------------------------------------------------------------
-// exchange + gradient + sum over the shared local pattern, G lanes per row:
-//   H_n = sum_k ( L_nk m_k - G_nk u_k ) + H_applied,  gl = {Gx, Gy, Gz, L}
+// exchange and gradient over the shared local pattern, G lanes per row:
+//   k_exch:  H_ex,n = sum_k L_nk m_k                 (records {col, L})
+//   k_gsum:  H_n = H_ex,n - sum_k G_nk u_k + H_applied  (records {col, Gx, Gy, Gz})
+// The exchange needs only m, so the library runs it on the second stream
+// beside the grid steps; k_gsum then adds the magnetostatic gradient.
 
 template <int G>
-__global__ void __launch_bounds__(256) k_grad(int64_t n, const int32_t* __restrict__ rp,
-                                              const int32_t* __restrict__ col,
-                                              const float4* __restrict__ gl,
+__global__ void __launch_bounds__(256) k_exch(int64_t n, const int32_t* __restrict__ rp,
+                                              const int2* __restrict__ lrec,
                                               const float* __restrict__ m,
-                                              const float* __restrict__ u,
-                                              float* __restrict__ h, float hax, float hay,
-                                              float haz, int with_ex, int with_ms) {
+                                              float* __restrict__ hex) {
   const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   const int lane = threadIdx.x & (G - 1);
   if (row >= n) return;  // whole groups leave together
@@ -970,40 +971,68 @@ __global__ void __launch_bounds__(256) k_grad(int64_t n, const int32_t* __restri
   const int e0 = rp[row], e1 = rp[row + 1];
 #pragma unroll 2
   for (int e = e0 + lane; e < e1; e += G) {
-    const int64_t k = col[e];
-    const float4 w = gl[e];
-    if (with_ex) {
-      const float* mk = m + 3 * k;
-      hx = fmaf(w.w, mk[0], hx);
-      hy = fmaf(w.w, mk[1], hy);
-      hz = fmaf(w.w, mk[2], hz);
-    }
-    if (with_ms) {
-      const float uk = u[k];
-      hx = fmaf(-w.x, uk, hx);
-      hy = fmaf(-w.y, uk, hy);
-      hz = fmaf(-w.z, uk, hz);
-    }
+    const int2 r = lrec[e];
+    const float* mk = m + 3 * (int64_t)r.x;
+    const float w = __int_as_float(r.y);
+    hx = fmaf(w, mk[0], hx);
+    hy = fmaf(w, mk[1], hy);
+    hz = fmaf(w, mk[2], hz);
   }
   hx = group_sum<G>(hx);
   hy = group_sum<G>(hy);
   hz = group_sum<G>(hz);
   if (lane == 0) {
+    hex[3 * row] = hx;
+    hex[3 * row + 1] = hy;
+    hex[3 * row + 2] = hz;
+  }
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) k_gsum(int64_t n, const int32_t* __restrict__ rp,
+                                              const int4* __restrict__ grec,
+                                              const float* __restrict__ u,
+                                              const float* __restrict__ hex,
+                                              float* __restrict__ h, float hax, float hay,
+                                              float haz, int with_hex, int with_ms) {
+  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int lane = threadIdx.x & (G - 1);
+  if (row >= n) return;  // whole groups leave together
+  float hx = 0.f, hy = 0.f, hz = 0.f;
+  if (with_ms) {
+    const int e0 = rp[row], e1 = rp[row + 1];
+#pragma unroll 2
+    for (int e = e0 + lane; e < e1; e += G) {
+      const int4 r = grec[e];
+      const float uk = u[r.x];
+      hx = fmaf(-__int_as_float(r.y), uk, hx);
+      hy = fmaf(-__int_as_float(r.z), uk, hy);
+      hz = fmaf(-__int_as_float(r.w), uk, hz);
+    }
+    hx = group_sum<G>(hx);
+    hy = group_sum<G>(hy);
+    hz = group_sum<G>(hz);
+  }
+  if (lane == 0) {
+    if (with_hex) {
+      hx += hex[3 * row];
+      hy += hex[3 * row + 1];
+      hz += hex[3 * row + 2];
+    }
     h[3 * row] = hx + hax;
     h[3 * row + 1] = hy + hay;
     h[3 * row + 2] = hz + haz;
   }
 }
 
-template __global__ void k_grad<4>(int64_t, const int32_t*, const int32_t*, const float4*,
-                                   const float*, const float*, float*, float, float, float, int,
-                                   int);
-template __global__ void k_grad<8>(int64_t, const int32_t*, const int32_t*, const float4*,
-                                   const float*, const float*, float*, float, float, float, int,
-                                   int);
-template __global__ void k_grad<16>(int64_t, const int32_t*, const int32_t*, const float4*,
-                                    const float*, const float*, float*, float, float, float, int,
-                                    int);
+#define PMFEM_LOCAL_KERNELS(G)                                                                  \
+  template __global__ void k_exch<G>(int64_t, const int32_t*, const int2*, const float*, float*); \
+  template __global__ void k_gsum<G>(int64_t, const int32_t*, const int4*, const float*,         \
+                                     const float*, float*, float, float, float, int, int);
+PMFEM_LOCAL_KERNELS(4)
+PMFEM_LOCAL_KERNELS(8)
+PMFEM_LOCAL_KERNELS(16)
+#undef PMFEM_LOCAL_KERNELS
 
 // ---------------------------------------------------------------------------
 // LLG (unit-vector Landau-Lifshitz form), classic RK4 in FP64
