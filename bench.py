@@ -159,7 +159,7 @@ def main():
     ap.add_argument("--config", default="composite_c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
-                    help="also run a plain device copy of this many MiB (counter calibration)")
+                    help="also stream this many MiB through plain kernels (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for --gpus {args.gpus}); "
@@ -181,14 +181,16 @@ def main():
     m = torch.tensor(prob.m[nou], dtype=torch.float32, device="cuda")
     h = torch.empty_like(m)
     if args.copy_mib > 0:
-        # a plain copy of known size: HBM counters of a profiled run are scaled
-        # by what they read for it (bytes read = bytes written = copy_mib MiB)
+        # plain streams of known size, each one elementwise kernel (a device
+        # copy may run on a DMA engine that the counters do not see): a fill
+        # writes copy_mib MiB, a negation reads and writes copy_mib MiB each;
+        # HBM counters of a profiled run are scaled by what they read for them
         src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.neg(src, out=dst)
         torch.cuda.synchronize()
-        log(f"copy calibration: 3 copies of {args.copy_mib} MiB")
+        log(f"counter calibration: one {args.copy_mib} MiB fill, 3 negations of {args.copy_mib} MiB")
         del src, dst
     for _ in range(args.warmup):
         ctx.heff(m, h)

@@ -627,6 +627,18 @@ int upload_all(pmfem_ctx* c) {
     d->nnz_p_dev = tot;
     d->icp.plast = (int)tot;  // pv holds tot + 4 values
     d->icp_small.plast = (int)tot;
+    // chunks per lane in registers: the mean row's share per lane, rounded up
+    // to {2, 4, 6, 8} (longer rows take the rest in a loop)
+    {
+      const int64_t mean = n > 0 ? (tot / 4 + n - 1) / n : 0;
+      const int64_t per_lane = (mean + kIcLanes - 1) / kIcLanes;
+      int kc = per_lane <= 2 ? 2 : per_lane <= 4 ? 4 : per_lane <= 6 ? 6 : 8;
+#ifdef PMFEM_IC_FORCE_KC
+      kc = PMFEM_IC_FORCE_KC;
+#endif
+      d->icp.kc = kc;
+      d->icp_small.kc = kc;
+    }
   }
   if ((rc = upload(c, &d->khat, o.khat.data(), o.khat.size()))) return rc;
   auto tx = twiddles(o.M[0]), ty = twiddles(o.M[1]), tz = twiddles(o.M[2]);
@@ -710,6 +722,30 @@ void convolve(pmfem_dev* d, hipStream_t s, const float* Qg, float* Ug, Mark&& ma
 }
 
 // One evaluation. Intermediates land in the context's work buffers.
+// k_interp_tile for 2 r_b + 1 = WT runs per row and the plan's chunks per lane.
+template <int WT>
+void launch_interp(const IcPlan& pl, dim3 grid, dim3 blk, size_t lds, hipStream_t s,
+                   const GridParams& g, const pmfem_dev* d, const pmfem_dev::IcLists& L) {
+#define PMFEM_IC_LAUNCH(KC)                                                                  \
+  hipLaunchKernelGGL((k_interp_tile<WT, KC>), grid, blk, lds, s, g, pl, d->grid, d->pos4,    \
+                     L.list, L.lstart, L.wseg, L.rdesc, d->prp, d->pv, d->q, d->uz, d->u)
+  switch (pl.kc) {
+    case 2:
+      PMFEM_IC_LAUNCH(2);
+      break;
+    case 4:
+      PMFEM_IC_LAUNCH(4);
+      break;
+    case 6:
+      PMFEM_IC_LAUNCH(6);
+      break;
+    default:
+      PMFEM_IC_LAUNCH(8);
+      break;
+  }
+#undef PMFEM_IC_LAUNCH
+}
+
 int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const double* happ) {
   pmfem_dev* d = c->dev;
   hipStream_t s = stream_of(c);
@@ -793,24 +829,16 @@ int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const doubl
       const size_t lds = (size_t)pl.lds_bytes;
       switch (g.rb) {
         case 0:
-          hipLaunchKernelGGL(k_interp_tile<1>, grid, blk, lds, s, g, pl, d->grid, d->pos4,
-                             L.list, L.lstart, L.wseg, L.rdesc, d->prp, d->pv, d->q, d->uz,
-                             d->u);
+          launch_interp<1>(pl, grid, blk, lds, s, g, d, L);
           break;
         case 1:
-          hipLaunchKernelGGL(k_interp_tile<3>, grid, blk, lds, s, g, pl, d->grid, d->pos4,
-                             L.list, L.lstart, L.wseg, L.rdesc, d->prp, d->pv, d->q, d->uz,
-                             d->u);
+          launch_interp<3>(pl, grid, blk, lds, s, g, d, L);
           break;
         case 2:
-          hipLaunchKernelGGL(k_interp_tile<5>, grid, blk, lds, s, g, pl, d->grid, d->pos4,
-                             L.list, L.lstart, L.wseg, L.rdesc, d->prp, d->pv, d->q, d->uz,
-                             d->u);
+          launch_interp<5>(pl, grid, blk, lds, s, g, d, L);
           break;
         default:
-          hipLaunchKernelGGL(k_interp_tile<7>, grid, blk, lds, s, g, pl, d->grid, d->pos4,
-                             L.list, L.lstart, L.wseg, L.rdesc, d->prp, d->pv, d->q, d->uz,
-                             d->u);
+          launch_interp<7>(pl, grid, blk, lds, s, g, d, L);
           break;
       }
     }

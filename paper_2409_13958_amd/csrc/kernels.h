@@ -33,6 +33,7 @@ struct IcPlan {
   int rcap;      // observer rows per tile
   int ux, uzl;   // staged potential: points per line (xs + p), z-lines (tz + p)
   int plast;     // last valid 4-value chunk start of the device matrix values
+  int kc;        // chunks per lane in registers (2, 4, 6 or 8)
   int o_q, o_u, o_seg;  // LDS byte offsets
   int lds_bytes;
 };
@@ -71,7 +72,14 @@ __global__ void k_fft_z_mul(GridParams g, float2* spec, const float* khat, const
 __global__ void k_c2r_x(GridParams g, const float2* spec, float* U, const float2* twx,
                         int lines_per_block);
 
-template <int WT>
+#ifndef PMFEM_IC_LANES
+#define PMFEM_IC_LANES 8
+#endif
+// lanes per observer row of k_interp_tile (8 x 16 B = one 128 B line per
+// load); 4, 8 or 16
+constexpr int kIcLanes = PMFEM_IC_LANES;
+// WT = 2 r_b + 1 runs per row; KC = 4-value chunks per lane held in registers
+template <int WT, int KC>
 __global__ void k_interp_tile(GridParams g, IcPlan pl, const float* U, const float4* pos4,
                               const int32_t* list, const int32_t* lstart, const int32_t* wseg,
                               const uint32_t* rdesc, const int32_t* prp, const float* pval,

@@ -752,15 +752,20 @@ __global__ void __launch_bounds__(256) k_c2r_x(GridParams g, const float2* __res
 // the (start, length) of its runs. The (p + 1) y-lines of U over the tile's z
 // range are staged too. Each group of G lanes then takes one observer row:
 // u_n = W_n U + sum over the runs of P q + u_Z, in a fixed order.
+//
+// A row's values are one padded array (each run rounded up to 4 values with
+// zeros), read as 4-value chunks: lane l of the group takes chunks l, l + G,
+// ..., the first KC of them held in registers at once, so the lanes stay busy
+// whatever the run lengths are; a chunk finds its run from the cumulative
+// chunk counts of the row.
 
-#ifndef PMFEM_IC_LANES
-#define PMFEM_IC_LANES 8
+template <int WT, int KC>
+#ifdef PMFEM_IC_WAVES
+#define PMFEM_IC_OCC __attribute__((amdgpu_waves_per_eu(PMFEM_IC_WAVES)))
+#else
+#define PMFEM_IC_OCC
 #endif
-// lanes per observer row (8 x 16 B = one 128 B line per load); 4, 8 or 16
-constexpr int kIcLanes = PMFEM_IC_LANES;
-
-template <int WT>
-__global__ void __launch_bounds__(256) k_interp_tile(
+__global__ void __launch_bounds__(256) PMFEM_IC_OCC k_interp_tile(
     GridParams g, IcPlan pl, const float* __restrict__ U, const float4* __restrict__ pos4,
     const int32_t* __restrict__ list, const int32_t* __restrict__ lstart,
     const int32_t* __restrict__ wseg, const uint32_t* __restrict__ rdesc,
@@ -784,40 +789,50 @@ __global__ void __launch_bounds__(256) k_interp_tile(
   for (int i = tid; i < segw; i += T) s_seg[i] = wseg[(int64_t)w * segw + i];
   const int l0 = lstart[w];
   const int n = min(lstart[w + 1] - l0, pl.qcap);
-  // stage the listed charges, K loads in flight; 4 zeros after them
-  if (tid < 4) s_q[n + tid] = 0.f;
-  {
-    constexpr int K = 8;
-    for (int e0 = tid; e0 < n; e0 += K * T) {
-      int gi[K];
+  // the first list entries are requested before the potential lines are
+  // staged, so that both wait on memory together
+  constexpr int KQ = 8;
+  int gi[KQ];
 #pragma unroll
-      for (int j = 0; j < K; ++j) gi[j] = e0 + j * T < n ? list[l0 + e0 + j * T] : 0;
-      float v[K];
-#pragma unroll
-      for (int j = 0; j < K; ++j) v[j] = q[gi[j]];
-#pragma unroll
-      for (int j = 0; j < K; ++j)
-        if (e0 + j * T < n) s_q[e0 + j * T] = v[j];
-    }
-  }
+  for (int j = 0; j < KQ; ++j) gi[j] = tid + j * T < n ? list[l0 + tid + j * T] : 0;
   // stencil lines of U: z-lines [stz(z0), stz(z0) + tz + p), y-lines [sty, sty + p]
   const int ux0 = box_stencil_start(x0, g.N[0], p, g.per[0]);
   const int sty = box_stencil_start(by, g.N[1], p, g.per[1]);
   const int stz = box_stencil_start(z0, g.N[2], p, g.per[2]);
   {
     const int nu = pl.uzl * p1 * pl.ux;
+    const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
+    // a periodic line wraps at most once (ux, p + 1 and uzl never exceed N)
+    const int wx = g.per[0] ? Nx : 0, wy = g.per[1] ? Ny : 0, wz = g.per[2] ? Nz : 0;
+    const float inv_ux = 1.0f / (float)pl.ux, inv_p1 = 1.0f / (float)p1;
     batched<8>(
         nu,
         [&](int e) {
-          const int t = e % pl.ux, l = e / pl.ux;
-          int y = sty + l % p1, z = stz + l / p1, x = ux0 + t;
-          if (g.per[0]) x = x < 0 ? x + g.N[0] : (x >= g.N[0] ? x - g.N[0] : x);
-          if (g.per[1]) y = y < 0 ? y + g.N[1] : (y >= g.N[1] ? y - g.N[1] : y);
-          if (g.per[2]) z = z < 0 ? z + g.N[2] : (z >= g.N[2] ? z - g.N[2] : z);
-          const bool ok = x < g.N[0] && z < g.N[2];
-          return ok ? U[((int64_t)z * g.N[1] + y) * g.N[0] + x] : 0.f;
+          const int l = fdiv(e, pl.ux, inv_ux), lz = fdiv(l, p1, inv_p1);
+          int x = ux0 + (e - l * pl.ux), y = sty + (l - lz * p1), z = stz + lz;
+          x += x < 0 ? wx : 0;
+          x -= x >= Nx ? wx : 0;
+          y += y < 0 ? wy : 0;
+          y -= y >= Ny ? wy : 0;
+          z += z < 0 ? wz : 0;
+          z -= z >= Nz ? wz : 0;
+          return x < Nx && z < Nz ? U[(z * Ny + y) * Nx + x] : 0.f;
         },
         [&](int e, float v) { s_U[e] = v; });
+  }
+  // stage the listed charges, KQ loads in flight, the next list entries
+  // requested while the charges arrive; 4 zeros after them
+  if (tid < 4) s_q[n + tid] = 0.f;
+  for (int e0 = tid; e0 < n; e0 += KQ * T) {
+    float v[KQ];
+#pragma unroll
+    for (int j = 0; j < KQ; ++j) v[j] = q[gi[j]];
+    const int e1 = e0 + KQ * T;
+#pragma unroll
+    for (int j = 0; j < KQ; ++j) gi[j] = e1 + j * T < n ? list[l0 + e1 + j * T] : 0;
+#pragma unroll
+    for (int j = 0; j < KQ; ++j)
+      if (e0 + j * T < n) s_q[e0 + j * T] = v[j];
   }
   __syncthreads();
   const int nrows = s_seg[tz];
@@ -827,11 +842,6 @@ __global__ void __launch_bounds__(256) k_interp_tile(
   // current row is formed
   constexpr int G = kIcLanes;
   constexpr int W = WT;                 // 2 r_b + 1
-#ifndef PMFEM_IC_RK
-#define PMFEM_IC_RK 2
-#endif
-  // float4 chunks per lane per run held in registers
-  constexpr int RK = WT <= 5 ? PMFEM_IC_RK : 1;
   const int lane = tid & (G - 1), grp = tid / G, ngrp = T / G;
   const bool cubic = p == 3;
   // lane-constant parts of the interpolation weights (p = 3): lane -> x point
@@ -842,69 +852,64 @@ __global__ void __launch_bounds__(256) k_interp_tile(
   Cubic cby[NY];
 #pragma unroll
   for (int i = 0; i < NY; ++i) cby[i] = cubic_basis(ay0 + i);
+  // slot sl of the tile -> its row: segment kz by bisection over the prefix
+  // (pl.tz is a power of two; prefix entries past the tile equal nrows)
   auto fetch = [&](int sl, uint32_t* dsc, int& pp, float4& xi, int& r) {
     int kz = 0;
-    while (kz + 1 < tz && s_seg[kz + 1] <= sl) ++kz;
+    for (int s = pl.tz >> 1; s > 0; s >>= 1) kz = s_seg[kz + s] <= sl ? kz + s : kz;
     r = s_first[kz] + (sl - s_seg[kz]);
 #pragma unroll
-    for (int dx = 0; dx < WT; ++dx) dsc[dx] = rdesc[(int64_t)r * W + dx];
+    for (int dx = 0; dx < W; ++dx) dsc[dx] = rdesc[(int64_t)r * W + dx];
     pp = prp[r];
     xi = pos4[r];
   };
-  uint32_t dsc[WT];
+  uint32_t dsc[W];
   int pp = 0, r = 0;
   float4 xi = make_float4(0.f, 0.f, 0.f, 0.f);
   if (grp < nrows) fetch(grp, dsc, pp, xi, r);
   for (int sl = grp; sl < nrows; sl += ngrp) {
-    // all run values of the row in flight at once: each run's values start
-    // 16-byte aligned (runs are padded with zeros to a multiple of 4)
-    int po[WT];
-    {
-      int acc_p = pp;
+    // cumulative chunk counts cb of the runs and the staged index of chunk j
+    // of run d, qb_d + 4 j with qb_d = start_d - 4 cb_d, kept as qb_0 and the
+    // steps dq_d = qb_d - qb_(d-1) (a sum of selects, not an indexed array)
+    int cb[W + 1], dq[W];
+    cb[0] = 0;
+    int qprev = 0;
 #pragma unroll
-      for (int dx = 0; dx < WT; ++dx) {
-        po[dx] = acc_p;
-        acc_p += ((int)(dsc[dx] >> 16) + 3) & ~3;
-      }
+    for (int d = 0; d < W; ++d) {
+      const int qbd = (int)(dsc[d] & 0xFFFFu) - 4 * cb[d];
+      dq[d] = qbd - qprev;
+      qprev = qbd;
+      cb[d + 1] = cb[d] + (((int)(dsc[d] >> 16) + 3) >> 2);
     }
-    // branch-free slots: a slot past its run reads a valid (finite) matrix
-    // chunk and pairs it with the zeros after the staged charges
-    float4 v[WT][RK];
+    const int C = cb[W];
+    // the first KC chunks of every lane in flight at once; a chunk past the
+    // row reads valid (finite) values and pairs them with the zeros after the
+    // staged charges
+    float4 v[KC];
 #pragma unroll
-    for (int dx = 0; dx < WT; ++dx)
-#pragma unroll
-      for (int t = 0; t < RK; ++t) {
-        const int c = 4 * (lane + G * t);
-        v[dx][t] = *reinterpret_cast<const float4*>(pval + min(po[dx] + c, pl.plast));
-      }
-    uint32_t dn[WT];
+    for (int t = 0; t < KC; ++t)
+      v[t] = *reinterpret_cast<const float4*>(pval + min(pp + 4 * (lane + G * t), pl.plast));
+    uint32_t dn[W];
     int ppn = 0, rn = 0;
     float4 xin = make_float4(0.f, 0.f, 0.f, 0.f);
     if (sl + ngrp < nrows) fetch(sl + ngrp, dn, ppn, xin, rn);
     float acc = 0.f;
+    // padding values are zero and 4 zeros follow the staged charges, so the
+    // 4 products of a chunk need no per-value test
+    auto chunk = [&](int j, const float4& pv) {
+      int b = dq[0] + 4 * j;
 #pragma unroll
-    for (int dx = 0; dx < WT; ++dx) {
-      const int qs = (int)(dsc[dx] & 0xFFFFu), ln = (int)(dsc[dx] >> 16);
-      // the padding values are zero and the staged charges are padded with
-      // zeros, so the 4 products of a chunk need no per-value test
+      for (int d = 1; d < W; ++d) b += j >= cb[d] ? dq[d] : 0;
+      const float* sq = s_q + (j < C ? b : n);
+      acc = fmaf(pv.x, sq[0], acc);
+      acc = fmaf(pv.y, sq[1], acc);
+      acc = fmaf(pv.z, sq[2], acc);
+      acc = fmaf(pv.w, sq[3], acc);
+    };
 #pragma unroll
-      for (int t = 0; t < RK; ++t) {
-        const int c = 4 * (lane + G * t);
-        const float* sq = s_q + (c < ln ? qs + c : n);
-        acc = fmaf(v[dx][t].x, sq[0], acc);
-        acc = fmaf(v[dx][t].y, sq[1], acc);
-        acc = fmaf(v[dx][t].z, sq[2], acc);
-        acc = fmaf(v[dx][t].w, sq[3], acc);
-      }
-      for (int c = 4 * (lane + G * RK); c < ln; c += 4 * G) {
-        const float4 pv4 = *reinterpret_cast<const float4*>(pval + po[dx] + c);
-        const float* sq = s_q + qs + c;
-        acc = fmaf(pv4.x, sq[0], acc);
-        acc = fmaf(pv4.y, sq[1], acc);
-        acc = fmaf(pv4.z, sq[2], acc);
-        acc = fmaf(pv4.w, sq[3], acc);
-      }
-    }
+    for (int t = 0; t < KC; ++t) chunk(lane + G * t, v[t]);
+    for (int j = lane + G * KC; j < C; j += G)
+      chunk(j, *reinterpret_cast<const float4*>(pval + pp + 4 * j));
     // W U from the staged lines; the box of the row from its packed coordinates
     const uint32_t bc = __float_as_uint(xi.w);
     const int bx = (int)(bc & 1023u), bz = (int)((bc >> 20) & 1023u);
@@ -934,22 +939,27 @@ __global__ void __launch_bounds__(256) k_interp_tile(
     acc = group_sum<G>(acc);
     if (lane == 0) u[r] = acc + uz[r];
 #pragma unroll
-    for (int dx = 0; dx < WT; ++dx) dsc[dx] = dn[dx];
+    for (int dx = 0; dx < W; ++dx) dsc[dx] = dn[dx];
     pp = ppn;
     xi = xin;
     r = rn;
   }
 }
 
-#define PMFEM_INTERP_TILE(WT)                                                              \
-  template __global__ void k_interp_tile<WT>(GridParams, IcPlan, const float*, const float4*,   \
-                                             const int32_t*, const int32_t*, const int32_t*,    \
-                                             const uint32_t*, const int32_t*, const float*,     \
-                                             const float*, const float*, float*);
-PMFEM_INTERP_TILE(1)
-PMFEM_INTERP_TILE(3)
-PMFEM_INTERP_TILE(5)
-PMFEM_INTERP_TILE(7)
+#define PMFEM_INTERP_TILE(WT, KC)                                                             \
+  template __global__ void k_interp_tile<WT, KC>(                                             \
+      GridParams, IcPlan, const float*, const float4*, const int32_t*, const int32_t*,        \
+      const int32_t*, const uint32_t*, const int32_t*, const float*, const float*, const float*, \
+      float*);
+#define PMFEM_INTERP_TILES(WT) \
+  PMFEM_INTERP_TILE(WT, 2)     \
+  PMFEM_INTERP_TILE(WT, 4)     \
+  PMFEM_INTERP_TILE(WT, 6)     \
+  PMFEM_INTERP_TILE(WT, 8)
+PMFEM_INTERP_TILES(1)
+PMFEM_INTERP_TILES(3)
+PMFEM_INTERP_TILES(5)
+PMFEM_INTERP_TILES(7)
 #undef PMFEM_INTERP_TILE
 
 // ---------------------------------------------------------------------------
