@@ -612,7 +612,9 @@ int upload_all(pmfem_ctx* c) {
       if (tot > 2147483647LL) return set_err(c, PMFEM_ENOMEM, "padded precorrection too large");
     }
     prp[n] = (int32_t)tot;
-    std::vector<float> pv((size_t)tot + 4, 0.f);
+    // zeros after the last row: a lane's register chunks (at most 8 per lane)
+    // may reach past the end of the matrix
+    std::vector<float> pv((size_t)tot + 4 + 32 * kIcLanes, 0.f);
     for (int64_t r = 0; r < n; ++r) {
       int64_t src = o.p_rowptr[r], dst = prp[r];
       for (int dx = 0; dx < W; ++dx) {
@@ -625,8 +627,6 @@ int upload_all(pmfem_ctx* c) {
     if ((rc = upload(c, &d->prp, prp.data(), n + 1))) return rc;
     if ((rc = upload(c, &d->pv, pv.data(), pv.size()))) return rc;
     d->nnz_p_dev = tot;
-    d->icp.plast = (int)tot;  // pv holds tot + 4 values
-    d->icp_small.plast = (int)tot;
     // chunks per lane in registers: the mean row's share per lane, rounded up
     // to {2, 4, 6, 8} (longer rows take the rest in a loop)
     {

@@ -32,7 +32,6 @@ struct IcPlan {
   int qcap;      // staged source charges
   int rcap;      // observer rows per tile
   int ux, uzl;   // staged potential: points per line (xs + p), z-lines (tz + p)
-  int plast;     // last valid 4-value chunk start of the device matrix values
   int kc;        // chunks per lane in registers (2, 4, 6 or 8)
   int o_q, o_u, o_seg;  // LDS byte offsets
   int lds_bytes;

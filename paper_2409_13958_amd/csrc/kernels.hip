@@ -759,12 +759,13 @@ __global__ void __launch_bounds__(256) k_c2r_x(GridParams g, const float2* __res
 // whatever the run lengths are; a chunk finds its run from the cumulative
 // chunk counts of the row.
 
-template <int WT, int KC>
-#ifdef PMFEM_IC_WAVES
-#define PMFEM_IC_OCC __attribute__((amdgpu_waves_per_eu(PMFEM_IC_WAVES)))
-#else
-#define PMFEM_IC_OCC
+// five waves per SIMD (at most 96 registers) where the row state fits them
+// without spilling, else four
+#ifndef PMFEM_IC_WAVES
+#define PMFEM_IC_WAVES (WT * KC <= 30 ? 5 : 4)
 #endif
+#define PMFEM_IC_OCC __attribute__((amdgpu_waves_per_eu(PMFEM_IC_WAVES)))
+template <int WT, int KC>
 __global__ void __launch_bounds__(256) PMFEM_IC_OCC k_interp_tile(
     GridParams g, IcPlan pl, const float* __restrict__ U, const float4* __restrict__ pos4,
     const int32_t* __restrict__ list, const int32_t* __restrict__ lstart,
@@ -800,25 +801,43 @@ __global__ void __launch_bounds__(256) PMFEM_IC_OCC k_interp_tile(
   const int sty = box_stencil_start(by, g.N[1], p, g.per[1]);
   const int stz = box_stencil_start(z0, g.N[2], p, g.per[2]);
   {
-    const int nu = pl.uzl * p1 * pl.ux;
+    // thread -> one x point t of the lines l = l00, l00 + lpp, ... (lpp whole
+    // lines per pass); y and z follow l incrementally, so no division per value
     const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
-    // a periodic line wraps at most once (ux, p + 1 and uzl never exceed N)
-    const int wx = g.per[0] ? Nx : 0, wy = g.per[1] ? Ny : 0, wz = g.per[2] ? Nz : 0;
-    const float inv_ux = 1.0f / (float)pl.ux, inv_p1 = 1.0f / (float)p1;
-    batched<8>(
-        nu,
-        [&](int e) {
-          const int l = fdiv(e, pl.ux, inv_ux), lz = fdiv(l, p1, inv_p1);
-          int x = ux0 + (e - l * pl.ux), y = sty + (l - lz * p1), z = stz + lz;
-          x += x < 0 ? wx : 0;
-          x -= x >= Nx ? wx : 0;
+    const int ux = pl.ux, nl = pl.uzl * p1, lpp = T / ux;
+    const int l00 = tid / ux, t = tid - l00 * ux;
+    if (l00 < lpp) {
+      // a periodic line wraps at most once (ux, p + 1 and uzl never exceed N)
+      int x = ux0 + t;
+      if (g.per[0]) x = x < 0 ? x + Nx : (x >= Nx ? x - Nx : x);
+      const bool okx = x < Nx;
+      const int wy = g.per[1] ? Ny : 0, wz = g.per[2] ? Nz : 0;
+      const int dly = lpp % p1, dlz = lpp / p1;
+      int ly = l00 % p1, lz = l00 / p1;
+      constexpr int KU = 8;
+      for (int l0 = l00; l0 < nl; l0 += KU * lpp) {
+        float v[KU];
+#pragma unroll
+        for (int k = 0; k < KU; ++k) {
+          int y = sty + ly, z = stz + lz;
           y += y < 0 ? wy : 0;
           y -= y >= Ny ? wy : 0;
           z += z < 0 ? wz : 0;
           z -= z >= Nz ? wz : 0;
-          return x < Nx && z < Nz ? U[(z * Ny + y) * Nx + x] : 0.f;
-        },
-        [&](int e, float v) { s_U[e] = v; });
+          const bool ok = okx && z < Nz && l0 + k * lpp < nl;
+          v[k] = ok ? U[(z * Ny + y) * Nx + x] : 0.f;
+          ly += dly;
+          lz += dlz;
+          if (ly >= p1) {
+            ly -= p1;
+            ++lz;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < KU; ++k)
+          if (l0 + k * lpp < nl) s_U[(l0 + k * lpp) * ux + t] = v[k];
+      }
+    }
   }
   // stage the listed charges, KQ loads in flight, the next list entries
   // requested while the charges arrive; 4 zeros after them
@@ -883,12 +902,12 @@ __global__ void __launch_bounds__(256) PMFEM_IC_OCC k_interp_tile(
     }
     const int C = cb[W];
     // the first KC chunks of every lane in flight at once; a chunk past the
-    // row reads valid (finite) values and pairs them with the zeros after the
-    // staged charges
+    // row reads valid (finite) values of the next rows, or the zeros that pad
+    // the matrix, and pairs them with the zeros after the staged charges
+    const float4* prow = reinterpret_cast<const float4*>(pval + pp) + lane;
     float4 v[KC];
 #pragma unroll
-    for (int t = 0; t < KC; ++t)
-      v[t] = *reinterpret_cast<const float4*>(pval + min(pp + 4 * (lane + G * t), pl.plast));
+    for (int t = 0; t < KC; ++t) v[t] = prow[G * t];
     uint32_t dn[W];
     int ppn = 0, rn = 0;
     float4 xin = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -908,8 +927,7 @@ __global__ void __launch_bounds__(256) PMFEM_IC_OCC k_interp_tile(
     };
 #pragma unroll
     for (int t = 0; t < KC; ++t) chunk(lane + G * t, v[t]);
-    for (int j = lane + G * KC; j < C; j += G)
-      chunk(j, *reinterpret_cast<const float4*>(pval + pp + 4 * j));
+    for (int j = lane + G * KC; j < C; j += G) chunk(j, prow[j - lane]);
     // W U from the staged lines; the box of the row from its packed coordinates
     const uint32_t bc = __float_as_uint(xi.w);
     const int bx = (int)(bc & 1023u), bz = (int)((bc >> 20) & 1023u);
