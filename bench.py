@@ -196,16 +196,25 @@ def main():
         ctx.heff(m, h)
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} done")
-    ctx.profile_begin(args.steps)
+    # timed region: the evaluations alone
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ctx.heff(m, h)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = ctx.profile_end()
     dt = (t1 - t0) / args.steps
     log(f"timed {args.steps} steps: {dt * 1e3:.4f} ms/step")
+    # the same number of evaluations again with a HIP event pair around every
+    # kernel (on the stream it runs on): per-kernel durations for the roofline
+    # (the events add gaps between kernels, so this pass is not the one timed)
+    ctx.profile_begin(args.steps)
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.heff(m, h)
+    prof = ctx.profile_end()
+    t3 = time.perf_counter()
+    log(f"event pass {args.steps} steps: {(t3 - t2) / args.steps * 1e3:.4f} ms/step")
     kb = kernel_bytes(ctx, list(prof))
     per_kernel = {k: (ms / max(c, 1), c) for k, (ms, c) in prof.items()}
     for k, (avg, c) in per_kernel.items():

@@ -104,16 +104,19 @@ int pmfem_set_aim(pmfem_ctx* ctx, const int32_t grid[3], int32_t order_p, int32_
 
 /*
  * Kernel form of one stage of the evaluation; the results agree within
- * FP32 rounding order. stage "anterp": 1 tile gather, 2 line gather;
+ * FP32 rounding order. stage "anterp": 1 tile gather, 2 line gather, 3 tile
+ * scatter (per-workgroup LDS sums in a fixed order, then a fixed-order sum of
+ * the overlapping tile footprints);
  * "interp" (interpolation + precorrection): 1 narrow observer tiles (at
  * most 4 boxes along x), 2 the largest tiles whose staging fits in LDS;
  * "fft": 1 separate x, y, z passes, 2 whole z-planes in LDS for x and y;
  * "spmv" (charges, element correction, exchange and gradient rows): 4, 8
  * or 16 lanes per row on both patterns. variant 0 (the default) picks the
- * staged forms (2) wherever their LDS plans fit, and per pattern the lanes
- * that give each about four entries of a mean row. May be called before or after pmfem_build; EINVAL if the stage
- * or variant is unknown or a forced form does not fit the built problem
- * (the previous choice is kept).
+ * scatter anterpolation (3) and the staged forms (2) of the other stages
+ * wherever their LDS plans fit, and per pattern the lanes that give each
+ * about four entries of a mean row. May be called before or after
+ * pmfem_build; EINVAL if the stage or variant is unknown or a forced form
+ * does not fit the built problem (the previous choice is kept).
  */
 int pmfem_set_variant(pmfem_ctx* ctx, const char* stage, int32_t variant);
 

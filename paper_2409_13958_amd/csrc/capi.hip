@@ -27,6 +27,11 @@ struct pmfem_dev {
   bool ant_ok = false, ic_ok = false, fft_ok = false;  // the plans fit
   bool ant_line = false;   // false: the tile form k_anterp
   int ant_threads = 0;
+  ScPlan sp{};              // scatter form of anterpolation
+  bool sc_ok = false, ant_scatter = false;
+  int32_t *sc_list = nullptr, *sc_lstart = nullptr;  // nodes of every tile, box order
+  int2* sc_tab[3] = {};     // per axis and grid index: (tile, offset) of the covering tiles
+  float* sc_part = nullptr; // footprint sums of every tile
   IcPlan icp{}, icp_small{};  // interpolation+precorrection tiles: chosen, narrow
   struct IcLists {
     int32_t *list = nullptr, *lstart = nullptr, *wseg = nullptr;
@@ -36,7 +41,7 @@ struct pmfem_dev {
   bool ic_seg = false;        // false: the narrow tiles
   bool fft_plane = false;  // x and y transforms of a whole z-plane in one kernel
   size_t fft_plane_lds = 0;
-  const char* kname[11] = {};  // kernel in each profiling slot
+  const char* kname[12] = {};  // kernel in each profiling slot
   hipStream_t side = nullptr;   // second stream: element correction beside the grid steps
   hipEvent_t fork = nullptr, join = nullptr;
   int2 *brx = nullptr, *bry = nullptr, *brz = nullptr;
@@ -69,7 +74,7 @@ struct pmfem_dev {
 
 namespace {
 
-constexpr int kNumKernels = 11;
+constexpr int kNumKernels = 12;
 int set_err(pmfem_ctx* c, int code, const std::string& m) {
   if (c) c->err = m;
   return code;
@@ -157,25 +162,27 @@ int select_variants(pmfem_ctx* c) {
   const int va = c->variant[0], vi = c->variant[1], vf = c->variant[2];
   d->lanes_l = c->variant[3] == 0 ? d->auto_l : c->variant[3];
   d->lanes_z = c->variant[3] == 0 ? d->auto_z : c->variant[3];
-  if ((va == 2 && !d->ant_ok) || (vi == 2 && !d->ic_ok) || (vf == 2 && !d->fft_ok) ||
-      (vi == 1 && !d->ic_small_ok))
+  if ((va == 2 && !d->ant_ok) || (va == 3 && !d->sc_ok) || (vi == 2 && !d->ic_ok) ||
+      (vf == 2 && !d->fft_ok) || (vi == 1 && !d->ic_small_ok))
     return set_err(c, PMFEM_EINVAL, "requested kernel form does not fit this problem");
   if (!d->ic_ok && !d->ic_small_ok)
     return set_err(c, PMFEM_EGRID, "near region too dense for the LDS staging of any tile");
-  d->ant_line = va == 0 ? d->ant_ok : va == 2;
+  d->ant_scatter = va == 0 ? d->sc_ok : va == 3;
+  d->ant_line = !d->ant_scatter && (va == 0 ? d->ant_ok : va == 2);
   d->ic_seg = vi == 0 ? d->ic_ok : vi == 2;
   d->fft_plane = vf == 0 ? d->fft_ok : vf == 2;
-  const char* names_split[11] = {"k_charges",   "k_anterp",    "k_r2c_x",     "k_fft_y_fwd",
-                                 "k_fft_z_mul", "k_fft_y_inv", "k_c2r_x",     "k_interp",
-                                 "k_gsum",      "k_zcorr",     "k_exch"};
-  for (int k = 0; k < 11; ++k) d->kname[k] = names_split[k];
+  const char* names_split[12] = {"k_charges", "k_anterp",    "k_r2c_x", "k_fft_y_fwd",
+                                 "k_fft_z_mul", "k_fft_y_inv", "k_c2r_x", "k_interp",
+                                 "k_gsum",    "k_zcorr",     "k_exch",  "-"};
+  for (int k = 0; k < 12; ++k) d->kname[k] = names_split[k];
   if (d->fft_plane) {
     d->kname[2] = "k_fft_xy_fwd";
     d->kname[3] = "-";
     d->kname[5] = "-";
     d->kname[6] = "k_fft_yx_inv";
   }
-  d->kname[1] = d->ant_line ? "k_anterp_line" : "k_anterp";
+  d->kname[1] = d->ant_scatter ? "k_anterp_scatter" : d->ant_line ? "k_anterp_line" : "k_anterp";
+  if (d->ant_scatter) d->kname[11] = "k_anterp_sum";
   d->kname[7] = "k_interp_tile";
   return PMFEM_OK;
 }
@@ -320,6 +327,81 @@ bool build_interp_lists(const HostOps& o, const IcPlan& pl, std::vector<int32_t>
   if ((int64_t)list.size() > 2147483647LL) return false;
   lstart[nwg] = (int32_t)list.size();
   return true;
+}
+
+#ifndef PMFEM_SC_TB
+#define PMFEM_SC_TB 8, 8, 4
+#endif
+#ifndef PMFEM_SC_LDS_BUDGET
+#define PMFEM_SC_LDS_BUDGET 65536
+#endif
+// Scatter plan of anterpolation: tiles of tb boxes per axis (at least p + 1,
+// so that a grid point lies in the footprints of at most two tiles per axis;
+// on a periodic axis at most N - p, so that a footprint does not wrap onto
+// itself), the tile node lists in launch order (tiles x fastest, nodes in box
+// order), and per axis and grid index the covering tiles with the point's
+// offset in their footprints. Returns false if the tiles do not fit.
+bool plan_scatter(const HostOps& o, ScPlan& pl, std::vector<int32_t>& list,
+                  std::vector<int32_t>& lstart, std::vector<int2> tab[3]) {
+  const int p = o.p, shift = (p - 1) / 2;
+  const int want[3] = {PMFEM_SC_TB};
+  auto start = [&](int a, int b) {
+    return o.per[a] ? b - shift : std::min(std::max(b - shift, 0), o.N[a] - p - 1);
+  };
+  for (int a = 0; a < 3; ++a) {
+    int tb = std::max(want[a], p + 1);
+    if (o.per[a]) tb = std::min(tb, o.N[a] - p);
+    tb = std::min(tb, o.nbox[a]);
+    if (tb < 1) return false;
+    pl.tb[a] = tb;
+    pl.nt[a] = (o.nbox[a] + tb - 1) / tb;
+    int fd = 0;
+    tab[a].assign((size_t)2 * o.N[a], make_int2(-1, 0));
+    for (int t = 0; t < pl.nt[a]; ++t) {
+      const int b0 = t * tb, b1 = std::min(b0 + tb, o.nbox[a]) - 1;
+      const int f0 = start(a, b0), w = start(a, b1) + p + 1 - f0;
+      fd = std::max(fd, w);
+      if (o.per[a] && w > o.N[a]) return false;
+      for (int i = 0; i < w; ++i) {
+        int gi = f0 + i;
+        if (o.per[a]) gi = ((gi % o.N[a]) + o.N[a]) % o.N[a];
+        if (gi < 0 || gi >= o.N[a]) return false;
+        int2* e = &tab[a][(size_t)2 * gi];
+        if (e[0].x < 0) e[0] = make_int2(t, i);
+        else if (e[1].x < 0) e[1] = make_int2(t, i);
+        else return false;  // a third covering tile
+      }
+    }
+    pl.fd[a] = fd;
+  }
+  pl.fsize = pl.fd[0] * pl.fd[1] * pl.fd[2];
+  const int nbx = o.nbox[0], nby = o.nbox[1];
+  const std::vector<int32_t>& bs = o.box_start;
+  const int64_t nt = (int64_t)pl.nt[0] * pl.nt[1] * pl.nt[2];
+  lstart.assign(nt + 1, 0);
+  list.clear();
+  list.reserve((size_t)o.n_unk);
+  for (int64_t w = 0; w < nt; ++w) {
+    const int tx = (int)(w % pl.nt[0]);
+    const int64_t r = w / pl.nt[0];
+    const int ty = (int)(r % pl.nt[1]), tz = (int)(r / pl.nt[1]);
+    lstart[w] = (int32_t)list.size();
+    const int x0 = tx * pl.tb[0], x1 = std::min(x0 + pl.tb[0], nbx);
+    for (int bz = tz * pl.tb[2]; bz < std::min((tz + 1) * pl.tb[2], o.nbox[2]); ++bz)
+      for (int by = ty * pl.tb[1]; by < std::min((ty + 1) * pl.tb[1], nby); ++by) {
+        const int64_t row = ((int64_t)bz * nby + by) * nbx;
+        for (int32_t nd = bs[row + x0]; nd < bs[row + x1]; ++nd) list.push_back(nd);
+      }
+  }
+  lstart[nt] = (int32_t)list.size();
+  int64_t ncap = 1;
+  for (int64_t w = 0; w < nt; ++w) ncap = std::max<int64_t>(ncap, lstart[w + 1] - lstart[w]);
+  // staged nodes (16 + 4 bytes each), then the footprint copies
+  const int64_t lds = (ncap + 1) * 20 + (int64_t)pl.fsize * (o.p <= 3 ? 4 : 1) * 4;
+  if (lds > PMFEM_SC_LDS_BUDGET) return false;
+  pl.ncap = (int)ncap;
+  pl.lds_bytes = (int)lds;
+  return (int64_t)list.size() == o.n_unk;
 }
 
 bool build_anterp_lists(const HostOps& o, const std::vector<int2>& bx,
@@ -524,6 +606,19 @@ int upload_all(pmfem_ctx* c) {
     }
   }
   d->ant_threads = std::max(64, std::min(128, (d->ap.xa + 63) / 64 * 64));
+  {
+    std::vector<int32_t> list, lstart;
+    std::vector<int2> tab[3];
+    d->sc_ok = plan_scatter(o, d->sp, list, lstart, tab);
+    if (d->sc_ok) {
+      if ((rc = upload(c, &d->sc_list, list.data(), list.size()))) return rc;
+      if ((rc = upload(c, &d->sc_lstart, lstart.data(), lstart.size()))) return rc;
+      for (int a = 0; a < 3; ++a)
+        if ((rc = upload(c, &d->sc_tab[a], tab[a].data(), tab[a].size()))) return rc;
+      const int64_t nt = (int64_t)d->sp.nt[0] * d->sp.nt[1] * d->sp.nt[2];
+      if ((rc = dalloc(c, &d->sc_part, nt * d->sp.fsize))) return rc;
+    }
+  }
   if ((rc = select_variants(c))) return rc;
   if ((rc = upload(c, &d->brx, bx.data(), bx.size()))) return rc;
   if ((rc = upload(c, &d->bry, by.data(), by.size()))) return rc;
@@ -807,17 +902,49 @@ int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const doubl
     const int64_t ntiles = (int64_t)((g.N[0] + kAntTX - 1) / kAntTX) *
                            ((g.N[1] + kAntTY - 1) / kAntTY) * ((g.N[2] + kAntTZ - 1) / kAntTZ);
     mark(1, 0);
-    if (d->ant_line) {
+    if (d->ant_scatter) {
+      const ScPlan& pl = d->sp;
+      const int64_t nt = (int64_t)pl.nt[0] * pl.nt[1] * pl.nt[2];
+      const size_t lds = (size_t)pl.lds_bytes;
+#define PMFEM_SC_LAUNCH(P)                                                                    \
+  hipLaunchKernelGGL(k_anterp_scatter<P>, dim3((unsigned)nt), dim3(64), lds, s, g, pl, d->q,   \
+                     d->pos4, d->sc_list, d->sc_lstart, d->sc_part)
+      switch (g.p) {
+        case 1:
+          PMFEM_SC_LAUNCH(1);
+          break;
+        case 2:
+          PMFEM_SC_LAUNCH(2);
+          break;
+        case 3:
+          PMFEM_SC_LAUNCH(3);
+          break;
+        case 4:
+          PMFEM_SC_LAUNCH(4);
+          break;
+        default:
+          PMFEM_SC_LAUNCH(5);
+          break;
+      }
+#undef PMFEM_SC_LAUNCH
+      mark(1, 1);
+      mark(11, 0);
+      const int64_t ng = (int64_t)g.N[0] * g.N[1] * g.N[2];
+      hipLaunchKernelGGL(k_anterp_sum, dim3((unsigned)((ng + T - 1) / T)), dim3(T), 0, s, g, pl,
+                         d->sc_tab[0], d->sc_tab[1], d->sc_tab[2], d->sc_part, d->grid);
+      mark(11, 1);
+    } else if (d->ant_line) {
       const AntPlan& pl = d->ap;
       const int64_t nwg = (int64_t)pl.nsx * g.N[1] * g.N[2];
       hipLaunchKernelGGL(k_anterp_line, dim3((unsigned)nwg), dim3(d->ant_threads),
                          (size_t)pl.lds_bytes, s, g, pl, d->q, d->pos4, d->ant_list,
                          d->ant_lstart, d->ant_col, d->brx, d->bry, d->brz, d->grid);
+      mark(1, 1);
     } else {
       hipLaunchKernelGGL(k_anterp, dim3((unsigned)ntiles), dim3(T), 0, s, g, d->q, d->pos4,
                          d->box_start, d->brx, d->bry, d->brz, d->grid);
+      mark(1, 1);
     }
-    mark(1, 1);
     convolve(d, s, d->grid, d->grid, mark);
     (void)hipStreamWaitEvent(s, d->join, 0);
     mark(7, 0);
@@ -946,7 +1073,9 @@ int pmfem_set_variant(pmfem_ctx* c, const char* stage, int32_t variant) {
   if (std::strcmp(stage, "fft") == 0) k = 2;
   if (std::strcmp(stage, "spmv") == 0) k = 3;
   if (k < 0) return set_err(c, PMFEM_EINVAL, "unknown stage");
-  if (k < 3 && (variant < 0 || variant > 2))
+  if (k == 0 && (variant < 0 || variant > 3))
+    return set_err(c, PMFEM_EINVAL, "anterp variant must be 0, 1, 2 or 3");
+  if ((k == 1 || k == 2) && (variant < 0 || variant > 2))
     return set_err(c, PMFEM_EINVAL, "variant must be 0, 1 or 2");
   if (k == 3 && variant != 0 && variant != 4 && variant != 8 && variant != 16)
     return set_err(c, PMFEM_EINVAL, "spmv lanes must be 0, 4, 8 or 16");

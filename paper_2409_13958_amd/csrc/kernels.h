@@ -49,6 +49,18 @@ struct AntPlan {
   int lds_bytes;
 };
 
+// anterpolation by scatter: one 64-lane workgroup per tile of
+// tb[0] x tb[1] x tb[2] boxes, its footprint (the grid points the stencils
+// of its boxes cover) fd[0] x fd[1] x fd[2] points at most
+struct ScPlan {
+  int tb[3];  // boxes per tile along each axis
+  int nt[3];  // tiles along each axis
+  int fd[3];  // footprint extent along each axis (tb + p at most)
+  int fsize;  // fd[0] fd[1] fd[2]
+  int ncap;   // nodes per tile (largest tile)
+  int lds_bytes;
+};
+
 template <int G>
 __global__ void k_rowdot3(int64_t n, const float* m, const int32_t* rp, const int4* rec,
                           float* out);
@@ -58,6 +70,11 @@ __global__ void k_anterp(GridParams g, const float* q, const float4* pos4,
 __global__ void k_anterp_line(GridParams g, AntPlan pl, const float* q, const float4* pos4,
                               const int32_t* list, const int32_t* lstart, const int32_t* colst,
                               const int2* brx, const int2* bry, const int2* brz, float* Q);
+template <int P>
+__global__ void k_anterp_scatter(GridParams g, ScPlan pl, const float* q, const float4* pos4,
+                                 const int32_t* list, const int32_t* lstart, float* part);
+__global__ void k_anterp_sum(GridParams g, ScPlan pl, const int2* tabx, const int2* taby,
+                             const int2* tabz, const float* part, float* Q);
 __global__ void k_r2c_x(GridParams g, const float* Q, float2* spec, const float2* twx,
                         int lines_per_block);
 __global__ void k_fft_y(GridParams g, float2* spec, const float2* twy, int B, int inverse,

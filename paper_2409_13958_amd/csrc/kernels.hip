@@ -413,6 +413,169 @@ __global__ void __launch_bounds__(128) k_anterp_line(
 }
 
 // ---------------------------------------------------------------------------
+// anterpolation by scatter. One 64-lane workgroup per tile of boxes: its
+// nodes (listed on the host, box order) are split among NG groups of GS
+// lanes, node f of the tile going to group f mod NG. A lane of a group owns
+// one (a, b) pair of x and y stencil offsets and adds, for every node of its
+// group, q L_a(xi_x) L_b(xi_y) L_c(xi_z), c = 0..p, to the grid points of the
+// node's stencil in the group's own LDS copy of the tile footprint (the
+// grid points the stencils of the tile's boxes cover). Within an instruction
+// the lanes of a group address distinct points and the groups distinct
+// copies, and each group takes its nodes in a fixed order, so the sums do
+// not depend on timing. The copies are then added in group order and the
+// footprint written out; k_anterp_sum adds, for every grid point, the
+// footprints of the (at most two per axis) tiles that cover it.
+
+// L_a(xi) for compile-time p and a
+template <int P>
+__device__ __forceinline__ float basis_ct(int a, float xi) {
+  if constexpr (P == 3) return cubic_eval(cubic_basis(a), xi);
+  else return lagrange(a, xi, P);
+}
+
+#ifndef PMFEM_SC_ATOMIC
+#define PMFEM_SC_ATOMIC 0
+#endif
+template <int P>
+__global__ void __launch_bounds__(64) k_anterp_scatter(
+    GridParams g, ScPlan pl, const float* __restrict__ q, const float4* __restrict__ pos4,
+    const int32_t* __restrict__ list, const int32_t* __restrict__ lstart,
+    float* __restrict__ part) {
+  constexpr int P1 = P + 1, GS = P1 * P1 <= 16 ? 16 : 64, NG = 64 / GS, K = 8;
+  extern __shared__ float4 s_nd[];  // [ncap + 1] staged nodes (xi, box), then [ncap + 1]
+                                    // charges, then [NG][fsize] footprint copies
+  float* s_qn = reinterpret_cast<float*>(s_nd + pl.ncap + 1);
+  float* s_acc = s_qn + pl.ncap + 1;
+  const int lane = threadIdx.x, grp = lane / GS, gl = lane - grp * GS;
+  const bool act = gl < P1 * P1;
+  const int a = gl % P1, b = gl / P1;  // the lane's x and y stencil offsets
+  const int w = blockIdx.x;
+  const int tx = w % pl.nt[0], rest = w / pl.nt[0];
+  const int ty = rest % pl.nt[1], tz = rest / pl.nt[1];
+  const int l0 = lstart[w], cnt = min(lstart[w + 1] - l0, pl.ncap);
+  // stage the tile's nodes, K loads in flight per lane
+  for (int f0 = lane; f0 < cnt; f0 += 64 * K) {
+    int nd[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) nd[k] = f0 + 64 * k < cnt ? list[l0 + f0 + 64 * k] : 0;
+    float4 ps[K];
+    float qq[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      ps[k] = pos4[nd[k]];
+      qq[k] = q[nd[k]];
+    }
+    // stores past the tile's nodes go to the spare slot ncap, so that no
+    // store (and no load feeding it) sits behind a branch
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int f = f0 + 64 * k < cnt ? f0 + 64 * k : pl.ncap;
+      s_nd[f] = ps[k];
+      s_qn[f] = qq[k];
+    }
+  }
+  // footprint origin: stencil start of the tile's first box on each axis
+  const int fx0 = box_stencil_start(tx * pl.tb[0], g.N[0], P, g.per[0]);
+  const int fy0 = box_stencil_start(ty * pl.tb[1], g.N[1], P, g.per[1]);
+  const int fz0 = box_stencil_start(tz * pl.tb[2], g.N[2], P, g.per[2]);
+  const int FX = pl.fd[0], FXY = pl.fd[0] * pl.fd[1], fsize = pl.fsize;
+  for (int i = lane; i < NG * fsize; i += 64) s_acc[i] = 0.f;
+  __syncthreads();
+  float* acc = s_acc + grp * fsize + b * FX + a;
+  Cubic cxa{}, cyb{};
+  if constexpr (P == 3) {
+    cxa = cubic_basis(a);
+    cyb = cubic_basis(b);
+  }
+  if (act) {
+    for (int f = grp; f < cnt; f += NG) {
+      const float4 ps = s_nd[f];
+      const float qq = s_qn[f];
+      const uint32_t bc = __float_as_uint(ps.w);
+      const int sx = box_stencil_start((int)(bc & 1023u), g.N[0], P, g.per[0]) - fx0;
+      const int sy = box_stencil_start((int)((bc >> 10) & 1023u), g.N[1], P, g.per[1]) - fy0;
+      const int sz = box_stencil_start((int)((bc >> 20) & 1023u), g.N[2], P, g.per[2]) - fz0;
+      float wab;
+      if constexpr (P == 3) wab = qq * cubic_eval(cxa, ps.x) * cubic_eval(cyb, ps.y);
+      else wab = qq * lagrange(a, ps.x, P) * lagrange(b, ps.y, P);
+      float* base = acc + sz * FXY + sy * FX + sx;
+#if PMFEM_SC_ATOMIC
+#pragma unroll
+      for (int c = 0; c < P1; ++c) atomicAdd(base + c * FXY, wab * basis_ct<P>(c, ps.z));
+#else
+      // a plain read-add-write: a group's lanes address distinct points of the
+      // group's own copy, and one wavefront's LDS accesses complete in order
+      float v[P1];
+#pragma unroll
+      for (int c = 0; c < P1; ++c) v[c] = base[c * FXY];
+#pragma unroll
+      for (int c = 0; c < P1; ++c) base[c * FXY] = fmaf(wab, basis_ct<P>(c, ps.z), v[c]);
+      // keep the next node's reads behind these writes (other lanes' points)
+      __builtin_amdgcn_wave_barrier();
+#endif
+    }
+  }
+  __syncthreads();
+  float* out = part + (int64_t)w * fsize;
+  for (int i = lane; i < fsize; i += 64) {
+    float v = s_acc[i];
+#pragma unroll
+    for (int k = 1; k < NG; ++k) v += s_acc[k * fsize + i];
+    out[i] = v;
+  }
+}
+
+#define PMFEM_ANTERP_SCATTER(P)                                                               \
+  template __global__ void k_anterp_scatter<P>(GridParams, ScPlan, const float*, const float4*, \
+                                               const int32_t*, const int32_t*, float*);
+PMFEM_ANTERP_SCATTER(1)
+PMFEM_ANTERP_SCATTER(2)
+PMFEM_ANTERP_SCATTER(3)
+PMFEM_ANTERP_SCATTER(4)
+PMFEM_ANTERP_SCATTER(5)
+
+// Q at every grid point: the sum, z tile outermost, then y, then x, of the
+// footprint values of the tiles covering it; tab_a[2 g + i] = (tile, offset)
+// along axis a, tile < 0 when absent.
+__global__ void __launch_bounds__(256) k_anterp_sum(GridParams g, ScPlan pl,
+                                                    const int2* __restrict__ tabx,
+                                                    const int2* __restrict__ taby,
+                                                    const int2* __restrict__ tabz,
+                                                    const float* __restrict__ part,
+                                                    float* __restrict__ Q) {
+  const int Nx = g.N[0], Ny = g.N[1];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)Nx * Ny * g.N[2]) return;
+  const int gx = (int)(i % Nx);
+  const int64_t r = i / Nx;
+  const int gy = (int)(r % Ny), gz = (int)(r / Ny);
+  const int2 ex0 = tabx[2 * gx], ex1 = tabx[2 * gx + 1];
+  const int2 ey0 = taby[2 * gy], ey1 = taby[2 * gy + 1];
+  const int2 ez0 = tabz[2 * gz], ez1 = tabz[2 * gz + 1];
+  const int FX = pl.fd[0], FY = pl.fd[1];
+  float s = 0.f;
+#pragma unroll
+  for (int kz = 0; kz < 2; ++kz) {
+    const int2 ez = kz ? ez1 : ez0;
+    if (ez.x < 0) continue;
+#pragma unroll
+    for (int ky = 0; ky < 2; ++ky) {
+      const int2 ey = ky ? ey1 : ey0;
+      if (ey.x < 0) continue;
+      const int64_t t0 = ((int64_t)ez.x * pl.nt[1] + ey.x) * pl.nt[0];
+      const int o0 = (ez.y * FY + ey.y) * FX;
+#pragma unroll
+      for (int kx = 0; kx < 2; ++kx) {
+        const int2 ex = kx ? ex1 : ex0;
+        if (ex.x < 0) continue;
+        s += part[(t0 + ex.x) * pl.fsize + o0 + ex.y];
+      }
+    }
+  }
+  Q[i] = s;
+}
+
+// ---------------------------------------------------------------------------
 // LDS radix-2 FFT on `lines` lines of length n, lines `stride` elements apart
 // (a stride of n + 1 keeps column-wise access free of bank conflicts), input
 // in bit-reversed order; decimation in time, natural-order output. lds_fft is

@@ -22,10 +22,11 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-# kernel forms: staged (the default choice) and the basic forms of each stage
+# kernel forms: staged line anterpolation, the basic forms of each stage and
+# scatter anterpolation (the default choice)
 FORMS = {"staged": dict(anterp=2, interp=2, fft=2, spmv=8),
          "basic": dict(anterp=1, interp=1, fft=1, spmv=16),
-         "spmv4": dict(spmv=4)}
+         "scatter": dict(anterp=3, spmv=4)}
 
 
 def lib_fields(prob, m_nodes, forms=None, **kw):

@@ -206,7 +206,8 @@ def test_kernel_variant_arguments_are_checked():
     c.set_variant("interp", 2)
     c.set_variant("fft", 0)
     c.set_variant("spmv", 8)
-    for stage, v in (("anterp", 3), ("interp", -1), ("convolution", 1), ("spmv", 2)):
+    c.set_variant("anterp", 3)
+    for stage, v in (("anterp", 4), ("interp", -1), ("convolution", 1), ("spmv", 2)):
         with pytest.raises(lib.PmfemError) as e:
             c.set_variant(stage, v)
         assert e.value.code == lib.Status.EINVAL
