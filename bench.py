@@ -48,6 +48,8 @@ def kernel_bytes(ctx, names):
         "k_charges": n * (4 + 12 + 4) + nL * 16,
         "k_zcorr": n * (4 + 12 + 4) + nZ * 16,
         "k_anterp": n * (4 + 16) + nbox * 4 + ng * 4,
+        "k_anterp_scatter": n * (4 + 16 + 4),
+        "k_anterp_sum": ng * 4,
         "k_r2c_x": ng * 4 + s_in,
         "k_fft_y_fwd": s_in + s_full,
         "k_fft_z_mul": 2 * s_full + khat,

@@ -394,12 +394,9 @@ bool plan_scatter(const HostOps& o, ScPlan& pl, std::vector<int32_t>& list,
       }
   }
   lstart[nt] = (int32_t)list.size();
-  int64_t ncap = 1;
-  for (int64_t w = 0; w < nt; ++w) ncap = std::max<int64_t>(ncap, lstart[w + 1] - lstart[w]);
-  // staged nodes (16 + 4 bytes each), then the footprint copies
-  const int64_t lds = (ncap + 1) * 20 + (int64_t)pl.fsize * (o.p <= 3 ? 4 : 1) * 4;
+  // the footprint copies, one per lane group (four groups of 16 lanes for p <= 3)
+  const int64_t lds = (int64_t)pl.fsize * (o.p <= 3 ? 4 : 1) * 4;
   if (lds > PMFEM_SC_LDS_BUDGET) return false;
-  pl.ncap = (int)ncap;
   pl.lds_bytes = (int)lds;
   return (int64_t)list.size() == o.n_unk;
 }

@@ -57,7 +57,6 @@ struct ScPlan {
   int nt[3];  // tiles along each axis
   int fd[3];  // footprint extent along each axis (tb + p at most)
   int fsize;  // fd[0] fd[1] fd[2]
-  int ncap;   // nodes per tile (largest tile)
   int lds_bytes;
 };
 

@@ -433,47 +433,37 @@ __device__ __forceinline__ float basis_ct(int a, float xi) {
   else return lagrange(a, xi, P);
 }
 
-#ifndef PMFEM_SC_ATOMIC
-#define PMFEM_SC_ATOMIC 0
-#endif
+// value of lane I of this lane's 16-lane row (DPP row broadcast)
+template <int I>
+__device__ __forceinline__ float row_lane(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + I, 0xf, 0xf, false));
+}
+
 template <int P>
 __global__ void __launch_bounds__(64) k_anterp_scatter(
     GridParams g, ScPlan pl, const float* __restrict__ q, const float4* __restrict__ pos4,
     const int32_t* __restrict__ list, const int32_t* __restrict__ lstart,
     float* __restrict__ part) {
-  constexpr int P1 = P + 1, GS = P1 * P1 <= 16 ? 16 : 64, NG = 64 / GS, K = 8;
-  extern __shared__ float4 s_nd[];  // [ncap + 1] staged nodes (xi, box), then [ncap + 1]
-                                    // charges, then [NG][fsize] footprint copies
-  float* s_qn = reinterpret_cast<float*>(s_nd + pl.ncap + 1);
-  float* s_acc = s_qn + pl.ncap + 1;
+  constexpr int P1 = P + 1, GS = P1 * P1 <= 16 ? 16 : 64, NG = 64 / GS;
+  extern __shared__ float s_acc[];  // [NG][fsize] footprint copies
   const int lane = threadIdx.x, grp = lane / GS, gl = lane - grp * GS;
   const bool act = gl < P1 * P1;
   const int a = gl % P1, b = gl / P1;  // the lane's x and y stencil offsets
   const int w = blockIdx.x;
   const int tx = w % pl.nt[0], rest = w / pl.nt[0];
   const int ty = rest % pl.nt[1], tz = rest / pl.nt[1];
-  const int l0 = lstart[w], cnt = min(lstart[w + 1] - l0, pl.ncap);
-  // stage the tile's nodes, K loads in flight per lane
-  for (int f0 = lane; f0 < cnt; f0 += 64 * K) {
-    int nd[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) nd[k] = f0 + 64 * k < cnt ? list[l0 + f0 + 64 * k] : 0;
-    float4 ps[K];
-    float qq[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      ps[k] = pos4[nd[k]];
-      qq[k] = q[nd[k]];
-    }
-    // stores past the tile's nodes go to the spare slot ncap, so that no
-    // store (and no load feeding it) sits behind a branch
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int f = f0 + 64 * k < cnt ? f0 + 64 * k : pl.ncap;
-      s_nd[f] = ps[k];
-      s_qn[f] = qq[k];
-    }
-  }
+  const int l0 = lstart[w], cnt = lstart[w + 1] - l0;
+  // nodes come in batches of 64, lane L holding node f0 + L; the next batch
+  // is requested while the current one is added
+  auto fetch = [&](int f0, float4& ps, float& qq) {
+    const int f = f0 + lane;
+    const int nd = f < cnt ? list[l0 + f] : 0;
+    ps = pos4[nd];
+    qq = f < cnt ? q[nd] : 0.f;
+  };
+  float4 ps = make_float4(0.f, 0.f, 0.f, 0.f);
+  float qq = 0.f;
+  if (cnt > 0) fetch(0, ps, qq);
   // footprint origin: stencil start of the tile's first box on each axis
   const int fx0 = box_stencil_start(tx * pl.tb[0], g.N[0], P, g.per[0]);
   const int fy0 = box_stencil_start(ty * pl.tb[1], g.N[1], P, g.per[1]);
@@ -487,33 +477,59 @@ __global__ void __launch_bounds__(64) k_anterp_scatter(
     cxa = cubic_basis(a);
     cyb = cubic_basis(b);
   }
-  if (act) {
-    for (int f = grp; f < cnt; f += NG) {
-      const float4 ps = s_nd[f];
-      const float qq = s_qn[f];
-      const uint32_t bc = __float_as_uint(ps.w);
-      const int sx = box_stencil_start((int)(bc & 1023u), g.N[0], P, g.per[0]) - fx0;
-      const int sy = box_stencil_start((int)((bc >> 10) & 1023u), g.N[1], P, g.per[1]) - fy0;
-      const int sz = box_stencil_start((int)((bc >> 20) & 1023u), g.N[2], P, g.per[2]) - fz0;
-      float wab;
-      if constexpr (P == 3) wab = qq * cubic_eval(cxa, ps.x) * cubic_eval(cyb, ps.y);
-      else wab = qq * lagrange(a, ps.x, P) * lagrange(b, ps.y, P);
-      float* base = acc + sz * FXY + sy * FX + sx;
-#if PMFEM_SC_ATOMIC
+  // one node: its stencil's contributions on the lane's (a, b) column, a
+  // plain read-add-write (the lanes of a group address distinct points of
+  // the group's own copy, and one wavefront's LDS accesses complete in order)
+  auto add = [&](const float4& p, float qv) {
+    const uint32_t bc = __float_as_uint(p.w);
+    const int sx = box_stencil_start((int)(bc & 1023u), g.N[0], P, g.per[0]) - fx0;
+    const int sy = box_stencil_start((int)((bc >> 10) & 1023u), g.N[1], P, g.per[1]) - fy0;
+    const int sz = box_stencil_start((int)((bc >> 20) & 1023u), g.N[2], P, g.per[2]) - fz0;
+    float wab;
+    if constexpr (P == 3) wab = qv * cubic_eval(cxa, p.x) * cubic_eval(cyb, p.y);
+    else wab = qv * lagrange(a, p.x, P) * lagrange(b, p.y, P);
+    float* base = acc + sz * FXY + sy * FX + sx;
+    float v[P1];
 #pragma unroll
-      for (int c = 0; c < P1; ++c) atomicAdd(base + c * FXY, wab * basis_ct<P>(c, ps.z));
-#else
-      // a plain read-add-write: a group's lanes address distinct points of the
-      // group's own copy, and one wavefront's LDS accesses complete in order
-      float v[P1];
+    for (int c = 0; c < P1; ++c) v[c] = base[c * FXY];
 #pragma unroll
-      for (int c = 0; c < P1; ++c) v[c] = base[c * FXY];
-#pragma unroll
-      for (int c = 0; c < P1; ++c) base[c * FXY] = fmaf(wab, basis_ct<P>(c, ps.z), v[c]);
-      // keep the next node's reads behind these writes (other lanes' points)
-      __builtin_amdgcn_wave_barrier();
-#endif
+    for (int c = 0; c < P1; ++c) base[c * FXY] = fmaf(wab, basis_ct<P>(c, p.z), v[c]);
+    // keep the next node's reads behind these writes (other lanes' points)
+    __builtin_amdgcn_wave_barrier();
+  };
+  for (int f0 = 0; f0 < cnt; f0 += 64) {
+    float4 psn = make_float4(0.f, 0.f, 0.f, 0.f);
+    float qqn = 0.f;
+    if (f0 + 64 < cnt) fetch(f0 + 64, psn, qqn);
+    const int nb = min(64, cnt - f0);
+    if constexpr (GS == 16) {
+      // group g adds the nodes of its row's lanes 0..15 in order
+      const int mine = nb - 16 * grp;  // nodes of this batch in the group's row
+#define PMFEM_SC_NODE(I)                                                                   \
+  {                                                                                        \
+    const float4 p = make_float4(row_lane<I>(ps.x), row_lane<I>(ps.y), row_lane<I>(ps.z), \
+                                 row_lane<I>(ps.w));                                       \
+    const float qv = row_lane<I>(qq);                                                      \
+    if (act && I < mine) add(p, qv);                                                       \
+  }
+      PMFEM_SC_NODE(0) PMFEM_SC_NODE(1) PMFEM_SC_NODE(2) PMFEM_SC_NODE(3)
+      PMFEM_SC_NODE(4) PMFEM_SC_NODE(5) PMFEM_SC_NODE(6) PMFEM_SC_NODE(7)
+      PMFEM_SC_NODE(8) PMFEM_SC_NODE(9) PMFEM_SC_NODE(10) PMFEM_SC_NODE(11)
+      PMFEM_SC_NODE(12) PMFEM_SC_NODE(13) PMFEM_SC_NODE(14) PMFEM_SC_NODE(15)
+#undef PMFEM_SC_NODE
+    } else {
+      // one group: every lane adds node i of the batch
+      for (int i = 0; i < nb; ++i) {
+        const float4 pi = make_float4(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(ps.x), i)),
+                                      __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ps.y), i)),
+                                      __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ps.z), i)),
+                                      __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ps.w), i)));
+        const float qv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qq), i));
+        if (act) add(pi, qv);
+      }
     }
+    ps = psn;
+    qq = qqn;
   }
   __syncthreads();
   float* out = part + (int64_t)w * fsize;
