@@ -2,7 +2,8 @@
 //
 // One H_eff evaluation (paper Eqs. heff, hex, hms_d1 - hms_d3):
 //   k_rowdot3      q = D m (Eq. hms_d1); on a second stream u_Z = Z0 m (Eq. hms_d2b)
-//   k_anterp_line  Q = W^T q                      (Sec. 3.2.2, step 1; k_anterp: tile form)
+//   k_anterp_scatter, k_anterp_sum  Q = W^T q      (Sec. 3.2.2, step 1; other forms:
+//                  k_anterp_line by grid lines, k_anterp by tiles, both gathers)
 //   k_fft_xy_fwd   real-to-complex FFT along x, FFT along y, per z-plane (step 2)
 //   k_fft_z_mul    FFT along z, multiply by the PGF spectrum, inverse along z
 //   k_fft_yx_inv   inverse FFT along y, complex-to-real along x -> U = (1/4 pi) K * Q
