@@ -927,8 +927,12 @@ int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const doubl
       mark(1, 1);
       mark(11, 0);
       const int64_t ng = (int64_t)g.N[0] * g.N[1] * g.N[2];
-      hipLaunchKernelGGL(k_anterp_sum, dim3((unsigned)((ng + T - 1) / T)), dim3(T), 0, s, g, pl,
-                         d->sc_tab[0], d->sc_tab[1], d->sc_tab[2], d->sc_part, d->grid);
+      if (g.N[0] % 4 == 0)
+        hipLaunchKernelGGL(k_anterp_sum<4>, dim3((unsigned)((ng / 4 + T - 1) / T)), dim3(T), 0, s,
+                           g, pl, d->sc_tab[0], d->sc_tab[1], d->sc_tab[2], d->sc_part, d->grid);
+      else
+        hipLaunchKernelGGL(k_anterp_sum<1>, dim3((unsigned)((ng + T - 1) / T)), dim3(T), 0, s, g,
+                           pl, d->sc_tab[0], d->sc_tab[1], d->sc_tab[2], d->sc_part, d->grid);
       mark(11, 1);
     } else if (d->ant_line) {
       const AntPlan& pl = d->ap;

@@ -72,6 +72,7 @@ __global__ void k_anterp_line(GridParams g, AntPlan pl, const float* q, const fl
 template <int P>
 __global__ void k_anterp_scatter(GridParams g, ScPlan pl, const float* q, const float4* pos4,
                                  const int32_t* list, const int32_t* lstart, float* part);
+template <int PT>
 __global__ void k_anterp_sum(GridParams g, ScPlan pl, const int2* tabx, const int2* taby,
                              const int2* tabz, const float* part, float* Q);
 __global__ void k_r2c_x(GridParams g, const float* Q, float2* spec, const float2* twx,

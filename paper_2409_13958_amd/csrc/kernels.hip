@@ -130,6 +130,22 @@ __device__ __forceinline__ float group_sum(float v) {
   return v;
 }
 
+// Entries e0 + lane, e0 + lane + G, ... of a row, K records of a lane in
+// flight at once: all K record loads, then the K uses (which issue their
+// gathers together). A record past the row end re-reads entry e (valid) and
+// is passed on with ok = false; the sum order is the entry order.
+template <int G, int K, class Rec, class Use>
+__device__ __forceinline__ void row_entries(int e0, int e1, int lane, const Rec* __restrict__ rec,
+                                            Use&& use) {
+  for (int e = e0 + lane; e < e1; e += K * G) {
+    Rec r[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] = rec[e + k * G < e1 ? e + k * G : e];
+#pragma unroll
+    for (int k = 0; k < K; ++k) use(r[k], e + k * G < e1);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // charges and element-exact correction, G lanes per row, one 16-byte record
 // {column, x, y, z} per entry (one vector load):
@@ -147,15 +163,13 @@ __global__ void __launch_bounds__(256) k_rowdot3(int64_t n, const float* __restr
   const int lane = threadIdx.x & (G - 1);
   if (row >= n) return;  // whole groups leave together
   float acc = 0.f;
-  const int e0 = rp[row], e1 = rp[row + 1];
-#pragma unroll 2
-  for (int e = e0 + lane; e < e1; e += G) {
-    const int4 r = rec[e];
+  row_entries<G, 4>(rp[row], rp[row + 1], lane, rec, [&](const int4& r, bool ok) {
     const float* mk = m + 3 * (int64_t)r.x;
-    acc = fmaf(__int_as_float(r.y), mk[0], acc);
-    acc = fmaf(__int_as_float(r.z), mk[1], acc);
-    acc = fmaf(__int_as_float(r.w), mk[2], acc);
-  }
+    const float m0 = mk[0], m1 = mk[1], m2 = mk[2];
+    acc = fmaf(ok ? __int_as_float(r.y) : 0.f, m0, acc);
+    acc = fmaf(ok ? __int_as_float(r.z) : 0.f, m1, acc);
+    acc = fmaf(ok ? __int_as_float(r.w) : 0.f, m2, acc);
+  });
   acc = group_sum<G>(acc);
   if (lane == 0) out[row] = acc;
 }
@@ -553,7 +567,9 @@ PMFEM_ANTERP_SCATTER(5)
 
 // Q at every grid point: the sum, z tile outermost, then y, then x, of the
 // footprint values of the tiles covering it; tab_a[2 g + i] = (tile, offset)
-// along axis a, tile < 0 when absent.
+// along axis a, tile < 0 when absent. A thread takes PT consecutive x points
+// of one grid line (PT divides Nx), sharing their y and z entries.
+template <int PT>
 __global__ void __launch_bounds__(256) k_anterp_sum(GridParams g, ScPlan pl,
                                                     const int2* __restrict__ tabx,
                                                     const int2* __restrict__ taby,
@@ -561,16 +577,23 @@ __global__ void __launch_bounds__(256) k_anterp_sum(GridParams g, ScPlan pl,
                                                     const float* __restrict__ part,
                                                     float* __restrict__ Q) {
   const int Nx = g.N[0], Ny = g.N[1];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)Nx * Ny * g.N[2]) return;
-  const int gx = (int)(i % Nx);
-  const int64_t r = i / Nx;
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * PT;
+  if (i0 >= (int64_t)Nx * Ny * g.N[2]) return;
+  const int gx0 = (int)(i0 % Nx);
+  const int64_t r = i0 / Nx;
   const int gy = (int)(r % Ny), gz = (int)(r / Ny);
-  const int2 ex0 = tabx[2 * gx], ex1 = tabx[2 * gx + 1];
+  int2 ex[PT][2];
+#pragma unroll
+  for (int k = 0; k < PT; ++k) {
+    ex[k][0] = tabx[2 * (gx0 + k)];
+    ex[k][1] = tabx[2 * (gx0 + k) + 1];
+  }
   const int2 ey0 = taby[2 * gy], ey1 = taby[2 * gy + 1];
   const int2 ez0 = tabz[2 * gz], ez1 = tabz[2 * gz + 1];
   const int FX = pl.fd[0], FY = pl.fd[1];
-  float s = 0.f;
+  float sum[PT];
+#pragma unroll
+  for (int k = 0; k < PT; ++k) sum[k] = 0.f;
 #pragma unroll
   for (int kz = 0; kz < 2; ++kz) {
     const int2 ez = kz ? ez1 : ez0;
@@ -582,15 +605,22 @@ __global__ void __launch_bounds__(256) k_anterp_sum(GridParams g, ScPlan pl,
       const int64_t t0 = ((int64_t)ez.x * pl.nt[1] + ey.x) * pl.nt[0];
       const int o0 = (ez.y * FY + ey.y) * FX;
 #pragma unroll
-      for (int kx = 0; kx < 2; ++kx) {
-        const int2 ex = kx ? ex1 : ex0;
-        if (ex.x < 0) continue;
-        s += part[(t0 + ex.x) * pl.fsize + o0 + ex.y];
-      }
+      for (int k = 0; k < PT; ++k)
+#pragma unroll
+        for (int kx = 0; kx < 2; ++kx) {
+          const int2 e = ex[k][kx];
+          if (e.x >= 0) sum[k] += part[(t0 + e.x) * pl.fsize + o0 + e.y];
+        }
     }
   }
-  Q[i] = s;
+#pragma unroll
+  for (int k = 0; k < PT; ++k) Q[i0 + k] = sum[k];
 }
+
+template __global__ void k_anterp_sum<1>(GridParams, ScPlan, const int2*, const int2*,
+                                         const int2*, const float*, float*);
+template __global__ void k_anterp_sum<4>(GridParams, ScPlan, const int2*, const int2*,
+                                         const int2*, const float*, float*);
 
 // ---------------------------------------------------------------------------
 // LDS radix-2 FFT on `lines` lines of length n, lines `stride` elements apart
@@ -1176,16 +1206,14 @@ __global__ void __launch_bounds__(256) k_exch(int64_t n, const int32_t* __restri
   const int lane = threadIdx.x & (G - 1);
   if (row >= n) return;  // whole groups leave together
   float hx = 0.f, hy = 0.f, hz = 0.f;
-  const int e0 = rp[row], e1 = rp[row + 1];
-#pragma unroll 2
-  for (int e = e0 + lane; e < e1; e += G) {
-    const int2 r = lrec[e];
+  row_entries<G, 4>(rp[row], rp[row + 1], lane, lrec, [&](const int2& r, bool ok) {
     const float* mk = m + 3 * (int64_t)r.x;
-    const float w = __int_as_float(r.y);
-    hx = fmaf(w, mk[0], hx);
-    hy = fmaf(w, mk[1], hy);
-    hz = fmaf(w, mk[2], hz);
-  }
+    const float m0 = mk[0], m1 = mk[1], m2 = mk[2];
+    const float w = ok ? __int_as_float(r.y) : 0.f;
+    hx = fmaf(w, m0, hx);
+    hy = fmaf(w, m1, hy);
+    hz = fmaf(w, m2, hz);
+  });
   hx = group_sum<G>(hx);
   hy = group_sum<G>(hy);
   hz = group_sum<G>(hz);
@@ -1208,15 +1236,13 @@ __global__ void __launch_bounds__(256) k_gsum(int64_t n, const int32_t* __restri
   if (row >= n) return;  // whole groups leave together
   float hx = 0.f, hy = 0.f, hz = 0.f;
   if (with_ms) {
-    const int e0 = rp[row], e1 = rp[row + 1];
-#pragma unroll 2
-    for (int e = e0 + lane; e < e1; e += G) {
-      const int4 r = grec[e];
-      const float uk = u[r.x];
+    row_entries<G, 4>(rp[row], rp[row + 1], lane, grec, [&](const int4& r, bool ok) {
+      const float uv = u[r.x];
+      const float uk = ok ? uv : 0.f;
       hx = fmaf(-__int_as_float(r.y), uk, hx);
       hy = fmaf(-__int_as_float(r.z), uk, hy);
       hz = fmaf(-__int_as_float(r.w), uk, hz);
-    }
+    });
     hx = group_sum<G>(hx);
     hy = group_sum<G>(hy);
     hz = group_sum<G>(hz);
