@@ -29,7 +29,8 @@ struct pmfem_dev {
   int ant_threads = 0;
   ScPlan sp{};              // scatter form of anterpolation
   bool sc_ok = false, ant_scatter = false;
-  int32_t *sc_list = nullptr, *sc_lstart = nullptr;  // nodes of every tile, box order
+  int2* sc_list = nullptr;     // {node, stencil offset in the footprint} of every tile, box order
+  int32_t* sc_lstart = nullptr;
   int2* sc_tab[3] = {};     // per axis and grid index: (tile, offset) of the covering tiles
   float* sc_part = nullptr; // footprint sums of every tile
   IcPlan icp{}, icp_small{};  // interpolation+precorrection tiles: chosen, narrow
@@ -341,7 +342,7 @@ bool build_interp_lists(const HostOps& o, const IcPlan& pl, std::vector<int32_t>
 // itself), the tile node lists in launch order (tiles x fastest, nodes in box
 // order), and per axis and grid index the covering tiles with the point's
 // offset in their footprints. Returns false if the tiles do not fit.
-bool plan_scatter(const HostOps& o, ScPlan& pl, std::vector<int32_t>& list,
+bool plan_scatter(const HostOps& o, ScPlan& pl, std::vector<int2>& list,
                   std::vector<int32_t>& lstart, std::vector<int2> tab[3]) {
   const int p = o.p, shift = (p - 1) / 2;
   const int want[3] = {PMFEM_SC_TB};
@@ -387,10 +388,16 @@ bool plan_scatter(const HostOps& o, ScPlan& pl, std::vector<int32_t>& list,
     const int ty = (int)(r % pl.nt[1]), tz = (int)(r / pl.nt[1]);
     lstart[w] = (int32_t)list.size();
     const int x0 = tx * pl.tb[0], x1 = std::min(x0 + pl.tb[0], nbx);
-    for (int bz = tz * pl.tb[2]; bz < std::min((tz + 1) * pl.tb[2], o.nbox[2]); ++bz)
-      for (int by = ty * pl.tb[1]; by < std::min((ty + 1) * pl.tb[1], nby); ++by) {
+    const int y0 = ty * pl.tb[1], z0 = tz * pl.tb[2];
+    for (int bz = z0; bz < std::min(z0 + pl.tb[2], o.nbox[2]); ++bz)
+      for (int by = y0; by < std::min(y0 + pl.tb[1], nby); ++by) {
         const int64_t row = ((int64_t)bz * nby + by) * nbx;
-        for (int32_t nd = bs[row + x0]; nd < bs[row + x1]; ++nd) list.push_back(nd);
+        const int oz = start(2, bz) - start(2, z0), oy = start(1, by) - start(1, y0);
+        for (int bx = x0; bx < x1; ++bx) {
+          // offset of the box's stencil origin in the tile footprint
+          const int off = (oz * pl.fd[1] + oy) * pl.fd[0] + start(0, bx) - start(0, x0);
+          for (int32_t nd = bs[row + bx]; nd < bs[row + bx + 1]; ++nd) list.push_back(make_int2(nd, off));
+        }
       }
   }
   lstart[nt] = (int32_t)list.size();
@@ -604,7 +611,8 @@ int upload_all(pmfem_ctx* c) {
   }
   d->ant_threads = std::max(64, std::min(128, (d->ap.xa + 63) / 64 * 64));
   {
-    std::vector<int32_t> list, lstart;
+    std::vector<int2> list;
+    std::vector<int32_t> lstart;
     std::vector<int2> tab[3];
     d->sc_ok = plan_scatter(o, d->sp, list, lstart, tab);
     if (d->sc_ok) {

@@ -71,7 +71,7 @@ __global__ void k_anterp_line(GridParams g, AntPlan pl, const float* q, const fl
                               const int2* brx, const int2* bry, const int2* brz, float* Q);
 template <int P>
 __global__ void k_anterp_scatter(GridParams g, ScPlan pl, const float* q, const float4* pos4,
-                                 const int32_t* list, const int32_t* lstart, float* part);
+                                 const int2* list, const int32_t* lstart, float* part);
 template <int PT>
 __global__ void k_anterp_sum(GridParams g, ScPlan pl, const int2* tabx, const int2* taby,
                              const int2* tabz, const float* part, float* Q);

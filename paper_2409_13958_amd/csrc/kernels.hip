@@ -429,9 +429,11 @@ __global__ void __launch_bounds__(128) k_anterp_line(
 
 // ---------------------------------------------------------------------------
 // anterpolation by scatter. One 64-lane workgroup per tile of boxes: its
-// nodes (listed on the host, box order) are split among NG groups of GS
-// lanes, node f of the tile going to group f mod NG. A lane of a group owns
-// one (a, b) pair of x and y stencil offsets and adds, for every node of its
+// nodes (listed on the host in box order, each with the offset of its box's
+// stencil in the tile footprint) come in batches of 64, one per lane, and the
+// 16 nodes of a 16-lane row go to that row's lane group (DPP broadcasts
+// within the row; one 64-lane group for p > 3). A lane of a group owns one
+// (a, b) pair of x and y stencil offsets and adds, for every node of its
 // group, q L_a(xi_x) L_b(xi_y) L_c(xi_z), c = 0..p, to the grid points of the
 // node's stencil in the group's own LDS copy of the tile footprint (the
 // grid points the stencils of the tile's boxes cover). Within an instruction
@@ -457,75 +459,79 @@ __device__ __forceinline__ float row_lane(float v) {
 template <int P>
 __global__ void __launch_bounds__(64) k_anterp_scatter(
     GridParams g, ScPlan pl, const float* __restrict__ q, const float4* __restrict__ pos4,
-    const int32_t* __restrict__ list, const int32_t* __restrict__ lstart,
+    const int2* __restrict__ list, const int32_t* __restrict__ lstart,
     float* __restrict__ part) {
   constexpr int P1 = P + 1, GS = P1 * P1 <= 16 ? 16 : 64, NG = 64 / GS;
   extern __shared__ float s_acc[];  // [NG][fsize] footprint copies
   const int lane = threadIdx.x, grp = lane / GS, gl = lane - grp * GS;
   const bool act = gl < P1 * P1;
-  const int a = gl % P1, b = gl / P1;  // the lane's x and y stencil offsets
+  // the lane's x and y stencil offsets; lane c of a group (b = 0) also
+  // evaluates the z weight of index c for the group
+  const int a = gl % P1, b = gl / P1;
   const int w = blockIdx.x;
-  const int tx = w % pl.nt[0], rest = w / pl.nt[0];
-  const int ty = rest % pl.nt[1], tz = rest / pl.nt[1];
   const int l0 = lstart[w], cnt = lstart[w + 1] - l0;
-  // nodes come in batches of 64, lane L holding node f0 + L; the next batch
-  // is requested while the current one is added
-  auto fetch = [&](int f0, float4& ps, float& qq) {
+  // nodes come in batches of 64, lane L holding entry f0 + L of the tile's
+  // list {node, footprint offset of its stencil}; the next batch is requested
+  // while the current one is added
+  auto fetch = [&](int f0, float4& ps, float& qq, int& off) {
     const int f = f0 + lane;
-    const int nd = f < cnt ? list[l0 + f] : 0;
-    ps = pos4[nd];
-    qq = f < cnt ? q[nd] : 0.f;
+    const int2 e = list[l0 + (f < cnt ? f : 0)];
+    ps = pos4[e.x];
+    qq = f < cnt ? q[e.x] : 0.f;
+    off = e.y;
   };
   float4 ps = make_float4(0.f, 0.f, 0.f, 0.f);
   float qq = 0.f;
-  if (cnt > 0) fetch(0, ps, qq);
-  // footprint origin: stencil start of the tile's first box on each axis
-  const int fx0 = box_stencil_start(tx * pl.tb[0], g.N[0], P, g.per[0]);
-  const int fy0 = box_stencil_start(ty * pl.tb[1], g.N[1], P, g.per[1]);
-  const int fz0 = box_stencil_start(tz * pl.tb[2], g.N[2], P, g.per[2]);
-  const int FX = pl.fd[0], FXY = pl.fd[0] * pl.fd[1], fsize = pl.fsize;
+  int ofs = 0;
+  if (cnt > 0) fetch(0, ps, qq, ofs);
+  const int FXY = pl.fd[0] * pl.fd[1], fsize = pl.fsize;
   for (int i = lane; i < NG * fsize; i += 64) s_acc[i] = 0.f;
   __syncthreads();
-  float* acc = s_acc + grp * fsize + b * FX + a;
+  float* acc = s_acc + grp * fsize + b * pl.fd[0] + a;
   Cubic cxa{}, cyb{};
   if constexpr (P == 3) {
     cxa = cubic_basis(a);
     cyb = cubic_basis(b);
   }
+  auto lane_basis = [&](int k, const Cubic& ck, float xi) {
+    if constexpr (P == 3) return cubic_eval(ck, xi);
+    else return lagrange(k, xi, P);
+  };
   // one node: its stencil's contributions on the lane's (a, b) column, a
   // plain read-add-write (the lanes of a group address distinct points of
   // the group's own copy, and one wavefront's LDS accesses complete in order)
-  auto add = [&](const float4& p, float qv) {
-    const uint32_t bc = __float_as_uint(p.w);
-    const int sx = box_stencil_start((int)(bc & 1023u), g.N[0], P, g.per[0]) - fx0;
-    const int sy = box_stencil_start((int)((bc >> 10) & 1023u), g.N[1], P, g.per[1]) - fy0;
-    const int sz = box_stencil_start((int)((bc >> 20) & 1023u), g.N[2], P, g.per[2]) - fz0;
-    float wab;
-    if constexpr (P == 3) wab = qv * cubic_eval(cxa, p.x) * cubic_eval(cyb, p.y);
-    else wab = qv * lagrange(a, p.x, P) * lagrange(b, p.y, P);
-    float* base = acc + sz * FXY + sy * FX + sx;
+  auto add = [&](float px, float py, float qv, int off, const float* lz) {
+    const float wab = qv * lane_basis(a, cxa, px) * lane_basis(b, cyb, py);
+    float* base = acc + off;
     float v[P1];
 #pragma unroll
     for (int c = 0; c < P1; ++c) v[c] = base[c * FXY];
 #pragma unroll
-    for (int c = 0; c < P1; ++c) base[c * FXY] = fmaf(wab, basis_ct<P>(c, p.z), v[c]);
+    for (int c = 0; c < P1; ++c) base[c * FXY] = fmaf(wab, lz[c], v[c]);
     // keep the next node's reads behind these writes (other lanes' points)
     __builtin_amdgcn_wave_barrier();
   };
   for (int f0 = 0; f0 < cnt; f0 += 64) {
     float4 psn = make_float4(0.f, 0.f, 0.f, 0.f);
     float qqn = 0.f;
-    if (f0 + 64 < cnt) fetch(f0 + 64, psn, qqn);
+    int ofsn = 0;
+    if (f0 + 64 < cnt) fetch(f0 + 64, psn, qqn, ofsn);
     const int nb = min(64, cnt - f0);
     if constexpr (GS == 16) {
       // group g adds the nodes of its row's lanes 0..15 in order
       const int mine = nb - 16 * grp;  // nodes of this batch in the group's row
-#define PMFEM_SC_NODE(I)                                                                   \
-  {                                                                                        \
-    const float4 p = make_float4(row_lane<I>(ps.x), row_lane<I>(ps.y), row_lane<I>(ps.z), \
-                                 row_lane<I>(ps.w));                                       \
-    const float qv = row_lane<I>(qq);                                                      \
-    if (act && I < mine) add(p, qv);                                                       \
+#define PMFEM_SC_NODE(I)                                                                     \
+  {                                                                                          \
+    const float px = row_lane<I>(ps.x), py = row_lane<I>(ps.y), pz = row_lane<I>(ps.z);     \
+    const float qv = row_lane<I>(qq);                                                        \
+    const int off = __float_as_int(row_lane<I>(__int_as_float(ofs)));                        \
+    const float lzm = lane_basis(a, cxa, pz);                                                \
+    float lz[P1];                                                                            \
+    lz[0] = row_lane<0>(lzm);                                                                \
+    if constexpr (P1 > 1) lz[1 % P1] = row_lane<1>(lzm);                                     \
+    if constexpr (P1 > 2) lz[2 % P1] = row_lane<2>(lzm);                                     \
+    if constexpr (P1 > 3) lz[3 % P1] = row_lane<3>(lzm);                                     \
+    if (act && I < mine) add(px, py, qv, off, lz);                                           \
   }
       PMFEM_SC_NODE(0) PMFEM_SC_NODE(1) PMFEM_SC_NODE(2) PMFEM_SC_NODE(3)
       PMFEM_SC_NODE(4) PMFEM_SC_NODE(5) PMFEM_SC_NODE(6) PMFEM_SC_NODE(7)
@@ -535,16 +541,22 @@ __global__ void __launch_bounds__(64) k_anterp_scatter(
     } else {
       // one group: every lane adds node i of the batch
       for (int i = 0; i < nb; ++i) {
-        const float4 pi = make_float4(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(ps.x), i)),
-                                      __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ps.y), i)),
-                                      __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ps.z), i)),
-                                      __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ps.w), i)));
-        const float qv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qq), i));
-        if (act) add(pi, qv);
+        auto bc = [&](float v) {
+          return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
+        };
+        const float px = bc(ps.x), py = bc(ps.y), pz = bc(ps.z), qv = bc(qq);
+        const int off = __builtin_amdgcn_readlane(ofs, i);
+        const float lzm = lane_basis(a, cxa, pz);
+        float lz[P1];
+#pragma unroll
+        for (int c = 0; c < P1; ++c)
+          lz[c] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lzm), c));
+        if (act) add(px, py, qv, off, lz);
       }
     }
     ps = psn;
     qq = qqn;
+    ofs = ofsn;
   }
   __syncthreads();
   float* out = part + (int64_t)w * fsize;
@@ -558,7 +570,7 @@ __global__ void __launch_bounds__(64) k_anterp_scatter(
 
 #define PMFEM_ANTERP_SCATTER(P)                                                               \
   template __global__ void k_anterp_scatter<P>(GridParams, ScPlan, const float*, const float4*, \
-                                               const int32_t*, const int32_t*, float*);
+                                               const int2*, const int32_t*, float*);
 PMFEM_ANTERP_SCATTER(1)
 PMFEM_ANTERP_SCATTER(2)
 PMFEM_ANTERP_SCATTER(3)
