@@ -603,17 +603,15 @@ __global__ void __launch_bounds__(256) k_anterp_sum(GridParams g, ScPlan pl,
   const int2 ey0 = taby[2 * gy], ey1 = taby[2 * gy + 1];
   const int2 ez0 = tabz[2 * gz], ez1 = tabz[2 * gz + 1];
   const int FX = pl.fd[0], FY = pl.fd[1];
-  float sum[PT];
-#pragma unroll
-  for (int k = 0; k < PT; ++k) sum[k] = 0.f;
+  // all 8 PT candidate values are loaded at once (an absent tile reads entry
+  // 0 and counts as zero), so that no load waits behind a branch
+  float val[2][2][PT][2];
 #pragma unroll
   for (int kz = 0; kz < 2; ++kz) {
     const int2 ez = kz ? ez1 : ez0;
-    if (ez.x < 0) continue;
 #pragma unroll
     for (int ky = 0; ky < 2; ++ky) {
       const int2 ey = ky ? ey1 : ey0;
-      if (ey.x < 0) continue;
       const int64_t t0 = ((int64_t)ez.x * pl.nt[1] + ey.x) * pl.nt[0];
       const int o0 = (ez.y * FY + ey.y) * FX;
 #pragma unroll
@@ -621,9 +619,22 @@ __global__ void __launch_bounds__(256) k_anterp_sum(GridParams g, ScPlan pl,
 #pragma unroll
         for (int kx = 0; kx < 2; ++kx) {
           const int2 e = ex[k][kx];
-          if (e.x >= 0) sum[k] += part[(t0 + e.x) * pl.fsize + o0 + e.y];
+          const bool ok = ez.x >= 0 && ey.x >= 0 && e.x >= 0;
+          val[kz][ky][k][kx] = part[ok ? (t0 + e.x) * pl.fsize + o0 + e.y : 0];
+          if (!ok) val[kz][ky][k][kx] = 0.f;
         }
     }
+  }
+  float sum[PT];
+#pragma unroll
+  for (int k = 0; k < PT; ++k) {
+    sum[k] = 0.f;
+#pragma unroll
+    for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+      for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+        for (int kx = 0; kx < 2; ++kx) sum[k] += val[kz][ky][k][kx];
   }
 #pragma unroll
   for (int k = 0; k < PT; ++k) Q[i0 + k] = sum[k];
