@@ -651,27 +651,62 @@ template __global__ void k_anterp_sum<4>(GridParams, ScPlan, const int2*, const 
 // in bit-reversed order; decimation in time, natural-order output. lds_fft is
 // the contiguous case.
 
+__device__ __forceinline__ void radix2(float2& a, float2& b, float2 w) {
+  const float2 t = make_float2(b.x * w.x - b.y * w.y, b.x * w.y + b.y * w.x);
+  b = make_float2(a.x - t.x, a.y - t.y);
+  a = make_float2(a.x + t.x, a.y + t.y);
+}
+
 __device__ void lds_fft_s(float2* buf, int n, int logn, int lines, int stride, const float2* tw,
                           float sign) {
-  // radix-2 decimation in time; n = 2^logn, so every index split is a shift
-  const int lh = logn - 1;  // log2(n / 2)
-  const int total = lines << lh;
-  for (int s = 1; s <= logn; ++s) {
-    const int ls = s - 1;  // log2(half)
+  // radix-2 decimation in time; n = 2^logn, so every index split is a shift.
+  // Stages s and s + 1 are done together by one thread per 4 elements (the
+  // same four butterflies, in registers), so a pair of stages costs one LDS
+  // round trip and one barrier.
+  int s = 1;
+  for (; s + 1 <= logn; s += 2) {
+    const int ls = s - 1;  // log2(h), h the half of stage s
+    const int h = 1 << ls;
+    const int total = lines << (logn - 2);
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+      const int line = idx >> (logn - 2);
+      const int j = idx & ((1 << (logn - 2)) - 1);
+      const int k = j & (h - 1);
+      const int i0 = line * stride + ((j >> ls) << (ls + 2)) + k;
+      float2 w1 = tw[k << (logn - s)];
+      float2 w2 = tw[k << (logn - s - 1)];
+      float2 w3 = tw[(k + h) << (logn - s - 1)];
+      w1.y *= sign;
+      w2.y *= sign;
+      w3.y *= sign;
+      float2 a0 = buf[i0], a1 = buf[i0 + h], a2 = buf[i0 + 2 * h], a3 = buf[i0 + 3 * h];
+      radix2(a0, a1, w1);
+      radix2(a2, a3, w1);
+      radix2(a0, a2, w2);
+      radix2(a1, a3, w3);
+      buf[i0] = a0;
+      buf[i0 + h] = a1;
+      buf[i0 + 2 * h] = a2;
+      buf[i0 + 3 * h] = a3;
+    }
+    __syncthreads();
+  }
+  if (s == logn) {  // a last single stage
+    const int ls = s - 1;
     const int half = 1 << ls;
-    const int tsh = logn - s;  // log2(twiddle step)
+    const int lh = logn - 1;
+    const int total = lines << lh;
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
       const int line = idx >> lh;
       const int j = idx & ((1 << lh) - 1);
       const int k = j & (half - 1);
       const int i0 = line * stride + ((j >> ls) << (ls + 1)) + k;
-      const int i1 = i0 + half;
-      float2 w = tw[k << tsh];
+      float2 w = tw[k];  // tw step 1 in the last stage
       w.y *= sign;
-      const float2 a = buf[i0], b = buf[i1];
-      const float2 t = make_float2(b.x * w.x - b.y * w.y, b.x * w.y + b.y * w.x);
-      buf[i0] = make_float2(a.x + t.x, a.y + t.y);
-      buf[i1] = make_float2(a.x - t.x, a.y - t.y);
+      float2 a = buf[i0], b = buf[i0 + half];
+      radix2(a, b, w);
+      buf[i0] = a;
+      buf[i0 + half] = b;
     }
     __syncthreads();
   }
