@@ -194,8 +194,12 @@ int pmfem_profile_end(pmfem_ctx* ctx, int32_t* n_kernels, double* ms, int32_t* c
  * name selects the array (see the table in the library source: "mu",
  * "loc_rowptr", "loc_col", "loc_val", "z0_rowptr", "z0_col", "z0_val",
  * "p_rowptr", "p_col", "p_val", "pos", "khat", "kgrid", "box_start",
- * "grid_info"). With out == NULL only *count (elements) and *elem_bytes
- * are set; otherwise *count elements are copied to out.
+ * "grid_info"; the scatter anterpolation's tiles: "sc_plan" (int32 tb[3],
+ * nt[3], fd[3], fsize), "sc_list" (int32 pairs: unknown, stencil offset in
+ * its tile's footprint), "sc_lstart", "sc_tab" (int32 pairs (tile, footprint
+ * offset), two per grid index, x then y then z; tile -1 when absent)). With
+ * out == NULL only *count (elements) and *elem_bytes are set; otherwise
+ * *count elements are copied to out.
  */
 int pmfem_export(pmfem_ctx* ctx, const char* name, void* out, int64_t* count,
                  int32_t* elem_bytes);

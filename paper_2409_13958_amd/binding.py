@@ -216,7 +216,7 @@ class Context:
                                           ctypes.byref(eb)), f"export {name}")
         dt = {4: np.float32, 8: np.float64}[eb.value]
         if name in ("loc_rowptr", "loc_col", "z0_rowptr", "z0_col", "p_rowptr", "p_col",
-                    "box_start"):
+                    "box_start", "sc_plan", "sc_list", "sc_lstart", "sc_tab"):
             dt = np.int32
         if name in ("unk_of_node", "node_of_unk"):
             dt = np.int64

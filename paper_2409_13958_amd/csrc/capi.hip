@@ -1342,6 +1342,7 @@ int pmfem_export(pmfem_ctx* c, const char* name, void* out, int64_t* count, int3
   int64_t cnt = 0;
   int32_t eb = 0;
   std::vector<double> info;
+  std::vector<int32_t> ivec;
   std::string nm(name);
   if (nm == "mu") { src = o.mu.data(); cnt = (int64_t)o.mu.size(); eb = 8; }
   else if (nm == "pos") { src = o.pos.data(); cnt = (int64_t)o.pos.size(); eb = 8; }
@@ -1373,6 +1374,27 @@ int pmfem_export(pmfem_ctx* c, const char* name, void* out, int64_t* count, int3
     src = info.data();
     cnt = (int64_t)info.size();
     eb = 8;
+  } else if (nm == "sc_plan" || nm == "sc_list" || nm == "sc_lstart" || nm == "sc_tab") {
+    // the scatter anterpolation's tiles (built here from the box table)
+    ScPlan pl{};
+    std::vector<int2> list, tab[3];
+    std::vector<int32_t> lstart;
+    if (!plan_scatter(o, pl, list, lstart, tab))
+      return set_err(c, PMFEM_EGRID, "scatter tiles do not fit this problem");
+    if (nm == "sc_plan") {
+      ivec = {pl.tb[0], pl.tb[1], pl.tb[2], pl.nt[0], pl.nt[1], pl.nt[2],
+              pl.fd[0], pl.fd[1], pl.fd[2], pl.fsize};
+    } else if (nm == "sc_list") {
+      for (const int2& e : list) ivec.insert(ivec.end(), {e.x, e.y});
+    } else if (nm == "sc_lstart") {
+      ivec = lstart;
+    } else {
+      for (int a = 0; a < 3; ++a)
+        for (const int2& e : tab[a]) ivec.insert(ivec.end(), {e.x, e.y});
+    }
+    src = ivec.data();
+    cnt = (int64_t)ivec.size();
+    eb = 4;
   } else {
     return set_err(c, PMFEM_EINVAL, "unknown export name: " + nm);
   }

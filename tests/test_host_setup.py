@@ -273,3 +273,56 @@ def test_precorrection_column_order_matches_tile_staging(pair, shape):
     assert len(got) == ctx.n
     for r in range(ctx.n):
         assert got[r] == col[rp[r]:rp[r + 1]].tolist(), r
+
+
+def test_scatter_tiles_map_every_stencil_point(pair):
+    """Scatter anterpolation tiles (host plan): every unknown is listed once,
+    and each of its (p+1)^3 stencil points, reached through the listed
+    footprint offset and the per-axis (tile, offset) tables, is the grid point
+    the oracle's stencil start gives; at most two tiles of different parity
+    cover a grid index along an axis."""
+    prob, ctx, orc = pair
+    perm = _perm(ctx, orc)
+    info = ctx.export("grid_info")
+    N = info[0:3].astype(int)
+    per = info[-3:].astype(bool)
+    p = int(info[-5])
+    plan = ctx.export("sc_plan")
+    tb, nt, fd = plan[0:3], plan[3:6], plan[6:9]
+    assert plan[9] == fd[0] * fd[1] * fd[2]
+    lst = ctx.export("sc_list").reshape(-1, 2)
+    ls = ctx.export("sc_lstart")
+    tab = ctx.export("sc_tab").reshape(-1, 2)
+    assert ls.size == int(np.prod(nt)) + 1 and ls[-1] == ctx.n
+    assert np.array_equal(np.sort(lst[:, 0]), np.arange(ctx.n))
+    # per axis: (tile, offset) -> grid index, and the coverage rule
+    inv, start = [], 0
+    for a in range(3):
+        t_a = tab[start:start + 2 * N[a]].reshape(N[a], 2, 2)
+        start += 2 * N[a]
+        m = {}
+        for gi in range(N[a]):
+            ents = [tuple(e) for e in t_a[gi] if e[0] >= 0]
+            assert 1 <= len(ents) <= 2
+            if len(ents) == 2:
+                assert ents[0][0] % 2 != ents[1][0] % 2
+            for e in ents:
+                assert e not in m
+                m[e] = gi
+        inv.append(m)
+    st = orc.aim.st[perm]            # oracle stencil starts, library order
+    FX, FXY = fd[0], fd[0] * fd[1]
+    rng = np.random.default_rng(5)
+    tiles = rng.choice(int(np.prod(nt)), size=min(64, int(np.prod(nt))), replace=False)
+    for w in tiles:
+        t = (w % nt[0], (w // nt[0]) % nt[1], w // (nt[0] * nt[1]))
+        for node, off in lst[ls[w]:ls[w + 1]]:
+            oz, rem = divmod(int(off), FXY)
+            oy, ox = divmod(rem, FX)
+            for a, o0 in enumerate((ox, oy, oz)):
+                for c in range(p + 1):
+                    gi = inv[a][(t[a], o0 + c)]
+                    want = st[node, a] + c
+                    if per[a]:
+                        want %= N[a]
+                    assert gi == want, (w, node, a, c)
