@@ -13,6 +13,9 @@
 
 using namespace pmfem;
 
+#ifndef PMFEM_FFT_SPLIT
+#define PMFEM_FFT_SPLIT 2  // workgroups per z-plane in the plane transforms
+#endif
 #ifndef PMFEM_IC_LDS_BUDGET
 #define PMFEM_IC_LDS_BUDGET 24576  // LDS bytes per interpolation tile
 #endif
@@ -776,8 +779,8 @@ void convolve(pmfem_dev* d, hipStream_t s, const float* Qg, float* Ug, Mark&& ma
   const int64_t cols = (int64_t)My * Hx;
   if (d->fft_plane) {
     mark(2, 0);
-    hipLaunchKernelGGL(k_fft_xy_fwd, dim3((unsigned)g.N[2]), dim3(1024), d->fft_plane_lds, s, g,
-                       Qg, d->spec, d->twx, d->twy);
+    hipLaunchKernelGGL(k_fft_xy_fwd, dim3((unsigned)(g.N[2] * PMFEM_FFT_SPLIT)), dim3(1024),
+                       d->fft_plane_lds, s, g, Qg, d->spec, d->twx, d->twy, PMFEM_FFT_SPLIT);
     mark(2, 1);
     mark(4, 0);
     hipLaunchKernelGGL(k_fft_z_mul, dim3((unsigned)((cols + Bz - 1) / Bz)), dim3(T),
@@ -785,8 +788,9 @@ void convolve(pmfem_dev* d, hipStream_t s, const float* Qg, float* Ug, Mark&& ma
                        d->twz, Bz);
     mark(4, 1);
     mark(6, 0);
-    hipLaunchKernelGGL(k_fft_yx_inv, dim3((unsigned)g.N[2]), dim3(1024), d->fft_plane_lds, s, g,
-                       (const float2*)d->spec, Ug, d->twx, d->twy);
+    hipLaunchKernelGGL(k_fft_yx_inv, dim3((unsigned)(g.N[2] * PMFEM_FFT_SPLIT)), dim3(1024),
+                       d->fft_plane_lds, s, g, (const float2*)d->spec, Ug, d->twx, d->twy,
+                       PMFEM_FFT_SPLIT);
     mark(6, 1);
     return;
   }

@@ -79,10 +79,11 @@ __global__ void k_r2c_x(GridParams g, const float* Q, float2* spec, const float2
                         int lines_per_block);
 __global__ void k_fft_y(GridParams g, float2* spec, const float2* twy, int B, int inverse,
                         int n_in, int n_out);
+// nsplit workgroups per z-plane (1 or 2)
 __global__ void k_fft_xy_fwd(GridParams g, const float* Q, float2* spec, const float2* twx,
-                             const float2* twy);
+                             const float2* twy, int nsplit);
 __global__ void k_fft_yx_inv(GridParams g, const float2* spec, float* U, const float2* twx,
-                             const float2* twy);
+                             const float2* twy, int nsplit);
 __global__ void k_fft_z_mul(GridParams g, float2* spec, const float* khat, const float2* twz,
                             int B);
 __global__ void k_c2r_x(GridParams g, const float2* spec, float* U, const float2* twx,

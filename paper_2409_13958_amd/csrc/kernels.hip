@@ -771,11 +771,13 @@ __device__ __forceinline__ int fdiv(int n, int d, float inv_d) {
 // Forward transform of one z-plane held whole in LDS: real rows y < Ny are
 // paired into complex lines (R2C along x), separated into the half spectrum
 // kx < Hx, transposed into columns (stride My + 1) and transformed along y.
-// Q[z][y][x] -> spec[z][ky][kx] for all ky < My.
+// Q[z][y][x] -> spec[z][ky][kx] for all ky < My. nsplit workgroups share a
+// plane: each does the x pass and the y pass of its share of the columns.
 __global__ void __launch_bounds__(1024) k_fft_xy_fwd(GridParams g, const float* __restrict__ Q,
                                                      float2* __restrict__ spec,
                                                      const float2* __restrict__ twx,
-                                                     const float2* __restrict__ twy) {
+                                                     const float2* __restrict__ twy,
+                                                     int nsplit) {
   extern __shared__ float2 sh[];
   const int Mx = g.M[0], My = g.M[1], Hx = Mx / 2 + 1, lx = g.logM[0], ly = g.logM[1];
   const int Nx = g.N[0], Ny = g.N[1], pairs = (Ny + 1) / 2, cs = My + 1;
@@ -783,7 +785,9 @@ __global__ void __launch_bounds__(1024) k_fft_xy_fwd(GridParams g, const float* 
   float2* ty = tx + Mx / 2;
   float2* A = ty + My / 2;        // [pairs][Mx]
   float2* C = A + pairs * Mx;     // [Hx][My + 1]
-  const int z = blockIdx.x;
+  const int z = blockIdx.x / nsplit, part = blockIdx.x - z * nsplit;
+  const int kw = (Hx + nsplit - 1) / nsplit, k0 = part * kw, nk = min(Hx, k0 + kw) - k0;
+  const float invnk = 1.0f / (float)nk;
   for (int i = threadIdx.x; i < Mx / 2; i += blockDim.x) tx[i] = twx[i];
   for (int i = threadIdx.x; i < My / 2; i += blockDim.x) ty[i] = twy[i];
   const float* Qz = Q + (int64_t)z * Ny * Nx;
@@ -804,15 +808,15 @@ __global__ void __launch_bounds__(1024) k_fft_xy_fwd(GridParams g, const float* 
         A[li * Mx + bitrev(x, lx)] = v;
       });
   // rows Ny..My-1 of the columns are the zero padding
-  for (int idx = threadIdx.x; idx < Hx * (My - 2 * pairs); idx += blockDim.x) {
-    const int yq = fdiv(idx, Hx, invHx);
-    const int k = idx - yq * Hx, y = 2 * pairs + yq;
+  for (int idx = threadIdx.x; idx < nk * (My - 2 * pairs); idx += blockDim.x) {
+    const int yq = fdiv(idx, nk, invnk);
+    const int k = k0 + idx - yq * nk, y = 2 * pairs + yq;
     C[k * cs + bitrev(y, ly)] = make_float2(0.f, 0.f);
   }
   __syncthreads();
   lds_fft_s(A, Mx, lx, pairs, Mx, tx, 1.0f);
-  for (int idx = threadIdx.x; idx < pairs * Hx; idx += blockDim.x) {
-    const int li = fdiv(idx, Hx, invHx), k = idx - li * Hx, y = 2 * li;
+  for (int idx = threadIdx.x; idx < pairs * nk; idx += blockDim.x) {
+    const int li = fdiv(idx, nk, invnk), k = k0 + idx - li * nk, y = 2 * li;
     const float2 a = A[li * Mx + k];
     const float2 b = A[li * Mx + ((Mx - k) & (Mx - 1))];
     // X_y = (Z[k] + conj Z[-k]) / 2, X_{y+1} = (Z[k] - conj Z[-k]) / (2i)
@@ -821,21 +825,24 @@ __global__ void __launch_bounds__(1024) k_fft_xy_fwd(GridParams g, const float* 
         y + 1 < Ny ? make_float2(0.5f * (a.y + b.y), -0.5f * (a.x - b.x)) : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  lds_fft_s(C, My, ly, Hx, cs, ty, 1.0f);
+  lds_fft_s(C + k0 * cs, My, ly, nk, cs, ty, 1.0f);
   float2* Sz = spec + (int64_t)z * My * Hx;
-  for (int idx = threadIdx.x; idx < My * Hx; idx += blockDim.x) {
-    const int ky = fdiv(idx, Hx, invHx), k = idx - ky * Hx;
-    Sz[idx] = C[k * cs + ky];
+  for (int idx = threadIdx.x; idx < My * nk; idx += blockDim.x) {
+    const int ky = fdiv(idx, nk, invnk), k = k0 + idx - ky * nk;
+    Sz[ky * Hx + k] = C[k * cs + ky];
   }
 }
 
 // Inverse of k_fft_xy_fwd for one z-plane: inverse FFT along y of the half
 // spectrum columns, rows y < Ny paired into complex lines with Hermitian
 // extension (C2R along x), inverse FFT along x. spec[z] -> U[z][y][x].
+// nsplit workgroups share a plane: each does the y pass and the x pass of
+// its share of the row pairs.
 __global__ void __launch_bounds__(1024) k_fft_yx_inv(GridParams g, const float2* __restrict__ spec,
                                                      float* __restrict__ U,
                                                      const float2* __restrict__ twx,
-                                                     const float2* __restrict__ twy) {
+                                                     const float2* __restrict__ twy,
+                                                     int nsplit) {
   extern __shared__ float2 sh[];
   const int Mx = g.M[0], My = g.M[1], Hx = Mx / 2 + 1, lx = g.logM[0], ly = g.logM[1];
   const int Nx = g.N[0], Ny = g.N[1], pairs = (Ny + 1) / 2, cs = My + 1;
@@ -843,7 +850,8 @@ __global__ void __launch_bounds__(1024) k_fft_yx_inv(GridParams g, const float2*
   float2* ty = tx + Mx / 2;
   float2* A = ty + My / 2;
   float2* C = A + pairs * Mx;
-  const int z = blockIdx.x;
+  const int z = blockIdx.x / nsplit, part = blockIdx.x - z * nsplit;
+  const int lw = (pairs + nsplit - 1) / nsplit, l0 = part * lw, nl = min(pairs, l0 + lw) - l0;
   for (int i = threadIdx.x; i < Mx / 2; i += blockDim.x) tx[i] = twx[i];
   for (int i = threadIdx.x; i < My / 2; i += blockDim.x) ty[i] = twy[i];
   const float2* Sz = spec + (int64_t)z * My * Hx;
@@ -856,8 +864,8 @@ __global__ void __launch_bounds__(1024) k_fft_yx_inv(GridParams g, const float2*
       });
   __syncthreads();
   lds_fft_s(C, My, ly, Hx, cs, ty, -1.0f);
-  for (int idx = threadIdx.x; idx < pairs * Mx; idx += blockDim.x) {
-    const int li = idx >> lx, k = idx & (Mx - 1), y = 2 * li;
+  for (int idx = threadIdx.x; idx < nl * Mx; idx += blockDim.x) {
+    const int li = l0 + (idx >> lx), k = idx & (Mx - 1), y = 2 * li;
     const int kk = k <= Mx / 2 ? k : Mx - k;
     float2 a = C[kk * cs + y];
     float2 b = y + 1 < Ny ? C[kk * cs + y + 1] : make_float2(0.f, 0.f);
@@ -869,11 +877,11 @@ __global__ void __launch_bounds__(1024) k_fft_yx_inv(GridParams g, const float2*
     A[li * Mx + bitrev(k, lx)] = make_float2(a.x - b.y, a.y + b.x);
   }
   __syncthreads();
-  lds_fft_s(A, Mx, lx, pairs, Mx, tx, -1.0f);
+  lds_fft_s(A + l0 * Mx, Mx, lx, nl, Mx, tx, -1.0f);
   float* Uz = U + (int64_t)z * Ny * Nx;
   const float invNx = 1.0f / (float)Nx;
-  for (int idx = threadIdx.x; idx < pairs * Nx; idx += blockDim.x) {
-    const int li = fdiv(idx, Nx, invNx), x = idx - li * Nx, y = 2 * li;
+  for (int idx = threadIdx.x; idx < nl * Nx; idx += blockDim.x) {
+    const int li = l0 + fdiv(idx, Nx, invNx), x = idx - (li - l0) * Nx, y = 2 * li;
     const float2 v = A[li * Mx + x];
     Uz[(int64_t)y * Nx + x] = v.x;
     if (y + 1 < Ny) Uz[(int64_t)(y + 1) * Nx + x] = v.y;
