@@ -13,6 +13,12 @@
 
 using namespace pmfem;
 
+#ifndef PMFEM_FFTZ_B
+#define PMFEM_FFTZ_B 8  // z columns per workgroup of the z pass
+#endif
+#ifndef PMFEM_FFTZ_T
+#define PMFEM_FFTZ_T 256  // threads per workgroup of the z pass
+#endif
 #ifndef PMFEM_FFT_SPLIT
 #define PMFEM_FFT_SPLIT 2  // workgroups per z-plane in the plane transforms
 #endif
@@ -775,7 +781,7 @@ void convolve(pmfem_dev* d, hipStream_t s, const float* Qg, float* Ug, Mark&& ma
   const GridParams& g = d->g;
   const int T = 256;
   const int Mx = g.M[0], My = g.M[1], Mz = g.M[2], Hx = Mx / 2 + 1;
-  const int Bz = std::max(1, std::min(16, 4096 / Mz));
+  const int Bz = std::max(1, std::min(PMFEM_FFTZ_B, 4096 / Mz)), Tz = PMFEM_FFTZ_T;
   const int64_t cols = (int64_t)My * Hx;
   if (d->fft_plane) {
     mark(2, 0);
@@ -783,7 +789,7 @@ void convolve(pmfem_dev* d, hipStream_t s, const float* Qg, float* Ug, Mark&& ma
                        d->fft_plane_lds, s, g, Qg, d->spec, d->twx, d->twy, PMFEM_FFT_SPLIT);
     mark(2, 1);
     mark(4, 0);
-    hipLaunchKernelGGL(k_fft_z_mul, dim3((unsigned)((cols + Bz - 1) / Bz)), dim3(T),
+    hipLaunchKernelGGL(k_fft_z_mul, dim3((unsigned)((cols + Bz - 1) / Bz)), dim3(Tz),
                        (size_t)(Mz / 2 + Bz * Mz) * sizeof(float2), s, g, d->spec, d->khat,
                        d->twz, Bz);
     mark(4, 1);
@@ -809,7 +815,7 @@ void convolve(pmfem_dev* d, hipStream_t s, const float* Qg, float* Ug, Mark&& ma
                      g.N[1], My);
   mark(3, 1);
   mark(4, 0);
-  hipLaunchKernelGGL(k_fft_z_mul, dim3((unsigned)((cols + Bz - 1) / Bz)), dim3(T),
+  hipLaunchKernelGGL(k_fft_z_mul, dim3((unsigned)((cols + Bz - 1) / Bz)), dim3(Tz),
                      (size_t)(Mz / 2 + Bz * Mz) * sizeof(float2), s, g, d->spec, d->khat, d->twz,
                      Bz);
   mark(4, 1);
