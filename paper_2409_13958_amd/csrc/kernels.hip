@@ -660,10 +660,51 @@ __device__ __forceinline__ void radix2(float2& a, float2& b, float2 w) {
 __device__ void lds_fft_s(float2* buf, int n, int logn, int lines, int stride, const float2* tw,
                           float sign) {
   // radix-2 decimation in time; n = 2^logn, so every index split is a shift.
-  // Stages s and s + 1 are done together by one thread per 4 elements (the
-  // same four butterflies, in registers), so a pair of stages costs one LDS
-  // round trip and one barrier.
+  // Three stages s, s + 1, s + 2 are done together by one thread per 8
+  // elements (the same twelve butterflies, in registers), then a pair, then a
+  // single stage as needed, so every pass costs one LDS round trip and one
+  // barrier.
   int s = 1;
+  for (; s + 2 <= logn; s += 3) {
+    const int ls = s - 1;  // log2(h), h the half of stage s
+    const int h = 1 << ls;
+    const int total = lines << (logn - 3);
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+      const int line = idx >> (logn - 3);
+      const int j = idx & ((1 << (logn - 3)) - 1);
+      const int k = j & (h - 1);
+      const int i0 = line * stride + ((j >> ls) << (ls + 3)) + k;
+      float2 w1 = tw[k << (logn - s)];
+      float2 w2 = tw[k << (logn - s - 1)], w3 = tw[(k + h) << (logn - s - 1)];
+      float2 w4 = tw[k << (logn - s - 2)], w5 = tw[(k + h) << (logn - s - 2)];
+      float2 w6 = tw[(k + 2 * h) << (logn - s - 2)], w7 = tw[(k + 3 * h) << (logn - s - 2)];
+      w1.y *= sign;
+      w2.y *= sign;
+      w3.y *= sign;
+      w4.y *= sign;
+      w5.y *= sign;
+      w6.y *= sign;
+      w7.y *= sign;
+      float2 a[8];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) a[m] = buf[i0 + m * h];
+      radix2(a[0], a[1], w1);
+      radix2(a[2], a[3], w1);
+      radix2(a[4], a[5], w1);
+      radix2(a[6], a[7], w1);
+      radix2(a[0], a[2], w2);
+      radix2(a[1], a[3], w3);
+      radix2(a[4], a[6], w2);
+      radix2(a[5], a[7], w3);
+      radix2(a[0], a[4], w4);
+      radix2(a[1], a[5], w5);
+      radix2(a[2], a[6], w6);
+      radix2(a[3], a[7], w7);
+#pragma unroll
+      for (int m = 0; m < 8; ++m) buf[i0 + m * h] = a[m];
+    }
+    __syncthreads();
+  }
   for (; s + 1 <= logn; s += 2) {
     const int ls = s - 1;  // log2(h), h the half of stage s
     const int h = 1 << ls;
