@@ -57,8 +57,19 @@ SMALL = {
     "film_long_axis_512": lambda: mg.kuhn_box((40, 4, 1), 2e-9, periodic=0b011, grid=(512, 16, 4)),
     "order5_radius3": lambda: mg.kuhn_box((6, 6, 2), 1e-9, periodic=0b011, jitter=0.2,
                                           grid=(32, 32, 8)),
+    # the remaining Lagrange orders and near radii, and a cell with no
+    # periodic axis (every FFT axis zero-padded)
+    "open_box_p1_rb0": lambda: mg.kuhn_box((5, 5, 4), 1e-9, periodic=0, jitter=0.2,
+                                           grid=(8, 8, 8)),
+    "film_p2_rb1": lambda: mg.kuhn_box((6, 6, 2), 1e-9, periodic=0b011, jitter=0.2,
+                                       grid=(16, 16, 4)),
+    "slab_p4_rb1": lambda: mg.kuhn_box((5, 6, 4), 1e-9, periodic=0b011, jitter=0.2,
+                                       grid=(16, 16, 8)),
 }
-KW = {"order5_radius3": dict(order_p=5, near_boxes=3)}
+KW = {"order5_radius3": dict(order_p=5, near_boxes=3),
+      "open_box_p1_rb0": dict(order_p=1, near_boxes=0),
+      "film_p2_rb1": dict(order_p=2, near_boxes=1),
+      "slab_p4_rb1": dict(order_p=4, near_boxes=1)}
 
 
 @pytest.mark.parametrize("name", sorted(SMALL))

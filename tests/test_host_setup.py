@@ -43,13 +43,24 @@ PROBLEMS = {
                                      grid=(8, 8, 16)),
     "film_xz": lambda: mg.kuhn_box((6, 3, 6), 1e-9, periodic=0b101, jitter=0.15,
                                    grid=(16, 4, 16)),
+    # the other Lagrange orders and near radii, and a cell with no periodic axis
+    "open_box_p1_rb0": lambda: mg.kuhn_box((5, 5, 4), 1e-9, periodic=0, jitter=0.2,
+                                           grid=(8, 8, 8)),
+    "film_p2_rb1": lambda: mg.kuhn_box((6, 6, 2), 1e-9, periodic=0b011, jitter=0.2,
+                                       grid=(16, 16, 4)),
+    "slab_p4_rb1": lambda: mg.kuhn_box((5, 6, 4), 1e-9, periodic=0b011, jitter=0.2,
+                                       grid=(16, 16, 8)),
 }
+KW = {"open_box_p1_rb0": dict(order_p=1, near_boxes=0),
+      "film_p2_rb1": dict(order_p=2, near_boxes=1),
+      "slab_p4_rb1": dict(order_p=4, near_boxes=1)}
 
 
 @pytest.fixture(scope="module", params=sorted(PROBLEMS))
 def pair(request):
     prob = PROBLEMS[request.param]()
-    return prob, _ctx(prob), model.Oracle(prob)
+    kw = KW.get(request.param, {})
+    return prob, _ctx(prob, **kw), model.Oracle(prob, **kw)
 
 
 def test_unknowns_and_lca(pair):
