@@ -67,6 +67,13 @@ def kernel_bytes(ctx, names):
                        if name.startswith(k)) for name in names}
 
 
+WORKLOADS = {
+    "composite_c3": "3D-periodic composite, 27 spheres r=12-18 nm in a 100 nm cell",
+    "wire_c2": "1D-periodic wire, radius 10 nm, period 40 nm, two domain walls",
+    "film_c1": "2D-periodic film, 20x20x2 nm cell",
+}
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
     None when the kernel source has changed since the counters were taken."""
@@ -253,9 +260,10 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": (f"3D-periodic composite, 27 spheres r=12-18 nm in a 100 nm cell, "
+            "workload": (f"{WORKLOADS.get(args.config, args.config)}, "
                          f"N'={n} unknowns, {prob.tets.shape[0]} tets, AIM grid "
-                         f"{'x'.join(str(g) for g in prob.grid)}, p=3, r_b=2, kappa=1"),
+                         f"{'x'.join(str(g) for g in prob.grid)}, p={prob.order_p}, "
+                         f"r_b={prob.near_boxes}, kappa={prob.z0_radius:g}"),
             "name": args.config,
             "n_unknowns": n,
             "model_bytes_per_eval": bpe,
