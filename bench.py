@@ -171,8 +171,8 @@ def main():
                     help="also stream this many MiB through plain kernels (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md, not implemented", file=sys.stderr)
+        print(f"bench.py: the library runs on exactly one GPU (asked for --gpus {args.gpus}); "
+              "sharding over several GPUs is designed but not implemented", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
 
