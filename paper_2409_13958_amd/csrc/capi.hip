@@ -350,9 +350,11 @@ bool build_interp_lists(const HostOps& o, const IcPlan& pl, std::vector<int32_t>
 // on a periodic axis at most N - p, so that a footprint does not wrap onto
 // itself), the tile node lists in launch order (tiles x fastest, nodes in box
 // order), and per axis and grid index the covering tiles with the point's
-// offset in their footprints. Returns false if the tiles do not fit.
-bool plan_scatter(const HostOps& o, ScPlan& pl, std::vector<int2>& list,
-                  std::vector<int32_t>& lstart, std::vector<int2> tab[3]) {
+// offset in their footprints. Returns false if the tiles do not fit. With
+// divisors, a periodic axis takes the smallest tile that divides it (a
+// shorter last tile can leave a grid point in three footprints).
+bool plan_scatter_with(const HostOps& o, ScPlan& pl, std::vector<int2>& list,
+                       std::vector<int32_t>& lstart, std::vector<int2> tab[3], bool divisors) {
   const int p = o.p, shift = (p - 1) / 2;
   const int want[3] = {PMFEM_SC_TB};
   auto start = [&](int a, int b) {
@@ -361,6 +363,11 @@ bool plan_scatter(const HostOps& o, ScPlan& pl, std::vector<int2>& list,
   for (int a = 0; a < 3; ++a) {
     int tb = std::max(want[a], p + 1);
     if (o.per[a]) tb = std::min(tb, o.N[a] - p);
+    if (divisors && o.per[a]) {
+      tb = std::max(want[a], p + 1);
+      while (tb <= o.N[a] - p && o.nbox[a] % tb != 0) ++tb;
+      if (tb > o.N[a] - p) return false;
+    }
     tb = std::min(tb, o.nbox[a]);
     if (tb < 1) return false;
     pl.tb[a] = tb;
@@ -415,6 +422,14 @@ bool plan_scatter(const HostOps& o, ScPlan& pl, std::vector<int2>& list,
   if (lds > PMFEM_SC_LDS_BUDGET) return false;
   pl.lds_bytes = (int)lds;
   return (int64_t)list.size() == o.n_unk;
+}
+
+// The scatter plan: the preferred tile sizes, else tiles dividing the
+// periodic axes.
+bool plan_scatter(const HostOps& o, ScPlan& pl, std::vector<int2>& list,
+                  std::vector<int32_t>& lstart, std::vector<int2> tab[3]) {
+  return plan_scatter_with(o, pl, list, lstart, tab, false) ||
+         plan_scatter_with(o, pl, list, lstart, tab, true);
 }
 
 bool build_anterp_lists(const HostOps& o, const std::vector<int2>& bx,

@@ -65,11 +65,16 @@ SMALL = {
                                        grid=(16, 16, 4)),
     "slab_p4_rb1": lambda: mg.kuhn_box((5, 6, 4), 1e-9, periodic=0b011, jitter=0.2,
                                        grid=(16, 16, 8)),
+    # p = 4 on 16 periodic points: the preferred z tiles (5 boxes) leave a
+    # short last tile, so the scatter plan takes tiles that divide the axis
+    "box3d_p4_rb1": lambda: mg.kuhn_box((5, 6, 5), 1e-9, periodic=0b111, jitter=0.2,
+                                        grid=(16, 16, 16)),
 }
 KW = {"order5_radius3": dict(order_p=5, near_boxes=3),
       "open_box_p1_rb0": dict(order_p=1, near_boxes=0),
       "film_p2_rb1": dict(order_p=2, near_boxes=1),
-      "slab_p4_rb1": dict(order_p=4, near_boxes=1)}
+      "slab_p4_rb1": dict(order_p=4, near_boxes=1),
+      "box3d_p4_rb1": dict(order_p=4, near_boxes=1)}
 
 
 @pytest.mark.parametrize("name", sorted(SMALL))
