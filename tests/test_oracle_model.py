@@ -122,3 +122,22 @@ def test_exchange_only_energy_conserved_without_damping():
     # and with damping the energy decreases
     m = o.rk4(m0, 2e-15, 0.5, 50, method="direct", terms=("ex",))
     assert o.ops.exchange_energy(m) < e0
+
+
+def test_aim_error_report_on_the_film(film):
+    # the full-size AIM error script, run with every unknown of the film as a
+    # sample, reports the whole-film AIM-vs-direct error of H_ms
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    o = model.Oracle(film)
+    m = o.unknown_values(film.m)
+    Ha = o.heff(m, method="aim", terms=("ms",))
+    Hd = o.heff(m, method="direct", terms=("ms",))
+    want = np.linalg.norm(Ha - Hd) / np.linalg.norm(Hd)
+    out = subprocess.run([sys.executable, os.path.join(root, "oracle", "report_aim_error.py"),
+                          "film_c1", str(o.n), "2"], capture_output=True, text=True, timeout=300,
+                         check=True).stdout
+    line = next(ln for ln in out.splitlines() if ln.startswith("H_ms at the samples rel L2"))
+    assert float(line.split()[-1]) == pytest.approx(want, rel=1e-3)
