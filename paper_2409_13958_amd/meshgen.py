@@ -97,13 +97,15 @@ def _random_unit(rng, n):
 
 
 def kuhn_box(n_cells, h, periodic=0, jitter=0.0, seed=SEED0, Ms=8e5, Aex=1.3e-11,
-             grid=None, m="random", name="kuhn_box"):
+             grid=None, m="random", name="kuhn_box", region_of=None):
     """A fully filled box of ``n_cells`` cubes of side ``h`` (metres), 6 tets each.
 
     On periodic axes the last node layer is the image of the first and the
     jitter is drawn per wrapped lattice index, so image nodes sit exactly one
     period apart. ``m`` is "random" (iid uniform on the sphere per wrapped
-    node) or a callable ``f(xyz) -> [N,3]``.
+    node) or a callable ``f(xyz) -> [N,3]``. ``region_of`` (optional) maps
+    the integer lattice cell of every tetrahedron, an array [T, 3], to its
+    region id; ``Ms`` and ``Aex`` then hold one value per region.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     n = np.asarray(n_cells, dtype=np.int64)
@@ -127,10 +129,25 @@ def kuhn_box(n_cells, h, periodic=0, jitter=0.0, seed=SEED0, Ms=8e5, Aex=1.3e-11
         mm = np.broadcast_to(np.asarray(m, dtype=np.float64), xyz.shape).copy()
     if grid is None:
         grid = tuple(int(max(4, c)) for c in n)
-    return Problem(name=name, xyz=xyz, tets=tets.astype(np.int32),
-                   region=np.zeros(tets.shape[0], np.int32),
-                   Ms=np.array([Ms]), Aex=np.array([Aex]), periodic=periodic,
+    if region_of is None:
+        region = np.zeros(tets.shape[0], np.int32)
+    else:
+        region = np.asarray(region_of(np.repeat(cells, 6, axis=0)), dtype=np.int32)
+    return Problem(name=name, xyz=xyz, tets=tets.astype(np.int32), region=region,
+                   Ms=np.atleast_1d(np.asarray(Ms, dtype=np.float64)),
+                   Aex=np.atleast_1d(np.asarray(Aex, dtype=np.float64)), periodic=periodic,
                    L=L.astype(np.float64), grid=grid, m=mm)
+
+
+def ball_regions(n_cells, radius):
+    """``region_of`` for kuhn_box: region 1 for the cells whose centre lies
+    within ``radius`` cells of the box centre, region 0 elsewhere."""
+    ctr = np.asarray(n_cells, dtype=np.float64) / 2.0
+
+    def region_of(cells):
+        d = cells + 0.5 - ctr
+        return (np.einsum("ij,ij->i", d, d) <= radius * radius).astype(np.int32)
+    return region_of
 
 
 def film_c1(seed=SEED0 + 0):

@@ -54,6 +54,17 @@ PROBLEMS = {
     # short last tile, so the scatter plan takes tiles that divide the axis
     "box3d_p4_rb1": lambda: mg.kuhn_box((5, 6, 5), 1e-9, periodic=0b111, jitter=0.2,
                                         grid=(16, 16, 16)),
+    # two materials (Sec. 3.2.1): a jittered 3D-periodic cell with a ball of
+    # cells of another Ms and A (interfaces of every orientation), and a
+    # bilayer film (interface plus outer boundary faces)
+    "inclusion_3d": lambda: mg.kuhn_box((6, 6, 6), 1e-9, periodic=0b111, jitter=0.2,
+                                        Ms=[8e5, 3e5], Aex=[1.3e-11, 0.7e-11],
+                                        region_of=mg.ball_regions((6, 6, 6), 2.2),
+                                        grid=(16, 16, 16)),
+    "bilayer_film": lambda: mg.kuhn_box((6, 6, 4), 1e-9, periodic=0b011, jitter=0.2,
+                                        Ms=[8e5, 1.4e6], Aex=[1.3e-11, 2e-11],
+                                        region_of=lambda c: (c[:, 2] >= 2).astype(np.int32),
+                                        grid=(16, 16, 8)),
 }
 KW = {"open_box_p1_rb0": dict(order_p=1, near_boxes=0),
       "film_p2_rb1": dict(order_p=2, near_boxes=1),

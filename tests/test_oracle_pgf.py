@@ -72,7 +72,13 @@ def test_laplacian_away_from_lattice(name, mask, L):
     h = 1e-2 * L.max()
     rich = (4 * lap(h / 2) - lap(h)) / 3          # removes the O(h^2) error
     expect = 4 * np.pi / np.prod(L) if mask == 0b111 else 0.0
-    assert np.allclose(rich, expect, atol=1e-5 * 4 * np.pi / np.prod(L))
+    # a scale that is finite for every periodicity: 4 pi / L_max^3 is the
+    # 3D background density for a cube of the largest period (12.1 for the
+    # 3D case here, 1.6 - 9.4 for the others); the residuals are ~3e-7, and
+    # dropping the 2D/1D far-field or background terms moves them to O(1)
+    scale = 4 * np.pi / L.max() ** 3
+    assert np.all(np.isfinite(rich))
+    assert np.allclose(rich, expect, rtol=0, atol=1e-6 * scale)
 
 
 def test_lattice_sum_1d():
