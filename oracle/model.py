@@ -27,7 +27,12 @@ It acts on m directly (three sparse blocks), separate from the precorrection.
 LLG (Eq. llg, reading of the garbled "M x M_n x H"): unit-vector
 Landau-Lifshitz form dm/dt = -gamma0/(1+alpha^2) [m x H + alpha m x (m x H)],
 gamma0 = mu0 * 1.76086e11 m/(A s) (the paper gives no value), classic RK4
-with the norm restored after each full step.
+with the norm restored after each full step. The paper itself integrates
+implicitly (midpoint or BDF with Newton and a preconditioned Krylov solver,
+Sec. 2.2); ``implicit_midpoint`` is that rule written out plainly: each step
+solves x = m + dt f((m + x)/2) by Newton's method with the exact Jacobian
+(the field is linear in m, so H = A m + H_app with A assembled densely on
+small meshes) and a dense linear solve; the rule keeps |m| by itself.
 """
 from __future__ import annotations
 
@@ -270,3 +275,62 @@ class Oracle:
             m = m + dt / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4)
             m /= np.linalg.norm(m, axis=1, keepdims=True)
         return m
+
+    # -- implicit midpoint (small meshes: dense operators) ------------------
+    def field_matrix(self, method="aim", terms=("ex", "ms")):
+        """Dense A [3N', 3N'] with H(m) = A m (row-major [node][component]):
+        the field without the applied part is linear in m (Eqs. hex, hms_d)."""
+        n3 = 3 * self.n
+        A = np.empty((n3, n3))
+        for j in range(n3):
+            e = np.zeros(n3)
+            e[j] = 1.0
+            A[:, j] = self.heff(e.reshape(self.n, 3), None, method, terms).ravel()
+        return A
+
+    @staticmethod
+    def _cross_matrix(v):
+        """[N,3,3] matrices C with C[n] w = v[n] x w."""
+        C = np.zeros(v.shape[:1] + (3, 3))
+        C[:, 0, 1], C[:, 0, 2] = -v[:, 2], v[:, 1]
+        C[:, 1, 0], C[:, 1, 2] = v[:, 2], -v[:, 0]
+        C[:, 2, 0], C[:, 2, 1] = -v[:, 1], v[:, 0]
+        return C
+
+    def implicit_midpoint(self, m, dt, alpha, n_steps, method="aim", terms=("ex", "ms"),
+                          h_app=None, tol=1e-14, max_newton=30, A=None):
+        """n_steps of x = m + dt f((m + x)/2), f the right side of Eq. llg;
+        Newton on G(x) = x - m - dt f(mb), mb = (m + x)/2, with
+        dG/dx = I - (dt/2) df/dmb,
+        df/dmb w = c [w x H + mb x (A w) + alpha (w x (mb x H) + mb x (w x H)
+                   + mb x (mb x (A w)))],  c = -gamma0/(1 + alpha^2).
+        Returns the final m and the Newton iterations of each step."""
+        n = self.n
+        A = self.field_matrix(method, terms) if A is None else A
+        b = np.zeros(3) if h_app is None else np.asarray(h_app, dtype=np.float64)
+        c = -GAMMA0 / (1 + alpha * alpha)
+        m = np.array(m, dtype=np.float64, copy=True)
+        iters = []
+        for _ in range(n_steps):
+            x = m.copy()
+            for it in range(max_newton):
+                mb = 0.5 * (m + x)
+                H = (A @ mb.ravel()).reshape(n, 3) + b[None, :]
+                mxh = np.cross(mb, H)
+                G = x - m - dt * c * (mxh + alpha * np.cross(mb, mxh))
+                if np.abs(G).max() <= tol:
+                    break
+                CH, CM, CMH = self._cross_matrix(H), self._cross_matrix(mb), self._cross_matrix(mxh)
+                local = -CH - alpha * CMH - alpha * CM @ CH       # [N,3,3], acts on w
+                left = CM + alpha * CM @ CM                       # [N,3,3], acts on A w
+                J = np.zeros((3 * n, 3 * n))
+                for k in range(n):
+                    J[3 * k:3 * k + 3, 3 * k:3 * k + 3] += local[k]
+                    J[3 * k:3 * k + 3, :] += left[k] @ A[3 * k:3 * k + 3, :]
+                dG = np.eye(3 * n) - 0.5 * dt * c * J
+                x = x - np.linalg.solve(dG, G.ravel()).reshape(n, 3)
+            else:
+                raise RuntimeError("implicit midpoint: Newton did not converge")
+            iters.append(it)
+            m = x
+        return m, iters

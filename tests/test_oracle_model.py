@@ -221,3 +221,74 @@ def test_laminate_exchange_per_material():
         assert np.allclose(H[sel], c * m[sel], rtol=1e-9, atol=1e-9 * abs(c))
     # uniform magnetisation has no exchange field across the interface either
     assert np.abs(o.ops.exchange(np.tile([0.0, 0.6, 0.8], (o.n, 1)))).max() < 1e-6
+
+
+# --- implicit midpoint (the paper integrates implicitly, Sec. 2.2) ---------
+
+def test_implicit_midpoint_undamped_macrospin_is_a_cayley_rotation():
+    """alpha = 0, uniform m in a fully filled 3D-periodic cell (no exchange or
+    demagnetising field), H = H z: x - m = -gamma0 dt ((m + x)/2) x H is the
+    Cayley transform of the rotation, i.e. each step turns m about z by
+    exactly 2 atan(gamma0 H dt / 2) and keeps its polar angle."""
+    p = mg.kuhn_box((3, 3, 3), 2e-9, periodic=0b111, Ms=MS, grid=(12, 12, 12))
+    o = model.Oracle(p)
+    th0, ph0, Hap, dt, n = 0.9, 0.3, 2e5, 2e-12, 12
+    m0 = np.tile([np.sin(th0) * np.cos(ph0), np.sin(th0) * np.sin(ph0), np.cos(th0)], (o.n, 1))
+    m, its = o.implicit_midpoint(m0, dt, 0.0, n, h_app=[0.0, 0.0, Hap])
+    ph = ph0 + n * 2 * np.arctan(model.GAMMA0 * Hap * dt / 2)
+    ex = np.array([np.sin(th0) * np.cos(ph), np.sin(th0) * np.sin(ph), np.cos(th0)])
+    assert np.abs(m - ex[None, :]).max() < 1e-9
+    # the explicit-rate angle gamma0 H dt per step would be off by far more
+    ph_rate = ph0 + n * model.GAMMA0 * Hap * dt
+    assert abs(ph_rate - ph) > 1e-4
+
+
+def test_implicit_midpoint_damped_macrospin_second_order():
+    p = mg.kuhn_box((3, 3, 3), 2e-9, periodic=0b111, Ms=MS, grid=(12, 12, 12))
+    o = model.Oracle(p)
+    A = o.field_matrix()
+    th0, ph0, Hap, alpha, T = 0.9, 0.3, 2e5, 0.3, 4e-12
+    m0 = np.tile([np.sin(th0) * np.cos(ph0), np.sin(th0) * np.sin(ph0), np.cos(th0)], (o.n, 1))
+    g = model.GAMMA0 * Hap / (1 + alpha ** 2)
+    th = 2 * np.arctan(np.tan(th0 / 2) * np.exp(-alpha * g * T))
+    ph = ph0 + g * T
+    ex = np.array([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)])
+    errs = []
+    for n in (4, 8, 16):
+        m, _ = o.implicit_midpoint(m0, T / n, alpha, n, h_app=[0.0, 0.0, Hap], A=A)
+        errs.append(np.abs(m - ex[None, :]).max())
+        assert np.allclose(np.linalg.norm(m, axis=1), 1.0, atol=1e-13)
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.6 < r1 < 4.4 and 3.6 < r2 < 4.4, errs
+
+
+def test_implicit_midpoint_conserves_exchange_energy_without_damping():
+    """E_ex = m.K m is quadratic and conserved by the undamped flow, so the
+    midpoint rule keeps it to the Newton tolerance (RK4 only to its order),
+    and |m| stays 1 with no renormalisation."""
+    p = mg.kuhn_box((4, 4, 1), 2e-9, periodic=0b011, jitter=0.2, grid=(12, 12, 4))
+    o = model.Oracle(p, with_aim=False)
+    m0 = o.unknown_values(p.m)
+    e0 = o.ops.exchange_energy(m0)
+    m, its = o.implicit_midpoint(m0, 2e-14, 0.0, 10, method="direct", terms=("ex",))
+    assert abs(o.ops.exchange_energy(m) - e0) < 1e-11 * abs(e0)
+    assert np.allclose(np.linalg.norm(m, axis=1), 1.0, atol=1e-13)
+    assert max(its) <= 8
+    # RK4 at the same step drifts visibly more
+    mr = o.rk4(m0, 2e-14, 0.0, 10, method="direct", terms=("ex",))
+    assert abs(o.ops.exchange_energy(mr) - e0) > 100 * abs(o.ops.exchange_energy(m) - e0)
+
+
+def test_implicit_midpoint_agrees_with_rk4_on_the_film(film):
+    """Both rules approximate the same flow: at a step well inside RK4's
+    accuracy the two trajectories agree to the midpoint rule's O(dt^2)."""
+    o = model.Oracle(film)
+    m0 = o.unknown_values(film.m)
+    A = o.field_matrix()
+    mi, _ = o.implicit_midpoint(m0, 2e-14, 0.5, 10, A=A)
+    mi2, _ = o.implicit_midpoint(m0, 1e-14, 0.5, 20, A=A)
+    mr = o.rk4(m0, 1e-14, 0.5, 20)
+    e1 = np.linalg.norm(mi - mr) / np.linalg.norm(mr - m0)
+    e2 = np.linalg.norm(mi2 - mr) / np.linalg.norm(mr - m0)
+    assert e2 < e1 / 3.5 and e1 < 1e-2, (e1, e2)
+    assert np.allclose(np.linalg.norm(mi, axis=1), 1.0, atol=1e-13)
