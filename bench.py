@@ -95,7 +95,25 @@ def measured_traffic(kernel):
     return None
 
 
-def cpu_baseline(prob, rows_sample=64, seed=7):
+def host_info():
+    """CPU model and the number of hardware threads this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        threads = os.cpu_count() or 1
+    return model, threads
+
+
+def cpu_baseline(prob, rows_sample=64, seed=7, budget_s=10.0):
     """Time the FP64 oracle on a bounded sample of the same workload.
 
     The oracle's operators for a sample of observer rows are built untimed
@@ -103,9 +121,12 @@ def cpu_baseline(prob, rows_sample=64, seed=7):
     full-size steps (exchange, charges, projection, 3D FFT convolution) once,
     plus interpolation, precorrection and element correction on the ring of
     the sampled rows and the gradient at the sampled rows, extrapolated
-    linearly to all N' rows.
+    linearly to all N' rows. It is timed twice: with its thread pools held to
+    one thread, and with every hardware thread of the host allowed; the
+    threads actually used are the process CPU time over the wall time.
     """
     from oracle import model
+    from threadpoolctl import threadpool_limits
     t0 = time.perf_counter()
     orc = model.Oracle(prob)
     log(f"  oracle operators built ({time.perf_counter() - t0:.0f} s)")
@@ -119,45 +140,91 @@ def cpu_baseline(prob, rows_sample=64, seed=7):
     P = orc._cache[("P", tuple(ring.tolist()))]
     Z = orc.z0(ring)
     A = orc.aim
-    tt = {k: 0.0 for k in ("exchange", "charges", "grid", "ring", "grad")}
-    reps = 0
-    from threadpoolctl import threadpool_limits
-    limiter = threadpool_limits(limits=1)   # the oracle as it stands, on one core
-    # repeat the evaluation until about 10 s of CPU work have been timed
-    while reps < 200 and (reps == 0 or sum(tt.values()) < 10.0):
-        t = time.perf_counter()
-        orc.ops.exchange(m)
-        tt["exchange"] += time.perf_counter() - t
-        t = time.perf_counter()
-        q = orc.ops.charges(m)
-        tt["charges"] += time.perf_counter() - t
-        t = time.perf_counter()
-        U = A.convolve(A.project(q))
-        tt["grid"] += time.perf_counter() - t
-        t = time.perf_counter()
-        u_ring = ((A.interpolate(U, ring) + P @ q) / (4 * np.pi)
-                  + sum(Z[c] @ m[:, c] for c in range(3)))
-        tt["ring"] += time.perf_counter() - t
-        u = np.zeros(orc.n)
-        u[ring] = u_ring
-        t = time.perf_counter()
-        orc.ops.gradient_field(u, rows)
-        tt["grad"] += time.perf_counter() - t
-        reps += 1
-    limiter.restore_original_limits()
-    full = (tt["exchange"] + tt["charges"] + tt["grid"] + tt["ring"] * orc.n / ring.size
-            + tt["grad"] * orc.n / rows.size) / reps
+
+    def timed(limit):
+        tt = {k: 0.0 for k in ("exchange", "charges", "grid", "ring", "grad")}
+        reps = 0
+        limiter = threadpool_limits(limits=limit)
+        c0, w0 = time.process_time(), time.perf_counter()
+        # repeat the evaluation until about budget_s of CPU work have been timed
+        while reps < 200 and (reps == 0 or sum(tt.values()) < budget_s):
+            t = time.perf_counter()
+            orc.ops.exchange(m)
+            tt["exchange"] += time.perf_counter() - t
+            t = time.perf_counter()
+            q = orc.ops.charges(m)
+            tt["charges"] += time.perf_counter() - t
+            t = time.perf_counter()
+            U = A.convolve(A.project(q))
+            tt["grid"] += time.perf_counter() - t
+            t = time.perf_counter()
+            u_ring = ((A.interpolate(U, ring) + P @ q) / (4 * np.pi)
+                      + sum(Z[c] @ m[:, c] for c in range(3)))
+            tt["ring"] += time.perf_counter() - t
+            u = np.zeros(orc.n)
+            u[ring] = u_ring
+            t = time.perf_counter()
+            orc.ops.gradient_field(u, rows)
+            tt["grad"] += time.perf_counter() - t
+            reps += 1
+        used = (time.process_time() - c0) / max(time.perf_counter() - w0, 1e-9)
+        limiter.restore_original_limits()
+        full = (tt["exchange"] + tt["charges"] + tt["grid"] + tt["ring"] * orc.n / ring.size
+                + tt["grad"] * orc.n / rows.size) / reps
+        return 1.0 / full, reps, sum(tt.values()), used
+
+    model_name, threads = host_info()
+    v1, reps1, t1, used1 = timed(1)
+    log(f"  one thread: {v1:.4f} evals/s ({reps1} reps, {t1:.1f} s, {used1:.2f} threads busy)")
+    va, repsa, ta, useda = timed(threads)
+    log(f"  {threads} threads allowed: {va:.4f} evals/s ({repsa} reps, {ta:.1f} s, "
+        f"{useda:.2f} threads busy)")
     return {
-        "value": 1.0 / full,
+        "value": v1,
         "unit": "H_eff evals/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"one FP64 oracle evaluation: full-size exchange, charges and 128^3 FFT "
-                   f"convolution timed once; interpolation+precorrection+element correction "
-                   f"on the {ring.size}-row ring of {rows.size} sampled rows and their "
-                   f"gradient, scaled to N'={orc.n}; {reps} repetitions, timed "
-                   f"{sum(tt.values()):.1f} s (setup {t_setup:.0f} s untimed)"),
+        "sample": (f"one FP64 oracle evaluation: full-size exchange, charges and "
+                   f"{'x'.join(str(g) for g in prob.grid)} FFT convolution timed once; "
+                   f"interpolation+precorrection+element correction on the {ring.size}-row "
+                   f"ring of {rows.size} sampled rows and their gradient, scaled to "
+                   f"N'={orc.n}; {reps1} repetitions, timed {t1:.1f} s (setup "
+                   f"{t_setup:.0f} s untimed)"),
+        "all_threads": {"value": va, "threads_allowed": threads,
+                        "threads_busy": round(useda, 2), "reps": repsa,
+                        "timed_s": round(ta, 1)},
+        "host": {"cpu_model": model_name, "nproc": threads},
     }
+
+
+def sampled_error(ctx, prob, name, m, h):
+    """Relative error of the timed run's H_eff (and of H_ex, H_ms evaluated
+    alone) at the unknowns whose FP64 oracle values are stored with the tests:
+    relative L2 over the samples and max-norm relative to the largest sample."""
+    import torch
+    from paper_2409_13958_amd import binding as B
+    path = os.path.join(ROOT, "tests", "golden", "expected_fullsize.npz")
+    try:
+        exp = np.load(path)
+    except OSError:
+        return None
+    if f"{name}_nodes" not in exp.files:
+        return None
+    _, uon, _, _ = ctx.query()
+    idx = uon[exp[f"{name}_nodes"]]
+    hex_, hms = torch.empty_like(h), torch.empty_like(h)
+    ctx.heff(m, hex_, terms=B.TERM_EX)
+    ctx.heff(m, hms, terms=B.TERM_MS)
+    torch.cuda.synchronize()
+    out = {"samples": int(idx.size),
+           "reference": "FP64 oracle (same AIM), stored at sampled unknowns"}
+    for k, v in (("h_eff", h), ("h_ex", hex_), ("h_ms", hms)):
+        got = v.cpu().numpy().astype(np.float64)[idx]
+        ref = exp[f"{name}_{k.replace('_eff', '').replace('_', '')}"]
+        d = got - ref
+        out[k] = {"rel_l2": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+                  "rel_max": float(np.abs(d).max() / np.abs(ref).max())}
+    return out
 
 
 def main():
@@ -214,6 +281,13 @@ def main():
     t1 = time.perf_counter()
     dt = (t1 - t0) / args.steps
     log(f"timed {args.steps} steps: {dt * 1e3:.4f} ms/step")
+    # error of the timed run's output against the stored oracle values
+    h_timed = h.clone()
+    rel_err = sampled_error(ctx, prob, args.config, m, h_timed)
+    if rel_err:
+        log("error vs FP64 oracle at %d samples: " % rel_err["samples"]
+            + " ".join(f"{k} {rel_err[k]['rel_l2']:.2e}/{rel_err[k]['rel_max']:.2e}"
+                       for k in ("h_eff", "h_ex", "h_ms")) + " (rel L2 / rel max)")
     # the same number of evaluations again with a HIP event pair around every
     # kernel (on the stream it runs on): per-kernel durations for the roofline
     # (the events add gaps between kernels, so this pass is not the one timed)
@@ -281,6 +355,7 @@ def main():
             "stream_frac": achieved / stream_gbs,
             "traffic": measured_traffic(dom) if args.config == "composite_c3" else None,
         },
+        "rel_err": rel_err,
     }
     if rank == 0 and not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle, bounded sample) ...")
