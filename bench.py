@@ -7,7 +7,7 @@ one full H_eff = H_ex + H_ms evaluation (all nine kernels) of a fixed
 magnetisation already resident in HBM. Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME]
-                    [--no-cpu-baseline] [--copy-mib MIB]
+                    [--precision 0|1|2] [--no-cpu-baseline] [--copy-mib MIB]
 """
 from __future__ import annotations
 
@@ -29,8 +29,12 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_bytes(ctx, names):
-    """Algorithmic HBM bytes per launch of each named kernel (every array once)."""
+def kernel_bytes(ctx, names, precision=0):
+    """Algorithmic HBM bytes per launch of each named kernel (every array once).
+
+    precision 1 stores the grid charges and potential as BF16 (2 bytes per
+    grid value), precision 0 as FP32 and precision 2 as a BF16 pair (4)."""
+    gb = 2.0 if precision == 1 else 4.0
     info = ctx.export("grid_info")
     N = info[0:3].astype(np.int64)
     M = info[3:6].astype(np.int64)
@@ -47,17 +51,17 @@ def kernel_bytes(ctx, names):
     fam = {
         "k_charges": n * (4 + 12 + 4) + nL * 16,
         "k_zcorr": n * (4 + 12 + 4) + nZ * 16,
-        "k_anterp": n * (4 + 16) + nbox * 4 + ng * 4,
+        "k_anterp": n * (4 + 16) + nbox * 4 + ng * gb,
         "k_anterp_scatter": n * (4 + 16 + 4),
-        "k_anterp_sum": ng * 4,
-        "k_r2c_x": ng * 4 + s_in,
+        "k_anterp_sum": ng * gb,
+        "k_r2c_x": ng * gb + s_in,
         "k_fft_y_fwd": s_in + s_full,
         "k_fft_z_mul": 2 * s_full + khat,
         "k_fft_y_inv": s_full + s_in,
-        "k_c2r_x": s_in + ng * 4,
-        "k_fft_xy_fwd": ng * 4 + s_full,
-        "k_fft_yx_inv": s_full + ng * 4,
-        "k_interp": n * (16 + 4 + 4 + 4 + 4) + ng * 4 + nP * 4,
+        "k_c2r_x": s_in + ng * gb,
+        "k_fft_xy_fwd": ng * gb + s_full,
+        "k_fft_yx_inv": s_full + ng * gb,
+        "k_interp": n * (16 + 4 + 4 + 4 + 4) + ng * gb + nP * 4,
         "k_grad": n * (4 + 12 + 4 + 12) + nL * 20,
         "k_exch": n * (4 + 12 + 12) + nL * 8,
         "k_gsum": n * (4 + 4 + 12 + 12) + nL * 16,
@@ -234,6 +238,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", default="composite_c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", type=int, default=0, choices=(0, 1, 2),
+                    help="grid storage: 0 FP32, 1 BF16, 2 BF16 hi + lo (one refinement step)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also stream this many MiB through plain kernels (counter calibration)")
     args = ap.parse_args()
@@ -251,7 +257,7 @@ def main():
     log(f"mesh {args.config}: {prob.n_nodes} nodes, {prob.tets.shape[0]} tets "
         f"({time.perf_counter() - t:.1f} s)")
     t = time.perf_counter()
-    ctx = B.Context.from_problem(prob, device=0)
+    ctx = B.Context.from_problem(prob, device=0, precision=args.precision)
     n, uon, nou, bpe = ctx.query()
     log(f"setup: N'={n}, model bytes/eval={bpe / 1e9:.3f} GB ({time.perf_counter() - t:.1f} s)")
     m = torch.tensor(prob.m[nou], dtype=torch.float32, device="cuda")
@@ -312,7 +318,7 @@ def main():
     stream_gbs = 2 * src.numel() * 4 / ((time.perf_counter() - t4) / 10) / 1e9
     del src, dst
     log(f"plain stream (elementwise, read + write): {stream_gbs:.0f} GB/s")
-    kb = kernel_bytes(ctx, list(prof))
+    kb = kernel_bytes(ctx, list(prof), args.precision)
     per_kernel = {k: (ms / max(c, 1), c) for k, (ms, c) in prof.items()}
     for k, (avg, c) in per_kernel.items():
         gbs = kb[k] / (avg * 1e-3) / 1e9 if avg > 0 else 0.0
@@ -320,8 +326,10 @@ def main():
     dom = max(per_kernel, key=lambda k: per_kernel[k][0])
     avg_ms = per_kernel[dom][0]
     achieved = kb[dom] / (avg_ms * 1e-3) / 1e9
+    storage = {0: "fp32", 1: "bf16", 2: "bf16 hi+lo"}[args.precision]
     result = {
-        "metric": "H_eff evals/s at 1M nodes (plain FP32)",
+        "metric": ("H_eff evals/s at 1M nodes (plain FP32)" if args.precision == 0 else
+                   f"H_eff evals/s at 1M nodes (FP32 arithmetic, {storage} grid storage)"),
         "value": 1.0 / dt,
         "unit": "H_eff evals/s",
         "n_gpus": 1,
@@ -339,6 +347,7 @@ def main():
                          f"{'x'.join(str(g) for g in prob.grid)}, p={prob.order_p}, "
                          f"r_b={prob.near_boxes}, kappa={prob.z0_radius:g}"),
             "name": args.config,
+            "grid_storage": storage,
             "n_unknowns": n,
             "model_bytes_per_eval": bpe,
             "model_gbs": bpe / dt / 1e9,
@@ -353,7 +362,8 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "stream_gbs": stream_gbs,
             "stream_frac": achieved / stream_gbs,
-            "traffic": measured_traffic(dom) if args.config == "composite_c3" else None,
+            "traffic": (measured_traffic(dom)
+                        if args.config == "composite_c3" and args.precision == 0 else None),
         },
         "rel_err": rel_err,
     }

@@ -94,7 +94,17 @@ int pmfem_set_periodicity(pmfem_ctx* ctx, uint32_t axis_mask, const double L[3],
  * order_p (1..5) of projection/interpolation; near_boxes = r_b (0..3), the
  * per-axis box radius of the precorrection region; z0_radius_edges = kappa,
  * the radius of the element-exact correction in mean edge lengths;
- * precision must be 0 (FP32 grid and operators). On a periodic axis the
+ * precision selects how the grid charges Q and the grid potential U are
+ * stored between the kernels of an evaluation (Sec. 3.2.2 steps 1-3; the
+ * paper's own path is single precision at a 1e-3 error level, Sec. 4.5):
+ * 0 FP32; 1 BF16 (half the grid bytes, about 8 significant bits); 2 BF16
+ * with one refinement step, each grid value stored as the BF16 pair
+ * hi = bf16(v), lo = bf16(v - hi) and widened to hi + lo before use (the
+ * grid bytes of FP32, about 16 significant bits). All arithmetic, the FFT
+ * spectrum, K-hat and every other operator stay FP32; the PGF, the
+ * precorrection and element-exact assembly stay FP64 on the host. Other
+ * values are EINVAL at pmfem_build. pmfem_grid_convolve always takes and
+ * returns FP32 grids. On a periodic axis the
  * grid spacing is L/N and the FFT extent is N; on a non-periodic axis the
  * grid spans the mesh and the FFT extent is 2N. FFT extents must be powers
  * of two in [4, 512]; periodic axes need N >= 2 (r_b + p) + 1.

@@ -186,14 +186,14 @@ class Context:
 
     @classmethod
     def from_problem(cls, prob, device=0, stream=None, order_p=None, near_boxes=None,
-                     z0_radius=None):
+                     z0_radius=None, precision=0):
         ctx = cls(device, stream)
         ctx.set_mesh(prob.xyz, prob.tets, prob.region)
         ctx.set_materials(prob.Ms, prob.Aex)
         ctx.set_periodicity(prob.periodic, prob.L)
         ctx.set_aim(prob.grid, prob.order_p if order_p is None else order_p,
                     prob.near_boxes if near_boxes is None else near_boxes,
-                    prob.z0_radius if z0_radius is None else z0_radius)
+                    prob.z0_radius if z0_radius is None else z0_radius, precision)
         ctx.build()
         return ctx
 

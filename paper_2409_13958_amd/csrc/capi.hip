@@ -26,6 +26,7 @@ using namespace pmfem;
 #define PMFEM_IC_LDS_BUDGET 24576  // LDS bytes per interpolation tile
 #endif
 
+
 struct pmfem_dev {
   int64_t n = 0;
   GridParams g{};
@@ -583,6 +584,7 @@ int upload_all(pmfem_ctx* c) {
   for (int a = 0; a < 3; ++a) d->g.per[a] = o.per[a];
   d->g.p = o.p;
   d->g.rb = o.rb;
+  d->g.gmode = c->precision;  // grid storage between the kernels of one evaluation
   int rc;
   if ((rc = upload(c, &d->pos4, o.pos4.data(), n))) return rc;
   if ((rc = upload(c, &d->box_start, o.box_start.data(), o.box_start.size()))) return rc;
@@ -791,9 +793,14 @@ int upload_all(pmfem_ctx* c) {
 hipStream_t stream_of(pmfem_ctx* c) { return (hipStream_t)c->stream; }
 
 // Step 2 of the AIM: Ug = (1/4 pi) K * Qg on the grid (profiling slots 2-6).
+// spec: the half-spectrum work buffer ([N_z][M_y][M_x/2 + 1] complex),
+// written in full by the forward passes before any pass reads it.
+// gmode: storage of Qg and Ug (GridParams::gmode; 0 for caller FP32 grids).
 template <class Mark>
-void convolve(pmfem_dev* d, hipStream_t s, const float* Qg, float* Ug, Mark&& mark) {
-  const GridParams& g = d->g;
+void convolve(pmfem_dev* d, hipStream_t s, const float* Qg, float* Ug, float2* spec, int gmode,
+              Mark&& mark) {
+  GridParams g = d->g;
+  g.gmode = gmode;
   const int T = 256;
   const int Mx = g.M[0], My = g.M[1], Mz = g.M[2], Hx = Mx / 2 + 1;
   const int Bz = std::max(1, std::min(PMFEM_FFTZ_B, 4096 / Mz)), Tz = PMFEM_FFTZ_T;
@@ -801,16 +808,16 @@ void convolve(pmfem_dev* d, hipStream_t s, const float* Qg, float* Ug, Mark&& ma
   if (d->fft_plane) {
     mark(2, 0);
     hipLaunchKernelGGL(k_fft_xy_fwd, dim3((unsigned)(g.N[2] * PMFEM_FFT_SPLIT)), dim3(1024),
-                       d->fft_plane_lds, s, g, Qg, d->spec, d->twx, d->twy, PMFEM_FFT_SPLIT);
+                       d->fft_plane_lds, s, g, Qg, spec, d->twx, d->twy, PMFEM_FFT_SPLIT);
     mark(2, 1);
     mark(4, 0);
     hipLaunchKernelGGL(k_fft_z_mul, dim3((unsigned)((cols + Bz - 1) / Bz)), dim3(Tz),
-                       (size_t)(Mz / 2 + Bz * Mz) * sizeof(float2), s, g, d->spec, d->khat,
+                       (size_t)(Mz / 2 + Bz * Mz) * sizeof(float2), s, g, spec, d->khat,
                        d->twz, Bz);
     mark(4, 1);
     mark(6, 0);
     hipLaunchKernelGGL(k_fft_yx_inv, dim3((unsigned)(g.N[2] * PMFEM_FFT_SPLIT)), dim3(1024),
-                       d->fft_plane_lds, s, g, (const float2*)d->spec, Ug, d->twx, d->twy,
+                       d->fft_plane_lds, s, g, (const float2*)spec, Ug, d->twx, d->twy,
                        PMFEM_FFT_SPLIT);
     mark(6, 1);
     return;
@@ -819,29 +826,29 @@ void convolve(pmfem_dev* d, hipStream_t s, const float* Qg, float* Ug, Mark&& ma
   const int64_t xlines = (int64_t)((g.N[1] + 1) / 2) * g.N[2];
   mark(2, 0);
   hipLaunchKernelGGL(k_r2c_x, dim3((unsigned)((xlines + lpb - 1) / lpb)), dim3(T),
-                     (size_t)(Mx / 2 + lpb * Mx) * sizeof(float2), s, g, Qg, d->spec, d->twx,
+                     (size_t)(Mx / 2 + lpb * Mx) * sizeof(float2), s, g, Qg, spec, d->twx,
                      lpb);
   mark(2, 1);
   const int By = std::max(1, std::min(16, 4096 / My));
   const int gy = (Hx + By - 1) / By;
   mark(3, 0);
   hipLaunchKernelGGL(k_fft_y, dim3((unsigned)(g.N[2] * gy)), dim3(T),
-                     (size_t)(My / 2 + By * My) * sizeof(float2), s, g, d->spec, d->twy, By, 0,
+                     (size_t)(My / 2 + By * My) * sizeof(float2), s, g, spec, d->twy, By, 0,
                      g.N[1], My);
   mark(3, 1);
   mark(4, 0);
   hipLaunchKernelGGL(k_fft_z_mul, dim3((unsigned)((cols + Bz - 1) / Bz)), dim3(Tz),
-                     (size_t)(Mz / 2 + Bz * Mz) * sizeof(float2), s, g, d->spec, d->khat, d->twz,
+                     (size_t)(Mz / 2 + Bz * Mz) * sizeof(float2), s, g, spec, d->khat, d->twz,
                      Bz);
   mark(4, 1);
   mark(5, 0);
   hipLaunchKernelGGL(k_fft_y, dim3((unsigned)(g.N[2] * gy)), dim3(T),
-                     (size_t)(My / 2 + By * My) * sizeof(float2), s, g, d->spec, d->twy, By, 1,
+                     (size_t)(My / 2 + By * My) * sizeof(float2), s, g, spec, d->twy, By, 1,
                      My, g.N[1]);
   mark(5, 1);
   mark(6, 0);
   hipLaunchKernelGGL(k_c2r_x, dim3((unsigned)((xlines + lpb - 1) / lpb)), dim3(T),
-                     (size_t)(Mx / 2 + lpb * Mx) * sizeof(float2), s, g, d->spec, Ug, d->twx,
+                     (size_t)(Mx / 2 + lpb * Mx) * sizeof(float2), s, g, spec, Ug, d->twx,
                      lpb);
   mark(6, 1);
 }
@@ -979,7 +986,7 @@ int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const doubl
                          d->box_start, d->brx, d->bry, d->brz, d->grid);
       mark(1, 1);
     }
-    convolve(d, s, d->grid, d->grid, mark);
+    convolve(d, s, d->grid, d->grid, d->spec, d->g.gmode, mark);
     (void)hipStreamWaitEvent(s, d->join, 0);
     mark(7, 0);
     {
@@ -1189,13 +1196,14 @@ int pmfem_query(pmfem_ctx* c, int64_t* n_unknowns, int64_t* unknown_of_node,
     const double hx = o.M[0] / 2 + 1;
     const double spec = (double)o.N[2] * o.M[1] * hx * 8.0;
     const double khat = hx * o.M[1] * o.M[2] * 4.0;
+    const double gb = c->precision == 1 ? 2.0 : 4.0;  // bytes per stored grid value
     double b = 0;
     b += 2 * n * (4 + 12 + 4) + nL * 16 + nZ * 16;                      // charges, u_Z
-    b += n * (16 + 4) + ng * 4 + (double)o.box_start.size() * 4;       // anterpolation
-    b += ng * 4 + spec;                                                  // x/y forward
+    b += n * (16 + 4) + ng * gb + (double)o.box_start.size() * 4;      // anterpolation
+    b += ng * gb + spec;                                                 // x/y forward
     b += 2 * spec + khat;                                                // z, K multiply
-    b += spec + ng * 4;                                                  // y/x inverse
-    b += n * (16 + 4 + 4 + 4 + 4) + ng * 4 + nP * 4;                     // interp+corr
+    b += spec + ng * gb;                                                 // y/x inverse
+    b += n * (16 + 4 + 4 + 4 + 4) + ng * gb + nP * 4;                    // interp+corr
     b += n * (4 + 12 + 12) + nL * 8;                                     // exchange
     b += n * (4 + 4 + 12 + 12) + nL * 16;                                // gradient sum
     *bytes_per_eval = b;
@@ -1237,7 +1245,7 @@ int pmfem_grid_convolve(pmfem_ctx* c, const float* q_grid_dev, float* u_grid_dev
   pmfem_dev* d = c->dev;
   const GridParams& g = d->g;
   hipStream_t s = stream_of(c);
-  convolve(d, s, q_grid_dev, u_grid_dev, [](int, int) {});
+  convolve(d, s, q_grid_dev, u_grid_dev, d->spec, 0, [](int, int) {});
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_err(c, e, "kernel launch");
   return PMFEM_OK;

@@ -14,6 +14,9 @@ struct GridParams {
   int per[3];   // periodic axes
   int p;        // Lagrange order
   int rb;       // near-region radius in boxes (<= 3)
+  int gmode;    // storage of the grid charges Q and potential U between
+                // kernels: 0 FP32; 1 BF16; 2 BF16 pair hi + lo (the hi part
+                // in the first N_g halves of the buffer, the lo part after)
 };
 
 // anterpolation tile (grid points per workgroup) and staged-node capacity

@@ -62,6 +62,43 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Grid storage (GridParams::gmode). BF16 is the upper half of an FP32 word,
+// rounded to nearest even (the grid values are finite); the pair form keeps
+// the rounding residual as a second BF16 value, so hi + lo carries 16
+// significant bits. Arithmetic stays FP32: values are widened on load.
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+  return __uint_as_float((uint32_t)h << 16);
+}
+
+__device__ __forceinline__ int64_t grid_points(const GridParams& g) {
+  return (int64_t)g.N[0] * g.N[1] * g.N[2];
+}
+
+__device__ __forceinline__ void grid_store(float* G, int64_t i, float v, const GridParams& g) {
+  if (g.gmode == 0) {
+    G[i] = v;
+    return;
+  }
+  uint16_t* H = reinterpret_cast<uint16_t*>(G);
+  const uint16_t hi = f32_to_bf16(v);
+  H[i] = hi;
+  if (g.gmode == 2) H[grid_points(g) + i] = f32_to_bf16(v - bf16_to_f32(hi));
+}
+
+__device__ __forceinline__ float grid_load(const float* G, int64_t i, const GridParams& g) {
+  if (g.gmode == 0) return G[i];
+  const uint16_t* H = reinterpret_cast<const uint16_t*>(G);
+  float v = bf16_to_f32(H[i]);
+  if (g.gmode == 2) v += bf16_to_f32(H[grid_points(g) + i]);
+  return v;
+}
+
 __device__ __forceinline__ int st_of(uint32_t packed, int axis) {
   return (int)((packed >> (10 * axis)) & 1023u);
 }
@@ -257,7 +294,7 @@ __global__ void __launch_bounds__(256) k_anterp(
   const bool inside = lx < te[0] && ly < te[1] && lz < te[2];
   const int gx = t0[0] + lx, gy = t0[1] + ly, gz = t0[2] + lz;
   if (total == 0) {  // no node reaches this tile (uniform across the block)
-    if (inside) Q[((int64_t)gz * g.N[1] + gy) * g.N[0] + gx] = 0.f;
+    if (inside) grid_store(Q, ((int64_t)gz * g.N[1] + gy) * g.N[0] + gx, 0.f, g);
     return;
   }
   const bool staged = total <= kAntCap;
@@ -317,7 +354,7 @@ __global__ void __launch_bounds__(256) k_anterp(
       }
     }
   }
-  Q[((int64_t)gz * g.N[1] + gy) * g.N[0] + gx] = acc;
+  grid_store(Q, ((int64_t)gz * g.N[1] + gy) * g.N[0] + gx, acc, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -424,7 +461,7 @@ __global__ void __launch_bounds__(128) k_anterp_line(
       }
     }
   }
-  Q[((int64_t)gz * g.N[1] + gy) * g.N[0] + gx] = acc;
+  grid_store(Q, ((int64_t)gz * g.N[1] + gy) * g.N[0] + gx, acc, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -637,7 +674,7 @@ __global__ void __launch_bounds__(256) k_anterp_sum(GridParams g, ScPlan pl,
         for (int kx = 0; kx < 2; ++kx) sum[k] += val[kz][ky][k][kx];
   }
 #pragma unroll
-  for (int k = 0; k < PT; ++k) Q[i0 + k] = sum[k];
+  for (int k = 0; k < PT; ++k) grid_store(Q, i0 + k, sum[k], g);
 }
 
 template __global__ void k_anterp_sum<1>(GridParams, ScPlan, const int2*, const int2*,
@@ -779,8 +816,8 @@ __global__ void __launch_bounds__(256) k_r2c_x(GridParams g, const float* __rest
     int z = (int)(L / pairs), y = 2 * (int)(L % pairs);
     float re = 0.f, im = 0.f;
     if (x < g.N[0]) {
-      re = Q[((int64_t)z * g.N[1] + y) * g.N[0] + x];
-      if (y + 1 < g.N[1]) im = Q[((int64_t)z * g.N[1] + y + 1) * g.N[0] + x];
+      re = grid_load(Q, ((int64_t)z * g.N[1] + y) * g.N[0] + x, g);
+      if (y + 1 < g.N[1]) im = grid_load(Q, ((int64_t)z * g.N[1] + y + 1) * g.N[0] + x, g);
     }
     buf[li * Mx + bitrev(x, logM)] = make_float2(re, im);
   }
@@ -831,7 +868,7 @@ __global__ void __launch_bounds__(1024) k_fft_xy_fwd(GridParams g, const float* 
   const float invnk = 1.0f / (float)nk;
   for (int i = threadIdx.x; i < Mx / 2; i += blockDim.x) tx[i] = twx[i];
   for (int i = threadIdx.x; i < My / 2; i += blockDim.x) ty[i] = twy[i];
-  const float* Qz = Q + (int64_t)z * Ny * Nx;
+  const int64_t qz = (int64_t)z * Ny * Nx;
   const float invHx = 1.0f / (float)Hx;
   batched<8>(
       pairs * Mx,
@@ -839,8 +876,8 @@ __global__ void __launch_bounds__(1024) k_fft_xy_fwd(GridParams g, const float* 
         const int li = idx >> lx, x = idx & (Mx - 1), y = 2 * li;
         float2 v = make_float2(0.f, 0.f);
         if (x < Nx) {
-          v.x = Qz[(int64_t)y * Nx + x];
-          if (y + 1 < Ny) v.y = Qz[(int64_t)(y + 1) * Nx + x];
+          v.x = grid_load(Q, qz + (int64_t)y * Nx + x, g);
+          if (y + 1 < Ny) v.y = grid_load(Q, qz + (int64_t)(y + 1) * Nx + x, g);
         }
         return v;
       },
@@ -919,13 +956,13 @@ __global__ void __launch_bounds__(1024) k_fft_yx_inv(GridParams g, const float2*
   }
   __syncthreads();
   lds_fft_s(A + l0 * Mx, Mx, lx, nl, Mx, tx, -1.0f);
-  float* Uz = U + (int64_t)z * Ny * Nx;
+  const int64_t uzo = (int64_t)z * Ny * Nx;
   const float invNx = 1.0f / (float)Nx;
   for (int idx = threadIdx.x; idx < nl * Nx; idx += blockDim.x) {
     const int li = l0 + fdiv(idx, Nx, invNx), x = idx - (li - l0) * Nx, y = 2 * li;
     const float2 v = A[li * Mx + x];
-    Uz[(int64_t)y * Nx + x] = v.x;
-    if (y + 1 < Ny) Uz[(int64_t)(y + 1) * Nx + x] = v.y;
+    grid_store(U, uzo + (int64_t)y * Nx + x, v.x, g);
+    if (y + 1 < Ny) grid_store(U, uzo + (int64_t)(y + 1) * Nx + x, v.y, g);
   }
 }
 
@@ -1049,8 +1086,8 @@ __global__ void __launch_bounds__(256) k_c2r_x(GridParams g, const float2* __res
     int64_t L = l0 + li;
     int z = (int)(L / pairs), y = 2 * (int)(L % pairs);
     float2 v = buf[li * Mx + x];
-    U[((int64_t)z * g.N[1] + y) * g.N[0] + x] = v.x;
-    if (y + 1 < g.N[1]) U[((int64_t)z * g.N[1] + y + 1) * g.N[0] + x] = v.y;
+    grid_store(U, ((int64_t)z * g.N[1] + y) * g.N[0] + x, v.x, g);
+    if (y + 1 < g.N[1]) grid_store(U, ((int64_t)z * g.N[1] + y + 1) * g.N[0] + x, v.y, g);
   }
 }
 
@@ -1142,7 +1179,7 @@ __global__ void __launch_bounds__(256) PMFEM_IC_OCC k_interp_tile(
           z += z < 0 ? wz : 0;
           z -= z >= Nz ? wz : 0;
           const bool ok = okx && z < Nz && l0 + k * lpp < nl;
-          v[k] = ok ? U[(z * Ny + y) * Nx + x] : 0.f;
+          v[k] = ok ? grid_load(U, (int64_t)(z * Ny + y) * Nx + x, g) : 0.f;
           ly += dly;
           lz += dlz;
           if (ly >= p1) {

@@ -95,7 +95,8 @@ int host_build(pmfem_ctx* c) {
   const int64_t N = c->n_nodes, T = c->n_tets;
   if (!c->have_mesh || !c->have_mat || !c->have_aim)
     return fail(c, PMFEM_ESTATE, "mesh, materials and AIM parameters must be set before build");
-  if (c->precision != 0) return fail(c, PMFEM_EINVAL, "only precision 0 (FP32) is supported");
+  if (c->precision < 0 || c->precision > 2)
+    return fail(c, PMFEM_EINVAL, "precision must be 0 (FP32), 1 (BF16 grid) or 2 (BF16 hi + lo grid)");
   const int p = c->order_p, rb = c->near_boxes;
   if (p < 1 || p > 5) return fail(c, PMFEM_EINVAL, "order_p must be in [1, 5]");
   if (rb < 0 || rb > 3) return fail(c, PMFEM_EINVAL, "near_boxes must be in [0, 3]");

@@ -210,6 +210,14 @@ def test_errors_are_reported():
     with pytest.raises(lib.PmfemError) as e:
         c.build()
     assert e.value.code == lib.Status.EINVAL
+    c.set_materials(p.Ms, p.Aex)
+    c.set_aim((16, 16, 4), precision=3)   # grid storage 0, 1 or 2 only
+    with pytest.raises(lib.PmfemError) as e:
+        c.build()
+    assert e.value.code == lib.Status.EINVAL
+    for prec in (1, 2):
+        c.set_aim((16, 16, 4), precision=prec)
+        c.build()
 
 
 def test_library_exports_every_declared_symbol():
