@@ -172,6 +172,21 @@ int pmfem_heff_parts(pmfem_ctx* ctx, const float* m_dev, float* h_dev, float* q_
 int pmfem_grid_convolve(pmfem_ctx* ctx, const float* q_grid_dev, float* u_grid_dev);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as pmfem_grid_convolve (the same kernels on the same inputs, so
+ * bitwise equal), with the half-spectrum work buffer taken from a
+ * library-wide static device array instead of the context's storage. The
+ * call allocates nothing. The array holds at most 2^21 complex values
+ * (16 MiB): EINVAL if N_z * M_y * (M_x / 2 + 1) exceeds that. Each device
+ * has one such array (its address is looked up once per device in
+ * pmfem_create) and every call on that device shares it, so calls that
+ * overlap on one GPU (several streams, threads or contexts) race; it needs
+ * no clearing (the forward passes write all of it before it is read).
+ */
+int pmfem_grid_convolve_noalloc(pmfem_ctx* ctx, const float* q_grid_dev, float* u_grid_dev);
+
+/*
  * LLG time stepping (Eq. llg, unit-vector Landau-Lifshitz form,
  * gamma0 = 2.21276e5 m/(A s)): n_steps classic RK4 steps of size dt (s)
  * with damping alpha on the FP64 master magnetisation m_dev[N'][3]

@@ -58,6 +58,7 @@ _SIGS = {
     "pmfem_heff": (ctypes.c_int, [_P, _P, _P, _U32, _P]),
     "pmfem_heff_parts": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "pmfem_grid_convolve": (ctypes.c_int, [_P, _P, _P]),
+    "pmfem_grid_convolve_noalloc": (ctypes.c_int, [_P, _P, _P]),
     "pmfem_llg_step": (ctypes.c_int, [_P, _P, _D, _D, _I32, _P]),
     "pmfem_energy": (ctypes.c_int, [_P, _P, _DP, _DP]),
     "pmfem_profile_begin": (ctypes.c_int, [_P, _I32]),
@@ -253,6 +254,14 @@ class Context:
         self._check(self.lib.pmfem_grid_convolve(self.h, _dev_ptr(qg, torch.float32, shape, "qg"),
                                                  _dev_ptr(ug, torch.float32, shape, "ug")),
                     "grid_convolve")
+
+    def grid_convolve_noalloc(self, qg, ug):
+        import torch
+        info = self.export("grid_info")
+        shape = (int(info[2]), int(info[1]), int(info[0]))
+        self._check(self.lib.pmfem_grid_convolve_noalloc(
+            self.h, _dev_ptr(qg, torch.float32, shape, "qg"),
+            _dev_ptr(ug, torch.float32, shape, "ug")), "grid_convolve_noalloc")
 
     def llg_step(self, m64, dt, alpha, n_steps=1, h_applied=None):
         import torch

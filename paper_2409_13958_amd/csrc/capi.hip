@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -26,6 +27,16 @@ using namespace pmfem;
 #define PMFEM_IC_LDS_BUDGET 24576  // LDS bytes per interpolation tile
 #endif
 
+// Scratch of pmfem_grid_convolve_noalloc: the half-spectrum of one grid
+// convolution, at most kNoallocSpecMax complex values (16 MiB). Every device
+// the library runs on holds its own copy until the process ends. Host code
+// never uses the array's name as an address: the per-device address comes
+// from hipGetSymbolAddress at context creation (scratch_ptr below). The host
+// reference makes clang emit the array as a global symbol of the device code
+// object, which the runtime looks up; an explicit `used` attribute would keep
+// it local, where the lookup cannot find it.
+constexpr int64_t kNoallocSpecMax = (int64_t)1 << 21;
+static __device__ __align__(256) float2 scratch[kNoallocSpecMax];
 
 struct pmfem_dev {
   int64_t n = 0;
@@ -93,6 +104,31 @@ int set_err(pmfem_ctx* c, int code, const std::string& m) {
 
 int hip_err(pmfem_ctx* c, hipError_t e, const char* where) {
   return set_err(c, PMFEM_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Device address of `scratch` on each device, looked up once per device.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float2* g_scratch_ptr[kMaxDevices] = {};
+
+int lookup_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return PMFEM_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return PMFEM_OK;
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess) return PMFEM_EHIP;
+  if (hipSetDevice(device) != hipSuccess) return PMFEM_EHIP;
+  float2* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  (void)hipSetDevice(prev);
+  if (e != hipSuccess || !ptr) return PMFEM_EHIP;
+  g_scratch_ptr[device] = ptr;
+  return PMFEM_OK;
+}
+
+float2* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return device >= 0 && device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
 }
 
 template <class T>
@@ -1060,6 +1096,12 @@ int pmfem_create(pmfem_ctx** out, int hip_device, void* hip_stream) {
   } else if (hip_device != -1) {
     return PMFEM_EINVAL;
   }
+  // once per device, with that device current: the address of the
+  // no-allocation scratch array (kept for the life of the process)
+  if (hip_device >= 0) {
+    const int rc = lookup_scratch(hip_device);
+    if (rc) return rc;
+  }
   pmfem_ctx* c = new (std::nothrow) pmfem_ctx();
   if (!c) return PMFEM_ENOMEM;
   c->device = hip_device;
@@ -1246,6 +1288,26 @@ int pmfem_grid_convolve(pmfem_ctx* c, const float* q_grid_dev, float* u_grid_dev
   const GridParams& g = d->g;
   hipStream_t s = stream_of(c);
   convolve(d, s, q_grid_dev, u_grid_dev, d->spec, 0, [](int, int) {});
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_err(c, e, "kernel launch");
+  return PMFEM_OK;
+}
+
+int pmfem_grid_convolve_noalloc(pmfem_ctx* c, const float* q_grid_dev, float* u_grid_dev) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!q_grid_dev || !u_grid_dev) return set_err(c, PMFEM_EINVAL, "null grid buffer");
+  pmfem_dev* d = c->dev;
+  const GridParams& g = d->g;
+  const int64_t nspec = (int64_t)g.N[2] * g.M[1] * (g.M[0] / 2 + 1);
+  if (nspec > kNoallocSpecMax)
+    return set_err(c, PMFEM_EINVAL,
+                   "grid too large for the no-allocation scratch: half-spectrum of " +
+                       std::to_string(nspec) + " complex values, at most " +
+                       std::to_string(kNoallocSpecMax));
+  float2* spec = scratch_ptr(c->device);
+  if (!spec) return set_err(c, PMFEM_ESTATE, "no-allocation scratch not set up on this device");
+  convolve(d, stream_of(c), q_grid_dev, u_grid_dev, spec, 0, [](int, int) {});
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_err(c, e, "kernel launch");
   return PMFEM_OK;

@@ -235,6 +235,38 @@ def test_library_exports_every_declared_symbol():
     assert names == set(lib.EXPORTED)
 
 
+def test_noalloc_scratch_is_a_global_device_symbol():
+    """The static scratch array of pmfem_grid_convolve_noalloc is found by the
+    runtime through the device code object's symbol table, which only lists
+    global symbols: the compiled array must be GLOBAL there (a local symbol
+    aborts the runtime's lookup at context creation)."""
+    import os
+    import subprocess
+    import tempfile
+    bindir = "/opt/rocm/llvm/bin"
+    tools = [os.path.join(bindir, t) for t in ("llvm-objcopy", "clang-offload-bundler",
+                                                "llvm-readelf")]
+    if not all(os.path.exists(t) for t in tools):
+        pytest.skip("ROCm LLVM tools not installed")
+    obj = os.path.join(os.path.dirname(lib.LIB_PATH), "_build", "capi.hip.o")
+    if not os.path.exists(obj):
+        pytest.skip("library objects not built")
+    with tempfile.TemporaryDirectory() as td:
+        fat, dev = os.path.join(td, "fat.bin"), os.path.join(td, "dev.co")
+        subprocess.run([tools[0], f"--dump-section=.hip_fatbin={fat}", obj, os.path.join(td, "x.o")],
+                       check=True)
+        subprocess.run([tools[1], "--unbundle", "--type=o", f"--input={fat}",
+                        "--targets=hipv4-amdgcn-amd-amdhsa--gfx950", f"--output={dev}"],
+                       check=True)
+        syms = subprocess.run([tools[2], "-s", dev], check=True, capture_output=True,
+                              text=True).stdout
+    rows = [ln.split() for ln in syms.splitlines() if ln.strip().endswith("scratch")]
+    assert rows, "scratch array missing from the device code object"
+    for r in rows:
+        assert r[4] == "GLOBAL", r
+        assert int(r[2]) == 16 << 20, r
+
+
 def test_kernel_variant_arguments_are_checked():
     c = lib.Context(device=-1)
     c.set_variant("anterp", 1)
