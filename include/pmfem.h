@@ -49,7 +49,8 @@ typedef enum {
   PMFEM_EGRID = -4,   /* AIM grid unusable (too short, not a power of two)  */
   PMFEM_ENOMEM = -5,  /* host or device allocation failed                   */
   PMFEM_EHIP = -6,    /* HIP runtime error                                  */
-  PMFEM_ESTATE = -7   /* call out of order (e.g. heff before build)         */
+  PMFEM_ESTATE = -7,  /* call out of order (e.g. heff before build)         */
+  PMFEM_ECONV = -8    /* an iteration did not reach its tolerance           */
 } pmfem_status;
 
 /* Field terms for pmfem_heff. */
@@ -195,6 +196,34 @@ int pmfem_grid_convolve_noalloc(pmfem_ctx* ctx, const float* q_grid_dev, float* 
  */
 int pmfem_llg_step(pmfem_ctx* ctx, double* m_dev, double dt, double alpha, int32_t n_steps,
                    const double* h_applied);
+
+/*
+ * LLG time stepping by the implicit midpoint rule (Sec. 2.2 advances the
+ * semi-discrete Eq. llg implicitly, with a Newton iteration whose linear
+ * systems a preconditioned Krylov method solves): each of n_steps steps of
+ * size dt (s) solves x = m + dt f((m + x)/2), f the right side of Eq. llg
+ * (unit-vector Landau-Lifshitz form, damping alpha, gamma0 = 2.21276e5
+ * m/(A s)), for the FP64 master magnetisation m_dev[N'][3] (device), with the
+ * field terms `terms` (PMFEM_TERM_EX | PMFEM_TERM_MS) plus h_applied (host,
+ * 3 doubles, A/m, or NULL). Newton's linear systems are solved by GMRES of
+ * at most krylov_dim (<= 60; <= 0 selects 30) vectors, right-preconditioned
+ * by the inverse of each node's 3x3 diagonal block of the Jacobian (the field
+ * operator replaced by its exchange diagonal); each Krylov vector costs one
+ * FP32 field evaluation. A step ends when the root mean square of the
+ * residual x - m - dt f((m + x)/2) per component is <= newton_tol (<= 0
+ * selects 1e-8; the FP32 field bounds what is reachable, about
+ * 1e-7 dt gamma0 |H|). The rule keeps |m| = 1 up to that tolerance without
+ * renormalisation. iterations (host, 2 int32, or NULL) receives the Newton and
+ * the Krylov iterations of the call. PMFEM_ECONV if a step's Newton iteration
+ * does not reach the tolerance in 30 iterations, or stops decreasing for 3
+ * (m_dev then holds the last completed step; the message lists the
+ * residuals). The first call allocates the solver's device workspace
+ * (kept until pmfem_destroy; (krylov_dim + 1) vectors of 24 N' bytes and a
+ * few more). Synchronises.
+ */
+int pmfem_llg_implicit(pmfem_ctx* ctx, double* m_dev, double dt, double alpha, int32_t n_steps,
+                       uint32_t terms, const double* h_applied, double newton_tol,
+                       int32_t krylov_dim, int32_t* iterations);
 
 /*
  * Energies in J for the FP64 magnetisation m_dev[N'][3] (device):

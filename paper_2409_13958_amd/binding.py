@@ -29,6 +29,7 @@ class Status(enum.IntEnum):
     ENOMEM = -5
     EHIP = -6
     ESTATE = -7
+    ECONV = -8
 
 
 class PmfemError(RuntimeError):
@@ -60,6 +61,7 @@ _SIGS = {
     "pmfem_grid_convolve": (ctypes.c_int, [_P, _P, _P]),
     "pmfem_grid_convolve_noalloc": (ctypes.c_int, [_P, _P, _P]),
     "pmfem_llg_step": (ctypes.c_int, [_P, _P, _D, _D, _I32, _P]),
+    "pmfem_llg_implicit": (ctypes.c_int, [_P, _P, _D, _D, _I32, _U32, _P, _D, _I32, _P]),
     "pmfem_energy": (ctypes.c_int, [_P, _P, _DP, _DP]),
     "pmfem_profile_begin": (ctypes.c_int, [_P, _I32]),
     "pmfem_profile_end": (ctypes.c_int, [_P, ctypes.POINTER(_I32), _P, _P, _P]),
@@ -269,6 +271,18 @@ class Context:
         self._check(self.lib.pmfem_llg_step(self.h, _dev_ptr(m64, torch.float64, (self.n, 3), "m"),
                                             float(dt), float(alpha), int(n_steps), _ptr(ha)),
                     "llg_step")
+
+    def llg_implicit(self, m64, dt, alpha, n_steps=1, terms=TERM_EX | TERM_MS, h_applied=None,
+                     tol=0.0, krylov_dim=0):
+        """Implicit midpoint steps; returns (Newton iterations, Krylov iterations)."""
+        import torch
+        ha = None if h_applied is None else np.ascontiguousarray(h_applied, dtype=np.float64)
+        its = np.zeros(2, dtype=np.int32)
+        self._check(self.lib.pmfem_llg_implicit(
+            self.h, _dev_ptr(m64, torch.float64, (self.n, 3), "m"), float(dt), float(alpha),
+            int(n_steps), int(terms), _ptr(ha), float(tol), int(krylov_dim), _ptr(its)),
+            "llg_implicit")
+        return int(its[0]), int(its[1])
 
     def energy(self, m64):
         import torch

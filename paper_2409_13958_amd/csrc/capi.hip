@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -88,6 +89,16 @@ struct pmfem_dev {
   float *m32 = nullptr, *h32 = nullptr;
   double* part = nullptr;
   int nparts = 0;
+  // implicit midpoint LLG workspace, allocated by the first pmfem_llg_implicit
+  // call (again if a later call asks for a larger Krylov space)
+  struct Implicit {
+    int kdim = 0;
+    double *x = nullptr, *mb = nullptr, *G = nullptr, *Minv = nullptr, *adiag = nullptr;
+    double *V = nullptr, *w = nullptr, *z = nullptr, *part = nullptr, *red = nullptr;
+    double* coef = nullptr;
+    float *mb32 = nullptr, *H = nullptr, *z32 = nullptr, *Az = nullptr;
+    double* host = nullptr;  // pinned: coefficients out, reductions back
+  } imp;
   std::vector<void*> allocs;
   // profiling
   int prof_max = 0, prof_calls = 0;
@@ -155,6 +166,8 @@ int upload(pmfem_ctx* c, T** p, const void* src, size_t count) {
 void free_dev(pmfem_ctx* c) {
   if (!c->dev) return;
   if (c->dev->side) (void)hipStreamSynchronize(c->dev->side);
+  if (c->stream || c->dev->side) (void)hipStreamSynchronize((hipStream_t)c->stream);
+  if (c->dev->imp.host) (void)hipHostFree(c->dev->imp.host);
   for (void* p : c->dev->allocs) (void)hipFree(p);
   for (hipEvent_t e : c->dev->ev) (void)hipEventDestroy(e);
   if (c->dev->fork) (void)hipEventDestroy(c->dev->fork);
@@ -686,7 +699,6 @@ int upload_all(pmfem_ctx* c) {
       if ((rc = dalloc(c, &d->sc_part, nt * d->sp.fsize))) return rc;
     }
   }
-  if ((rc = select_variants(c))) return rc;
   if ((rc = upload(c, &d->brx, bx.data(), bx.size()))) return rc;
   if ((rc = upload(c, &d->bry, by.data(), by.size()))) return rc;
   if ((rc = upload(c, &d->brz, bz.data(), bz.size()))) return rc;
@@ -823,7 +835,8 @@ int upload_all(pmfem_ctx* c) {
   if ((rc = dalloc(c, &d->h32, 3 * n))) return rc;
   d->nparts = 1024;
   if ((rc = dalloc(c, &d->part, 2 * d->nparts))) return rc;
-  return PMFEM_OK;
+  // kernel forms, now that every plan and the mean row lengths are known
+  return select_variants(c);
 }
 
 hipStream_t stream_of(pmfem_ctx* c) { return (hipStream_t)c->stream; }
@@ -1079,6 +1092,219 @@ int ready(pmfem_ctx* c) {
   if (!c->dev) return set_err(c, PMFEM_ESTATE, "host-only context has no device operators");
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_err(c, e, "hipSetDevice");
+  return PMFEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Implicit midpoint LLG (Sec. 2.2): Newton on G(x) = x - m - dt f((m + x)/2)
+// with right-preconditioned GMRES on dG/dx d = G (matrix-free, one field
+// evaluation per Krylov vector) and the per-node 3x3 block inverse of dG/dx
+// with the field operator replaced by its exchange diagonal as the
+// preconditioner. Dot products are reduced on the device in a fixed order.
+
+constexpr int kMaxKrylov = 60;
+constexpr int kDotParts = 1024;
+
+int implicit_setup(pmfem_ctx* c, int kdim) {
+  pmfem_dev* d = c->dev;
+  pmfem_dev::Implicit& W = d->imp;
+  if (W.kdim >= kdim) return PMFEM_OK;
+  const int64_t n = d->n, n3 = 3 * n;
+  int rc;
+  if ((rc = dalloc(c, &W.x, n3)) || (rc = dalloc(c, &W.mb, n3)) || (rc = dalloc(c, &W.G, n3)) ||
+      (rc = dalloc(c, &W.Minv, 9 * n)) || (rc = dalloc(c, &W.V, (int64_t)(kdim + 1) * n3)) ||
+      (rc = dalloc(c, &W.w, n3)) || (rc = dalloc(c, &W.z, n3)) ||
+      (rc = dalloc(c, &W.part, (int64_t)(kMaxKrylov + 1) * kDotParts)) ||
+      (rc = dalloc(c, &W.red, kMaxKrylov + 1)) || (rc = dalloc(c, &W.coef, kMaxKrylov + 1)) ||
+      (rc = dalloc(c, &W.mb32, n3)) || (rc = dalloc(c, &W.H, n3)) || (rc = dalloc(c, &W.z32, n3)) ||
+      (rc = dalloc(c, &W.Az, n3)))
+    return rc;
+  if (!W.adiag) {
+    // the exchange operator's diagonal entry of every row (its own column)
+    const HostOps& o = c->ops;
+    std::vector<double> a((size_t)n, 0.0);
+    for (int64_t r = 0; r < n; ++r)
+      for (int32_t e = o.loc_rowptr[r]; e < o.loc_rowptr[r + 1]; ++e)
+        if (o.loc_col[e] == r) a[(size_t)r] = (double)o.loc_val[8 * (size_t)e];
+    if ((rc = upload(c, &W.adiag, a.data(), (size_t)n))) return rc;
+  }
+  if (!W.host) {
+    const hipError_t e = hipHostMalloc((void**)&W.host, 2 * (kMaxKrylov + 1) * sizeof(double));
+    if (e != hipSuccess) return set_err(c, PMFEM_ENOMEM, "hipHostMalloc");
+  }
+  W.kdim = kdim;
+  return PMFEM_OK;
+}
+
+// out[j] = V_j . w for j < nv (V with leading dimension ldv); synchronises
+int dots(pmfem_ctx* c, hipStream_t s, const double* V, int64_t ldv, int nv, const double* w,
+         double* out) {
+  pmfem_dev* d = c->dev;
+  pmfem_dev::Implicit& W = d->imp;
+  const int64_t n3 = 3 * d->n;
+  hipLaunchKernelGGL(k_mdot, dim3(kDotParts), dim3(256), 0, s, n3, V, ldv, nv, w, W.part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(nv), dim3(256), 0, s, (const double*)W.part, kDotParts,
+                     W.red);
+  hipError_t e = hipMemcpyAsync(W.host, W.red, nv * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_err(c, e, "implicit dot products");
+  for (int j = 0; j < nv; ++j) out[j] = W.host[j];
+  return PMFEM_OK;
+}
+
+// out = aw w + sum_j coef[j] V_j
+int lincomb(pmfem_ctx* c, hipStream_t s, const double* V, int64_t ldv, int nv, const double* coef,
+            double aw, const double* w, double* out) {
+  pmfem_dev* d = c->dev;
+  pmfem_dev::Implicit& W = d->imp;
+  const int64_t n3 = 3 * d->n;
+  if (nv > 0) {
+    // the pinned buffer's second half carries the coefficients; the copy is
+    // ordered before the kernel on the stream and the stream is drained
+    // before the buffer is written again
+    double* hc = W.host + kMaxKrylov + 1;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_err(c, e, "implicit update");
+    for (int j = 0; j < nv; ++j) hc[j] = coef[j];
+    e = hipMemcpyAsync(W.coef, hc, nv * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_err(c, e, "implicit update");
+  }
+  hipLaunchKernelGGL(k_lincomb, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, n3, V, ldv,
+                     nv, (const double*)W.coef, aw, w, out);
+  return PMFEM_OK;
+}
+
+int run_implicit(pmfem_ctx* c, double* m, double dt, double alpha, int32_t n_steps,
+                 uint32_t terms, const double* happ, double tol, int kdim, int32_t* stats) {
+  pmfem_dev* d = c->dev;
+  pmfem_dev::Implicit& W = d->imp;
+  hipStream_t s = stream_of(c);
+  const int64_t n = d->n, n3 = 3 * n;
+  const unsigned b3 = (unsigned)((n3 + 255) / 256), b1 = (unsigned)((n + 255) / 256);
+  const double cc = -kGamma0 / (1.0 + alpha * alpha);
+  const double sj = -0.5 * dt * cc;  // dG/dx = I + sj D
+  const double eta = 1e-6;           // GMRES: relative residual of each Newton system
+  const int max_newton = 30;
+  const double rms = std::sqrt((double)n3);
+  int32_t newton_total = 0, krylov_total = 0;
+  std::vector<double> hcol(kMaxKrylov + 2), h2(kMaxKrylov + 2), y(kMaxKrylov + 1),
+      g(kMaxKrylov + 2), cs(kMaxKrylov + 1), sn(kMaxKrylov + 1);
+  std::vector<double> R((size_t)(kMaxKrylov + 1) * (kMaxKrylov + 1));
+  int rc;
+  for (int32_t step = 0; step < n_steps; ++step) {
+    hipError_t e = hipMemcpyAsync(W.x, m, n3 * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_err(c, e, "implicit step");
+    bool converged = false;
+    std::string hist;  // residual rms after each Newton iteration, for the error message
+    double best = HUGE_VAL;
+    int stall = 0;
+    for (int it = 0; it <= max_newton; ++it) {
+      hipLaunchKernelGGL(k_mid_point, dim3(b3), dim3(256), 0, s, n3, (const double*)m,
+                         (const double*)W.x, W.mb, W.mb32);
+      if ((rc = run_heff(c, W.mb32, W.H, terms, happ))) return rc;
+      hipLaunchKernelGGL(k_mid_residual, dim3(kDotParts), dim3(256), 0, s, n, (const double*)m,
+                         (const double*)W.x, (const double*)W.mb, (const float*)W.H,
+                         (const double*)W.adiag, dt, cc, alpha, W.G, W.Minv, W.part);
+      hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, (const double*)W.part, kDotParts,
+                         W.red);
+      e = hipMemcpyAsync(W.host, W.red, sizeof(double), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return hip_err(c, e, "implicit residual");
+      const double beta = std::sqrt(W.host[0]);
+      {
+        char buf[32];
+        std::snprintf(buf, sizeof buf, "%s%.3e", it ? " " : "", beta / rms);
+        hist += buf;
+      }
+      if (beta / rms <= tol) {
+        converged = true;
+        break;
+      }
+      // three iterations without a decrease: the residual has reached the
+      // rounding level of the FP32 field, above the tolerance
+      stall = beta < best ? 0 : stall + 1;
+      best = std::min(best, beta);
+      if (it == max_newton || stall >= 3) break;
+      ++newton_total;
+      // GMRES: V_0 = G / beta, Arnoldi with classical Gram-Schmidt done twice
+      const double inv = 1.0 / beta;
+      if ((rc = lincomb(c, s, nullptr, 0, 0, nullptr, inv, W.G, W.V))) return rc;
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      int used = 0;
+      for (int i = 0; i < kdim; ++i) {
+        double* Vi = W.V + (int64_t)i * n3;
+        hipLaunchKernelGGL(k_mid_precond, dim3(b1), dim3(256), 0, s, n, (const double*)W.Minv,
+                           (const double*)Vi, W.z, W.z32);
+        if ((rc = run_heff(c, W.z32, W.Az, terms, nullptr))) return rc;
+        hipLaunchKernelGGL(k_mid_jvp, dim3(b1), dim3(256), 0, s, n, (const double*)W.z,
+                           (const float*)W.Az, (const double*)W.mb, (const float*)W.H, sj, alpha,
+                           W.w);
+        ++krylov_total;
+        if ((rc = dots(c, s, W.V, n3, i + 1, W.w, hcol.data()))) return rc;
+        for (int j = 0; j <= i; ++j) hcol[j] = -hcol[j];
+        if ((rc = lincomb(c, s, W.V, n3, i + 1, hcol.data(), 1.0, W.w, W.w))) return rc;
+        if ((rc = dots(c, s, W.V, n3, i + 1, W.w, h2.data()))) return rc;
+        for (int j = 0; j <= i; ++j) h2[j] = -h2[j];
+        if ((rc = lincomb(c, s, W.V, n3, i + 1, h2.data(), 1.0, W.w, W.w))) return rc;
+        double nw2 = 0.0;
+        if ((rc = dots(c, s, W.w, n3, 1, W.w, &nw2))) return rc;
+        const double hn = std::sqrt(nw2);
+        // column i of the Hessenberg matrix, rotated by the previous Givens
+        // rotations, then a new rotation that zeroes its subdiagonal
+        for (int j = 0; j <= i; ++j) hcol[j] = -(hcol[j] + h2[j]);
+        for (int j = 0; j < i; ++j) {
+          const double a = cs[j] * hcol[j] + sn[j] * hcol[j + 1];
+          hcol[j + 1] = -sn[j] * hcol[j] + cs[j] * hcol[j + 1];
+          hcol[j] = a;
+        }
+        const double den = std::hypot(hcol[i], hn);
+        cs[i] = den > 0.0 ? hcol[i] / den : 1.0;
+        sn[i] = den > 0.0 ? hn / den : 0.0;
+        hcol[i] = den;
+        for (int j = 0; j <= i; ++j) R[(size_t)j * (kMaxKrylov + 1) + i] = hcol[j];
+        g[i + 1] = -sn[i] * g[i];
+        g[i] = cs[i] * g[i];
+        used = i + 1;
+        if (std::fabs(g[i + 1]) <= eta * beta || hn == 0.0 || i + 1 == kdim) break;
+        if ((rc = lincomb(c, s, nullptr, 0, 0, nullptr, 1.0 / hn, W.w, W.V + (int64_t)(i + 1) * n3)))
+          return rc;
+      }
+      // y from R y = g, then x -= Minv (V y)
+      for (int j = used - 1; j >= 0; --j) {
+        double v = g[j];
+        for (int k = j + 1; k < used; ++k) v -= R[(size_t)j * (kMaxKrylov + 1) + k] * y[k];
+        const double rjj = R[(size_t)j * (kMaxKrylov + 1) + j];
+        y[j] = rjj != 0.0 ? v / rjj : 0.0;
+      }
+      if ((rc = lincomb(c, s, W.V, n3, used, y.data(), 0.0, W.w, W.w))) return rc;
+      hipLaunchKernelGGL(k_mid_precond, dim3(b1), dim3(256), 0, s, n, (const double*)W.Minv,
+                         (const double*)W.w, W.z, (float*)nullptr);
+      {
+        // x -= z
+        const double minus_one = -1.0;
+        if ((rc = lincomb(c, s, W.z, n3, 1, &minus_one, 1.0, W.x, W.x))) return rc;
+      }
+    }
+    if (!converged) {
+      if (stats) {
+        stats[0] = newton_total;
+        stats[1] = krylov_total;
+      }
+      return set_err(c, PMFEM_ECONV,
+                     "implicit midpoint: Newton did not reach the tolerance at step " +
+                         std::to_string(step) + " (residual rms per iteration: " + hist + ")");
+    }
+    hipError_t e2 = hipMemcpyAsync(m, W.x, n3 * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (e2 != hipSuccess) return hip_err(c, e2, "implicit step");
+  }
+  if (stats) {
+    stats[0] = newton_total;
+    stats[1] = krylov_total;
+  }
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_err(c, e, "implicit step");
   return PMFEM_OK;
 }
 
@@ -1347,6 +1573,20 @@ int pmfem_llg_step(pmfem_ctx* c, double* m_dev, double dt, double alpha, int32_t
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_err(c, e, "kernel launch");
   return PMFEM_OK;
+}
+
+int pmfem_llg_implicit(pmfem_ctx* c, double* m_dev, double dt, double alpha, int32_t n_steps,
+                       uint32_t terms, const double* h_applied, double newton_tol,
+                       int32_t krylov_dim, int32_t* iterations) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!m_dev || n_steps < 0 || !(dt > 0.0) || !(alpha >= 0.0) || terms < 1 || terms > 3)
+    return set_err(c, PMFEM_EINVAL, "bad implicit llg arguments");
+  const int kdim = krylov_dim <= 0 ? 30 : krylov_dim;
+  if (kdim > kMaxKrylov) return set_err(c, PMFEM_EINVAL, "krylov_dim above 60");
+  const double tol = newton_tol > 0.0 ? newton_tol : 1e-8;
+  if ((rc = implicit_setup(c, kdim))) return rc;
+  return run_implicit(c, m_dev, dt, alpha, n_steps, terms, h_applied, tol, kdim, iterations);
 }
 
 int pmfem_energy(pmfem_ctx* c, const double* m_dev, double* e_ex, double* e_ms) {

@@ -117,5 +117,19 @@ __global__ void k_rk_rhs(int64_t n, const double* mst, const float* h, double pr
 __global__ void k_rk_final(int64_t n, double* m, const double* acc, double dt6);
 __global__ void k_energy(int64_t n, const double* m, const double* mu, const float* hex,
                          const float* q, const float* u, double* part);
+// implicit midpoint LLG (Newton-Krylov)
+__global__ void k_mid_point(int64_t n3, const double* m, const double* x, double* mb, float* mb32);
+__global__ void k_mid_residual(int64_t n, const double* m, const double* x, const double* mb,
+                               const float* H, const double* adiag, double dt, double c,
+                               double alpha, double* G, double* Minv, double* part);
+__global__ void k_mid_precond(int64_t n, const double* Minv, const double* v, double* z,
+                              float* z32);
+__global__ void k_mid_jvp(int64_t n, const double* z, const float* Az, const double* mb,
+                          const float* H, double s, double alpha, double* w);
+__global__ void k_mdot(int64_t n3, const double* V, int64_t ldv, int nv, const double* w,
+                       double* part);
+__global__ void k_sum_parts(const double* part, int nparts, double* out);
+__global__ void k_lincomb(int64_t n3, const double* V, int64_t ldv, int nv, const double* coef,
+                          double aw, const double* w, double* out);
 
 }  // namespace pmfem

@@ -1463,6 +1463,203 @@ __global__ void k_rk_final(int64_t n, double* __restrict__ m, const double* __re
 }
 
 // energy partial sums: block b writes {sum mu m.Hex, sum q u}
+// ---------------------------------------------------------------------------
+// LLG by the implicit midpoint rule (Sec. 2.2: implicit time stepping with a
+// Newton iteration and a preconditioned Krylov solver). One step solves
+//   G(x) = x - m - dt f(mb) = 0,   mb = (m + x) / 2,
+//   f(v) = c [v x H(v) + alpha v x (v x H(v))],  c = -gamma0 / (1 + alpha^2),
+// by Newton; the linear systems dG/dx d = G are solved by GMRES with the
+// Jacobian applied matrix-free (the field is linear in m, H(v) = A v + H_app):
+//   dG/dx w = w - (dt/2) c [w x H + mb x (A w)
+//                          + alpha (w x (mb x H) + mb x (w x H) + mb x (mb x (A w)))].
+// All vectors are FP64; A w is one FP32 field evaluation.
+
+__device__ __forceinline__ void cross3(double ax, double ay, double az, double bx, double by,
+                                       double bz, double& cx, double& cy, double& cz) {
+  cx = ay * bz - az * by;
+  cy = az * bx - ax * bz;
+  cz = ax * by - ay * bx;
+}
+
+// mb = (m + x) / 2 and its FP32 copy for the field evaluation
+__global__ void k_mid_point(int64_t n3, const double* __restrict__ m, const double* __restrict__ x,
+                            double* __restrict__ mb, float* __restrict__ mb32) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n3) return;
+  const double v = 0.5 * (m[i] + x[i]);
+  mb[i] = v;
+  mb32[i] = (float)v;
+}
+
+// Residual G at the midpoint field H and, per node, the inverse of the 3x3
+// diagonal block of dG/dx with A replaced by its exchange diagonal a_n
+// (the block-inverse preconditioner); part[b] = block b's share of |G|^2,
+// summed in a fixed order (grid-stride, then a tree in LDS).
+__global__ void __launch_bounds__(256) k_mid_residual(int64_t n, const double* __restrict__ m,
+                                                      const double* __restrict__ x,
+                                                      const double* __restrict__ mb,
+                                                      const float* __restrict__ H,
+                                                      const double* __restrict__ adiag, double dt,
+                                                      double c, double alpha,
+                                                      double* __restrict__ G,
+                                                      double* __restrict__ Minv,
+                                                      double* __restrict__ part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double bx = mb[3 * i], by = mb[3 * i + 1], bz = mb[3 * i + 2];
+    const double hx = H[3 * i], hy = H[3 * i + 1], hz = H[3 * i + 2];
+    double px, py, pz, qx, qy, qz;
+    cross3(bx, by, bz, hx, hy, hz, px, py, pz);   // mb x H
+    cross3(bx, by, bz, px, py, pz, qx, qy, qz);   // mb x (mb x H)
+    const double gx = x[3 * i] - m[3 * i] - dt * c * (px + alpha * qx);
+    const double gy = x[3 * i + 1] - m[3 * i + 1] - dt * c * (py + alpha * qy);
+    const double gz = x[3 * i + 2] - m[3 * i + 2] - dt * c * (pz + alpha * qz);
+    G[3 * i] = gx;
+    G[3 * i + 1] = gy;
+    G[3 * i + 2] = gz;
+    acc += gx * gx + gy * gy + gz * gz;
+    // columns of the block: D e_k = e_k x H + a mb x e_k
+    //   + alpha (e_k x (mb x H) + mb x (e_k x H) + a mb x (mb x e_k))
+    const double a = adiag[i];
+    double B[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double ex = k == 0, ey = k == 1, ez = k == 2;
+      double t1x, t1y, t1z, t2x, t2y, t2z, t3x, t3y, t3z, t4x, t4y, t4z, t5x, t5y, t5z, ux, uy, uz;
+      cross3(ex, ey, ez, hx, hy, hz, t1x, t1y, t1z);        // e x H
+      cross3(bx, by, bz, ex, ey, ez, t2x, t2y, t2z);        // mb x e
+      cross3(ex, ey, ez, px, py, pz, t3x, t3y, t3z);        // e x (mb x H)
+      cross3(bx, by, bz, t1x, t1y, t1z, t4x, t4y, t4z);     // mb x (e x H)
+      cross3(bx, by, bz, t2x, t2y, t2z, t5x, t5y, t5z);     // mb x (mb x e)
+      ux = t1x + a * t2x + alpha * (t3x + t4x + a * t5x);
+      uy = t1y + a * t2y + alpha * (t3y + t4y + a * t5y);
+      uz = t1z + a * t2z + alpha * (t3z + t4z + a * t5z);
+      const double s = -0.5 * dt * c;
+      B[0][k] = (k == 0) + s * ux;
+      B[1][k] = (k == 1) + s * uy;
+      B[2][k] = (k == 2) + s * uz;
+    }
+    // inverse by the adjugate
+    const double c00 = B[1][1] * B[2][2] - B[1][2] * B[2][1];
+    const double c01 = B[1][2] * B[2][0] - B[1][0] * B[2][2];
+    const double c02 = B[1][0] * B[2][1] - B[1][1] * B[2][0];
+    const double det = B[0][0] * c00 + B[0][1] * c01 + B[0][2] * c02;
+    const double r = 1.0 / det;
+    double* Mi = Minv + 9 * i;
+    Mi[0] = c00 * r;
+    Mi[1] = (B[0][2] * B[2][1] - B[0][1] * B[2][2]) * r;
+    Mi[2] = (B[0][1] * B[1][2] - B[0][2] * B[1][1]) * r;
+    Mi[3] = c01 * r;
+    Mi[4] = (B[0][0] * B[2][2] - B[0][2] * B[2][0]) * r;
+    Mi[5] = (B[0][2] * B[1][0] - B[0][0] * B[1][2]) * r;
+    Mi[6] = c02 * r;
+    Mi[7] = (B[0][1] * B[2][0] - B[0][0] * B[2][1]) * r;
+    Mi[8] = (B[0][0] * B[1][1] - B[0][1] * B[1][0]) * r;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// z = Minv v per node; z32 its FP32 copy (NULL: not written)
+__global__ void k_mid_precond(int64_t n, const double* __restrict__ Minv,
+                              const double* __restrict__ v, double* __restrict__ z,
+                              float* __restrict__ z32) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double* Mi = Minv + 9 * i;
+  const double vx = v[3 * i], vy = v[3 * i + 1], vz = v[3 * i + 2];
+  const double a = Mi[0] * vx + Mi[1] * vy + Mi[2] * vz;
+  const double b = Mi[3] * vx + Mi[4] * vy + Mi[5] * vz;
+  const double d = Mi[6] * vx + Mi[7] * vy + Mi[8] * vz;
+  z[3 * i] = a;
+  z[3 * i + 1] = b;
+  z[3 * i + 2] = d;
+  if (z32) {
+    z32[3 * i] = (float)a;
+    z32[3 * i + 1] = (float)b;
+    z32[3 * i + 2] = (float)d;
+  }
+}
+
+// w = dG/dx z, with Az = A z from one FP32 field evaluation
+__global__ void k_mid_jvp(int64_t n, const double* __restrict__ z, const float* __restrict__ Az,
+                          const double* __restrict__ mb, const float* __restrict__ H, double s,
+                          double alpha, double* __restrict__ w) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double bx = mb[3 * i], by = mb[3 * i + 1], bz = mb[3 * i + 2];
+  const double hx = H[3 * i], hy = H[3 * i + 1], hz = H[3 * i + 2];
+  const double zx = z[3 * i], zy = z[3 * i + 1], zz = z[3 * i + 2];
+  const double ax = Az[3 * i], ay = Az[3 * i + 1], az = Az[3 * i + 2];
+  double px, py, pz, t1x, t1y, t1z, t2x, t2y, t2z, t3x, t3y, t3z, t4x, t4y, t4z, t5x, t5y, t5z;
+  cross3(bx, by, bz, hx, hy, hz, px, py, pz);          // mb x H
+  cross3(zx, zy, zz, hx, hy, hz, t1x, t1y, t1z);       // z x H
+  cross3(bx, by, bz, ax, ay, az, t2x, t2y, t2z);       // mb x (A z)
+  cross3(zx, zy, zz, px, py, pz, t3x, t3y, t3z);       // z x (mb x H)
+  cross3(bx, by, bz, t1x, t1y, t1z, t4x, t4y, t4z);    // mb x (z x H)
+  cross3(bx, by, bz, t2x, t2y, t2z, t5x, t5y, t5z);    // mb x (mb x (A z))
+  w[3 * i] = zx + s * (t1x + t2x + alpha * (t3x + t4x + t5x));
+  w[3 * i + 1] = zy + s * (t1y + t2y + alpha * (t3y + t4y + t5y));
+  w[3 * i + 2] = zz + s * (t1z + t2z + alpha * (t3z + t4z + t5z));
+}
+
+// part[j * gridDim.x + b] = block b's share of V_j . w for j < nv (fixed
+// order: grid-stride per thread, then a tree in LDS)
+__global__ void __launch_bounds__(256) k_mdot(int64_t n3, const double* __restrict__ V,
+                                              int64_t ldv, int nv, const double* __restrict__ w,
+                                              double* __restrict__ part) {
+  __shared__ double red[256];
+  for (int j = 0; j < nv; ++j) {
+    const double* Vj = V + (int64_t)j * ldv;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n3;
+         i += (int64_t)gridDim.x * blockDim.x)
+      acc = fma(Vj[i], w[i], acc);
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)j * gridDim.x + blockIdx.x] = red[0];
+    __syncthreads();
+  }
+}
+
+// out[j] = sum over b < nparts of part[j * nparts + b], one block per j,
+// fixed order
+__global__ void __launch_bounds__(256) k_sum_parts(const double* __restrict__ part, int nparts,
+                                                   double* __restrict__ out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x) acc += part[(int64_t)blockIdx.x * nparts + b];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+// out = aw w + sum_j coef[j] V_j (j < nv); out may alias w
+__global__ void k_lincomb(int64_t n3, const double* __restrict__ V, int64_t ldv, int nv,
+                          const double* __restrict__ coef, double aw, const double* w,
+                          double* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n3) return;
+  double v = aw != 0.0 ? aw * w[i] : 0.0;
+  for (int j = 0; j < nv; ++j) v = fma(coef[j], V[(int64_t)j * ldv + i], v);
+  out[i] = v;
+}
+
 __global__ void __launch_bounds__(256) k_energy(int64_t n, const double* __restrict__ m,
                                                 const double* __restrict__ mu,
                                                 const float* __restrict__ hex,

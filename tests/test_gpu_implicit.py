@@ -1,0 +1,129 @@
+"""Implicit midpoint LLG (pmfem_llg_implicit) on the GPU.
+
+Sec. 2.2 advances the semi-discrete LLG equation implicitly, solving each
+step's nonlinear system by Newton with a preconditioned Krylov method. The
+library does that matrix-free (GMRES, one FP32 field evaluation per Krylov
+vector, block-inverse preconditioner); the oracle solves the same midpoint
+rule with the exact dense Jacobian. Checked: the closed forms of the
+macrospin (undamped: a Cayley rotation per step; damped: second-order
+convergence to the exact precession), the film trajectory against the
+oracle's, |m| = 1 without renormalisation, and the conservation of the
+exchange energy by the undamped flow (a quadratic invariant the midpoint rule
+keeps, up to the FP32 field and the Newton tolerance).
+"""
+import numpy as np
+import pytest
+
+from oracle import model
+from paper_2409_13958_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+B = pytest.importorskip("paper_2409_13958_amd.binding")
+
+MS = 8e5
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def macrospin_cell():
+    # no exchange: the closed forms are those of a lone moment in the applied
+    # field (a uniform m has no demagnetising field in a filled periodic
+    # cell), and the FP32 exchange sum over a uniform m would only add its
+    # cancellation noise (a few A/m at 2 nm cells)
+    return mg.kuhn_box((3, 3, 3), 2e-9, periodic=0b111, Ms=MS, Aex=0.0, grid=(16, 16, 16))
+
+
+def test_undamped_macrospin_is_a_cayley_rotation():
+    ctx = B.Context.from_problem(macrospin_cell(), device=0)
+    th0, ph0, Hap, dt, n = 0.9, 0.3, 2e5, 2e-12, 12
+    m0 = np.array([np.sin(th0) * np.cos(ph0), np.sin(th0) * np.sin(ph0), np.cos(th0)])
+    m = torch.tensor(np.tile(m0, (ctx.n, 1)), dtype=torch.float64, device="cuda")
+    newton, krylov = ctx.llg_implicit(m, dt, 0.0, n, h_applied=[0.0, 0.0, Hap], tol=1e-9)
+    ph = ph0 + n * 2 * np.arctan(model.GAMMA0 * Hap * dt / 2)
+    ex = np.array([np.sin(th0) * np.cos(ph), np.sin(th0) * np.sin(ph), np.cos(th0)])
+    got = m.cpu().numpy()
+    err = np.abs(got - ex[None, :]).max()
+    print(f"[gpu implicit] Cayley macrospin: max err {err:.2e}, Newton {newton}, Krylov {krylov}")
+    # the plain rate gamma0 H dt per step would be 6.8e-4 rad off after 12 steps
+    assert err < 5e-6
+    assert np.allclose(np.linalg.norm(got, axis=1), 1.0, atol=1e-7)
+    assert 0 < newton <= 4 * n
+
+
+def test_damped_macrospin_second_order():
+    ctx = B.Context.from_problem(macrospin_cell(), device=0)
+    th0, ph0, Hap, alpha, T = 0.9, 0.3, 2e5, 0.3, 4e-12
+    m0 = np.array([np.sin(th0) * np.cos(ph0), np.sin(th0) * np.sin(ph0), np.cos(th0)])
+    g = model.GAMMA0 * Hap / (1 + alpha ** 2)
+    th = 2 * np.arctan(np.tan(th0 / 2) * np.exp(-alpha * g * T))
+    ph = ph0 + g * T
+    ex = np.array([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)])
+    errs = []
+    for n in (1, 2, 4):
+        m = torch.tensor(np.tile(m0, (ctx.n, 1)), dtype=torch.float64, device="cuda")
+        ctx.llg_implicit(m, T / n, alpha, n, h_applied=[0.0, 0.0, Hap], tol=1e-9)
+        errs.append(float(np.abs(m.cpu().numpy() - ex[None, :]).max()))
+    print(f"[gpu implicit] damped macrospin errors (1, 2, 4 steps): {errs}")
+    assert 3.6 < errs[0] / errs[1] < 4.4 and 3.6 < errs[1] / errs[2] < 4.4, errs
+
+
+def test_film_trajectory_against_oracle():
+    """10 midpoint steps of 20 fs, alpha = 0.5, exchange + magnetostatic field."""
+    prob = mg.film_c1()
+    ctx = B.Context.from_problem(prob, device=0)
+    n, uon, nou, _ = ctx.query()
+    orc = model.Oracle(prob)
+    perm = orc.uk[nou]
+    m0 = orc.unknown_values(prob.m)
+    ref, its = orc.implicit_midpoint(m0, 2e-14, 0.5, 10)
+    m = torch.tensor(prob.m[nou], dtype=torch.float64, device="cuda")
+    newton, krylov = ctx.llg_implicit(m, 2e-14, 0.5, 10, tol=1e-8)
+    got = m.cpu().numpy()
+    err = rel(got - m0[perm], ref[perm] - m0[perm])
+    print(f"[gpu implicit] film 10 steps: rel L2 of the change vs oracle {err:.2e}; "
+          f"Newton {newton} (oracle {sum(its)}), Krylov {krylov}")
+    assert err < 1e-5
+    # each step keeps |m| up to its residual (rms <= 1e-8 per component)
+    assert np.abs(np.linalg.norm(got, axis=1) - 1.0).max() < 1e-7
+
+
+def test_undamped_exchange_energy_is_conserved():
+    prob = mg.kuhn_box((4, 4, 1), 2e-9, periodic=0b011, jitter=0.2, grid=(16, 16, 4))
+    ctx = B.Context.from_problem(prob, device=0)
+    n, uon, nou, _ = ctx.query()
+    m0 = torch.tensor(prob.m[nou], dtype=torch.float64, device="cuda")
+    e0, _ = ctx.energy(m0)
+    m = m0.clone()
+    # the FP32 exchange sum leaves a residual floor near 6e-10 at this step
+    ctx.llg_implicit(m, 2e-14, 0.0, 10, terms=B.TERM_EX, tol=2e-9)
+    e1, _ = ctx.energy(m)
+    mr = m0.clone()
+    # RK4 with both terms would change the energy for another reason; its
+    # exchange-only counterpart is the oracle's (FP64)
+    orc = model.Oracle(prob, with_aim=False)
+    mo = orc.unknown_values(prob.m)
+    er0 = orc.ops.exchange_energy(mo)
+    er = orc.ops.exchange_energy(orc.rk4(mo, 2e-14, 0.0, 10, method="direct", terms=("ex",)))
+    drift = abs(e1 - e0) / abs(e0)
+    drift_rk4 = abs(er - er0) / abs(er0)
+    print(f"[gpu implicit] exchange energy drift {drift:.2e} (RK4 at the same step {drift_rk4:.2e})")
+    assert drift < 1e-6 and drift < drift_rk4
+    assert np.abs(np.linalg.norm(m.cpu().numpy(), axis=1) - 1.0).max() < 1e-7
+    del mr
+
+
+def test_bad_arguments_are_refused():
+    ctx = B.Context.from_problem(macrospin_cell(), device=0)
+    m = torch.zeros((ctx.n, 3), dtype=torch.float64, device="cuda")
+    m[:, 2] = 1.0
+    for kw in (dict(dt=-1.0), dict(krylov_dim=61), dict(terms=0)):
+        args = dict(dt=1e-13, alpha=0.1, n_steps=1, terms=3, krylov_dim=0)
+        args.update(kw)
+        with pytest.raises(B.PmfemError) as e:
+            ctx.llg_implicit(m, args["dt"], args["alpha"], args["n_steps"], terms=args["terms"],
+                             krylov_dim=args["krylov_dim"])
+        assert e.value.code == B.Status.EINVAL
