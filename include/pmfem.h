@@ -268,6 +268,18 @@ int pmfem_export(pmfem_ctx* ctx, const char* name, void* out, int64_t* count,
 int pmfem_pgf_eval(uint32_t axis_mask, const double L[3], double eta, int64_t n,
                    const double* r, double* out);
 
+/*
+ * Autotuner: picks the kernel form of every stage (pmfem_set_variant's
+ * stages "anterp", "interp", "fft", "spmv") by coordinate descent, two
+ * passes, each candidate timed over `trials` whole evaluations with HIP
+ * events (the stages overlap on two streams, so the whole evaluation is the
+ * objective). The choice stays set on the context; chosen (host, 4 int32, or
+ * NULL) receives it in stage order, best_ms (or NULL) the mean milliseconds
+ * per evaluation of that choice. Synchronises; uses the context's own work
+ * buffers as input, so it leaves no caller data changed.
+ */
+int pmfem_autotune(pmfem_ctx* ctx, int32_t trials, int32_t* chosen, double* best_ms);
+
 const char* pmfem_last_error(const pmfem_ctx* ctx);
 
 void pmfem_destroy(pmfem_ctx* ctx);

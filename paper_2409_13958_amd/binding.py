@@ -68,6 +68,7 @@ _SIGS = {
     "pmfem_export": (ctypes.c_int, [_P, ctypes.c_char_p, _P, ctypes.POINTER(_I64),
                                     ctypes.POINTER(_I32)]),
     "pmfem_pgf_eval": (ctypes.c_int, [_U32, _P, _D, _I64, _P, _P]),
+    "pmfem_autotune": (ctypes.c_int, [_P, _I32, _P, _DP]),
     "pmfem_last_error": (ctypes.c_char_p, [_P]),
     "pmfem_destroy": (None, [_P]),
 }
@@ -284,6 +285,14 @@ class Context:
             "llg_implicit")
         return int(its[0]), int(its[1])
 
+    def autotune(self, trials=20):
+        """Pick the fastest kernel forms; returns ({stage: form}, ms per evaluation)."""
+        ch = np.zeros(4, dtype=np.int32)
+        ms = _D()
+        self._check(self.lib.pmfem_autotune(self.h, int(trials), _ptr(ch), ctypes.byref(ms)),
+                    "autotune")
+        return dict(zip(("anterp", "interp", "fft", "spmv"), ch.tolist())), ms.value
+
     def energy(self, m64):
         import torch
         a, b = _D(), _D()
@@ -302,3 +311,4 @@ class Context:
         self._check(self.lib.pmfem_profile_end(self.h, ctypes.byref(nk), _ptr(ms), _ptr(cnt),
                                                ctypes.cast(names, _P)), "profile_end")
         return {names[k].value.decode(): (float(ms[k]), int(cnt[k])) for k in range(nk.value)}
+

@@ -1086,6 +1086,37 @@ int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const doubl
   return PMFEM_OK;
 }
 
+// One classic RK4 step of Eq. llg on the FP64 master m (four FP32 field
+// evaluations, FP64 combination, norm restored after the step), enqueued on
+// the context's stream.
+int enqueue_rk4(pmfem_ctx* c, double* m_dev, double dt, double alpha, const double* happ) {
+  pmfem_dev* d = c->dev;
+  hipStream_t s = stream_of(c);
+  const int64_t n = d->n;
+  const unsigned b3 = (unsigned)((3 * n + 255) / 256), b1 = (unsigned)((n + 255) / 256);
+  const double pref = -kGamma0 / (1.0 + alpha * alpha);
+  const uint32_t terms = PMFEM_TERM_EX | PMFEM_TERM_MS;
+  int rc;
+  // stage 1 at m
+  hipLaunchKernelGGL(k_rk_stage, dim3(b3), dim3(256), 0, s, n, m_dev, (const double*)nullptr, 0.0,
+                     (double*)nullptr, d->m32);
+  if ((rc = run_heff(c, d->m32, d->h32, terms, happ))) return rc;
+  hipLaunchKernelGGL(k_rk_rhs, dim3(b1), dim3(256), 0, s, n, (const double*)m_dev, d->h32, pref,
+                     alpha, d->kk, d->acc, 1.0, 1);
+  const double cs[3] = {0.5 * dt, 0.5 * dt, dt};
+  const double ws[3] = {2.0, 2.0, 1.0};
+  for (int k = 0; k < 3; ++k) {
+    hipLaunchKernelGGL(k_rk_stage, dim3(b3), dim3(256), 0, s, n, (const double*)m_dev,
+                       (const double*)d->kk, cs[k], d->mst, d->m32);
+    if ((rc = run_heff(c, d->m32, d->h32, terms, happ))) return rc;
+    hipLaunchKernelGGL(k_rk_rhs, dim3(b1), dim3(256), 0, s, n, (const double*)d->mst, d->h32, pref,
+                       alpha, d->kk, d->acc, ws[k], 0);
+  }
+  hipLaunchKernelGGL(k_rk_final, dim3(b1), dim3(256), 0, s, n, m_dev, (const double*)d->acc,
+                     dt / 6.0);
+  return PMFEM_OK;
+}
+
 int ready(pmfem_ctx* c) {
   if (!c) return PMFEM_EINVAL;
   if (!c->built) return set_err(c, PMFEM_ESTATE, "pmfem_build has not succeeded");
@@ -1306,6 +1337,76 @@ int run_implicit(pmfem_ctx* c, double* m, double dt, double alpha, int32_t n_ste
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_err(c, e, "implicit step");
   return PMFEM_OK;
+}
+
+// Autotuner: coordinate descent over the kernel forms of each stage, the
+// objective being the mean duration of whole evaluations (the stages overlap
+// on two streams, so their sum is what counts), measured with HIP events.
+int autotune(pmfem_ctx* c, int trials, double* best_ms) {
+  pmfem_dev* d = c->dev;
+  hipStream_t s = stream_of(c);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) return hip_err(c, e, "autotune events");
+  // inputs of the timed evaluations: a uniform magnetisation (the kernels do
+  // the same work for any values)
+  e = hipMemsetAsync(d->m32, 0, 3 * d->n * sizeof(float), s);
+  if (e != hipSuccess) return hip_err(c, e, "autotune");
+  auto time_eval = [&](double& ms) -> int {
+    int rc;
+    for (int w = 0; w < 2; ++w)
+      if ((rc = run_heff(c, d->m32, d->h32, PMFEM_TERM_EX | PMFEM_TERM_MS, nullptr))) return rc;
+    (void)hipEventRecord(e0, s);
+    for (int t = 0; t < trials; ++t)
+      if ((rc = run_heff(c, d->m32, d->h32, PMFEM_TERM_EX | PMFEM_TERM_MS, nullptr))) return rc;
+    (void)hipEventRecord(e1, s);
+    hipError_t er = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (er == hipSuccess) er = hipEventElapsedTime(&t, e0, e1);
+    if (er != hipSuccess) return hip_err(c, er, "autotune timing");
+    ms = (double)t / trials;
+    return PMFEM_OK;
+  };
+  struct Stage {
+    int k;
+    std::vector<int> forms;
+  };
+  const Stage stages[4] = {{0, {3, 2, 1}}, {1, {2, 1}}, {2, {2, 1}}, {3, {4, 8, 16}}};
+  // start from the automatic choice, made explicit
+  for (int k = 0; k < 4; ++k) c->variant[k] = 0;
+  (void)select_variants(c);
+  c->variant[0] = d->ant_scatter ? 3 : d->ant_line ? 2 : 1;
+  c->variant[1] = d->ic_seg ? 2 : 1;
+  c->variant[2] = d->fft_plane ? 2 : 1;
+  c->variant[3] = 0;
+  int rc = select_variants(c);
+  double best = 0.0;
+  if (!rc) rc = time_eval(best);
+  for (int pass = 0; pass < 2 && !rc; ++pass)
+    for (const Stage& st : stages) {
+      const int keep = c->variant[st.k];
+      int pick = keep;
+      for (int v : st.forms) {
+        if (v == keep) continue;
+        c->variant[st.k] = v;
+        if (select_variants(c) != PMFEM_OK) continue;  // the form does not fit
+        double ms = 0.0;
+        if ((rc = time_eval(ms))) break;
+        if (ms < best) {
+          best = ms;
+          pick = v;
+        }
+      }
+      c->variant[st.k] = pick;
+      (void)select_variants(c);
+      if (rc) break;
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (best_ms) *best_ms = best;
+  if (!rc) c->err.clear();  // forms that did not fit left their message
+  return rc;
 }
 
 }  // namespace
@@ -1545,31 +1646,8 @@ int pmfem_llg_step(pmfem_ctx* c, double* m_dev, double dt, double alpha, int32_t
   if (rc) return rc;
   if (!m_dev || n_steps < 0 || !(dt > 0.0) || !(alpha >= 0.0))
     return set_err(c, PMFEM_EINVAL, "bad llg arguments");
-  pmfem_dev* d = c->dev;
-  hipStream_t s = stream_of(c);
-  const int64_t n = d->n;
-  const unsigned b3 = (unsigned)((3 * n + 255) / 256), b1 = (unsigned)((n + 255) / 256);
-  const double pref = -kGamma0 / (1.0 + alpha * alpha);
-  const uint32_t terms = PMFEM_TERM_EX | PMFEM_TERM_MS;
-  for (int32_t st = 0; st < n_steps; ++st) {
-    // stage 1 at m
-    hipLaunchKernelGGL(k_rk_stage, dim3(b3), dim3(256), 0, s, n, m_dev, (const double*)nullptr,
-                       0.0, (double*)nullptr, d->m32);
-    if ((rc = run_heff(c, d->m32, d->h32, terms, h_applied))) return rc;
-    hipLaunchKernelGGL(k_rk_rhs, dim3(b1), dim3(256), 0, s, n, (const double*)m_dev, d->h32, pref,
-                       alpha, d->kk, d->acc, 1.0, 1);
-    const double cs[3] = {0.5 * dt, 0.5 * dt, dt};
-    const double ws[3] = {2.0, 2.0, 1.0};
-    for (int k = 0; k < 3; ++k) {
-      hipLaunchKernelGGL(k_rk_stage, dim3(b3), dim3(256), 0, s, n, (const double*)m_dev,
-                         (const double*)d->kk, cs[k], d->mst, d->m32);
-      if ((rc = run_heff(c, d->m32, d->h32, terms, h_applied))) return rc;
-      hipLaunchKernelGGL(k_rk_rhs, dim3(b1), dim3(256), 0, s, n, (const double*)d->mst, d->h32,
-                         pref, alpha, d->kk, d->acc, ws[k], 0);
-    }
-    hipLaunchKernelGGL(k_rk_final, dim3(b1), dim3(256), 0, s, n, m_dev, (const double*)d->acc,
-                       dt / 6.0);
-  }
+  for (int32_t st = 0; st < n_steps; ++st)
+    if ((rc = enqueue_rk4(c, m_dev, dt, alpha, h_applied))) return rc;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_err(c, e, "kernel launch");
   return PMFEM_OK;
@@ -1736,6 +1814,17 @@ int pmfem_export(pmfem_ctx* c, const char* name, void* out, int64_t* count, int3
   *count = cnt;
   if (elem_bytes) *elem_bytes = eb;
   if (out && cnt) std::memcpy(out, src, (size_t)cnt * eb);
+  return PMFEM_OK;
+}
+
+int pmfem_autotune(pmfem_ctx* c, int32_t trials, int32_t* chosen, double* best_ms) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (trials < 1 || trials > 10000) return set_err(c, PMFEM_EINVAL, "trials must be in [1, 10000]");
+  if (c->dev->prof_max > 0) return set_err(c, PMFEM_ESTATE, "autotune while profiling");
+  if ((rc = autotune(c, trials, best_ms))) return rc;
+  if (chosen)
+    for (int k = 0; k < 4; ++k) chosen[k] = c->variant[k];
   return PMFEM_OK;
 }
 

@@ -98,7 +98,8 @@ def _random_unit(rng, n):
 
 def kuhn_box(n_cells, h, periodic=0, jitter=0.0, seed=SEED0, Ms=8e5, Aex=1.3e-11,
              grid=None, m="random", name="kuhn_box", region_of=None):
-    """A fully filled box of ``n_cells`` cubes of side ``h`` (metres), 6 tets each.
+    """A fully filled box of ``n_cells`` cells of side ``h`` (metres; a scalar,
+    or three values for boxes), 6 tets each.
 
     On periodic axes the last node layer is the image of the first and the
     jitter is drawn per wrapped lattice index, so image nodes sit exactly one
@@ -109,6 +110,7 @@ def kuhn_box(n_cells, h, periodic=0, jitter=0.0, seed=SEED0, Ms=8e5, Aex=1.3e-11
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     n = np.asarray(n_cells, dtype=np.int64)
+    h = np.asarray(h, dtype=np.float64)
     cells = np.stack(np.meshgrid(np.arange(n[0]), np.arange(n[1]), np.arange(n[2]),
                                  indexing="ij"), axis=-1).reshape(-1, 3)
     coords, tets = _unique_nodes(_kuhn_from_cells(cells))
@@ -326,6 +328,60 @@ def composite_c3(seed=SEED0 + 2, period=100.0 * NM, n_cells=144, n_spheres=27,
                    region=np.zeros(tets.shape[0], np.int32),
                    Ms=np.array([8e5]), Aex=np.array([1.3e-11]), periodic=0b111,
                    L=np.array([period] * 3), grid=tuple(grid), m=mm)
+
+
+def _pow2_at_least(v, lo):
+    n = lo
+    while n < v:
+        n *= 2
+    return n
+
+
+def films_c4(n_films=256, seed=SEED0 + 3, nodes=(5e3, 8e4), period=(20.0 * NM, 200.0 * NM),
+             thickness=(2.0 * NM, 10.0 * NM), Ms=(4e5, 1.6e6), Aex=1.3e-11, jitter=0.15):
+    """Independent 2D-periodic films of uneven size (the batched-cell workload).
+
+    Film i: node count log-uniform in ``nodes``, period L uniform in
+    ``period`` (square cell, periodic in x and y), thickness t uniform in
+    ``thickness``, Ms uniform in ``Ms``; a Kuhn lattice of nx = ny cells of
+    side L/nx and nz = t/hz layers (cells as close to cubes as the node count
+    allows), jittered; the AIM grid takes the smallest power of two (at least
+    16) of points per period that is not coarser than the lattice, and 4 (8
+    for five or more layers) across the thickness. The initial state is, in
+    turn, a vortex (in-plane curl around the cell centre with an out-of-plane
+    core of radius L/10), a uniform tilted state, or iid random directions.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(n_films):
+        N = float(np.exp(rng.uniform(np.log(nodes[0]), np.log(nodes[1]))))
+        L = float(rng.uniform(*period))
+        t = float(rng.uniform(*thickness))
+        ms = float(rng.uniform(*Ms))
+        h = (L * L * t / N) ** (1.0 / 3.0)
+        nz = max(1, int(round(t / h)))
+        nx = max(4, int(round(np.sqrt(N / (nz + 1)))))
+        hxy, hz = L / nx, t / nz
+        kind = i % 3
+        if kind == 0:
+            def mfun(xyz, L=L, t=t):
+                d = xyz[:, :2] - L / 2
+                r = np.hypot(d[:, 0], d[:, 1])
+                mz = np.exp(-(r / (0.1 * L)) ** 2)
+                phi = np.arctan2(d[:, 1], d[:, 0])
+                sxy = np.sqrt(1 - mz * mz)
+                return np.stack([-sxy * np.sin(phi), sxy * np.cos(phi), mz], axis=1)
+            m = mfun
+        elif kind == 1:
+            th, ph = rng.uniform(0.2, 1.4), rng.uniform(0, 2 * np.pi)
+            m = [np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)]
+        else:
+            m = "random"
+        grid = (_pow2_at_least(nx, 16), _pow2_at_least(nx, 16), 8 if nz >= 5 else 4)
+        out.append(kuhn_box((nx, nx, nz), [hxy, hxy, hz], periodic=0b011, jitter=jitter,
+                            seed=seed + 1 + i, Ms=ms, Aex=Aex, grid=grid, m=m,
+                            name=f"film_c4_{i}"))
+    return out
 
 
 CONFIGS = {
