@@ -274,11 +274,55 @@ int pmfem_pgf_eval(uint32_t axis_mask, const double L[3], double eta, int64_t n,
  * passes, each candidate timed over `trials` whole evaluations with HIP
  * events (the stages overlap on two streams, so the whole evaluation is the
  * objective). The choice stays set on the context; chosen (host, 4 int32, or
- * NULL) receives it in stage order, best_ms (or NULL) the mean milliseconds
+ * NULL) receives it in stage order ("spmv" 0: lanes chosen per pattern from
+ * its mean row length), best_ms (or NULL) the mean milliseconds
  * per evaluation of that choice. Synchronises; uses the context's own work
  * buffers as input, so it leaves no caller data changed.
  */
 int pmfem_autotune(pmfem_ctx* ctx, int32_t trials, int32_t* chosen, double* best_ms);
+
+/*
+ * Batches of independent unit cells (the batched-cell workload: many small
+ * periodic cells, each with its own mesh, periods, materials and grid; no
+ * data flows between cells). A batch evaluates every cell with one kernel
+ * launch per stage for all cells: the exchange, charge, element-correction
+ * and gradient operators of the cells concatenated block-diagonally, and the
+ * anterpolation, FFT and interpolation kernels in multi-cell form (each
+ * workgroup finds its cell in a table). Per cell the arithmetic is that of
+ * pmfem_heff with the scatter anterpolation, whole-plane FFT and large
+ * interpolation tiles, so the fields agree with the per-cell calls (bitwise
+ * when the cells use those forms and the same SpMV lanes).
+ *
+ * pmfem_batch_create: cells[n_cells] built contexts on one device with the
+ * same Lagrange order and near radius, each fitting those kernel forms;
+ * hip_stream (or NULL) is the stream the batch's work goes to (part of it on
+ * an internal second stream forked from and joined back to it within each
+ * call); spmv_lanes 0 picks the SpMV lanes from the mean row lengths, else
+ * 4, 8 or 16. The batch copies the cells' local operators; it uses each
+ * cell's grid work buffers, so a cell must not be used by other calls while a
+ * batch call on it is in flight, and must outlive the batch. Errors: EINVAL
+ * (no cells, a repeated cell, different devices, orders or radii, a cell
+ * whose plans do not fit), ESTATE (a cell not built), ENOMEM, EHIP; on a
+ * set-up error *out still receives the batch (for pmfem_batch_last_error; it
+ * must be destroyed), unless it could not be made (then *out is NULL).
+ */
+typedef struct pmfem_batch pmfem_batch;
+int pmfem_batch_create(pmfem_batch** out, int32_t n_cells, pmfem_ctx* const* cells,
+                       void* hip_stream, int32_t spmv_lanes);
+/* n_unknowns = sum of the cells' N'; cell_offsets[n_cells + 1] (or NULL) the
+ * first row of every cell in the packed vectors; bytes_per_eval (or NULL) the
+ * sum of the cells' algorithmic bytes per evaluation. */
+int pmfem_batch_query(pmfem_batch* b, int64_t* n_unknowns, int64_t* cell_offsets,
+                      double* bytes_per_eval);
+/* pmfem_heff of every cell: m_dev, h_dev [n_unknowns][3] (device), the cells'
+ * unknowns packed in cell order, each cell in its own unknown order. */
+int pmfem_batch_heff(pmfem_batch* b, const float* m_dev, float* h_dev, uint32_t terms);
+/* n_steps RK4 steps (as pmfem_llg_step, no applied field) of every cell on the
+ * packed FP64 master magnetisation m_dev[n_unknowns][3]. */
+int pmfem_batch_llg_step(pmfem_batch* b, double* m_dev, double dt, double alpha,
+                         int32_t n_steps);
+const char* pmfem_batch_last_error(const pmfem_batch* b);
+void pmfem_batch_destroy(pmfem_batch* b);
 
 const char* pmfem_last_error(const pmfem_ctx* ctx);
 

@@ -69,6 +69,12 @@ _SIGS = {
                                     ctypes.POINTER(_I32)]),
     "pmfem_pgf_eval": (ctypes.c_int, [_U32, _P, _D, _I64, _P, _P]),
     "pmfem_autotune": (ctypes.c_int, [_P, _I32, _P, _DP]),
+    "pmfem_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), _I32, _P, _P, _I32]),
+    "pmfem_batch_query": (ctypes.c_int, [_P, ctypes.POINTER(_I64), _P, _DP]),
+    "pmfem_batch_heff": (ctypes.c_int, [_P, _P, _P, _U32]),
+    "pmfem_batch_llg_step": (ctypes.c_int, [_P, _P, _D, _D, _I32]),
+    "pmfem_batch_last_error": (ctypes.c_char_p, [_P]),
+    "pmfem_batch_destroy": (None, [_P]),
     "pmfem_last_error": (ctypes.c_char_p, [_P]),
     "pmfem_destroy": (None, [_P]),
 }
@@ -312,3 +318,59 @@ class Context:
                                                ctypes.cast(names, _P)), "profile_end")
         return {names[k].value.decode(): (float(ms[k]), int(cnt[k])) for k in range(nk.value)}
 
+
+
+class Batch:
+    """Independent built contexts on one device, evaluated with one launch per
+    stage for all of them. Vectors are packed in cell order (see offsets)."""
+
+    def __init__(self, contexts, stream=None, spmv_lanes=0):
+        self.lib = load_library()
+        self.cells = list(contexts)
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream(self.cells[0].device).cuda_stream
+        arr = (_P * len(self.cells))(*[c.h for c in self.cells])
+        h = _P()
+        rc = self.lib.pmfem_batch_create(ctypes.byref(h), len(self.cells), ctypes.cast(arr, _P),
+                                         _P(stream) if stream else None, int(spmv_lanes))
+        self.h = h if h.value else None
+        if rc:
+            msg = self.lib.pmfem_batch_last_error(h) if h.value else b""
+            self.close()
+            raise PmfemError(rc, f"pmfem_batch_create: {msg.decode() if msg else ''}")
+        n = _I64()
+        self.offsets = np.zeros(len(self.cells) + 1, dtype=np.int64)
+        bpe = _D()
+        self._check(self.lib.pmfem_batch_query(self.h, ctypes.byref(n), _ptr(self.offsets),
+                                               ctypes.byref(bpe)), "batch_query")
+        self.n = int(n.value)
+        self.bytes_per_eval = float(bpe.value)
+
+    def _check(self, rc, what):
+        if rc:
+            msg = self.lib.pmfem_batch_last_error(self.h)
+            raise PmfemError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def heff(self, m, h, terms=TERM_EX | TERM_MS):
+        import torch
+        self._check(self.lib.pmfem_batch_heff(self.h, _dev_ptr(m, torch.float32, (self.n, 3), "m"),
+                                              _dev_ptr(h, torch.float32, (self.n, 3), "h"),
+                                              int(terms)), "batch_heff")
+
+    def llg_step(self, m64, dt, alpha, n_steps=1):
+        import torch
+        self._check(self.lib.pmfem_batch_llg_step(
+            self.h, _dev_ptr(m64, torch.float64, (self.n, 3), "m"), float(dt), float(alpha),
+            int(n_steps)), "batch_llg_step")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pmfem_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1372,7 +1372,8 @@ int autotune(pmfem_ctx* c, int trials, double* best_ms) {
     int k;
     std::vector<int> forms;
   };
-  const Stage stages[4] = {{0, {3, 2, 1}}, {1, {2, 1}}, {2, {2, 1}}, {3, {4, 8, 16}}};
+  // SpMV lanes 0: chosen per pattern from its mean row length
+  const Stage stages[4] = {{0, {3, 2, 1}}, {1, {2, 1}}, {2, {2, 1}}, {3, {0, 4, 8, 16}}};
   // start from the automatic choice, made explicit
   for (int k = 0; k < 4; ++k) c->variant[k] = 0;
   (void)select_variants(c);
@@ -1407,6 +1408,419 @@ int autotune(pmfem_ctx* c, int trials, double* best_ms) {
   if (best_ms) *best_ms = best;
   if (!rc) c->err.clear();  // forms that did not fit left their message
   return rc;
+}
+
+}  // namespace
+
+// A batch of independent unit cells evaluated together: the local operators
+// of all cells concatenated block-diagonally (one launch of each SpMV for all
+// cells), and every grid kernel in its multi-cell form, one launch per kernel
+// for all cells, each workgroup finding its cell in a block-to-cell table.
+struct pmfem_batch {
+  int device = 0;
+  hipStream_t stream = nullptr, side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  std::vector<pmfem_ctx*> cells;
+  std::vector<int64_t> off;  // first unknown of each cell in the batch vectors, [K + 1]
+  int64_t n = 0;
+  int32_t *lrp = nullptr, *zrp = nullptr;
+  int4 *drec = nullptr, *grec = nullptr, *zrec = nullptr;
+  int2* lrec = nullptr;
+  int lanes_l = 4, lanes_z = 8;
+  float *q = nullptr, *uz = nullptr, *u = nullptr, *hex = nullptr;
+  float *m32 = nullptr, *h32 = nullptr;
+  double *mst = nullptr, *kk = nullptr, *acc = nullptr;
+  pmfem::CellTab* tab = nullptr;
+  struct Launch {
+    int32_t* bcell = nullptr;
+    int32_t* boff = nullptr;
+    unsigned blocks = 0;
+  } sc, sum, xy, zm, yx, ic, r2c, fy, c2r;
+  size_t lds_sc = 0, lds_plane = 0, lds_z = 0, lds_ic = 0, lds_r2c = 0, lds_fy = 0;
+  int p = 3, W = 5, KC = 2, PT = 4, Bz = 8;
+  double bytes = 0.0;
+  std::vector<void*> allocs;
+  std::string err;
+};
+
+namespace {
+
+int batch_err(pmfem_batch* b, int code, const std::string& m) {
+  if (b) b->err = m;
+  return code;
+}
+
+template <class T>
+int balloc(pmfem_batch* b, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) return batch_err(b, PMFEM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  b->allocs.push_back((void*)*p);
+  return PMFEM_OK;
+}
+
+template <class T>
+int bupload(pmfem_batch* b, T** p, const void* src, size_t count) {
+  int rc = balloc(b, p, count);
+  if (rc) return rc;
+  if (count) {
+    hipError_t e = hipMemcpy(*p, src, count * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return batch_err(b, PMFEM_EHIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  }
+  return PMFEM_OK;
+}
+
+void batch_free(pmfem_batch* b) {
+  if (b->stream || b->side) (void)hipStreamSynchronize(b->stream);
+  if (b->side) (void)hipStreamSynchronize(b->side);
+  for (void* p : b->allocs) (void)hipFree(p);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->join) (void)hipEventDestroy(b->join);
+  if (b->side) (void)hipStreamDestroy(b->side);
+  delete b;
+}
+
+// block-to-cell table of one multi-cell launch: blocks[c] workgroups for cell c
+int batch_launch_table(pmfem_batch* b, const std::vector<int64_t>& blocks, pmfem_batch::Launch& L) {
+  std::vector<int32_t> boff(blocks.size() + 1, 0), bcell;
+  for (size_t c = 0; c < blocks.size(); ++c) {
+    if ((int64_t)boff[c] + blocks[c] > 2147483647LL)
+      return batch_err(b, PMFEM_EINVAL, "batch launch too large");
+    boff[c + 1] = boff[c] + (int32_t)blocks[c];
+    for (int64_t k = 0; k < blocks[c]; ++k) bcell.push_back((int32_t)c);
+  }
+  L.blocks = (unsigned)boff.back();
+  int rc = bupload(b, &L.boff, boff.data(), boff.size());
+  if (!rc) rc = bupload(b, &L.bcell, bcell.data(), bcell.size());
+  return rc;
+}
+
+int batch_setup(pmfem_batch* b, int32_t spmv_lanes) {
+  const size_t K = b->cells.size();
+  b->off.assign(K + 1, 0);
+  int64_t nnzL = 0, nnzZ = 0;
+  for (size_t c = 0; c < K; ++c) {
+    const HostOps& o = b->cells[c]->ops;
+    b->off[c + 1] = b->off[c] + o.n_unk;
+    nnzL += o.loc_rowptr[o.n_unk];
+    nnzZ += o.z0_rowptr[o.n_unk];
+    double bpe = 0.0;
+    (void)pmfem_query(b->cells[c], nullptr, nullptr, nullptr, &bpe);
+    b->bytes += bpe;
+  }
+  const int64_t n = b->off[K];
+  b->n = n;
+  if (n >= 2147483647LL || nnzL >= 2147483647LL || nnzZ >= 2147483647LL)
+    return batch_err(b, PMFEM_EINVAL, "batch too large for 32-bit indices");
+  // concatenated local operators, columns shifted by the cell's first unknown
+  {
+    std::vector<int32_t> lrp(n + 1, 0), zrp(n + 1, 0);
+    std::vector<int4> dr, gr, zr;
+    std::vector<int2> lr;
+    dr.reserve(nnzL);
+    gr.reserve(nnzL);
+    lr.reserve(nnzL);
+    zr.reserve(nnzZ);
+    for (size_t c = 0; c < K; ++c) {
+      const HostOps& o = b->cells[c]->ops;
+      const int32_t base = (int32_t)b->off[c];
+      for (int64_t r = 0; r < o.n_unk; ++r) {
+        for (int32_t e = o.loc_rowptr[r]; e < o.loc_rowptr[r + 1]; ++e) {
+          const float* v = &o.loc_val[8 * (size_t)e];
+          int4 d4, g4;
+          int2 l2;
+          d4.x = g4.x = l2.x = o.loc_col[e] + base;
+          std::memcpy(&d4.y, &v[1], 4);
+          std::memcpy(&d4.z, &v[2], 4);
+          std::memcpy(&d4.w, &v[3], 4);
+          std::memcpy(&g4.y, &v[4], 4);
+          std::memcpy(&g4.z, &v[5], 4);
+          std::memcpy(&g4.w, &v[6], 4);
+          std::memcpy(&l2.y, &v[0], 4);
+          dr.push_back(d4);
+          gr.push_back(g4);
+          lr.push_back(l2);
+        }
+        lrp[base + r + 1] = (int32_t)dr.size();
+        for (int32_t e = o.z0_rowptr[r]; e < o.z0_rowptr[r + 1]; ++e) {
+          int4 z4;
+          z4.x = o.z0_col[e] + base;
+          std::memcpy(&z4.y, &o.z0_val[4 * (size_t)e], 4);
+          std::memcpy(&z4.z, &o.z0_val[4 * (size_t)e + 1], 4);
+          std::memcpy(&z4.w, &o.z0_val[4 * (size_t)e + 2], 4);
+          zr.push_back(z4);
+        }
+        zrp[base + r + 1] = (int32_t)zr.size();
+      }
+    }
+    int rc;
+    if ((rc = bupload(b, &b->lrp, lrp.data(), lrp.size())) ||
+        (rc = bupload(b, &b->drec, dr.data(), dr.size())) ||
+        (rc = bupload(b, &b->grec, gr.data(), gr.size())) ||
+        (rc = bupload(b, &b->lrec, lr.data(), lr.size())) ||
+        (rc = bupload(b, &b->zrp, zrp.data(), zrp.size())) ||
+        (rc = bupload(b, &b->zrec, zr.data(), zr.size())))
+      return rc;
+    auto pick = [](double mean) { return mean > 48.0 ? 16 : mean > 24.0 ? 8 : 4; };
+    b->lanes_l = spmv_lanes ? spmv_lanes : pick((double)nnzL / std::max<int64_t>(n, 1));
+    b->lanes_z = spmv_lanes ? spmv_lanes : pick((double)nnzZ / std::max<int64_t>(n, 1));
+  }
+  int rc;
+  if ((rc = balloc(b, &b->q, n)) || (rc = balloc(b, &b->uz, n)) || (rc = balloc(b, &b->u, n)) ||
+      (rc = balloc(b, &b->hex, 3 * n)) || (rc = balloc(b, &b->m32, 3 * n)) ||
+      (rc = balloc(b, &b->h32, 3 * n)) || (rc = balloc(b, &b->mst, 3 * n)) ||
+      (rc = balloc(b, &b->kk, 3 * n)) || (rc = balloc(b, &b->acc, 3 * n)))
+    return rc;
+  // the cell table and the launch tables of the grid kernels
+  std::vector<CellTab> tab(K);
+  std::vector<int64_t> nsc(K), nsum(K), nxy(K), nzm(K), nic(K), nr2c(K), nfy(K);
+  b->p = b->cells[0]->dev->g.p;
+  b->W = 2 * b->cells[0]->dev->g.rb + 1;
+  b->PT = 4;
+  for (size_t c = 0; c < K; ++c)
+    if (b->cells[c]->dev->g.N[0] % 4 != 0) b->PT = 1;
+  for (size_t c = 0; c < K; ++c) {
+    const pmfem_dev* d = b->cells[c]->dev;
+    if (d->g.p != b->p || 2 * d->g.rb + 1 != b->W)
+      return batch_err(b, PMFEM_EINVAL, "cells of a batch must share the Lagrange order and near radius");
+    if (!d->sc_ok || (!d->ic_ok && !d->ic_small_ok))
+      return batch_err(b, PMFEM_EINVAL, "a cell does not fit the batched kernel forms");
+    CellTab& t = tab[c];
+    t.g = d->g;
+    t.sp = d->sp;
+    t.icp = d->icp;
+    t.pos4 = d->pos4;
+    t.sc_list = d->sc_list;
+    t.sc_lstart = d->sc_lstart;
+    for (int a = 0; a < 3; ++a) t.sc_tab[a] = d->sc_tab[a];
+    t.sc_part = d->sc_part;
+    t.grid = d->grid;
+    t.spec = d->spec;
+    t.khat = d->khat;
+    t.twx = d->twx;
+    t.twy = d->twy;
+    t.twz = d->twz;
+    // interpolation: the largest tiles whose staging fits, else the narrow ones
+    const IcPlan& ipl = d->ic_ok ? d->icp : d->icp_small;
+    const pmfem_dev::IcLists& il = d->ic_ok ? d->icl : d->icl_small;
+    t.icp = ipl;
+    t.ic_list = il.list;
+    t.ic_lstart = il.lstart;
+    t.ic_wseg = il.wseg;
+    t.ic_rdesc = il.rdesc;
+    t.prp = d->prp;
+    t.pv = d->pv;
+    t.q = b->q + b->off[c];
+    t.uz = b->uz + b->off[c];
+    t.u = b->u + b->off[c];
+    const GridParams& g = d->g;
+    const int64_t ng = (int64_t)g.N[0] * g.N[1] * g.N[2];
+    const int Hx = g.M[0] / 2 + 1;
+    nsc[c] = (int64_t)d->sp.nt[0] * d->sp.nt[1] * d->sp.nt[2];
+    nsum[c] = (ng / b->PT + 255) / 256;
+    // FFT: whole z-planes in LDS where they fit, else one axis per pass
+    t.lpb = std::max(1, 2048 / g.M[0]);
+    t.by = std::max(1, std::min(16, 4096 / g.M[1]));
+    if (d->fft_ok) {
+      nxy[c] = (int64_t)g.N[2] * PMFEM_FFT_SPLIT;
+      nr2c[c] = nfy[c] = 0;
+      b->lds_plane = std::max(b->lds_plane, d->fft_plane_lds);
+    } else {
+      nxy[c] = 0;
+      const int64_t xlines = (int64_t)((g.N[1] + 1) / 2) * g.N[2];
+      nr2c[c] = (xlines + t.lpb - 1) / t.lpb;
+      nfy[c] = (int64_t)g.N[2] * ((Hx + t.by - 1) / t.by);
+      b->lds_r2c = std::max(b->lds_r2c, (size_t)(g.M[0] / 2 + t.lpb * g.M[0]) * sizeof(float2));
+      b->lds_fy = std::max(b->lds_fy, (size_t)(g.M[1] / 2 + t.by * g.M[1]) * sizeof(float2));
+    }
+    b->Bz = std::min(b->Bz, std::max(1, std::min(PMFEM_FFTZ_B, 4096 / g.M[2])));
+    nic[c] = (int64_t)ipl.nsx * g.nbox[1] * ipl.nsz;
+    b->lds_sc = std::max(b->lds_sc, (size_t)d->sp.lds_bytes);
+    b->lds_ic = std::max(b->lds_ic, (size_t)ipl.lds_bytes);
+    b->KC = std::max(b->KC, ipl.kc);
+  }
+  for (size_t c = 0; c < K; ++c) {
+    const GridParams& g = b->cells[c]->dev->g;
+    nzm[c] = ((int64_t)g.M[1] * (g.M[0] / 2 + 1) + b->Bz - 1) / b->Bz;
+    b->lds_z = std::max(b->lds_z, (size_t)(g.M[2] / 2 + b->Bz * g.M[2]) * sizeof(float2));
+  }
+  if ((rc = bupload(b, &b->tab, tab.data(), K)) || (rc = batch_launch_table(b, nsc, b->sc)) ||
+      (rc = batch_launch_table(b, nsum, b->sum)) || (rc = batch_launch_table(b, nxy, b->xy)) ||
+      (rc = batch_launch_table(b, nxy, b->yx)) || (rc = batch_launch_table(b, nzm, b->zm)) ||
+      (rc = batch_launch_table(b, nic, b->ic)) || (rc = batch_launch_table(b, nr2c, b->r2c)) ||
+      (rc = batch_launch_table(b, nfy, b->fy)) || (rc = batch_launch_table(b, nr2c, b->c2r)))
+    return rc;
+  if (b->lds_plane > 65536) {
+    const int lb = (int)b->lds_plane;
+    if (hipFuncSetAttribute((const void*)k_fft_xy_fwd_cells,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lb) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_fft_yx_inv_cells,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lb) != hipSuccess)
+      return batch_err(b, PMFEM_EINVAL, "FFT planes of the batch do not fit in LDS");
+  }
+  return PMFEM_OK;
+}
+
+template <int WT, int KC>
+void launch_interp_cells(const pmfem_batch* b, hipStream_t s) {
+  hipLaunchKernelGGL((k_interp_tile_cells<WT, KC>), dim3(b->ic.blocks), dim3(256), b->lds_ic, s,
+                     (const CellTab*)b->tab, (const int32_t*)b->ic.bcell, (const int32_t*)b->ic.boff);
+}
+
+template <int WT>
+void launch_interp_cells_kc(const pmfem_batch* b, hipStream_t s) {
+  switch (b->KC) {
+    case 2:
+      launch_interp_cells<WT, 2>(b, s);
+      break;
+    case 4:
+      launch_interp_cells<WT, 4>(b, s);
+      break;
+    case 6:
+      launch_interp_cells<WT, 6>(b, s);
+      break;
+    default:
+      launch_interp_cells<WT, 8>(b, s);
+      break;
+  }
+}
+
+// One evaluation of every cell: m, h [n][3] packed in cell order.
+int batch_heff(pmfem_batch* b, const float* m, float* h, uint32_t terms) {
+  hipStream_t s = b->stream;
+  const int64_t n = b->n;
+  const int T = 256;
+  const int with_ex = (terms & PMFEM_TERM_EX) ? 1 : 0;
+  const int with_ms = (terms & PMFEM_TERM_MS) ? 1 : 0;
+  auto rowdot3 = [&](hipStream_t st, const int32_t* rp, const int4* rec, float* out, int lanes) {
+    const dim3 grid((unsigned)((n * lanes + T - 1) / T));
+    if (lanes == 4) hipLaunchKernelGGL(k_rowdot3<4>, grid, dim3(T), 0, st, n, m, rp, rec, out);
+    else if (lanes == 8) hipLaunchKernelGGL(k_rowdot3<8>, grid, dim3(T), 0, st, n, m, rp, rec, out);
+    else hipLaunchKernelGGL(k_rowdot3<16>, grid, dim3(T), 0, st, n, m, rp, rec, out);
+  };
+  auto exch = [&](hipStream_t st) {
+    const dim3 grid((unsigned)((n * b->lanes_l + T - 1) / T));
+    if (b->lanes_l == 4) hipLaunchKernelGGL(k_exch<4>, grid, dim3(T), 0, st, n, b->lrp, b->lrec, m, b->hex);
+    else if (b->lanes_l == 8) hipLaunchKernelGGL(k_exch<8>, grid, dim3(T), 0, st, n, b->lrp, b->lrec, m, b->hex);
+    else hipLaunchKernelGGL(k_exch<16>, grid, dim3(T), 0, st, n, b->lrp, b->lrec, m, b->hex);
+  };
+  const CellTab* tab = b->tab;
+  if (with_ms) {
+    rowdot3(s, b->lrp, b->drec, b->q, b->lanes_l);
+    (void)hipEventRecord(b->fork, s);
+    (void)hipStreamWaitEvent(b->side, b->fork, 0);
+    rowdot3(b->side, b->zrp, b->zrec, b->uz, b->lanes_z);
+    if (with_ex) exch(b->side);
+    (void)hipEventRecord(b->join, b->side);
+#define PMFEM_SCC(P)                                                                           \
+  hipLaunchKernelGGL(k_anterp_scatter_cells<P>, dim3(b->sc.blocks), dim3(64), b->lds_sc, s, tab, \
+                     (const int32_t*)b->sc.bcell, (const int32_t*)b->sc.boff)
+    switch (b->p) {
+      case 1:
+        PMFEM_SCC(1);
+        break;
+      case 2:
+        PMFEM_SCC(2);
+        break;
+      case 3:
+        PMFEM_SCC(3);
+        break;
+      case 4:
+        PMFEM_SCC(4);
+        break;
+      default:
+        PMFEM_SCC(5);
+        break;
+    }
+#undef PMFEM_SCC
+    if (b->PT == 4)
+      hipLaunchKernelGGL(k_anterp_sum_cells<4>, dim3(b->sum.blocks), dim3(T), 0, s, tab,
+                         (const int32_t*)b->sum.bcell, (const int32_t*)b->sum.boff);
+    else
+      hipLaunchKernelGGL(k_anterp_sum_cells<1>, dim3(b->sum.blocks), dim3(T), 0, s, tab,
+                         (const int32_t*)b->sum.bcell, (const int32_t*)b->sum.boff);
+    // cells whose z-planes fit in LDS take the plane passes, the others the
+    // per-axis passes; the z pass with the K multiply serves both
+    if (b->xy.blocks)
+      hipLaunchKernelGGL(k_fft_xy_fwd_cells, dim3(b->xy.blocks), dim3(1024), b->lds_plane, s, tab,
+                         (const int32_t*)b->xy.bcell, (const int32_t*)b->xy.boff, PMFEM_FFT_SPLIT);
+    if (b->r2c.blocks) {
+      hipLaunchKernelGGL(k_r2c_x_cells, dim3(b->r2c.blocks), dim3(T), b->lds_r2c, s, tab,
+                         (const int32_t*)b->r2c.bcell, (const int32_t*)b->r2c.boff);
+      hipLaunchKernelGGL(k_fft_y_cells, dim3(b->fy.blocks), dim3(T), b->lds_fy, s, tab,
+                         (const int32_t*)b->fy.bcell, (const int32_t*)b->fy.boff, 0);
+    }
+    hipLaunchKernelGGL(k_fft_z_mul_cells, dim3(b->zm.blocks), dim3(PMFEM_FFTZ_T), b->lds_z, s, tab,
+                       (const int32_t*)b->zm.bcell, (const int32_t*)b->zm.boff, b->Bz);
+    if (b->yx.blocks)
+      hipLaunchKernelGGL(k_fft_yx_inv_cells, dim3(b->yx.blocks), dim3(1024), b->lds_plane, s, tab,
+                         (const int32_t*)b->yx.bcell, (const int32_t*)b->yx.boff, PMFEM_FFT_SPLIT);
+    if (b->r2c.blocks) {
+      hipLaunchKernelGGL(k_fft_y_cells, dim3(b->fy.blocks), dim3(T), b->lds_fy, s, tab,
+                         (const int32_t*)b->fy.bcell, (const int32_t*)b->fy.boff, 1);
+      hipLaunchKernelGGL(k_c2r_x_cells, dim3(b->c2r.blocks), dim3(T), b->lds_r2c, s, tab,
+                         (const int32_t*)b->c2r.bcell, (const int32_t*)b->c2r.boff);
+    }
+    (void)hipStreamWaitEvent(s, b->join, 0);
+    switch (b->W) {
+      case 1:
+        launch_interp_cells_kc<1>(b, s);
+        break;
+      case 3:
+        launch_interp_cells_kc<3>(b, s);
+        break;
+      case 5:
+        launch_interp_cells_kc<5>(b, s);
+        break;
+      default:
+        launch_interp_cells_kc<7>(b, s);
+        break;
+    }
+  } else if (with_ex) {
+    exch(s);
+  }
+  {
+    const dim3 grid((unsigned)((n * b->lanes_l + T - 1) / T));
+    if (b->lanes_l == 4)
+      hipLaunchKernelGGL(k_gsum<4>, grid, dim3(T), 0, s, n, b->lrp, b->grec, b->u, b->hex, h, 0.f,
+                         0.f, 0.f, with_ex, with_ms);
+    else if (b->lanes_l == 8)
+      hipLaunchKernelGGL(k_gsum<8>, grid, dim3(T), 0, s, n, b->lrp, b->grec, b->u, b->hex, h, 0.f,
+                         0.f, 0.f, with_ex, with_ms);
+    else
+      hipLaunchKernelGGL(k_gsum<16>, grid, dim3(T), 0, s, n, b->lrp, b->grec, b->u, b->hex, h,
+                         0.f, 0.f, 0.f, with_ex, with_ms);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return batch_err(b, PMFEM_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return PMFEM_OK;
+}
+
+// one RK4 step of every cell on the packed FP64 master magnetisation
+int batch_rk4(pmfem_batch* b, double* m, double dt, double alpha) {
+  hipStream_t s = b->stream;
+  const int64_t n = b->n;
+  const unsigned b3 = (unsigned)((3 * n + 255) / 256), b1 = (unsigned)((n + 255) / 256);
+  const double pref = -kGamma0 / (1.0 + alpha * alpha);
+  const uint32_t terms = PMFEM_TERM_EX | PMFEM_TERM_MS;
+  int rc;
+  hipLaunchKernelGGL(k_rk_stage, dim3(b3), dim3(256), 0, s, n, m, (const double*)nullptr, 0.0,
+                     (double*)nullptr, b->m32);
+  if ((rc = batch_heff(b, b->m32, b->h32, terms))) return rc;
+  hipLaunchKernelGGL(k_rk_rhs, dim3(b1), dim3(256), 0, s, n, (const double*)m, b->h32, pref, alpha,
+                     b->kk, b->acc, 1.0, 1);
+  const double cs[3] = {0.5 * dt, 0.5 * dt, dt};
+  const double ws[3] = {2.0, 2.0, 1.0};
+  for (int k = 0; k < 3; ++k) {
+    hipLaunchKernelGGL(k_rk_stage, dim3(b3), dim3(256), 0, s, n, (const double*)m,
+                       (const double*)b->kk, cs[k], b->mst, b->m32);
+    if ((rc = batch_heff(b, b->m32, b->h32, terms))) return rc;
+    hipLaunchKernelGGL(k_rk_rhs, dim3(b1), dim3(256), 0, s, n, (const double*)b->mst, b->h32, pref,
+                       alpha, b->kk, b->acc, ws[k], 0);
+  }
+  hipLaunchKernelGGL(k_rk_final, dim3(b1), dim3(256), 0, s, n, m, (const double*)b->acc, dt / 6.0);
+  return PMFEM_OK;
 }
 
 }  // namespace
@@ -1826,6 +2240,90 @@ int pmfem_autotune(pmfem_ctx* c, int32_t trials, int32_t* chosen, double* best_m
   if (chosen)
     for (int k = 0; k < 4; ++k) chosen[k] = c->variant[k];
   return PMFEM_OK;
+}
+
+int pmfem_batch_create(pmfem_batch** out, int32_t n_cells, pmfem_ctx* const* cells,
+                       void* hip_stream, int32_t spmv_lanes) {
+  if (!out) return PMFEM_EINVAL;
+  *out = nullptr;
+  if (n_cells < 1 || !cells) return PMFEM_EINVAL;
+  if (spmv_lanes != 0 && spmv_lanes != 4 && spmv_lanes != 8 && spmv_lanes != 16) return PMFEM_EINVAL;
+  for (int32_t k = 0; k < n_cells; ++k) {
+    if (!cells[k] || !cells[k]->built || !cells[k]->dev) return PMFEM_ESTATE;
+    if (cells[k]->device != cells[0]->device) return PMFEM_EINVAL;
+    for (int32_t j = 0; j < k; ++j)
+      if (cells[j] == cells[k]) return PMFEM_EINVAL;
+  }
+  pmfem_batch* b = new (std::nothrow) pmfem_batch();
+  if (!b) return PMFEM_ENOMEM;
+  b->device = cells[0]->device;
+  b->stream = (hipStream_t)hip_stream;
+  b->cells.assign(cells, cells + n_cells);
+  hipError_t e = hipSetDevice(b->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    batch_free(b);
+    return PMFEM_EHIP;
+  }
+  int rc;
+  try {
+    rc = batch_setup(b, spmv_lanes);
+  } catch (const std::bad_alloc&) {
+    rc = PMFEM_ENOMEM;
+  }
+  if (rc) {
+    // the caller gets the batch back to read the message, unless it could not be made
+    *out = b;
+    return rc;
+  }
+  *out = b;
+  return PMFEM_OK;
+}
+
+int pmfem_batch_query(pmfem_batch* b, int64_t* n_unknowns, int64_t* cell_offsets,
+                      double* bytes_per_eval) {
+  if (!b) return PMFEM_EINVAL;
+  if (n_unknowns) *n_unknowns = b->n;
+  if (cell_offsets)
+    for (size_t c = 0; c < b->off.size(); ++c) cell_offsets[c] = b->off[c];
+  if (bytes_per_eval) *bytes_per_eval = b->bytes;
+  return PMFEM_OK;
+}
+
+int pmfem_batch_heff(pmfem_batch* b, const float* m_dev, float* h_dev, uint32_t terms) {
+  if (!b) return PMFEM_EINVAL;
+  if (!b->tab) return batch_err(b, PMFEM_ESTATE, "batch set-up failed");
+  if (!m_dev || !h_dev || terms < 1 || terms > 3)
+    return batch_err(b, PMFEM_EINVAL, "bad batch heff arguments");
+  hipError_t e = hipSetDevice(b->device);
+  if (e != hipSuccess) return batch_err(b, PMFEM_EHIP, "hipSetDevice");
+  return batch_heff(b, m_dev, h_dev, terms);
+}
+
+int pmfem_batch_llg_step(pmfem_batch* b, double* m_dev, double dt, double alpha, int32_t n_steps) {
+  if (!b) return PMFEM_EINVAL;
+  if (!b->tab) return batch_err(b, PMFEM_ESTATE, "batch set-up failed");
+  if (!m_dev || n_steps < 0 || !(dt > 0.0) || !(alpha >= 0.0))
+    return batch_err(b, PMFEM_EINVAL, "bad batch llg arguments");
+  hipError_t e = hipSetDevice(b->device);
+  if (e != hipSuccess) return batch_err(b, PMFEM_EHIP, "hipSetDevice");
+  for (int32_t st = 0; st < n_steps; ++st) {
+    const int rc = batch_rk4(b, m_dev, dt, alpha);
+    if (rc) return rc;
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return batch_err(b, PMFEM_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return PMFEM_OK;
+}
+
+const char* pmfem_batch_last_error(const pmfem_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+void pmfem_batch_destroy(pmfem_batch* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  batch_free(b);
 }
 
 const char* pmfem_last_error(const pmfem_ctx* c) { return c ? c->err.c_str() : "null context"; }

@@ -63,6 +63,33 @@ struct ScPlan {
   int lds_bytes;
 };
 
+// One unit cell of a batch: its grid and kernel plans, its own operator
+// arrays, and its slices of the batch's per-unknown vectors. The multi-cell
+// kernels (k_*_cells) take every workgroup's cell from a block-to-cell table
+// and its workgroup index within the cell from the cell's first block.
+struct CellTab {
+  GridParams g;
+  ScPlan sp;
+  IcPlan icp;
+  const float4* pos4;
+  const int2* sc_list;
+  const int32_t* sc_lstart;
+  const int2* sc_tab[3];
+  float* sc_part;
+  float* grid;
+  float2* spec;
+  const float* khat;
+  const float2 *twx, *twy, *twz;
+  const int32_t *ic_list, *ic_lstart, *ic_wseg;
+  const uint32_t* ic_rdesc;
+  const int32_t* prp;
+  const float* pv;
+  int lpb, by;      // per-axis FFT form: x lines per block, y columns per block
+  const float* q;   // the cell's charges in the batch vector
+  const float* uz;  // element correction
+  float* u;         // potential
+};
+
 template <int G>
 __global__ void k_rowdot3(int64_t n, const float* m, const int32_t* rp, const int4* rec,
                           float* out);
@@ -104,6 +131,24 @@ __global__ void k_interp_tile(GridParams g, IcPlan pl, const float* U, const flo
                               const int32_t* list, const int32_t* lstart, const int32_t* wseg,
                               const uint32_t* rdesc, const int32_t* prp, const float* pval,
                               const float* q, const float* uz, float* u);
+// multi-cell forms (one launch for every cell of a batch)
+template <int P>
+__global__ void k_anterp_scatter_cells(const CellTab* tab, const int32_t* bcell,
+                                       const int32_t* boff);
+template <int PT>
+__global__ void k_anterp_sum_cells(const CellTab* tab, const int32_t* bcell, const int32_t* boff);
+__global__ void k_fft_xy_fwd_cells(const CellTab* tab, const int32_t* bcell, const int32_t* boff,
+                                   int nsplit);
+__global__ void k_fft_yx_inv_cells(const CellTab* tab, const int32_t* bcell, const int32_t* boff,
+                                   int nsplit);
+__global__ void k_fft_z_mul_cells(const CellTab* tab, const int32_t* bcell, const int32_t* boff,
+                                  int B);
+template <int WT, int KC>
+__global__ void k_interp_tile_cells(const CellTab* tab, const int32_t* bcell, const int32_t* boff);
+__global__ void k_r2c_x_cells(const CellTab* tab, const int32_t* bcell, const int32_t* boff);
+__global__ void k_fft_y_cells(const CellTab* tab, const int32_t* bcell, const int32_t* boff,
+                              int inverse);
+__global__ void k_c2r_x_cells(const CellTab* tab, const int32_t* bcell, const int32_t* boff);
 template <int G>
 __global__ void k_exch(int64_t n, const int32_t* rp, const int2* lrec, const float* m, float* hex);
 template <int G>

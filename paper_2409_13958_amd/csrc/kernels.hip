@@ -494,10 +494,10 @@ __device__ __forceinline__ float row_lane(float v) {
 }
 
 template <int P>
-__global__ void __launch_bounds__(64) k_anterp_scatter(
+__device__ __forceinline__ void anterp_scatter_body(
     GridParams g, ScPlan pl, const float* __restrict__ q, const float4* __restrict__ pos4,
     const int2* __restrict__ list, const int32_t* __restrict__ lstart,
-    float* __restrict__ part) {
+    float* __restrict__ part, const int blk) {
   constexpr int P1 = P + 1, GS = P1 * P1 <= 16 ? 16 : 64, NG = 64 / GS;
   extern __shared__ float s_acc[];  // [NG][fsize] footprint copies
   const int lane = threadIdx.x, grp = lane / GS, gl = lane - grp * GS;
@@ -505,7 +505,7 @@ __global__ void __launch_bounds__(64) k_anterp_scatter(
   // the lane's x and y stencil offsets; lane c of a group (b = 0) also
   // evaluates the z weight of index c for the group
   const int a = gl % P1, b = gl / P1;
-  const int w = blockIdx.x;
+  const int w = blk;
   const int l0 = lstart[w], cnt = lstart[w + 1] - l0;
   // nodes come in batches of 64, lane L holding entry f0 + L of the tile's
   // list {node, footprint offset of its stencil}; the next batch is requested
@@ -605,9 +605,29 @@ __global__ void __launch_bounds__(64) k_anterp_scatter(
   }
 }
 
+template <int P>
+__global__ void __launch_bounds__(64) k_anterp_scatter(
+    GridParams g, ScPlan pl, const float* __restrict__ q, const float4* __restrict__ pos4,
+    const int2* __restrict__ list, const int32_t* __restrict__ lstart,
+    float* __restrict__ part) {
+  anterp_scatter_body<P>(g, pl, q, pos4, list, lstart, part, blockIdx.x);
+}
+
+template <int P>
+__global__ void __launch_bounds__(64) k_anterp_scatter_cells(const CellTab* __restrict__ tab,
+                                                            const int32_t* __restrict__ bcell,
+                                                            const int32_t* __restrict__ boff) {
+  const int c = bcell[blockIdx.x];
+  const CellTab& t = tab[c];
+  anterp_scatter_body<P>(t.g, t.sp, t.q, t.pos4, t.sc_list, t.sc_lstart, t.sc_part,
+                         blockIdx.x - boff[c]);
+}
+
 #define PMFEM_ANTERP_SCATTER(P)                                                               \
   template __global__ void k_anterp_scatter<P>(GridParams, ScPlan, const float*, const float4*, \
-                                               const int2*, const int32_t*, float*);
+                                               const int2*, const int32_t*, float*);         \
+  template __global__ void k_anterp_scatter_cells<P>(const CellTab*, const int32_t*,          \
+                                                     const int32_t*);
 PMFEM_ANTERP_SCATTER(1)
 PMFEM_ANTERP_SCATTER(2)
 PMFEM_ANTERP_SCATTER(3)
@@ -619,14 +639,14 @@ PMFEM_ANTERP_SCATTER(5)
 // along axis a, tile < 0 when absent. A thread takes PT consecutive x points
 // of one grid line (PT divides Nx), sharing their y and z entries.
 template <int PT>
-__global__ void __launch_bounds__(256) k_anterp_sum(GridParams g, ScPlan pl,
+__device__ __forceinline__ void anterp_sum_body(GridParams g, ScPlan pl,
                                                     const int2* __restrict__ tabx,
                                                     const int2* __restrict__ taby,
                                                     const int2* __restrict__ tabz,
                                                     const float* __restrict__ part,
-                                                    float* __restrict__ Q) {
+                                                    float* __restrict__ Q, const int blk) {
   const int Nx = g.N[0], Ny = g.N[1];
-  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * PT;
+  const int64_t i0 = ((int64_t)blk * blockDim.x + threadIdx.x) * PT;
   if (i0 >= (int64_t)Nx * Ny * g.N[2]) return;
   const int gx0 = (int)(i0 % Nx);
   const int64_t r = i0 / Nx;
@@ -677,10 +697,32 @@ __global__ void __launch_bounds__(256) k_anterp_sum(GridParams g, ScPlan pl,
   for (int k = 0; k < PT; ++k) grid_store(Q, i0 + k, sum[k], g);
 }
 
+template <int PT>
+__global__ void __launch_bounds__(256) k_anterp_sum(GridParams g, ScPlan pl,
+                                                    const int2* __restrict__ tabx,
+                                                    const int2* __restrict__ taby,
+                                                    const int2* __restrict__ tabz,
+                                                    const float* __restrict__ part,
+                                                    float* __restrict__ Q) {
+  anterp_sum_body<PT>(g, pl, tabx, taby, tabz, part, Q, blockIdx.x);
+}
+
+template <int PT>
+__global__ void __launch_bounds__(256) k_anterp_sum_cells(const CellTab* __restrict__ tab,
+                                                         const int32_t* __restrict__ bcell,
+                                                         const int32_t* __restrict__ boff) {
+  const int c = bcell[blockIdx.x];
+  const CellTab& t = tab[c];
+  anterp_sum_body<PT>(t.g, t.sp, t.sc_tab[0], t.sc_tab[1], t.sc_tab[2], t.sc_part, t.grid,
+                      blockIdx.x - boff[c]);
+}
+
 template __global__ void k_anterp_sum<1>(GridParams, ScPlan, const int2*, const int2*,
                                          const int2*, const float*, float*);
 template __global__ void k_anterp_sum<4>(GridParams, ScPlan, const int2*, const int2*,
                                          const int2*, const float*, float*);
+template __global__ void k_anterp_sum_cells<1>(const CellTab*, const int32_t*, const int32_t*);
+template __global__ void k_anterp_sum_cells<4>(const CellTab*, const int32_t*, const int32_t*);
 
 // ---------------------------------------------------------------------------
 // LDS radix-2 FFT on `lines` lines of length n, lines `stride` elements apart
@@ -798,9 +840,9 @@ __device__ __forceinline__ int bitrev(int i, int logn) { return (int)(__brev((un
 
 // R2C along x: pairs of real rows (y, y+1) of plane z form one complex line.
 // grid [Nz][Ny][Nx] real -> spec [Nz][My][Hx] complex (rows y < Ny written).
-__global__ void __launch_bounds__(256) k_r2c_x(GridParams g, const float* __restrict__ Q,
+__device__ __forceinline__ void r2c_x_body(GridParams g, const float* __restrict__ Q,
                                                float2* __restrict__ spec, const float2* __restrict__ twx,
-                                               int lines_per_block) {
+                                               int lines_per_block, const int blk) {
   extern __shared__ float2 sh[];
   const int Mx = g.M[0], logM = g.logM[0], Hx = Mx / 2 + 1;
   float2* tw = sh;
@@ -808,7 +850,7 @@ __global__ void __launch_bounds__(256) k_r2c_x(GridParams g, const float* __rest
   for (int i = threadIdx.x; i < Mx / 2; i += blockDim.x) tw[i] = twx[i];
   const int pairs = (g.N[1] + 1) / 2;
   const int64_t total_lines = (int64_t)pairs * g.N[2];
-  const int64_t l0 = (int64_t)blockIdx.x * lines_per_block;
+  const int64_t l0 = (int64_t)blk * lines_per_block;
   int nl = (int)((total_lines - l0) < lines_per_block ? (total_lines - l0) : lines_per_block);
   for (int idx = threadIdx.x; idx < nl * Mx; idx += blockDim.x) {
     int li = idx / Mx, x = idx - li * Mx;
@@ -837,6 +879,20 @@ __global__ void __launch_bounds__(256) k_r2c_x(GridParams g, const float* __rest
   }
 }
 
+__global__ void __launch_bounds__(256) k_r2c_x(GridParams g, const float* __restrict__ Q,
+                                               float2* __restrict__ spec, const float2* __restrict__ twx,
+                                               int lines_per_block) {
+  r2c_x_body(g, Q, spec, twx, lines_per_block, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_r2c_x_cells(const CellTab* __restrict__ tab,
+                                                     const int32_t* __restrict__ bcell,
+                                                     const int32_t* __restrict__ boff) {
+  const int c = bcell[blockIdx.x];
+  const CellTab& t = tab[c];
+  r2c_x_body(t.g, t.grid, t.spec, t.twx, t.lpb, blockIdx.x - boff[c]);
+}
+
 // n / d for 0 <= n < 2^22 and 1 <= d < 2^10 without an integer divide: the
 // float quotient is off by at most one, which the correction removes.
 __device__ __forceinline__ int fdiv(int n, int d, float inv_d) {
@@ -851,11 +907,11 @@ __device__ __forceinline__ int fdiv(int n, int d, float inv_d) {
 // kx < Hx, transposed into columns (stride My + 1) and transformed along y.
 // Q[z][y][x] -> spec[z][ky][kx] for all ky < My. nsplit workgroups share a
 // plane: each does the x pass and the y pass of its share of the columns.
-__global__ void __launch_bounds__(1024) k_fft_xy_fwd(GridParams g, const float* __restrict__ Q,
+__device__ __forceinline__ void fft_xy_fwd_body(GridParams g, const float* __restrict__ Q,
                                                      float2* __restrict__ spec,
                                                      const float2* __restrict__ twx,
                                                      const float2* __restrict__ twy,
-                                                     int nsplit) {
+                                                     int nsplit, const int blk) {
   extern __shared__ float2 sh[];
   const int Mx = g.M[0], My = g.M[1], Hx = Mx / 2 + 1, lx = g.logM[0], ly = g.logM[1];
   const int Nx = g.N[0], Ny = g.N[1], pairs = (Ny + 1) / 2, cs = My + 1;
@@ -863,7 +919,7 @@ __global__ void __launch_bounds__(1024) k_fft_xy_fwd(GridParams g, const float* 
   float2* ty = tx + Mx / 2;
   float2* A = ty + My / 2;        // [pairs][Mx]
   float2* C = A + pairs * Mx;     // [Hx][My + 1]
-  const int z = blockIdx.x / nsplit, part = blockIdx.x - z * nsplit;
+  const int z = blk / nsplit, part = blk - z * nsplit;
   const int kw = (Hx + nsplit - 1) / nsplit, k0 = part * kw, nk = min(Hx, k0 + kw) - k0;
   const float invnk = 1.0f / (float)nk;
   for (int i = threadIdx.x; i < Mx / 2; i += blockDim.x) tx[i] = twx[i];
@@ -911,16 +967,33 @@ __global__ void __launch_bounds__(1024) k_fft_xy_fwd(GridParams g, const float* 
   }
 }
 
+__global__ void __launch_bounds__(1024) k_fft_xy_fwd(GridParams g, const float* __restrict__ Q,
+                                                     float2* __restrict__ spec,
+                                                     const float2* __restrict__ twx,
+                                                     const float2* __restrict__ twy,
+                                                     int nsplit) {
+  fft_xy_fwd_body(g, Q, spec, twx, twy, nsplit, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(1024) k_fft_xy_fwd_cells(const CellTab* __restrict__ tab,
+                                                           const int32_t* __restrict__ bcell,
+                                                           const int32_t* __restrict__ boff,
+                                                           int nsplit) {
+  const int c = bcell[blockIdx.x];
+  const CellTab& t = tab[c];
+  fft_xy_fwd_body(t.g, t.grid, t.spec, t.twx, t.twy, nsplit, blockIdx.x - boff[c]);
+}
+
 // Inverse of k_fft_xy_fwd for one z-plane: inverse FFT along y of the half
 // spectrum columns, rows y < Ny paired into complex lines with Hermitian
 // extension (C2R along x), inverse FFT along x. spec[z] -> U[z][y][x].
 // nsplit workgroups share a plane: each does the y pass and the x pass of
 // its share of the row pairs.
-__global__ void __launch_bounds__(1024) k_fft_yx_inv(GridParams g, const float2* __restrict__ spec,
+__device__ __forceinline__ void fft_yx_inv_body(GridParams g, const float2* __restrict__ spec,
                                                      float* __restrict__ U,
                                                      const float2* __restrict__ twx,
                                                      const float2* __restrict__ twy,
-                                                     int nsplit) {
+                                                     int nsplit, const int blk) {
   extern __shared__ float2 sh[];
   const int Mx = g.M[0], My = g.M[1], Hx = Mx / 2 + 1, lx = g.logM[0], ly = g.logM[1];
   const int Nx = g.N[0], Ny = g.N[1], pairs = (Ny + 1) / 2, cs = My + 1;
@@ -928,7 +1001,7 @@ __global__ void __launch_bounds__(1024) k_fft_yx_inv(GridParams g, const float2*
   float2* ty = tx + Mx / 2;
   float2* A = ty + My / 2;
   float2* C = A + pairs * Mx;
-  const int z = blockIdx.x / nsplit, part = blockIdx.x - z * nsplit;
+  const int z = blk / nsplit, part = blk - z * nsplit;
   const int lw = (pairs + nsplit - 1) / nsplit, l0 = part * lw, nl = min(pairs, l0 + lw) - l0;
   for (int i = threadIdx.x; i < Mx / 2; i += blockDim.x) tx[i] = twx[i];
   for (int i = threadIdx.x; i < My / 2; i += blockDim.x) ty[i] = twy[i];
@@ -966,20 +1039,37 @@ __global__ void __launch_bounds__(1024) k_fft_yx_inv(GridParams g, const float2*
   }
 }
 
+__global__ void __launch_bounds__(1024) k_fft_yx_inv(GridParams g, const float2* __restrict__ spec,
+                                                     float* __restrict__ U,
+                                                     const float2* __restrict__ twx,
+                                                     const float2* __restrict__ twy,
+                                                     int nsplit) {
+  fft_yx_inv_body(g, spec, U, twx, twy, nsplit, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(1024) k_fft_yx_inv_cells(const CellTab* __restrict__ tab,
+                                                           const int32_t* __restrict__ bcell,
+                                                           const int32_t* __restrict__ boff,
+                                                           int nsplit) {
+  const int c = bcell[blockIdx.x];
+  const CellTab& t = tab[c];
+  fft_yx_inv_body(t.g, t.spec, t.grid, t.twx, t.twy, nsplit, blockIdx.x - boff[c]);
+}
+
 // FFT along y for lines (z < Nz, kx): groups of B consecutive kx per block.
 // Forward: input rows y < Ny (others zero), all My outputs written.
 // Inverse: all My inputs, outputs y < n_out written.
-__global__ void __launch_bounds__(256) k_fft_y(GridParams g, float2* __restrict__ spec,
+__device__ __forceinline__ void fft_y_body(GridParams g, float2* __restrict__ spec,
                                                const float2* __restrict__ twy, int B, int inverse,
-                                               int n_in, int n_out) {
+                                               int n_in, int n_out, const int blk) {
   extern __shared__ float2 sh[];
   const int My = g.M[1], logM = g.logM[1], Hx = g.M[0] / 2 + 1;
   float2* tw = sh;
   float2* buf = sh + My / 2;
   for (int i = threadIdx.x; i < My / 2; i += blockDim.x) tw[i] = twy[i];
   const int groups_per_plane = (Hx + B - 1) / B;
-  const int z = blockIdx.x / groups_per_plane;
-  const int kx0 = (blockIdx.x - z * groups_per_plane) * B;
+  const int z = blk / groups_per_plane;
+  const int kx0 = (blk - z * groups_per_plane) * B;
   const int nb = (Hx - kx0) < B ? (Hx - kx0) : B;
   for (int idx = threadIdx.x; idx < nb * My; idx += blockDim.x) {
     int y = idx / nb, li = idx - y * nb;
@@ -995,18 +1085,36 @@ __global__ void __launch_bounds__(256) k_fft_y(GridParams g, float2* __restrict_
   }
 }
 
+__global__ void __launch_bounds__(256) k_fft_y(GridParams g, float2* __restrict__ spec,
+                                               const float2* __restrict__ twy, int B, int inverse,
+                                               int n_in, int n_out) {
+  fft_y_body(g, spec, twy, B, inverse, n_in, n_out, blockIdx.x);
+}
+
+// inverse = 0: rows y < N_y in, all M_y out; inverse = 1: all in, y < N_y out
+__global__ void __launch_bounds__(256) k_fft_y_cells(const CellTab* __restrict__ tab,
+                                                     const int32_t* __restrict__ bcell,
+                                                     const int32_t* __restrict__ boff,
+                                                     int inverse) {
+  const int c = bcell[blockIdx.x];
+  const CellTab& t = tab[c];
+  const int ny = t.g.N[1], my = t.g.M[1];
+  fft_y_body(t.g, t.spec, t.twy, t.by, inverse, inverse ? my : ny, inverse ? ny : my,
+             blockIdx.x - boff[c]);
+}
+
 // FFT along z of lines c = ky*Hx + kx (B consecutive per block), multiply by
 // the real spectrum khat[kz][c], inverse FFT, write z < Nz.
-__global__ void __launch_bounds__(256) k_fft_z_mul(GridParams g, float2* __restrict__ spec,
+__device__ __forceinline__ void fft_z_mul_body(GridParams g, float2* __restrict__ spec,
                                                    const float* __restrict__ khat,
-                                                   const float2* __restrict__ twz, int B) {
+                                                   const float2* __restrict__ twz, int B, const int blk) {
   extern __shared__ float2 sh[];
   const int Mz = g.M[2], logM = g.logM[2], Hx = g.M[0] / 2 + 1;
   const int64_t plane = (int64_t)g.M[1] * Hx;
   float2* tw = sh;
   float2* buf = sh + Mz / 2;
   for (int i = threadIdx.x; i < Mz / 2; i += blockDim.x) tw[i] = twz[i];
-  const int64_t c0 = (int64_t)blockIdx.x * B;
+  const int64_t c0 = (int64_t)blk * B;
   const int nb = (int)((plane - c0) < B ? (plane - c0) : B);
   batched<8>(
       nb * Mz,
@@ -1051,10 +1159,25 @@ __global__ void __launch_bounds__(256) k_fft_z_mul(GridParams g, float2* __restr
   }
 }
 
+__global__ void __launch_bounds__(256) k_fft_z_mul(GridParams g, float2* __restrict__ spec,
+                                                   const float* __restrict__ khat,
+                                                   const float2* __restrict__ twz, int B) {
+  fft_z_mul_body(g, spec, khat, twz, B, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_fft_z_mul_cells(const CellTab* __restrict__ tab,
+                                                         const int32_t* __restrict__ bcell,
+                                                         const int32_t* __restrict__ boff,
+                                                         int B) {
+  const int c = bcell[blockIdx.x];
+  const CellTab& t = tab[c];
+  fft_z_mul_body(t.g, t.spec, t.khat, t.twz, B, blockIdx.x - boff[c]);
+}
+
 // C2R along x: rows (y, y+1) of plane z from their half spectra -> U[z][y][x].
-__global__ void __launch_bounds__(256) k_c2r_x(GridParams g, const float2* __restrict__ spec,
+__device__ __forceinline__ void c2r_x_body(GridParams g, const float2* __restrict__ spec,
                                                float* __restrict__ U, const float2* __restrict__ twx,
-                                               int lines_per_block) {
+                                               int lines_per_block, const int blk) {
   extern __shared__ float2 sh[];
   const int Mx = g.M[0], logM = g.logM[0], Hx = Mx / 2 + 1;
   float2* tw = sh;
@@ -1062,7 +1185,7 @@ __global__ void __launch_bounds__(256) k_c2r_x(GridParams g, const float2* __res
   for (int i = threadIdx.x; i < Mx / 2; i += blockDim.x) tw[i] = twx[i];
   const int pairs = (g.N[1] + 1) / 2;
   const int64_t total_lines = (int64_t)pairs * g.N[2];
-  const int64_t l0 = (int64_t)blockIdx.x * lines_per_block;
+  const int64_t l0 = (int64_t)blk * lines_per_block;
   int nl = (int)((total_lines - l0) < lines_per_block ? (total_lines - l0) : lines_per_block);
   for (int idx = threadIdx.x; idx < nl * Mx; idx += blockDim.x) {
     int li = idx / Mx, k = idx - li * Mx;
@@ -1089,6 +1212,20 @@ __global__ void __launch_bounds__(256) k_c2r_x(GridParams g, const float2* __res
     grid_store(U, ((int64_t)z * g.N[1] + y) * g.N[0] + x, v.x, g);
     if (y + 1 < g.N[1]) grid_store(U, ((int64_t)z * g.N[1] + y + 1) * g.N[0] + x, v.y, g);
   }
+}
+
+__global__ void __launch_bounds__(256) k_c2r_x(GridParams g, const float2* __restrict__ spec,
+                                               float* __restrict__ U, const float2* __restrict__ twx,
+                                               int lines_per_block) {
+  c2r_x_body(g, spec, U, twx, lines_per_block, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_c2r_x_cells(const CellTab* __restrict__ tab,
+                                                     const int32_t* __restrict__ bcell,
+                                                     const int32_t* __restrict__ boff) {
+  const int c = bcell[blockIdx.x];
+  const CellTab& t = tab[c];
+  c2r_x_body(t.g, t.spec, t.grid, t.twx, t.lpb, blockIdx.x - boff[c]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1120,12 +1257,12 @@ __global__ void __launch_bounds__(256) k_c2r_x(GridParams g, const float2* __res
 #endif
 #define PMFEM_IC_OCC __attribute__((amdgpu_waves_per_eu(PMFEM_IC_WAVES)))
 template <int WT, int KC>
-__global__ void __launch_bounds__(256) PMFEM_IC_OCC k_interp_tile(
+__device__ __forceinline__ void interp_tile_body(
     GridParams g, IcPlan pl, const float* __restrict__ U, const float4* __restrict__ pos4,
     const int32_t* __restrict__ list, const int32_t* __restrict__ lstart,
     const int32_t* __restrict__ wseg, const uint32_t* __restrict__ rdesc,
     const int32_t* __restrict__ prp, const float* __restrict__ pval,
-    const float* __restrict__ q, const float* __restrict__ uz, float* __restrict__ u) {
+    const float* __restrict__ q, const float* __restrict__ uz, float* __restrict__ u, const int blk) {
   extern __shared__ float4 smem4[];
   unsigned char* smem = reinterpret_cast<unsigned char*>(smem4);
   float* s_q = reinterpret_cast<float*>(smem + pl.o_q);   // staged charges
@@ -1134,7 +1271,7 @@ __global__ void __launch_bounds__(256) PMFEM_IC_OCC k_interp_tile(
   const int tid = threadIdx.x, T = blockDim.x;
   const int nby = g.nbox[1];
   const int p = g.p, p1 = p + 1;
-  const int w = blockIdx.x;
+  const int w = blk;
   const int sx = w % pl.nsx, rest = w / pl.nsx;
   const int by = rest % nby, sz = rest / nby;
   const int x0 = sx * pl.xs, z0 = sz * pl.tz;
@@ -1318,11 +1455,34 @@ __global__ void __launch_bounds__(256) PMFEM_IC_OCC k_interp_tile(
   }
 }
 
+template <int WT, int KC>
+__global__ void __launch_bounds__(256) PMFEM_IC_OCC k_interp_tile(
+    GridParams g, IcPlan pl, const float* __restrict__ U, const float4* __restrict__ pos4,
+    const int32_t* __restrict__ list, const int32_t* __restrict__ lstart,
+    const int32_t* __restrict__ wseg, const uint32_t* __restrict__ rdesc,
+    const int32_t* __restrict__ prp, const float* __restrict__ pval,
+    const float* __restrict__ q, const float* __restrict__ uz, float* __restrict__ u) {
+  interp_tile_body<WT, KC>(g, pl, U, pos4, list, lstart, wseg, rdesc, prp, pval, q, uz, u,
+                           blockIdx.x);
+}
+
+template <int WT, int KC>
+__global__ void __launch_bounds__(256) PMFEM_IC_OCC k_interp_tile_cells(
+    const CellTab* __restrict__ tab, const int32_t* __restrict__ bcell,
+    const int32_t* __restrict__ boff) {
+  const int c = bcell[blockIdx.x];
+  const CellTab& t = tab[c];
+  interp_tile_body<WT, KC>(t.g, t.icp, t.grid, t.pos4, t.ic_list, t.ic_lstart, t.ic_wseg,
+                           t.ic_rdesc, t.prp, t.pv, t.q, t.uz, t.u, blockIdx.x - boff[c]);
+}
+
 #define PMFEM_INTERP_TILE(WT, KC)                                                             \
   template __global__ void k_interp_tile<WT, KC>(                                             \
       GridParams, IcPlan, const float*, const float4*, const int32_t*, const int32_t*,        \
       const int32_t*, const uint32_t*, const int32_t*, const float*, const float*, const float*, \
-      float*);
+      float*);                                                                                \
+  template __global__ void k_interp_tile_cells<WT, KC>(const CellTab*, const int32_t*,        \
+                                                       const int32_t*);
 #define PMFEM_INTERP_TILES(WT) \
   PMFEM_INTERP_TILE(WT, 2)     \
   PMFEM_INTERP_TILE(WT, 4)     \
