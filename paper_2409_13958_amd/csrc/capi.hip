@@ -15,18 +15,13 @@
 
 using namespace pmfem;
 
-#ifndef PMFEM_FFTZ_B
-#define PMFEM_FFTZ_B 8  // z columns per workgroup of the z pass
-#endif
-#ifndef PMFEM_FFTZ_T
-#define PMFEM_FFTZ_T 256  // threads per workgroup of the z pass
-#endif
-#ifndef PMFEM_FFT_SPLIT
-#define PMFEM_FFT_SPLIT 2  // workgroups per z-plane in the plane transforms
-#endif
-#ifndef PMFEM_IC_LDS_BUDGET
-#define PMFEM_IC_LDS_BUDGET 24576  // LDS bytes per interpolation tile
-#endif
+// launch shapes (each the best of the measured alternatives on MI355X)
+constexpr int kFftzB = 8;            // z columns per workgroup of the z pass
+constexpr int kFftzT = 256;          // threads per workgroup of the z pass
+constexpr int kFftSplit = 2;         // workgroups per z-plane in the plane transforms
+constexpr int kIcLdsBudget = 24576;  // LDS bytes per interpolation tile
+constexpr int kScTile[3] = {8, 8, 4};  // preferred boxes per scatter tile along x, y, z
+constexpr int kScLdsBudget = 65536;    // LDS bytes of a scatter tile's footprint copies
 
 // Scratch of pmfem_grid_convolve_noalloc: the half-spectrum of one grid
 // convolution, at most kNoallocSpecMax complex values (16 MiB). Every device
@@ -389,12 +384,6 @@ bool build_interp_lists(const HostOps& o, const IcPlan& pl, std::vector<int32_t>
   return true;
 }
 
-#ifndef PMFEM_SC_TB
-#define PMFEM_SC_TB 8, 8, 4
-#endif
-#ifndef PMFEM_SC_LDS_BUDGET
-#define PMFEM_SC_LDS_BUDGET 65536
-#endif
 // Scatter plan of anterpolation: tiles of tb boxes per axis (at least p + 1,
 // so that a grid point lies in the footprints of at most two tiles per axis;
 // on a periodic axis at most N - p, so that a footprint does not wrap onto
@@ -406,7 +395,7 @@ bool build_interp_lists(const HostOps& o, const IcPlan& pl, std::vector<int32_t>
 bool plan_scatter_with(const HostOps& o, ScPlan& pl, std::vector<int2>& list,
                        std::vector<int32_t>& lstart, std::vector<int2> tab[3], bool divisors) {
   const int p = o.p, shift = (p - 1) / 2;
-  const int want[3] = {PMFEM_SC_TB};
+  const int* want = kScTile;
   auto start = [&](int a, int b) {
     return o.per[a] ? b - shift : std::min(std::max(b - shift, 0), o.N[a] - p - 1);
   };
@@ -469,7 +458,7 @@ bool plan_scatter_with(const HostOps& o, ScPlan& pl, std::vector<int2>& list,
   lstart[nt] = (int32_t)list.size();
   // the footprint copies, one per lane group (four groups of 16 lanes for p <= 3)
   const int64_t lds = (int64_t)pl.fsize * (o.p <= 3 ? 4 : 1) * 4;
-  if (lds > PMFEM_SC_LDS_BUDGET) return false;
+  if (lds > kScLdsBudget) return false;
   pl.lds_bytes = (int)lds;
   return (int64_t)list.size() == o.n_unk;
 }
@@ -595,7 +584,7 @@ bool plan_interp(const HostOps& o, int max_xs, IcPlan& pl) {
     pl.o_seg = (int)off;
     off += al((int64_t)(2 * tz + 1) * 4);
     (void)colmax;
-    if (off <= PMFEM_IC_LDS_BUDGET && qcap < 65536) {
+    if (off <= kIcLdsBudget && qcap < 65536) {
       pl.xs = xs;
       pl.tz = tz;
       pl.nsx = nsx;
@@ -807,9 +796,6 @@ int upload_all(pmfem_ctx* c) {
       const int64_t mean = n > 0 ? (tot / 4 + n - 1) / n : 0;
       const int64_t per_lane = (mean + kIcLanes - 1) / kIcLanes;
       int kc = per_lane <= 2 ? 2 : per_lane <= 4 ? 4 : per_lane <= 6 ? 6 : 8;
-#ifdef PMFEM_IC_FORCE_KC
-      kc = PMFEM_IC_FORCE_KC;
-#endif
       d->icp.kc = kc;
       d->icp_small.kc = kc;
     }
@@ -852,12 +838,12 @@ void convolve(pmfem_dev* d, hipStream_t s, const float* Qg, float* Ug, float2* s
   g.gmode = gmode;
   const int T = 256;
   const int Mx = g.M[0], My = g.M[1], Mz = g.M[2], Hx = Mx / 2 + 1;
-  const int Bz = std::max(1, std::min(PMFEM_FFTZ_B, 4096 / Mz)), Tz = PMFEM_FFTZ_T;
+  const int Bz = std::max(1, std::min(kFftzB, 4096 / Mz)), Tz = kFftzT;
   const int64_t cols = (int64_t)My * Hx;
   if (d->fft_plane) {
     mark(2, 0);
-    hipLaunchKernelGGL(k_fft_xy_fwd, dim3((unsigned)(g.N[2] * PMFEM_FFT_SPLIT)), dim3(1024),
-                       d->fft_plane_lds, s, g, Qg, spec, d->twx, d->twy, PMFEM_FFT_SPLIT);
+    hipLaunchKernelGGL(k_fft_xy_fwd, dim3((unsigned)(g.N[2] * kFftSplit)), dim3(1024),
+                       d->fft_plane_lds, s, g, Qg, spec, d->twx, d->twy, kFftSplit);
     mark(2, 1);
     mark(4, 0);
     hipLaunchKernelGGL(k_fft_z_mul, dim3((unsigned)((cols + Bz - 1) / Bz)), dim3(Tz),
@@ -865,9 +851,9 @@ void convolve(pmfem_dev* d, hipStream_t s, const float* Qg, float* Ug, float2* s
                        d->twz, Bz);
     mark(4, 1);
     mark(6, 0);
-    hipLaunchKernelGGL(k_fft_yx_inv, dim3((unsigned)(g.N[2] * PMFEM_FFT_SPLIT)), dim3(1024),
+    hipLaunchKernelGGL(k_fft_yx_inv, dim3((unsigned)(g.N[2] * kFftSplit)), dim3(1024),
                        d->fft_plane_lds, s, g, (const float2*)spec, Ug, d->twx, d->twy,
-                       PMFEM_FFT_SPLIT);
+                       kFftSplit);
     mark(6, 1);
     return;
   }
@@ -1623,7 +1609,7 @@ int batch_setup(pmfem_batch* b, int32_t spmv_lanes) {
     t.lpb = std::max(1, 2048 / g.M[0]);
     t.by = std::max(1, std::min(16, 4096 / g.M[1]));
     if (d->fft_ok) {
-      nxy[c] = (int64_t)g.N[2] * PMFEM_FFT_SPLIT;
+      nxy[c] = (int64_t)g.N[2] * kFftSplit;
       nr2c[c] = nfy[c] = 0;
       b->lds_plane = std::max(b->lds_plane, d->fft_plane_lds);
     } else {
@@ -1634,7 +1620,7 @@ int batch_setup(pmfem_batch* b, int32_t spmv_lanes) {
       b->lds_r2c = std::max(b->lds_r2c, (size_t)(g.M[0] / 2 + t.lpb * g.M[0]) * sizeof(float2));
       b->lds_fy = std::max(b->lds_fy, (size_t)(g.M[1] / 2 + t.by * g.M[1]) * sizeof(float2));
     }
-    b->Bz = std::min(b->Bz, std::max(1, std::min(PMFEM_FFTZ_B, 4096 / g.M[2])));
+    b->Bz = std::min(b->Bz, std::max(1, std::min(kFftzB, 4096 / g.M[2])));
     nic[c] = (int64_t)ipl.nsx * g.nbox[1] * ipl.nsz;
     b->lds_sc = std::max(b->lds_sc, (size_t)d->sp.lds_bytes);
     b->lds_ic = std::max(b->lds_ic, (size_t)ipl.lds_bytes);
@@ -1744,18 +1730,18 @@ int batch_heff(pmfem_batch* b, const float* m, float* h, uint32_t terms) {
     // per-axis passes; the z pass with the K multiply serves both
     if (b->xy.blocks)
       hipLaunchKernelGGL(k_fft_xy_fwd_cells, dim3(b->xy.blocks), dim3(1024), b->lds_plane, s, tab,
-                         (const int32_t*)b->xy.bcell, (const int32_t*)b->xy.boff, PMFEM_FFT_SPLIT);
+                         (const int32_t*)b->xy.bcell, (const int32_t*)b->xy.boff, kFftSplit);
     if (b->r2c.blocks) {
       hipLaunchKernelGGL(k_r2c_x_cells, dim3(b->r2c.blocks), dim3(T), b->lds_r2c, s, tab,
                          (const int32_t*)b->r2c.bcell, (const int32_t*)b->r2c.boff);
       hipLaunchKernelGGL(k_fft_y_cells, dim3(b->fy.blocks), dim3(T), b->lds_fy, s, tab,
                          (const int32_t*)b->fy.bcell, (const int32_t*)b->fy.boff, 0);
     }
-    hipLaunchKernelGGL(k_fft_z_mul_cells, dim3(b->zm.blocks), dim3(PMFEM_FFTZ_T), b->lds_z, s, tab,
+    hipLaunchKernelGGL(k_fft_z_mul_cells, dim3(b->zm.blocks), dim3(kFftzT), b->lds_z, s, tab,
                        (const int32_t*)b->zm.bcell, (const int32_t*)b->zm.boff, b->Bz);
     if (b->yx.blocks)
       hipLaunchKernelGGL(k_fft_yx_inv_cells, dim3(b->yx.blocks), dim3(1024), b->lds_plane, s, tab,
-                         (const int32_t*)b->yx.bcell, (const int32_t*)b->yx.boff, PMFEM_FFT_SPLIT);
+                         (const int32_t*)b->yx.bcell, (const int32_t*)b->yx.boff, kFftSplit);
     if (b->r2c.blocks) {
       hipLaunchKernelGGL(k_fft_y_cells, dim3(b->fy.blocks), dim3(T), b->lds_fy, s, tab,
                          (const int32_t*)b->fy.bcell, (const int32_t*)b->fy.boff, 1);

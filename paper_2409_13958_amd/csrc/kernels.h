@@ -119,12 +119,9 @@ __global__ void k_fft_z_mul(GridParams g, float2* spec, const float* khat, const
 __global__ void k_c2r_x(GridParams g, const float2* spec, float* U, const float2* twx,
                         int lines_per_block);
 
-#ifndef PMFEM_IC_LANES
-#define PMFEM_IC_LANES 8
-#endif
 // lanes per observer row of k_interp_tile (8 x 16 B = one 128 B line per
-// load); 4, 8 or 16
-constexpr int kIcLanes = PMFEM_IC_LANES;
+// load; 4 and 16 measured slower)
+constexpr int kIcLanes = 8;
 // WT = 2 r_b + 1 runs per row; KC = 4-value chunks per lane held in registers
 template <int WT, int KC>
 __global__ void k_interp_tile(GridParams g, IcPlan pl, const float* U, const float4* pos4,

@@ -1252,10 +1252,7 @@ __global__ void __launch_bounds__(256) k_c2r_x_cells(const CellTab* __restrict__
 
 // five waves per SIMD (at most 96 registers) where the row state fits them
 // without spilling, else four
-#ifndef PMFEM_IC_WAVES
-#define PMFEM_IC_WAVES (WT * KC <= 30 ? 5 : 4)
-#endif
-#define PMFEM_IC_OCC __attribute__((amdgpu_waves_per_eu(PMFEM_IC_WAVES)))
+#define PMFEM_IC_OCC __attribute__((amdgpu_waves_per_eu(WT * KC <= 30 ? 5 : 4)))
 template <int WT, int KC>
 __device__ __forceinline__ void interp_tile_body(
     GridParams g, IcPlan pl, const float* __restrict__ U, const float4* __restrict__ pos4,
