@@ -46,7 +46,7 @@ typedef enum {
   PMFEM_EINVAL = -1,  /* bad argument or material value                    */
   PMFEM_EMESH = -2,   /* invalid mesh (index out of range, volume <= 0)      */
   PMFEM_EPBC = -3,    /* periodic images inside one tetrahedron (too coarse) */
-  PMFEM_EGRID = -4,   /* AIM grid unusable (too short, not a power of two)  */
+  PMFEM_EGRID = -4,   /* AIM grid unusable (too short, FFT extent not 2,3,5,7-smooth) */
   PMFEM_ENOMEM = -5,  /* host or device allocation failed                   */
   PMFEM_EHIP = -6,    /* HIP runtime error                                  */
   PMFEM_ESTATE = -7,  /* call out of order (e.g. heff before build)         */
@@ -107,8 +107,10 @@ int pmfem_set_periodicity(pmfem_ctx* ctx, uint32_t axis_mask, const double L[3],
  * values are EINVAL at pmfem_build. pmfem_grid_convolve always takes and
  * returns FP32 grids. On a periodic axis the
  * grid spacing is L/N and the FFT extent is N; on a non-periodic axis the
- * grid spans the mesh and the FFT extent is 2N. FFT extents must be powers
- * of two in [4, 512]; periodic axes need N >= 2 (r_b + p) + 1.
+ * grid spans the mesh and the FFT extent is 2N. FFT extents must be
+ * products of the factors 2, 3, 5 and 7 in [4, 512] (powers of two take the
+ * radix-2 passes, with whole z-planes in LDS where they fit; the others the
+ * mixed-radix per-axis passes); periodic axes need N >= 2 (r_b + p) + 1.
  */
 int pmfem_set_aim(pmfem_ctx* ctx, const int32_t grid[3], int32_t order_p, int32_t near_boxes,
                   double z0_radius_edges, int32_t precision);

@@ -58,6 +58,8 @@ struct pmfem_dev {
   bool ic_small_ok = false;
   bool ic_seg = false;        // false: the narrow tiles
   bool fft_plane = false;  // x and y transforms of a whole z-plane in one kernel
+  bool fft_mr = false;     // an FFT extent is not a power of two: mixed-radix passes
+  float2 *twfx = nullptr, *twfy = nullptr, *twfz = nullptr;  // full-circle twiddles (mixed radix)
   size_t fft_plane_lds = 0;
   const char* kname[12] = {};  // kernel in each profiling slot
   hipStream_t side = nullptr;   // second stream: element correction beside the grid steps
@@ -399,10 +401,14 @@ bool plan_scatter_with(const HostOps& o, ScPlan& pl, std::vector<int2>& list,
   auto start = [&](int a, int b) {
     return o.per[a] ? b - shift : std::min(std::max(b - shift, 0), o.N[a] - p - 1);
   };
-  for (int a = 0; a < 3; ++a) {
+  // one axis: tiles of the preferred size, or (div) the smallest size that
+  // divides a periodic axis; false if a grid index would lie in three
+  // footprints or a footprint would wrap onto itself
+  auto plan_axis = [&](int a, bool div) -> bool {
     int tb = std::max(want[a], p + 1);
     if (o.per[a]) tb = std::min(tb, o.N[a] - p);
-    if (divisors && o.per[a]) {
+    if (div) {
+      if (!o.per[a]) return false;
       tb = std::max(want[a], p + 1);
       while (tb <= o.N[a] - p && o.nbox[a] % tb != 0) ++tb;
       if (tb > o.N[a] - p) return false;
@@ -429,7 +435,10 @@ bool plan_scatter_with(const HostOps& o, ScPlan& pl, std::vector<int2>& list,
       }
     }
     pl.fd[a] = fd;
-  }
+    return true;
+  };
+  for (int a = 0; a < 3; ++a)
+    if (!plan_axis(a, divisors) && !(!divisors && plan_axis(a, true))) return false;
   pl.fsize = pl.fd[0] * pl.fd[1] * pl.fd[2];
   const int nbx = o.nbox[0], nby = o.nbox[1];
   const std::vector<int32_t>& bs = o.box_start;
@@ -642,15 +651,17 @@ int upload_all(pmfem_ctx* c) {
     if ((rc = upload(c, &L.rdesc, rdesc.data(), rdesc.size()))) return rc;
   }
 
+  for (int a = 0; a < 3; ++a)
+    if (o.M[a] & (o.M[a] - 1)) d->fft_mr = true;
   {
     // whole-plane x/y transforms when a plane (row pairs + half-spectrum
-    // columns) fits in one workgroup's LDS
+    // columns) fits in one workgroup's LDS (radix-2 extents only)
     const int Mx = o.M[0], My = o.M[1], Hx = Mx / 2 + 1, pairs = (o.N[1] + 1) / 2;
     d->fft_plane_lds =
         (size_t)(Mx / 2 + My / 2 + (size_t)pairs * Mx + (size_t)Hx * (My + 1)) * sizeof(float2);
     int max_lds = 0;
     (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
-    d->fft_ok = d->fft_plane_lds <= (size_t)max_lds;
+    d->fft_ok = !d->fft_mr && d->fft_plane_lds <= (size_t)max_lds;
     if (d->fft_ok && d->fft_plane_lds > 65536) {
       const int b = (int)d->fft_plane_lds;
       d->fft_ok =
@@ -805,6 +816,20 @@ int upload_all(pmfem_ctx* c) {
   if ((rc = upload(c, &d->twx, tx.data(), tx.size()))) return rc;
   if ((rc = upload(c, &d->twy, ty.data(), ty.size()))) return rc;
   if ((rc = upload(c, &d->twz, tz.data(), tz.size()))) return rc;
+  if (d->fft_mr) {
+    auto full = [](int n) {
+      std::vector<float2> t(n);
+      for (int k = 0; k < n; ++k) {
+        const double a = -2.0 * kPi * k / n;
+        t[k] = make_float2((float)std::cos(a), (float)std::sin(a));
+      }
+      return t;
+    };
+    auto fx = full(o.M[0]), fy = full(o.M[1]), fz = full(o.M[2]);
+    if ((rc = upload(c, &d->twfx, fx.data(), fx.size()))) return rc;
+    if ((rc = upload(c, &d->twfy, fy.data(), fy.size()))) return rc;
+    if ((rc = upload(c, &d->twfz, fz.data(), fz.size()))) return rc;
+  }
   if ((rc = upload(c, &d->mu, o.mu.data(), n))) return rc;
   if ((rc = dalloc(c, &d->hex, 3 * n))) return rc;
   if ((rc = dalloc(c, &d->q, n))) return rc;
@@ -854,6 +879,38 @@ void convolve(pmfem_dev* d, hipStream_t s, const float* Qg, float* Ug, float2* s
     hipLaunchKernelGGL(k_fft_yx_inv, dim3((unsigned)(g.N[2] * kFftSplit)), dim3(1024),
                        d->fft_plane_lds, s, g, (const float2*)spec, Ug, d->twx, d->twy,
                        kFftSplit);
+    mark(6, 1);
+    return;
+  }
+  if (d->fft_mr) {
+    // mixed-radix passes: twiddle table and two line buffers in LDS
+    const int lpb = std::max(1, 2048 / Mx);
+    const int64_t xlines = (int64_t)((g.N[1] + 1) / 2) * g.N[2];
+    const int By = std::max(1, std::min(16, 2048 / My));
+    const int gy = (Hx + By - 1) / By;
+    const int Bzm = std::max(1, std::min(kFftzB, 2048 / Mz));
+    mark(2, 0);
+    hipLaunchKernelGGL(k_r2c_x_mr, dim3((unsigned)((xlines + lpb - 1) / lpb)), dim3(T),
+                       (size_t)(Mx + 2 * lpb * Mx) * sizeof(float2), s, g, Qg, spec, d->twfx, lpb);
+    mark(2, 1);
+    mark(3, 0);
+    hipLaunchKernelGGL(k_fft_y_mr, dim3((unsigned)(g.N[2] * gy)), dim3(T),
+                       (size_t)(My + 2 * By * My) * sizeof(float2), s, g, spec, d->twfy, By, 0,
+                       g.N[1], My);
+    mark(3, 1);
+    mark(4, 0);
+    hipLaunchKernelGGL(k_fft_z_mul_mr, dim3((unsigned)((cols + Bzm - 1) / Bzm)), dim3(kFftzT),
+                       (size_t)(Mz + 2 * Bzm * Mz) * sizeof(float2), s, g, spec, d->khat, d->twfz,
+                       Bzm);
+    mark(4, 1);
+    mark(5, 0);
+    hipLaunchKernelGGL(k_fft_y_mr, dim3((unsigned)(g.N[2] * gy)), dim3(T),
+                       (size_t)(My + 2 * By * My) * sizeof(float2), s, g, spec, d->twfy, By, 1,
+                       My, g.N[1]);
+    mark(5, 1);
+    mark(6, 0);
+    hipLaunchKernelGGL(k_c2r_x_mr, dim3((unsigned)((xlines + lpb - 1) / lpb)), dim3(T),
+                       (size_t)(Mx + 2 * lpb * Mx) * sizeof(float2), s, g, spec, Ug, d->twfx, lpb);
     mark(6, 1);
     return;
   }
@@ -1572,6 +1629,8 @@ int batch_setup(pmfem_batch* b, int32_t spmv_lanes) {
       return batch_err(b, PMFEM_EINVAL, "cells of a batch must share the Lagrange order and near radius");
     if (!d->sc_ok || (!d->ic_ok && !d->ic_small_ok))
       return batch_err(b, PMFEM_EINVAL, "a cell does not fit the batched kernel forms");
+    if (d->fft_mr)
+      return batch_err(b, PMFEM_EINVAL, "batched cells need power-of-two FFT extents");
     CellTab& t = tab[c];
     t.g = d->g;
     t.sp = d->sp;

@@ -1,7 +1,10 @@
 // FP64 complex 3D FFT on the host, used once per build to take the
-// spectrum of the sampled periodic Green's function. Iterative radix-2
-// decimation in time along each axis; extents are powers of two.
+// spectrum of the sampled periodic Green's function. Mixed radix: each
+// extent is a product of the factors 2, 3, 5 and 7; a transform of length
+// n = r m splits into r interleaved transforms of length m (decimation in
+// time) whose outputs are combined by r-point DFTs with twiddles.
 #include <cmath>
+#include <complex>
 #include <vector>
 
 #include "internal.h"
@@ -9,29 +12,30 @@
 namespace pmfem {
 namespace {
 
-void fft1(double* re, double* im, int n, const std::vector<double>& cr,
-          const std::vector<double>& ci) {
-  for (int i = 1, j = 0; i < n; ++i) {  // bit reversal
-    int bit = n >> 1;
-    for (; j & bit; bit >>= 1) j ^= bit;
-    j ^= bit;
-    if (i < j) {
-      std::swap(re[i], re[j]);
-      std::swap(im[i], im[j]);
-    }
+using cplx = std::complex<double>;
+
+int first_factor(int n) {
+  for (int r : {4, 2, 3, 5, 7})
+    if (n % r == 0) return r;
+  return n;  // a prime beyond 7: the direct DFT below
+}
+
+// out[k] = sum_j in[j s] w^(j k), w = exp(-2 pi i / n), k < n
+void fft_rec(const cplx* in, int64_t s, cplx* out, int n, const std::vector<cplx>& w, int wstep) {
+  if (n == 1) {
+    out[0] = in[0];
+    return;
   }
-  for (int len = 2; len <= n; len <<= 1) {
-    int half = len >> 1, step = n / len;
-    for (int s = 0; s < n; s += len)
-      for (int k = 0; k < half; ++k) {
-        double wr = cr[k * step], wi = ci[k * step];
-        double xr = re[s + k + half], xi = im[s + k + half];
-        double tr = xr * wr - xi * wi, ti = xr * wi + xi * wr;
-        re[s + k + half] = re[s + k] - tr;
-        im[s + k + half] = im[s + k] - ti;
-        re[s + k] += tr;
-        im[s + k] += ti;
-      }
+  const int r = first_factor(n), m = n / r;
+  for (int q = 0; q < r; ++q) fft_rec(in + q * s, s * r, out + (int64_t)q * m, m, w, wstep * r);
+  std::vector<cplx> t(r);
+  for (int k = 0; k < m; ++k) {
+    for (int q = 0; q < r; ++q) t[q] = out[(int64_t)q * m + k] * w[((int64_t)q * k * wstep) % ((int64_t)n * wstep)];
+    for (int p = 0; p < r; ++p) {
+      cplx acc = 0.0;
+      for (int q = 0; q < r; ++q) acc += t[q] * w[((int64_t)q * p * m * wstep) % ((int64_t)n * wstep)];
+      out[(int64_t)p * m + k] = acc;
+    }
   }
 }
 
@@ -41,26 +45,21 @@ void fft3_inplace(std::vector<double>& re, std::vector<double>& im, const int M[
   const int64_t sx = 1, sy = M[0], sz = (int64_t)M[0] * M[1];
   const int64_t strides[3] = {sx, sy, sz};
   for (int ax = 0; ax < 3; ++ax) {
-    int n = M[ax];
-    std::vector<double> cr(n / 2 + 1), ci(n / 2 + 1);
-    for (int k = 0; k <= n / 2; ++k) {
-      cr[k] = std::cos(2.0 * kPi * k / n);
-      ci[k] = -std::sin(2.0 * kPi * k / n);
-    }
+    const int n = M[ax];
+    // w[t] = exp(-2 pi i t / n), t < n
+    std::vector<cplx> w(n);
+    for (int t = 0; t < n; ++t) w[t] = std::polar(1.0, -2.0 * kPi * t / n);
     int o1 = (ax + 1) % 3, o2 = (ax + 2) % 3;
     int64_t lines = (int64_t)M[o1] * M[o2];
     parallel_for(lines, [&](int64_t l) {
       int64_t i1 = l % M[o1], i2 = l / M[o1];
       int64_t base = i1 * strides[o1] + i2 * strides[o2];
-      std::vector<double> br(n), bi(n);
+      std::vector<cplx> in(n), out(n);
+      for (int k = 0; k < n; ++k) in[k] = cplx(re[base + k * strides[ax]], im[base + k * strides[ax]]);
+      fft_rec(in.data(), 1, out.data(), n, w, 1);
       for (int k = 0; k < n; ++k) {
-        br[k] = re[base + k * strides[ax]];
-        bi[k] = im[base + k * strides[ax]];
-      }
-      fft1(br.data(), bi.data(), n, cr, ci);
-      for (int k = 0; k < n; ++k) {
-        re[base + k * strides[ax]] = br[k];
-        im[base + k * strides[ax]] = bi[k];
+        re[base + k * strides[ax]] = out[k].real();
+        im[base + k * strides[ax]] = out[k].imag();
       }
     }, 16);
   }

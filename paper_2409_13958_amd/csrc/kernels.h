@@ -118,6 +118,16 @@ __global__ void k_fft_z_mul(GridParams g, float2* spec, const float* khat, const
                             int B);
 __global__ void k_c2r_x(GridParams g, const float2* spec, float* U, const float2* twx,
                         int lines_per_block);
+// mixed-radix forms (extents that are products of 2, 3, 5, 7); twf[t] =
+// exp(-2 pi i t / M) for t < M; dynamic LDS: (M + 2 lines M) complex values
+__global__ void k_r2c_x_mr(GridParams g, const float* Q, float2* spec, const float2* twf,
+                           int lines_per_block);
+__global__ void k_fft_y_mr(GridParams g, float2* spec, const float2* twf, int B, int inverse,
+                           int n_in, int n_out);
+__global__ void k_fft_z_mul_mr(GridParams g, float2* spec, const float* khat, const float2* twf,
+                               int B);
+__global__ void k_c2r_x_mr(GridParams g, const float2* spec, float* U, const float2* twf,
+                           int lines_per_block);
 
 // lanes per observer row of k_interp_tile (8 x 16 B = one 128 B line per
 // load; 4 and 16 measured slower)

@@ -1229,6 +1229,272 @@ __global__ void __launch_bounds__(256) k_c2r_x_cells(const CellTab* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Mixed-radix FFT passes (extents that are products of 2, 3, 5 and 7):
+// Stockham autosort in LDS, natural order in and out, ping-pong between two
+// buffers, radices 4, 2, 3, 5, 7 taken in that order of preference. Pass
+// with Ns = product of the radices done so far and radix R: element j of
+// the n/R groups reads a_q = src[j + q n/R], q < R, multiplies a_q by the
+// twiddle w^(q k) with k = j mod Ns and w = exp(-2 pi i / (Ns R)) (conjugated
+// for the inverse), forms the R-point DFT b_p = sum_q a_q exp(-2 pi i q p / R)
+// and writes b_p to dst[(j / Ns) Ns R + k + p Ns]. tw[t] = exp(-2 pi i t / n).
+
+__device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// R-point DFT in place, sign +1 forward (exp(-i ...)), -1 inverse
+template <int R>
+__device__ __forceinline__ void dft_small(float2* v, float sign) {
+  // cos and sin of 2 pi m / R, m < R
+  float c[R], sn[R];
+  if constexpr (R == 2) {
+    c[0] = 1.f; sn[0] = 0.f; c[1] = -1.f; sn[1] = 0.f;
+  } else if constexpr (R == 3) {
+    c[0] = 1.f; sn[0] = 0.f;
+    c[1] = -0.5f; sn[1] = 0.86602540378443865f;
+    c[2] = -0.5f; sn[2] = -0.86602540378443865f;
+  } else if constexpr (R == 4) {
+    c[0] = 1.f; sn[0] = 0.f; c[1] = 0.f; sn[1] = 1.f;
+    c[2] = -1.f; sn[2] = 0.f; c[3] = 0.f; sn[3] = -1.f;
+  } else if constexpr (R == 5) {
+    c[0] = 1.f; sn[0] = 0.f;
+    c[1] = 0.30901699437494742f; sn[1] = 0.95105651629515357f;
+    c[2] = -0.80901699437494742f; sn[2] = 0.58778525229247313f;
+    c[3] = -0.80901699437494742f; sn[3] = -0.58778525229247313f;
+    c[4] = 0.30901699437494742f; sn[4] = -0.95105651629515357f;
+  } else {
+    c[0] = 1.f; sn[0] = 0.f;
+    c[1] = 0.62348980185873353f; sn[1] = 0.78183148246802981f;
+    c[2] = -0.22252093395631440f; sn[2] = 0.97492791218182361f;
+    c[3] = -0.90096886790241913f; sn[3] = 0.43388373911755812f;
+    c[4] = -0.90096886790241913f; sn[4] = -0.43388373911755812f;
+    c[5] = -0.22252093395631440f; sn[5] = -0.97492791218182361f;
+    c[6] = 0.62348980185873353f; sn[6] = -0.78183148246802981f;
+  }
+  float2 out[R];
+#pragma unroll
+  for (int p = 0; p < R; ++p) {
+    float2 acc = v[0];
+#pragma unroll
+    for (int q = 1; q < R; ++q) {
+      const int m = (q * p) % R;
+      // exp(-i sign 2 pi m / R)
+      const float2 w = make_float2(c[m], -sign * sn[m]);
+      const float2 t = cmulf(v[q], w);
+      acc.x += t.x;
+      acc.y += t.y;
+    }
+    out[p] = acc;
+  }
+#pragma unroll
+  for (int p = 0; p < R; ++p) v[p] = out[p];
+}
+
+template <int R>
+__device__ __forceinline__ void stockham_pass(const float2* src, float2* dst, int n, int Ns,
+                                              int lines, int ld, const float2* tw, float sign) {
+  const int nR = n / R, step = n / (Ns * R);
+  const int total = lines * nR;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int line = idx / nR, j = idx - line * nR;
+    const float2* s = src + line * ld;
+    float2* d = dst + line * ld;
+    const int k = j % Ns;
+    float2 v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = s[j + q * nR];
+#pragma unroll
+    for (int q = 1; q < R; ++q) {
+      float2 w = tw[q * k * step];  // q k step < n
+      w.y *= sign;
+      v[q] = cmulf(v[q], w);
+    }
+    dft_small<R>(v, sign);
+    const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+    for (int p = 0; p < R; ++p) d[base + p * Ns] = v[p];
+  }
+}
+
+// lines of length n, line stride ld, in a; returns the buffer (a or b)
+// holding the transform
+__device__ float2* lds_fft_mr(float2* a, float2* b, int n, int lines, int ld, const float2* tw,
+                              float sign) {
+  int Ns = 1;
+  while (Ns < n) {
+    const int rem = n / Ns;
+    if (rem % 4 == 0) {
+      stockham_pass<4>(a, b, n, Ns, lines, ld, tw, sign);
+      Ns *= 4;
+    } else if (rem % 2 == 0) {
+      stockham_pass<2>(a, b, n, Ns, lines, ld, tw, sign);
+      Ns *= 2;
+    } else if (rem % 3 == 0) {
+      stockham_pass<3>(a, b, n, Ns, lines, ld, tw, sign);
+      Ns *= 3;
+    } else if (rem % 5 == 0) {
+      stockham_pass<5>(a, b, n, Ns, lines, ld, tw, sign);
+      Ns *= 5;
+    } else {
+      stockham_pass<7>(a, b, n, Ns, lines, ld, tw, sign);
+      Ns *= 7;
+    }
+    __syncthreads();
+    float2* t = a;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+// R2C along x, mixed radix: as k_r2c_x (pairs of real rows y, y + 1 as one
+// complex line, half spectrum of each), LDS: twiddles [Mx], two line buffers.
+__global__ void __launch_bounds__(256) k_r2c_x_mr(GridParams g, const float* __restrict__ Q,
+                                                  float2* __restrict__ spec,
+                                                  const float2* __restrict__ twf,
+                                                  int lines_per_block) {
+  extern __shared__ float2 sh[];
+  const int Mx = g.M[0], Hx = Mx / 2 + 1;
+  float2* tw = sh;
+  float2* A = sh + Mx;
+  float2* Bf = A + lines_per_block * Mx;
+  for (int i = threadIdx.x; i < Mx; i += blockDim.x) tw[i] = twf[i];
+  const int pairs = (g.N[1] + 1) / 2;
+  const int64_t total_lines = (int64_t)pairs * g.N[2];
+  const int64_t l0 = (int64_t)blockIdx.x * lines_per_block;
+  const int nl = (int)((total_lines - l0) < lines_per_block ? (total_lines - l0) : lines_per_block);
+  for (int idx = threadIdx.x; idx < nl * Mx; idx += blockDim.x) {
+    const int li = idx / Mx, x = idx - li * Mx;
+    const int64_t L = l0 + li;
+    const int z = (int)(L / pairs), y = 2 * (int)(L % pairs);
+    float re = 0.f, im = 0.f;
+    if (x < g.N[0]) {
+      re = grid_load(Q, ((int64_t)z * g.N[1] + y) * g.N[0] + x, g);
+      if (y + 1 < g.N[1]) im = grid_load(Q, ((int64_t)z * g.N[1] + y + 1) * g.N[0] + x, g);
+    }
+    A[li * Mx + x] = make_float2(re, im);
+  }
+  __syncthreads();
+  const float2* R = lds_fft_mr(A, Bf, Mx, nl, Mx, tw, 1.0f);
+  for (int idx = threadIdx.x; idx < nl * Hx; idx += blockDim.x) {
+    const int li = idx / Hx, k = idx - li * Hx;
+    const int64_t L = l0 + li;
+    const int z = (int)(L / pairs), y = 2 * (int)(L % pairs);
+    const float2 a = R[li * Mx + k];
+    const float2 b = R[li * Mx + (k == 0 ? 0 : Mx - k)];
+    // X_y = (Z[k] + conj Z[-k]) / 2, X_{y+1} = (Z[k] - conj Z[-k]) / (2i)
+    spec[((int64_t)z * g.M[1] + y) * Hx + k] = make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y));
+    if (y + 1 < g.N[1])
+      spec[((int64_t)z * g.M[1] + y + 1) * Hx + k] =
+          make_float2(0.5f * (a.y + b.y), -0.5f * (a.x - b.x));
+  }
+}
+
+// FFT along y, mixed radix, as k_fft_y (B columns kx per block)
+__global__ void __launch_bounds__(256) k_fft_y_mr(GridParams g, float2* __restrict__ spec,
+                                                  const float2* __restrict__ twf, int B,
+                                                  int inverse, int n_in, int n_out) {
+  extern __shared__ float2 sh[];
+  const int My = g.M[1], Hx = g.M[0] / 2 + 1;
+  float2* tw = sh;
+  float2* A = sh + My;
+  float2* Bf = A + B * My;
+  for (int i = threadIdx.x; i < My; i += blockDim.x) tw[i] = twf[i];
+  const int groups_per_plane = (Hx + B - 1) / B;
+  const int z = blockIdx.x / groups_per_plane;
+  const int kx0 = (blockIdx.x - z * groups_per_plane) * B;
+  const int nb = (Hx - kx0) < B ? (Hx - kx0) : B;
+  for (int idx = threadIdx.x; idx < nb * My; idx += blockDim.x) {
+    const int y = idx / nb, li = idx - y * nb;
+    float2 v = make_float2(0.f, 0.f);
+    if (y < n_in) v = spec[((int64_t)z * My + y) * Hx + kx0 + li];
+    A[li * My + y] = v;
+  }
+  __syncthreads();
+  const float2* R = lds_fft_mr(A, Bf, My, nb, My, tw, inverse ? -1.0f : 1.0f);
+  for (int idx = threadIdx.x; idx < nb * n_out; idx += blockDim.x) {
+    const int y = idx / nb, li = idx - y * nb;
+    spec[((int64_t)z * My + y) * Hx + kx0 + li] = R[li * My + y];
+  }
+}
+
+// FFT along z, K multiply, inverse FFT along z, mixed radix, as k_fft_z_mul
+__global__ void __launch_bounds__(256) k_fft_z_mul_mr(GridParams g, float2* __restrict__ spec,
+                                                      const float* __restrict__ khat,
+                                                      const float2* __restrict__ twf, int B) {
+  extern __shared__ float2 sh[];
+  const int Mz = g.M[2], Hx = g.M[0] / 2 + 1;
+  const int64_t plane = (int64_t)g.M[1] * Hx;
+  float2* tw = sh;
+  float2* A = sh + Mz;
+  float2* Bf = A + B * Mz;
+  for (int i = threadIdx.x; i < Mz; i += blockDim.x) tw[i] = twf[i];
+  const int64_t c0 = (int64_t)blockIdx.x * B;
+  const int nb = (int)((plane - c0) < B ? (plane - c0) : B);
+  for (int idx = threadIdx.x; idx < nb * Mz; idx += blockDim.x) {
+    const int z = idx / nb, li = idx - z * nb;
+    A[li * Mz + z] = z < g.N[2] ? spec[(int64_t)z * plane + c0 + li] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  float2* F = lds_fft_mr(A, Bf, Mz, nb, Mz, tw, 1.0f);
+  float2* other = F == A ? Bf : A;
+  for (int idx = threadIdx.x; idx < nb * Mz; idx += blockDim.x) {
+    const int kz = idx / nb, li = idx - kz * nb;
+    const float kk = khat[(int64_t)kz * plane + c0 + li];
+    const float2 v = F[li * Mz + kz];
+    F[li * Mz + kz] = make_float2(v.x * kk, v.y * kk);  // same element, same thread
+  }
+  __syncthreads();
+  const float2* R = lds_fft_mr(F, other, Mz, nb, Mz, tw, -1.0f);
+  for (int idx = threadIdx.x; idx < nb * g.N[2]; idx += blockDim.x) {
+    const int z = idx / nb, li = idx - z * nb;
+    spec[(int64_t)z * plane + c0 + li] = R[li * Mz + z];
+  }
+}
+
+// C2R along x, mixed radix, as k_c2r_x
+__global__ void __launch_bounds__(256) k_c2r_x_mr(GridParams g, const float2* __restrict__ spec,
+                                                  float* __restrict__ U,
+                                                  const float2* __restrict__ twf,
+                                                  int lines_per_block) {
+  extern __shared__ float2 sh[];
+  const int Mx = g.M[0], Hx = Mx / 2 + 1;
+  float2* tw = sh;
+  float2* A = sh + Mx;
+  float2* Bf = A + lines_per_block * Mx;
+  for (int i = threadIdx.x; i < Mx; i += blockDim.x) tw[i] = twf[i];
+  const int pairs = (g.N[1] + 1) / 2;
+  const int64_t total_lines = (int64_t)pairs * g.N[2];
+  const int64_t l0 = (int64_t)blockIdx.x * lines_per_block;
+  const int nl = (int)((total_lines - l0) < lines_per_block ? (total_lines - l0) : lines_per_block);
+  for (int idx = threadIdx.x; idx < nl * Mx; idx += blockDim.x) {
+    const int li = idx / Mx, k = idx - li * Mx;
+    const int64_t L = l0 + li;
+    const int z = (int)(L / pairs), y = 2 * (int)(L % pairs);
+    const int kk = k < Hx ? k : Mx - k;
+    float2 a = spec[((int64_t)z * g.M[1] + y) * Hx + kk];
+    float2 b = make_float2(0.f, 0.f);
+    if (y + 1 < g.N[1]) b = spec[((int64_t)z * g.M[1] + y + 1) * Hx + kk];
+    if (k >= Hx) {
+      a.y = -a.y;
+      b.y = -b.y;
+    }
+    // Z = X_y + i X_{y+1}
+    A[li * Mx + k] = make_float2(a.x - b.y, a.y + b.x);
+  }
+  __syncthreads();
+  const float2* R = lds_fft_mr(A, Bf, Mx, nl, Mx, tw, -1.0f);
+  for (int idx = threadIdx.x; idx < nl * g.N[0]; idx += blockDim.x) {
+    const int li = idx / g.N[0], x = idx - li * g.N[0];
+    const int64_t L = l0 + li;
+    const int z = (int)(L / pairs), y = 2 * (int)(L % pairs);
+    const float2 v = R[li * Mx + x];
+    grid_store(U, ((int64_t)z * g.N[1] + y) * g.N[0] + x, v.x, g);
+    if (y + 1 < g.N[1]) grid_store(U, ((int64_t)z * g.N[1] + y + 1) * g.N[0] + x, v.y, g);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // interpolation + precorrection (steps 3 and 4), tile form. A workgroup
 // takes the observer boxes x in [x0, x0 + xs), y = by, z in [z0, z0 + tz).
 // Every source box their near regions touch lies in the block

@@ -85,7 +85,13 @@ int fail(pmfem_ctx* c, int code, const std::string& m) {
   return code;
 }
 
-bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+// a product of the factors 2, 3, 5 and 7 (the radices of the FFT passes)
+bool is_smooth7(int v) {
+  if (v < 1) return false;
+  for (int r : {2, 3, 5, 7})
+    while (v % r == 0) v /= r;
+  return v == 1;
+}
 
 }  // namespace
 
@@ -252,8 +258,8 @@ int host_build(pmfem_ctx* c) {
     o.M[a] = o.per[a] ? o.N[a] : 2 * o.N[a];
     o.nbox[a] = o.per[a] ? o.N[a] : o.N[a] - 1;
     if (o.N[a] < p + 1) return fail(c, PMFEM_EGRID, "grid axis shorter than the stencil");
-    if (!is_pow2(o.M[a]) || o.M[a] < 4 || o.M[a] > 512)
-      return fail(c, PMFEM_EGRID, "FFT extent must be a power of two in [4, 512]");
+    if (!is_smooth7(o.M[a]) || o.M[a] < 4 || o.M[a] > 512)
+      return fail(c, PMFEM_EGRID, "FFT extent must be a product of 2, 3, 5 and 7 in [4, 512]");
     if (o.per[a] && o.N[a] < 2 * (rb + p) + 1)
       return fail(c, PMFEM_EGRID, "periodic grid axis too short for the near region");
     if (o.per[a]) {

@@ -202,3 +202,61 @@ def test_film_llg_trajectory_against_oracle():
     # FP32 fields in an FP64 trajectory: about 5e-8 measured
     assert err < 1e-6
     assert np.allclose(np.linalg.norm(got, axis=1), 1.0, atol=1e-13)
+
+
+# FFT extents that are products of 2, 3, 5 and 7 but not powers of two take
+# the mixed-radix per-axis passes (the plane form needs powers of two)
+MIXED = {
+    "film_12x20x6": lambda: mg.kuhn_box((6, 5, 2), 1e-9, periodic=0b011, jitter=0.2,
+                                        grid=(12, 20, 6)),
+    "box3d_15x14x21": lambda: mg.kuhn_box((5, 6, 5), 1e-9, periodic=0b111, jitter=0.2,
+                                          grid=(15, 14, 21)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MIXED))
+def test_heff_parity_mixed_radix(name):
+    prob = MIXED[name]()
+    print(f"[gpu parity] {name} nodes={prob.n_nodes}", flush=True)
+    orc = model.Oracle(prob)
+    m = orc.unknown_values(prob.m)
+    ref = dict(h=orc.heff(m, method="aim"), hms=orc.heff(m, method="aim", terms=("ms",)),
+               u=orc.potential(m, None, "aim"))
+    tried = 0
+    for anterp in (0, 1, 2, 3):
+        ctx = B.Context.from_problem(prob, device=0)
+        try:
+            ctx.set_variant("anterp", anterp)
+        except B.PmfemError:
+            continue                     # this form's plan does not fit the grid
+        tried += 1
+        n, uon, nou, _ = ctx.query()
+        mt = torch.tensor(prob.m[nou], dtype=torch.float32, device="cuda")
+        h, hms, u = torch.empty_like(mt), torch.empty_like(mt), torch.empty(n, device="cuda")
+        ctx.heff_parts(mt, h, None, u, None)
+        ctx.heff(mt, hms, terms=B.TERM_MS)
+        torch.cuda.synchronize()
+        perm = orc.uk[nou]
+        got = dict(h=h, hms=hms, u=u)
+        errs = {k: rel(got[k].cpu().numpy().astype(np.float64), r[perm]) for k, r in ref.items()}
+        print(f"[gpu parity] {name} anterp={anterp} rel L2: "
+              + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+        for k, v in errs.items():
+            assert v <= TOL, (anterp, k, v)
+    assert tried >= 2
+
+
+@pytest.mark.parametrize("case", sorted(MIXED))
+def test_grid_convolution_mixed_radix(case):
+    prob = MIXED[case]()
+    ctx = B.Context.from_problem(prob, device=0)
+    orc = model.Oracle(prob)
+    N = orc.aim.grid.N
+    Q = np.random.default_rng(5).standard_normal(tuple(N))
+    qg = torch.tensor(Q.transpose(2, 1, 0).copy(), dtype=torch.float32, device="cuda")
+    ug = torch.empty_like(qg)
+    ctx.grid_convolve(qg, ug)
+    U = ug.cpu().numpy().astype(np.float64).transpose(2, 1, 0)
+    err = rel(U, orc.aim.convolve(Q) / (4 * np.pi))
+    print(f"[gpu parity] convolution {case} (mixed radix): rel L2 {err:.2e}", flush=True)
+    assert err <= 1e-6

@@ -65,6 +65,12 @@ PROBLEMS = {
                                         Ms=[8e5, 1.4e6], Aex=[1.3e-11, 2e-11],
                                         region_of=lambda c: (c[:, 2] >= 2).astype(np.int32),
                                         grid=(16, 16, 8)),
+    # FFT extents that are not powers of two (mixed-radix passes): 12 x 20
+    # periodic with 6 points across (extent 12), and 15 x 14 x 21 periodic
+    "film_mixed_radix": lambda: mg.kuhn_box((6, 5, 2), 1e-9, periodic=0b011, jitter=0.2,
+                                            grid=(12, 20, 6)),
+    "box3d_mixed_radix": lambda: mg.kuhn_box((5, 6, 5), 1e-9, periodic=0b111, jitter=0.2,
+                                             grid=(15, 14, 21)),
 }
 KW = {"open_box_p1_rb0": dict(order_p=1, near_boxes=0),
       "film_p2_rb1": dict(order_p=2, near_boxes=1),
@@ -184,7 +190,7 @@ def test_errors_are_reported():
     with pytest.raises(lib.PmfemError) as e:
         c.build()
     assert e.value.code == lib.Status.EGRID
-    c.set_aim((16, 16, 3))           # non-periodic FFT extent 6: not a power of two
+    c.set_aim((16, 16, 11))          # non-periodic FFT extent 22: the factor 11 has no pass
     with pytest.raises(lib.PmfemError) as e:
         c.build()
     assert e.value.code == lib.Status.EGRID
@@ -346,8 +352,8 @@ def test_scatter_tiles_map_every_stencil_point(pair):
     """Scatter anterpolation tiles (host plan): every unknown is listed once,
     and each of its (p+1)^3 stencil points, reached through the listed
     footprint offset and the per-axis (tile, offset) tables, is the grid point
-    the oracle's stencil start gives; at most two tiles of different parity
-    cover a grid index along an axis."""
+    the oracle's stencil start gives; at most two different tiles cover a grid
+    index along an axis."""
     prob, ctx, orc = pair
     perm = _perm(ctx, orc)
     info = ctx.export("grid_info")
@@ -372,7 +378,7 @@ def test_scatter_tiles_map_every_stencil_point(pair):
             ents = [tuple(e) for e in t_a[gi] if e[0] >= 0]
             assert 1 <= len(ents) <= 2
             if len(ents) == 2:
-                assert ents[0][0] % 2 != ents[1][0] % 2
+                assert ents[0][0] != ents[1][0]
             for e in ents:
                 assert e not in m
                 m[e] = gi
