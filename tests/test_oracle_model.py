@@ -292,3 +292,85 @@ def test_implicit_midpoint_agrees_with_rk4_on_the_film(film):
     e2 = np.linalg.norm(mi2 - mr) / np.linalg.norm(mr - m0)
     assert e2 < e1 / 3.5 and e1 < 1e-2, (e1, e2)
     assert np.allclose(np.linalg.norm(mi, axis=1), 1.0, atol=1e-13)
+
+
+# --- adaptive midpoint (time-step adaptive predictor-corrector, Sec. 2.2) ---
+
+def _macrospin(alpha, Hap=2e5, th0=0.9, ph0=0.3, T=40e-12):
+    """A lone moment in H = Hap z: the rate is gamma0 Hap / (1 + alpha^2),
+    the polar angle follows tan(th/2) = tan(th0/2) exp(-alpha g t)."""
+    p = mg.kuhn_box((3, 3, 3), 2e-9, periodic=0b111, Ms=MS, Aex=0.0, grid=(12, 12, 12))
+    o = model.Oracle(p, with_aim=False)
+    A = np.zeros((3 * o.n, 3 * o.n))     # a uniform m in a filled periodic cell: no own field
+    m0 = np.tile([np.sin(th0) * np.cos(ph0), np.sin(th0) * np.sin(ph0), np.cos(th0)], (o.n, 1))
+    g = model.GAMMA0 * Hap / (1 + alpha ** 2)
+    th = 2 * np.arctan(np.tan(th0 / 2) * np.exp(-alpha * g * T))
+    ph = ph0 + g * T
+    ex = np.array([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)])
+    return o, A, m0, ex
+
+
+def test_adaptive_midpoint_estimate_is_the_local_error():
+    """Undamped, the right side is linear and a midpoint step turns m by
+    exactly 2 atan(x / 2), x = gamma0 H h, where the flow turns it by x: the
+    local error of every step is known in closed form, and the estimate
+    (predictor constant with non-uniform steps and the history's own errors)
+    must reproduce it to leading order."""
+    Hap, th0 = 2e5, 0.9
+    o, A, m0, ex = _macrospin(0.0, Hap, th0)
+    m, info = o.implicit_midpoint_adaptive(m0, 40e-12, 1e-14, 0.0, 1e-8, h_app=[0, 0, Hap], A=A)
+    dts = np.array(info["dts"])
+    x = model.GAMMA0 * Hap * dts
+    true = np.sin(th0) * np.abs(2 * np.arctan(x / 2) - x) / np.sqrt(3)
+    est = np.array(info["lte"][2:], dtype=float)
+    ratio = est / true[2:]
+    assert info["lte"][0] is None and info["lte"][1] is None
+    assert np.all(est <= 1e-8)
+    assert 0.99 < ratio.min() and ratio.max() < 1.01, (ratio.min(), ratio.max())
+    # the steps grew from the first trial step and vary along the run
+    assert dts[0] == 1e-14 and dts.max() > 5 * dts[0]
+    assert abs(dts.sum() - 40e-12) < 1e-24
+    assert np.abs(m - ex[None, :]).max() < 1e-5
+
+
+def test_adaptive_midpoint_error_follows_the_tolerance():
+    """Damped (nonlinear) macrospin against its closed form: each accepted step
+    keeps its error near the tolerance and the steps grow as tol^(-1/3), so
+    the global error falls as tol^(2/3): a tolerance 8 times smaller gives
+    about twice the steps and a quarter of the error."""
+    o, A, m0, ex = _macrospin(0.3)
+    res = []
+    for tol in (1.25e-7, 1.5625e-8):
+        m, info = o.implicit_midpoint_adaptive(m0, 40e-12, 1e-14, 0.3, tol, h_app=[0, 0, 2e5],
+                                               A=A)
+        err = np.abs(m - ex[None, :]).max()
+        res.append((len(info["dts"]), err))
+        assert err < 2 * len(info["dts"]) * tol
+        assert np.allclose(np.linalg.norm(m, axis=1), 1.0, atol=1e-12)
+        assert info["rejected"] == 0
+    (n1, e1), (n2, e2) = res
+    assert 1.7 < n2 / n1 < 2.3, res
+    assert 3.2 < e1 / e2 < 4.8, res
+
+
+def test_adaptive_midpoint_recovers_from_a_failed_newton_step():
+    """A first trial step far too long for two Newton iterations is halved
+    until Newton converges; the run still meets the closed form."""
+    o, A, m0, ex = _macrospin(0.3)
+    m, info = o.implicit_midpoint_adaptive(m0, 40e-12, 1e-11, 0.3, 1e-7, h_app=[0, 0, 2e5],
+                                           A=A, max_newton=2)
+    assert info["rejected"] >= 1 and info["dts"][0] < 1e-11
+    assert np.abs(m - ex[None, :]).max() < 1e-4
+    with pytest.raises(RuntimeError, match="underflow"):
+        o.implicit_midpoint_adaptive(m0, 40e-12, 1e-12, 0.3, 1e-7, h_app=[0, 0, 2e5], A=A,
+                                     max_newton=0)
+
+
+def test_predictor_constant_uniform_steps():
+    """Uniform steps: the slope line misses by -h^2 y''' and each slope carries
+    (1/24 + 1/12) h^2 y''', which the extrapolation (2 s1 - s2) keeps once,
+    so C_p = -1 + 1/8 - 1/24 = -11/12 and Milne's factor C / (C - C_p) = 1/12."""
+    cp = model.Oracle.predictor_constant(1.0, 1.0, 1.0)
+    assert abs(cp + 11.0 / 12.0) < 1e-15
+    c = model.Oracle.LTE_C
+    assert abs(c / (c - cp) - 1.0 / 12.0) < 1e-15
