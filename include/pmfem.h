@@ -228,6 +228,43 @@ int pmfem_llg_implicit(pmfem_ctx* ctx, double* m_dev, double dt, double alpha, i
                        int32_t krylov_dim, int32_t* iterations);
 
 /*
+ * The midpoint rule of pmfem_llg_implicit with an adaptive time step, as a
+ * predictor-corrector pair (the time-step adaptive midpoint scheme of
+ * Sec. 2.2 and Sec. 5; its formulas here are this library's choice): it
+ * advances m_dev[N'][3] (FP64, device) from t = 0 to t_end (s). The
+ * predictor extrapolates the midpoint slopes of the last two accepted
+ * steps linearly to the new step's midpoint; Newton (as in
+ * pmfem_llg_implicit, from the predictor, tolerance newton_tol, <= 0
+ * selects 0.1 lte_tol) corrects it, at least once even where the predictor
+ * already meets the tolerance. From the third accepted step on, the
+ * local error estimate |C / (C - C_p)| rms(x_c - x_p) per component
+ * (Milne's device: C = 1/12 the midpoint rule's constant for a linear right
+ * side, C_p the predictor's for the step sizes at hand, history errors
+ * included) must be <= lte_tol, else the step is rejected; the next step is
+ * h min(2, max(0.2, 0.9 (lte_tol / E)^(1/3))), at most 0.9 h after a
+ * rejection. A Newton iteration that fails (10 iterations, 3 without
+ * progress, or a residual three times its first) halves the step. Each
+ * accepted state is renormalised per node (the rule keeps |m| up to the
+ * Newton residual, an rms that a few nodes could exceed). *dt
+ * (host) is the first trial step on entry and the proposed next step on
+ * return. stats (host, 5 int32, or NULL): accepted steps, steps rejected by
+ * the error estimate, steps rejected for a failed Newton iteration, Newton
+ * iterations, Krylov iterations. dt_log (host, dt_log_cap doubles,
+ * or NULL with cap 0) receives the step size of the first dt_log_cap
+ * attempts in order, negated for the rejected ones. max_steps
+ * (<= 0 selects 1e6) bounds the accepted steps. PMFEM_ECONV when the step
+ * limit is reached or the step falls below 1e-9 t_end (m_dev then holds the
+ * last accepted state); PMFEM_EINVAL for bad arguments. Allocates the
+ * workspace of pmfem_llg_implicit plus 72 N' bytes on its first call.
+ * Synchronises.
+ */
+int pmfem_llg_implicit_adaptive(pmfem_ctx* ctx, double* m_dev, double t_end, double* dt,
+                                double alpha, uint32_t terms, const double* h_applied,
+                                double lte_tol, double newton_tol, int32_t krylov_dim,
+                                int32_t max_steps, int32_t* stats, double* dt_log,
+                                int32_t dt_log_cap);
+
+/*
  * Energies in J for the FP64 magnetisation m_dev[N'][3] (device):
  * exchange E_ex = m.K m and magnetostatic E_ms = (mu0/2) q.u. Synchronises.
  */

@@ -95,6 +95,7 @@ struct pmfem_dev {
     double* coef = nullptr;
     float *mb32 = nullptr, *H = nullptr, *z32 = nullptr, *Az = nullptr;
     double* host = nullptr;  // pinned: coefficients out, reductions back
+    double *xp = nullptr, *S = nullptr;  // adaptive steps: predictor, two slopes
   } imp;
   std::vector<void*> allocs;
   // profiling
@@ -970,7 +971,8 @@ void launch_interp(const IcPlan& pl, dim3 grid, dim3 blk, size_t lds, hipStream_
 #undef PMFEM_IC_LAUNCH
 }
 
-int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const double* happ) {
+int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const double* happ,
+             const double* m64 = nullptr) {
   pmfem_dev* d = c->dev;
   hipStream_t s = stream_of(c);
   const int64_t n = d->n;
@@ -986,14 +988,24 @@ int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const doubl
     if (ev) (void)hipEventRecord(ev[2 * k + which], s);
   };
   const int T = 256;
+  // the exchange reads the FP64 magnetisation where the caller has one (the
+  // implicit solver's residual), else the FP32 copy
   auto exch = [&](hipStream_t st) {
     const dim3 grid((unsigned)((n * d->lanes_l + T - 1) / T));
-    if (d->lanes_l == 4)
-      hipLaunchKernelGGL(k_exch<4>, grid, dim3(T), 0, st, n, d->lrp, d->lrec, m, d->hex);
-    else if (d->lanes_l == 8)
-      hipLaunchKernelGGL(k_exch<8>, grid, dim3(T), 0, st, n, d->lrp, d->lrec, m, d->hex);
-    else
-      hipLaunchKernelGGL(k_exch<16>, grid, dim3(T), 0, st, n, d->lrp, d->lrec, m, d->hex);
+    if (m64) {
+      if (d->lanes_l == 4)
+        hipLaunchKernelGGL((k_exch<4, double>), grid, dim3(T), 0, st, n, d->lrp, d->lrec, m64, d->hex);
+      else if (d->lanes_l == 8)
+        hipLaunchKernelGGL((k_exch<8, double>), grid, dim3(T), 0, st, n, d->lrp, d->lrec, m64, d->hex);
+      else
+        hipLaunchKernelGGL((k_exch<16, double>), grid, dim3(T), 0, st, n, d->lrp, d->lrec, m64, d->hex);
+    } else if (d->lanes_l == 4) {
+      hipLaunchKernelGGL((k_exch<4, float>), grid, dim3(T), 0, st, n, d->lrp, d->lrec, m, d->hex);
+    } else if (d->lanes_l == 8) {
+      hipLaunchKernelGGL((k_exch<8, float>), grid, dim3(T), 0, st, n, d->lrp, d->lrec, m, d->hex);
+    } else {
+      hipLaunchKernelGGL((k_exch<16, float>), grid, dim3(T), 0, st, n, d->lrp, d->lrec, m, d->hex);
+    }
   };
   auto rowdot3 = [&](hipStream_t st, const int32_t* rp, const int4* rec, float* out, int lanes) {
     const dim3 grid((unsigned)((n * lanes + T - 1) / T));
@@ -1179,12 +1191,14 @@ int ready(pmfem_ctx* c) {
 constexpr int kMaxKrylov = 60;
 constexpr int kDotParts = 1024;
 
-int implicit_setup(pmfem_ctx* c, int kdim) {
+int implicit_setup(pmfem_ctx* c, int kdim, bool adaptive) {
   pmfem_dev* d = c->dev;
   pmfem_dev::Implicit& W = d->imp;
-  if (W.kdim >= kdim) return PMFEM_OK;
   const int64_t n = d->n, n3 = 3 * n;
   int rc;
+  if (adaptive && !W.xp && ((rc = dalloc(c, &W.xp, n3)) || (rc = dalloc(c, &W.S, 2 * n3))))
+    return rc;
+  if (W.kdim >= kdim) return PMFEM_OK;
   if ((rc = dalloc(c, &W.x, n3)) || (rc = dalloc(c, &W.mb, n3)) || (rc = dalloc(c, &W.G, n3)) ||
       (rc = dalloc(c, &W.Minv, 9 * n)) || (rc = dalloc(c, &W.V, (int64_t)(kdim + 1) * n3)) ||
       (rc = dalloc(c, &W.w, n3)) || (rc = dalloc(c, &W.z, n3)) ||
@@ -1248,8 +1262,21 @@ int lincomb(pmfem_ctx* c, hipStream_t s, const double* V, int64_t ldv, int nv, c
   return PMFEM_OK;
 }
 
-int run_implicit(pmfem_ctx* c, double* m, double dt, double alpha, int32_t n_steps,
-                 uint32_t terms, const double* happ, double tol, int kdim, int32_t* stats) {
+// Newton's iteration for one midpoint step of size dt from m, starting from
+// the guess in W.x and leaving the solution there. Converged when the rms of
+// the residual per component is <= tol after at least min_newton
+// corrections (a predictor-corrector step needs one: a predictor accepted
+// as it stands would make the error estimate zero and put predictor values
+// into the step history); gives up after max_newton
+// iterations, after three without a decrease (the residual has reached the
+// rounding level of the FP32 field, above the tolerance), or when the
+// residual exceeds diverge times its first value (diverge <= 0: never).
+// GMRES ends a linear solve at a relative residual of 1e-6 or at half the
+// Newton tolerance, whichever is reached first.
+int newton_solve(pmfem_ctx* c, const double* m, double dt, double alpha, uint32_t terms,
+                 const double* happ, double tol, int kdim, int min_newton, int max_newton,
+                 double diverge,
+                 bool* converged, int32_t* newton_its, int32_t* krylov_its, std::string* hist) {
   pmfem_dev* d = c->dev;
   pmfem_dev::Implicit& W = d->imp;
   hipStream_t s = stream_of(c);
@@ -1257,128 +1284,270 @@ int run_implicit(pmfem_ctx* c, double* m, double dt, double alpha, int32_t n_ste
   const unsigned b3 = (unsigned)((n3 + 255) / 256), b1 = (unsigned)((n + 255) / 256);
   const double cc = -kGamma0 / (1.0 + alpha * alpha);
   const double sj = -0.5 * dt * cc;  // dG/dx = I + sj D
-  const double eta = 1e-6;           // GMRES: relative residual of each Newton system
-  const int max_newton = 30;
+  const double eta = 1e-6;
   const double rms = std::sqrt((double)n3);
-  int32_t newton_total = 0, krylov_total = 0;
   std::vector<double> hcol(kMaxKrylov + 2), h2(kMaxKrylov + 2), y(kMaxKrylov + 1),
       g(kMaxKrylov + 2), cs(kMaxKrylov + 1), sn(kMaxKrylov + 1);
   std::vector<double> R((size_t)(kMaxKrylov + 1) * (kMaxKrylov + 1));
   int rc;
+  double best = HUGE_VAL, first = 0.0;
+  int stall = 0;
+  *converged = false;
+  if (hist) hist->clear();
+  for (int it = 0; it <= max_newton; ++it) {
+    hipLaunchKernelGGL(k_mid_point, dim3(b3), dim3(256), 0, s, n3, m, (const double*)W.x, W.mb,
+                       W.mb32);
+    if ((rc = run_heff(c, W.mb32, W.H, terms, happ, W.mb))) return rc;
+    hipLaunchKernelGGL(k_mid_residual, dim3(kDotParts), dim3(256), 0, s, n, m, (const double*)W.x,
+                       (const double*)W.mb, (const float*)W.H, (const double*)W.adiag, dt, cc,
+                       alpha, W.G, W.Minv, W.part);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, (const double*)W.part, kDotParts,
+                       W.red);
+    hipError_t e = hipMemcpyAsync(W.host, W.red, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_err(c, e, "implicit residual");
+    const double beta = std::sqrt(W.host[0]);
+    if (hist) {
+      char buf[32];
+      std::snprintf(buf, sizeof buf, "%s%.3e", it ? " " : "", beta / rms);
+      *hist += buf;
+    }
+    if (it >= min_newton && beta / rms <= tol) {
+      *converged = true;
+      return PMFEM_OK;
+    }
+    if (it == 0) first = beta;
+    stall = beta < best ? 0 : stall + 1;
+    best = std::min(best, beta);
+    if (it == max_newton || stall >= 3 || !std::isfinite(beta) ||
+        (diverge > 0.0 && beta > diverge * first))
+      return PMFEM_OK;
+    ++*newton_its;
+    // GMRES: V_0 = G / beta, Arnoldi with classical Gram-Schmidt done twice
+    const double stop = std::max(eta * beta, 0.5 * tol * rms);
+    if ((rc = lincomb(c, s, nullptr, 0, 0, nullptr, 1.0 / beta, W.G, W.V))) return rc;
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int used = 0;
+    for (int i = 0; i < kdim; ++i) {
+      double* Vi = W.V + (int64_t)i * n3;
+      hipLaunchKernelGGL(k_mid_precond, dim3(b1), dim3(256), 0, s, n, (const double*)W.Minv,
+                         (const double*)Vi, W.z, W.z32);
+      if ((rc = run_heff(c, W.z32, W.Az, terms, nullptr))) return rc;
+      hipLaunchKernelGGL(k_mid_jvp, dim3(b1), dim3(256), 0, s, n, (const double*)W.z,
+                         (const float*)W.Az, (const double*)W.mb, (const float*)W.H, sj, alpha,
+                         W.w);
+      ++*krylov_its;
+      if ((rc = dots(c, s, W.V, n3, i + 1, W.w, hcol.data()))) return rc;
+      for (int j = 0; j <= i; ++j) hcol[j] = -hcol[j];
+      if ((rc = lincomb(c, s, W.V, n3, i + 1, hcol.data(), 1.0, W.w, W.w))) return rc;
+      if ((rc = dots(c, s, W.V, n3, i + 1, W.w, h2.data()))) return rc;
+      for (int j = 0; j <= i; ++j) h2[j] = -h2[j];
+      if ((rc = lincomb(c, s, W.V, n3, i + 1, h2.data(), 1.0, W.w, W.w))) return rc;
+      double nw2 = 0.0;
+      if ((rc = dots(c, s, W.w, n3, 1, W.w, &nw2))) return rc;
+      const double hn = std::sqrt(nw2);
+      // column i of the Hessenberg matrix, rotated by the previous Givens
+      // rotations, then a new rotation that zeroes its subdiagonal
+      for (int j = 0; j <= i; ++j) hcol[j] = -(hcol[j] + h2[j]);
+      for (int j = 0; j < i; ++j) {
+        const double a = cs[j] * hcol[j] + sn[j] * hcol[j + 1];
+        hcol[j + 1] = -sn[j] * hcol[j] + cs[j] * hcol[j + 1];
+        hcol[j] = a;
+      }
+      const double den = std::hypot(hcol[i], hn);
+      cs[i] = den > 0.0 ? hcol[i] / den : 1.0;
+      sn[i] = den > 0.0 ? hn / den : 0.0;
+      hcol[i] = den;
+      for (int j = 0; j <= i; ++j) R[(size_t)j * (kMaxKrylov + 1) + i] = hcol[j];
+      g[i + 1] = -sn[i] * g[i];
+      g[i] = cs[i] * g[i];
+      used = i + 1;
+      if (std::fabs(g[i + 1]) <= stop || hn == 0.0 || i + 1 == kdim) break;
+      if ((rc = lincomb(c, s, nullptr, 0, 0, nullptr, 1.0 / hn, W.w, W.V + (int64_t)(i + 1) * n3)))
+        return rc;
+    }
+    // y from R y = g, then x -= Minv (V y)
+    for (int j = used - 1; j >= 0; --j) {
+      double v = g[j];
+      for (int k = j + 1; k < used; ++k) v -= R[(size_t)j * (kMaxKrylov + 1) + k] * y[k];
+      const double rjj = R[(size_t)j * (kMaxKrylov + 1) + j];
+      y[j] = rjj != 0.0 ? v / rjj : 0.0;
+    }
+    if ((rc = lincomb(c, s, W.V, n3, used, y.data(), 0.0, W.w, W.w))) return rc;
+    hipLaunchKernelGGL(k_mid_precond, dim3(b1), dim3(256), 0, s, n, (const double*)W.Minv,
+                       (const double*)W.w, W.z, (float*)nullptr);
+    const double minus_one = -1.0;
+    if ((rc = lincomb(c, s, W.z, n3, 1, &minus_one, 1.0, W.x, W.x))) return rc;
+  }
+  return PMFEM_OK;
+}
+
+int run_implicit(pmfem_ctx* c, double* m, double dt, double alpha, int32_t n_steps,
+                 uint32_t terms, const double* happ, double tol, int kdim, int32_t* stats) {
+  pmfem_dev::Implicit& W = c->dev->imp;
+  hipStream_t s = stream_of(c);
+  const int64_t n3 = 3 * c->dev->n;
+  int32_t newton_total = 0, krylov_total = 0;
+  int rc;
+  auto report = [&]() {
+    if (stats) {
+      stats[0] = newton_total;
+      stats[1] = krylov_total;
+    }
+  };
+  std::string hist;  // residual rms after each Newton iteration, for the error message
   for (int32_t step = 0; step < n_steps; ++step) {
     hipError_t e = hipMemcpyAsync(W.x, m, n3 * sizeof(double), hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return hip_err(c, e, "implicit step");
     bool converged = false;
-    std::string hist;  // residual rms after each Newton iteration, for the error message
-    double best = HUGE_VAL;
-    int stall = 0;
-    for (int it = 0; it <= max_newton; ++it) {
-      hipLaunchKernelGGL(k_mid_point, dim3(b3), dim3(256), 0, s, n3, (const double*)m,
-                         (const double*)W.x, W.mb, W.mb32);
-      if ((rc = run_heff(c, W.mb32, W.H, terms, happ))) return rc;
-      hipLaunchKernelGGL(k_mid_residual, dim3(kDotParts), dim3(256), 0, s, n, (const double*)m,
-                         (const double*)W.x, (const double*)W.mb, (const float*)W.H,
-                         (const double*)W.adiag, dt, cc, alpha, W.G, W.Minv, W.part);
-      hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, (const double*)W.part, kDotParts,
-                         W.red);
-      e = hipMemcpyAsync(W.host, W.red, sizeof(double), hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess) e = hipStreamSynchronize(s);
-      if (e != hipSuccess) return hip_err(c, e, "implicit residual");
-      const double beta = std::sqrt(W.host[0]);
-      {
-        char buf[32];
-        std::snprintf(buf, sizeof buf, "%s%.3e", it ? " " : "", beta / rms);
-        hist += buf;
-      }
-      if (beta / rms <= tol) {
-        converged = true;
-        break;
-      }
-      // three iterations without a decrease: the residual has reached the
-      // rounding level of the FP32 field, above the tolerance
-      stall = beta < best ? 0 : stall + 1;
-      best = std::min(best, beta);
-      if (it == max_newton || stall >= 3) break;
-      ++newton_total;
-      // GMRES: V_0 = G / beta, Arnoldi with classical Gram-Schmidt done twice
-      const double inv = 1.0 / beta;
-      if ((rc = lincomb(c, s, nullptr, 0, 0, nullptr, inv, W.G, W.V))) return rc;
-      std::fill(g.begin(), g.end(), 0.0);
-      g[0] = beta;
-      int used = 0;
-      for (int i = 0; i < kdim; ++i) {
-        double* Vi = W.V + (int64_t)i * n3;
-        hipLaunchKernelGGL(k_mid_precond, dim3(b1), dim3(256), 0, s, n, (const double*)W.Minv,
-                           (const double*)Vi, W.z, W.z32);
-        if ((rc = run_heff(c, W.z32, W.Az, terms, nullptr))) return rc;
-        hipLaunchKernelGGL(k_mid_jvp, dim3(b1), dim3(256), 0, s, n, (const double*)W.z,
-                           (const float*)W.Az, (const double*)W.mb, (const float*)W.H, sj, alpha,
-                           W.w);
-        ++krylov_total;
-        if ((rc = dots(c, s, W.V, n3, i + 1, W.w, hcol.data()))) return rc;
-        for (int j = 0; j <= i; ++j) hcol[j] = -hcol[j];
-        if ((rc = lincomb(c, s, W.V, n3, i + 1, hcol.data(), 1.0, W.w, W.w))) return rc;
-        if ((rc = dots(c, s, W.V, n3, i + 1, W.w, h2.data()))) return rc;
-        for (int j = 0; j <= i; ++j) h2[j] = -h2[j];
-        if ((rc = lincomb(c, s, W.V, n3, i + 1, h2.data(), 1.0, W.w, W.w))) return rc;
-        double nw2 = 0.0;
-        if ((rc = dots(c, s, W.w, n3, 1, W.w, &nw2))) return rc;
-        const double hn = std::sqrt(nw2);
-        // column i of the Hessenberg matrix, rotated by the previous Givens
-        // rotations, then a new rotation that zeroes its subdiagonal
-        for (int j = 0; j <= i; ++j) hcol[j] = -(hcol[j] + h2[j]);
-        for (int j = 0; j < i; ++j) {
-          const double a = cs[j] * hcol[j] + sn[j] * hcol[j + 1];
-          hcol[j + 1] = -sn[j] * hcol[j] + cs[j] * hcol[j + 1];
-          hcol[j] = a;
-        }
-        const double den = std::hypot(hcol[i], hn);
-        cs[i] = den > 0.0 ? hcol[i] / den : 1.0;
-        sn[i] = den > 0.0 ? hn / den : 0.0;
-        hcol[i] = den;
-        for (int j = 0; j <= i; ++j) R[(size_t)j * (kMaxKrylov + 1) + i] = hcol[j];
-        g[i + 1] = -sn[i] * g[i];
-        g[i] = cs[i] * g[i];
-        used = i + 1;
-        if (std::fabs(g[i + 1]) <= eta * beta || hn == 0.0 || i + 1 == kdim) break;
-        if ((rc = lincomb(c, s, nullptr, 0, 0, nullptr, 1.0 / hn, W.w, W.V + (int64_t)(i + 1) * n3)))
-          return rc;
-      }
-      // y from R y = g, then x -= Minv (V y)
-      for (int j = used - 1; j >= 0; --j) {
-        double v = g[j];
-        for (int k = j + 1; k < used; ++k) v -= R[(size_t)j * (kMaxKrylov + 1) + k] * y[k];
-        const double rjj = R[(size_t)j * (kMaxKrylov + 1) + j];
-        y[j] = rjj != 0.0 ? v / rjj : 0.0;
-      }
-      if ((rc = lincomb(c, s, W.V, n3, used, y.data(), 0.0, W.w, W.w))) return rc;
-      hipLaunchKernelGGL(k_mid_precond, dim3(b1), dim3(256), 0, s, n, (const double*)W.Minv,
-                         (const double*)W.w, W.z, (float*)nullptr);
-      {
-        // x -= z
-        const double minus_one = -1.0;
-        if ((rc = lincomb(c, s, W.z, n3, 1, &minus_one, 1.0, W.x, W.x))) return rc;
-      }
-    }
+    if ((rc = newton_solve(c, m, dt, alpha, terms, happ, tol, kdim, 0, 30, 0.0, &converged,
+                           &newton_total, &krylov_total, &hist)))
+      return rc;
     if (!converged) {
-      if (stats) {
-        stats[0] = newton_total;
-        stats[1] = krylov_total;
-      }
+      report();
       return set_err(c, PMFEM_ECONV,
                      "implicit midpoint: Newton did not reach the tolerance at step " +
                          std::to_string(step) + " (residual rms per iteration: " + hist + ")");
     }
-    hipError_t e2 = hipMemcpyAsync(m, W.x, n3 * sizeof(double), hipMemcpyDeviceToDevice, s);
-    if (e2 != hipSuccess) return hip_err(c, e2, "implicit step");
+    e = hipMemcpyAsync(m, W.x, n3 * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_err(c, e, "implicit step");
   }
-  if (stats) {
-    stats[0] = newton_total;
-    stats[1] = krylov_total;
-  }
+  report();
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_err(c, e, "implicit step");
+  return PMFEM_OK;
+}
+
+// Step-size-adaptive midpoint rule as a predictor-corrector pair. The
+// predictor extrapolates the midpoint slopes s = (m_k+1 - m_k) / h_k of the
+// last two accepted steps linearly to the new step's midpoint (one slope:
+// that slope; none: m itself); Newton corrects from there, at least once.
+// From the third accepted step on, Milne's device estimates the corrector's
+// local error as |C / (C - C_p)| rms(x_c - x_p). C = 1/12 is the midpoint
+// rule's error
+// constant for a linear right side (its local error is C h^3 times the third
+// derivative of the solution); C_p is the predictor's, which counts the chord
+// error of each slope (1/24), the error its own step left in the history
+// (C), and the miss of the straight line through the two midpoint values. A
+// step is accepted when the estimate is <= lte_tol; the next step is
+// h min(2, max(0.2, 0.9 (lte_tol / E)^(1/3))), at most 0.9 h after a
+// rejection; a failed Newton iteration (10 iterations, three without
+// progress, or three times its first residual) halves the step.
+double predictor_constant(double h, double h1, double h2) {
+  const double C = 1.0 / 12.0;
+  const double a = 0.5 * (h + h1), b = a + 0.5 * (h1 + h2), r = (h + h1) / (h1 + h2);
+  return (-0.5 * a * b + (1.0 / 24.0 + C) * ((1.0 + r) * h1 * h1 - r * h2 * h2)) / (h * h) -
+         1.0 / 24.0;
+}
+
+int run_implicit_adaptive(pmfem_ctx* c, double* m, double t_end, double* dt_io, double alpha,
+                          uint32_t terms, const double* happ, double lte_tol, double tol,
+                          int kdim, int32_t max_steps, int32_t* stats, double* dt_log,
+                          int32_t log_cap) {
+  pmfem_dev::Implicit& W = c->dev->imp;
+  hipStream_t s = stream_of(c);
+  const int64_t n3 = 3 * c->dev->n;
+  const double rms = std::sqrt((double)n3);
+  const double C = 1.0 / 12.0;
+  int32_t accepted = 0, rej_error = 0, rej_newton = 0, newton_total = 0, krylov_total = 0;
+  auto report = [&]() {
+    if (stats) {
+      stats[0] = accepted;
+      stats[1] = rej_error;
+      stats[2] = rej_newton;
+      stats[3] = newton_total;
+      stats[4] = krylov_total;
+    }
+  };
+  double t = 0.0, dt = *dt_io;
+  int32_t attempts = 0;
+  auto log_attempt = [&](double h) {
+    if (dt_log && attempts < log_cap) dt_log[attempts] = h;
+    ++attempts;
+  };
+  int ns = 0, newest = 0;  // slopes held; the slot of the latest
+  double hs[2] = {0.0, 0.0};
+  int rc;
+  hipError_t e;
+  while (t_end - t > 1e-12 * t_end) {
+    if (accepted >= max_steps) {
+      report();
+      return set_err(c, PMFEM_ECONV, "adaptive midpoint: step limit reached at t = " +
+                                         std::to_string(t) + " s");
+    }
+    const double h = std::min(dt, t_end - t);
+    if (h < 1e-9 * t_end) {
+      report();
+      return set_err(c, PMFEM_ECONV, "adaptive midpoint: time step underflow at t = " +
+                                         std::to_string(t) + " s");
+    }
+    // predictor into W.xp, Newton's start in W.x
+    if (ns >= 2) {
+      const double h1 = hs[newest], h2 = hs[1 - newest], r = (h + h1) / (h1 + h2);
+      double coef[2];
+      coef[newest] = h * (1.0 + r);
+      coef[1 - newest] = -h * r;
+      rc = lincomb(c, s, W.S, n3, 2, coef, 1.0, m, W.xp);
+    } else if (ns == 1) {
+      rc = lincomb(c, s, W.S + (int64_t)newest * n3, n3, 1, &h, 1.0, m, W.xp);
+    } else {
+      rc = lincomb(c, s, nullptr, 0, 0, nullptr, 1.0, m, W.xp);
+    }
+    if (rc) return rc;
+    e = hipMemcpyAsync(W.x, W.xp, n3 * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_err(c, e, "adaptive midpoint");
+    bool converged = false;
+    if ((rc = newton_solve(c, m, h, alpha, terms, happ, tol, kdim, 1, 10, 3.0, &converged,
+                           &newton_total, &krylov_total, nullptr)))
+      return rc;
+    if (!converged) {
+      ++rej_newton;
+      log_attempt(-h);
+      dt = 0.5 * h;
+      continue;
+    }
+    double dt_new = dt;
+    if (ns >= 2) {
+      const double minus_one = -1.0;
+      if ((rc = lincomb(c, s, W.xp, n3, 1, &minus_one, 1.0, W.x, W.z))) return rc;
+      double d2 = 0.0;
+      if ((rc = dots(c, s, W.z, n3, 1, W.z, &d2))) return rc;
+      const double cp = predictor_constant(h, hs[newest], hs[1 - newest]);
+      const double est = std::fabs(C / (C - cp)) * std::sqrt(d2) / rms;
+      const double fac = est > 0.0 ? 0.9 * std::cbrt(lte_tol / est) : 2.0;
+      if (!(est <= lte_tol)) {
+        ++rej_error;
+        log_attempt(-h);
+        dt = h * std::max(0.2, std::min(0.9, fac));
+        continue;
+      }
+      dt_new = h * std::min(2.0, std::max(0.2, fac));
+    }
+    // accept: x renormalised, the new slope (x - m) / h replaces the older
+    // one, then m = x
+    hipLaunchKernelGGL(k_mid_normalize, dim3((unsigned)((n3 / 3 + 255) / 256)), dim3(256), 0, s,
+                       n3 / 3, W.x);
+    const int slot = ns == 0 ? 0 : 1 - newest;
+    const double minus_inv_h = -1.0 / h;
+    if ((rc = lincomb(c, s, m, n3, 1, &minus_inv_h, 1.0 / h, W.x, W.S + (int64_t)slot * n3)))
+      return rc;
+    newest = slot;
+    hs[slot] = h;
+    ns = std::min(ns + 1, 2);
+    e = hipMemcpyAsync(m, W.x, n3 * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_err(c, e, "adaptive midpoint");
+    log_attempt(h);
+    ++accepted;
+    t += h;
+    dt = dt_new;
+  }
+  *dt_io = dt;
+  report();
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_err(c, e, "adaptive midpoint");
   return PMFEM_OK;
 }
 
@@ -1746,9 +1915,9 @@ int batch_heff(pmfem_batch* b, const float* m, float* h, uint32_t terms) {
   };
   auto exch = [&](hipStream_t st) {
     const dim3 grid((unsigned)((n * b->lanes_l + T - 1) / T));
-    if (b->lanes_l == 4) hipLaunchKernelGGL(k_exch<4>, grid, dim3(T), 0, st, n, b->lrp, b->lrec, m, b->hex);
-    else if (b->lanes_l == 8) hipLaunchKernelGGL(k_exch<8>, grid, dim3(T), 0, st, n, b->lrp, b->lrec, m, b->hex);
-    else hipLaunchKernelGGL(k_exch<16>, grid, dim3(T), 0, st, n, b->lrp, b->lrec, m, b->hex);
+    if (b->lanes_l == 4) hipLaunchKernelGGL((k_exch<4, float>), grid, dim3(T), 0, st, n, b->lrp, b->lrec, m, b->hex);
+    else if (b->lanes_l == 8) hipLaunchKernelGGL((k_exch<8, float>), grid, dim3(T), 0, st, n, b->lrp, b->lrec, m, b->hex);
+    else hipLaunchKernelGGL((k_exch<16, float>), grid, dim3(T), 0, st, n, b->lrp, b->lrec, m, b->hex);
   };
   const CellTab* tab = b->tab;
   if (with_ms) {
@@ -2122,8 +2291,27 @@ int pmfem_llg_implicit(pmfem_ctx* c, double* m_dev, double dt, double alpha, int
   const int kdim = krylov_dim <= 0 ? 30 : krylov_dim;
   if (kdim > kMaxKrylov) return set_err(c, PMFEM_EINVAL, "krylov_dim above 60");
   const double tol = newton_tol > 0.0 ? newton_tol : 1e-8;
-  if ((rc = implicit_setup(c, kdim))) return rc;
+  if ((rc = implicit_setup(c, kdim, false))) return rc;
   return run_implicit(c, m_dev, dt, alpha, n_steps, terms, h_applied, tol, kdim, iterations);
+}
+
+int pmfem_llg_implicit_adaptive(pmfem_ctx* c, double* m_dev, double t_end, double* dt,
+                                double alpha, uint32_t terms, const double* h_applied,
+                                double lte_tol, double newton_tol, int32_t krylov_dim,
+                                int32_t max_steps, int32_t* stats, double* dt_log,
+                                int32_t dt_log_cap) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!m_dev || !dt || !(t_end > 0.0) || !(*dt > 0.0) || !(alpha >= 0.0) || terms < 1 ||
+      terms > 3 || !(lte_tol > 0.0) || max_steps < 0 || dt_log_cap < 0 ||
+      (dt_log_cap > 0 && !dt_log))
+    return set_err(c, PMFEM_EINVAL, "bad adaptive llg arguments");
+  const int kdim = krylov_dim <= 0 ? 30 : krylov_dim;
+  if (kdim > kMaxKrylov) return set_err(c, PMFEM_EINVAL, "krylov_dim above 60");
+  const double tol = newton_tol > 0.0 ? newton_tol : 0.1 * lte_tol;
+  if ((rc = implicit_setup(c, kdim, true))) return rc;
+  return run_implicit_adaptive(c, m_dev, t_end, dt, alpha, terms, h_applied, lte_tol, tol, kdim,
+                               max_steps > 0 ? max_steps : 1000000, stats, dt_log, dt_log_cap);
 }
 
 int pmfem_energy(pmfem_ctx* c, const double* m_dev, double* e_ex, double* e_ms) {

@@ -156,8 +156,8 @@ __global__ void k_r2c_x_cells(const CellTab* tab, const int32_t* bcell, const in
 __global__ void k_fft_y_cells(const CellTab* tab, const int32_t* bcell, const int32_t* boff,
                               int inverse);
 __global__ void k_c2r_x_cells(const CellTab* tab, const int32_t* bcell, const int32_t* boff);
-template <int G>
-__global__ void k_exch(int64_t n, const int32_t* rp, const int2* lrec, const float* m, float* hex);
+template <int G, typename MT>
+__global__ void k_exch(int64_t n, const int32_t* rp, const int2* lrec, const MT* m, float* hex);
 template <int G>
 __global__ void k_gsum(int64_t n, const int32_t* rp, const int4* grec, const float* u,
                        const float* hex, float* h, float hax, float hay, float haz, int with_hex,
@@ -167,6 +167,7 @@ __global__ void k_rk_stage(int64_t n, const double* m, const double* k, double c
 __global__ void k_rk_rhs(int64_t n, const double* mst, const float* h, double pref,
                          double alpha, double* kout, double* acc, double weight, int first);
 __global__ void k_rk_final(int64_t n, double* m, const double* acc, double dt6);
+__global__ void k_mid_normalize(int64_t n, double* x);
 __global__ void k_energy(int64_t n, const double* m, const double* mu, const float* hex,
                          const float* q, const float* u, double* part);
 // implicit midpoint LLG (Newton-Krylov)

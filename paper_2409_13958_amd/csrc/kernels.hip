@@ -9,7 +9,7 @@
 //   k_fft_yx_inv   inverse FFT along y, complex-to-real along x -> U = (1/4 pi) K * Q
 //                  (k_r2c_x, k_fft_y, k_c2r_x: the same passes one axis at a time)
 //   k_interp_tile  u = W U + P q + u_Z            (steps 3 and 4)
-//   k_exch         H_ex = L m (second stream)     (Eqs. hex, lapl_2)
+//   k_exch         H_ex = L m, as differences     (Eqs. hex, lapl_2; second stream)
 //   k_gsum         H = H_ex - G u (+ H_applied)   (Eq. hms_d3, heff)
 // All arithmetic is FP32; every reduction is done in a fixed order inside a
 // wavefront or a thread, so results are bitwise reproducible (no atomics).
@@ -1759,27 +1759,35 @@ PMFEM_INTERP_TILES(7)
 
 // ---------------------------------------------------------------------------
 // exchange and gradient over the shared local pattern, G lanes per row:
-//   k_exch:  H_ex,n = sum_k L_nk m_k                 (records {col, L})
+//   k_exch:  H_ex,n = sum_k L_nk (m_k - m_n)         (records {col, L})
 //   k_gsum:  H_n = H_ex,n - sum_k G_nk u_k + H_applied  (records {col, Gx, Gy, Gz})
 // The exchange needs only m, so the library runs it on the second stream
 // beside the grid steps; k_gsum then adds the magnetostatic gradient.
 
-template <int G>
+template <int G, typename MT>
 __global__ void __launch_bounds__(256) k_exch(int64_t n, const int32_t* __restrict__ rp,
                                               const int2* __restrict__ lrec,
-                                              const float* __restrict__ m,
+                                              const MT* __restrict__ m,
                                               float* __restrict__ hex) {
   const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   const int lane = threadIdx.x & (G - 1);
   if (row >= n) return;  // whole groups leave together
+  // difference form: the rows of L sum to zero (constants are in its null
+  // space), so H_ex,n = sum_k L_nk (m_k - m_n); a uniform m gives exactly
+  // zero and the FP32 rounding scales with the variation of m, not with m.
+  // With an FP64 m (MT = double) the differences are formed before the one
+  // rounding to FP32, so the rounding of m itself, which the exchange
+  // operator would amplify by its largest eigenvalue, never enters.
+  const MT* mn = m + 3 * row;
+  const MT n0 = mn[0], n1 = mn[1], n2 = mn[2];
   float hx = 0.f, hy = 0.f, hz = 0.f;
   row_entries<G, 4>(rp[row], rp[row + 1], lane, lrec, [&](const int2& r, bool ok) {
-    const float* mk = m + 3 * (int64_t)r.x;
-    const float m0 = mk[0], m1 = mk[1], m2 = mk[2];
+    const MT* mk = m + 3 * (int64_t)r.x;
+    const float d0 = (float)(mk[0] - n0), d1 = (float)(mk[1] - n1), d2 = (float)(mk[2] - n2);
     const float w = ok ? __int_as_float(r.y) : 0.f;
-    hx = fmaf(w, m0, hx);
-    hy = fmaf(w, m1, hy);
-    hz = fmaf(w, m2, hz);
+    hx = fmaf(w, d0, hx);
+    hy = fmaf(w, d1, hy);
+    hz = fmaf(w, d2, hz);
   });
   hx = group_sum<G>(hx);
   hy = group_sum<G>(hy);
@@ -1827,7 +1835,10 @@ __global__ void __launch_bounds__(256) k_gsum(int64_t n, const int32_t* __restri
 }
 
 #define PMFEM_LOCAL_KERNELS(G)                                                                  \
-  template __global__ void k_exch<G>(int64_t, const int32_t*, const int2*, const float*, float*); \
+  template __global__ void k_exch<G, float>(int64_t, const int32_t*, const int2*, const float*,   \
+                                            float*);                                             \
+  template __global__ void k_exch<G, double>(int64_t, const int32_t*, const int2*, const double*, \
+                                             float*);                                            \
   template __global__ void k_gsum<G>(int64_t, const int32_t*, const int4*, const float*,         \
                                      const float*, float*, float, float, float, int, int);
 PMFEM_LOCAL_KERNELS(4)
@@ -1988,6 +1999,19 @@ __global__ void __launch_bounds__(256) k_mid_residual(int64_t n, const double* _
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// x / |x| per node (an accepted adaptive step: the rule keeps |m| only up to
+// the Newton residual, which is an rms over all nodes, so a few nodes could
+// otherwise drift over many steps)
+__global__ void k_mid_normalize(int64_t n, double* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = x[3 * i], b = x[3 * i + 1], c = x[3 * i + 2];
+  const double r = 1.0 / sqrt(a * a + b * b + c * c);
+  x[3 * i] = a * r;
+  x[3 * i + 1] = b * r;
+  x[3 * i + 2] = c * r;
 }
 
 // z = Minv v per node; z32 its FP32 copy (NULL: not written)

@@ -127,3 +127,89 @@ def test_bad_arguments_are_refused():
             ctx.llg_implicit(m, args["dt"], args["alpha"], args["n_steps"], terms=args["terms"],
                              krylov_dim=args["krylov_dim"])
         assert e.value.code == B.Status.EINVAL
+
+
+# --- adaptive steps (pmfem_llg_implicit_adaptive) ----------------------------
+
+def test_adaptive_macrospin_follows_the_oracle_steps():
+    """Undamped macrospin, 40 ps from a 10 fs first step: the library's step
+    sequence (predictor, Milne estimate, step control) against the oracle's
+    FP64 run of the same rules, and the end state against the closed form."""
+    ctx = B.Context.from_problem(macrospin_cell(), device=0)
+    Hap, th0, ph0, T, tol = 2e5, 0.9, 0.3, 40e-12, 1e-7
+    m0 = np.array([np.sin(th0) * np.cos(ph0), np.sin(th0) * np.sin(ph0), np.cos(th0)])
+    m = torch.tensor(np.tile(m0, (ctx.n, 1)), dtype=torch.float64, device="cuda")
+    got = ctx.llg_implicit_adaptive(m, T, 1e-14, 0.0, lte_tol=tol, h_applied=[0.0, 0.0, Hap],
+                                    log_steps=4096)
+    orc = model.Oracle(macrospin_cell(), with_aim=False)
+    A = np.zeros((3 * orc.n, 3 * orc.n))
+    mo, info = orc.implicit_midpoint_adaptive(np.tile(m0, (orc.n, 1)), T, 1e-14, 0.0, tol,
+                                              h_app=[0.0, 0.0, Hap], A=A)
+    ref = np.array(info["dts"])
+    ph = ph0 + model.GAMMA0 * Hap * T
+    ex = np.array([np.sin(th0) * np.cos(ph), np.sin(th0) * np.sin(ph), np.cos(th0)])
+    err = np.abs(m.cpu().numpy() - ex[None, :]).max()
+    err_o = np.abs(mo - ex[None, :]).max()
+    k = min(len(ref), got["accepted"])
+    dstep = np.abs(got["dts"][:k] / ref[:k] - 1).max()
+    print(f"[gpu implicit] adaptive macrospin: {got['accepted']} steps (oracle {len(ref)}), "
+          f"{got['rejected']} rejected, max step difference {dstep:.2e}, error {err:.2e} "
+          f"(oracle {err_o:.2e}), Newton {got['newton']}, Krylov {got['krylov']}")
+    rej = np.flatnonzero(got["attempts"] < 0)
+    for i in rej:
+        print(f"  rejected attempt {i}: h {-got['attempts'][i]:.6e}, around "
+              f"{got['attempts'][max(0, i - 3):i + 3]}")
+    assert abs(got["accepted"] - len(ref)) <= 1 and got["rejected"] == info["rejected"]
+    assert dstep < 1e-2
+    assert abs(got["dts"].sum() - T) < 1e-6 * T if got["accepted"] <= 4096 else True
+    assert err < 1.5 * err_o + 1e-7
+    assert np.allclose(np.linalg.norm(m.cpu().numpy(), axis=1), 1.0, atol=1e-7)
+
+
+def test_adaptive_film_against_oracle():
+    """Film, exchange + magnetostatic field, alpha = 0.5, 1 ps from a 1 fs first
+    step at a local tolerance of 1e-5: steps and the end state against the
+    oracle's adaptive run with the exact dense Jacobian."""
+    prob = mg.film_c1()
+    ctx = B.Context.from_problem(prob, device=0)
+    n, uon, nou, _ = ctx.query()
+    orc = model.Oracle(prob)
+    perm = orc.uk[nou]
+    m0 = orc.unknown_values(prob.m)
+    T, tol = 1e-12, 1e-5
+    ref, info = orc.implicit_midpoint_adaptive(m0, T, 1e-15, 0.5, tol)
+    m = torch.tensor(prob.m[nou], dtype=torch.float64, device="cuda")
+    got = ctx.llg_implicit_adaptive(m, T, 1e-15, 0.5, lte_tol=tol, log_steps=4096)
+    dts = np.array(info["dts"])
+    k = min(len(dts), got["accepted"])
+    dstep = np.abs(got["dts"][:k] / dts[:k] - 1).max()
+    out = m.cpu().numpy()
+    err = rel(out - m0[perm], ref[perm] - m0[perm])
+    print(f"[gpu implicit] adaptive film: {got['accepted']} steps (oracle {len(dts)}), "
+          f"{got['rejected']} rejected (oracle {info['rejected']}), max step difference "
+          f"{dstep:.2e}, rel L2 of the change vs oracle {err:.2e}, Newton {got['newton']} "
+          f"(oracle {sum(info['newton'])}), Krylov {got['krylov']}")
+    assert abs(got["accepted"] - len(dts)) <= 1
+    assert dstep < 5e-2
+    assert err < 1e-3
+    assert np.abs(np.linalg.norm(out, axis=1) - 1.0).max() < 1e-5
+
+
+def test_adaptive_limits_and_bad_arguments():
+    ctx = B.Context.from_problem(macrospin_cell(), device=0)
+    m = torch.zeros((ctx.n, 3), dtype=torch.float64, device="cuda")
+    m[:, 0] = 1.0
+    with pytest.raises(B.PmfemError) as e:
+        ctx.llg_implicit_adaptive(m, 40e-12, 1e-14, 0.1, lte_tol=1e-8,
+                                  h_applied=[0.0, 0.0, 2e5], max_steps=3)
+    assert e.value.code == B.Status.ECONV and "step limit" in str(e.value)
+    # m holds the third accepted step, still a unit vector
+    assert np.allclose(np.linalg.norm(m.cpu().numpy(), axis=1), 1.0, atol=1e-9)
+    for kw in (dict(t_end=0.0), dict(dt0=-1.0), dict(lte_tol=0.0), dict(krylov_dim=61),
+               dict(terms=4)):
+        args = dict(t_end=1e-12, dt0=1e-14, lte_tol=1e-6, krylov_dim=0, terms=3)
+        args.update(kw)
+        with pytest.raises(B.PmfemError) as e:
+            ctx.llg_implicit_adaptive(m, args["t_end"], args["dt0"], 0.1, lte_tol=args["lte_tol"],
+                                      krylov_dim=args["krylov_dim"], terms=args["terms"])
+        assert e.value.code == B.Status.EINVAL

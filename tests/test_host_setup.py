@@ -116,6 +116,12 @@ def test_local_operators(pair):
     for c, Gm in enumerate((Gx, Gy, Gz)):
         ref = sp.diags(1.0 / ops.mu) @ ops.D[c].T
         assert abs(Gm - ref).max() <= 2e-7 * abs(ref).max()
+    # the exchange kernel sums L_nk (m_k - m_n), which is L m only if every
+    # row of L sums to zero: the oracle's rows do (constants have no
+    # exchange energy), and the stored FP32 rows to their rounding
+    assert np.abs(np.asarray(Lo.sum(axis=1))).max() <= 1e-12 * abs(Lo).max()
+    rs = np.abs(np.asarray(L.sum(axis=1)).ravel()) / np.abs(L.diagonal())
+    assert rs.max() <= 2e-7
 
 
 def test_grid_kernel_and_spectrum(pair):
