@@ -91,7 +91,8 @@ struct pmfem_dev {
   struct Implicit {
     int kdim = 0;
     double *x = nullptr, *mb = nullptr, *G = nullptr, *Minv = nullptr, *adiag = nullptr;
-    double *V = nullptr, *w = nullptr, *z = nullptr, *part = nullptr, *red = nullptr;
+    float* V = nullptr;  // Krylov basis, FP32
+    double *w = nullptr, *z = nullptr, *part = nullptr, *red = nullptr;
     double* coef = nullptr;
     float *mb32 = nullptr, *H = nullptr, *z32 = nullptr, *Az = nullptr;
     double* host = nullptr;  // pinned: coefficients out, reductions back
@@ -1190,6 +1191,11 @@ int ready(pmfem_ctx* c) {
 
 constexpr int kMaxKrylov = 60;
 constexpr int kDotParts = 1024;
+// device reductions: dot products at [0, 62), an updated norm at kRedNorm;
+// the pinned host buffer mirrors them and carries coefficients at kHostCoef
+constexpr int kRedNorm = 64;
+constexpr int kHostCoef = 128;
+static_assert(kMaxKrylov + 2 <= kRedNorm && kMaxKrylov + 1 <= kGsMaxVectors, "Krylov sizes");
 
 int implicit_setup(pmfem_ctx* c, int kdim, bool adaptive) {
   pmfem_dev* d = c->dev;
@@ -1202,8 +1208,8 @@ int implicit_setup(pmfem_ctx* c, int kdim, bool adaptive) {
   if ((rc = dalloc(c, &W.x, n3)) || (rc = dalloc(c, &W.mb, n3)) || (rc = dalloc(c, &W.G, n3)) ||
       (rc = dalloc(c, &W.Minv, 9 * n)) || (rc = dalloc(c, &W.V, (int64_t)(kdim + 1) * n3)) ||
       (rc = dalloc(c, &W.w, n3)) || (rc = dalloc(c, &W.z, n3)) ||
-      (rc = dalloc(c, &W.part, (int64_t)(kMaxKrylov + 1) * kDotParts)) ||
-      (rc = dalloc(c, &W.red, kMaxKrylov + 1)) || (rc = dalloc(c, &W.coef, kMaxKrylov + 1)) ||
+      (rc = dalloc(c, &W.part, (int64_t)(kMaxKrylov + 2) * kDotParts)) ||
+      (rc = dalloc(c, &W.red, kRedNorm + 1)) || (rc = dalloc(c, &W.coef, kMaxKrylov + 1)) ||
       (rc = dalloc(c, &W.mb32, n3)) || (rc = dalloc(c, &W.H, n3)) || (rc = dalloc(c, &W.z32, n3)) ||
       (rc = dalloc(c, &W.Az, n3)))
     return rc;
@@ -1217,7 +1223,7 @@ int implicit_setup(pmfem_ctx* c, int kdim, bool adaptive) {
     if ((rc = upload(c, &W.adiag, a.data(), (size_t)n))) return rc;
   }
   if (!W.host) {
-    const hipError_t e = hipHostMalloc((void**)&W.host, 2 * (kMaxKrylov + 1) * sizeof(double));
+    const hipError_t e = hipHostMalloc((void**)&W.host, (kHostCoef + kMaxKrylov + 1) * sizeof(double));
     if (e != hipSuccess) return set_err(c, PMFEM_ENOMEM, "hipHostMalloc");
   }
   W.kdim = kdim;
@@ -1250,7 +1256,7 @@ int lincomb(pmfem_ctx* c, hipStream_t s, const double* V, int64_t ldv, int nv, c
     // the pinned buffer's second half carries the coefficients; the copy is
     // ordered before the kernel on the stream and the stream is drained
     // before the buffer is written again
-    double* hc = W.host + kMaxKrylov + 1;
+    double* hc = W.host + kHostCoef;
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_err(c, e, "implicit update");
     for (int j = 0; j < nv; ++j) hc[j] = coef[j];
@@ -1323,33 +1329,53 @@ int newton_solve(pmfem_ctx* c, const double* m, double dt, double alpha, uint32_
         (diverge > 0.0 && beta > diverge * first))
       return PMFEM_OK;
     ++*newton_its;
-    // GMRES: V_0 = G / beta, Arnoldi with classical Gram-Schmidt done twice
+    // GMRES: V_0 = G / beta, Arnoldi with classical Gram-Schmidt, a second
+    // pass where the first removed more than half of |w|^2 (w has lost
+    // orthogonality to the basis), the basis held in FP32
     const double stop = std::max(eta * beta, 0.5 * tol * rms);
-    if ((rc = lincomb(c, s, nullptr, 0, 0, nullptr, 1.0 / beta, W.G, W.V))) return rc;
+    hipLaunchKernelGGL(k_gs_store, dim3(b3), dim3(256), 0, s, n3, (const double*)W.G, 1.0 / beta,
+                       W.V);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int used = 0;
+    // h = V^T w and |w|^2, then w -= V h and |w|^2 again; one wait per pass
+    auto gs_pass = [&](int nv, double* h, double* ww, double* w2) -> int {
+      hipLaunchKernelGGL(k_gs_dots, dim3(kDotParts), dim3(256), 0, s, n3, (const float*)W.V, n3,
+                         nv, (const double*)W.w, W.part);
+      hipLaunchKernelGGL(k_sum_parts, dim3(nv + 1), dim3(256), 0, s, (const double*)W.part,
+                         kDotParts, W.red);
+      hipLaunchKernelGGL(k_gs_update, dim3(kDotParts), dim3(256), 0, s, n3, (const float*)W.V, n3,
+                         nv, (const double*)W.red, W.w, W.part);
+      hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, (const double*)W.part, kDotParts,
+                         W.red + kRedNorm);
+      hipError_t e2 = hipMemcpyAsync(W.host, W.red, (kRedNorm + 1) * sizeof(double),
+                                     hipMemcpyDeviceToHost, s);
+      if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+      if (e2 != hipSuccess) return hip_err(c, e2, "implicit Gram-Schmidt");
+      for (int j = 0; j < nv; ++j) h[j] = W.host[j];
+      *ww = W.host[nv];
+      *w2 = W.host[kRedNorm];
+      return PMFEM_OK;
+    };
     for (int i = 0; i < kdim; ++i) {
-      double* Vi = W.V + (int64_t)i * n3;
-      hipLaunchKernelGGL(k_mid_precond, dim3(b1), dim3(256), 0, s, n, (const double*)W.Minv,
-                         (const double*)Vi, W.z, W.z32);
+      const float* Vi = W.V + (int64_t)i * n3;
+      hipLaunchKernelGGL(k_mid_precond<float>, dim3(b1), dim3(256), 0, s, n,
+                         (const double*)W.Minv, Vi, W.z, W.z32);
       if ((rc = run_heff(c, W.z32, W.Az, terms, nullptr))) return rc;
       hipLaunchKernelGGL(k_mid_jvp, dim3(b1), dim3(256), 0, s, n, (const double*)W.z,
                          (const float*)W.Az, (const double*)W.mb, (const float*)W.H, sj, alpha,
                          W.w);
       ++*krylov_its;
-      if ((rc = dots(c, s, W.V, n3, i + 1, W.w, hcol.data()))) return rc;
-      for (int j = 0; j <= i; ++j) hcol[j] = -hcol[j];
-      if ((rc = lincomb(c, s, W.V, n3, i + 1, hcol.data(), 1.0, W.w, W.w))) return rc;
-      if ((rc = dots(c, s, W.V, n3, i + 1, W.w, h2.data()))) return rc;
-      for (int j = 0; j <= i; ++j) h2[j] = -h2[j];
-      if ((rc = lincomb(c, s, W.V, n3, i + 1, h2.data(), 1.0, W.w, W.w))) return rc;
-      double nw2 = 0.0;
-      if ((rc = dots(c, s, W.w, n3, 1, W.w, &nw2))) return rc;
-      const double hn = std::sqrt(nw2);
+      double ww = 0.0, w2 = 0.0, ww2 = 0.0, w3 = 0.0;
+      if ((rc = gs_pass(i + 1, hcol.data(), &ww, &w2))) return rc;
+      if (w2 < 0.5 * ww) {
+        if ((rc = gs_pass(i + 1, h2.data(), &ww2, &w3))) return rc;
+        for (int j = 0; j <= i; ++j) hcol[j] += h2[j];
+        w2 = w3;
+      }
+      const double hn = std::sqrt(std::max(w2, 0.0));
       // column i of the Hessenberg matrix, rotated by the previous Givens
       // rotations, then a new rotation that zeroes its subdiagonal
-      for (int j = 0; j <= i; ++j) hcol[j] = -(hcol[j] + h2[j]);
       for (int j = 0; j < i; ++j) {
         const double a = cs[j] * hcol[j] + sn[j] * hcol[j + 1];
         hcol[j + 1] = -sn[j] * hcol[j] + cs[j] * hcol[j + 1];
@@ -1364,8 +1390,8 @@ int newton_solve(pmfem_ctx* c, const double* m, double dt, double alpha, uint32_
       g[i] = cs[i] * g[i];
       used = i + 1;
       if (std::fabs(g[i + 1]) <= stop || hn == 0.0 || i + 1 == kdim) break;
-      if ((rc = lincomb(c, s, nullptr, 0, 0, nullptr, 1.0 / hn, W.w, W.V + (int64_t)(i + 1) * n3)))
-        return rc;
+      hipLaunchKernelGGL(k_gs_store, dim3(b3), dim3(256), 0, s, n3, (const double*)W.w, 1.0 / hn,
+                         W.V + (int64_t)(i + 1) * n3);
     }
     // y from R y = g, then x -= Minv (V y)
     for (int j = used - 1; j >= 0; --j) {
@@ -1374,9 +1400,18 @@ int newton_solve(pmfem_ctx* c, const double* m, double dt, double alpha, uint32_
       const double rjj = R[(size_t)j * (kMaxKrylov + 1) + j];
       y[j] = rjj != 0.0 ? v / rjj : 0.0;
     }
-    if ((rc = lincomb(c, s, W.V, n3, used, y.data(), 0.0, W.w, W.w))) return rc;
-    hipLaunchKernelGGL(k_mid_precond, dim3(b1), dim3(256), 0, s, n, (const double*)W.Minv,
-                       (const double*)W.w, W.z, (float*)nullptr);
+    {
+      hipError_t e2 = hipStreamSynchronize(s);
+      double* hc = W.host + kHostCoef;
+      for (int j = 0; j < used; ++j) hc[j] = y[j];
+      if (e2 == hipSuccess)
+        e2 = hipMemcpyAsync(W.coef, hc, used * sizeof(double), hipMemcpyHostToDevice, s);
+      if (e2 != hipSuccess) return hip_err(c, e2, "implicit update");
+    }
+    hipLaunchKernelGGL(k_gs_combine, dim3(b3), dim3(256), 0, s, n3, (const float*)W.V, n3, used,
+                       (const double*)W.coef, W.w);
+    hipLaunchKernelGGL(k_mid_precond<double>, dim3(b1), dim3(256), 0, s, n,
+                       (const double*)W.Minv, (const double*)W.w, W.z, (float*)nullptr);
     const double minus_one = -1.0;
     if ((rc = lincomb(c, s, W.z, n3, 1, &minus_one, 1.0, W.x, W.x))) return rc;
   }

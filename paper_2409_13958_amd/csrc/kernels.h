@@ -175,8 +175,16 @@ __global__ void k_mid_point(int64_t n3, const double* m, const double* x, double
 __global__ void k_mid_residual(int64_t n, const double* m, const double* x, const double* mb,
                                const float* H, const double* adiag, double dt, double c,
                                double alpha, double* G, double* Minv, double* part);
-__global__ void k_mid_precond(int64_t n, const double* Minv, const double* v, double* z,
-                              float* z32);
+template <typename VT>
+__global__ void k_mid_precond(int64_t n, const double* Minv, const VT* v, double* z, float* z32);
+constexpr int kGsMaxVectors = 64;  // Krylov vectors one Gram-Schmidt update takes
+__global__ void k_gs_dots(int64_t n3, const float* V, int64_t ldv, int nv, const double* w,
+                          double* part);
+__global__ void k_gs_update(int64_t n3, const float* V, int64_t ldv, int nv, const double* h,
+                            double* w, double* part);
+__global__ void k_gs_store(int64_t n3, const double* w, double s, float* out);
+__global__ void k_gs_combine(int64_t n3, const float* V, int64_t ldv, int nv, const double* coef,
+                             double* out);
 __global__ void k_mid_jvp(int64_t n, const double* z, const float* Az, const double* mb,
                           const float* H, double s, double alpha, double* w);
 __global__ void k_mdot(int64_t n3, const double* V, int64_t ldv, int nv, const double* w,

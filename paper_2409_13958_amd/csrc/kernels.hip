@@ -2015,13 +2015,14 @@ __global__ void k_mid_normalize(int64_t n, double* __restrict__ x) {
 }
 
 // z = Minv v per node; z32 its FP32 copy (NULL: not written)
+template <typename VT>
 __global__ void k_mid_precond(int64_t n, const double* __restrict__ Minv,
-                              const double* __restrict__ v, double* __restrict__ z,
+                              const VT* __restrict__ v, double* __restrict__ z,
                               float* __restrict__ z32) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double* Mi = Minv + 9 * i;
-  const double vx = v[3 * i], vy = v[3 * i + 1], vz = v[3 * i + 2];
+  const double vx = (double)v[3 * i], vy = (double)v[3 * i + 1], vz = (double)v[3 * i + 2];
   const double a = Mi[0] * vx + Mi[1] * vy + Mi[2] * vz;
   const double b = Mi[3] * vx + Mi[4] * vy + Mi[5] * vz;
   const double d = Mi[6] * vx + Mi[7] * vy + Mi[8] * vz;
@@ -2034,6 +2035,10 @@ __global__ void k_mid_precond(int64_t n, const double* __restrict__ Minv,
     z32[3 * i + 2] = (float)d;
   }
 }
+template __global__ void k_mid_precond<double>(int64_t, const double*, const double*, double*,
+                                               float*);
+template __global__ void k_mid_precond<float>(int64_t, const double*, const float*, double*,
+                                              float*);
 
 // w = dG/dx z, with Az = A z from one FP32 field evaluation
 __global__ void k_mid_jvp(int64_t n, const double* __restrict__ z, const float* __restrict__ Az,
@@ -2055,6 +2060,98 @@ __global__ void k_mid_jvp(int64_t n, const double* __restrict__ z, const float* 
   w[3 * i] = zx + s * (t1x + t2x + alpha * (t3x + t4x + t5x));
   w[3 * i + 1] = zy + s * (t1y + t2y + alpha * (t3y + t4y + t5y));
   w[3 * i + 2] = zz + s * (t1z + t2z + alpha * (t3z + t4z + t5z));
+}
+
+// Gram-Schmidt of the implicit solver's GMRES. The Krylov basis V is held
+// in FP32 (its rounding, 6e-8 relative, lies below the relative residual
+// GMRES is asked for, and each basis vector is one FP32 field evaluation's
+// input anyway); w and every sum are FP64, each sum in a fixed order
+// (grid-stride per thread, a fixed shuffle tree per wavefront, the four
+// wavefronts in order, then k_sum_parts).
+constexpr int kGsChunk = 16;
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+  return v;
+}
+
+// part[j * gridDim.x + b] = block b's share of V_j . w for j < nv and of
+// w . w for j = nv
+__global__ void __launch_bounds__(256) k_gs_dots(int64_t n3, const float* __restrict__ V,
+                                                 int64_t ldv, int nv, const double* __restrict__ w,
+                                                 double* __restrict__ part) {
+  __shared__ double red[4][kGsChunk];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int j0 = 0; j0 <= nv; j0 += kGsChunk) {
+    const int jn = min(kGsChunk, nv + 1 - j0);
+    double acc[kGsChunk];
+#pragma unroll
+    for (int k = 0; k < kGsChunk; ++k) acc[k] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n3;
+         i += (int64_t)gridDim.x * blockDim.x) {
+      const double wi = w[i];
+#pragma unroll
+      for (int k = 0; k < kGsChunk; ++k) {
+        const int j = j0 + k;
+        if (k < jn) acc[k] = fma(j < nv ? (double)V[(int64_t)j * ldv + i] : wi, wi, acc[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kGsChunk; ++k) {
+      if (k < jn) {
+        const double sv = wave_sum_d(acc[k]);
+        if (lane == 0) red[wv][k] = sv;
+      }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < jn)
+      part[(int64_t)(j0 + threadIdx.x) * gridDim.x + blockIdx.x] =
+          ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+    __syncthreads();
+  }
+}
+
+// w -= sum_j h[j] V_j (j < nv, ascending); part[b] = block b's share of
+// |w|^2 after the update
+__global__ void __launch_bounds__(256) k_gs_update(int64_t n3, const float* __restrict__ V,
+                                                   int64_t ldv, int nv,
+                                                   const double* __restrict__ h,
+                                                   double* __restrict__ w,
+                                                   double* __restrict__ part) {
+  __shared__ double hs[kGsMaxVectors];
+  __shared__ double red[4];
+  for (int t = threadIdx.x; t < nv; t += blockDim.x) hs[t] = h[t];
+  __syncthreads();
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n3;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double v = w[i];
+    for (int j = 0; j < nv; ++j) v = fma(-hs[j], (double)V[(int64_t)j * ldv + i], v);
+    w[i] = v;
+    acc = fma(v, v, acc);
+  }
+  const double sv = wave_sum_d(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sv;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// out = (float)(s w)
+__global__ void k_gs_store(int64_t n3, const double* __restrict__ w, double s,
+                           float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n3) out[i] = (float)(s * w[i]);
+}
+
+// out = sum_j coef[j] V_j (j < nv, ascending)
+__global__ void k_gs_combine(int64_t n3, const float* __restrict__ V, int64_t ldv, int nv,
+                             const double* __restrict__ coef, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n3) return;
+  double v = 0.0;
+  for (int j = 0; j < nv; ++j) v = fma(coef[j], (double)V[(int64_t)j * ldv + i], v);
+  out[i] = v;
 }
 
 // part[j * gridDim.x + b] = block b's share of V_j . w for j < nv (fixed
