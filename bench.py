@@ -241,7 +241,7 @@ def run_batched(args):
     import torch
     from paper_2409_13958_amd import binding as B, meshgen as mg
     t = time.perf_counter()
-    probs = mg.films_c4(args.cells)
+    probs = mg.films_c4(args.cells, extents=args.film_extents)
     log(f"{len(probs)} films, {sum(p.n_nodes for p in probs)} nodes "
         f"({time.perf_counter() - t:.1f} s)")
     t = time.perf_counter()
@@ -303,10 +303,13 @@ def run_batched(args):
         "config": {
             "workload": (f"{len(ctxs)} independent 2D-periodic films, node counts log-uniform "
                          f"5k-80k ({batch.n} unknowns in all), periods 20-200 nm, thickness "
-                         f"2-10 nm, Ms 4e5-1.6e6 A/m, one H_eff of every film per step, one "
-                         f"launch per stage for all films"),
+                         f"2-10 nm, Ms 4e5-1.6e6 A/m, in-plane FFT extents "
+                         f"{'with factors 2, 3, 5, 7' if args.film_extents == 'smooth' else 'powers of two'}"
+                         f" ({sum(int(np.prod(p.grid)) for p in probs)} grid points in all), one "
+                         f"H_eff of every film per step, one launch per stage for all films"),
             "name": "batched_films",
             "cells": len(ctxs),
+            "film_extents": args.film_extents,
             "n_unknowns": batch.n,
             "unknown_evals_per_s": batch.n / dt_batch,
             "one_after_another_ms": dt_loop * 1e3,
@@ -429,6 +432,8 @@ def main():
                     help="--llg: untimed relaxation before the driven run (s)")
     ap.add_argument("--cells", type=int, default=64,
                     help="films of the batched_films workload")
+    ap.add_argument("--film-extents", choices=("smooth", "pow2"), default="smooth",
+                    help="batched_films: FFT extents with factors 2, 3, 5, 7, or powers of two")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also stream this many MiB through plain kernels (counter calibration)")
     args = ap.parse_args()

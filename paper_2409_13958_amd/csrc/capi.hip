@@ -403,17 +403,21 @@ bool plan_scatter_with(const HostOps& o, ScPlan& pl, std::vector<int2>& list,
   auto start = [&](int a, int b) {
     return o.per[a] ? b - shift : std::min(std::max(b - shift, 0), o.N[a] - p - 1);
   };
-  // one axis: tiles of the preferred size, or (div) the smallest size that
-  // divides a periodic axis; false if a grid index would lie in three
-  // footprints or a footprint would wrap onto itself
+  // one axis: tiles of the preferred size, or (div) the size that divides a
+  // periodic axis closest to the preferred one (at least p + 1, at most
+  // N - p; the larger of two equally close); false if a grid index would lie
+  // in three footprints or a footprint would wrap onto itself
   auto plan_axis = [&](int a, bool div) -> bool {
     int tb = std::max(want[a], p + 1);
     if (o.per[a]) tb = std::min(tb, o.N[a] - p);
     if (div) {
       if (!o.per[a]) return false;
-      tb = std::max(want[a], p + 1);
-      while (tb <= o.N[a] - p && o.nbox[a] % tb != 0) ++tb;
-      if (tb > o.N[a] - p) return false;
+      const int pref = std::max(want[a], p + 1);
+      int best = 0;
+      for (int d = p + 1; d <= o.N[a] - p; ++d)
+        if (o.nbox[a] % d == 0 && (!best || std::abs(d - pref) <= std::abs(best - pref))) best = d;
+      if (!best) return false;
+      tb = best;
     }
     tb = std::min(tb, o.nbox[a]);
     if (tb < 1) return false;
@@ -1682,9 +1686,10 @@ struct pmfem_batch {
     int32_t* bcell = nullptr;
     int32_t* boff = nullptr;
     unsigned blocks = 0;
-  } sc, sum, xy, zm, yx, ic, r2c, fy, c2r;
+  } sc, sum, xy, zm, yx, ic, r2c, fy, c2r, r2c_mr, fy_mr, zm_mr;
   size_t lds_sc = 0, lds_plane = 0, lds_z = 0, lds_ic = 0, lds_r2c = 0, lds_fy = 0;
-  int p = 3, W = 5, KC = 2, PT = 4, Bz = 8;
+  size_t lds_r2c_mr = 0, lds_fy_mr = 0, lds_z_mr = 0;
+  int p = 3, W = 5, KC = 2, PT = 4, Bz = 8, Bzm = 8;
   double bytes = 0.0;
   std::vector<void*> allocs;
   std::string err;
@@ -1821,7 +1826,8 @@ int batch_setup(pmfem_batch* b, int32_t spmv_lanes) {
     return rc;
   // the cell table and the launch tables of the grid kernels
   std::vector<CellTab> tab(K);
-  std::vector<int64_t> nsc(K), nsum(K), nxy(K), nzm(K), nic(K), nr2c(K), nfy(K);
+  std::vector<int64_t> nsc(K), nsum(K), nxy(K), nzm(K), nic(K), nr2c(K), nfy(K), nr2c_mr(K),
+      nfy_mr(K), nzm_mr(K);
   b->p = b->cells[0]->dev->g.p;
   b->W = 2 * b->cells[0]->dev->g.rb + 1;
   b->PT = 4;
@@ -1833,8 +1839,6 @@ int batch_setup(pmfem_batch* b, int32_t spmv_lanes) {
       return batch_err(b, PMFEM_EINVAL, "cells of a batch must share the Lagrange order and near radius");
     if (!d->sc_ok || (!d->ic_ok && !d->ic_small_ok))
       return batch_err(b, PMFEM_EINVAL, "a cell does not fit the batched kernel forms");
-    if (d->fft_mr)
-      return batch_err(b, PMFEM_EINVAL, "batched cells need power-of-two FFT extents");
     CellTab& t = tab[c];
     t.g = d->g;
     t.sp = d->sp;
@@ -1850,6 +1854,9 @@ int batch_setup(pmfem_batch* b, int32_t spmv_lanes) {
     t.twx = d->twx;
     t.twy = d->twy;
     t.twz = d->twz;
+    t.twfx = d->twfx;
+    t.twfy = d->twfy;
+    t.twfz = d->twfz;
     // interpolation: the largest tiles whose staging fits, else the narrow ones
     const IcPlan& ipl = d->ic_ok ? d->icp : d->icp_small;
     const pmfem_dev::IcLists& il = d->ic_ok ? d->icl : d->icl_small;
@@ -1869,9 +1876,21 @@ int batch_setup(pmfem_batch* b, int32_t spmv_lanes) {
     nsc[c] = (int64_t)d->sp.nt[0] * d->sp.nt[1] * d->sp.nt[2];
     nsum[c] = (ng / b->PT + 255) / 256;
     // FFT: whole z-planes in LDS where they fit, else one axis per pass
+    // (radix 2, or mixed radix where an extent is not a power of two)
     t.lpb = std::max(1, 2048 / g.M[0]);
     t.by = std::max(1, std::min(16, 4096 / g.M[1]));
-    if (d->fft_ok) {
+    nr2c_mr[c] = nfy_mr[c] = 0;
+    if (d->fft_mr) {
+      nxy[c] = nr2c[c] = nfy[c] = 0;
+      t.by = std::max(1, std::min(16, 2048 / g.M[1]));
+      const int64_t xlines = (int64_t)((g.N[1] + 1) / 2) * g.N[2];
+      nr2c_mr[c] = (xlines + t.lpb - 1) / t.lpb;
+      nfy_mr[c] = (int64_t)g.N[2] * ((Hx + t.by - 1) / t.by);
+      b->lds_r2c_mr =
+          std::max(b->lds_r2c_mr, (size_t)(g.M[0] + 2 * t.lpb * g.M[0]) * sizeof(float2));
+      b->lds_fy_mr = std::max(b->lds_fy_mr, (size_t)(g.M[1] + 2 * t.by * g.M[1]) * sizeof(float2));
+      b->Bzm = std::min(b->Bzm, std::max(1, std::min(kFftzB, 2048 / g.M[2])));
+    } else if (d->fft_ok) {
       nxy[c] = (int64_t)g.N[2] * kFftSplit;
       nr2c[c] = nfy[c] = 0;
       b->lds_plane = std::max(b->lds_plane, d->fft_plane_lds);
@@ -1883,7 +1902,7 @@ int batch_setup(pmfem_batch* b, int32_t spmv_lanes) {
       b->lds_r2c = std::max(b->lds_r2c, (size_t)(g.M[0] / 2 + t.lpb * g.M[0]) * sizeof(float2));
       b->lds_fy = std::max(b->lds_fy, (size_t)(g.M[1] / 2 + t.by * g.M[1]) * sizeof(float2));
     }
-    b->Bz = std::min(b->Bz, std::max(1, std::min(kFftzB, 4096 / g.M[2])));
+    if (!d->fft_mr) b->Bz = std::min(b->Bz, std::max(1, std::min(kFftzB, 4096 / g.M[2])));
     nic[c] = (int64_t)ipl.nsx * g.nbox[1] * ipl.nsz;
     b->lds_sc = std::max(b->lds_sc, (size_t)d->sp.lds_bytes);
     b->lds_ic = std::max(b->lds_ic, (size_t)ipl.lds_bytes);
@@ -1891,14 +1910,25 @@ int batch_setup(pmfem_batch* b, int32_t spmv_lanes) {
   }
   for (size_t c = 0; c < K; ++c) {
     const GridParams& g = b->cells[c]->dev->g;
-    nzm[c] = ((int64_t)g.M[1] * (g.M[0] / 2 + 1) + b->Bz - 1) / b->Bz;
-    b->lds_z = std::max(b->lds_z, (size_t)(g.M[2] / 2 + b->Bz * g.M[2]) * sizeof(float2));
+    const int64_t cols = (int64_t)g.M[1] * (g.M[0] / 2 + 1);
+    if (b->cells[c]->dev->fft_mr) {
+      nzm[c] = 0;
+      nzm_mr[c] = (cols + b->Bzm - 1) / b->Bzm;
+      b->lds_z_mr = std::max(b->lds_z_mr, (size_t)(g.M[2] + 2 * b->Bzm * g.M[2]) * sizeof(float2));
+    } else {
+      nzm_mr[c] = 0;
+      nzm[c] = (cols + b->Bz - 1) / b->Bz;
+      b->lds_z = std::max(b->lds_z, (size_t)(g.M[2] / 2 + b->Bz * g.M[2]) * sizeof(float2));
+    }
   }
   if ((rc = bupload(b, &b->tab, tab.data(), K)) || (rc = batch_launch_table(b, nsc, b->sc)) ||
       (rc = batch_launch_table(b, nsum, b->sum)) || (rc = batch_launch_table(b, nxy, b->xy)) ||
       (rc = batch_launch_table(b, nxy, b->yx)) || (rc = batch_launch_table(b, nzm, b->zm)) ||
       (rc = batch_launch_table(b, nic, b->ic)) || (rc = batch_launch_table(b, nr2c, b->r2c)) ||
-      (rc = batch_launch_table(b, nfy, b->fy)) || (rc = batch_launch_table(b, nr2c, b->c2r)))
+      (rc = batch_launch_table(b, nfy, b->fy)) || (rc = batch_launch_table(b, nr2c, b->c2r)) ||
+      (rc = batch_launch_table(b, nr2c_mr, b->r2c_mr)) ||
+      (rc = batch_launch_table(b, nfy_mr, b->fy_mr)) ||
+      (rc = batch_launch_table(b, nzm_mr, b->zm_mr)))
     return rc;
   if (b->lds_plane > 65536) {
     const int lb = (int)b->lds_plane;
@@ -2000,8 +2030,22 @@ int batch_heff(pmfem_batch* b, const float* m, float* h, uint32_t terms) {
       hipLaunchKernelGGL(k_fft_y_cells, dim3(b->fy.blocks), dim3(T), b->lds_fy, s, tab,
                          (const int32_t*)b->fy.bcell, (const int32_t*)b->fy.boff, 0);
     }
-    hipLaunchKernelGGL(k_fft_z_mul_cells, dim3(b->zm.blocks), dim3(kFftzT), b->lds_z, s, tab,
-                       (const int32_t*)b->zm.bcell, (const int32_t*)b->zm.boff, b->Bz);
+    if (b->r2c_mr.blocks) {
+      hipLaunchKernelGGL(k_r2c_x_mr_cells, dim3(b->r2c_mr.blocks), dim3(T), b->lds_r2c_mr, s, tab,
+                         (const int32_t*)b->r2c_mr.bcell, (const int32_t*)b->r2c_mr.boff);
+      hipLaunchKernelGGL(k_fft_y_mr_cells, dim3(b->fy_mr.blocks), dim3(T), b->lds_fy_mr, s, tab,
+                         (const int32_t*)b->fy_mr.bcell, (const int32_t*)b->fy_mr.boff, 0);
+      hipLaunchKernelGGL(k_fft_z_mul_mr_cells, dim3(b->zm_mr.blocks), dim3(kFftzT), b->lds_z_mr,
+                         s, tab, (const int32_t*)b->zm_mr.bcell, (const int32_t*)b->zm_mr.boff,
+                         b->Bzm);
+      hipLaunchKernelGGL(k_fft_y_mr_cells, dim3(b->fy_mr.blocks), dim3(T), b->lds_fy_mr, s, tab,
+                         (const int32_t*)b->fy_mr.bcell, (const int32_t*)b->fy_mr.boff, 1);
+      hipLaunchKernelGGL(k_c2r_x_mr_cells, dim3(b->r2c_mr.blocks), dim3(T), b->lds_r2c_mr, s, tab,
+                         (const int32_t*)b->r2c_mr.bcell, (const int32_t*)b->r2c_mr.boff);
+    }
+    if (b->zm.blocks)
+      hipLaunchKernelGGL(k_fft_z_mul_cells, dim3(b->zm.blocks), dim3(kFftzT), b->lds_z, s, tab,
+                         (const int32_t*)b->zm.bcell, (const int32_t*)b->zm.boff, b->Bz);
     if (b->yx.blocks)
       hipLaunchKernelGGL(k_fft_yx_inv_cells, dim3(b->yx.blocks), dim3(1024), b->lds_plane, s, tab,
                          (const int32_t*)b->yx.bcell, (const int32_t*)b->yx.boff, kFftSplit);

@@ -80,6 +80,7 @@ struct CellTab {
   float2* spec;
   const float* khat;
   const float2 *twx, *twy, *twz;
+  const float2 *twfx, *twfy, *twfz;  // full-circle tables of the mixed-radix passes
   const int32_t *ic_list, *ic_lstart, *ic_wseg;
   const uint32_t* ic_rdesc;
   const int32_t* prp;
@@ -128,6 +129,12 @@ __global__ void k_fft_z_mul_mr(GridParams g, float2* spec, const float* khat, co
                                int B);
 __global__ void k_c2r_x_mr(GridParams g, const float2* spec, float* U, const float2* twf,
                            int lines_per_block);
+__global__ void k_r2c_x_mr_cells(const CellTab* tab, const int32_t* bcell, const int32_t* boff);
+__global__ void k_fft_y_mr_cells(const CellTab* tab, const int32_t* bcell, const int32_t* boff,
+                                 int inverse);
+__global__ void k_fft_z_mul_mr_cells(const CellTab* tab, const int32_t* bcell,
+                                     const int32_t* boff, int B);
+__global__ void k_c2r_x_mr_cells(const CellTab* tab, const int32_t* bcell, const int32_t* boff);
 
 // lanes per observer row of k_interp_tile (8 x 16 B = one 128 B line per
 // load; 4 and 16 measured slower)

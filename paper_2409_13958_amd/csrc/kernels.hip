@@ -1349,10 +1349,10 @@ __device__ float2* lds_fft_mr(float2* a, float2* b, int n, int lines, int ld, co
 
 // R2C along x, mixed radix: as k_r2c_x (pairs of real rows y, y + 1 as one
 // complex line, half spectrum of each), LDS: twiddles [Mx], two line buffers.
-__global__ void __launch_bounds__(256) k_r2c_x_mr(GridParams g, const float* __restrict__ Q,
-                                                  float2* __restrict__ spec,
-                                                  const float2* __restrict__ twf,
-                                                  int lines_per_block) {
+__device__ __forceinline__ void r2c_x_mr_body(GridParams g, const float* __restrict__ Q,
+                                              float2* __restrict__ spec,
+                                              const float2* __restrict__ twf,
+                                              int lines_per_block, const int blk) {
   extern __shared__ float2 sh[];
   const int Mx = g.M[0], Hx = Mx / 2 + 1;
   float2* tw = sh;
@@ -1361,7 +1361,7 @@ __global__ void __launch_bounds__(256) k_r2c_x_mr(GridParams g, const float* __r
   for (int i = threadIdx.x; i < Mx; i += blockDim.x) tw[i] = twf[i];
   const int pairs = (g.N[1] + 1) / 2;
   const int64_t total_lines = (int64_t)pairs * g.N[2];
-  const int64_t l0 = (int64_t)blockIdx.x * lines_per_block;
+  const int64_t l0 = (int64_t)blk * lines_per_block;
   const int nl = (int)((total_lines - l0) < lines_per_block ? (total_lines - l0) : lines_per_block);
   for (int idx = threadIdx.x; idx < nl * Mx; idx += blockDim.x) {
     const int li = idx / Mx, x = idx - li * Mx;
@@ -1390,10 +1390,25 @@ __global__ void __launch_bounds__(256) k_r2c_x_mr(GridParams g, const float* __r
   }
 }
 
+__global__ void __launch_bounds__(256) k_r2c_x_mr(GridParams g, const float* __restrict__ Q,
+                                                  float2* __restrict__ spec,
+                                                  const float2* __restrict__ twf,
+                                                  int lines_per_block) {
+  r2c_x_mr_body(g, Q, spec, twf, lines_per_block, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_r2c_x_mr_cells(const CellTab* __restrict__ tab,
+                                                        const int32_t* __restrict__ bcell,
+                                                        const int32_t* __restrict__ boff) {
+  const int c = bcell[blockIdx.x];
+  const CellTab& t = tab[c];
+  r2c_x_mr_body(t.g, t.grid, t.spec, t.twfx, t.lpb, blockIdx.x - boff[c]);
+}
+
 // FFT along y, mixed radix, as k_fft_y (B columns kx per block)
-__global__ void __launch_bounds__(256) k_fft_y_mr(GridParams g, float2* __restrict__ spec,
-                                                  const float2* __restrict__ twf, int B,
-                                                  int inverse, int n_in, int n_out) {
+__device__ __forceinline__ void fft_y_mr_body(GridParams g, float2* __restrict__ spec,
+                                              const float2* __restrict__ twf, int B, int inverse,
+                                              int n_in, int n_out, const int blk) {
   extern __shared__ float2 sh[];
   const int My = g.M[1], Hx = g.M[0] / 2 + 1;
   float2* tw = sh;
@@ -1401,8 +1416,8 @@ __global__ void __launch_bounds__(256) k_fft_y_mr(GridParams g, float2* __restri
   float2* Bf = A + B * My;
   for (int i = threadIdx.x; i < My; i += blockDim.x) tw[i] = twf[i];
   const int groups_per_plane = (Hx + B - 1) / B;
-  const int z = blockIdx.x / groups_per_plane;
-  const int kx0 = (blockIdx.x - z * groups_per_plane) * B;
+  const int z = blk / groups_per_plane;
+  const int kx0 = (blk - z * groups_per_plane) * B;
   const int nb = (Hx - kx0) < B ? (Hx - kx0) : B;
   for (int idx = threadIdx.x; idx < nb * My; idx += blockDim.x) {
     const int y = idx / nb, li = idx - y * nb;
@@ -1418,10 +1433,28 @@ __global__ void __launch_bounds__(256) k_fft_y_mr(GridParams g, float2* __restri
   }
 }
 
+__global__ void __launch_bounds__(256) k_fft_y_mr(GridParams g, float2* __restrict__ spec,
+                                                  const float2* __restrict__ twf, int B,
+                                                  int inverse, int n_in, int n_out) {
+  fft_y_mr_body(g, spec, twf, B, inverse, n_in, n_out, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_fft_y_mr_cells(const CellTab* __restrict__ tab,
+                                                        const int32_t* __restrict__ bcell,
+                                                        const int32_t* __restrict__ boff,
+                                                        int inverse) {
+  const int c = bcell[blockIdx.x];
+  const CellTab& t = tab[c];
+  const int ny = t.g.N[1], my = t.g.M[1];
+  fft_y_mr_body(t.g, t.spec, t.twfy, t.by, inverse, inverse ? my : ny, inverse ? ny : my,
+                blockIdx.x - boff[c]);
+}
+
 // FFT along z, K multiply, inverse FFT along z, mixed radix, as k_fft_z_mul
-__global__ void __launch_bounds__(256) k_fft_z_mul_mr(GridParams g, float2* __restrict__ spec,
-                                                      const float* __restrict__ khat,
-                                                      const float2* __restrict__ twf, int B) {
+__device__ __forceinline__ void fft_z_mul_mr_body(GridParams g, float2* __restrict__ spec,
+                                                  const float* __restrict__ khat,
+                                                  const float2* __restrict__ twf, int B,
+                                                  const int blk) {
   extern __shared__ float2 sh[];
   const int Mz = g.M[2], Hx = g.M[0] / 2 + 1;
   const int64_t plane = (int64_t)g.M[1] * Hx;
@@ -1429,7 +1462,7 @@ __global__ void __launch_bounds__(256) k_fft_z_mul_mr(GridParams g, float2* __re
   float2* A = sh + Mz;
   float2* Bf = A + B * Mz;
   for (int i = threadIdx.x; i < Mz; i += blockDim.x) tw[i] = twf[i];
-  const int64_t c0 = (int64_t)blockIdx.x * B;
+  const int64_t c0 = (int64_t)blk * B;
   const int nb = (int)((plane - c0) < B ? (plane - c0) : B);
   for (int idx = threadIdx.x; idx < nb * Mz; idx += blockDim.x) {
     const int z = idx / nb, li = idx - z * nb;
@@ -1452,11 +1485,26 @@ __global__ void __launch_bounds__(256) k_fft_z_mul_mr(GridParams g, float2* __re
   }
 }
 
+__global__ void __launch_bounds__(256) k_fft_z_mul_mr(GridParams g, float2* __restrict__ spec,
+                                                      const float* __restrict__ khat,
+                                                      const float2* __restrict__ twf, int B) {
+  fft_z_mul_mr_body(g, spec, khat, twf, B, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_fft_z_mul_mr_cells(const CellTab* __restrict__ tab,
+                                                            const int32_t* __restrict__ bcell,
+                                                            const int32_t* __restrict__ boff,
+                                                            int B) {
+  const int c = bcell[blockIdx.x];
+  const CellTab& t = tab[c];
+  fft_z_mul_mr_body(t.g, t.spec, t.khat, t.twfz, B, blockIdx.x - boff[c]);
+}
+
 // C2R along x, mixed radix, as k_c2r_x
-__global__ void __launch_bounds__(256) k_c2r_x_mr(GridParams g, const float2* __restrict__ spec,
-                                                  float* __restrict__ U,
-                                                  const float2* __restrict__ twf,
-                                                  int lines_per_block) {
+__device__ __forceinline__ void c2r_x_mr_body(GridParams g, const float2* __restrict__ spec,
+                                              float* __restrict__ U,
+                                              const float2* __restrict__ twf,
+                                              int lines_per_block, const int blk) {
   extern __shared__ float2 sh[];
   const int Mx = g.M[0], Hx = Mx / 2 + 1;
   float2* tw = sh;
@@ -1465,7 +1513,7 @@ __global__ void __launch_bounds__(256) k_c2r_x_mr(GridParams g, const float2* __
   for (int i = threadIdx.x; i < Mx; i += blockDim.x) tw[i] = twf[i];
   const int pairs = (g.N[1] + 1) / 2;
   const int64_t total_lines = (int64_t)pairs * g.N[2];
-  const int64_t l0 = (int64_t)blockIdx.x * lines_per_block;
+  const int64_t l0 = (int64_t)blk * lines_per_block;
   const int nl = (int)((total_lines - l0) < lines_per_block ? (total_lines - l0) : lines_per_block);
   for (int idx = threadIdx.x; idx < nl * Mx; idx += blockDim.x) {
     const int li = idx / Mx, k = idx - li * Mx;
@@ -1492,6 +1540,21 @@ __global__ void __launch_bounds__(256) k_c2r_x_mr(GridParams g, const float2* __
     grid_store(U, ((int64_t)z * g.N[1] + y) * g.N[0] + x, v.x, g);
     if (y + 1 < g.N[1]) grid_store(U, ((int64_t)z * g.N[1] + y + 1) * g.N[0] + x, v.y, g);
   }
+}
+
+__global__ void __launch_bounds__(256) k_c2r_x_mr(GridParams g, const float2* __restrict__ spec,
+                                                  float* __restrict__ U,
+                                                  const float2* __restrict__ twf,
+                                                  int lines_per_block) {
+  c2r_x_mr_body(g, spec, U, twf, lines_per_block, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_c2r_x_mr_cells(const CellTab* __restrict__ tab,
+                                                        const int32_t* __restrict__ bcell,
+                                                        const int32_t* __restrict__ boff) {
+  const int c = bcell[blockIdx.x];
+  const CellTab& t = tab[c];
+  c2r_x_mr_body(t.g, t.spec, t.grid, t.twfx, t.lpb, blockIdx.x - boff[c]);
 }
 
 // ---------------------------------------------------------------------------

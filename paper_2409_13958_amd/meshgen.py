@@ -337,16 +337,31 @@ def _pow2_at_least(v, lo):
     return n
 
 
+def _smooth_at_least(v, lo):
+    """Smallest n >= max(v, lo) whose prime factors are 2, 3, 5 and 7."""
+    n = max(int(v), int(lo))
+    while True:
+        k = n
+        for f in (2, 3, 5, 7):
+            while k % f == 0:
+                k //= f
+        if k == 1:
+            return n
+        n += 1
+
+
 def films_c4(n_films=256, seed=SEED0 + 3, nodes=(5e3, 8e4), period=(20.0 * NM, 200.0 * NM),
-             thickness=(2.0 * NM, 10.0 * NM), Ms=(4e5, 1.6e6), Aex=1.3e-11, jitter=0.15):
+             thickness=(2.0 * NM, 10.0 * NM), Ms=(4e5, 1.6e6), Aex=1.3e-11, jitter=0.15,
+             extents="smooth"):
     """Independent 2D-periodic films of uneven size (the batched-cell workload).
 
     Film i: node count log-uniform in ``nodes``, period L uniform in
     ``period`` (square cell, periodic in x and y), thickness t uniform in
     ``thickness``, Ms uniform in ``Ms``; a Kuhn lattice of nx = ny cells of
     side L/nx and nz = t/hz layers (cells as close to cubes as the node count
-    allows), jittered; the AIM grid takes the smallest power of two (at least
-    16) of points per period that is not coarser than the lattice, and 4 (8
+    allows), jittered; the AIM grid takes the smallest number of points per
+    period (at least 16) not coarser than the lattice whose prime factors are
+    2, 3, 5 and 7 (``extents="pow2"``: the smallest power of two), and 4 (8
     for five or more layers) across the thickness. The initial state is, in
     turn, a vortex (in-plane curl around the cell centre with an out-of-plane
     core of radius L/10), a uniform tilted state, or iid random directions.
@@ -377,7 +392,8 @@ def films_c4(n_films=256, seed=SEED0 + 3, nodes=(5e3, 8e4), period=(20.0 * NM, 2
             m = [np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)]
         else:
             m = "random"
-        grid = (_pow2_at_least(nx, 16), _pow2_at_least(nx, 16), 8 if nz >= 5 else 4)
+        nper = _pow2_at_least(nx, 16) if extents == "pow2" else _smooth_at_least(nx, 16)
+        grid = (nper, nper, 8 if nz >= 5 else 4)
         out.append(kuhn_box((nx, nx, nz), [hxy, hxy, hz], periodic=0b011, jitter=jitter,
                             seed=seed + 1 + i, Ms=ms, Aex=Aex, grid=grid, m=m,
                             name=f"film_c4_{i}"))

@@ -4,8 +4,9 @@ A batch evaluates all its cells with one launch per stage (block-diagonal
 local operators, multi-cell grid kernels). Per cell the arithmetic is that of
 a single-cell evaluation with the same kernel forms and SpMV lanes, so the
 packed results must equal the per-cell calls bit for bit, for H_eff and for
-RK4 steps, on cells of every periodicity, two materials and uneven sizes;
-two cells are also checked against the FP64 oracle.
+RK4 steps, on cells of every periodicity, two materials, uneven sizes and
+every FFT form (whole planes, per-axis radix 2, mixed radix 2, 3, 5, 7); two
+cells are also checked against the FP64 oracle.
 
 An earlier graph-captured batch (each cell's work captured on its own branch
 of one HIP graph, then replayed) crashed the host process (segmentation
@@ -147,6 +148,10 @@ def batch_cells():
     # a 256 x 256 plane does not fit in LDS: this cell takes the per-axis FFT
     # passes inside the batch
     probs.append(mg.kuhn_box((4, 4, 1), 2e-9, periodic=0b011, jitter=0.1, grid=(256, 256, 4)))
+    # extents with factors 3, 5 and 7: the mixed-radix passes inside the batch
+    # (the films above have such extents too)
+    probs.append(mg.kuhn_box((6, 5, 2), 1e-9, periodic=0b011, jitter=0.2, grid=(12, 20, 6)))
+    probs.append(mg.kuhn_box((5, 6, 5), 1e-9, periodic=0b111, jitter=0.2, grid=(15, 14, 21)))
     out = []
     for p in probs:
         ctx = B.Context.from_problem(p, device=0)
@@ -184,8 +189,8 @@ def test_batch_heff_equals_per_cell_calls():
     for k in range(len(cs)):
         assert torch.equal(h[off[k]:off[k + 1]], ref[k]), k
         assert torch.equal(hms[off[k]:off[k + 1]], ref_ms[k]), k
-    # two cells against the FP64 oracle
-    for k in (0, 3):
+    # three cells against the FP64 oracle, the last a mixed-radix one
+    for k in (0, 3, len(cs) - 1):
         p, ctx, nou = cs[k]
         orc = model.Oracle(p)
         r = orc.heff(orc.unknown_values(p.m), method="aim")[orc.uk[nou]]

@@ -405,3 +405,37 @@ def test_scatter_tiles_map_every_stencil_point(pair):
                     if per[a]:
                         want %= N[a]
                     assert gi == want, (w, node, a, c)
+
+
+def test_batched_films_build_with_smooth_extents():
+    """The batched-film generator gives every film an in-plane FFT extent with
+    factors 2, 3, 5 and 7 only (at least 16; most of them not powers of two),
+    and each such film builds on the host (plans and operators)."""
+    films = mg.films_c4(12, nodes=(2e3, 6e3), period=(20e-9, 60e-9))
+    for f in films:
+        n = f.grid[0]
+        k = n
+        for p in (2, 3, 5, 7):
+            while k % p == 0:
+                k //= p
+        assert k == 1 and n >= 16 and f.grid[1] == n
+        ctx = _ctx(f)
+        assert ctx.query()[0] > 0
+        ctx.export("sc_plan")        # EGRID if the scatter tiles do not fit
+    assert sum(1 for f in films if f.grid[0] & (f.grid[0] - 1)) >= 6
+
+
+@pytest.mark.parametrize("n", [21, 35, 49, 125])
+def test_scatter_tiles_on_odd_periodic_extents(n):
+    """Periodic extents that the preferred tile (8 boxes) does not divide: the
+    preferred tiles with a short last one where no grid point then lies in
+    three footprints, else the divisor closest to 8 (at least p + 1; 49 has
+    no divisor from 8 to 46 and takes 7, which the upward-only search missed)."""
+    prob = mg.kuhn_box((4, 4, 1), n * 1e-10, periodic=0b011, jitter=0.1, grid=(n, n, 4))
+    ctx = _ctx(prob)
+    plan = ctx.export("sc_plan")       # EGRID if no tiling fits
+    tb, nt = plan[0:3], plan[3:6]
+    assert tb[0] == tb[1] and (tb[0] == 8 or n % tb[0] == 0)
+    assert nt[0] == -(-n // tb[0])
+    if n == 49:
+        assert tb[0] == 7
