@@ -17,6 +17,10 @@ using namespace pmfem;
 
 // launch shapes (each the best of the measured alternatives on MI355X)
 constexpr int kFftzB = 8;            // z columns per workgroup of the z pass
+// z columns per workgroup of the mixed-radix z pass (short columns: many)
+constexpr int kFftzMr = 64;
+// threads of a mixed-radix plane workgroup
+constexpr int kFftPlaneMrT = 512;
 constexpr int kFftzT = 256;          // threads per workgroup of the z pass
 constexpr int kFftSplit = 2;         // workgroups per z-plane in the plane transforms
 constexpr int kIcLdsBudget = 24576;  // LDS bytes per interpolation tile
@@ -661,20 +665,25 @@ int upload_all(pmfem_ctx* c) {
     if (o.M[a] & (o.M[a] - 1)) d->fft_mr = true;
   {
     // whole-plane x/y transforms when a plane (row pairs + half-spectrum
-    // columns) fits in one workgroup's LDS (radix-2 extents only)
+    // columns) fits in one workgroup's LDS: radix 2 in place with half
+    // twiddle tables, mixed radix with full tables and two buffers
     const int Mx = o.M[0], My = o.M[1], Hx = Mx / 2 + 1, pairs = (o.N[1] + 1) / 2;
+    const size_t cap = std::max((size_t)pairs * Mx, (size_t)Hx * My);
     d->fft_plane_lds =
-        (size_t)(Mx / 2 + My / 2 + (size_t)pairs * Mx + (size_t)Hx * (My + 1)) * sizeof(float2);
+        d->fft_mr ? (size_t)(Mx + My + 2 * cap) * sizeof(float2)
+                  : (size_t)(Mx / 2 + My / 2 + (size_t)pairs * Mx + (size_t)Hx * (My + 1)) *
+                        sizeof(float2);
     int max_lds = 0;
     (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
-    d->fft_ok = !d->fft_mr && d->fft_plane_lds <= (size_t)max_lds;
+    d->fft_ok = d->fft_plane_lds <= (size_t)max_lds;
     if (d->fft_ok && d->fft_plane_lds > 65536) {
       const int b = (int)d->fft_plane_lds;
-      d->fft_ok =
-          hipFuncSetAttribute((const void*)k_fft_xy_fwd, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              b) == hipSuccess &&
-          hipFuncSetAttribute((const void*)k_fft_yx_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              b) == hipSuccess;
+      const void* fwd = d->fft_mr ? (const void*)k_fft_xy_fwd_mr : (const void*)k_fft_xy_fwd;
+      const void* inv = d->fft_mr ? (const void*)k_fft_yx_inv_mr : (const void*)k_fft_yx_inv;
+      d->fft_ok = hipFuncSetAttribute(fwd, hipFuncAttributeMaxDynamicSharedMemorySize, b) ==
+                      hipSuccess &&
+                  hipFuncSetAttribute(inv, hipFuncAttributeMaxDynamicSharedMemorySize, b) ==
+                      hipSuccess;
       (void)hipGetLastError();
     }
   }
@@ -871,6 +880,24 @@ void convolve(pmfem_dev* d, hipStream_t s, const float* Qg, float* Ug, float2* s
   const int Mx = g.M[0], My = g.M[1], Mz = g.M[2], Hx = Mx / 2 + 1;
   const int Bz = std::max(1, std::min(kFftzB, 4096 / Mz)), Tz = kFftzT;
   const int64_t cols = (int64_t)My * Hx;
+  if (d->fft_plane && d->fft_mr) {
+    // whole planes in LDS for x and y, the mixed-radix z pass between them
+    const int Bzm = std::max(1, std::min(kFftzMr, 2048 / Mz));
+    mark(2, 0);
+    hipLaunchKernelGGL(k_fft_xy_fwd_mr, dim3((unsigned)g.N[2]), dim3(kFftPlaneMrT),
+                       d->fft_plane_lds, s, g, Qg, spec, d->twfx, d->twfy);
+    mark(2, 1);
+    mark(4, 0);
+    hipLaunchKernelGGL(k_fft_z_mul_mr, dim3((unsigned)((cols + Bzm - 1) / Bzm)), dim3(kFftzT),
+                       (size_t)(Mz + 2 * Bzm * Mz) * sizeof(float2), s, g, spec, d->khat, d->twfz,
+                       Bzm);
+    mark(4, 1);
+    mark(6, 0);
+    hipLaunchKernelGGL(k_fft_yx_inv_mr, dim3((unsigned)g.N[2]), dim3(kFftPlaneMrT),
+                       d->fft_plane_lds, s, g, (const float2*)spec, Ug, d->twfx, d->twfy);
+    mark(6, 1);
+    return;
+  }
   if (d->fft_plane) {
     mark(2, 0);
     hipLaunchKernelGGL(k_fft_xy_fwd, dim3((unsigned)(g.N[2] * kFftSplit)), dim3(1024),
@@ -894,7 +921,7 @@ void convolve(pmfem_dev* d, hipStream_t s, const float* Qg, float* Ug, float2* s
     const int64_t xlines = (int64_t)((g.N[1] + 1) / 2) * g.N[2];
     const int By = std::max(1, std::min(16, 2048 / My));
     const int gy = (Hx + By - 1) / By;
-    const int Bzm = std::max(1, std::min(kFftzB, 2048 / Mz));
+    const int Bzm = std::max(1, std::min(kFftzMr, 2048 / Mz));
     mark(2, 0);
     hipLaunchKernelGGL(k_r2c_x_mr, dim3((unsigned)((xlines + lpb - 1) / lpb)), dim3(T),
                        (size_t)(Mx + 2 * lpb * Mx) * sizeof(float2), s, g, Qg, spec, d->twfx, lpb);
@@ -1686,10 +1713,10 @@ struct pmfem_batch {
     int32_t* bcell = nullptr;
     int32_t* boff = nullptr;
     unsigned blocks = 0;
-  } sc, sum, xy, zm, yx, ic, r2c, fy, c2r, r2c_mr, fy_mr, zm_mr;
+  } sc, sum, xy, zm, yx, ic, r2c, fy, c2r, r2c_mr, fy_mr, zm_mr, xy_mr;
   size_t lds_sc = 0, lds_plane = 0, lds_z = 0, lds_ic = 0, lds_r2c = 0, lds_fy = 0;
-  size_t lds_r2c_mr = 0, lds_fy_mr = 0, lds_z_mr = 0;
-  int p = 3, W = 5, KC = 2, PT = 4, Bz = 8, Bzm = 8;
+  size_t lds_r2c_mr = 0, lds_fy_mr = 0, lds_z_mr = 0, lds_plane_mr = 0;
+  int p = 3, W = 5, KC = 2, PT = 4, Bz = 8, Bzm = kFftzMr;
   double bytes = 0.0;
   std::vector<void*> allocs;
   std::string err;
@@ -1827,7 +1854,7 @@ int batch_setup(pmfem_batch* b, int32_t spmv_lanes) {
   // the cell table and the launch tables of the grid kernels
   std::vector<CellTab> tab(K);
   std::vector<int64_t> nsc(K), nsum(K), nxy(K), nzm(K), nic(K), nr2c(K), nfy(K), nr2c_mr(K),
-      nfy_mr(K), nzm_mr(K);
+      nfy_mr(K), nzm_mr(K), nxy_mr(K);
   b->p = b->cells[0]->dev->g.p;
   b->W = 2 * b->cells[0]->dev->g.rb + 1;
   b->PT = 4;
@@ -1879,8 +1906,13 @@ int batch_setup(pmfem_batch* b, int32_t spmv_lanes) {
     // (radix 2, or mixed radix where an extent is not a power of two)
     t.lpb = std::max(1, 2048 / g.M[0]);
     t.by = std::max(1, std::min(16, 4096 / g.M[1]));
-    nr2c_mr[c] = nfy_mr[c] = 0;
-    if (d->fft_mr) {
+    nr2c_mr[c] = nfy_mr[c] = nxy_mr[c] = 0;
+    if (d->fft_mr && d->fft_ok) {
+      nxy[c] = nr2c[c] = nfy[c] = 0;
+      nxy_mr[c] = g.N[2];
+      b->lds_plane_mr = std::max(b->lds_plane_mr, d->fft_plane_lds);
+      b->Bzm = std::min(b->Bzm, std::max(1, std::min(kFftzMr, 2048 / g.M[2])));
+    } else if (d->fft_mr) {
       nxy[c] = nr2c[c] = nfy[c] = 0;
       t.by = std::max(1, std::min(16, 2048 / g.M[1]));
       const int64_t xlines = (int64_t)((g.N[1] + 1) / 2) * g.N[2];
@@ -1889,7 +1921,7 @@ int batch_setup(pmfem_batch* b, int32_t spmv_lanes) {
       b->lds_r2c_mr =
           std::max(b->lds_r2c_mr, (size_t)(g.M[0] + 2 * t.lpb * g.M[0]) * sizeof(float2));
       b->lds_fy_mr = std::max(b->lds_fy_mr, (size_t)(g.M[1] + 2 * t.by * g.M[1]) * sizeof(float2));
-      b->Bzm = std::min(b->Bzm, std::max(1, std::min(kFftzB, 2048 / g.M[2])));
+      b->Bzm = std::min(b->Bzm, std::max(1, std::min(kFftzMr, 2048 / g.M[2])));
     } else if (d->fft_ok) {
       nxy[c] = (int64_t)g.N[2] * kFftSplit;
       nr2c[c] = nfy[c] = 0;
@@ -1928,8 +1960,17 @@ int batch_setup(pmfem_batch* b, int32_t spmv_lanes) {
       (rc = batch_launch_table(b, nfy, b->fy)) || (rc = batch_launch_table(b, nr2c, b->c2r)) ||
       (rc = batch_launch_table(b, nr2c_mr, b->r2c_mr)) ||
       (rc = batch_launch_table(b, nfy_mr, b->fy_mr)) ||
-      (rc = batch_launch_table(b, nzm_mr, b->zm_mr)))
+      (rc = batch_launch_table(b, nzm_mr, b->zm_mr)) ||
+      (rc = batch_launch_table(b, nxy_mr, b->xy_mr)))
     return rc;
+  if (b->lds_plane_mr > 65536) {
+    const int lb = (int)b->lds_plane_mr;
+    if (hipFuncSetAttribute((const void*)k_fft_xy_fwd_mr_cells,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lb) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_fft_yx_inv_mr_cells,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lb) != hipSuccess)
+      return batch_err(b, PMFEM_EINVAL, "FFT planes of the batch do not fit in LDS");
+  }
   if (b->lds_plane > 65536) {
     const int lb = (int)b->lds_plane;
     if (hipFuncSetAttribute((const void*)k_fft_xy_fwd_cells,
@@ -2030,14 +2071,25 @@ int batch_heff(pmfem_batch* b, const float* m, float* h, uint32_t terms) {
       hipLaunchKernelGGL(k_fft_y_cells, dim3(b->fy.blocks), dim3(T), b->lds_fy, s, tab,
                          (const int32_t*)b->fy.bcell, (const int32_t*)b->fy.boff, 0);
     }
+    if (b->xy_mr.blocks)
+      hipLaunchKernelGGL(k_fft_xy_fwd_mr_cells, dim3(b->xy_mr.blocks), dim3(kFftPlaneMrT),
+                         b->lds_plane_mr, s, tab, (const int32_t*)b->xy_mr.bcell,
+                         (const int32_t*)b->xy_mr.boff);
     if (b->r2c_mr.blocks) {
       hipLaunchKernelGGL(k_r2c_x_mr_cells, dim3(b->r2c_mr.blocks), dim3(T), b->lds_r2c_mr, s, tab,
                          (const int32_t*)b->r2c_mr.bcell, (const int32_t*)b->r2c_mr.boff);
       hipLaunchKernelGGL(k_fft_y_mr_cells, dim3(b->fy_mr.blocks), dim3(T), b->lds_fy_mr, s, tab,
                          (const int32_t*)b->fy_mr.bcell, (const int32_t*)b->fy_mr.boff, 0);
+    }
+    if (b->zm_mr.blocks)
       hipLaunchKernelGGL(k_fft_z_mul_mr_cells, dim3(b->zm_mr.blocks), dim3(kFftzT), b->lds_z_mr,
                          s, tab, (const int32_t*)b->zm_mr.bcell, (const int32_t*)b->zm_mr.boff,
                          b->Bzm);
+    if (b->xy_mr.blocks)
+      hipLaunchKernelGGL(k_fft_yx_inv_mr_cells, dim3(b->xy_mr.blocks), dim3(kFftPlaneMrT),
+                         b->lds_plane_mr, s, tab, (const int32_t*)b->xy_mr.bcell,
+                         (const int32_t*)b->xy_mr.boff);
+    if (b->r2c_mr.blocks) {
       hipLaunchKernelGGL(k_fft_y_mr_cells, dim3(b->fy_mr.blocks), dim3(T), b->lds_fy_mr, s, tab,
                          (const int32_t*)b->fy_mr.bcell, (const int32_t*)b->fy_mr.boff, 1);
       hipLaunchKernelGGL(k_c2r_x_mr_cells, dim3(b->r2c_mr.blocks), dim3(T), b->lds_r2c_mr, s, tab,

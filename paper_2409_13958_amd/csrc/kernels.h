@@ -129,6 +129,14 @@ __global__ void k_fft_z_mul_mr(GridParams g, float2* spec, const float* khat, co
                                int B);
 __global__ void k_c2r_x_mr(GridParams g, const float2* spec, float* U, const float2* twf,
                            int lines_per_block);
+__global__ void k_fft_xy_fwd_mr(GridParams g, const float* Q, float2* spec, const float2* twfx,
+                                const float2* twfy);
+__global__ void k_fft_yx_inv_mr(GridParams g, const float2* spec, float* U, const float2* twfx,
+                                const float2* twfy);
+__global__ void k_fft_xy_fwd_mr_cells(const CellTab* tab, const int32_t* bcell,
+                                      const int32_t* boff);
+__global__ void k_fft_yx_inv_mr_cells(const CellTab* tab, const int32_t* bcell,
+                                      const int32_t* boff);
 __global__ void k_r2c_x_mr_cells(const CellTab* tab, const int32_t* bcell, const int32_t* boff);
 __global__ void k_fft_y_mr_cells(const CellTab* tab, const int32_t* bcell, const int32_t* boff,
                                  int inverse);

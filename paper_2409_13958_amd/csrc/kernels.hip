@@ -1347,6 +1347,142 @@ __device__ float2* lds_fft_mr(float2* a, float2* b, int n, int lines, int ld, co
   return a;
 }
 
+// Whole z-plane x and y passes, mixed radix (as k_fft_xy_fwd / k_fft_yx_inv
+// for powers of two): one workgroup per plane; LDS: the two twiddle tables
+// and two buffers of max(pairs Mx, Hx My) values. Forward: the pairs of real
+// rows as complex lines along x, their half spectra unpacked into the
+// columns of the plane, the columns along y. Inverse: the columns along y,
+// the pairs of rows rebuilt as complex lines with the Hermitian half, the
+// lines along x.
+__device__ __forceinline__ void fft_xy_fwd_mr_body(GridParams g, const float* __restrict__ Q,
+                                                   float2* __restrict__ spec,
+                                                   const float2* __restrict__ twfx,
+                                                   const float2* __restrict__ twfy,
+                                                   const int blk) {
+  extern __shared__ float2 sh[];
+  const int Mx = g.M[0], My = g.M[1], Hx = Mx / 2 + 1, Ny = g.N[1];
+  const int pairs = (Ny + 1) / 2;
+  const int cap = max(pairs * Mx, Hx * My);
+  float2* twx = sh;
+  float2* twy = twx + Mx;
+  float2* A = twy + My;
+  float2* Bf = A + cap;
+  for (int i = threadIdx.x; i < Mx; i += blockDim.x) twx[i] = twfx[i];
+  for (int i = threadIdx.x; i < My; i += blockDim.x) twy[i] = twfy[i];
+  const int z = blk;
+  for (int idx = threadIdx.x; idx < pairs * Mx; idx += blockDim.x) {
+    const int l = idx / Mx, x = idx - l * Mx, y = 2 * l;
+    float re = 0.f, im = 0.f;
+    if (x < g.N[0]) {
+      re = grid_load(Q, ((int64_t)z * Ny + y) * g.N[0] + x, g);
+      if (y + 1 < Ny) im = grid_load(Q, ((int64_t)z * Ny + y + 1) * g.N[0] + x, g);
+    }
+    A[idx] = make_float2(re, im);
+  }
+  __syncthreads();
+  const float2* R = lds_fft_mr(A, Bf, Mx, pairs, Mx, twx, 1.0f);
+  float2* C = R == A ? Bf : A;
+  float2* D = R == A ? A : Bf;
+  // X_y = (Z[k] + conj Z[-k]) / 2, X_{y+1} = (Z[k] - conj Z[-k]) / (2i), as
+  // the columns C[kx My + y], zero past the rows
+  for (int idx = threadIdx.x; idx < Hx * My; idx += blockDim.x) {
+    const int kx = idx / My, y = idx - kx * My;
+    float2 v = make_float2(0.f, 0.f);
+    if (y < Ny) {
+      const int l = y >> 1;
+      const float2 a = R[l * Mx + kx];
+      const float2 b = R[l * Mx + (kx == 0 ? 0 : Mx - kx)];
+      v = (y & 1) ? make_float2(0.5f * (a.y + b.y), -0.5f * (a.x - b.x))
+                  : make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y));
+    }
+    C[idx] = v;
+  }
+  __syncthreads();
+  const float2* S = lds_fft_mr(C, D, My, Hx, My, twy, 1.0f);
+  for (int idx = threadIdx.x; idx < My * Hx; idx += blockDim.x) {
+    const int ky = idx / Hx, kx = idx - ky * Hx;
+    spec[((int64_t)z * My + ky) * Hx + kx] = S[kx * My + ky];
+  }
+}
+
+__device__ __forceinline__ void fft_yx_inv_mr_body(GridParams g, const float2* __restrict__ spec,
+                                                   float* __restrict__ U,
+                                                   const float2* __restrict__ twfx,
+                                                   const float2* __restrict__ twfy,
+                                                   const int blk) {
+  extern __shared__ float2 sh[];
+  const int Mx = g.M[0], My = g.M[1], Hx = Mx / 2 + 1, Ny = g.N[1];
+  const int pairs = (Ny + 1) / 2;
+  const int cap = max(pairs * Mx, Hx * My);
+  float2* twx = sh;
+  float2* twy = twx + Mx;
+  float2* A = twy + My;
+  float2* Bf = A + cap;
+  for (int i = threadIdx.x; i < Mx; i += blockDim.x) twx[i] = twfx[i];
+  for (int i = threadIdx.x; i < My; i += blockDim.x) twy[i] = twfy[i];
+  const int z = blk;
+  for (int idx = threadIdx.x; idx < My * Hx; idx += blockDim.x) {
+    const int ky = idx / Hx, kx = idx - ky * Hx;
+    A[kx * My + ky] = spec[((int64_t)z * My + ky) * Hx + kx];
+  }
+  __syncthreads();
+  const float2* R = lds_fft_mr(A, Bf, My, Hx, My, twy, -1.0f);
+  float2* L = R == A ? Bf : A;
+  float2* D = R == A ? A : Bf;
+  // Z = X_y + i X_{y+1} over the full line, X[k] = conj X[Mx - k] for k >= Hx
+  for (int idx = threadIdx.x; idx < pairs * Mx; idx += blockDim.x) {
+    const int l = idx / Mx, k = idx - l * Mx, y = 2 * l;
+    const int kk = k < Hx ? k : Mx - k;
+    float2 a = R[kk * My + y];
+    float2 b = make_float2(0.f, 0.f);
+    if (y + 1 < Ny) b = R[kk * My + y + 1];
+    if (k >= Hx) {
+      a.y = -a.y;
+      b.y = -b.y;
+    }
+    L[idx] = make_float2(a.x - b.y, a.y + b.x);
+  }
+  __syncthreads();
+  const float2* S = lds_fft_mr(L, D, Mx, pairs, Mx, twx, -1.0f);
+  for (int idx = threadIdx.x; idx < pairs * g.N[0]; idx += blockDim.x) {
+    const int l = idx / g.N[0], x = idx - l * g.N[0], y = 2 * l;
+    const float2 v = S[l * Mx + x];
+    grid_store(U, ((int64_t)z * Ny + y) * g.N[0] + x, v.x, g);
+    if (y + 1 < Ny) grid_store(U, ((int64_t)z * Ny + y + 1) * g.N[0] + x, v.y, g);
+  }
+}
+
+__global__ void __launch_bounds__(512) k_fft_xy_fwd_mr(GridParams g, const float* __restrict__ Q,
+                                                       float2* __restrict__ spec,
+                                                       const float2* __restrict__ twfx,
+                                                       const float2* __restrict__ twfy) {
+  fft_xy_fwd_mr_body(g, Q, spec, twfx, twfy, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(512) k_fft_yx_inv_mr(GridParams g,
+                                                       const float2* __restrict__ spec,
+                                                       float* __restrict__ U,
+                                                       const float2* __restrict__ twfx,
+                                                       const float2* __restrict__ twfy) {
+  fft_yx_inv_mr_body(g, spec, U, twfx, twfy, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(512) k_fft_xy_fwd_mr_cells(const CellTab* __restrict__ tab,
+                                                             const int32_t* __restrict__ bcell,
+                                                             const int32_t* __restrict__ boff) {
+  const int c = bcell[blockIdx.x];
+  const CellTab& t = tab[c];
+  fft_xy_fwd_mr_body(t.g, t.grid, t.spec, t.twfx, t.twfy, blockIdx.x - boff[c]);
+}
+
+__global__ void __launch_bounds__(512) k_fft_yx_inv_mr_cells(const CellTab* __restrict__ tab,
+                                                             const int32_t* __restrict__ bcell,
+                                                             const int32_t* __restrict__ boff) {
+  const int c = bcell[blockIdx.x];
+  const CellTab& t = tab[c];
+  fft_yx_inv_mr_body(t.g, t.spec, t.grid, t.twfx, t.twfy, blockIdx.x - boff[c]);
+}
+
 // R2C along x, mixed radix: as k_r2c_x (pairs of real rows y, y + 1 as one
 // complex line, half spectrum of each), LDS: twiddles [Mx], two line buffers.
 __device__ __forceinline__ void r2c_x_mr_body(GridParams g, const float* __restrict__ Q,

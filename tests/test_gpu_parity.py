@@ -249,12 +249,13 @@ def test_heff_parity_mixed_radix(name):
     ref = dict(h=orc.heff(m, method="aim"), hms=orc.heff(m, method="aim", terms=("ms",)),
                u=orc.potential(m, None, "aim"))
     tried = 0
-    for anterp in (0, 1, 2, 3):
+    for anterp, fft in ((0, 0), (1, 1), (2, 2), (3, 1)):
         ctx = B.Context.from_problem(prob, device=0)
         try:
             ctx.set_variant("anterp", anterp)
         except B.PmfemError:
             continue                     # this form's plan does not fit the grid
+        ctx.set_variant("fft", fft)
         tried += 1
         n, uon, nou, _ = ctx.query()
         mt = torch.tensor(prob.m[nou], dtype=torch.float32, device="cuda")
@@ -265,7 +266,7 @@ def test_heff_parity_mixed_radix(name):
         perm = orc.uk[nou]
         got = dict(h=h, hms=hms, u=u)
         errs = {k: rel(got[k].cpu().numpy().astype(np.float64), r[perm]) for k, r in ref.items()}
-        print(f"[gpu parity] {name} anterp={anterp} rel L2: "
+        print(f"[gpu parity] {name} anterp={anterp} fft={fft} rel L2: "
               + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
         for k, v in errs.items():
             assert v <= TOL, (anterp, k, v)
@@ -274,15 +275,21 @@ def test_heff_parity_mixed_radix(name):
 
 @pytest.mark.parametrize("case", sorted(MIXED))
 def test_grid_convolution_mixed_radix(case):
+    """Both forms of the mixed-radix passes: whole planes in LDS for x and y
+    (fft 2) and one axis per pass (fft 1)."""
     prob = MIXED[case]()
-    ctx = B.Context.from_problem(prob, device=0)
     orc = model.Oracle(prob)
     N = orc.aim.grid.N
     Q = np.random.default_rng(5).standard_normal(tuple(N))
-    qg = torch.tensor(Q.transpose(2, 1, 0).copy(), dtype=torch.float32, device="cuda")
-    ug = torch.empty_like(qg)
-    ctx.grid_convolve(qg, ug)
-    U = ug.cpu().numpy().astype(np.float64).transpose(2, 1, 0)
-    err = rel(U, orc.aim.convolve(Q) / (4 * np.pi))
-    print(f"[gpu parity] convolution {case} (mixed radix): rel L2 {err:.2e}", flush=True)
-    assert err <= 1e-6
+    ref = orc.aim.convolve(Q) / (4 * np.pi)
+    for fft in (2, 1):
+        ctx = B.Context.from_problem(prob, device=0)
+        ctx.set_variant("fft", fft)
+        qg = torch.tensor(Q.transpose(2, 1, 0).copy(), dtype=torch.float32, device="cuda")
+        ug = torch.empty_like(qg)
+        ctx.grid_convolve(qg, ug)
+        U = ug.cpu().numpy().astype(np.float64).transpose(2, 1, 0)
+        err = rel(U, ref)
+        print(f"[gpu parity] convolution {case} (mixed radix, fft={fft}): rel L2 {err:.2e}",
+              flush=True)
+        assert err <= 1e-6
