@@ -109,8 +109,8 @@ int pmfem_set_periodicity(pmfem_ctx* ctx, uint32_t axis_mask, const double L[3],
  * grid spacing is L/N and the FFT extent is N; on a non-periodic axis the
  * grid spans the mesh and the FFT extent is 2N. FFT extents must be
  * products of the factors 2, 3, 5 and 7 in [4, 512] (powers of two take the
- * radix-2 passes, with whole z-planes in LDS where they fit; the others the
- * mixed-radix per-axis passes); periodic axes need N >= 2 (r_b + p) + 1.
+ * radix-2 passes, the others mixed-radix passes; both with x and y of whole
+ * z-planes in LDS where a plane fits); periodic axes need N >= 2 (r_b + p) + 1.
  */
 int pmfem_set_aim(pmfem_ctx* ctx, const int32_t grid[3], int32_t order_p, int32_t near_boxes,
                   double z0_radius_edges, int32_t precision);
