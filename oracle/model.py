@@ -33,6 +33,8 @@ Sec. 2.2); ``implicit_midpoint`` is that rule written out plainly: each step
 solves x = m + dt f((m + x)/2) by Newton's method with the exact Jacobian
 (the field is linear in m, so H = A m + H_app with A assembled densely on
 small meshes) and a dense linear solve; the rule keeps |m| by itself.
+``implicit_midpoint_adaptive`` and ``implicit_bdf2_adaptive`` add the
+paper's time-step control (Sec. 2.2, Sec. 5) as predictor-corrector pairs.
 """
 from __future__ import annotations
 
@@ -458,6 +460,135 @@ class Oracle:
             m = x
             t += dt_try
             info["dts"].append(dt_try)
+            info["lte"].append(est)
+            info["newton"].append(its)
+            dt = dt_new
+        info["dt_next"] = dt
+        return m, info
+
+    # -- step-size-adaptive BDF2 -------------------------------------------
+    @staticmethod
+    def bdf2_coefficients(h, h1):
+        """Variable-step BDF2 from y_n (step h1 before it: y_{n-1}): the new
+        state solves x = r + beta h f(x) with r = a y_n - b y_{n-1}; the
+        coefficients make the quadratic through the three states have slope
+        f(x) at the new point. With w = h / h1: a = (1 + w)^2 / (1 + 2 w),
+        b = w^2 / (1 + 2 w), beta = (1 + w) / (1 + 2 w)."""
+        w = h / h1
+        return (1 + w) ** 2 / (1 + 2 * w), w * w / (1 + 2 * w), (1 + w) / (1 + 2 * w)
+
+    @staticmethod
+    def bdf2_estimate_factor(h, h1, h2):
+        """Local error of a BDF2 step from the gap between the corrector and
+        the quadratic extrapolation of the last three states. Along the rule's
+        own trajectory z the scheme's relation holds exactly, which makes z
+        the solution of y' = f(y) + (z'''/6) h (h + h1); over the step that
+        is a deviation of (1/6) h^2 (h + h1) y''' from the exact flow through
+        the current state, while the extrapolation misses z(t + h) by
+        (1/6) h (h + h1) (h + h1 + h2) y'''. Their ratio is h / (h + h1 + h2)."""
+        return h / (h + h1 + h2)
+
+    def implicit_bdf2_adaptive(self, m, t_end, dt0, alpha, lte_tol, method="aim",
+                               terms=("ex", "ms"), h_app=None, tol=1e-13, max_newton=10,
+                               A=None, max_steps=100000, record=False):
+        """Time-step adaptive BDF2 (the paper's timed dynamics run uses a
+        step-adaptive BDF scheme, Sec. 2.2 and Sec. 5; its formulas are this
+        oracle's reading), a predictor-corrector pair like
+        ``implicit_midpoint_adaptive``:
+
+        * the first step is backward Euler (x = m + h f(x)) from the
+          predictor m; the later ones BDF2 (``bdf2_coefficients``);
+        * predictor: the line through the last two states (second step) or
+          the quadratic through the last three, extrapolated to t + h;
+        * corrector: Newton from the predictor (exact dense Jacobian of
+          x - r - beta h f(x)), converged at residual rms <= tol; a failure
+          halves the step;
+        * from the third accepted step on, E = ``bdf2_estimate_factor`` times
+          rms(x_c - x_p); E > lte_tol rejects the step; step control and the
+          renormalisation of each accepted state as in the midpoint version.
+
+        Returns (m, info) as ``implicit_midpoint_adaptive``; with ``record``,
+        info["states"] holds the initial and every accepted state."""
+        n = self.n
+        A = self.field_matrix(method, terms) if A is None else A
+        b = np.zeros(3) if h_app is None else np.asarray(h_app, dtype=np.float64)
+        c = -GAMMA0 / (1 + alpha * alpha)
+        m = np.array(m, dtype=np.float64, copy=True)
+        rms = np.sqrt(3.0 * n)
+
+        def newton(x, r, bh):
+            g0 = None
+            for it in range(max_newton + 1):
+                H = (A @ x.ravel()).reshape(n, 3) + b[None, :]
+                mxh = np.cross(x, H)
+                G = x - r - bh * c * (mxh + alpha * np.cross(x, mxh))
+                g = np.linalg.norm(G) / rms
+                if g <= tol:
+                    return x, it
+                if it == max_newton or not np.isfinite(g) or (g0 is not None and g > 3 * g0):
+                    return None, it
+                g0 = g if g0 is None else g0
+                CH, CM, CMH = self._cross_matrix(H), self._cross_matrix(x), self._cross_matrix(mxh)
+                local = -CH - alpha * CMH - alpha * CM @ CH
+                left = CM + alpha * CM @ CM
+                J = np.zeros((3 * n, 3 * n))
+                for k in range(n):
+                    J[3 * k:3 * k + 3, 3 * k:3 * k + 3] += local[k]
+                    J[3 * k:3 * k + 3, :] += left[k] @ A[3 * k:3 * k + 3, :]
+                dG = np.eye(3 * n) - bh * c * J
+                x = x - np.linalg.solve(dG, G.ravel()).reshape(n, 3)
+            return None, max_newton
+
+        t, dt = 0.0, float(dt0)
+        hist = []                                    # [(state, step from it)], latest first
+        info = dict(dts=[], lte=[], newton=[], rejected=0, dt_next=dt)
+        if record:
+            info["states"] = [m.copy()]
+        while t_end - t > 1e-12 * t_end:
+            if len(info["dts"]) >= max_steps:
+                raise RuntimeError("adaptive BDF2: step limit")
+            h = min(dt, t_end - t)
+            if h < 1e-9 * t_end:
+                raise RuntimeError("adaptive BDF2: time step underflow")
+            if not hist:
+                r, bh, xp = m, h, m.copy()
+            else:
+                y1, h1 = hist[0]
+                a, bb, beta = self.bdf2_coefficients(h, h1)
+                r, bh = a * m - bb * y1, beta * h
+                if len(hist) >= 2:
+                    y2, h2 = hist[1]
+                    l0 = (h + h1) * (h + h1 + h2) / (h1 * (h1 + h2))
+                    l1 = -h * (h + h1 + h2) / (h1 * h2)
+                    l2 = h * (h + h1) / ((h1 + h2) * h2)
+                    xp = l0 * m + l1 * y1 + l2 * y2
+                else:
+                    xp = m + (h / h1) * (m - y1)
+            x, its = newton(xp.copy(), r, bh)
+            if x is None:
+                info["rejected"] += 1
+                dt = 0.5 * h
+                continue
+            est = None
+            dt_new = dt
+            if len(hist) >= 2:
+                est = self.bdf2_estimate_factor(h, hist[0][1], hist[1][1]) * \
+                    np.linalg.norm(x - xp) / rms
+                fac = 0.9 * (lte_tol / est) ** (1.0 / 3.0) if est > 0 else 2.0
+                if est > lte_tol:
+                    info["rejected"] += 1
+                    dt = h * max(0.2, min(0.9, fac))
+                    continue
+                dt_new = h * min(2.0, max(0.2, fac))
+            x = x / np.linalg.norm(x, axis=1, keepdims=True)
+            # history: the earlier states, each with the step that leaves it
+            hist.insert(0, (m, h))
+            del hist[2:]
+            m = x
+            t += h
+            if record:
+                info["states"].append(m.copy())
+            info["dts"].append(h)
             info["lte"].append(est)
             info["newton"].append(its)
             dt = dt_new

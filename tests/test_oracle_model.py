@@ -374,3 +374,64 @@ def test_predictor_constant_uniform_steps():
     assert abs(cp + 11.0 / 12.0) < 1e-15
     c = model.Oracle.LTE_C
     assert abs(c / (c - cp) - 1.0 / 12.0) < 1e-15
+
+
+# --- adaptive BDF2 (the step-adaptive BDF scheme of the paper's timed run) ---
+
+def test_bdf2_coefficients_are_exact_on_quadratics():
+    """The variable-step BDF2 relation x - (a y_n - b y_{n-1}) = beta h y'(t + h)
+    holds exactly for y = 1, t and t^2 (its defining property), for uneven
+    steps; uniform steps give the textbook 4/3, 1/3, 2/3."""
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        h, h1 = rng.uniform(0.1, 2.0, size=2)
+        a, b, beta = model.Oracle.bdf2_coefficients(h, h1)
+        t0, t1, t2 = -h1, 0.0, h
+        for k in range(3):
+            y = lambda t: t ** k
+            dy = k * t2 ** (k - 1) if k else 0.0
+            assert abs(y(t2) - (a * y(t1) - b * y(t0)) - beta * h * dy) < 1e-12
+    a, b, beta = model.Oracle.bdf2_coefficients(1.0, 1.0)
+    assert abs(a - 4 / 3) < 1e-15 and abs(b - 1 / 3) < 1e-15 and abs(beta - 2 / 3) < 1e-15
+    assert model.Oracle.bdf2_estimate_factor(1.0, 1.0, 1.0) == pytest.approx(1 / 3)
+
+
+def test_bdf2_estimate_is_the_local_error():
+    """Undamped macrospin (linear right side): the true local error of each
+    accepted step is the distance of the new state from the current one
+    turned by gamma0 H h about z. Past the start (a backward-Euler step,
+    whose error is not smooth in the history, makes the first estimates
+    conservative) and before the shortened last step, the estimate equals it
+    to leading order."""
+    Hap, th0 = 2e5, 0.9
+    o, A, m0, ex = _macrospin(0.0, Hap, th0)
+    m, info = o.implicit_bdf2_adaptive(m0, 40e-12, 1e-14, 0.0, 1e-8, h_app=[0, 0, Hap], A=A,
+                                       record=True)
+    st = info["states"]
+    ratios = []
+    for k, h in enumerate(info["dts"]):
+        if info["lte"][k] is None:
+            continue
+        ang = model.GAMMA0 * Hap * h
+        R = np.array([[np.cos(ang), -np.sin(ang), 0], [np.sin(ang), np.cos(ang), 0], [0, 0, 1]])
+        true = np.linalg.norm(st[k + 1][0] - R @ st[k][0]) / np.sqrt(3)
+        ratios.append(info["lte"][k] / true)
+    ratios = np.array(ratios)
+    assert np.all(ratios[:8] >= 0.95)
+    mid = ratios[8:-1]
+    assert mid.size > 300 and 0.97 < mid.min() and mid.max() < 1.03, (mid.min(), mid.max())
+    assert np.abs(m - ex[None, :]).max() < 1e-5
+
+
+def test_bdf2_error_follows_the_tolerance():
+    """Damped macrospin against its closed form: a tolerance 8 times smaller
+    gives about twice the steps and a quarter of the error."""
+    o, A, m0, ex = _macrospin(0.3)
+    res = []
+    for tol in (1.25e-7, 1.5625e-8):
+        m, info = o.implicit_bdf2_adaptive(m0, 40e-12, 1e-14, 0.3, tol, h_app=[0, 0, 2e5], A=A)
+        res.append((len(info["dts"]), np.abs(m - ex[None, :]).max()))
+        assert np.allclose(np.linalg.norm(m, axis=1), 1.0, atol=1e-12)
+    (n1, e1), (n2, e2) = res
+    assert 1.7 < n2 / n1 < 2.3, res
+    assert 3.2 < e1 / e2 < 4.8, res
