@@ -265,6 +265,27 @@ int pmfem_llg_implicit_adaptive(pmfem_ctx* ctx, double* m_dev, double t_end, dou
                                 int32_t dt_log_cap);
 
 /*
+ * Time-step adaptive BDF2 (the step-adaptive BDF scheme that the paper's
+ * timed dynamics run uses, Sec. 2.2 and Sec. 5; its formulas here are this
+ * library's choice), with the arguments, Newton-GMRES corrector, step
+ * control, renormalisation, statistics and errors of
+ * pmfem_llg_implicit_adaptive. The first step is backward Euler,
+ * x = m + h f(x); the later ones variable-step BDF2,
+ * x = a m - b m_prev + beta h f(x) with w = h / h_prev, a = (1 + w)^2 /
+ * (1 + 2 w), b = w^2 / (1 + 2 w), beta = (1 + w) / (1 + 2 w). The predictor
+ * extrapolates the line through the last two states or the quadratic
+ * through the last three; from the third accepted step on, the local error
+ * estimate is h / (h + h1 + h2) times the rms per component of the
+ * corrector-predictor gap (h1, h2 the previous steps). BDF2 damps the stiff
+ * exchange modes that the midpoint rule carries undamped.
+ */
+int pmfem_llg_bdf2_adaptive(pmfem_ctx* ctx, double* m_dev, double t_end, double* dt,
+                            double alpha, uint32_t terms, const double* h_applied,
+                            double lte_tol, double newton_tol, int32_t krylov_dim,
+                            int32_t max_steps, int32_t* stats, double* dt_log,
+                            int32_t dt_log_cap);
+
+/*
  * Energies in J for the FP64 magnetisation m_dev[N'][3] (device):
  * exchange E_ex = m.K m and magnetostatic E_ms = (mu0/2) q.u. Synchronises.
  */

@@ -64,6 +64,8 @@ _SIGS = {
     "pmfem_llg_implicit": (ctypes.c_int, [_P, _P, _D, _D, _I32, _U32, _P, _D, _I32, _P]),
     "pmfem_llg_implicit_adaptive": (ctypes.c_int, [_P, _P, _D, _P, _D, _U32, _P, _D, _D, _I32,
                                                    _I32, _P, _P, _I32]),
+    "pmfem_llg_bdf2_adaptive": (ctypes.c_int, [_P, _P, _D, _P, _D, _U32, _P, _D, _D, _I32,
+                                               _I32, _P, _P, _I32]),
     "pmfem_energy": (ctypes.c_int, [_P, _P, _DP, _DP]),
     "pmfem_profile_begin": (ctypes.c_int, [_P, _I32]),
     "pmfem_profile_end": (ctypes.c_int, [_P, ctypes.POINTER(_I32), _P, _P, _P]),
@@ -295,17 +297,20 @@ class Context:
 
     def llg_implicit_adaptive(self, m64, t_end, dt0, alpha, lte_tol=1e-6, terms=TERM_EX | TERM_MS,
                               h_applied=None, newton_tol=0.0, krylov_dim=0, max_steps=0,
-                              log_steps=0):
-        """Adaptive midpoint steps from 0 to t_end; returns a dict with the
-        accepted and rejected steps, Newton and Krylov iterations, the proposed
-        next step, the step sizes of the first log_steps attempts ("attempts",
-        negative where rejected) and those of the accepted ones ("dts")."""
+                              log_steps=0, scheme="midpoint"):
+        """Adaptive implicit steps (scheme "midpoint" or "bdf2") from 0 to
+        t_end; returns a dict with the accepted and rejected steps, Newton and
+        Krylov iterations, the proposed next step, the step sizes of the first
+        log_steps attempts ("attempts", negative where rejected) and those of
+        the accepted ones ("dts")."""
         import torch
+        fn = {"midpoint": self.lib.pmfem_llg_implicit_adaptive,
+              "bdf2": self.lib.pmfem_llg_bdf2_adaptive}[scheme]
         ha = None if h_applied is None else np.ascontiguousarray(h_applied, dtype=np.float64)
         st = np.zeros(5, dtype=np.int32)
         dt = np.array([float(dt0)], dtype=np.float64)
         log = np.zeros(max(int(log_steps), 1), dtype=np.float64)
-        self._check(self.lib.pmfem_llg_implicit_adaptive(
+        self._check(fn(
             self.h, _dev_ptr(m64, torch.float64, (self.n, 3), "m"), float(t_end),
             _ptr(dt), float(alpha), int(terms), _ptr(ha), float(lte_tol),
             float(newton_tol), int(krylov_dim), int(max_steps), _ptr(st),

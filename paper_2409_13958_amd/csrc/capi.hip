@@ -100,7 +100,8 @@ struct pmfem_dev {
     double* coef = nullptr;
     float *mb32 = nullptr, *H = nullptr, *z32 = nullptr, *Az = nullptr;
     double* host = nullptr;  // pinned: coefficients out, reductions back
-    double *xp = nullptr, *S = nullptr;  // adaptive steps: predictor, two slopes
+    double *xp = nullptr, *S = nullptr;  // adaptive steps: predictor, two slopes or states
+    double* r = nullptr;                 // BDF2: the combination of past states
   } imp;
   std::vector<void*> allocs;
   // profiling
@@ -1233,7 +1234,8 @@ int implicit_setup(pmfem_ctx* c, int kdim, bool adaptive) {
   pmfem_dev::Implicit& W = d->imp;
   const int64_t n = d->n, n3 = 3 * n;
   int rc;
-  if (adaptive && !W.xp && ((rc = dalloc(c, &W.xp, n3)) || (rc = dalloc(c, &W.S, 2 * n3))))
+  if (adaptive && !W.xp &&
+      ((rc = dalloc(c, &W.xp, n3)) || (rc = dalloc(c, &W.S, 2 * n3)) || (rc = dalloc(c, &W.r, n3))))
     return rc;
   if (W.kdim >= kdim) return PMFEM_OK;
   if ((rc = dalloc(c, &W.x, n3)) || (rc = dalloc(c, &W.mb, n3)) || (rc = dalloc(c, &W.G, n3)) ||
@@ -1299,8 +1301,10 @@ int lincomb(pmfem_ctx* c, hipStream_t s, const double* V, int64_t ldv, int nv, c
   return PMFEM_OK;
 }
 
-// Newton's iteration for one midpoint step of size dt from m, starting from
-// the guess in W.x and leaving the solution there. Converged when the rms of
+// Newton's iteration for one implicit step x = r + dt f((1 - theta) m + theta x)
+// (the midpoint rule: r = m, theta = 1/2; BDF: r from the past states, dt the
+// step times the BDF coefficient, theta = 1), starting from the guess in W.x
+// and leaving the solution there. Converged when the rms of
 // the residual per component is <= tol after at least min_newton
 // corrections (a predictor-corrector step needs one: a predictor accepted
 // as it stands would make the error estimate zero and put predictor values
@@ -1310,17 +1314,17 @@ int lincomb(pmfem_ctx* c, hipStream_t s, const double* V, int64_t ldv, int nv, c
 // residual exceeds diverge times its first value (diverge <= 0: never).
 // GMRES ends a linear solve at a relative residual of 1e-6 or at half the
 // Newton tolerance, whichever is reached first.
-int newton_solve(pmfem_ctx* c, const double* m, double dt, double alpha, uint32_t terms,
-                 const double* happ, double tol, int kdim, int min_newton, int max_newton,
-                 double diverge,
-                 bool* converged, int32_t* newton_its, int32_t* krylov_its, std::string* hist) {
+int newton_solve(pmfem_ctx* c, const double* r, const double* m, double theta, double dt,
+                 double alpha, uint32_t terms, const double* happ, double tol, int kdim,
+                 int min_newton, int max_newton, double diverge, bool* converged,
+                 int32_t* newton_its, int32_t* krylov_its, std::string* hist) {
   pmfem_dev* d = c->dev;
   pmfem_dev::Implicit& W = d->imp;
   hipStream_t s = stream_of(c);
   const int64_t n = d->n, n3 = 3 * n;
   const unsigned b3 = (unsigned)((n3 + 255) / 256), b1 = (unsigned)((n + 255) / 256);
   const double cc = -kGamma0 / (1.0 + alpha * alpha);
-  const double sj = -0.5 * dt * cc;  // dG/dx = I + sj D
+  const double sj = -theta * dt * cc;  // dG/dx = I + sj D
   const double eta = 1e-6;
   const double rms = std::sqrt((double)n3);
   std::vector<double> hcol(kMaxKrylov + 2), h2(kMaxKrylov + 2), y(kMaxKrylov + 1),
@@ -1332,12 +1336,12 @@ int newton_solve(pmfem_ctx* c, const double* m, double dt, double alpha, uint32_
   *converged = false;
   if (hist) hist->clear();
   for (int it = 0; it <= max_newton; ++it) {
-    hipLaunchKernelGGL(k_mid_point, dim3(b3), dim3(256), 0, s, n3, m, (const double*)W.x, W.mb,
-                       W.mb32);
+    hipLaunchKernelGGL(k_mid_point, dim3(b3), dim3(256), 0, s, n3, m, (const double*)W.x, theta,
+                       W.mb, W.mb32);
     if ((rc = run_heff(c, W.mb32, W.H, terms, happ, W.mb))) return rc;
-    hipLaunchKernelGGL(k_mid_residual, dim3(kDotParts), dim3(256), 0, s, n, m, (const double*)W.x,
+    hipLaunchKernelGGL(k_mid_residual, dim3(kDotParts), dim3(256), 0, s, n, r, (const double*)W.x,
                        (const double*)W.mb, (const float*)W.H, (const double*)W.adiag, dt, cc,
-                       alpha, W.G, W.Minv, W.part);
+                       alpha, theta, W.G, W.Minv, W.part);
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, (const double*)W.part, kDotParts,
                        W.red);
     hipError_t e = hipMemcpyAsync(W.host, W.red, sizeof(double), hipMemcpyDeviceToHost, s);
@@ -1467,8 +1471,8 @@ int run_implicit(pmfem_ctx* c, double* m, double dt, double alpha, int32_t n_ste
     hipError_t e = hipMemcpyAsync(W.x, m, n3 * sizeof(double), hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return hip_err(c, e, "implicit step");
     bool converged = false;
-    if ((rc = newton_solve(c, m, dt, alpha, terms, happ, tol, kdim, 0, 30, 0.0, &converged,
-                           &newton_total, &krylov_total, &hist)))
+    if ((rc = newton_solve(c, m, m, 0.5, dt, alpha, terms, happ, tol, kdim, 0, 30, 0.0,
+                           &converged, &newton_total, &krylov_total, &hist)))
       return rc;
     if (!converged) {
       report();
@@ -1486,21 +1490,34 @@ int run_implicit(pmfem_ctx* c, double* m, double dt, double alpha, int32_t n_ste
   return PMFEM_OK;
 }
 
-// Step-size-adaptive midpoint rule as a predictor-corrector pair. The
-// predictor extrapolates the midpoint slopes s = (m_k+1 - m_k) / h_k of the
-// last two accepted steps linearly to the new step's midpoint (one slope:
-// that slope; none: m itself); Newton corrects from there, at least once.
-// From the third accepted step on, Milne's device estimates the corrector's
-// local error as |C / (C - C_p)| rms(x_c - x_p). C = 1/12 is the midpoint
-// rule's error
-// constant for a linear right side (its local error is C h^3 times the third
-// derivative of the solution); C_p is the predictor's, which counts the chord
-// error of each slope (1/24), the error its own step left in the history
-// (C), and the miss of the straight line through the two midpoint values. A
-// step is accepted when the estimate is <= lte_tol; the next step is
+// Step-size-adaptive implicit stepping as a predictor-corrector pair, for
+// the midpoint rule (scheme 0) and BDF2 (scheme 1). Newton corrects the
+// predictor, at least once. From the third accepted step on, the local
+// error is estimated from the corrector-predictor gap, and a step is
+// accepted when the estimate is <= lte_tol; the next step is
 // h min(2, max(0.2, 0.9 (lte_tol / E)^(1/3))), at most 0.9 h after a
 // rejection; a failed Newton iteration (10 iterations, three without
-// progress, or three times its first residual) halves the step.
+// progress, or three times its first residual) halves the step; each
+// accepted state is renormalised.
+//
+// Midpoint rule: the predictor extrapolates the midpoint slopes
+// s = (m_k+1 - m_k) / h_k of the last two accepted steps linearly to the new
+// step's midpoint (one slope: that slope; none: m itself), and Milne's
+// device gives E = |C / (C - C_p)| rms(x_c - x_p). C = 1/12 is the rule's
+// error constant for a linear right side (its local error is C h^3 times the
+// third derivative of the solution); C_p is the predictor's, which counts
+// the chord error of each slope (1/24), the error its own step left in the
+// history (C), and the miss of the straight line through the two midpoint
+// values.
+//
+// BDF2: the first step is backward Euler from m, the later ones variable-step
+// BDF2, x = a m - b y_prev + beta h f(x) with w = h / h1, a = (1 + w)^2 /
+// (1 + 2 w), b = w^2 / (1 + 2 w), beta = (1 + w) / (1 + 2 w); the predictor
+// is the line through the last two states or the quadratic through the last
+// three, and E = h / (h + h1 + h2) rms(x_c - x_p): the rule's own trajectory
+// satisfies the scheme exactly, so it deviates from the exact flow by
+// (1/6) h^2 (h + h1) y''' per step, while the quadratic misses it by
+// (1/6) h (h + h1) (h + h1 + h2) y'''.
 double predictor_constant(double h, double h1, double h2) {
   const double C = 1.0 / 12.0;
   const double a = 0.5 * (h + h1), b = a + 0.5 * (h1 + h2), r = (h + h1) / (h1 + h2);
@@ -1508,15 +1525,17 @@ double predictor_constant(double h, double h1, double h2) {
          1.0 / 24.0;
 }
 
-int run_implicit_adaptive(pmfem_ctx* c, double* m, double t_end, double* dt_io, double alpha,
-                          uint32_t terms, const double* happ, double lte_tol, double tol,
-                          int kdim, int32_t max_steps, int32_t* stats, double* dt_log,
-                          int32_t log_cap) {
+int run_implicit_adaptive(pmfem_ctx* c, int scheme, double* m, double t_end, double* dt_io,
+                          double alpha, uint32_t terms, const double* happ, double lte_tol,
+                          double tol, int kdim, int32_t max_steps, int32_t* stats,
+                          double* dt_log, int32_t log_cap) {
   pmfem_dev::Implicit& W = c->dev->imp;
   hipStream_t s = stream_of(c);
   const int64_t n3 = 3 * c->dev->n;
   const double rms = std::sqrt((double)n3);
   const double C = 1.0 / 12.0;
+  const bool bdf = scheme == 1;
+  const char* what = bdf ? "adaptive BDF2" : "adaptive midpoint";
   int32_t accepted = 0, rej_error = 0, rej_newton = 0, newton_total = 0, krylov_total = 0;
   auto report = [&]() {
     if (stats) {
@@ -1533,40 +1552,67 @@ int run_implicit_adaptive(pmfem_ctx* c, double* m, double t_end, double* dt_io, 
     if (dt_log && attempts < log_cap) dt_log[attempts] = h;
     ++attempts;
   };
-  int ns = 0, newest = 0;  // slopes held; the slot of the latest
+  // history in the two slots of W.S: midpoint slopes, or BDF past states;
+  // hs[slot] the step that belongs to it
+  int ns = 0, newest = 0;
   double hs[2] = {0.0, 0.0};
   int rc;
   hipError_t e;
   while (t_end - t > 1e-12 * t_end) {
     if (accepted >= max_steps) {
       report();
-      return set_err(c, PMFEM_ECONV, "adaptive midpoint: step limit reached at t = " +
-                                         std::to_string(t) + " s");
+      return set_err(c, PMFEM_ECONV,
+                     std::string(what) + ": step limit reached at t = " + std::to_string(t) + " s");
     }
     const double h = std::min(dt, t_end - t);
     if (h < 1e-9 * t_end) {
       report();
-      return set_err(c, PMFEM_ECONV, "adaptive midpoint: time step underflow at t = " +
+      return set_err(c, PMFEM_ECONV, std::string(what) + ": time step underflow at t = " +
                                          std::to_string(t) + " s");
     }
-    // predictor into W.xp, Newton's start in W.x
-    if (ns >= 2) {
-      const double h1 = hs[newest], h2 = hs[1 - newest], r = (h + h1) / (h1 + h2);
-      double coef[2];
-      coef[newest] = h * (1.0 + r);
-      coef[1 - newest] = -h * r;
-      rc = lincomb(c, s, W.S, n3, 2, coef, 1.0, m, W.xp);
-    } else if (ns == 1) {
-      rc = lincomb(c, s, W.S + (int64_t)newest * n3, n3, 1, &h, 1.0, m, W.xp);
+    const double h1 = hs[newest], h2 = hs[1 - newest];
+    double* y1 = W.S + (int64_t)newest * n3;
+    // predictor into W.xp; for BDF2 the right side r into W.r
+    double hn = h;  // the step the corrector's f is scaled with
+    if (!bdf) {
+      if (ns >= 2) {
+        const double r = (h + h1) / (h1 + h2);
+        double coef[2];
+        coef[newest] = h * (1.0 + r);
+        coef[1 - newest] = -h * r;
+        rc = lincomb(c, s, W.S, n3, 2, coef, 1.0, m, W.xp);
+      } else if (ns == 1) {
+        rc = lincomb(c, s, y1, n3, 1, &h, 1.0, m, W.xp);
+      } else {
+        rc = lincomb(c, s, nullptr, 0, 0, nullptr, 1.0, m, W.xp);
+      }
     } else {
-      rc = lincomb(c, s, nullptr, 0, 0, nullptr, 1.0, m, W.xp);
+      if (ns == 0) {
+        rc = lincomb(c, s, nullptr, 0, 0, nullptr, 1.0, m, W.xp);
+        if (!rc) rc = lincomb(c, s, nullptr, 0, 0, nullptr, 1.0, m, W.r);
+      } else {
+        const double w = h / h1, den = 1.0 + 2.0 * w;
+        const double mb = -w * w / den;
+        hn = h * (1.0 + w) / den;
+        rc = lincomb(c, s, y1, n3, 1, &mb, (1.0 + w) * (1.0 + w) / den, m, W.r);
+        if (!rc && ns >= 2) {
+          double coef[2];
+          coef[newest] = -h * (h + h1 + h2) / (h1 * h2);
+          coef[1 - newest] = h * (h + h1) / ((h1 + h2) * h2);
+          rc = lincomb(c, s, W.S, n3, 2, coef, (h + h1) * (h + h1 + h2) / (h1 * (h1 + h2)), m,
+                       W.xp);
+        } else if (!rc) {
+          const double cl = -h / h1;
+          rc = lincomb(c, s, y1, n3, 1, &cl, 1.0 + h / h1, m, W.xp);
+        }
+      }
     }
     if (rc) return rc;
     e = hipMemcpyAsync(W.x, W.xp, n3 * sizeof(double), hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return hip_err(c, e, "adaptive midpoint");
+    if (e != hipSuccess) return hip_err(c, e, what);
     bool converged = false;
-    if ((rc = newton_solve(c, m, h, alpha, terms, happ, tol, kdim, 1, 10, 3.0, &converged,
-                           &newton_total, &krylov_total, nullptr)))
+    if ((rc = newton_solve(c, bdf ? W.r : m, m, bdf ? 1.0 : 0.5, hn, alpha, terms, happ, tol,
+                           kdim, 1, 10, 3.0, &converged, &newton_total, &krylov_total, nullptr)))
       return rc;
     if (!converged) {
       ++rej_newton;
@@ -1580,8 +1626,9 @@ int run_implicit_adaptive(pmfem_ctx* c, double* m, double t_end, double* dt_io, 
       if ((rc = lincomb(c, s, W.xp, n3, 1, &minus_one, 1.0, W.x, W.z))) return rc;
       double d2 = 0.0;
       if ((rc = dots(c, s, W.z, n3, 1, W.z, &d2))) return rc;
-      const double cp = predictor_constant(h, hs[newest], hs[1 - newest]);
-      const double est = std::fabs(C / (C - cp)) * std::sqrt(d2) / rms;
+      const double factor =
+          bdf ? h / (h + h1 + h2) : std::fabs(C / (C - predictor_constant(h, h1, h2)));
+      const double est = factor * std::sqrt(d2) / rms;
       const double fac = est > 0.0 ? 0.9 * std::cbrt(lte_tol / est) : 2.0;
       if (!(est <= lte_tol)) {
         ++rej_error;
@@ -1591,19 +1638,24 @@ int run_implicit_adaptive(pmfem_ctx* c, double* m, double t_end, double* dt_io, 
       }
       dt_new = h * std::min(2.0, std::max(0.2, fac));
     }
-    // accept: x renormalised, the new slope (x - m) / h replaces the older
-    // one, then m = x
+    // accept: x renormalised; the history's older slot takes the new slope
+    // (x - m) / h, or for BDF2 the state m, then m = x
     hipLaunchKernelGGL(k_mid_normalize, dim3((unsigned)((n3 / 3 + 255) / 256)), dim3(256), 0, s,
                        n3 / 3, W.x);
     const int slot = ns == 0 ? 0 : 1 - newest;
-    const double minus_inv_h = -1.0 / h;
-    if ((rc = lincomb(c, s, m, n3, 1, &minus_inv_h, 1.0 / h, W.x, W.S + (int64_t)slot * n3)))
-      return rc;
+    double* dst = W.S + (int64_t)slot * n3;
+    if (bdf) {
+      e = hipMemcpyAsync(dst, m, n3 * sizeof(double), hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return hip_err(c, e, what);
+    } else {
+      const double minus_inv_h = -1.0 / h;
+      if ((rc = lincomb(c, s, m, n3, 1, &minus_inv_h, 1.0 / h, W.x, dst))) return rc;
+    }
     newest = slot;
     hs[slot] = h;
     ns = std::min(ns + 1, 2);
     e = hipMemcpyAsync(m, W.x, n3 * sizeof(double), hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return hip_err(c, e, "adaptive midpoint");
+    if (e != hipSuccess) return hip_err(c, e, what);
     log_attempt(h);
     ++accepted;
     t += h;
@@ -1613,7 +1665,7 @@ int run_implicit_adaptive(pmfem_ctx* c, double* m, double t_end, double* dt_io, 
   report();
   e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_err(c, e, "adaptive midpoint");
+  if (e != hipSuccess) return hip_err(c, e, what);
   return PMFEM_OK;
 }
 
@@ -2441,8 +2493,28 @@ int pmfem_llg_implicit_adaptive(pmfem_ctx* c, double* m_dev, double t_end, doubl
   if (kdim > kMaxKrylov) return set_err(c, PMFEM_EINVAL, "krylov_dim above 60");
   const double tol = newton_tol > 0.0 ? newton_tol : 0.1 * lte_tol;
   if ((rc = implicit_setup(c, kdim, true))) return rc;
-  return run_implicit_adaptive(c, m_dev, t_end, dt, alpha, terms, h_applied, lte_tol, tol, kdim,
-                               max_steps > 0 ? max_steps : 1000000, stats, dt_log, dt_log_cap);
+  return run_implicit_adaptive(c, 0, m_dev, t_end, dt, alpha, terms, h_applied, lte_tol, tol,
+                               kdim, max_steps > 0 ? max_steps : 1000000, stats, dt_log,
+                               dt_log_cap);
+}
+
+int pmfem_llg_bdf2_adaptive(pmfem_ctx* c, double* m_dev, double t_end, double* dt, double alpha,
+                            uint32_t terms, const double* h_applied, double lte_tol,
+                            double newton_tol, int32_t krylov_dim, int32_t max_steps,
+                            int32_t* stats, double* dt_log, int32_t dt_log_cap) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!m_dev || !dt || !(t_end > 0.0) || !(*dt > 0.0) || !(alpha >= 0.0) || terms < 1 ||
+      terms > 3 || !(lte_tol > 0.0) || max_steps < 0 || dt_log_cap < 0 ||
+      (dt_log_cap > 0 && !dt_log))
+    return set_err(c, PMFEM_EINVAL, "bad adaptive llg arguments");
+  const int kdim = krylov_dim <= 0 ? 30 : krylov_dim;
+  if (kdim > kMaxKrylov) return set_err(c, PMFEM_EINVAL, "krylov_dim above 60");
+  const double tol = newton_tol > 0.0 ? newton_tol : 0.1 * lte_tol;
+  if ((rc = implicit_setup(c, kdim, true))) return rc;
+  return run_implicit_adaptive(c, 1, m_dev, t_end, dt, alpha, terms, h_applied, lte_tol, tol,
+                               kdim, max_steps > 0 ? max_steps : 1000000, stats, dt_log,
+                               dt_log_cap);
 }
 
 int pmfem_energy(pmfem_ctx* c, const double* m_dev, double* e_ex, double* e_ms) {

@@ -186,10 +186,11 @@ __global__ void k_mid_normalize(int64_t n, double* x);
 __global__ void k_energy(int64_t n, const double* m, const double* mu, const float* hex,
                          const float* q, const float* u, double* part);
 // implicit midpoint LLG (Newton-Krylov)
-__global__ void k_mid_point(int64_t n3, const double* m, const double* x, double* mb, float* mb32);
+__global__ void k_mid_point(int64_t n3, const double* m, const double* x, double theta, double* mb,
+                            float* mb32);
 __global__ void k_mid_residual(int64_t n, const double* m, const double* x, const double* mb,
                                const float* H, const double* adiag, double dt, double c,
-                               double alpha, double* G, double* Minv, double* part);
+                               double alpha, double theta, double* G, double* Minv, double* part);
 template <typename VT>
 __global__ void k_mid_precond(int64_t n, const double* Minv, const VT* v, double* z, float* z32);
 constexpr int kGsMaxVectors = 64;  // Krylov vectors one Gram-Schmidt update takes

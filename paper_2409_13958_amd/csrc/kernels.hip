@@ -2097,15 +2097,18 @@ __global__ void k_rk_final(int64_t n, double* __restrict__ m, const double* __re
 
 // energy partial sums: block b writes {sum mu m.Hex, sum q u}
 // ---------------------------------------------------------------------------
-// LLG by the implicit midpoint rule (Sec. 2.2: implicit time stepping with a
-// Newton iteration and a preconditioned Krylov solver). One step solves
-//   G(x) = x - m - dt f(mb) = 0,   mb = (m + x) / 2,
+// Implicit LLG steps (Sec. 2.2: implicit time stepping with a Newton
+// iteration and a preconditioned Krylov solver). One step solves
+//   G(x) = x - r - dt f(mb) = 0,   mb = (1 - theta) m + theta x,
 //   f(v) = c [v x H(v) + alpha v x (v x H(v))],  c = -gamma0 / (1 + alpha^2),
-// by Newton; the linear systems dG/dx d = G are solved by GMRES with the
-// Jacobian applied matrix-free (the field is linear in m, H(v) = A v + H_app):
-//   dG/dx w = w - (dt/2) c [w x H + mb x (A w)
-//                          + alpha (w x (mb x H) + mb x (w x H) + mb x (mb x (A w)))].
-// All vectors are FP64; A w is one FP32 field evaluation.
+// with r = m, theta = 1/2 for the midpoint rule and r a combination of past
+// states, dt the step times the BDF coefficient, theta = 1 for BDF; by
+// Newton, the linear systems dG/dx d = G by GMRES with the Jacobian applied
+// matrix-free (the field is linear in m, H(v) = A v + H_app):
+//   dG/dx w = w - theta dt c [w x H + mb x (A w)
+//                            + alpha (w x (mb x H) + mb x (w x H) + mb x (mb x (A w)))].
+// All vectors are FP64; A w is one FP32 field evaluation. (Below, "m" of
+// the residual kernel is r.)
 
 __device__ __forceinline__ void cross3(double ax, double ay, double az, double bx, double by,
                                        double bz, double& cx, double& cy, double& cz) {
@@ -2114,17 +2117,18 @@ __device__ __forceinline__ void cross3(double ax, double ay, double az, double b
   cz = ax * by - ay * bx;
 }
 
-// mb = (m + x) / 2 and its FP32 copy for the field evaluation
+// the evaluation point mb = (1 - theta) m + theta x (theta = 1/2: the
+// midpoint rule; theta = 1: BDF, mb = x) and its FP32 copy for the field
 __global__ void k_mid_point(int64_t n3, const double* __restrict__ m, const double* __restrict__ x,
-                            double* __restrict__ mb, float* __restrict__ mb32) {
+                            double theta, double* __restrict__ mb, float* __restrict__ mb32) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n3) return;
-  const double v = 0.5 * (m[i] + x[i]);
+  const double v = theta == 1.0 ? x[i] : (1.0 - theta) * m[i] + theta * x[i];
   mb[i] = v;
   mb32[i] = (float)v;
 }
 
-// Residual G at the midpoint field H and, per node, the inverse of the 3x3
+// Residual G at the field H of the evaluation point and, per node, the inverse of the 3x3
 // diagonal block of dG/dx with A replaced by its exchange diagonal a_n
 // (the block-inverse preconditioner); part[b] = block b's share of |G|^2,
 // summed in a fixed order (grid-stride, then a tree in LDS).
@@ -2133,7 +2137,7 @@ __global__ void __launch_bounds__(256) k_mid_residual(int64_t n, const double* _
                                                       const double* __restrict__ mb,
                                                       const float* __restrict__ H,
                                                       const double* __restrict__ adiag, double dt,
-                                                      double c, double alpha,
+                                                      double c, double alpha, double theta,
                                                       double* __restrict__ G,
                                                       double* __restrict__ Minv,
                                                       double* __restrict__ part) {
@@ -2169,7 +2173,7 @@ __global__ void __launch_bounds__(256) k_mid_residual(int64_t n, const double* _
       ux = t1x + a * t2x + alpha * (t3x + t4x + a * t5x);
       uy = t1y + a * t2y + alpha * (t3y + t4y + a * t5y);
       uz = t1z + a * t2z + alpha * (t3z + t4z + a * t5z);
-      const double s = -0.5 * dt * c;
+      const double s = -theta * dt * c;
       B[0][k] = (k == 0) + s * ux;
       B[1][k] = (k == 1) + s * uy;
       B[2][k] = (k == 2) + s * uz;

@@ -215,3 +215,73 @@ def test_adaptive_limits_and_bad_arguments():
             ctx.llg_implicit_adaptive(m, args["t_end"], args["dt0"], 0.1, lte_tol=args["lte_tol"],
                                       krylov_dim=args["krylov_dim"], terms=args["terms"])
         assert e.value.code == B.Status.EINVAL
+
+
+# --- adaptive BDF2 (pmfem_llg_bdf2_adaptive) ----------------------------------
+
+def test_bdf2_macrospin_follows_the_oracle_steps():
+    """Damped macrospin, 40 ps from a 10 fs first step: the library's BDF2 step
+    sequence against the oracle's FP64 run of the same rules, and the end
+    state against the closed form."""
+    ctx = B.Context.from_problem(macrospin_cell(), device=0)
+    Hap, th0, ph0, alpha, T, tol = 2e5, 0.9, 0.3, 0.3, 40e-12, 1e-7
+    m0 = np.array([np.sin(th0) * np.cos(ph0), np.sin(th0) * np.sin(ph0), np.cos(th0)])
+    m = torch.tensor(np.tile(m0, (ctx.n, 1)), dtype=torch.float64, device="cuda")
+    got = ctx.llg_implicit_adaptive(m, T, 1e-14, alpha, lte_tol=tol, h_applied=[0.0, 0.0, Hap],
+                                    log_steps=4096, scheme="bdf2")
+    orc = model.Oracle(macrospin_cell(), with_aim=False)
+    A = np.zeros((3 * orc.n, 3 * orc.n))
+    mo, info = orc.implicit_bdf2_adaptive(np.tile(m0, (orc.n, 1)), T, 1e-14, alpha, tol,
+                                          h_app=[0.0, 0.0, Hap], A=A)
+    ref = np.array(info["dts"])
+    g = model.GAMMA0 * Hap / (1 + alpha ** 2)
+    th = 2 * np.arctan(np.tan(th0 / 2) * np.exp(-alpha * g * T))
+    ph = ph0 + g * T
+    ex = np.array([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)])
+    out = m.cpu().numpy()
+    err = np.abs(out - ex[None, :]).max()
+    err_o = np.abs(mo - ex[None, :]).max()
+    k = min(len(ref), got["accepted"])
+    dstep = np.abs(got["dts"][:k] / ref[:k] - 1).max()
+    print(f"[gpu implicit] BDF2 macrospin: {got['accepted']} steps (oracle {len(ref)}), "
+          f"{got['rejected']} rejected (oracle {info['rejected']}), max step difference "
+          f"{dstep:.2e}, error {err:.2e} (oracle {err_o:.2e}), Newton {got['newton']}, "
+          f"Krylov {got['krylov']}")
+    assert abs(got["accepted"] - len(ref)) <= 1 and got["rejected"] == info["rejected"]
+    assert dstep < 1e-2
+    assert err < 1.5 * err_o + 1e-7
+    assert np.allclose(np.linalg.norm(out, axis=1), 1.0, atol=1e-12)
+
+
+def test_bdf2_film_against_oracle():
+    """Film, exchange + magnetostatic field, alpha = 0.5, 1 ps from a 1 fs first
+    step at a local tolerance of 1e-5: BDF2 steps and end state against the
+    oracle's run with the exact dense Jacobian. The corrector is asked for a
+    residual of 1e-8: BDF2's estimate is a third of the corrector-predictor
+    gap, so at the default Newton tolerance (1e-6 here) the corrector's own
+    error would move each estimate by some 5 % and the two step sequences
+    apart."""
+    prob = mg.film_c1()
+    ctx = B.Context.from_problem(prob, device=0)
+    n, uon, nou, _ = ctx.query()
+    orc = model.Oracle(prob)
+    perm = orc.uk[nou]
+    m0 = orc.unknown_values(prob.m)
+    T, tol = 1e-12, 1e-5
+    ref, info = orc.implicit_bdf2_adaptive(m0, T, 1e-15, 0.5, tol)
+    m = torch.tensor(prob.m[nou], dtype=torch.float64, device="cuda")
+    got = ctx.llg_implicit_adaptive(m, T, 1e-15, 0.5, lte_tol=tol, newton_tol=1e-8,
+                                    log_steps=4096, scheme="bdf2")
+    dts = np.array(info["dts"])
+    k = min(len(dts), got["accepted"])
+    dstep = np.abs(got["dts"][:k] / dts[:k] - 1).max()
+    out = m.cpu().numpy()
+    err = rel(out - m0[perm], ref[perm] - m0[perm])
+    print(f"[gpu implicit] BDF2 film: {got['accepted']} steps (oracle {len(dts)}), "
+          f"{got['rejected']} rejected (oracle {info['rejected']}), max step difference "
+          f"{dstep:.2e}, rel L2 of the change vs oracle {err:.2e}, Newton {got['newton']} "
+          f"(oracle {sum(info['newton'])}), Krylov {got['krylov']}")
+    assert abs(got["accepted"] - len(dts)) <= 1
+    assert dstep < 5e-2
+    assert err < 1e-3
+    assert np.abs(np.linalg.norm(out, axis=1) - 1.0).max() < 1e-12

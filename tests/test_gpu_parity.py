@@ -293,3 +293,27 @@ def test_grid_convolution_mixed_radix(case):
         print(f"[gpu parity] convolution {case} (mixed radix, fft={fft}): rel L2 {err:.2e}",
               flush=True)
         assert err <= 1e-6
+
+
+def test_grid_convolution_surrogate_workload_size():
+    """The grid of the surrogate workload, a film of 512 x 512 x 16 grid
+    points (FFT extents 512 x 512 x 32): a 512 x 512 plane does not fit in
+    LDS, so the convolution takes the per-axis radix-2 passes at their
+    longest lines; against the oracle's FFT convolution with its own PGF."""
+    prob = mg.kuhn_box((16, 16, 2), 32e-9, periodic=0b011, jitter=0.1, grid=(512, 512, 16))
+    orc = model.Oracle(prob)
+    N = orc.aim.grid.N
+    Q = np.random.default_rng(7).standard_normal(tuple(N))
+    ref = orc.aim.convolve(Q) / (4 * np.pi)
+    ctx = B.Context.from_problem(prob, device=0)
+    with pytest.raises(B.PmfemError):
+        ctx.set_variant("fft", 2)        # the plane form does not fit this grid
+    qg = torch.tensor(Q.transpose(2, 1, 0).copy(), dtype=torch.float32, device="cuda")
+    ug = torch.empty_like(qg)
+    ctx.grid_convolve(qg, ug)
+    U = ug.cpu().numpy().astype(np.float64).transpose(2, 1, 0)
+    err = rel(U, ref)
+    errmax = float(np.abs(U - ref).max() / np.abs(ref).max())
+    print(f"[gpu parity] convolution 512x512x16 film: rel L2 {err:.2e}, max {errmax:.2e}",
+          flush=True)
+    assert err <= 1e-6 and errmax <= 1e-5
