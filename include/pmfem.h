@@ -200,6 +200,19 @@ int pmfem_llg_step(pmfem_ctx* ctx, double* m_dev, double dt, double alpha, int32
                    const double* h_applied);
 
 /*
+ * pmfem_llg_step through a HIP graph: the first call (and any call whose
+ * m_dev, dt, alpha or h_applied differ from the previous one's) captures the
+ * kernels of one RK4 step, with their fork to the library's second stream
+ * and back, into a graph on a stream of the library's own; each call then
+ * launches that graph n_steps times on the context's stream. The results are
+ * those of pmfem_llg_step, bit for bit; small cells, whose steps are bound by
+ * kernel launches, gain most. The graph is kept until pmfem_destroy or the
+ * next capture. PMFEM_EHIP if capture, instantiation or a launch fails.
+ */
+int pmfem_llg_step_graph(pmfem_ctx* ctx, double* m_dev, double dt, double alpha, int32_t n_steps,
+                         const double* h_applied);
+
+/*
  * LLG time stepping by the implicit midpoint rule (Sec. 2.2 advances the
  * semi-discrete Eq. llg implicitly, with a Newton iteration whose linear
  * systems a preconditioned Krylov method solves): each of n_steps steps of

@@ -61,6 +61,7 @@ _SIGS = {
     "pmfem_grid_convolve": (ctypes.c_int, [_P, _P, _P]),
     "pmfem_grid_convolve_noalloc": (ctypes.c_int, [_P, _P, _P]),
     "pmfem_llg_step": (ctypes.c_int, [_P, _P, _D, _D, _I32, _P]),
+    "pmfem_llg_step_graph": (ctypes.c_int, [_P, _P, _D, _D, _I32, _P]),
     "pmfem_llg_implicit": (ctypes.c_int, [_P, _P, _D, _D, _I32, _U32, _P, _D, _I32, _P]),
     "pmfem_llg_implicit_adaptive": (ctypes.c_int, [_P, _P, _D, _P, _D, _U32, _P, _D, _D, _I32,
                                                    _I32, _P, _P, _I32]),
@@ -282,6 +283,14 @@ class Context:
         self._check(self.lib.pmfem_llg_step(self.h, _dev_ptr(m64, torch.float64, (self.n, 3), "m"),
                                             float(dt), float(alpha), int(n_steps), _ptr(ha)),
                     "llg_step")
+
+    def llg_step_graph(self, m64, dt, alpha, n_steps=1, h_applied=None):
+        """RK4 steps as launches of a captured HIP graph of one step."""
+        import torch
+        ha = None if h_applied is None else np.ascontiguousarray(h_applied, dtype=np.float64)
+        self._check(self.lib.pmfem_llg_step_graph(
+            self.h, _dev_ptr(m64, torch.float64, (self.n, 3), "m"), float(dt), float(alpha),
+            int(n_steps), _ptr(ha)), "llg_step_graph")
 
     def llg_implicit(self, m64, dt, alpha, n_steps=1, terms=TERM_EX | TERM_MS, h_applied=None,
                      tol=0.0, krylov_dim=0):

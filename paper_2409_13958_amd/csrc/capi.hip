@@ -103,6 +103,15 @@ struct pmfem_dev {
     double *xp = nullptr, *S = nullptr;  // adaptive steps: predictor, two slopes or states
     double* r = nullptr;                 // BDF2: the combination of past states
   } imp;
+  // one captured RK4 step (pmfem_llg_step_graph) and what it was captured for
+  struct StepGraph {
+    hipStream_t cap = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    double* m = nullptr;
+    double dt = 0.0, alpha = 0.0, happ[3] = {0.0, 0.0, 0.0};
+    bool with_happ = false;
+  } sg;
   std::vector<void*> allocs;
   // profiling
   int prof_max = 0, prof_calls = 0;
@@ -171,6 +180,9 @@ void free_dev(pmfem_ctx* c) {
   if (!c->dev) return;
   if (c->dev->side) (void)hipStreamSynchronize(c->dev->side);
   if (c->stream || c->dev->side) (void)hipStreamSynchronize((hipStream_t)c->stream);
+  if (c->dev->sg.x) (void)hipGraphExecDestroy(c->dev->sg.x);
+  if (c->dev->sg.g) (void)hipGraphDestroy(c->dev->sg.g);
+  if (c->dev->sg.cap) (void)hipStreamDestroy(c->dev->sg.cap);
   if (c->dev->imp.host) (void)hipHostFree(c->dev->imp.host);
   for (void* p : c->dev->allocs) (void)hipFree(p);
   for (hipEvent_t e : c->dev->ev) (void)hipEventDestroy(e);
@@ -2461,6 +2473,65 @@ int pmfem_llg_step(pmfem_ctx* c, double* m_dev, double dt, double alpha, int32_t
     if ((rc = enqueue_rk4(c, m_dev, dt, alpha, h_applied))) return rc;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_err(c, e, "kernel launch");
+  return PMFEM_OK;
+}
+
+int pmfem_llg_step_graph(pmfem_ctx* c, double* m_dev, double dt, double alpha, int32_t n_steps,
+                         const double* h_applied) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!m_dev || n_steps < 0 || !(dt > 0.0) || !(alpha >= 0.0))
+    return set_err(c, PMFEM_EINVAL, "bad llg arguments");
+  if (n_steps == 0) return PMFEM_OK;
+  pmfem_dev* d = c->dev;
+  pmfem_dev::StepGraph& G = d->sg;
+  const bool wh = h_applied != nullptr;
+  bool same = G.x && G.m == m_dev && G.dt == dt && G.alpha == alpha && G.with_happ == wh;
+  for (int k = 0; same && wh && k < 3; ++k) same = G.happ[k] == h_applied[k];
+  hipError_t e = hipSuccess;
+  if (!same) {
+    // capture one step on a stream of the library's own: the kernels of the
+    // step and the fork to the second stream and back, nothing else
+    if (G.x) {
+      e = hipStreamSynchronize(stream_of(c));
+      (void)hipGraphExecDestroy(G.x);
+      G.x = nullptr;
+    }
+    if (G.g) {
+      (void)hipGraphDestroy(G.g);
+      G.g = nullptr;
+    }
+    if (e == hipSuccess && !G.cap) e = hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_err(c, e, "graph stream");
+    void* saved = c->stream;
+    const int prof_max = d->prof_max;
+    d->prof_max = d->prof_calls;  // no profiling events inside the graph
+    c->stream = G.cap;
+    e = hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) rc = enqueue_rk4(c, m_dev, dt, alpha, h_applied);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(G.cap, &g) : e;
+    c->stream = saved;
+    d->prof_max = prof_max;
+    if (rc || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc ? rc : hip_err(c, e2, "graph capture");
+    }
+    e = hipGraphInstantiate(&G.x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      G.x = nullptr;
+      return hip_err(c, e, "graph instantiate");
+    }
+    G.g = g;
+    G.m = m_dev;
+    G.dt = dt;
+    G.alpha = alpha;
+    G.with_happ = wh;
+    for (int k = 0; k < 3; ++k) G.happ[k] = wh ? h_applied[k] : 0.0;
+  }
+  for (int32_t i = 0; i < n_steps && e == hipSuccess; ++i) e = hipGraphLaunch(G.x, stream_of(c));
+  if (e != hipSuccess) return hip_err(c, e, "graph launch");
   return PMFEM_OK;
 }
 
