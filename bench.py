@@ -286,7 +286,9 @@ def run_batched(args):
     m64 = m.double()
     llg_steps = max(1, args.steps // 10)
     dt_llg = timed(lambda: batch.llg_step(m64, 1e-13, 0.5, 1), llg_steps)
-    log(f"one RK4 step of {len(ctxs)} films (batch): {dt_llg * 1e3:.3f} ms")
+    dt_graph = timed(lambda: batch.llg_step_graph(m64, 1e-13, 0.5, 1), llg_steps)
+    log(f"one RK4 step of {len(ctxs)} films (batch): {dt_llg * 1e3:.3f} ms, replayed from a "
+        f"captured HIP graph {dt_graph * 1e3:.3f} ms")
     achieved = batch.bytes_per_eval / dt_batch / 1e9
     result = {
         "metric": "H_eff evals/s of batched unit cells (cell evaluations)",
@@ -316,6 +318,7 @@ def run_batched(args):
             "one_after_another_ms": dt_loop * 1e3,
             "batch_speedup": dt_loop / dt_batch,
             "rk4_step_ms": dt_llg * 1e3,
+            "rk4_step_graph_ms": dt_graph * 1e3,
             "max_rel_diff_vs_per_cell": diff,
         },
         "roofline": {"kernel": "whole batch evaluation (model bytes)", "bound": "hbm",

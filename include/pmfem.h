@@ -394,6 +394,14 @@ int pmfem_batch_heff(pmfem_batch* b, const float* m_dev, float* h_dev, uint32_t 
  * packed FP64 master magnetisation m_dev[n_unknowns][3]. */
 int pmfem_batch_llg_step(pmfem_batch* b, double* m_dev, double dt, double alpha,
                          int32_t n_steps);
+/*
+ * pmfem_batch_llg_step through a HIP graph, as pmfem_llg_step_graph for one
+ * context: one RK4 step of the whole batch is captured (again when m_dev,
+ * dt or alpha change) and launched n_steps times on the batch's stream; the
+ * results are those of pmfem_batch_llg_step, bit for bit.
+ */
+int pmfem_batch_llg_step_graph(pmfem_batch* b, double* m_dev, double dt, double alpha,
+                               int32_t n_steps);
 const char* pmfem_batch_last_error(const pmfem_batch* b);
 void pmfem_batch_destroy(pmfem_batch* b);
 

@@ -78,6 +78,7 @@ _SIGS = {
     "pmfem_batch_query": (ctypes.c_int, [_P, ctypes.POINTER(_I64), _P, _DP]),
     "pmfem_batch_heff": (ctypes.c_int, [_P, _P, _P, _U32]),
     "pmfem_batch_llg_step": (ctypes.c_int, [_P, _P, _D, _D, _I32]),
+    "pmfem_batch_llg_step_graph": (ctypes.c_int, [_P, _P, _D, _D, _I32]),
     "pmfem_batch_last_error": (ctypes.c_char_p, [_P]),
     "pmfem_batch_destroy": (None, [_P]),
     "pmfem_last_error": (ctypes.c_char_p, [_P]),
@@ -401,6 +402,13 @@ class Batch:
         self._check(self.lib.pmfem_batch_llg_step(
             self.h, _dev_ptr(m64, torch.float64, (self.n, 3), "m"), float(dt), float(alpha),
             int(n_steps)), "batch_llg_step")
+
+    def llg_step_graph(self, m64, dt, alpha, n_steps=1):
+        """RK4 steps of the batch as launches of a captured HIP graph of one step."""
+        import torch
+        self._check(self.lib.pmfem_batch_llg_step_graph(
+            self.h, _dev_ptr(m64, torch.float64, (self.n, 3), "m"), float(dt), float(alpha),
+            int(n_steps)), "batch_llg_step_graph")
 
     def close(self):
         if getattr(self, "h", None):

@@ -1762,6 +1762,12 @@ struct pmfem_batch {
   int device = 0;
   hipStream_t stream = nullptr, side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
+  // one captured RK4 step of the batch (pmfem_batch_llg_step_graph)
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double* gm = nullptr;
+  double gdt = 0.0, galpha = 0.0;
   std::vector<pmfem_ctx*> cells;
   std::vector<int64_t> off;  // first unknown of each cell in the batch vectors, [K + 1]
   int64_t n = 0;
@@ -1817,6 +1823,9 @@ int bupload(pmfem_batch* b, T** p, const void* src, size_t count) {
 void batch_free(pmfem_batch* b) {
   if (b->stream || b->side) (void)hipStreamSynchronize(b->stream);
   if (b->side) (void)hipStreamSynchronize(b->side);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
   for (void* p : b->allocs) (void)hipFree(p);
   if (b->fork) (void)hipEventDestroy(b->fork);
   if (b->join) (void)hipEventDestroy(b->join);
@@ -2822,6 +2831,57 @@ int pmfem_batch_llg_step(pmfem_batch* b, double* m_dev, double dt, double alpha,
   }
   e = hipGetLastError();
   if (e != hipSuccess) return batch_err(b, PMFEM_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return PMFEM_OK;
+}
+
+int pmfem_batch_llg_step_graph(pmfem_batch* b, double* m_dev, double dt, double alpha,
+                               int32_t n_steps) {
+  if (!b) return PMFEM_EINVAL;
+  if (!b->tab) return batch_err(b, PMFEM_ESTATE, "batch set-up failed");
+  if (!m_dev || n_steps < 0 || !(dt > 0.0) || !(alpha >= 0.0))
+    return batch_err(b, PMFEM_EINVAL, "bad batch llg arguments");
+  hipError_t e = hipSetDevice(b->device);
+  if (e != hipSuccess) return batch_err(b, PMFEM_EHIP, "hipSetDevice");
+  if (n_steps == 0) return PMFEM_OK;
+  if (!(b->gexec && b->gm == m_dev && b->gdt == dt && b->galpha == alpha)) {
+    // capture one step on a stream of the batch's own: its kernels and the
+    // fork to the second stream and back
+    if (b->gexec) {
+      e = hipStreamSynchronize(b->stream);
+      (void)hipGraphExecDestroy(b->gexec);
+      b->gexec = nullptr;
+    }
+    if (b->graph) {
+      (void)hipGraphDestroy(b->graph);
+      b->graph = nullptr;
+    }
+    if (e == hipSuccess && !b->cap) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return batch_err(b, PMFEM_EHIP, "graph stream");
+    hipStream_t saved = b->stream;
+    b->stream = b->cap;
+    int rc = PMFEM_OK;
+    e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) rc = batch_rk4(b, m_dev, dt, alpha);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(b->cap, &g) : e;
+    b->stream = saved;
+    if (rc || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc ? rc : batch_err(b, PMFEM_EHIP, std::string("graph capture: ") + hipGetErrorString(e2));
+    }
+    e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      b->gexec = nullptr;
+      return batch_err(b, PMFEM_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    b->graph = g;
+    b->gm = m_dev;
+    b->gdt = dt;
+    b->galpha = alpha;
+  }
+  for (int32_t i = 0; i < n_steps && e == hipSuccess; ++i) e = hipGraphLaunch(b->gexec, b->stream);
+  if (e != hipSuccess) return batch_err(b, PMFEM_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
   return PMFEM_OK;
 }
 

@@ -54,3 +54,31 @@ def test_graph_step_refuses_bad_arguments():
         with pytest.raises(B.PmfemError) as e:
             ctx.llg_step_graph(m, dt, alpha, n)
         assert e.value.code == B.Status.EINVAL
+
+
+def test_batch_graph_steps_equal_eager_batch_steps():
+    """The batch's RK4 step captured as one graph (all cells, one launch per
+    stage, the second stream forked and joined): every replay equals the
+    eager batch steps bit for bit, with eager work between the replays."""
+    probs = [mg.film_c1(),
+             mg.kuhn_box((5, 7, 6), 1e-9, periodic=0b111, jitter=0.2, grid=(16, 16, 16)),
+             mg.kuhn_box((5, 6, 5), 1e-9, periodic=0b111, jitter=0.2, grid=(15, 14, 21))]
+    probs += mg.films_c4(3, nodes=(2e3, 6e3), period=(20e-9, 40e-9))
+    ctxs = [B.Context.from_problem(p, device=0) for p in probs]
+    noun = [c.query()[2] for c in ctxs]
+    batch = B.Batch(ctxs)
+    m0 = torch.cat([torch.tensor(p.m[nou], dtype=torch.float64) for p, nou in zip(probs, noun)]
+                   ).cuda()
+    me, mg_ = m0.clone(), m0.clone()
+    h = torch.empty(me.shape, dtype=torch.float32, device="cuda")
+    for rep in range(3):
+        batch.llg_step(me, 1e-13, 0.5, 2)
+        batch.llg_step_graph(mg_, 1e-13, 0.5, 2)
+        batch.heff(me.float().contiguous(), h)      # eager work between the replays
+        torch.cuda.synchronize()
+        assert torch.equal(me, mg_), rep
+    batch.llg_step(me, 3e-13, 0.2, 2)
+    batch.llg_step_graph(mg_, 3e-13, 0.2, 2)        # new arguments: captured anew
+    torch.cuda.synchronize()
+    assert torch.equal(me, mg_)
+    batch.close()
