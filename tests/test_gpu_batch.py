@@ -12,7 +12,9 @@ An earlier graph-captured batch (each cell's work captured on its own branch
 of one HIP graph, then replayed) crashed the host process (segmentation
 fault) in its first call on the GPU, before any result came back; no cause
 was found in this code by reading it, so that path was taken out of the
-library and its tests (test_graph_batch_*) stay skipped. The autotuner's
+library and its tests (test_graph_batch_*) stay skipped; a batch's RK4 step
+captured as one graph on a single stream with its second stream forked and
+joined is tested in test_gpu_graph.py. The autotuner's
 choice must give the same fields up to FP32 rounding order.
 """
 import numpy as np
