@@ -405,6 +405,81 @@ int pmfem_batch_llg_step_graph(pmfem_batch* b, double* m_dev, double dt, double 
 const char* pmfem_batch_last_error(const pmfem_batch* b);
 void pmfem_batch_destroy(pmfem_batch* b);
 
+/*
+ * Learned surrogate of the grid convolution: the second of the four AIM steps
+ * (Sec. 3.2.2: the grid charges Q convolved with the periodic Green's
+ * function to give the grid potential U, done by FFT in pmfem_heff) replaced
+ * by a network of 3x3x3 convolution layers on the same [nz][ny][nx] FP32 grid
+ * (x fastest), circular along x and y and zero-padded along z; for films
+ * (periodic along x and y only) with the FP32 grid (precision 0). Anterpolation,
+ * interpolation, precorrection and the local operators are unchanged.
+ *
+ * Network: layer 0 maps 1 -> 32 channels, layers 1 .. depth-2 map 32 -> 32,
+ * layer depth-1 maps 32 -> 1, ReLU after every layer but the last. Input
+ * Q s_in, output times s_out. Parameter vector (FP32), layer by layer:
+ * W[co][ci][3][3][3] (index [dz+1][dy+1][dx+1] for the input offset) then
+ * b[co]. The kernels use the weights rounded to BF16 (round to nearest even;
+ * biases FP32) and accumulate in FP32; the 32 -> 32 layers run on the matrix
+ * cores. bf16_activations = 0 keeps FP32 accuracy in those layers by
+ * multiplying a BF16 high part and a BF16 remainder of every activation; 1
+ * multiplies the BF16-rounded activations only.
+ *
+ * pmfem_surrogate_init: (re)creates the network of the built context with
+ * He-normal weights drawn from seed, zero biases and unset scales. EINVAL for
+ * depth outside [2, 12], a cell that is not a film, precision != 0; ENOMEM.
+ * The other calls return ESTATE before init; apply, loss_grad, enable(1) and
+ * llg_step_judged also while the scales are unset.
+ */
+int pmfem_surrogate_init(pmfem_ctx* ctx, int32_t depth, uint64_t seed, int32_t bf16_activations);
+int pmfem_surrogate_param_count(pmfem_ctx* ctx, int64_t* count);
+/* params[count] (host, FP32; count must equal the parameter count) replaces
+ * the weights and resets the optimiser; scales[2] = {s_in, s_out} (host,
+ * positive) or NULL to keep them. get copies them out (params or scales may
+ * be NULL). */
+int pmfem_surrogate_set_params(pmfem_ctx* ctx, const float* params, int64_t count,
+                               const double* scales);
+int pmfem_surrogate_get_params(pmfem_ctx* ctx, float* params, int64_t count, double* scales);
+/* u_grid_dev = surrogate(q_grid_dev), device [nz][ny][nx] FP32 buffers of the
+ * context's grid (they may be the same buffer); enqueued on the context's
+ * stream. */
+int pmfem_surrogate_apply(pmfem_ctx* ctx, const float* q_grid_dev, float* u_grid_dev);
+/* One forward and backward pass: y = network(q s_in) (before s_out), loss =
+ * mean over the grid points of (y - t)^2 with t_grid_dev in network units,
+ * grad[count] (host, or NULL) its gradient with respect to the parameter
+ * vector, loss (host, or NULL). Synchronous. */
+int pmfem_surrogate_loss_grad(pmfem_ctx* ctx, const float* q_grid_dev, const float* t_grid_dev,
+                              double* loss, float* grad, int64_t count);
+/* A synthetic magnetisation texture on the unknowns, m_dev[N'][3] FP64
+ * (device): kind 0 iid uniform on the sphere, 1 a vortex (random centre,
+ * core radius, chirality, polarity), 2 a pair of domain walls along x or y
+ * (random position, width, domain and turning directions); parameters drawn
+ * from seed. */
+int pmfem_surrogate_texture(pmfem_ctx* ctx, int32_t kind, uint64_t seed, double* m_dev);
+/* Trains on n_pairs AIM pairs, each a fresh texture (kinds: bit k enables
+ * kind k, used in turn) whose grid charges and FFT-convolved potential the
+ * plain AIM of this context produces; one Adam step (lr, beta 0.9 / 0.999)
+ * per pair on the mean-squared error of the potential in network units. The
+ * first pair sets unset scales (unit mean square at input and output).
+ * loss_log[n_pairs] (host, or NULL) receives each pair's loss before its
+ * step. Synchronous. */
+int pmfem_surrogate_train(pmfem_ctx* ctx, int32_t n_pairs, double lr, uint64_t seed,
+                          uint32_t kinds, double* loss_log);
+/* on != 0: pmfem_heff and the LLG steppers use the surrogate in place of the
+ * FFT convolution until disabled. */
+int pmfem_surrogate_enable(pmfem_ctx* ctx, int32_t on);
+/*
+ * n_steps RK4 steps (as pmfem_llg_step) with the surrogate, judged by the
+ * plain AIM: before every check_every-th step (from the first) the
+ * magnetostatic field of the current state is evaluated both ways, error =
+ * |H_sur - H_aim| / |H_aim| (2-norms over all unknowns); once an error
+ * exceeds tol the rest of the steps use the FFT convolution. report[4]
+ * (host, or NULL): checks made, largest and last error, the step of the
+ * fallback (-1 if none). Synchronises at every check.
+ */
+int pmfem_llg_step_judged(pmfem_ctx* ctx, double* m_dev, double dt, double alpha,
+                          int32_t n_steps, const double* h_applied, int32_t check_every,
+                          double tol, double* report);
+
 const char* pmfem_last_error(const pmfem_ctx* ctx);
 
 void pmfem_destroy(pmfem_ctx* ctx);

@@ -46,6 +46,7 @@ _I32 = ctypes.c_int32
 _U32 = ctypes.c_uint32
 _D = ctypes.c_double
 _DP = ctypes.POINTER(ctypes.c_double)
+_U64 = ctypes.c_uint64
 
 _SIGS = {
     "pmfem_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P]),
@@ -79,6 +80,16 @@ _SIGS = {
     "pmfem_batch_heff": (ctypes.c_int, [_P, _P, _P, _U32]),
     "pmfem_batch_llg_step": (ctypes.c_int, [_P, _P, _D, _D, _I32]),
     "pmfem_batch_llg_step_graph": (ctypes.c_int, [_P, _P, _D, _D, _I32]),
+    "pmfem_surrogate_init": (ctypes.c_int, [_P, _I32, _U64, _I32]),
+    "pmfem_surrogate_param_count": (ctypes.c_int, [_P, ctypes.POINTER(_I64)]),
+    "pmfem_surrogate_set_params": (ctypes.c_int, [_P, _P, _I64, _P]),
+    "pmfem_surrogate_get_params": (ctypes.c_int, [_P, _P, _I64, _P]),
+    "pmfem_surrogate_apply": (ctypes.c_int, [_P, _P, _P]),
+    "pmfem_surrogate_loss_grad": (ctypes.c_int, [_P, _P, _P, _DP, _P, _I64]),
+    "pmfem_surrogate_texture": (ctypes.c_int, [_P, _I32, _U64, _P]),
+    "pmfem_surrogate_train": (ctypes.c_int, [_P, _I32, _D, _U64, _U32, _P]),
+    "pmfem_surrogate_enable": (ctypes.c_int, [_P, _I32]),
+    "pmfem_llg_step_judged": (ctypes.c_int, [_P, _P, _D, _D, _I32, _P, _I32, _D, _P]),
     "pmfem_batch_last_error": (ctypes.c_char_p, [_P]),
     "pmfem_batch_destroy": (None, [_P]),
     "pmfem_last_error": (ctypes.c_char_p, [_P]),
@@ -329,6 +340,83 @@ class Context:
         return dict(accepted=int(st[0]), rejected=int(st[1] + st[2]), rejected_error=int(st[1]),
                     rejected_newton=int(st[2]), newton=int(st[3]), krylov=int(st[4]),
                     dt_next=float(dt[0]), attempts=att, dts=att[att > 0])
+
+    # -- learned surrogate of the grid convolution -------------------------
+    def _grid_shape(self):
+        info = self.export("grid_info")
+        return (int(info[2]), int(info[1]), int(info[0]))
+
+    def surrogate_init(self, depth=6, seed=0, bf16_activations=False):
+        self._check(self.lib.pmfem_surrogate_init(self.h, int(depth), int(seed),
+                                                  int(bool(bf16_activations))), "surrogate_init")
+
+    def surrogate_param_count(self):
+        n = _I64(0)
+        self._check(self.lib.pmfem_surrogate_param_count(self.h, ctypes.byref(n)),
+                    "surrogate_param_count")
+        return int(n.value)
+
+    def surrogate_set_params(self, params, scales=None):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        sc = None if scales is None else np.ascontiguousarray(scales, dtype=np.float64)
+        self._check(self.lib.pmfem_surrogate_set_params(self.h, _ptr(p), p.size, _ptr(sc)),
+                    "surrogate_set_params")
+
+    def surrogate_get_params(self):
+        """(parameter vector, (s_in, s_out))"""
+        p = np.empty(self.surrogate_param_count(), np.float32)
+        sc = np.zeros(2, np.float64)
+        self._check(self.lib.pmfem_surrogate_get_params(self.h, _ptr(p), p.size, _ptr(sc)),
+                    "surrogate_get_params")
+        return p, (float(sc[0]), float(sc[1]))
+
+    def surrogate_apply(self, qg, ug):
+        import torch
+        shape = self._grid_shape()
+        self._check(self.lib.pmfem_surrogate_apply(
+            self.h, _dev_ptr(qg, torch.float32, shape, "qg"),
+            _dev_ptr(ug, torch.float32, shape, "ug")), "surrogate_apply")
+
+    def surrogate_loss_grad(self, qg, tg):
+        """(loss, gradient vector) of one forward/backward pass."""
+        import torch
+        shape = self._grid_shape()
+        g = np.empty(self.surrogate_param_count(), np.float32)
+        loss = ctypes.c_double(0.0)
+        self._check(self.lib.pmfem_surrogate_loss_grad(
+            self.h, _dev_ptr(qg, torch.float32, shape, "qg"),
+            _dev_ptr(tg, torch.float32, shape, "tg"), ctypes.byref(loss), _ptr(g), g.size),
+            "surrogate_loss_grad")
+        return float(loss.value), g
+
+    def surrogate_texture(self, m64, kind, seed=0):
+        import torch
+        self._check(self.lib.pmfem_surrogate_texture(
+            self.h, int(kind), int(seed), _dev_ptr(m64, torch.float64, (self.n, 3), "m")),
+            "surrogate_texture")
+
+    def surrogate_train(self, n_pairs, lr=1e-3, seed=0, kinds=0b111):
+        """Trains on n_pairs AIM pairs; returns the loss of every pair."""
+        log = np.zeros(max(1, int(n_pairs)), np.float64)
+        self._check(self.lib.pmfem_surrogate_train(self.h, int(n_pairs), float(lr), int(seed),
+                                                   int(kinds), _ptr(log)), "surrogate_train")
+        return log[:int(n_pairs)]
+
+    def surrogate_enable(self, on=True):
+        self._check(self.lib.pmfem_surrogate_enable(self.h, int(bool(on))), "surrogate_enable")
+
+    def llg_step_judged(self, m64, dt, alpha, n_steps, check_every=50, tol=1e-3,
+                        h_applied=None):
+        """RK4 steps with the surrogate, judged by the plain AIM; returns a dict
+        (checks, max_error, last_error, fallback_step)."""
+        import torch
+        ha = None if h_applied is None else np.ascontiguousarray(h_applied, dtype=np.float64)
+        rep = np.zeros(4, np.float64)
+        self._check(self.lib.pmfem_llg_step_judged(
+            self.h, _dev_ptr(m64, torch.float64, (self.n, 3), "m"), float(dt), float(alpha),
+            int(n_steps), _ptr(ha), int(check_every), float(tol), _ptr(rep)), "llg_step_judged")
+        return dict(checks=int(rep[0]), max_error=float(rep[1]), last_error=float(rep[2]),
+                    fallback_step=int(rep[3]))
 
     def autotune(self, trials=20):
         """Pick the fastest kernel forms; returns ({stage: form}, ms per evaluation)."""

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpmfem.so")
 HOST_SRC = ["setup.cpp", "pgf.cpp", "fft64.cpp", "z0.cpp"]
-HIP_SRC = ["kernels.hip", "capi.hip"]
+HIP_SRC = ["kernels.hip", "capi.hip", "surrogate.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed FP32 instructions are disabled for all device code

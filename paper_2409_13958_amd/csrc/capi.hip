@@ -12,6 +12,7 @@
 
 #include "internal.h"
 #include "kernels.h"
+#include "surrogate.h"
 
 using namespace pmfem;
 
@@ -112,6 +113,12 @@ struct pmfem_dev {
     double dt = 0.0, alpha = 0.0, happ[3] = {0.0, 0.0, 0.0};
     bool with_happ = false;
   } sg;
+  // learned surrogate of the grid convolution; net_on makes run_heff use it
+  // in place of the FFT convolution. tap_q / tap_u, when set, receive copies
+  // of the grid charges and potential of the next evaluation.
+  Surrogate* net = nullptr;
+  bool net_on = false;
+  float *tap_q = nullptr, *tap_u = nullptr;
   std::vector<void*> allocs;
   // profiling
   int prof_max = 0, prof_calls = 0;
@@ -184,6 +191,10 @@ void free_dev(pmfem_ctx* c) {
   if (c->dev->sg.g) (void)hipGraphDestroy(c->dev->sg.g);
   if (c->dev->sg.cap) (void)hipStreamDestroy(c->dev->sg.cap);
   if (c->dev->imp.host) (void)hipHostFree(c->dev->imp.host);
+  if (c->dev->net) {
+    sg_destroy(c->dev->net);
+    delete c->dev->net;
+  }
   for (void* p : c->dev->allocs) (void)hipFree(p);
   for (hipEvent_t e : c->dev->ev) (void)hipEventDestroy(e);
   if (c->dev->fork) (void)hipEventDestroy(c->dev->fork);
@@ -1135,7 +1146,14 @@ int run_heff(pmfem_ctx* c, const float* m, float* h, uint32_t terms, const doubl
                          d->box_start, d->brx, d->bry, d->brz, d->grid);
       mark(1, 1);
     }
-    convolve(d, s, d->grid, d->grid, d->spec, d->g.gmode, mark);
+    const size_t gbytes = (size_t)g.N[0] * g.N[1] * g.N[2] * sizeof(float);
+    if (d->tap_q) (void)hipMemcpyAsync(d->tap_q, d->grid, gbytes, hipMemcpyDeviceToDevice, s);
+    if (d->net_on) {
+      (void)sg_apply(d->net, s, d->grid, d->grid);
+    } else {
+      convolve(d, s, d->grid, d->grid, d->spec, d->g.gmode, mark);
+    }
+    if (d->tap_u) (void)hipMemcpyAsync(d->tap_u, d->grid, gbytes, hipMemcpyDeviceToDevice, s);
     (void)hipStreamWaitEvent(s, d->join, 0);
     mark(7, 0);
     {
@@ -2900,6 +2918,301 @@ void pmfem_destroy(pmfem_ctx* c) {
   if (c->dev && c->device >= 0) (void)hipSetDevice(c->device);
   free_dev(c);
   delete c;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Learned surrogate of the grid convolution (layers, layout and precision in
+// surrogate.h).
+
+namespace {
+
+int net_ready(pmfem_ctx* c, bool need_scales) {
+  int rc = ready(c);
+  if (rc) return rc;
+  if (!c->dev->net) return set_err(c, PMFEM_ESTATE, "pmfem_surrogate_init has not been called");
+  if (need_scales && !(c->dev->net->s_in > 0.f && c->dev->net->s_out > 0.f))
+    return set_err(c, PMFEM_ESTATE, "surrogate scales not set (train it or set its parameters)");
+  return PMFEM_OK;
+}
+
+// host RNG for the texture parameters: the same SplitMix64 finaliser
+struct HostRng {
+  uint64_t s;
+  uint64_t next() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  double uni() { return ((double)(next() >> 11) + 0.5) * 0x1p-53; }
+};
+
+SgTexture draw_texture(const pmfem_ctx* c, int kind, uint64_t seed) {
+  HostRng r{seed * 0x2545F4914F6CDD1Dull + 0x1234567ull};
+  SgTexture t{};
+  t.kind = kind;
+  t.seed = (uint32_t)(r.next() & 0xffffffffu);
+  t.Lx = c->L[0];
+  t.Ly = c->L[1];
+  const double lmin = std::min(t.Lx, t.Ly);
+  if (kind == 1) {
+    t.cx = r.uni() * t.Lx;
+    t.cy = r.uni() * t.Ly;
+    t.rc = lmin * (0.03 + 0.12 * r.uni());
+    t.chir = r.uni() < 0.5 ? -1.0 : 1.0;
+    t.pol = r.uni() < 0.5 ? -1.0 : 1.0;
+  } else if (kind == 2) {
+    const bool along_x = r.uni() < 0.5;
+    t.nx = along_x ? 1.0 : 0.0;
+    t.ny = along_x ? 0.0 : 1.0;
+    const double L = along_x ? t.Lx : t.Ly;
+    t.cx = r.uni() * L;
+    t.rc = L * (0.01 + 0.05 * r.uni());
+    // domain direction uniform on the sphere, the turning direction uniform
+    // on the circle perpendicular to it
+    const double z = 2.0 * r.uni() - 1.0, ph = 2.0 * kPi * r.uni(), rr = std::sqrt(1.0 - z * z);
+    const double ed[3] = {rr * std::cos(ph), rr * std::sin(ph), z};
+    double a[3] = {std::fabs(ed[0]) < 0.9 ? 1.0 : 0.0, std::fabs(ed[0]) < 0.9 ? 0.0 : 1.0, 0.0};
+    double u[3] = {ed[1] * a[2] - ed[2] * a[1], ed[2] * a[0] - ed[0] * a[2], ed[0] * a[1] - ed[1] * a[0]};
+    const double un = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    for (double& x : u) x /= un;
+    const double v[3] = {ed[1] * u[2] - ed[2] * u[1], ed[2] * u[0] - ed[0] * u[2], ed[0] * u[1] - ed[1] * u[0]};
+    const double ps = 2.0 * kPi * r.uni();
+    for (int k = 0; k < 3; ++k) {
+      t.ed[k] = ed[k];
+      t.er[k] = std::cos(ps) * u[k] + std::sin(ps) * v[k];
+    }
+  }
+  return t;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pmfem_surrogate_init(pmfem_ctx* c, int32_t depth, uint64_t seed, int32_t bf16_activations) {
+  int rc = ready(c);
+  if (rc) return rc;
+  pmfem_dev* d = c->dev;
+  if (depth < 2 || depth > kSgMaxDepth)
+    return set_err(c, PMFEM_EINVAL, "surrogate depth must be in [2, " + std::to_string(kSgMaxDepth) + "]");
+  if (!(d->g.per[0] && d->g.per[1] && !d->g.per[2]))
+    return set_err(c, PMFEM_EINVAL, "the surrogate needs a film: periodic along x and y only");
+  if (d->g.gmode != 0)
+    return set_err(c, PMFEM_EINVAL, "the surrogate needs the FP32 grid (precision 0)");
+  if (d->net) {
+    sg_destroy(d->net);
+    delete d->net;
+    d->net = nullptr;
+    d->net_on = false;
+  }
+  Surrogate* net = new Surrogate();
+  const SgGrid gd{d->g.N[0], d->g.N[1], d->g.N[2]};
+  hipError_t e = sg_create(net, depth, gd, d->n, c->ops.pos.data(), bf16_activations == 0);
+  if (e != hipSuccess) {
+    sg_destroy(net);
+    delete net;
+    return e == hipErrorOutOfMemory ? set_err(c, PMFEM_ENOMEM, "surrogate buffers")
+                                    : hip_err(c, e, "surrogate allocation");
+  }
+  d->net = net;
+  std::vector<float> p;
+  sg_default_params(net, seed, p);
+  if ((e = sg_set_params(net, p.data(), stream_of(c))) != hipSuccess)
+    return hip_err(c, e, "surrogate parameters");
+  if ((e = hipStreamSynchronize(stream_of(c))) != hipSuccess) return hip_err(c, e, "surrogate init");
+  return PMFEM_OK;
+}
+
+int pmfem_surrogate_param_count(pmfem_ctx* c, int64_t* count) {
+  int rc = net_ready(c, false);
+  if (rc) return rc;
+  if (!count) return set_err(c, PMFEM_EINVAL, "null count");
+  *count = c->dev->net->nparam;
+  return PMFEM_OK;
+}
+
+int pmfem_surrogate_set_params(pmfem_ctx* c, const float* params, int64_t count,
+                               const double* scales) {
+  int rc = net_ready(c, false);
+  if (rc) return rc;
+  Surrogate* net = c->dev->net;
+  if (!params || count != net->nparam)
+    return set_err(c, PMFEM_EINVAL, "parameter vector must hold " + std::to_string(net->nparam) + " values");
+  if (scales && !(scales[0] > 0.0 && scales[1] > 0.0))
+    return set_err(c, PMFEM_EINVAL, "surrogate scales must be positive");
+  hipError_t e = sg_set_params(net, params, stream_of(c));
+  if (e == hipSuccess) e = hipStreamSynchronize(stream_of(c));
+  if (e != hipSuccess) return hip_err(c, e, "surrogate parameters");
+  if (scales) {
+    net->s_in = (float)scales[0];
+    net->s_out = (float)scales[1];
+  }
+  return PMFEM_OK;
+}
+
+int pmfem_surrogate_get_params(pmfem_ctx* c, float* params, int64_t count, double* scales) {
+  int rc = net_ready(c, false);
+  if (rc) return rc;
+  Surrogate* net = c->dev->net;
+  if (params) {
+    if (count != net->nparam)
+      return set_err(c, PMFEM_EINVAL, "parameter vector must hold " + std::to_string(net->nparam) + " values");
+    hipError_t e = sg_get_params(net, params, stream_of(c));
+    if (e != hipSuccess) return hip_err(c, e, "surrogate parameters");
+  }
+  if (scales) {
+    scales[0] = net->s_in;
+    scales[1] = net->s_out;
+  }
+  return PMFEM_OK;
+}
+
+int pmfem_surrogate_apply(pmfem_ctx* c, const float* q_grid_dev, float* u_grid_dev) {
+  int rc = net_ready(c, true);
+  if (rc) return rc;
+  if (!q_grid_dev || !u_grid_dev) return set_err(c, PMFEM_EINVAL, "null grid buffer");
+  hipError_t e = sg_apply(c->dev->net, stream_of(c), q_grid_dev, u_grid_dev);
+  if (e != hipSuccess) return hip_err(c, e, "surrogate launch");
+  return PMFEM_OK;
+}
+
+int pmfem_surrogate_loss_grad(pmfem_ctx* c, const float* q_grid_dev, const float* t_grid_dev,
+                              double* loss, float* grad, int64_t count) {
+  int rc = net_ready(c, true);
+  if (rc) return rc;
+  Surrogate* net = c->dev->net;
+  if (!q_grid_dev || !t_grid_dev) return set_err(c, PMFEM_EINVAL, "null grid buffer");
+  if (grad && count != net->nparam)
+    return set_err(c, PMFEM_EINVAL, "gradient vector must hold " + std::to_string(net->nparam) + " values");
+  hipStream_t s = stream_of(c);
+  hipError_t e = sg_ensure_training(net, 1);
+  if (e != hipSuccess) return set_err(c, PMFEM_ENOMEM, "surrogate training buffers");
+  if ((e = sg_loss_grad(net, s, q_grid_dev, t_grid_dev, 1.f, 0)) != hipSuccess)
+    return hip_err(c, e, "surrogate launch");
+  if (loss && (e = hipMemcpyAsync(loss, net->loss, sizeof(double), hipMemcpyDeviceToHost, s)))
+    return hip_err(c, e, "loss copy");
+  if (grad && (e = hipMemcpyAsync(grad, net->grad, (size_t)count * 4, hipMemcpyDeviceToHost, s)))
+    return hip_err(c, e, "gradient copy");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_err(c, e, "surrogate gradient");
+  return PMFEM_OK;
+}
+
+int pmfem_surrogate_texture(pmfem_ctx* c, int32_t kind, uint64_t seed, double* m_dev) {
+  int rc = net_ready(c, false);
+  if (rc) return rc;
+  if (!m_dev || kind < 0 || kind > 2) return set_err(c, PMFEM_EINVAL, "bad texture arguments");
+  hipError_t e = sg_texture(c->dev->net, stream_of(c), draw_texture(c, kind, seed), m_dev);
+  if (e != hipSuccess) return hip_err(c, e, "texture launch");
+  return PMFEM_OK;
+}
+
+int pmfem_surrogate_train(pmfem_ctx* c, int32_t n_pairs, double lr, uint64_t seed, uint32_t kinds,
+                          double* loss_log) {
+  int rc = net_ready(c, false);
+  if (rc) return rc;
+  if (n_pairs < 0 || !(lr > 0.0) || (kinds & 7u) == 0)
+    return set_err(c, PMFEM_EINVAL, "bad training arguments");
+  pmfem_dev* d = c->dev;
+  Surrogate* net = d->net;
+  hipStream_t s = stream_of(c);
+  hipError_t e = sg_ensure_training(net, std::max(1, n_pairs));
+  if (e != hipSuccess) return set_err(c, PMFEM_ENOMEM, "surrogate training buffers");
+  int list[3], nk = 0;
+  for (int k = 0; k < 3; ++k)
+    if (kinds & (1u << k)) list[nk++] = k;
+  const bool was_on = d->net_on;
+  for (int32_t it = 0; it < n_pairs; ++it) {
+    // one AIM pair: texture -> charges -> grid charges Q -> grid potential U
+    const SgTexture tx = draw_texture(c, list[it % nk], seed * 1000003ull + (uint64_t)it);
+    if ((e = sg_texture(net, s, tx, net->m64)) || (e = sg_to_f32(net, s, net->m64, net->m32)))
+      return hip_err(c, e, "texture launch");
+    d->net_on = false;
+    d->tap_q = net->qbuf;
+    d->tap_u = net->ubuf;
+    rc = run_heff(c, net->m32, net->ha, PMFEM_TERM_MS, nullptr);
+    d->tap_q = d->tap_u = nullptr;
+    d->net_on = was_on;
+    if (rc) return rc;
+    if (!(net->s_in > 0.f && net->s_out > 0.f)) {
+      // scales from the first pair: unit mean square at the input and output
+      double sq = 0.0, su = 0.0;
+      if ((e = sg_sumsq(net, s, net->qbuf, net->nvox, &sq)) ||
+          (e = sg_sumsq(net, s, net->ubuf, net->nvox, &su)))
+        return hip_err(c, e, "scale reduction");
+      if (!(sq > 0.0 && su > 0.0)) return set_err(c, PMFEM_ECONV, "training pair with zero charges");
+      net->s_in = (float)(1.0 / std::sqrt(sq / (double)net->nvox));
+      net->s_out = (float)std::sqrt(su / (double)net->nvox);
+    }
+    if ((e = sg_loss_grad(net, s, net->qbuf, net->ubuf, 1.f / net->s_out, it)) ||
+        (e = sg_adam(net, s, lr)))
+      return hip_err(c, e, "surrogate training launch");
+  }
+  if (loss_log && n_pairs > 0 &&
+      (e = hipMemcpyAsync(loss_log, net->loss, (size_t)n_pairs * sizeof(double),
+                          hipMemcpyDeviceToHost, s)))
+    return hip_err(c, e, "loss copy");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_err(c, e, "surrogate training");
+  return PMFEM_OK;
+}
+
+int pmfem_surrogate_enable(pmfem_ctx* c, int32_t on) {
+  int rc = on ? net_ready(c, true) : ready(c);
+  if (rc) return rc;
+  c->dev->net_on = on != 0;
+  return PMFEM_OK;
+}
+
+int pmfem_llg_step_judged(pmfem_ctx* c, double* m_dev, double dt, double alpha, int32_t n_steps,
+                          const double* h_applied, int32_t check_every, double tol,
+                          double* report) {
+  int rc = net_ready(c, true);
+  if (rc) return rc;
+  if (!m_dev || n_steps < 0 || !(dt > 0.0) || !(alpha >= 0.0) || check_every < 1 || !(tol >= 0.0))
+    return set_err(c, PMFEM_EINVAL, "bad llg arguments");
+  pmfem_dev* d = c->dev;
+  Surrogate* net = d->net;
+  hipStream_t s = stream_of(c);
+  const bool was_on = d->net_on;
+  bool use = true;
+  double checks = 0.0, emax = 0.0, elast = -1.0, fallback = -1.0;
+  hipError_t e;
+  for (int32_t st = 0; st < n_steps; ++st) {
+    if (use && st % check_every == 0) {
+      // the plain AIM judges the surrogate on the magnetostatic field
+      if ((e = sg_to_f32(net, s, m_dev, net->m32))) return hip_err(c, e, "conversion launch");
+      d->net_on = false;
+      if ((rc = run_heff(c, net->m32, net->ha, PMFEM_TERM_MS, nullptr))) break;
+      d->net_on = true;
+      if ((rc = run_heff(c, net->m32, net->hs, PMFEM_TERM_MS, nullptr))) break;
+      double e2[2];
+      if ((e = sg_field_error(net, s, net->hs, net->ha, e2))) {
+        rc = hip_err(c, e, "field error");
+        break;
+      }
+      const double err = e2[1] > 0.0 ? std::sqrt(e2[0] / e2[1]) : std::sqrt(e2[0]);
+      checks += 1.0;
+      emax = std::max(emax, err);
+      elast = err;
+      if (!(err <= tol)) {
+        use = false;
+        fallback = st;
+      }
+    }
+    d->net_on = use;
+    if ((rc = enqueue_rk4(c, m_dev, dt, alpha, h_applied))) break;
+  }
+  d->net_on = was_on;
+  if (rc) return rc;
+  if (report) {
+    report[0] = checks;
+    report[1] = emax;
+    report[2] = elast;
+    report[3] = fallback;
+  }
+  return PMFEM_OK;
 }
 
 }  // extern "C"

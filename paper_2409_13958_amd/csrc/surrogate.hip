@@ -1,0 +1,750 @@
+// Kernels and host object of the learned surrogate of the AIM grid
+// convolution (layout and conventions in surrogate.h).
+#include "surrogate.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace pmfem {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kT = 256;
+constexpr int kRedBlocks = 1024;   // blocks of the device reductions (partials in dred)
+
+// FP32 -> BF16, round to nearest even (finite inputs)
+__device__ __forceinline__ uint32_t bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+__device__ __forceinline__ float bf16_float(uint32_t h) { return __uint_as_float(h << 16); }
+
+inline uint16_t bf16_bits_host(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ int wrapi(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+__device__ __forceinline__ int64_t vox_of(const SgGrid& g, int z, int y, int x) {
+  return ((int64_t)z * g.ny + y) * g.nx + x;
+}
+
+// ---------------------------------------------------------------------------
+// First-layer form (one input channel -> kSgC outputs), FP32 FMA. Also the
+// data gradient of the last layer (weights flipped). Tile: 8 rows of 32
+// points of one z-plane per 256-thread workgroup; the 3 input planes of the
+// tile with a one-point halo staged in LDS.
+__global__ __launch_bounds__(kT) void k_sg_in(SgGrid g, const float* __restrict__ x, float xs,
+                                               const float* __restrict__ w,
+                                               const float* __restrict__ b,
+                                               float* __restrict__ out, int relu,
+                                               const float* __restrict__ mask) {
+  __shared__ float sx[3 * kSgHalo];
+  __shared__ float sw[kSgC * 27];
+  const int tiles_x = (g.nx + kSgTX - 1) / kSgTX;
+  const int x0 = (int)(blockIdx.x % tiles_x) * kSgTX, y0 = (int)(blockIdx.x / tiles_x) * kSgTY;
+  const int z = blockIdx.y, t = threadIdx.x;
+  for (int i = t; i < kSgC * 27; i += kT) sw[i] = w[i];
+  for (int i = t; i < 3 * kSgHalo; i += kT) {
+    const int pl = i / kSgHalo, h = i - pl * kSgHalo;
+    const int hy = h / kSgHX, hx = h - hy * kSgHX, gz = z + pl - 1;
+    float v = 0.f;
+    if (gz >= 0 && gz < g.nz)
+      v = x[vox_of(g, gz, wrapi(y0 + hy - 1, g.ny), wrapi(x0 + hx - 1, g.nx))] * xs;
+    sx[i] = v;
+  }
+  __syncthreads();
+  const int ty = t / kSgTX, tx = t % kSgTX;
+  float acc[kSgC];
+#pragma unroll
+  for (int co = 0; co < kSgC; ++co) acc[co] = b ? b[co] : 0.f;
+  for (int dz = 0; dz < 3; ++dz)
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const float v = sx[dz * kSgHalo + (ty + dy) * kSgHX + tx + dx];
+        const int o = dz * 9 + dy * 3 + dx;
+#pragma unroll
+        for (int co = 0; co < kSgC; ++co) acc[co] = fmaf(sw[co * 27 + o], v, acc[co]);
+      }
+  const int gx = x0 + tx, gy = y0 + ty;
+  if (gx >= g.nx || gy >= g.ny) return;
+  const int64_t v = vox_of(g, z, gy, gx);
+  float4* o4 = reinterpret_cast<float4*>(out + v * kSgC);
+  const float4* m4 = mask ? reinterpret_cast<const float4*>(mask + v * kSgC) : nullptr;
+#pragma unroll
+  for (int q = 0; q < kSgC / 4; ++q) {
+    float4 r = make_float4(acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]);
+    if (m4) {
+      const float4 mk = m4[q];
+      r.x = mk.x > 0.f ? r.x : 0.f;
+      r.y = mk.y > 0.f ? r.y : 0.f;
+      r.z = mk.z > 0.f ? r.z : 0.f;
+      r.w = mk.w > 0.f ? r.w : 0.f;
+    }
+    if (relu) {
+      r.x = fmaxf(r.x, 0.f);
+      r.y = fmaxf(r.y, 0.f);
+      r.z = fmaxf(r.z, 0.f);
+      r.w = fmaxf(r.w, 0.f);
+    }
+    o4[q] = r;
+  }
+}
+
+// Last-layer form (kSgC inputs -> one output), FP32 FMA: y = (conv + b) ys.
+// The input planes are staged one at a time with a padded point stride (33
+// floats) so that the per-point channel loop is free of bank conflicts.
+__global__ __launch_bounds__(kT) void k_sg_out(SgGrid g, const float* __restrict__ a,
+                                                const float* __restrict__ w,
+                                                const float* __restrict__ b, float ys,
+                                                float* __restrict__ y) {
+  constexpr int S = kSgC + 1;
+  __shared__ float sa[kSgHalo * S];
+  __shared__ float sw[kSgC * 27];
+  const int tiles_x = (g.nx + kSgTX - 1) / kSgTX;
+  const int x0 = (int)(blockIdx.x % tiles_x) * kSgTX, y0 = (int)(blockIdx.x / tiles_x) * kSgTY;
+  const int z = blockIdx.y, t = threadIdx.x;
+  const int ty = t / kSgTX, tx = t % kSgTX;
+  for (int i = t; i < kSgC * 27; i += kT) sw[i] = w[i];
+  float acc = 0.f;
+  for (int dz = 0; dz < 3; ++dz) {
+    const int gz = z + dz - 1;
+    if (gz < 0 || gz >= g.nz) continue;  // the same for the whole workgroup
+    __syncthreads();
+    for (int i = t; i < kSgHalo * (kSgC / 4); i += kT) {
+      const int h = i / (kSgC / 4), q = i % (kSgC / 4);
+      const int hy = h / kSgHX, hx = h - hy * kSgHX;
+      const float4 v = reinterpret_cast<const float4*>(
+          a + vox_of(g, gz, wrapi(y0 + hy - 1, g.ny), wrapi(x0 + hx - 1, g.nx)) * kSgC)[q];
+      float* d = &sa[h * S + 4 * q];
+      d[0] = v.x;
+      d[1] = v.y;
+      d[2] = v.z;
+      d[3] = v.w;
+    }
+    __syncthreads();
+    for (int dy = 0; dy < 3; ++dy)
+      for (int dx = 0; dx < 3; ++dx) {
+        const float* s = &sa[((ty + dy) * kSgHX + tx + dx) * S];
+        const int o = dz * 9 + dy * 3 + dx;
+#pragma unroll 8
+        for (int ci = 0; ci < kSgC; ++ci) acc = fmaf(sw[ci * 27 + o], s[ci], acc);
+      }
+  }
+  const int gx = x0 + tx, gy = y0 + ty;
+  if (gx >= g.nx || gy >= g.ny) return;
+  y[vox_of(g, z, gy, gx)] = (acc + b[0]) * ys;
+}
+
+// Middle layer (kSgC -> kSgC) on the matrix cores, as an implicit GEMM: M =
+// grid points, N = output channels, K = 27 offsets x kSgC input channels,
+// with v_mfma_f32_16x16x32_bf16 (A: 16 points x 32 channels of one offset;
+// B: 32 input x 16 output channels). Four waves per workgroup, each owning
+// two rows of 32 points (four 16-point M tiles) times both 16-channel N
+// tiles. The input plane of each dz is staged in LDS as BF16 (and, with
+// SPLIT, the BF16 remainder x - bf16(x), which a second product adds), 16-byte
+// channel chunks XOR-swizzled by point so that 16 consecutive points of one
+// chunk fall in distinct banks. Also the data gradient (weights transposed
+// and flipped, no bias) with the ReLU mask of the layer below.
+template <bool SPLIT>
+__global__ __launch_bounds__(kT) void k_sg_mid(SgGrid g, const float* __restrict__ a,
+                                                const uint16_t* __restrict__ w,
+                                                const float* __restrict__ b,
+                                                float* __restrict__ out, int relu,
+                                                const float* __restrict__ mask) {
+  __shared__ uint4 shi[kSgHalo * 4];
+  __shared__ uint4 slo[SPLIT ? kSgHalo * 4 : 1];
+  const int tiles_x = (g.nx + kSgTX - 1) / kSgTX;
+  const int x0 = (int)(blockIdx.x % tiles_x) * kSgTX, y0 = (int)(blockIdx.x / tiles_x) * kSgTY;
+  const int z = blockIdx.y, t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6, li = lane & 15, kg = lane >> 4;
+  f32x4 acc[4][2];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+    for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int dz = 0; dz < 3; ++dz) {
+    const int gz = z + dz - 1;
+    if (gz < 0 || gz >= g.nz) continue;  // the same for the whole workgroup
+    bf16x8 bw[9][2];
+#pragma unroll
+    for (int j = 0; j < 9; ++j)
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+        bw[j][nt] = *reinterpret_cast<const bf16x8*>(
+            w + ((int64_t)(dz * 9 + j) * kSgC + nt * 16 + li) * kSgC + kg * 8);
+    __syncthreads();
+    for (int i = t; i < kSgHalo * (kSgC / 4); i += kT) {
+      const int h = i >> 3, q = i & 7;
+      const int hy = h / kSgHX, hx = h - hy * kSgHX;
+      const float4 v = reinterpret_cast<const float4*>(
+          a + vox_of(g, gz, wrapi(y0 + hy - 1, g.ny), wrapi(x0 + hx - 1, g.nx)) * kSgC)[q];
+      const int chunk = (q >> 1) ^ ((h >> 2) & 3);
+      const uint32_t h0 = bf16_bits(v.x), h1 = bf16_bits(v.y), h2 = bf16_bits(v.z),
+                     h3 = bf16_bits(v.w);
+      reinterpret_cast<uint2*>(&shi[h * 4 + chunk])[q & 1] = make_uint2(h0 | (h1 << 16), h2 | (h3 << 16));
+      if (SPLIT) {
+        const uint32_t l0 = bf16_bits(v.x - bf16_float(h0)), l1 = bf16_bits(v.y - bf16_float(h1)),
+                       l2 = bf16_bits(v.z - bf16_float(h2)), l3 = bf16_bits(v.w - bf16_float(h3));
+        reinterpret_cast<uint2*>(&slo[h * 4 + chunk])[q & 1] =
+            make_uint2(l0 | (l1 << 16), l2 | (l3 << 16));
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      const int dy = j / 3, dx = j % 3;
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        const int row = 2 * wv + (mt >> 1);
+        const int h = (row + dy) * kSgHX + (mt & 1) * 16 + li + dx;
+        const int chunk = kg ^ ((h >> 2) & 3);
+        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&shi[h * 4 + chunk]);
+        acc[mt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bw[j][0], acc[mt][0], 0, 0, 0);
+        acc[mt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bw[j][1], acc[mt][1], 0, 0, 0);
+        if (SPLIT) {
+          const bf16x8 al = *reinterpret_cast<const bf16x8*>(&slo[h * 4 + chunk]);
+          acc[mt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bw[j][0], acc[mt][0], 0, 0, 0);
+          acc[mt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bw[j][1], acc[mt][1], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // D tile of 16 points x 16 channels: lane holds points 4 kg + r, channel li
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    const int gy = y0 + 2 * wv + (mt >> 1);
+    if (gy >= g.ny) continue;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const int co = nt * 16 + li;
+      const float bias = b ? b[co] : 0.f;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gx = x0 + (mt & 1) * 16 + kg * 4 + r;
+        if (gx >= g.nx) continue;
+        const int64_t v = vox_of(g, z, gy, gx);
+        float val = acc[mt][nt][r] + bias;
+        if (mask && !(mask[v * kSgC + co] > 0.f)) val = 0.f;
+        if (relu) val = fmaxf(val, 0.f);
+        out[v * kSgC + co] = val;
+      }
+    }
+  }
+}
+
+// Weight gradient of a kSgC -> kSgC layer: gW[co][ci][o] = sum over points v
+// of gr[v][co] a[v + o][ci] (circular in x, y; zero outside in z). Grid
+// (P, 3): blockIdx.y is dz; each 192-thread workgroup walks the tiles
+// blockIdx.x, +P, ... and owns, per thread, 4 output x 4 input channels x the
+// three dx at one dy. Partial sums per workgroup go to part[P][C*C*27].
+__global__ __launch_bounds__(192) void k_sg_wgrad(SgGrid g, const float* __restrict__ gr,
+                                                   const float* __restrict__ a,
+                                                   float* __restrict__ part) {
+  __shared__ float4 sg[kSgTX * kSgTY * 8];
+  __shared__ float4 sa[kSgHalo * 8];
+  const int t = threadIdx.x, ciq = t & 7, coq = (t >> 3) & 7, dy = t >> 6, dz = blockIdx.y;
+  const int tiles_x = (g.nx + kSgTX - 1) / kSgTX, tiles_y = (g.ny + kSgTY - 1) / kSgTY;
+  const int tpp = tiles_x * tiles_y, ntiles = tpp * g.nz;
+  float acc[3][4][4];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) acc[d][i][j] = 0.f;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int z = tile / tpp, r = tile - z * tpp;
+    const int x0 = (r % tiles_x) * kSgTX, y0 = (r / tiles_x) * kSgTY, gz = z + dz - 1;
+    if (gz < 0 || gz >= g.nz) continue;  // the same for the whole workgroup
+    __syncthreads();
+    for (int i = t; i < kSgTX * kSgTY * 8; i += 192) {
+      const int v = i >> 3, q = i & 7, gx = x0 + (v & (kSgTX - 1)), gy = y0 + v / kSgTX;
+      float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (gx < g.nx && gy < g.ny) val = reinterpret_cast<const float4*>(gr + vox_of(g, z, gy, gx) * kSgC)[q];
+      sg[i] = val;
+    }
+    for (int i = t; i < kSgHalo * 8; i += 192) {
+      const int h = i >> 3, q = i & 7, hy = h / kSgHX, hx = h - hy * kSgHX;
+      sa[i] = reinterpret_cast<const float4*>(
+          a + vox_of(g, gz, wrapi(y0 + hy - 1, g.ny), wrapi(x0 + hx - 1, g.nx)) * kSgC)[q];
+    }
+    __syncthreads();
+    for (int v = 0; v < kSgTX * kSgTY; ++v) {
+      const int ty = v / kSgTX, tx = v % kSgTX;
+      const float4 gv = sg[v * 8 + coq];
+      const int hb = (ty + dy) * kSgHX + tx;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const float4 av = sa[(hb + d) * 8 + ciq];
+        const float gg[4] = {gv.x, gv.y, gv.z, gv.w}, aa[4] = {av.x, av.y, av.z, av.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[d][i][j] = fmaf(gg[i], aa[j], acc[d][i][j]);
+      }
+    }
+  }
+  float* P = part + (int64_t)blockIdx.x * (kSgC * kSgC * 27);
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j)
+        P[((coq * 4 + i) * kSgC + ciq * 4 + j) * 27 + dz * 9 + dy * 3 + d] = acc[d][i][j];
+}
+
+// Column sums of g[V][C] (C divides 256): partial per workgroup -> part[P][C].
+__global__ __launch_bounds__(kT) void k_sg_colsum(int64_t V, int C, const float* __restrict__ g,
+                                                   float* __restrict__ part) {
+  __shared__ float red[kT];
+  const int t = threadIdx.x, c = t % C, grp = t / C, ng = kT / C;
+  float acc = 0.f;
+  for (int64_t v = (int64_t)blockIdx.x * ng + grp; v < V; v += (int64_t)gridDim.x * ng)
+    acc += g[v * C + c];
+  red[t] = acc;
+  __syncthreads();
+  if (t < C) {
+    float s = 0.f;
+    for (int k = 0; k < ng; ++k) s += red[k * C + t];
+    part[(int64_t)blockIdx.x * C + t] = s;
+  }
+}
+
+// dst[i] = sum_p part[p * n + src(i)], src(i) = (i / run) * stride + i % run
+__global__ void k_sg_reduce(int P, int64_t n, const float* __restrict__ part, int64_t count,
+                            int run, int64_t stride, float* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int64_t src = (i / run) * stride + i % run;
+  double s = 0.0;
+  for (int p = 0; p < P; ++p) s += part[(int64_t)p * n + src];
+  dst[i] = (float)s;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = kT / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// Mean-squared loss against t tscale: gy = dL/dy = 2 (y - t tscale) / V
+// (also into channel 0 of gpad), per-workgroup sums of squares to part.
+__global__ __launch_bounds__(kT) void k_sg_loss(int64_t V, const float* __restrict__ y,
+                                                 const float* __restrict__ tg, float tscale,
+                                                 float* __restrict__ gy, float* __restrict__ gpad,
+                                                 double* __restrict__ part) {
+  __shared__ double red[kT];
+  double s = 0.0;
+  const float k = 2.f / (float)V;
+  for (int64_t v = (int64_t)blockIdx.x * kT + threadIdx.x; v < V; v += (int64_t)gridDim.x * kT) {
+    const float d = y[v] - tg[v] * tscale;
+    s += (double)d * d;
+    gy[v] = k * d;
+    gpad[v * kSgC] = k * d;
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kT) void k_sg_sumd(int P, const double* __restrict__ part,
+                                                 double scale, double* __restrict__ out) {
+  __shared__ double red[kT];
+  double s = 0.0;
+  for (int p = threadIdx.x; p < P; p += kT) s += part[p];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) *out = s * scale;
+}
+
+// per-workgroup sums of |a - b|^2 (b may be null: |a|^2) and |b|^2
+__global__ __launch_bounds__(kT) void k_sg_sq2(int64_t n, const float* __restrict__ a,
+                                                const float* __restrict__ b,
+                                                double* __restrict__ part) {
+  __shared__ double red[kT];
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    const double bv = b ? (double)b[i] : 0.0, d = (double)a[i] - bv;
+    s0 += d * d;
+    s1 += bv * bv;
+  }
+  s0 = block_sum(s0, red);
+  __syncthreads();
+  s1 = block_sum(s1, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s0;
+    part[2 * blockIdx.x + 1] = s1;
+  }
+}
+
+__global__ void k_sg_pad(int64_t V, const float* __restrict__ x, float xs, float* __restrict__ dst) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < V) dst[v * kSgC] = x[v] * xs;
+}
+
+__global__ void k_sg_adam(int64_t n, float* __restrict__ p, const float* __restrict__ g,
+                          float* __restrict__ m1, float* __restrict__ m2, float lr_t, float b1,
+                          float b2, float eps) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float a = b1 * m1[i] + (1.f - b1) * gi, v = b2 * m2[i] + (1.f - b2) * gi * gi;
+  m1[i] = a;
+  m2[i] = v;
+  p[i] -= lr_t * a / (sqrtf(v) + eps);
+}
+
+// middle-layer weights W[co][ci][27] -> forward [27][co][ci] and, for the
+// data gradient, [27][ci][co] with the offset reversed; both BF16
+__global__ void k_sg_pack_mid(const float* __restrict__ W, uint16_t* __restrict__ wf,
+                              uint16_t* __restrict__ wt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 27 * kSgC * kSgC) return;
+  const int o = i / (kSgC * kSgC), r = i % (kSgC * kSgC), u = r / kSgC, v = r % kSgC;
+  wf[i] = (uint16_t)bf16_bits(W[(u * kSgC + v) * 27 + o]);
+  wt[i] = (uint16_t)bf16_bits(W[(v * kSgC + u) * 27 + 26 - o]);
+}
+
+// first/last-layer weights [C][27] -> BF16 values (and reversed offsets)
+__global__ void k_sg_pack_io(const float* __restrict__ W, float* __restrict__ w,
+                             float* __restrict__ wflip) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kSgC * 27) return;
+  const int c = i / 27, o = i % 27;
+  w[i] = bf16_float(bf16_bits(W[i]));
+  if (wflip) wflip[i] = bf16_float(bf16_bits(W[c * 27 + 26 - o]));
+}
+
+// SplitMix64 finaliser (Steele, Lea and Flood, 2014) as a counter-based hash
+__device__ __host__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_sg_texture(int64_t n, const double* __restrict__ pos, SgTexture tx,
+                             double* __restrict__ m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double x = pos[3 * i], y = pos[3 * i + 1];
+  double mx, my, mz;
+  if (tx.kind == 0) {
+    const uint64_t h1 = mix64(((uint64_t)tx.seed << 32) ^ (uint64_t)(2 * i));
+    const uint64_t h2 = mix64(((uint64_t)tx.seed << 32) ^ (uint64_t)(2 * i + 1));
+    const double u1 = (double)(h1 >> 11) * 0x1p-53, u2 = (double)(h2 >> 11) * 0x1p-53;
+    mz = 2.0 * u1 - 1.0;
+    const double r = sqrt(fmax(0.0, 1.0 - mz * mz)), ph = 2.0 * 3.14159265358979323846 * u2;
+    mx = r * cos(ph);
+    my = r * sin(ph);
+  } else if (tx.kind == 1) {
+    double dx = x - tx.cx, dy = y - tx.cy;
+    dx -= tx.Lx * rint(dx / tx.Lx);
+    dy -= tx.Ly * rint(dy / tx.Ly);
+    const double r = sqrt(dx * dx + dy * dy);
+    mz = tx.pol * exp(-(r * r) / (tx.rc * tx.rc));
+    const double ip = sqrt(fmax(0.0, 1.0 - mz * mz));
+    if (r > 0.0) {
+      mx = -tx.chir * dy / r * ip;
+      my = tx.chir * dx / r * ip;
+    } else {
+      mx = my = 0.0;
+      mz = tx.pol;
+    }
+  } else {
+    const double L = tx.nx != 0.0 ? tx.Lx : tx.Ly;
+    const double u = x * tx.nx + y * tx.ny - tx.cx;
+    const double d1 = u - L * rint(u / L), d2 = (u - 0.5 * L) - L * rint((u - 0.5 * L) / L);
+    const double th = fabs(d1) < fabs(d2) ? 2.0 * atan(exp(d1 / tx.rc)) : 2.0 * atan(exp(-d2 / tx.rc));
+    const double c = cos(th), s = sin(th);
+    mx = c * tx.ed[0] + s * tx.er[0];
+    my = c * tx.ed[1] + s * tx.er[1];
+    mz = c * tx.ed[2] + s * tx.er[2];
+  }
+  const double nrm = 1.0 / sqrt(mx * mx + my * my + mz * mz);
+  m[3 * i] = mx * nrm;
+  m[3 * i + 1] = my * nrm;
+  m[3 * i + 2] = mz * nrm;
+}
+
+__global__ void k_sg_f32(int64_t n3, const double* __restrict__ a, float* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n3) b[i] = (float)a[i];
+}
+
+unsigned blocks(int64_t n, int t = kT) { return (unsigned)((n + t - 1) / t); }
+
+dim3 tile_grid(const SgGrid& g) {
+  return dim3((unsigned)(((g.nx + kSgTX - 1) / kSgTX) * ((g.ny + kSgTY - 1) / kSgTY)),
+              (unsigned)g.nz);
+}
+
+template <class T>
+hipError_t alloc(T** p, int64_t count) {
+  return hipMalloc((void**)p, (size_t)count * sizeof(T));
+}
+
+void launch_mid(const Surrogate* s, hipStream_t st, const float* a, const uint16_t* w,
+                const float* b, float* out, int relu, const float* mask) {
+  if (s->split)
+    hipLaunchKernelGGL(k_sg_mid<true>, tile_grid(s->gd), dim3(kT), 0, st, s->gd, a, w, b, out, relu,
+                       mask);
+  else
+    hipLaunchKernelGGL(k_sg_mid<false>, tile_grid(s->gd), dim3(kT), 0, st, s->gd, a, w, b, out,
+                       relu, mask);
+}
+
+float* act_of(const Surrogate* s, int l, bool train) {
+  return s->act + (int64_t)(train ? l : (l & 1)) * s->nvox * kSgC;
+}
+
+// forward pass; the output grid gets (net + b) * ys
+void forward(Surrogate* s, hipStream_t st, const float* Q, bool train, float* yout, float ys) {
+  const int D = s->depth;
+  const dim3 grid = tile_grid(s->gd);
+  hipLaunchKernelGGL(k_sg_in, grid, dim3(kT), 0, st, s->gd, Q, s->s_in, s->win, s->p + s->boff[0],
+                     act_of(s, 0, train), 1, (const float*)nullptr);
+  for (int l = 1; l <= D - 2; ++l)
+    launch_mid(s, st, act_of(s, l - 1, train), s->wmid + (int64_t)(l - 1) * 27 * kSgC * kSgC,
+               s->p + s->boff[l], act_of(s, l, train), 1, nullptr);
+  hipLaunchKernelGGL(k_sg_out, grid, dim3(kT), 0, st, s->gd, act_of(s, D - 2, train), s->wout,
+                     s->p + s->boff[D - 1], ys, yout);
+}
+
+// weight and bias gradients of a layer from its output gradient g [V][C]
+// (channel 0 only for the last layer) and its input a [V][C]
+void layer_grads(Surrogate* s, hipStream_t st, int l, const float* g, const float* a) {
+  const SgGrid& gd = s->gd;
+  const int ntiles = (int)tile_grid(gd).x * gd.nz;
+  const int P = std::min(kSgWPart, ntiles);
+  const int64_t nW = (int64_t)kSgC * kSgC * 27;
+  hipLaunchKernelGGL(k_sg_wgrad, dim3((unsigned)P, 3), dim3(192), 0, st, gd, g, a, s->part);
+  const int D = s->depth;
+  const int ci = l == 0 ? 1 : kSgC, co = l == D - 1 ? 1 : kSgC;
+  const int64_t count = (int64_t)ci * co * 27;
+  // first layer: entries (co * C + 0) * 27 + o; others contiguous
+  const int64_t stride = l == 0 ? (int64_t)kSgC * 27 : 27;
+  hipLaunchKernelGGL(k_sg_reduce, dim3(blocks(count)), dim3(kT), 0, st, P, nW, s->part, count, 27,
+                     stride, s->grad + s->woff[l]);
+  // bias: column sums of the output gradient
+  float* bpart = s->part;  // reused after the reduction above (same stream)
+  if (co == 1) {
+    hipLaunchKernelGGL(k_sg_colsum, dim3(kRedBlocks), dim3(kT), 0, st, s->nvox, 1, s->gy, bpart);
+  } else {
+    hipLaunchKernelGGL(k_sg_colsum, dim3(kRedBlocks), dim3(kT), 0, st, s->nvox, kSgC, g, bpart);
+  }
+  hipLaunchKernelGGL(k_sg_reduce, dim3(1), dim3(kT), 0, st, kRedBlocks, (int64_t)co, bpart,
+                     (int64_t)co, co, (int64_t)0, s->grad + s->boff[l]);
+}
+
+}  // namespace
+
+hipError_t sg_create(Surrogate* s, int depth, SgGrid gd, int64_t n, const double* pos_host,
+                     bool split) {
+  s->depth = depth;
+  s->split = split;
+  s->gd = gd;
+  s->nvox = (int64_t)gd.nx * gd.ny * gd.nz;
+  s->n = n;
+  s->woff.assign(depth, 0);
+  s->boff.assign(depth, 0);
+  int64_t cur = 0;
+  for (int l = 0; l < depth; ++l) {
+    const int ci = l == 0 ? 1 : kSgC, co = l == depth - 1 ? 1 : kSgC;
+    s->woff[l] = cur;
+    cur += (int64_t)co * ci * 27;
+    s->boff[l] = cur;
+    cur += co;
+  }
+  s->nparam = cur;
+  hipError_t e;
+  const int nmid = std::max(0, depth - 2);
+  if ((e = alloc(&s->p, cur)) || (e = alloc(&s->grad, cur)) || (e = alloc(&s->m1, cur)) ||
+      (e = alloc(&s->m2, cur)))
+    return e;
+  if ((e = hipMemset(s->m1, 0, cur * 4)) || (e = hipMemset(s->m2, 0, cur * 4))) return e;
+  if ((e = alloc(&s->wmid, std::max<int64_t>(1, (int64_t)nmid * 27 * kSgC * kSgC))) ||
+      (e = alloc(&s->wmidt, std::max<int64_t>(1, (int64_t)nmid * 27 * kSgC * kSgC))) ||
+      (e = alloc(&s->win, kSgC * 27)) || (e = alloc(&s->wout, kSgC * 27)) ||
+      (e = alloc(&s->woutt, kSgC * 27)))
+    return e;
+  if ((e = alloc(&s->act, 2 * s->nvox * kSgC))) return e;
+  if ((e = alloc(&s->dred, 2 * kRedBlocks + 8))) return e;
+  if ((e = alloc(&s->pos, 3 * n)) || (e = alloc(&s->m64, 3 * n)) || (e = alloc(&s->m32, 3 * n)) ||
+      (e = alloc(&s->ha, 3 * n)) || (e = alloc(&s->hs, 3 * n)))
+    return e;
+  return hipMemcpy(s->pos, pos_host, (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice);
+}
+
+hipError_t sg_ensure_training(Surrogate* s, int n_loss) {
+  hipError_t e;
+  if (!s->trained_buffers) {
+    (void)hipFree(s->act);
+    s->act = nullptr;
+    const int64_t nb = (int64_t)std::max(2, s->depth - 1) * s->nvox * kSgC;
+    const int64_t vc = s->nvox * kSgC;
+    if ((e = alloc(&s->act, nb)) || (e = alloc(&s->gA, vc)) || (e = alloc(&s->gB, vc)) ||
+        (e = alloc(&s->xpad, vc)) || (e = alloc(&s->gpad, vc)) || (e = alloc(&s->y, s->nvox)) ||
+        (e = alloc(&s->gy, s->nvox)) || (e = alloc(&s->qbuf, s->nvox)) ||
+        (e = alloc(&s->ubuf, s->nvox)) ||
+        (e = alloc(&s->part, std::max<int64_t>((int64_t)kSgWPart * kSgC * kSgC * 27,
+                                               (int64_t)kRedBlocks * kSgC))))
+      return e;
+    if ((e = hipMemset(s->xpad, 0, vc * 4)) || (e = hipMemset(s->gpad, 0, vc * 4))) return e;
+    s->trained_buffers = true;
+  }
+  if (n_loss > s->loss_cap) {
+    (void)hipFree(s->loss);
+    s->loss = nullptr;
+    s->loss_cap = 0;
+    if ((e = alloc(&s->loss, n_loss))) return e;
+    s->loss_cap = n_loss;
+  }
+  return hipSuccess;
+}
+
+void sg_destroy(Surrogate* s) {
+  void* bufs[] = {s->p,   s->grad, s->m1,   s->m2,   s->wmid, s->wmidt, s->win, s->wout,
+                  s->woutt, s->act, s->gA,  s->gB,   s->xpad, s->gpad, s->y,    s->gy,
+                  s->qbuf, s->ubuf, s->part, s->dred, s->loss, s->pos,  s->m64, s->m32,
+                  s->ha,  s->hs};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  *s = Surrogate{};
+}
+
+void sg_default_params(const Surrogate* s, uint64_t seed, std::vector<float>& out) {
+  // He-normal weights (variance 2 / fan-in; 1 / fan-in for the linear last
+  // layer), zero biases; normal deviates by Box-Muller from the hash above
+  out.assign((size_t)s->nparam, 0.f);
+  uint64_t ctr = 0;
+  auto uni = [&]() { return ((double)(mix64(seed * 0x100000001B3ull + ctr++) >> 11) + 0.5) * 0x1p-53; };
+  for (int l = 0; l < s->depth; ++l) {
+    const int ci = l == 0 ? 1 : kSgC, co = l == s->depth - 1 ? 1 : kSgC;
+    const double sd = std::sqrt((l == s->depth - 1 ? 1.0 : 2.0) / (27.0 * ci));
+    for (int64_t k = 0; k < (int64_t)co * ci * 27; ++k) {
+      const double u1 = uni(), u2 = uni();
+      const double gsn = std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * 3.14159265358979323846 * u2);
+      out[(size_t)(s->woff[l] + k)] = (float)(sd * gsn);
+    }
+  }
+}
+
+hipError_t sg_set_params(Surrogate* s, const float* host, hipStream_t st) {
+  hipError_t e = hipMemcpyAsync(s->p, host, (size_t)s->nparam * 4, hipMemcpyHostToDevice, st);
+  if (e) return e;
+  if ((e = hipMemsetAsync(s->m1, 0, (size_t)s->nparam * 4, st)) ||
+      (e = hipMemsetAsync(s->m2, 0, (size_t)s->nparam * 4, st)))
+    return e;
+  s->adam_t = 0;
+  return sg_pack(s, st);
+}
+
+hipError_t sg_pack(Surrogate* s, hipStream_t st) {
+  const int D = s->depth;
+  hipLaunchKernelGGL(k_sg_pack_io, dim3(blocks(kSgC * 27)), dim3(kT), 0, st, s->p + s->woff[0],
+                     s->win, (float*)nullptr);
+  hipLaunchKernelGGL(k_sg_pack_io, dim3(blocks(kSgC * 27)), dim3(kT), 0, st, s->p + s->woff[D - 1],
+                     s->wout, s->woutt);
+  for (int l = 1; l <= D - 2; ++l) {
+    const int64_t off = (int64_t)(l - 1) * 27 * kSgC * kSgC;
+    hipLaunchKernelGGL(k_sg_pack_mid, dim3(blocks(27 * kSgC * kSgC)), dim3(kT), 0, st,
+                       s->p + s->woff[l], s->wmid + off, s->wmidt + off);
+  }
+  return hipGetLastError();
+}
+
+hipError_t sg_get_params(const Surrogate* s, float* host, hipStream_t st) {
+  hipError_t e = hipMemcpyAsync(host, s->p, (size_t)s->nparam * 4, hipMemcpyDeviceToHost, st);
+  if (e) return e;
+  return hipStreamSynchronize(st);
+}
+
+hipError_t sg_apply(Surrogate* s, hipStream_t st, const float* Q, float* U) {
+  forward(s, st, Q, s->trained_buffers, U, s->s_out);
+  return hipGetLastError();
+}
+
+hipError_t sg_loss_grad(Surrogate* s, hipStream_t st, const float* Q, const float* tg, float tscale,
+                        int slot) {
+  const int D = s->depth;
+  const SgGrid& gd = s->gd;
+  const dim3 grid = tile_grid(gd);
+  forward(s, st, Q, true, s->y, 1.f);
+  hipLaunchKernelGGL(k_sg_pad, dim3(blocks(s->nvox)), dim3(kT), 0, st, s->nvox, Q, s->s_in, s->xpad);
+  hipLaunchKernelGGL(k_sg_loss, dim3(kRedBlocks), dim3(kT), 0, st, s->nvox, s->y, tg, tscale, s->gy,
+                     s->gpad, s->dred);
+  hipLaunchKernelGGL(k_sg_sumd, dim3(1), dim3(kT), 0, st, kRedBlocks, s->dred,
+                     1.0 / (double)s->nvox, s->loss + slot);
+  // last layer
+  layer_grads(s, st, D - 1, s->gpad, act_of(s, D - 2, true));
+  hipLaunchKernelGGL(k_sg_in, grid, dim3(kT), 0, st, gd, s->gy, 1.f, s->woutt, (const float*)nullptr,
+                     s->gB, 0, act_of(s, D - 2, true));
+  float *gcur = s->gB, *gnext = s->gA;
+  for (int l = D - 2; l >= 1; --l) {
+    layer_grads(s, st, l, gcur, act_of(s, l - 1, true));
+    launch_mid(s, st, gcur, s->wmidt + (int64_t)(l - 1) * 27 * kSgC * kSgC, nullptr, gnext, 0,
+               act_of(s, l - 1, true));
+    std::swap(gcur, gnext);
+  }
+  layer_grads(s, st, 0, gcur, s->xpad);
+  return hipGetLastError();
+}
+
+hipError_t sg_adam(Surrogate* s, hipStream_t st, double lr) {
+  const double b1 = 0.9, b2 = 0.999;
+  s->adam_t++;
+  const double lr_t = lr * std::sqrt(1.0 - std::pow(b2, (double)s->adam_t)) /
+                      (1.0 - std::pow(b1, (double)s->adam_t));
+  hipLaunchKernelGGL(k_sg_adam, dim3(blocks(s->nparam)), dim3(kT), 0, st, s->nparam, s->p, s->grad,
+                     s->m1, s->m2, (float)lr_t, (float)b1, (float)b2, 1e-8f);
+  return sg_pack(s, st);
+}
+
+hipError_t sg_texture(Surrogate* s, hipStream_t st, const SgTexture& tx, double* m_dev) {
+  hipLaunchKernelGGL(k_sg_texture, dim3(blocks(s->n)), dim3(kT), 0, st, s->n, s->pos, tx, m_dev);
+  return hipGetLastError();
+}
+
+hipError_t sg_to_f32(Surrogate* s, hipStream_t st, const double* m64, float* m32) {
+  hipLaunchKernelGGL(k_sg_f32, dim3(blocks(3 * s->n)), dim3(kT), 0, st, 3 * s->n, m64, m32);
+  return hipGetLastError();
+}
+
+hipError_t sg_field_error(Surrogate* s, hipStream_t st, const float* a, const float* b,
+                          double* out2) {
+  hipLaunchKernelGGL(k_sg_sq2, dim3(kRedBlocks), dim3(kT), 0, st, 3 * s->n, a, b, s->dred);
+  std::vector<double> h(2 * kRedBlocks);
+  hipError_t e = hipMemcpyAsync(h.data(), s->dred, h.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e || (e = hipStreamSynchronize(st))) return e;
+  out2[0] = out2[1] = 0.0;
+  for (int i = 0; i < kRedBlocks; ++i) {
+    out2[0] += h[2 * i];
+    out2[1] += h[2 * i + 1];
+  }
+  return hipSuccess;
+}
+
+hipError_t sg_sumsq(Surrogate* s, hipStream_t st, const float* x, int64_t count, double* out) {
+  hipLaunchKernelGGL(k_sg_sq2, dim3(kRedBlocks), dim3(kT), 0, st, count, x, (const float*)nullptr,
+                     s->dred);
+  std::vector<double> h(2 * kRedBlocks);
+  hipError_t e = hipMemcpyAsync(h.data(), s->dred, h.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e || (e = hipStreamSynchronize(st))) return e;
+  *out = 0.0;
+  for (int i = 0; i < kRedBlocks; ++i) *out += h[2 * i];
+  return hipSuccess;
+}
+
+}  // namespace pmfem
