@@ -443,6 +443,11 @@ int pmfem_surrogate_get_params(pmfem_ctx* ctx, float* params, int64_t count, dou
  * context's grid (they may be the same buffer); enqueued on the context's
  * stream. */
 int pmfem_surrogate_apply(pmfem_ctx* ctx, const float* q_grid_dev, float* u_grid_dev);
+/* reps applications (as pmfem_surrogate_apply) with HIP events on the
+ * context's stream around every layer: ms_per_layer[depth] (host) the mean
+ * milliseconds of each layer's kernel. Synchronous. */
+int pmfem_surrogate_profile(pmfem_ctx* ctx, const float* q_grid_dev, float* u_grid_dev,
+                            int32_t reps, double* ms_per_layer);
 /* One forward and backward pass: y = network(q s_in) (before s_out), loss =
  * mean over the grid points of (y - t)^2 with t_grid_dev in network units,
  * grad[count] (host, or NULL) its gradient with respect to the parameter

@@ -86,6 +86,7 @@ _SIGS = {
     "pmfem_surrogate_get_params": (ctypes.c_int, [_P, _P, _I64, _P]),
     "pmfem_surrogate_apply": (ctypes.c_int, [_P, _P, _P]),
     "pmfem_surrogate_loss_grad": (ctypes.c_int, [_P, _P, _P, _DP, _P, _I64]),
+    "pmfem_surrogate_profile": (ctypes.c_int, [_P, _P, _P, _I32, _P]),
     "pmfem_surrogate_texture": (ctypes.c_int, [_P, _I32, _U64, _P]),
     "pmfem_surrogate_train": (ctypes.c_int, [_P, _I32, _D, _U64, _U32, _P]),
     "pmfem_surrogate_enable": (ctypes.c_int, [_P, _I32]),
@@ -349,6 +350,7 @@ class Context:
     def surrogate_init(self, depth=6, seed=0, bf16_activations=False):
         self._check(self.lib.pmfem_surrogate_init(self.h, int(depth), int(seed),
                                                   int(bool(bf16_activations))), "surrogate_init")
+        self.surrogate_depth = int(depth)
 
     def surrogate_param_count(self):
         n = _I64(0)
@@ -376,6 +378,16 @@ class Context:
         self._check(self.lib.pmfem_surrogate_apply(
             self.h, _dev_ptr(qg, torch.float32, shape, "qg"),
             _dev_ptr(ug, torch.float32, shape, "ug")), "surrogate_apply")
+
+    def surrogate_profile(self, qg, ug, reps=10):
+        """Mean milliseconds of each layer over reps applications."""
+        import torch
+        shape = self._grid_shape()
+        ms = np.zeros(self.surrogate_depth, np.float64)
+        self._check(self.lib.pmfem_surrogate_profile(
+            self.h, _dev_ptr(qg, torch.float32, shape, "qg"),
+            _dev_ptr(ug, torch.float32, shape, "ug"), int(reps), _ptr(ms)), "surrogate_profile")
+        return ms
 
     def surrogate_loss_grad(self, qg, tg):
         """(loss, gradient vector) of one forward/backward pass."""

@@ -3079,6 +3079,17 @@ int pmfem_surrogate_apply(pmfem_ctx* c, const float* q_grid_dev, float* u_grid_d
   return PMFEM_OK;
 }
 
+int pmfem_surrogate_profile(pmfem_ctx* c, const float* q_grid_dev, float* u_grid_dev, int32_t reps,
+                            double* ms_per_layer) {
+  int rc = net_ready(c, true);
+  if (rc) return rc;
+  if (!q_grid_dev || !u_grid_dev || !ms_per_layer || reps < 1)
+    return set_err(c, PMFEM_EINVAL, "bad profile arguments");
+  hipError_t e = sg_profile(c->dev->net, stream_of(c), q_grid_dev, u_grid_dev, reps, ms_per_layer);
+  if (e != hipSuccess) return hip_err(c, e, "surrogate profile");
+  return PMFEM_OK;
+}
+
 int pmfem_surrogate_loss_grad(pmfem_ctx* c, const float* q_grid_dev, const float* t_grid_dev,
                               double* loss, float* grad, int64_t count) {
   int rc = net_ready(c, true);

@@ -85,6 +85,9 @@ void sg_default_params(const Surrogate* s, uint64_t seed, std::vector<float>& ou
 // U = surrogate(Q) on the grid (inference). Q and U may be one buffer: the
 // first layer has read Q before the last layer writes U.
 hipError_t sg_apply(Surrogate* s, hipStream_t st, const float* Q, float* U);
+// reps forward passes with events around every layer; ms[depth] = mean
+// milliseconds of each layer (synchronises)
+hipError_t sg_profile(Surrogate* s, hipStream_t st, const float* Q, float* U, int reps, double* ms);
 // One forward and backward pass for the pair (Q, t): the network's input is
 // Q s_in; the loss is the mean over the grid of (y - t tscale)^2; the
 // gradient goes to s->grad, the loss to s->loss[slot].

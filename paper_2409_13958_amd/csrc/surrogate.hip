@@ -50,11 +50,11 @@ __global__ __launch_bounds__(kT) void k_sg_in(SgGrid g, const float* __restrict_
                                                float* __restrict__ out, int relu,
                                                const float* __restrict__ mask) {
   __shared__ float sx[3 * kSgHalo];
-  __shared__ float sw[kSgC * 27];
+  __shared__ __align__(16) float sw[kSgC * 27];
   const int tiles_x = (g.nx + kSgTX - 1) / kSgTX;
   const int x0 = (int)(blockIdx.x % tiles_x) * kSgTX, y0 = (int)(blockIdx.x / tiles_x) * kSgTY;
   const int z = blockIdx.y, t = threadIdx.x;
-  for (int i = t; i < kSgC * 27; i += kT) sw[i] = w[i];
+  for (int i = t; i < kSgC * 27; i += kT) sw[(i % 27) * kSgC + i / 27] = w[i];  // [o][co]
   for (int i = t; i < 3 * kSgHalo; i += kT) {
     const int pl = i / kSgHalo, h = i - pl * kSgHalo;
     const int hy = h / kSgHX, hx = h - hy * kSgHX, gz = z + pl - 1;
@@ -73,9 +73,15 @@ __global__ __launch_bounds__(kT) void k_sg_in(SgGrid g, const float* __restrict_
 #pragma unroll
       for (int dx = 0; dx < 3; ++dx) {
         const float v = sx[dz * kSgHalo + (ty + dy) * kSgHX + tx + dx];
-        const int o = dz * 9 + dy * 3 + dx;
+        const float4* w4 = reinterpret_cast<const float4*>(&sw[(dz * 9 + dy * 3 + dx) * kSgC]);
 #pragma unroll
-        for (int co = 0; co < kSgC; ++co) acc[co] = fmaf(sw[co * 27 + o], v, acc[co]);
+        for (int q = 0; q < kSgC / 4; ++q) {
+          const float4 ww = w4[q];
+          acc[4 * q] = fmaf(ww.x, v, acc[4 * q]);
+          acc[4 * q + 1] = fmaf(ww.y, v, acc[4 * q + 1]);
+          acc[4 * q + 2] = fmaf(ww.z, v, acc[4 * q + 2]);
+          acc[4 * q + 3] = fmaf(ww.w, v, acc[4 * q + 3]);
+        }
       }
   const int gx = x0 + tx, gy = y0 + ty;
   if (gx >= g.nx || gy >= g.ny) return;
@@ -103,20 +109,21 @@ __global__ __launch_bounds__(kT) void k_sg_in(SgGrid g, const float* __restrict_
 }
 
 // Last-layer form (kSgC inputs -> one output), FP32 FMA: y = (conv + b) ys.
-// The input planes are staged one at a time with a padded point stride (33
-// floats) so that the per-point channel loop is free of bank conflicts.
+// The input planes are staged one at a time with a padded point stride (36
+// floats: 16-byte aligned, and 16 consecutive points of a 16-byte read fall
+// in distinct banks); weights as [offset][channel], both read as float4.
 __global__ __launch_bounds__(kT) void k_sg_out(SgGrid g, const float* __restrict__ a,
                                                 const float* __restrict__ w,
                                                 const float* __restrict__ b, float ys,
                                                 float* __restrict__ y) {
-  constexpr int S = kSgC + 1;
-  __shared__ float sa[kSgHalo * S];
-  __shared__ float sw[kSgC * 27];
+  constexpr int S = kSgC + 4;
+  __shared__ __align__(16) float sa[kSgHalo * S];
+  __shared__ __align__(16) float sw[kSgC * 27];
   const int tiles_x = (g.nx + kSgTX - 1) / kSgTX;
   const int x0 = (int)(blockIdx.x % tiles_x) * kSgTX, y0 = (int)(blockIdx.x / tiles_x) * kSgTY;
   const int z = blockIdx.y, t = threadIdx.x;
   const int ty = t / kSgTX, tx = t % kSgTX;
-  for (int i = t; i < kSgC * 27; i += kT) sw[i] = w[i];
+  for (int i = t; i < kSgC * 27; i += kT) sw[(i % 27) * kSgC + i / 27] = w[i];  // [o][ci]
   float acc = 0.f;
   for (int dz = 0; dz < 3; ++dz) {
     const int gz = z + dz - 1;
@@ -127,19 +134,21 @@ __global__ __launch_bounds__(kT) void k_sg_out(SgGrid g, const float* __restrict
       const int hy = h / kSgHX, hx = h - hy * kSgHX;
       const float4 v = reinterpret_cast<const float4*>(
           a + vox_of(g, gz, wrapi(y0 + hy - 1, g.ny), wrapi(x0 + hx - 1, g.nx)) * kSgC)[q];
-      float* d = &sa[h * S + 4 * q];
-      d[0] = v.x;
-      d[1] = v.y;
-      d[2] = v.z;
-      d[3] = v.w;
+      reinterpret_cast<float4*>(&sa[h * S])[q] = v;
     }
     __syncthreads();
     for (int dy = 0; dy < 3; ++dy)
       for (int dx = 0; dx < 3; ++dx) {
-        const float* s = &sa[((ty + dy) * kSgHX + tx + dx) * S];
-        const int o = dz * 9 + dy * 3 + dx;
-#pragma unroll 8
-        for (int ci = 0; ci < kSgC; ++ci) acc = fmaf(sw[ci * 27 + o], s[ci], acc);
+        const float4* s4 = reinterpret_cast<const float4*>(&sa[((ty + dy) * kSgHX + tx + dx) * S]);
+        const float4* w4 = reinterpret_cast<const float4*>(&sw[(dz * 9 + dy * 3 + dx) * kSgC]);
+#pragma unroll
+        for (int q = 0; q < kSgC / 4; ++q) {
+          const float4 av = s4[q], ww = w4[q];
+          acc = fmaf(ww.x, av.x, acc);
+          acc = fmaf(ww.y, av.y, acc);
+          acc = fmaf(ww.z, av.z, acc);
+          acc = fmaf(ww.w, av.w, acc);
+        }
       }
   }
   const int gx = x0 + tx, gy = y0 + ty;
@@ -152,71 +161,97 @@ __global__ __launch_bounds__(kT) void k_sg_out(SgGrid g, const float* __restrict
 // with v_mfma_f32_16x16x32_bf16 (A: 16 points x 32 channels of one offset;
 // B: 32 input x 16 output channels). Four waves per workgroup, each owning
 // two rows of 32 points (four 16-point M tiles) times both 16-channel N
-// tiles. The input plane of each dz is staged in LDS as BF16 (and, with
-// SPLIT, the BF16 remainder x - bf16(x), which a second product adds), 16-byte
-// channel chunks XOR-swizzled by point so that 16 consecutive points of one
-// chunk fall in distinct banks. Also the data gradient (weights transposed
-// and flipped, no bias) with the ReLU mask of the layer below.
+// tiles: eight independent accumulators, so that consecutive products never
+// wait on each other. The input plane of each dz is staged in LDS as BF16
+// (and, with SPLIT, the BF16 remainder x - bf16(x), which a second product
+// adds), 16-byte channel chunks XOR-swizzled by point so that 16 consecutive
+// points of one chunk fall in distinct banks; the next plane's loads are in
+// flight (in registers) while the current plane is multiplied. Also the data
+// gradient (weights transposed and flipped, no bias) with the ReLU mask of
+// the layer below.
 template <bool SPLIT>
-__global__ __launch_bounds__(kT) void k_sg_mid(SgGrid g, const float* __restrict__ a,
+__global__ __launch_bounds__(kT, 2) void k_sg_mid(SgGrid g, const float* __restrict__ a,
                                                 const uint16_t* __restrict__ w,
                                                 const float* __restrict__ b,
                                                 float* __restrict__ out, int relu,
                                                 const float* __restrict__ mask) {
+  constexpr int kLoads = (kSgHalo * (kSgC / 4) + kT - 1) / kT;  // float4 per thread per plane
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
   __shared__ uint4 shi[kSgHalo * 4];
   __shared__ uint4 slo[SPLIT ? kSgHalo * 4 : 1];
   const int tiles_x = (g.nx + kSgTX - 1) / kSgTX;
   const int x0 = (int)(blockIdx.x % tiles_x) * kSgTX, y0 = (int)(blockIdx.x / tiles_x) * kSgTY;
   const int z = blockIdx.y, t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6, li = lane & 15, kg = lane >> 4;
+  // planes z + dz - 1 inside the grid: dz in [dz_lo, dz_hi]
+  const int dz_lo = z == 0 ? 1 : 0, dz_hi = z == g.nz - 1 ? 1 : 2;
+  float4 pre[kLoads];
+  auto load_plane = [&](int gz) {
+#pragma unroll
+    for (int k = 0; k < kLoads; ++k) {
+      const int i = t + k * kT;
+      if (i < kSgHalo * (kSgC / 4)) {
+        const int h = i >> 3, q = i & 7, hy = h / kSgHX, hx = h - hy * kSgHX;
+        pre[k] = reinterpret_cast<const float4*>(
+            a + vox_of(g, gz, wrapi(y0 + hy - 1, g.ny), wrapi(x0 + hx - 1, g.nx)) * kSgC)[q];
+      }
+    }
+  };
+  auto store_plane = [&]() {
+#pragma unroll
+    for (int k = 0; k < kLoads; ++k) {
+      const int i = t + k * kT;
+      if (i < kSgHalo * (kSgC / 4)) {
+        const int h = i >> 3, q = i & 7, chunk = (q >> 1) ^ ((h >> 2) & 3);
+        const float4 v = pre[k];
+        const bf16x4 hv = {(__bf16)v.x, (__bf16)v.y, (__bf16)v.z, (__bf16)v.w};
+        reinterpret_cast<bf16x4*>(&shi[h * 4 + chunk])[q & 1] = hv;
+        if (SPLIT) {
+          const bf16x4 lv = {(__bf16)(v.x - (float)hv[0]), (__bf16)(v.y - (float)hv[1]),
+                             (__bf16)(v.z - (float)hv[2]), (__bf16)(v.w - (float)hv[3])};
+          reinterpret_cast<bf16x4*>(&slo[h * 4 + chunk])[q & 1] = lv;
+        }
+      }
+    }
+  };
   f32x4 acc[4][2];
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt)
     for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int dz = 0; dz < 3; ++dz) {
-    const int gz = z + dz - 1;
-    if (gz < 0 || gz >= g.nz) continue;  // the same for the whole workgroup
-    bf16x8 bw[9][2];
-#pragma unroll
-    for (int j = 0; j < 9; ++j)
-#pragma unroll
-      for (int nt = 0; nt < 2; ++nt)
-        bw[j][nt] = *reinterpret_cast<const bf16x8*>(
-            w + ((int64_t)(dz * 9 + j) * kSgC + nt * 16 + li) * kSgC + kg * 8);
+  load_plane(z + dz_lo - 1);
+  for (int dz = dz_lo; dz <= dz_hi; ++dz) {
+    const bf16x8* wz = reinterpret_cast<const bf16x8*>(w + ((int64_t)dz * 9 * kSgC + li) * kSgC + kg * 8);
+    __syncthreads();  // the previous plane has been multiplied
+    store_plane();
     __syncthreads();
-    for (int i = t; i < kSgHalo * (kSgC / 4); i += kT) {
-      const int h = i >> 3, q = i & 7;
-      const int hy = h / kSgHX, hx = h - hy * kSgHX;
-      const float4 v = reinterpret_cast<const float4*>(
-          a + vox_of(g, gz, wrapi(y0 + hy - 1, g.ny), wrapi(x0 + hx - 1, g.nx)) * kSgC)[q];
-      const int chunk = (q >> 1) ^ ((h >> 2) & 3);
-      const uint32_t h0 = bf16_bits(v.x), h1 = bf16_bits(v.y), h2 = bf16_bits(v.z),
-                     h3 = bf16_bits(v.w);
-      reinterpret_cast<uint2*>(&shi[h * 4 + chunk])[q & 1] = make_uint2(h0 | (h1 << 16), h2 | (h3 << 16));
-      if (SPLIT) {
-        const uint32_t l0 = bf16_bits(v.x - bf16_float(h0)), l1 = bf16_bits(v.y - bf16_float(h1)),
-                       l2 = bf16_bits(v.z - bf16_float(h2)), l3 = bf16_bits(v.w - bf16_float(h3));
-        reinterpret_cast<uint2*>(&slo[h * 4 + chunk])[q & 1] =
-            make_uint2(l0 | (l1 << 16), l2 | (l3 << 16));
-      }
-    }
-    __syncthreads();
-#pragma unroll
+    if (dz < dz_hi) load_plane(z + dz);  // the next plane, in flight meanwhile
+#pragma unroll 3
     for (int j = 0; j < 9; ++j) {
       const int dy = j / 3, dx = j % 3;
+      // B fragments of offset j: output channels li and 16 + li, inputs 8 kg ..
+      bf16x8 bw[2];
+      bw[0] = wz[(j * kSgC) * (kSgC / 8)];
+      bw[1] = wz[(j * kSgC + 16) * (kSgC / 8)];
+      bf16x8 ah[4], al[4];
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt) {
-        const int row = 2 * wv + (mt >> 1);
-        const int h = (row + dy) * kSgHX + (mt & 1) * 16 + li + dx;
+        const int h = (2 * wv + (mt >> 1) + dy) * kSgHX + (mt & 1) * 16 + li + dx;
         const int chunk = kg ^ ((h >> 2) & 3);
-        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&shi[h * 4 + chunk]);
-        acc[mt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bw[j][0], acc[mt][0], 0, 0, 0);
-        acc[mt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bw[j][1], acc[mt][1], 0, 0, 0);
-        if (SPLIT) {
-          const bf16x8 al = *reinterpret_cast<const bf16x8*>(&slo[h * 4 + chunk]);
-          acc[mt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bw[j][0], acc[mt][0], 0, 0, 0);
-          acc[mt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bw[j][1], acc[mt][1], 0, 0, 0);
-        }
+        ah[mt] = *reinterpret_cast<const bf16x8*>(&shi[h * 4 + chunk]);
+        if (SPLIT) al[mt] = *reinterpret_cast<const bf16x8*>(&slo[h * 4 + chunk]);
+      }
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bw[nt], acc[mt][nt], 0, 0, 0);
+      if (SPLIT) {
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+          for (int nt = 0; nt < 2; ++nt)
+            acc[mt][nt] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mt], bw[nt], acc[mt][nt], 0, 0, 0);
       }
     }
   }
@@ -509,17 +544,26 @@ float* act_of(const Surrogate* s, int l, bool train) {
   return s->act + (int64_t)(train ? l : (l & 1)) * s->nvox * kSgC;
 }
 
-// forward pass; the output grid gets (net + b) * ys
-void forward(Surrogate* s, hipStream_t st, const float* Q, bool train, float* yout, float ys) {
+// forward pass; the output grid gets (net + b) * ys. ev (or null): events
+// recorded before and after every layer, [2 * depth].
+void forward(Surrogate* s, hipStream_t st, const float* Q, bool train, float* yout, float ys,
+             hipEvent_t* ev = nullptr) {
   const int D = s->depth;
   const dim3 grid = tile_grid(s->gd);
+  if (ev) (void)hipEventRecord(ev[0], st);
   hipLaunchKernelGGL(k_sg_in, grid, dim3(kT), 0, st, s->gd, Q, s->s_in, s->win, s->p + s->boff[0],
                      act_of(s, 0, train), 1, (const float*)nullptr);
-  for (int l = 1; l <= D - 2; ++l)
+  if (ev) (void)hipEventRecord(ev[1], st);
+  for (int l = 1; l <= D - 2; ++l) {
+    if (ev) (void)hipEventRecord(ev[2 * l], st);
     launch_mid(s, st, act_of(s, l - 1, train), s->wmid + (int64_t)(l - 1) * 27 * kSgC * kSgC,
                s->p + s->boff[l], act_of(s, l, train), 1, nullptr);
+    if (ev) (void)hipEventRecord(ev[2 * l + 1], st);
+  }
+  if (ev) (void)hipEventRecord(ev[2 * (D - 1)], st);
   hipLaunchKernelGGL(k_sg_out, grid, dim3(kT), 0, st, s->gd, act_of(s, D - 2, train), s->wout,
                      s->p + s->boff[D - 1], ys, yout);
+  if (ev) (void)hipEventRecord(ev[2 * D - 1], st);
 }
 
 // weight and bias gradients of a layer from its output gradient g [V][C]
@@ -674,6 +718,27 @@ hipError_t sg_get_params(const Surrogate* s, float* host, hipStream_t st) {
 hipError_t sg_apply(Surrogate* s, hipStream_t st, const float* Q, float* U) {
   forward(s, st, Q, s->trained_buffers, U, s->s_out);
   return hipGetLastError();
+}
+
+hipError_t sg_profile(Surrogate* s, hipStream_t st, const float* Q, float* U, int reps, double* ms) {
+  const int D = s->depth;
+  std::vector<hipEvent_t> ev(2 * D, nullptr);
+  hipError_t e = hipSuccess;
+  for (auto& x : ev)
+    if ((e = hipEventCreate(&x))) break;
+  for (int l = 0; l < D; ++l) ms[l] = 0.0;
+  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    forward(s, st, Q, s->trained_buffers, U, s->s_out, ev.data());
+    if ((e = hipGetLastError()) || (e = hipStreamSynchronize(st))) break;
+    for (int l = 0; l < D; ++l) {
+      float t = 0.f;
+      if ((e = hipEventElapsedTime(&t, ev[2 * l], ev[2 * l + 1]))) break;
+      ms[l] += (double)t / reps;
+    }
+  }
+  for (auto& x : ev)
+    if (x) (void)hipEventDestroy(x);
+  return e;
 }
 
 hipError_t sg_loss_grad(Surrogate* s, hipStream_t st, const float* Q, const float* tg, float tscale,

@@ -400,8 +400,20 @@ def films_c4(n_films=256, seed=SEED0 + 3, nodes=(5e3, 8e4), period=(20.0 * NM, 2
     return out
 
 
+def film_c5(seed=SEED0 + 4, n_xy=512, n_z=8, grid=None):
+    """The surrogate workload: a 2D-periodic film of 512 x 512 x 8 nm on a
+    1 nm structured lattice (n_xy x n_xy x n_z cells of 6 tets, 513 x 513 x 9
+    node layers, 2.36 M unknowns after the periodic identification), Ms = 8e5
+    A/m, A = 1.3e-11 J/m, AIM grid 512 x 512 x 8. ``n_xy`` and ``n_z`` give
+    smaller films of the same spacing (grid n_xy x n_xy x n_z by default)."""
+    g = grid if grid is not None else (n_xy, n_xy, n_z)
+    return kuhn_box((n_xy, n_xy, n_z), 1.0 * NM, periodic=0b011, jitter=0.0, seed=seed,
+                    Ms=8e5, Aex=1.3e-11, grid=g, name="film_c5")
+
+
 CONFIGS = {
     "film_c1": film_c1,
     "wire_c2": wire_c2,
     "composite_c3": composite_c3,
+    "film_c5": film_c5,
 }
