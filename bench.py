@@ -444,7 +444,13 @@ def run_surrogate(args):
     depth = 6
     ctx.surrogate_init(depth, seed=1, bf16_activations=args.sg_bf16)
     t = time.perf_counter()
-    losses = ctx.surrogate_train(args.sg_pairs, lr=args.sg_lr, seed=2)
+    chunks = []
+    for c0 in range(0, args.sg_pairs, 1000):
+        chunks.append(ctx.surrogate_train(min(1000, args.sg_pairs - c0), lr=args.sg_lr,
+                                          seed=2 + c0))
+        log(f"training: {c0 + chunks[-1].size} pairs, loss of the last {chunks[-1].size}: "
+            f"{chunks[-1].mean():.3e} ({time.perf_counter() - t:.1f} s)")
+    losses = np.concatenate(chunks) if chunks else np.zeros(1)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t
     k = max(1, min(50, args.sg_pairs // 10))
