@@ -201,7 +201,9 @@ int pmfem_llg_step(pmfem_ctx* ctx, double* m_dev, double dt, double alpha, int32
 
 /*
  * pmfem_llg_step through a HIP graph: the first call (and any call whose
- * m_dev, dt, alpha or h_applied differ from the previous one's) captures the
+ * m_dev, dt, alpha or h_applied differ from the previous one's, or that
+ * finds the surrogate switched on or off, or with the surrogate on,
+ * re-created, given parameters or trained since) captures the
  * kernels of one RK4 step, with their fork to the library's second stream
  * and back, into a graph on a stream of the library's own; each call then
  * launches that graph n_steps times on the context's stream. The results are

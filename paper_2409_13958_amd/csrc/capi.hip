@@ -112,12 +112,15 @@ struct pmfem_dev {
     double* m = nullptr;
     double dt = 0.0, alpha = 0.0, happ[3] = {0.0, 0.0, 0.0};
     bool with_happ = false;
+    bool net_on = false;       // captured with the surrogate in place of the FFT
+    uint64_t net_version = 0;  // of that surrogate
   } sg;
   // learned surrogate of the grid convolution; net_on makes run_heff use it
   // in place of the FFT convolution. tap_q / tap_u, when set, receive copies
   // of the grid charges and potential of the next evaluation.
   Surrogate* net = nullptr;
   bool net_on = false;
+  uint64_t net_version = 0;  // bumped whenever its buffers or scales may change
   float *tap_q = nullptr, *tap_u = nullptr;
   std::vector<void*> allocs;
   // profiling
@@ -2513,7 +2516,8 @@ int pmfem_llg_step_graph(pmfem_ctx* c, double* m_dev, double dt, double alpha, i
   pmfem_dev* d = c->dev;
   pmfem_dev::StepGraph& G = d->sg;
   const bool wh = h_applied != nullptr;
-  bool same = G.x && G.m == m_dev && G.dt == dt && G.alpha == alpha && G.with_happ == wh;
+  bool same = G.x && G.m == m_dev && G.dt == dt && G.alpha == alpha && G.with_happ == wh &&
+              G.net_on == d->net_on && (!d->net_on || G.net_version == d->net_version);
   for (int k = 0; same && wh && k < 3; ++k) same = G.happ[k] == h_applied[k];
   hipError_t e = hipSuccess;
   if (!same) {
@@ -2555,6 +2559,8 @@ int pmfem_llg_step_graph(pmfem_ctx* c, double* m_dev, double dt, double alpha, i
     G.dt = dt;
     G.alpha = alpha;
     G.with_happ = wh;
+    G.net_on = d->net_on;
+    G.net_version = d->net_version;
     for (int k = 0; k < 3; ++k) G.happ[k] = wh ? h_applied[k] : 0.0;
   }
   for (int32_t i = 0; i < n_steps && e == hipSuccess; ++i) e = hipGraphLaunch(G.x, stream_of(c));
@@ -3018,6 +3024,7 @@ int pmfem_surrogate_init(pmfem_ctx* c, int32_t depth, uint64_t seed, int32_t bf1
                                     : hip_err(c, e, "surrogate allocation");
   }
   d->net = net;
+  d->net_version++;
   std::vector<float> p;
   sg_default_params(net, seed, p);
   if ((e = sg_set_params(net, p.data(), stream_of(c))) != hipSuccess)
@@ -3050,6 +3057,7 @@ int pmfem_surrogate_set_params(pmfem_ctx* c, const float* params, int64_t count,
     net->s_in = (float)scales[0];
     net->s_out = (float)scales[1];
   }
+  c->dev->net_version++;
   return PMFEM_OK;
 }
 
@@ -3099,6 +3107,7 @@ int pmfem_surrogate_loss_grad(pmfem_ctx* c, const float* q_grid_dev, const float
   if (grad && count != net->nparam)
     return set_err(c, PMFEM_EINVAL, "gradient vector must hold " + std::to_string(net->nparam) + " values");
   hipStream_t s = stream_of(c);
+  c->dev->net_version++;  // the activation buffers may be reallocated
   hipError_t e = sg_ensure_training(net, 1);
   if (e != hipSuccess) return set_err(c, PMFEM_ENOMEM, "surrogate training buffers");
   if ((e = sg_loss_grad(net, s, q_grid_dev, t_grid_dev, 1.f, 0)) != hipSuccess)
@@ -3129,6 +3138,7 @@ int pmfem_surrogate_train(pmfem_ctx* c, int32_t n_pairs, double lr, uint64_t see
   pmfem_dev* d = c->dev;
   Surrogate* net = d->net;
   hipStream_t s = stream_of(c);
+  d->net_version++;  // the scales may be set below
   hipError_t e = sg_ensure_training(net, std::max(1, n_pairs));
   if (e != hipSuccess) return set_err(c, PMFEM_ENOMEM, "surrogate training buffers");
   int list[3], nk = 0;

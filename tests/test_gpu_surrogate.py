@@ -235,6 +235,37 @@ def test_judged_llg_and_fallback(ctx):
     assert np.abs(torch.linalg.norm(m_c, dim=1).cpu().numpy() - 1.0).max() < 1e-12
 
 
+def test_step_graph_follows_the_surrogate(ctx):
+    """The captured RK4 step is captured again when the surrogate is switched
+    on or off, re-created or retrained, and replays what pmfem_llg_step does
+    in each state, bit for bit."""
+    n = ctx.n
+    m0 = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    ctx.surrogate_init(3, seed=8)
+    ctx.surrogate_train(2, lr=1e-3, seed=3)
+    ctx.surrogate_texture(m0, 2, seed=9)
+    dt, alpha = 1e-13, 0.5
+
+    def both(on):
+        ctx.surrogate_enable(on)
+        a, b = m0.clone(), m0.clone()
+        ctx.llg_step_graph(a, dt, alpha, 3)
+        ctx.llg_step(b, dt, alpha, 3)
+        ctx.surrogate_enable(False)
+        assert torch.equal(a, b)
+        return a
+
+    plain = both(False)
+    sur = both(True)
+    assert not torch.equal(plain, sur)
+    assert torch.equal(both(False), plain)
+    # a new network (new buffers and weights) behind the same switch
+    ctx.surrogate_init(3, seed=10)
+    ctx.surrogate_train(2, lr=1e-3, seed=4)
+    sur2 = both(True)
+    assert not torch.equal(sur2, sur)
+
+
 def test_surrogate_rejects_bad_use():
     prob = mg.film_c1()
     c = B.Context.from_problem(prob, device=0)
