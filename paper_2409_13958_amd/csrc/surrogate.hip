@@ -159,32 +159,34 @@ __global__ __launch_bounds__(kT) void k_sg_out(SgGrid g, const float* __restrict
 // Middle layer (kSgC -> kSgC) on the matrix cores, as an implicit GEMM: M =
 // grid points, N = output channels, K = 27 offsets x kSgC input channels,
 // with v_mfma_f32_16x16x32_bf16 (A: 16 points x 32 channels of one offset;
-// B: 32 input x 16 output channels). Four waves per workgroup, each owning
-// two rows of 32 points (four 16-point M tiles) times both 16-channel N
-// tiles: eight independent accumulators, so that consecutive products never
-// wait on each other. The input plane of each dz is staged in LDS as BF16
-// (and, with SPLIT, the BF16 remainder x - bf16(x), which a second product
-// adds), 16-byte channel chunks XOR-swizzled by point so that 16 consecutive
-// points of one chunk fall in distinct banks; the next plane's loads are in
-// flight (in registers) while the current plane is multiplied. Also the data
-// gradient (weights transposed and flipped, no bias) with the ReLU mask of
-// the layer below.
+// B: 32 input x 16 output channels). A workgroup computes 8 rows x 32 points
+// of two consecutive z-planes; each of its four waves owns two rows (four
+// 16-point M tiles) times both 16-channel N tiles of both planes, sixteen
+// independent accumulators. The input planes z0-1 .. z0+2 are staged in LDS
+// one at a time as BF16 (and, with SPLIT, the BF16 remainder x - bf16(x),
+// which a second product adds), 16-byte channel chunks XOR-swizzled by point
+// so that 16 consecutive points of one chunk fall in distinct banks; every A
+// fragment read from LDS serves both output planes, and the next plane's
+// loads are in flight (in registers) while the current one is multiplied.
+// Also the data gradient (weights transposed and flipped, no bias) with the
+// ReLU mask of the layer below.
 template <bool SPLIT>
 __global__ __launch_bounds__(kT, 2) void k_sg_mid(SgGrid g, const float* __restrict__ a,
-                                                const uint16_t* __restrict__ w,
-                                                const float* __restrict__ b,
-                                                float* __restrict__ out, int relu,
-                                                const float* __restrict__ mask) {
+                                                   const uint16_t* __restrict__ w,
+                                                   const float* __restrict__ b,
+                                                   float* __restrict__ out, int relu,
+                                                   const float* __restrict__ mask) {
   constexpr int kLoads = (kSgHalo * (kSgC / 4) + kT - 1) / kT;  // float4 per thread per plane
   typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
   __shared__ uint4 shi[kSgHalo * 4];
   __shared__ uint4 slo[SPLIT ? kSgHalo * 4 : 1];
   const int tiles_x = (g.nx + kSgTX - 1) / kSgTX;
   const int x0 = (int)(blockIdx.x % tiles_x) * kSgTX, y0 = (int)(blockIdx.x / tiles_x) * kSgTY;
-  const int z = blockIdx.y, t = threadIdx.x;
+  const int z0 = 2 * (int)blockIdx.y, nout = min(2, g.nz - z0);
+  const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6, li = lane & 15, kg = lane >> 4;
-  // planes z + dz - 1 inside the grid: dz in [dz_lo, dz_hi]
-  const int dz_lo = z == 0 ? 1 : 0, dz_hi = z == g.nz - 1 ? 1 : 2;
+  // input planes of the two outputs inside the grid
+  const int p_lo = max(0, z0 - 1), p_hi = min(g.nz - 1, z0 + nout);
   float4 pre[kLoads];
   auto load_plane = [&](int gz) {
 #pragma unroll
@@ -214,24 +216,25 @@ __global__ __launch_bounds__(kT, 2) void k_sg_mid(SgGrid g, const float* __restr
       }
     }
   };
-  f32x4 acc[4][2];
+  f32x4 acc[2][4][2];
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-    for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-  load_plane(z + dz_lo - 1);
-  for (int dz = dz_lo; dz <= dz_hi; ++dz) {
-    const bf16x8* wz = reinterpret_cast<const bf16x8*>(w + ((int64_t)dz * 9 * kSgC + li) * kSgC + kg * 8);
+  for (int zo = 0; zo < 2; ++zo)
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) acc[zo][mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  load_plane(p_lo);
+  for (int p = p_lo; p <= p_hi; ++p) {
     __syncthreads();  // the previous plane has been multiplied
     store_plane();
     __syncthreads();
-    if (dz < dz_hi) load_plane(z + dz);  // the next plane, in flight meanwhile
+    if (p < p_hi) load_plane(p + 1);  // the next plane, in flight meanwhile
+    // offset dz of this plane for output z0 + zo (valid if 0..2)
+    const int dz0 = p - z0 + 1, dz1 = p - z0;
+    const bool on0 = dz0 <= 2, on1 = nout > 1 && dz1 >= 0;
 #pragma unroll 3
     for (int j = 0; j < 9; ++j) {
       const int dy = j / 3, dx = j % 3;
-      // B fragments of offset j: output channels li and 16 + li, inputs 8 kg ..
-      bf16x8 bw[2];
-      bw[0] = wz[(j * kSgC) * (kSgC / 8)];
-      bw[1] = wz[(j * kSgC + 16) * (kSgC / 8)];
       bf16x8 ah[4], al[4];
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt) {
@@ -241,38 +244,49 @@ __global__ __launch_bounds__(kT, 2) void k_sg_mid(SgGrid g, const float* __restr
         if (SPLIT) al[mt] = *reinterpret_cast<const bf16x8*>(&slo[h * 4 + chunk]);
       }
 #pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
+      for (int zo = 0; zo < 2; ++zo) {
+        if (!(zo == 0 ? on0 : on1)) continue;
+        // B fragments of offset (dz, j): output channels li and 16 + li, inputs 8 kg ..
+        const bf16x8* wz = reinterpret_cast<const bf16x8*>(
+            w + ((int64_t)((zo == 0 ? dz0 : dz1) * 9 + j) * kSgC + li) * kSgC + kg * 8);
+        const bf16x8 bw0 = wz[0], bw1 = wz[16 * (kSgC / 8)];
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt)
-          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bw[nt], acc[mt][nt], 0, 0, 0);
-      if (SPLIT) {
+        for (int mt = 0; mt < 4; ++mt) {
+          acc[zo][mt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bw0, acc[zo][mt][0], 0, 0, 0);
+          acc[zo][mt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bw1, acc[zo][mt][1], 0, 0, 0);
+        }
+        if (SPLIT) {
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-          for (int nt = 0; nt < 2; ++nt)
-            acc[mt][nt] =
-                __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mt], bw[nt], acc[mt][nt], 0, 0, 0);
+          for (int mt = 0; mt < 4; ++mt) {
+            acc[zo][mt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mt], bw0, acc[zo][mt][0], 0, 0, 0);
+            acc[zo][mt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mt], bw1, acc[zo][mt][1], 0, 0, 0);
+          }
+        }
       }
     }
   }
   // D tile of 16 points x 16 channels: lane holds points 4 kg + r, channel li
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-    const int gy = y0 + 2 * wv + (mt >> 1);
-    if (gy >= g.ny) continue;
+  for (int zo = 0; zo < 2; ++zo) {
+    if (zo >= nout) continue;
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-      const int co = nt * 16 + li;
-      const float bias = b ? b[co] : 0.f;
+    for (int mt = 0; mt < 4; ++mt) {
+      const int gy = y0 + 2 * wv + (mt >> 1);
+      if (gy >= g.ny) continue;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gx = x0 + (mt & 1) * 16 + kg * 4 + r;
-        if (gx >= g.nx) continue;
-        const int64_t v = vox_of(g, z, gy, gx);
-        float val = acc[mt][nt][r] + bias;
-        if (mask && !(mask[v * kSgC + co] > 0.f)) val = 0.f;
-        if (relu) val = fmaxf(val, 0.f);
-        out[v * kSgC + co] = val;
+      for (int nt = 0; nt < 2; ++nt) {
+        const int co = nt * 16 + li;
+        const float bias = b ? b[co] : 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gx = x0 + (mt & 1) * 16 + kg * 4 + r;
+          if (gx >= g.nx) continue;
+          const int64_t v = vox_of(g, z0 + zo, gy, gx);
+          float val = acc[zo][mt][nt][r] + bias;
+          if (mask && !(mask[v * kSgC + co] > 0.f)) val = 0.f;
+          if (relu) val = fmaxf(val, 0.f);
+          out[v * kSgC + co] = val;
+        }
       }
     }
   }
@@ -532,12 +546,11 @@ hipError_t alloc(T** p, int64_t count) {
 
 void launch_mid(const Surrogate* s, hipStream_t st, const float* a, const uint16_t* w,
                 const float* b, float* out, int relu, const float* mask) {
+  const dim3 grid(tile_grid(s->gd).x, (unsigned)((s->gd.nz + 1) / 2));  // two planes per workgroup
   if (s->split)
-    hipLaunchKernelGGL(k_sg_mid<true>, tile_grid(s->gd), dim3(kT), 0, st, s->gd, a, w, b, out, relu,
-                       mask);
+    hipLaunchKernelGGL(k_sg_mid<true>, grid, dim3(kT), 0, st, s->gd, a, w, b, out, relu, mask);
   else
-    hipLaunchKernelGGL(k_sg_mid<false>, tile_grid(s->gd), dim3(kT), 0, st, s->gd, a, w, b, out,
-                       relu, mask);
+    hipLaunchKernelGGL(k_sg_mid<false>, grid, dim3(kT), 0, st, s->gd, a, w, b, out, relu, mask);
 }
 
 float* act_of(const Surrogate* s, int l, bool train) {

@@ -111,6 +111,36 @@ def test_forward_matches_oracle(ctx, bf16_act):
     assert torch.equal(qg2, ug)
 
 
+@pytest.mark.parametrize("bf16_act", [False, True])
+def test_forward_odd_thickness(bf16_act):
+    """Grid 36 x 16 x 5: a ragged x tile of 4 points, and an odd number of
+    planes, so that the last workgroup of the matrix-core layer computes one
+    plane instead of two; bars as above."""
+    prob = mg.kuhn_box((18, 8, 2), 2e-9, periodic=0b011, jitter=0.1, seed=13, grid=(36, 16, 5))
+    c = B.Context.from_problem(prob, device=0)
+    try:
+        depth = 5
+        c.surrogate_init(depth, seed=2, bf16_activations=bf16_act)
+        shape = c._grid_shape()
+        assert shape == (5, 16, 36)
+        rng = np.random.default_rng(15)
+        ps = random_params(rng, depth)
+        c.surrogate_set_params(flat(ps), scales=(1.0, 1.0))
+        Q = rng.standard_normal(shape).astype(np.float32)
+        ref = S.forward(Q.astype(np.float64)[None], ps)[0][0]
+        qg = torch.tensor(Q, device="cuda")
+        ug = torch.empty_like(qg)
+        print(f"[gpu surrogate] forward grid {shape} bf16_act={bf16_act}", flush=True)
+        c.surrogate_apply(qg, ug)
+        U = ug.cpu().numpy().astype(np.float64)
+        errmax = np.abs(U - ref).max() / np.abs(ref).max()
+        errl2 = np.linalg.norm(U - ref) / np.linalg.norm(ref)
+        print(f"[gpu surrogate] forward: max {errmax:.2e}, rel L2 {errl2:.2e}", flush=True)
+        assert (errl2 <= 1e-2) if bf16_act else (errmax <= 1e-5)
+    finally:
+        c.close()
+
+
 def test_gradients_match_oracle(ctx):
     """Loss and every parameter's gradient against the oracle's
     back-propagation. Each hidden channel's bias puts zero in the middle of
