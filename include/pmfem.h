@@ -471,14 +471,17 @@ int pmfem_surrogate_texture(pmfem_ctx* ctx, int32_t kind, uint64_t seed, double*
  * step. Synchronous. */
 int pmfem_surrogate_train(pmfem_ctx* ctx, int32_t n_pairs, double lr, uint64_t seed,
                           uint32_t kinds, double* loss_log);
-/* on != 0: pmfem_heff and the LLG steppers use the surrogate in place of the
- * FFT convolution until disabled. */
+/* on != 0: every field evaluation of the context (pmfem_heff, heff_parts,
+ * energy, the RK4 and implicit steppers) uses the surrogate in place of the
+ * FFT convolution until disabled; pmfem_grid_convolve, pmfem_autotune (which
+ * times the plain forms) and batches (pmfem_batch_*) keep the FFT. */
 int pmfem_surrogate_enable(pmfem_ctx* ctx, int32_t on);
 /*
  * n_steps RK4 steps (as pmfem_llg_step) with the surrogate, judged by the
  * plain AIM: before every check_every-th step (from the first) the
  * magnetostatic field of the current state is evaluated both ways, error =
- * |H_sur - H_aim| / |H_aim| (2-norms over all unknowns); once an error
+ * |H_sur - H_aim| / |H_aim| (2-norms over all unknowns; |H_sur - H_aim| if
+ * H_aim is zero, as for an in-plane uniform film); once an error
  * exceeds tol the rest of the steps use the FFT convolution. report[4]
  * (host, or NULL): checks made, largest and last error, the step of the
  * fallback (-1 if none). Synchronises at every check.
