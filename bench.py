@@ -84,12 +84,12 @@ WORKLOADS = {
 }
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or
+def measured_traffic(kernel, summary="composite_c3_hbm_traffic.json", source="kernels.hip"):
+    """HBM bytes per launch of `kernel` from a committed counter summary, or
     None when the kernel source has changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "composite_c3_hbm_traffic.json")
-    src = os.path.join(ROOT, "paper_2409_13958_amd", "csrc", "kernels.hip")
+    path = os.path.join(ROOT, "profiles", summary)
+    src = os.path.join(ROOT, "paper_2409_13958_amd", "csrc", source)
     try:
         with open(path) as f:
             rec = json.load(f)
@@ -97,12 +97,27 @@ def measured_traffic(kernel):
             h = hashlib.sha256(f.read()).hexdigest()
     except OSError:
         return None
-    if rec.get("kernels_hip_sha256") != h:
+    if rec.get(source.replace(".", "_") + "_sha256") != h:
         return None
     for name, b in rec.get("bytes_per_launch", {}).items():
         if name.split("<")[0] == kernel:
             return float(b)
     return None
+
+
+def calibrate_counters(mib):
+    """Plain streams of known size for the HBM counters of a profiled run, each
+    one elementwise kernel (a device copy may run on a DMA engine that the
+    counters do not see): a fill writes mib MiB, a negation reads and writes
+    mib MiB each; the counters of the other kernels are scaled by what they
+    read for these."""
+    import torch
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    log(f"counter calibration: one {mib} MiB fill, 3 negations of {mib} MiB")
 
 
 def host_info():
@@ -441,6 +456,8 @@ def run_surrogate(args):
     shape = ctx._grid_shape()
     nvox = int(np.prod(shape))
     log(f"setup: N'={n}, grid {shape[::-1]} ({time.perf_counter() - t:.1f} s)")
+    if args.copy_mib > 0:
+        calibrate_counters(args.copy_mib)
     depth = 6
     ctx.surrogate_init(depth, seed=1, bf16_activations=args.sg_bf16)
     t = time.perf_counter()
@@ -549,7 +566,9 @@ def run_surrogate(args):
         },
         "roofline": {"kernel": "k_sg_mid (32->32 layer, matrix cores)", "bound": "mfma",
                      "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / MFMA_BF16_PEAK_TFLOPS,
+                     "traffic": (None if args.sg_bf16 else measured_traffic(
+                         "k_sg_mid", "film_c5_surrogate_hbm_traffic.json", "surrogate.hip")),
                      "flop_per_launch": flop_mid,
                      "note": ("algorithmic FLOPs 2*27*32*32 per grid point; the FP32-accurate "
                               "form issues twice as many matrix-core products (BF16 high part "
@@ -621,17 +640,7 @@ def main():
     m = torch.tensor(prob.m[nou], dtype=torch.float32, device="cuda")
     h = torch.empty_like(m)
     if args.copy_mib > 0:
-        # plain streams of known size, each one elementwise kernel (a device
-        # copy may run on a DMA engine that the counters do not see): a fill
-        # writes copy_mib MiB, a negation reads and writes copy_mib MiB each;
-        # HBM counters of a profiled run are scaled by what they read for them
-        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            torch.neg(src, out=dst)
-        torch.cuda.synchronize()
-        log(f"counter calibration: one {args.copy_mib} MiB fill, 3 negations of {args.copy_mib} MiB")
-        del src, dst
+        calibrate_counters(args.copy_mib)
     for _ in range(args.warmup):
         ctx.heff(m, h)
     torch.cuda.synchronize()
