@@ -141,7 +141,8 @@ def test_forward_odd_thickness(bf16_act):
         c.close()
 
 
-def test_gradients_match_oracle(ctx):
+@pytest.mark.parametrize("depth", [6, 2])
+def test_gradients_match_oracle(ctx, depth):
     """Loss and every parameter's gradient against the oracle's
     back-propagation. Each hidden channel's bias puts zero in the middle of
     the widest gap between its sorted convolution values inside a quantile
@@ -149,8 +150,8 @@ def test_gradients_match_oracle(ctx):
     varying set of points in every channel, and the test first checks, on the
     oracle alone, that no pre-activation lies within 1e-4 of its channel's
     spread of zero, far outside the kernel's forward error (~1e-6): so both
-    sides take the same ReLU decisions."""
-    depth = 6
+    sides take the same ReLU decisions. Depth 2 is the degenerate network
+    with no matrix-core layer (first layer straight into the last)."""
     ctx.surrogate_init(depth, seed=4)
     shape = ctx._grid_shape()
     rng = np.random.default_rng(9)
