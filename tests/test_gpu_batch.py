@@ -46,7 +46,7 @@ def cells():
 
 
 GRAPH_SKIP = ("graph-captured batch removed: its first call crashed the host process on the "
-              "GPU box and no cause was found in this code")
+              "GPU and no cause was found in this code")
 
 
 @pytest.mark.skip(reason=GRAPH_SKIP)
