@@ -226,6 +226,23 @@ def test_training_lowers_the_loss():
         c.close()
 
 
+def test_training_is_reproducible(ctx):
+    """The same initialisation and pairs give the same parameters and losses,
+    bit for bit (fixed-order reductions, no atomics)."""
+    runs = []
+    for _ in range(2):
+        ctx.surrogate_init(4, seed=12)
+        log = ctx.surrogate_train(6, lr=1e-3, seed=5)
+        p, sc = ctx.surrogate_get_params()
+        runs.append((log, p, sc))
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert np.array_equal(runs[0][1], runs[1][1])
+    assert runs[0][2] == runs[1][2]
+    ctx.surrogate_init(4, seed=12)
+    other = ctx.surrogate_train(6, lr=1e-3, seed=6)
+    assert not np.array_equal(other, runs[0][0])
+
+
 def test_judged_llg_and_fallback(ctx):
     n = ctx.n
     ctx.surrogate_init(4, seed=6)
