@@ -28,7 +28,7 @@ constexpr int kSgMaxDepth = 12;
 constexpr int kSgTX = 32, kSgTY = 8;          // output tile of one z-plane
 constexpr int kSgHX = kSgTX + 2, kSgHY = kSgTY + 2;
 constexpr int kSgHalo = kSgHX * kSgHY;        // staged points of one plane
-constexpr int kSgWPart = 512;                 // workgroups of the weight-gradient pass
+constexpr int kSgWPart = 512;                 // partial sums of the weight-gradient pass
 
 struct SgGrid {
   int nx, ny, nz;

@@ -14,6 +14,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kT = 256;
 constexpr int kRedBlocks = 1024;   // blocks of the device reductions (partials in dred)
+constexpr int kSgWS = 48;          // LDS point stride (floats) of the weight-gradient kernel
+constexpr size_t kSgWgradLds = (size_t)(kSgTX * kSgTY + kSgHalo) * kSgWS * sizeof(float);
 
 // FP32 -> BF16, round to nearest even (finite inputs)
 __device__ __forceinline__ uint32_t bf16_bits(float f) {
@@ -293,61 +295,111 @@ __global__ __launch_bounds__(kT, 2) void k_sg_mid(SgGrid g, const float* __restr
 }
 
 // Weight gradient of a kSgC -> kSgC layer: gW[co][ci][o] = sum over points v
-// of gr[v][co] a[v + o][ci] (circular in x, y; zero outside in z). Grid
-// (P, 3): blockIdx.y is dz; each 192-thread workgroup walks the tiles
-// blockIdx.x, +P, ... and owns, per thread, 4 output x 4 input channels x the
-// three dx at one dy. Partial sums per workgroup go to part[P][C*C*27].
-__global__ __launch_bounds__(192) void k_sg_wgrad(SgGrid g, const float* __restrict__ gr,
+// of gr[v][co] a[v + o][ci] (circular in x, y; zero outside in z), on the
+// matrix cores with FP32 operands (v_mfma_f32_16x16x4f32: M = 16 output
+// channels, N = 16 input channels, K = 4 points, FP32 products and sums).
+// Grid (P, 3): blockIdx.y is dz; each 512-thread workgroup walks the tiles
+// blockIdx.x, +P, ...; wave w owns the 16 x 16 channel block (w & 3) for the
+// nine (dy, dx) of its dz (nine independent accumulators) and every other
+// group of four points (w >> 2). The tile's output gradient and the input
+// plane are staged in LDS at a point stride of kSgWS floats, so that four
+// consecutive points of one 16-channel block fall in distinct banks. Partial
+// sums per workgroup and half go to part[2 P][C*C*27]. The next tile's loads
+// are in flight (in registers) while the current one is multiplied.
+__global__ __launch_bounds__(512) void k_sg_wgrad(SgGrid g, const float* __restrict__ gr,
                                                    const float* __restrict__ a,
                                                    float* __restrict__ part) {
-  __shared__ float4 sg[kSgTX * kSgTY * 8];
-  __shared__ float4 sa[kSgHalo * 8];
-  const int t = threadIdx.x, ciq = t & 7, coq = (t >> 3) & 7, dy = t >> 6, dz = blockIdx.y;
+  extern __shared__ float4 wsm4[];
+  float* sg = reinterpret_cast<float*>(wsm4);        // [kSgTX * kSgTY][kSgWS]
+  float* sa = sg + kSgTX * kSgTY * kSgWS;             // [kSgHalo][kSgWS]
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, li = lane & 15, kq = lane >> 4;
+  const int mt = (wv >> 1) & 1, nt = wv & 1, half = wv >> 2, dz = blockIdx.y;
   const int tiles_x = (g.nx + kSgTX - 1) / kSgTX, tiles_y = (g.ny + kSgTY - 1) / kSgTY;
   const int tpp = tiles_x * tiles_y, ntiles = tpp * g.nz;
-  float acc[3][4][4];
-#pragma unroll
-  for (int d = 0; d < 3; ++d)
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) acc[d][i][j] = 0.f;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int z = tile / tpp, r = tile - z * tpp;
+  constexpr int kLg = kSgTX * kSgTY * 8 / 512;            // float4 of the tile per thread
+  constexpr int kLa = (kSgHalo * 8 + 511) / 512;           // float4 of the plane per thread
+  static_assert(kLg * 512 == kSgTX * kSgTY * 8, "tile float4 count");
+  // the workgroup's tiles whose plane z + dz - 1 lies inside the grid
+  auto next_tile = [&](int tl) {
+    while (tl < ntiles && (tl / tpp + dz - 1 < 0 || tl / tpp + dz - 1 >= g.nz)) tl += gridDim.x;
+    return tl;
+  };
+  float4 pg[kLg], pa[kLa];
+  auto load_tile = [&](int tl) {
+    const int z = tl / tpp, r = tl - z * tpp;
     const int x0 = (r % tiles_x) * kSgTX, y0 = (r / tiles_x) * kSgTY, gz = z + dz - 1;
-    if (gz < 0 || gz >= g.nz) continue;  // the same for the whole workgroup
-    __syncthreads();
-    for (int i = t; i < kSgTX * kSgTY * 8; i += 192) {
-      const int v = i >> 3, q = i & 7, gx = x0 + (v & (kSgTX - 1)), gy = y0 + v / kSgTX;
-      float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (gx < g.nx && gy < g.ny) val = reinterpret_cast<const float4*>(gr + vox_of(g, z, gy, gx) * kSgC)[q];
-      sg[i] = val;
+#pragma unroll
+    for (int k = 0; k < kLg; ++k) {
+      const int i = t + k * 512, v = i >> 3, q = i & 7;
+      const int gx = x0 + (v & (kSgTX - 1)), gy = y0 + v / kSgTX;
+      pg[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (gx < g.nx && gy < g.ny) pg[k] = reinterpret_cast<const float4*>(gr + vox_of(g, z, gy, gx) * kSgC)[q];
     }
-    for (int i = t; i < kSgHalo * 8; i += 192) {
-      const int h = i >> 3, q = i & 7, hy = h / kSgHX, hx = h - hy * kSgHX;
-      sa[i] = reinterpret_cast<const float4*>(
-          a + vox_of(g, gz, wrapi(y0 + hy - 1, g.ny), wrapi(x0 + hx - 1, g.nx)) * kSgC)[q];
+#pragma unroll
+    for (int k = 0; k < kLa; ++k) {
+      const int i = t + k * 512;
+      pa[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (i < kSgHalo * 8) {
+        const int h = i >> 3, q = i & 7, hy = h / kSgHX, hx = h - hy * kSgHX;
+        pa[k] = reinterpret_cast<const float4*>(
+            a + vox_of(g, gz, wrapi(y0 + hy - 1, g.ny), wrapi(x0 + hx - 1, g.nx)) * kSgC)[q];
+      }
+    }
+  };
+  f32x4 acc[9];
+#pragma unroll
+  for (int j = 0; j < 9; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  int tile = next_tile(blockIdx.x);  // the same for the whole workgroup
+  if (tile < ntiles) load_tile(tile);
+  while (tile < ntiles) {
+    __syncthreads();  // the previous tile has been used
+#pragma unroll
+    for (int k = 0; k < kLg; ++k) {
+      const int i = t + k * 512;
+      reinterpret_cast<float4*>(sg + (i >> 3) * kSgWS)[i & 7] = pg[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kLa; ++k) {
+      const int i = t + k * 512;
+      if (i < kSgHalo * 8) reinterpret_cast<float4*>(sa + (i >> 3) * kSgWS)[i & 7] = pa[k];
     }
     __syncthreads();
-    for (int v = 0; v < kSgTX * kSgTY; ++v) {
-      const int ty = v / kSgTX, tx = v % kSgTX;
-      const float4 gv = sg[v * 8 + coq];
-      const int hb = (ty + dy) * kSgHX + tx;
+    const int nxt = next_tile(tile + gridDim.x);
+    if (nxt < ntiles) load_tile(nxt);  // in flight while this tile is multiplied
+    tile = nxt;
+    for (int st = half; st < kSgTX * kSgTY / 4; st += 2) {
+      const int v = 4 * st + kq, ty = v / kSgTX, tx = v % kSgTX;
+      const float ga = sg[v * kSgWS + mt * 16 + li];     // A: output channel x point
+      const float* sb = sa + (ty * kSgHX + tx) * kSgWS + nt * 16 + li;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const float4 av = sa[(hb + d) * 8 + ciq];
-        const float gg[4] = {gv.x, gv.y, gv.z, gv.w}, aa[4] = {av.x, av.y, av.z, av.w};
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[d][i][j] = fmaf(gg[i], aa[j], acc[d][i][j]);
+      for (int j = 0; j < 9; ++j) {
+        const float bb = sb[((j / 3) * kSgHX + j % 3) * kSgWS];  // B: point x input channel
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga, bb, acc[j], 0, 0, 0);
       }
     }
   }
-  float* P = part + (int64_t)blockIdx.x * (kSgC * kSgC * 27);
+  // D block: lane holds output channels 16 mt + 4 kq + r, input channel 16 nt + li;
+  // partial sums as [offset][co][ci], so that 16 lanes store 64 contiguous bytes
+  float* P = part + ((int64_t)blockIdx.x * 2 + half) * (kSgC * kSgC * 27);
 #pragma unroll
-  for (int d = 0; d < 3; ++d)
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j)
-        P[((coq * 4 + i) * kSgC + ciq * 4 + j) * 27 + dz * 9 + dy * 3 + d] = acc[d][i][j];
+  for (int j = 0; j < 9; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      P[((dz * 9 + j) * kSgC + mt * 16 + 4 * kq + r) * kSgC + nt * 16 + li] = acc[j][r];
+}
+
+// Sum of the weight-gradient partial sums part[P][27][C][C] into a layer's
+// W[co][ci][27] (ci < Ci, co < Co); one thread per partial entry, in the
+// partials' order, so that the reads are contiguous; fixed order over P.
+__global__ void k_sg_reduce_w(int P, const float* __restrict__ part, int Ci, int Co,
+                              float* __restrict__ dst) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 27 * kSgC * kSgC) return;
+  const int o = e / (kSgC * kSgC), co = (e / kSgC) % kSgC, ci = e % kSgC;
+  if (co >= Co || ci >= Ci) return;
+  double sum = 0.0;
+  for (int p = 0; p < P; ++p) sum += part[(int64_t)p * (27 * kSgC * kSgC) + e];
+  dst[(co * Ci + ci) * 27 + o] = (float)sum;
 }
 
 // Column sums of g[V][C] (C divides 256): partial per workgroup -> part[P][C].
@@ -584,16 +636,14 @@ void forward(Surrogate* s, hipStream_t st, const float* Q, bool train, float* yo
 void layer_grads(Surrogate* s, hipStream_t st, int l, const float* g, const float* a) {
   const SgGrid& gd = s->gd;
   const int ntiles = (int)tile_grid(gd).x * gd.nz;
-  const int P = std::min(kSgWPart, ntiles);
+  const int P = std::min(kSgWPart / 2, ntiles);  // two partial sums per workgroup
   const int64_t nW = (int64_t)kSgC * kSgC * 27;
-  hipLaunchKernelGGL(k_sg_wgrad, dim3((unsigned)P, 3), dim3(192), 0, st, gd, g, a, s->part);
+  hipLaunchKernelGGL(k_sg_wgrad, dim3((unsigned)P, 3), dim3(512), kSgWgradLds, st, gd, g, a,
+                     s->part);
   const int D = s->depth;
   const int ci = l == 0 ? 1 : kSgC, co = l == D - 1 ? 1 : kSgC;
-  const int64_t count = (int64_t)ci * co * 27;
-  // first layer: entries (co * C + 0) * 27 + o; others contiguous
-  const int64_t stride = l == 0 ? (int64_t)kSgC * 27 : 27;
-  hipLaunchKernelGGL(k_sg_reduce, dim3(blocks(count)), dim3(kT), 0, st, P, nW, s->part, count, 27,
-                     stride, s->grad + s->woff[l]);
+  hipLaunchKernelGGL(k_sg_reduce_w, dim3(blocks(nW)), dim3(kT), 0, st, 2 * P, s->part, ci, co,
+                     s->grad + s->woff[l]);
   // bias: column sums of the output gradient
   float* bpart = s->part;  // reused after the reduction above (same stream)
   if (co == 1) {
@@ -635,6 +685,9 @@ hipError_t sg_create(Surrogate* s, int depth, SgGrid gd, int64_t n, const double
       (e = alloc(&s->wmidt, std::max<int64_t>(1, (int64_t)nmid * 27 * kSgC * kSgC))) ||
       (e = alloc(&s->win, kSgC * 27)) || (e = alloc(&s->wout, kSgC * 27)) ||
       (e = alloc(&s->woutt, kSgC * 27)))
+    return e;
+  if ((e = hipFuncSetAttribute((const void*)k_sg_wgrad, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)kSgWgradLds)))
     return e;
   if ((e = alloc(&s->act, 2 * s->nvox * kSgC))) return e;
   if ((e = alloc(&s->dred, 2 * kRedBlocks + 8))) return e;
