@@ -389,17 +389,25 @@ __global__ __launch_bounds__(512) void k_sg_wgrad(SgGrid g, const float* __restr
 }
 
 // Sum of the weight-gradient partial sums part[P][27][C][C] into a layer's
-// W[co][ci][27] (ci < Ci, co < Co); one thread per partial entry, in the
-// partials' order, so that the reads are contiguous; fixed order over P.
-__global__ void k_sg_reduce_w(int P, const float* __restrict__ part, int Ci, int Co,
-                              float* __restrict__ dst) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= 27 * kSgC * kSgC) return;
+// W[co][ci][27] (ci < Ci, co < Co). A workgroup takes 64 consecutive partial
+// entries (contiguous loads) and four quarters of the P sums; the quarters
+// are added in a fixed order (FP64 throughout).
+__global__ __launch_bounds__(256) void k_sg_reduce_w(int P, const float* __restrict__ part, int Ci,
+                                                      int Co, float* __restrict__ dst) {
+  __shared__ double red[4][64];
+  const int el = threadIdx.x & 63, qt = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + el;
   const int o = e / (kSgC * kSgC), co = (e / kSgC) % kSgC, ci = e % kSgC;
-  if (co >= Co || ci >= Ci) return;
+  const bool used = e < 27 * kSgC * kSgC && co < Co && ci < Ci;
   double sum = 0.0;
-  for (int p = 0; p < P; ++p) sum += part[(int64_t)p * (27 * kSgC * kSgC) + e];
-  dst[(co * Ci + ci) * 27 + o] = (float)sum;
+  if (used) {
+#pragma unroll 8
+    for (int p = qt; p < P; p += 4) sum += part[(int64_t)p * (27 * kSgC * kSgC) + e];
+  }
+  red[qt][el] = sum;
+  __syncthreads();
+  if (qt == 0 && used)
+    dst[(co * Ci + ci) * 27 + o] = (float)(((red[0][el] + red[1][el]) + red[2][el]) + red[3][el]);
 }
 
 // Column sums of g[V][C] (C divides 256): partial per workgroup -> part[P][C].
@@ -419,15 +427,25 @@ __global__ __launch_bounds__(kT) void k_sg_colsum(int64_t V, int C, const float*
   }
 }
 
-// dst[i] = sum_p part[p * n + src(i)], src(i) = (i / run) * stride + i % run
-__global__ void k_sg_reduce(int P, int64_t n, const float* __restrict__ part, int64_t count,
-                            int run, int64_t stride, float* __restrict__ dst) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
+// dst[i] = sum_p part[p * n + src(i)], src(i) = (i / run) * stride + i % run:
+// one workgroup per output, the P partial sums split over its threads and
+// added by a fixed-order tree (FP64)
+__global__ __launch_bounds__(256) void k_sg_reduce(int P, int64_t n, const float* __restrict__ part,
+                                                    int64_t count, int run, int64_t stride,
+                                                    float* __restrict__ dst) {
+  __shared__ double red[256];
+  const int64_t i = blockIdx.x;
+  if (i >= count) return;  // the same for the whole workgroup
   const int64_t src = (i / run) * stride + i % run;
-  double s = 0.0;
-  for (int p = 0; p < P; ++p) s += part[(int64_t)p * n + src];
-  dst[i] = (float)s;
+  double sum = 0.0;
+  for (int p = threadIdx.x; p < P; p += blockDim.x) sum += part[(int64_t)p * n + src];
+  red[threadIdx.x] = sum;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dst[i] = (float)red[0];
 }
 
 __device__ __forceinline__ double block_sum(double v, double* red) {
@@ -642,8 +660,8 @@ void layer_grads(Surrogate* s, hipStream_t st, int l, const float* g, const floa
                      s->part);
   const int D = s->depth;
   const int ci = l == 0 ? 1 : kSgC, co = l == D - 1 ? 1 : kSgC;
-  hipLaunchKernelGGL(k_sg_reduce_w, dim3(blocks(nW)), dim3(kT), 0, st, 2 * P, s->part, ci, co,
-                     s->grad + s->woff[l]);
+  hipLaunchKernelGGL(k_sg_reduce_w, dim3((unsigned)((nW + 63) / 64)), dim3(kT), 0, st, 2 * P,
+                     s->part, ci, co, s->grad + s->woff[l]);
   // bias: column sums of the output gradient
   float* bpart = s->part;  // reused after the reduction above (same stream)
   if (co == 1) {
@@ -651,7 +669,7 @@ void layer_grads(Surrogate* s, hipStream_t st, int l, const float* g, const floa
   } else {
     hipLaunchKernelGGL(k_sg_colsum, dim3(kRedBlocks), dim3(kT), 0, st, s->nvox, kSgC, g, bpart);
   }
-  hipLaunchKernelGGL(k_sg_reduce, dim3(1), dim3(kT), 0, st, kRedBlocks, (int64_t)co, bpart,
+  hipLaunchKernelGGL(k_sg_reduce, dim3((unsigned)co), dim3(kT), 0, st, kRedBlocks, (int64_t)co, bpart,
                      (int64_t)co, co, (int64_t)0, s->grad + s->boff[l]);
 }
 
