@@ -141,6 +141,55 @@ def test_forward_odd_thickness(bf16_act):
         c.close()
 
 
+def test_grid_narrower_than_a_tile():
+    """The 20 x 20 x 2 nm film's grid, 16 x 16 x 4: narrower than a kernel
+    tile (32 points), so the staged halo wraps around the period more than
+    once and half of every tile lies outside the grid. Forward and gradients
+    of a three-layer network against the oracle, ReLU margins as in the
+    gradient test below."""
+    c = B.Context.from_problem(mg.film_c1(), device=0)
+    try:
+        depth = 3
+        c.surrogate_init(depth, seed=7)
+        shape = c._grid_shape()
+        assert shape == (4, 16, 16)
+        rng = np.random.default_rng(17)
+        ps = random_params(rng, depth, bias_sd=0.0)
+        Q = rng.standard_normal(shape).astype(np.float32)
+        h = Q.astype(np.float64)[None]
+        margins = []
+        for l in range(depth):
+            W, _ = ps[l]
+            z = S.layer(h, W, np.zeros(W.shape[0]))
+            sd = z.reshape(z.shape[0], -1).std(axis=1)
+            b = np.array([gap_bias(z[k], *((0.02, 0.2) if rng.random() < 0.5 else (0.8, 0.98)))
+                          for k in range(W.shape[0])]).astype(np.float32).astype(np.float64)
+            ps[l] = (W, b)
+            z = z + b[:, None, None, None]
+            if l + 1 < depth:
+                margins.append(np.min(np.abs(z).reshape(z.shape[0], -1) / sd[:, None]))
+                h = np.maximum(z, 0.0)
+        assert min(margins) > 1e-4, margins
+        c.surrogate_set_params(flat(ps), scales=(1.0, 1.0))
+        qg = torch.tensor(Q, device="cuda")
+        ug = torch.empty_like(qg)
+        print(f"[gpu surrogate] grid {shape}: forward and gradients", flush=True)
+        c.surrogate_apply(qg, ug)
+        ref = S.forward(Q.astype(np.float64)[None], ps)[0][0]
+        U = ug.cpu().numpy().astype(np.float64)
+        assert np.abs(U - ref).max() <= 1e-5 * np.abs(ref).max()
+        T = rng.standard_normal(shape).astype(np.float32)
+        loss_o, grads_o = S.loss_and_grads(Q.astype(np.float64)[None],
+                                           T.astype(np.float64)[None], ps)
+        loss_k, gk = c.surrogate_loss_grad(qg, torch.tensor(T, device="cuda"))
+        assert abs(loss_k - loss_o) <= 1e-5 * loss_o
+        for (gW, gb), (kW, kb) in zip(grads_o, unflat(gk.astype(np.float64), depth)):
+            assert np.abs(kW - gW).max() <= 1e-4 * np.abs(gW).max()
+            assert np.abs(kb - gb).max() <= 1e-4 * np.abs(gb).max()
+    finally:
+        c.close()
+
+
 @pytest.mark.parametrize("depth", [6, 2])
 def test_gradients_match_oracle(ctx, depth):
     """Loss and every parameter's gradient against the oracle's
